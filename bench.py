@@ -1,0 +1,164 @@
+"""Benchmark of the FastPI hot path on one MI355X.
+
+One step = the whole device path on resident inputs: value split (a1), block SVDs (a2),
+row update (a3), column update (a4), unpermute (a5) and the pseudoinverse apply
+Z = V Sigma^+ U^T Y (a6), for the workload 20000 x 2000 (0.5% dense, power-law 2.0,
+lognormal values, 200 Bernoulli(0.02) labels, alpha 0.2) unless --config says otherwise.
+The host reordering and planning run once before the timed region (their time is
+reported separately as plan_s).
+
+Prints one JSON line. `value` is the algorithmic throughput F_model / T_step in TFLOP/s,
+where F_model is the flop count of the exact method (see flop_model()).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+
+def svd_thin_flops(p, q):
+    """Golub & Van Loan R-SVD count for a p x q (p >= q) thin SVD with U and V."""
+    p, q = max(p, q), min(p, q)
+    return 6.0 * p * q * q + 20.0 * q ** 3
+
+
+def flop_model(plan, blocks, ranks, L):
+    """Algorithmic flops of one step (precision-independent):
+    a2: a thin SVD of every dense diagonal block;
+    a3: the thin SVD of M2 ((s_b + m2) x n1) plus the block products U1 Ut_top;
+    a4: the thin SVD of X3 (m x (s + n2)) plus V2 Vt_top;
+    a6: U^T Y and V (Sigma^+ W)."""
+    i = plan.info
+    f2 = sum(svd_thin_flops(r, c) for (_, _, r, c) in blocks if r > 0 and c > 0)
+    mis = sum(int(r) * int(s) for (_, _, r, _), s in zip(blocks, ranks))
+    f3 = svd_thin_flops(i["s_b"] + i["m2"], i["n1"]) + 2.0 * mis * i["s"] if i["n1"] else 0.0
+    f4 = svd_thin_flops(i["m"], i["s"] + i["n2"]) + 2.0 * i["n1"] * i["s"] * i["r"]
+    f6 = 2.0 * i["m"] * i["r"] * L + 2.0 * i["n"] * i["r"] * L
+    return {"a2": f2, "a3": f3, "a4": f4, "a6": f6, "total": f2 + f3 + f4 + f6}
+
+
+def cpu_baseline(prob, alpha, F, budget_s):
+    """The oracle as it stands, on the host cores, repeated on the same workload until
+    about budget_s seconds have passed (at least once)."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        res = oracle.fastpi_svd(prob.m, prob.n, prob.indptr, prob.indices, prob.data, alpha,
+                                prob.cfg.k)
+        oracle.pinv_apply(res.U, res.sigma, res.V, prob.Y, prob.m, prob.n)
+        reps += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": F * reps / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{reps} full run(s) of the oracle (reorder, block SVDs, both updates, "
+                      f"apply) on the same workload, {dt:.1f} s; s per run {dt / reps:.3f}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2011_04235_amd as fp
+    from synth import CONFIGS, make_problem
+
+    cfg = CONFIGS[args.config]
+    prob = make_problem(cfg)
+    fp.load()
+    t0 = time.perf_counter()
+    plan = fp.Plan(prob.m, prob.n, prob.indptr, prob.indices, prob.data, alpha=cfg.alpha, k=cfg.k)
+    plan_s = time.perf_counter() - t0
+    blocks = plan.blocks()
+    ranks = plan.block_ranks()
+    F = flop_model(plan, blocks, ranks, cfg.L)
+
+    dev = torch.device("cuda", 0)
+    h = fp.Handle(0, precision=args.precision)
+    h.upload_plan(plan)
+    rowptr = torch.from_numpy(prob.indptr).to(dev)
+    col = torch.from_numpy(prob.indices).to(dev)
+    val = torch.from_numpy(prob.data).to(dev)
+    Y = torch.from_numpy(prob.Y).to(dev)
+    m, n, r = plan.m, plan.n, plan.r
+    U = torch.empty((m, r), dtype=torch.float64, device=dev)
+    S = torch.empty((r,), dtype=torch.float64, device=dev)
+    V = torch.empty((n, r), dtype=torch.float64, device=dev)
+    Z = torch.empty((n, cfg.L), dtype=torch.float64, device=dev)
+
+    def step():
+        h.svd(rowptr, col, val, out=(U, S, V))
+        h.apply(U, S, V, Y, out=Z)
+
+    for _ in range(args.warmup):
+        step()
+    h.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    h.sync()
+    ms = dt / args.steps * 1e3
+    tflops = F["total"] / (ms * 1e-3) / 1e12
+
+    base = None
+    if not args.no_cpu_baseline:
+        base = cpu_baseline(prob, cfg.alpha, F["total"], args.cpu_budget)
+
+    out = {
+        "metric": "Ã⁺Y time & TFLOP/s, mixed-precision vs FP64 GPU at equal recon error",
+        "value": round(tflops, 4),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"fastpi {cfg.name}: A {m}x{n} ({prob.nnz} nnz, power-law "
+                               f"{cfg.gamma}, {cfg.values}), Y {m}x{cfg.L}, alpha {cfg.alpha}",
+                   "precision": args.precision, "m": m, "n": n, "nnz": prob.nnz, "L": cfg.L,
+                   "alpha": cfg.alpha, "shape": plan.info},
+        "flop_model": F,
+        "plan_s": round(plan_s, 4),
+        "sweeps": h.last_sweeps(),
+        "roofline": None,
+        "cpu_baseline": base,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,185 @@
+/*
+ * fastpi.h -- C ABI of the MI355X FastPI library (low-rank SVD of a reordered sparse
+ * feature matrix and the pseudoinverse apply), after Jung & Sael, "Fast and Accurate
+ * Pseudoinverse with Sparse Matrix Reordering and Incremental Approach" (arXiv 2011.04235).
+ *
+ * The library computes A ~= U Sigma V^T for a sparse A (m x n, CSR) and a rank ratio
+ * alpha in (0, 1] (Algorithm 1, lines 1-4), and then Z = V Sigma^+ U^T Y for a label
+ * matrix Y (Problem 1 with Application 1).
+ *
+ * Conventions for every call below:
+ *  - indices are 0-based; dense matrices are row-major (C order) with the stated shape;
+ *  - "host" pointers are ordinary CPU memory, "device" pointers are HIP device memory of
+ *    the handle's device; the caller owns every buffer passed in and the library never
+ *    frees or keeps caller memory beyond the call (except where a plan is uploaded);
+ *  - device calls are ordered on the handle's HIP stream and return before the device has
+ *    finished; fastpi_sync() waits and reports device-side failures;
+ *  - each call returns a fastpi_status; after an error the outputs are unspecified and
+ *    fastpi_last_error() returns a message for the calling thread;
+ *  - a handle is bound to one stream and must not be used from two threads at once.
+ */
+#ifndef FASTPI_H
+#define FASTPI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FASTPI_OK = 0,
+    FASTPI_EINVAL = -1,      /* bad argument: null pointer, alpha or k out of range, bad id   */
+    FASTPI_ESHAPE = -2,      /* CSR not well formed: rowptr not monotone, column out of range, */
+                             /* columns not strictly increasing within a row                  */
+    FASTPI_ENONFINITE = -3,  /* a stored value is NaN or infinite                              */
+    FASTPI_ENOMEM = -4,      /* device or host allocation failed, or the workspace cap is hit  */
+    FASTPI_EHIP = -5,        /* a HIP runtime call failed                                      */
+    FASTPI_ENOCONV = -6,     /* a Jacobi iteration reached its sweep cap before converging    */
+    FASTPI_EINTERNAL = -7
+} fastpi_status;
+
+typedef enum { FASTPI_FP64 = 0, FASTPI_MIXED = 1 } fastpi_precision;
+
+/* Shape report of a plan (symbols of Table 1). */
+typedef struct {
+    int64_t m, n;        /* rows (instances) and columns (features) of A                     */
+    int64_t nnz;         /* stored non-zeros used as edges (explicit zeros are dropped)      */
+    int64_t m1, n1;      /* spoke rows and columns: the size of A11                          */
+    int64_t m2, n2;      /* hub rows and columns                                             */
+    int64_t B;           /* diagonal blocks of A11, including blocks of height or width 0    */
+    int64_t B_dense;     /* blocks with both height and width > 0                            */
+    int64_t T_it;        /* reordering iterations (Algorithm 2)                               */
+    int64_t s_b;         /* sum of the block ranks s_i = min(ceil(alpha n_i), m_i, n_i)       */
+    int64_t s;           /* rank after the row update: min(ceil(alpha n1), s_b + m2, n1)      */
+    int64_t r;           /* final rank: min(ceil(alpha min(m, n)), s + n2, m)                 */
+} fastpi_split;
+
+typedef struct {
+    fastpi_precision precision;   /* FASTPI_FP64 (default) or FASTPI_MIXED                  */
+    int max_sweeps;               /* Jacobi sweep cap (0 = default 40)                       */
+    double tol;                   /* Jacobi rotation threshold (0 = default, size * eps)     */
+    size_t max_workspace_bytes;   /* 0 = unlimited; larger needs fail with FASTPI_ENOMEM     */
+} fastpi_options;
+
+typedef struct fastpi_plan fastpi_plan;
+typedef struct fastpi_handle fastpi_handle;
+
+/* ceil(alpha * x) evaluated in IEEE double, clamped at 0 (Table 1: r = ceil(alpha n)). */
+int64_t fastpi_target_rank(double alpha, int64_t x);
+
+/*
+ * Matrix reordering (Section 3.2, Algorithm 2). Host only, synchronous, integer work whose
+ * result is bit-exact and independent of threads and platform.
+ *   m, n         : shape of A (m, n >= 1)
+ *   rowptr       : host int64[m+1], col: host int32[nnz]; CSR pattern, columns strictly
+ *                  increasing in each row; val: host double[nnz] or NULL. When val is given,
+ *                  stored zeros are not edges (Definition 1).
+ *   k            : hub selection ratio, 0 < k < 1 (the paper uses 0.01)
+ *   piT, piF     : host int32[m], int32[n] outputs: original row/column -> new row/column
+ *   blocks       : host int64[4*blocks_cap] output (row0, col0, rows, cols) of every diagonal
+ *                  block of A11 in new ids, in order; may be NULL when blocks_cap is 0
+ *   num_blocks   : host output, the number of blocks (also when blocks_cap is too small,
+ *                  which returns FASTPI_EINVAL after filling nothing)
+ *   out          : host output shape report (the rank fields are 0: no alpha is involved)
+ * Tie-breaks: hubs by (degree in the current graph descending, index ascending), the first
+ * hub of a batch takes the highest free id; components discovered by scanning rows then
+ * columns in ascending original index; the giant component is the largest (rows+columns),
+ * first found on ties; non-giant components take the lowest free ids in discovery order,
+ * rows then columns each ascending; the loop stops once the giant component has fewer rows
+ * than this iteration's row-hub count or fewer columns than its column-hub count; the last
+ * giant component becomes the last block.
+ */
+int fastpi_reorder(int64_t m, int64_t n, const int64_t* rowptr, const int32_t* col,
+                   const double* val, double k, int32_t* piT, int32_t* piF,
+                   int64_t* blocks, int64_t blocks_cap, int64_t* num_blocks, fastpi_split* out);
+
+/*
+ * Plan for one sparsity pattern and one alpha (Algorithm 1, line 1, plus the rank rule
+ * of Eqs. 1-3): runs the reordering, derives every block's rank, and precomputes the index
+ * maps that move values from the caller's CSR into the blocks of A11, A21 and T = [A12; A22].
+ * Host only and synchronous. The CSR arguments are as in fastpi_reorder; the plan keeps no
+ * pointer to them. alpha in (0, 1], 0 < k < 1.
+ */
+int fastpi_plan_create(fastpi_plan** plan, int64_t m, int64_t n, const int64_t* rowptr,
+                       const int32_t* col, const double* val, double alpha, double k);
+int fastpi_plan_info(const fastpi_plan* plan, fastpi_split* out);
+/* Copies the permutations (host int32[m], int32[n]); either pointer may be NULL. */
+int fastpi_plan_permutation(const fastpi_plan* plan, int32_t* piT, int32_t* piF);
+/* Copies the block table, host int64[4*B], (row0, col0, rows, cols) per block. */
+int fastpi_plan_blocks(const fastpi_plan* plan, int64_t* blocks);
+/* Copies the rank s_i of every block (host int64[B]). */
+int fastpi_plan_block_ranks(const fastpi_plan* plan, int64_t* ranks);
+void fastpi_plan_destroy(fastpi_plan* plan);
+
+/*
+ * Device handle: binds a HIP device and stream (stream may be NULL for the default stream)
+ * and owns the device workspace. opts may be NULL for the defaults.
+ */
+int fastpi_create(fastpi_handle** h, int device, void* hip_stream, const fastpi_options* opts);
+int fastpi_set_precision(fastpi_handle* h, fastpi_precision p);
+void fastpi_destroy(fastpi_handle* h);
+
+/*
+ * Copies the plan's tables to the handle's device (stream-ordered). Needed once per plan
+ * before fastpi_svd; uploading another plan replaces it.
+ */
+int fastpi_upload_plan(fastpi_handle* h, const fastpi_plan* plan);
+
+/*
+ * Low-rank SVD A ~= U diag(S) V^T of the uploaded plan's matrix (Algorithm 1, lines 2-4:
+ * block SVDs of A11 by Eq. 1, row update by Eq. 2, column update by Eq. 3), mapped back to
+ * the caller's original row and column order.
+ *   rowptr, col, val : device CSR of A, the same pattern the plan was built from
+ *                      (int64[m+1], int32[nnz], double[nnz])
+ *   U : device double[m * r] row-major;  S : device double[r], descending;
+ *   V : device double[n * r] row-major;  r = fastpi_split.r of the plan.
+ * Columns whose singular value is at or below max(m, n) * eps * S[0] carry no information
+ * and may be zero.
+ */
+int fastpi_svd(fastpi_handle* h, const int64_t* rowptr, const int32_t* col, const double* val,
+               double* U, double* S, double* V);
+
+/*
+ * Pseudoinverse apply (Problem 1, Application 1): Z = V diag(S^+) U^T Y, with
+ * S^+_i = 1/S_i when S_i > max(m, n) * eps * max(S), else 0.
+ *   U : device double[m*r], S : device double[r], V : device double[n*r], row-major;
+ *   Y : device double[m*L] row-major; Z : device double[n*L] row-major output.
+ */
+int fastpi_apply(fastpi_handle* h, int64_t m, int64_t n, int64_t r, const double* U,
+                 const double* S, const double* V, int64_t L, const double* Y, double* Z);
+
+/*
+ * Intermediate results of the last fastpi_svd on this handle, for stage-level checks.
+ * which: 0 = block singular values sigma1 (s_b, block order, each block descending),
+ *        1 = row-update singular values sigma2 (s), 2 = row-update right factor V2 (n1 x s,
+ *        reordered column ids), 3 = row-update left factor U2 (m x s, reordered row ids).
+ * dst is a device pointer with room for count doubles; count must equal the stage's size.
+ */
+int fastpi_stage_output(fastpi_handle* h, int which, double* dst, int64_t count);
+
+/*
+ * Dense symmetric eigensolver used for the incremental cores (FP64 block Jacobi).
+ *   q    : order; G : device double[q*q] (symmetric, read only);
+ *   t    : number of leading eigenpairs wanted (0 < t <= q);
+ *   vals : device double[t], descending; vecs : device double[q*t] row-major, column k is
+ *          the eigenvector of vals[k].
+ */
+int fastpi_syev_top(fastpi_handle* h, int64_t q, const double* G, int64_t t, double* vals,
+                    double* vecs);
+
+/* Waits for the handle's stream and reports device-side failures (non-finite input,
+ * Jacobi sweep cap reached). */
+int fastpi_sync(fastpi_handle* h);
+
+/* Number of sweeps used by the last Jacobi run of each kind on this handle:
+ * out[0] = block stage (max over blocks), out[1] = row-update core, out[2] = column-update core. */
+int fastpi_last_sweeps(fastpi_handle* h, int32_t* out3);
+
+const char* fastpi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FASTPI_H */

@@ -1,0 +1,261 @@
+"""ctypes binding of libfastpi.so: argument marshalling only.
+
+Every step of the FastPI path runs inside the library (host reordering and planning in
+C++, everything else in HIP kernels on the device). PyTorch supplies device memory and the
+stream. There is no fallback: if the library is missing or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int, c_int32, c_int64, c_size_t, c_void_p
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfastpi.so")
+
+FP64, MIXED = 0, 1
+
+STATUS = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ENONFINITE", -4: "ENOMEM", -5: "EHIP",
+          -6: "ENOCONV", -7: "EINTERNAL"}
+
+
+class FastPIError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__(f"fastpi {STATUS.get(code, code)}: {message}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+class Split(ctypes.Structure):
+    _fields_ = [(name, c_int64) for name in
+                ("m", "n", "nnz", "m1", "n1", "m2", "n2", "B", "B_dense", "T_it", "s_b", "s", "r")]
+
+    def as_dict(self):
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", c_int), ("max_sweeps", c_int), ("tol", c_double),
+                ("max_workspace_bytes", c_size_t)]
+
+
+# (name, restype, argtypes) of every symbol declared in include/fastpi.h
+SIGNATURES = [
+    ("fastpi_target_rank", c_int64, [c_double, c_int64]),
+    ("fastpi_reorder", c_int, [c_int64, c_int64, c_void_p, c_void_p, c_void_p, c_double, c_void_p,
+                               c_void_p, c_void_p, c_int64, POINTER(c_int64), POINTER(Split)]),
+    ("fastpi_plan_create", c_int, [POINTER(c_void_p), c_int64, c_int64, c_void_p, c_void_p,
+                                   c_void_p, c_double, c_double]),
+    ("fastpi_plan_info", c_int, [c_void_p, POINTER(Split)]),
+    ("fastpi_plan_permutation", c_int, [c_void_p, c_void_p, c_void_p]),
+    ("fastpi_plan_blocks", c_int, [c_void_p, c_void_p]),
+    ("fastpi_plan_block_ranks", c_int, [c_void_p, c_void_p]),
+    ("fastpi_plan_destroy", None, [c_void_p]),
+    ("fastpi_create", c_int, [POINTER(c_void_p), c_int, c_void_p, POINTER(Options)]),
+    ("fastpi_set_precision", c_int, [c_void_p, c_int]),
+    ("fastpi_destroy", None, [c_void_p]),
+    ("fastpi_upload_plan", c_int, [c_void_p, c_void_p]),
+    ("fastpi_svd", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    ("fastpi_apply", c_int, [c_void_p, c_int64, c_int64, c_int64, c_void_p, c_void_p, c_void_p,
+                             c_int64, c_void_p, c_void_p]),
+    ("fastpi_stage_output", c_int, [c_void_p, c_int, c_void_p, c_int64]),
+    ("fastpi_syev_top", c_int, [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p]),
+    ("fastpi_sync", c_int, [c_void_p]),
+    ("fastpi_last_sweeps", c_int, [c_void_p, c_void_p]),
+    ("fastpi_last_error", ctypes.c_char_p, []),
+]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads the library once; raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FastPIError(-7, f"{path} is not built; run paper_2011_04235_amd/build.py "
+                              "or __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    for name, res, args in SIGNATURES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code):
+    if code != 0:
+        msg = load().fastpi_last_error()
+        raise FastPIError(code, msg.decode() if msg else "")
+
+
+def _ptr(a: np.ndarray):
+    return c_void_p(a.ctypes.data) if a is not None else None
+
+
+def target_rank(alpha: float, x: int) -> int:
+    return int(load().fastpi_target_rank(float(alpha), int(x)))
+
+
+def reorder(m, n, indptr, indices, data=None, k=0.01):
+    """Host reordering (Algorithm 2). Returns (piT, piF, blocks[B, 4], split dict)."""
+    lib = load()
+    indptr = np.ascontiguousarray(indptr, dtype=np.int64)
+    indices = np.ascontiguousarray(indices, dtype=np.int32)
+    data = None if data is None else np.ascontiguousarray(data, dtype=np.float64)
+    piT = np.empty(m, dtype=np.int32)
+    piF = np.empty(n, dtype=np.int32)
+    nb = c_int64(0)
+    sp = Split()
+    _check(lib.fastpi_reorder(m, n, _ptr(indptr), _ptr(indices), _ptr(data), float(k), _ptr(piT),
+                              _ptr(piF), None, 0, ctypes.byref(nb), ctypes.byref(sp)))
+    blocks = np.empty((nb.value, 4), dtype=np.int64)
+    _check(lib.fastpi_reorder(m, n, _ptr(indptr), _ptr(indices), _ptr(data), float(k), _ptr(piT),
+                              _ptr(piF), _ptr(blocks), nb.value, ctypes.byref(nb), ctypes.byref(sp)))
+    return piT, piF, blocks, sp.as_dict()
+
+
+class Plan:
+    """Reordering + ranks + value maps for one pattern and one alpha (host, C++)."""
+
+    def __init__(self, m, n, indptr, indices, data=None, alpha=0.2, k=0.01):
+        lib = load()
+        indptr = np.ascontiguousarray(indptr, dtype=np.int64)
+        indices = np.ascontiguousarray(indices, dtype=np.int32)
+        data = None if data is None else np.ascontiguousarray(data, dtype=np.float64)
+        h = c_void_p()
+        _check(lib.fastpi_plan_create(ctypes.byref(h), int(m), int(n), _ptr(indptr), _ptr(indices),
+                                      _ptr(data), float(alpha), float(k)))
+        self._h = h
+        self.alpha = alpha
+        self.k = k
+        sp = Split()
+        _check(lib.fastpi_plan_info(h, ctypes.byref(sp)))
+        self.info = sp.as_dict()
+
+    def __getattr__(self, name):
+        info = self.__dict__.get("info")
+        if info is not None and name in info:
+            return info[name]
+        raise AttributeError(name)
+
+    def permutation(self):
+        piT = np.empty(self.info["m"], dtype=np.int32)
+        piF = np.empty(self.info["n"], dtype=np.int32)
+        _check(load().fastpi_plan_permutation(self._h, _ptr(piT), _ptr(piF)))
+        return piT, piF
+
+    def blocks(self):
+        out = np.empty((self.info["B"], 4), dtype=np.int64)
+        if self.info["B"]:
+            _check(load().fastpi_plan_blocks(self._h, _ptr(out)))
+        return out
+
+    def block_ranks(self):
+        out = np.empty(self.info["B"], dtype=np.int64)
+        if self.info["B"]:
+            _check(load().fastpi_plan_block_ranks(self._h, _ptr(out)))
+        return out
+
+    def __del__(self):
+        h = self.__dict__.get("_h")
+        if h is not None and _lib is not None:
+            _lib.fastpi_plan_destroy(h)
+            self._h = None
+
+
+def _dptr(t):
+    return c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Handle:
+    """Device handle bound to a torch device and its current stream."""
+
+    def __init__(self, device=0, precision="fp64", max_sweeps=0, tol=0.0, max_workspace_bytes=0,
+                 stream=None):
+        import torch
+        lib = load()
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        opts = Options(FP64 if precision == "fp64" else MIXED, int(max_sweeps), float(tol),
+                       int(max_workspace_bytes))
+        h = c_void_p()
+        _check(lib.fastpi_create(ctypes.byref(h), int(device), c_void_p(stream.cuda_stream),
+                                 ctypes.byref(opts)))
+        self._h = h
+        self.plan = None
+
+    def set_precision(self, precision):
+        _check(load().fastpi_set_precision(self._h, FP64 if precision == "fp64" else MIXED))
+
+    def upload_plan(self, plan: Plan):
+        _check(load().fastpi_upload_plan(self._h, plan._h))
+        self.plan = plan
+
+    def svd(self, rowptr, col, val, out=None):
+        """Low-rank SVD of the uploaded plan's matrix; device tensors in, (U, S, V) out."""
+        torch = self.torch
+        info = self.plan.info
+        m, n, r = info["m"], info["n"], info["r"]
+        if out is None:
+            U = torch.empty((m, r), dtype=torch.float64, device=self.device)
+            S = torch.empty((r,), dtype=torch.float64, device=self.device)
+            V = torch.empty((n, r), dtype=torch.float64, device=self.device)
+        else:
+            U, S, V = out
+        for t in (rowptr, col, val, U, S, V):
+            assert t.is_contiguous() and t.device == self.device
+        assert rowptr.dtype == torch.int64 and col.dtype == torch.int32 and val.dtype == torch.float64
+        _check(load().fastpi_svd(self._h, _dptr(rowptr), _dptr(col), _dptr(val), _dptr(U), _dptr(S),
+                                 _dptr(V)))
+        return U, S, V
+
+    def apply(self, U, S, V, Y, out=None):
+        torch = self.torch
+        m, r = U.shape
+        n = V.shape[0]
+        L = Y.shape[1]
+        Z = torch.empty((n, L), dtype=torch.float64, device=self.device) if out is None else out
+        for t in (U, S, V, Y, Z):
+            assert t.is_contiguous() and t.dtype == torch.float64 and t.device == self.device
+        _check(load().fastpi_apply(self._h, m, n, r, _dptr(U), _dptr(S), _dptr(V), L, _dptr(Y),
+                                   _dptr(Z)))
+        return Z
+
+    def stage_output(self, which):
+        torch = self.torch
+        info = self.plan.info
+        sizes = {0: (info["s_b"],), 1: (info["s"],), 2: (info["n1"], info["s"]),
+                 3: (info["m"], info["s"])}
+        out = torch.empty(sizes[which], dtype=torch.float64, device=self.device)
+        _check(load().fastpi_stage_output(self._h, int(which), _dptr(out), out.numel()))
+        return out
+
+    def syev_top(self, G, t):
+        torch = self.torch
+        q = G.shape[0]
+        vals = torch.empty((t,), dtype=torch.float64, device=self.device)
+        vecs = torch.empty((q, t), dtype=torch.float64, device=self.device)
+        _check(load().fastpi_syev_top(self._h, q, _dptr(G), t, _dptr(vals), _dptr(vecs)))
+        return vals, vecs
+
+    def sync(self):
+        _check(load().fastpi_sync(self._h))
+
+    def last_sweeps(self):
+        out = np.zeros(3, dtype=np.int32)
+        _check(load().fastpi_last_sweeps(self._h, _ptr(out)))
+        return out.tolist()
+
+    def __del__(self):
+        h = self.__dict__.get("_h")
+        if h is not None and _lib is not None:
+            _lib.fastpi_destroy(h)
+            self._h = None

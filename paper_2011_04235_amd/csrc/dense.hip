@@ -1,0 +1,172 @@
+// Dense FP64 contractions of the update and apply steps (Eqs. 2-3, Problem 1).
+//
+// On gfx950 the FP64 matrix-core peak equals the FP64 vector-FMA peak (78.6 TFLOP/s), so
+// these are register-tiled FMA kernels: a 256-thread workgroup computes a 64 x 64 tile of C,
+// each thread a 4 x 4 micro-tile, with 16-deep slices of A and B staged in LDS.
+//
+//   gemm_tn : C_part[z] = A[kz]^T B[kz]  (A: K x M, B: K x N, both row-major; split over K)
+//   gemm_nn : C[ci(i)] = A[ai(i)] B        (A: M x K row-major with optional row gather,
+//                                            B: K x N row-major, optional C row scatter)
+#include "device_common.h"
+#include "kernels.h"
+
+namespace fastpi {
+
+constexpr int TM = 64, TN = 64, TK = 16;
+
+__global__ __launch_bounds__(256) void k_gemm_tn(const double* __restrict__ A, int64_t lda,
+                                                 const double* __restrict__ B, int64_t ldb,
+                                                 int64_t M, int64_t N, int64_t K, int64_t kchunk,
+                                                 double* __restrict__ Cpart) {
+    __shared__ double As[TK][TM + 2];
+    __shared__ double Bs[TK][TN + 2];
+    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * TM;
+    const int64_t j0 = static_cast<int64_t>(blockIdx.y) * TN;
+    const int64_t kb = static_cast<int64_t>(blockIdx.z) * kchunk;
+    const int64_t ke = min(K, kb + kchunk);
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    double acc[4][4] = {};
+    for (int64_t k0 = kb; k0 < ke; k0 += TK) {
+        for (int e = threadIdx.x; e < TK * TM; e += 256) {
+            const int kk = e / TM, ii = e % TM;
+            const int64_t k = k0 + kk, i = i0 + ii;
+            As[kk][ii] = (k < ke && i < M) ? A[k * lda + i] : 0.0;
+        }
+        for (int e = threadIdx.x; e < TK * TN; e += 256) {
+            const int kk = e / TN, jj = e % TN;
+            const int64_t k = k0 + kk, j = j0 + jj;
+            Bs[kk][jj] = (k < ke && j < N) ? B[k * ldb + j] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < TK; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a[u] = As[kk][ty * 4 + u];
+                b[u] = Bs[kk][tx * 4 + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+        }
+        __syncthreads();
+    }
+    double* C = Cpart + static_cast<int64_t>(blockIdx.z) * M * N;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t i = i0 + ty * 4 + u;
+        if (i >= M) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t j = j0 + tx * 4 + v;
+            if (j < N) C[i * N + j] = acc[u][v];
+        }
+    }
+}
+
+// C[i*ldc + j] = rs[i] * cs[j] * sum_z Cpart[z][i][j]  (rs, cs may be null = 1)
+__global__ void k_reduce_parts(const double* __restrict__ Cpart, int nsplit, int64_t M, int64_t N,
+                               double* __restrict__ C, int64_t ldc, const double* __restrict__ rs,
+                               const double* __restrict__ cs) {
+    const int64_t n = M * N;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += stride) {
+        double acc = 0;
+        for (int z = 0; z < nsplit; ++z) acc += Cpart[static_cast<int64_t>(z) * n + e];
+        const int64_t i = e / N, j = e % N;
+        if (rs) acc *= rs[i];
+        if (cs) acc *= cs[j];
+        C[i * ldc + j] = acc;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gemm_nn(const double* __restrict__ A, int64_t lda,
+                                                 const int* __restrict__ arow,
+                                                 const double* __restrict__ B, int64_t ldb,
+                                                 int64_t M, int64_t N, int64_t K,
+                                                 double* __restrict__ C, int64_t ldc,
+                                                 const int* __restrict__ crow) {
+    __shared__ double As[TK][TM + 2];
+    __shared__ double Bs[TK][TN + 2];
+    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * TM;
+    const int64_t j0 = static_cast<int64_t>(blockIdx.y) * TN;
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    double acc[4][4] = {};
+    for (int64_t k0 = 0; k0 < K; k0 += TK) {
+        for (int e = threadIdx.x; e < TK * TM; e += 256) {
+            const int ii = e / TK, kk = e % TK;
+            const int64_t k = k0 + kk, i = i0 + ii;
+            double v = 0.0;
+            if (k < K && i < M) {
+                const int64_t ar = arow ? arow[i] : i;
+                v = A[ar * lda + k];
+            }
+            As[kk][ii] = v;
+        }
+        for (int e = threadIdx.x; e < TK * TN; e += 256) {
+            const int kk = e / TN, jj = e % TN;
+            const int64_t k = k0 + kk, j = j0 + jj;
+            Bs[kk][jj] = (k < K && j < N) ? B[k * ldb + j] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < TK; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a[u] = As[kk][ty * 4 + u];
+                b[u] = Bs[kk][tx * 4 + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t i = i0 + ty * 4 + u;
+        if (i >= M) continue;
+        const int64_t ci = crow ? crow[i] : i;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t j = j0 + tx * 4 + v;
+            if (j < N) C[ci * ldc + j] = acc[u][v];
+        }
+    }
+}
+
+int gemm_tn_splits(int64_t M, int64_t N, int64_t K) {
+    // enough workgroups to cover the chip (~4 per CU), chunks of at least 256 rows of K
+    const int64_t tiles = ((M + TM - 1) / TM) * ((N + TN - 1) / TN);
+    int64_t splits = (1024 + tiles - 1) / tiles;
+    splits = std::min<int64_t>(splits, (K + 255) / 256);
+    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(splits, 256)));
+}
+
+void launch_gemm_tn(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M,
+                    int64_t N, int64_t K, double* C, int64_t ldc, const double* rs,
+                    const double* cs, double* part, int nsplit, hipStream_t st) {
+    if (M <= 0 || N <= 0) return;
+    const int64_t kchunk = ((K + nsplit - 1) / nsplit + TK - 1) / TK * TK;
+    dim3 grid(static_cast<unsigned>((M + TM - 1) / TM), static_cast<unsigned>((N + TN - 1) / TN),
+              static_cast<unsigned>(nsplit));
+    hipLaunchKernelGGL(k_gemm_tn, grid, dim3(256), 0, st, A, lda, B, ldb, M, N, K,
+                       std::max<int64_t>(kchunk, TK), part);
+    const int64_t n = M * N;
+    hipLaunchKernelGGL(k_reduce_parts, dim3(static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 8192))),
+                       dim3(256), 0, st, part, nsplit, M, N, C, ldc, rs, cs);
+}
+
+void launch_gemm_nn(const double* A, int64_t lda, const int* arow, const double* B, int64_t ldb,
+                    int64_t M, int64_t N, int64_t K, double* C, int64_t ldc, const int* crow,
+                    hipStream_t st) {
+    if (M <= 0 || N <= 0) return;
+    dim3 grid(static_cast<unsigned>((M + TM - 1) / TM), static_cast<unsigned>((N + TN - 1) / TN));
+    hipLaunchKernelGGL(k_gemm_nn, grid, dim3(256), 0, st, A, lda, arow, B, ldb, M, N, K, C, ldc, crow);
+}
+
+}  // namespace fastpi

@@ -1,0 +1,65 @@
+// Host-callable launchers of the HIP kernels (all stream-ordered, none synchronises unless
+// stated).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <vector>
+
+#include "host_internal.h"
+
+namespace fastpi {
+
+void launch_fill(double* p, int64_t n, double v, hipStream_t st);
+void launch_fill_i32(int* p, int64_t n, int v, hipStream_t st);
+void launch_gather(const double* val, const int64_t* dst0, const int64_t* dst1, int64_t nnz,
+                   double* out, int* status, hipStream_t st);
+
+void launch_block_svd(bool fp32, const BlockWork* work, int first, int count, const double* blk,
+                      void* gscratch, const int64_t* gscratch_off, int lds_bytes, double* U1,
+                      double* sig1, double* V1, int max_sweeps, double tol_scale,
+                      int* sweeps_used, int* status, hipStream_t st);
+
+// eigensolver (eig.hip)
+int64_t eig_padded_order(int64_t q);
+size_t eig_workspace_doubles(int64_t q);
+void eig_pair_table(int64_t q, std::vector<int2>& out);
+int eig_top(const double* G, int64_t q, int64_t t, double* vals, double* vecs, double* ws,
+            int* iws, const int2* pair_tables, int max_sweeps, double tol, int inner_sweeps,
+            int* sweeps_out, int* host_counter, hipStream_t st);
+
+// dense (dense.hip)
+int gemm_tn_splits(int64_t M, int64_t N, int64_t K);
+void launch_gemm_tn(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M,
+                    int64_t N, int64_t K, double* C, int64_t ldc, const double* rs,
+                    const double* cs, double* part, int nsplit, hipStream_t st);
+void launch_gemm_nn(const double* A, int64_t lda, const int* arow, const double* B, int64_t ldb,
+                    int64_t M, int64_t N, int64_t K, double* C, int64_t ldc, const int* crow,
+                    hipStream_t st);
+
+// sparse and block-structured (sparse.hip)
+void launch_sparse_gram(const int64_t* colptr, const int* rowidx, const double* cval,
+                        const int64_t* rowptr, const int* colidx, const double* rval, int64_t q,
+                        double* G, int64_t ldg, bool accumulate, hipStream_t st);
+void launch_sparse_proj(const int64_t* colptr, const int* rowidx, const double* cval, int64_t ncols,
+                        const double* U, int64_t s, const double* sigma, double* G, int64_t ldg,
+                        int64_t off, hipStream_t st);
+void launch_spmm_rows(const int64_t* rowptr, const int* colidx, const double* rval, int64_t M,
+                      const int* srow, const double* B, int64_t N, const double* cs, double* C,
+                      int64_t ldc, const int* crow, bool accumulate, hipStream_t st);
+void launch_blockdiag_gram(const BlockWork* work, int nwork, const double* V1, const double* sig1,
+                           double* G, int64_t ldg, hipStream_t st);
+void launch_u2_top(const BlockWork* work, int nwork, const double* U1, const double* sig1,
+                   const double* V1, const double* V2, int64_t s, const double* inv_sig2,
+                   double* U2, int* status, hipStream_t st);
+void launch_sqrt_inv(const double* lam, int64_t t, double rel_cut, double* sigma, double* inv,
+                     hipStream_t st);
+void launch_col_coeffs(const double* Vt, int64_t s, int64_t n2, int64_t r, const double* sig2,
+                       const double* inv3, double* C1, double* C2, hipStream_t st);
+void launch_copy_rows(const double* src, int64_t rows, int64_t cols, const int* dst_row, double* dst,
+                      hipStream_t st);
+void launch_pinv_sigma(const double* S, int64_t r, double cut, double* inv, hipStream_t st);
+
+}  // namespace fastpi

@@ -1,0 +1,172 @@
+// Planner: reordering, per-block ranks (Eq. 1), stage ranks (Eqs. 2-3) and the index maps
+// that move the caller's CSR values into the device layout. Host only; integer work.
+#include <algorithm>
+#include <numeric>
+
+#include "host_internal.h"
+
+namespace fastpi {
+
+int build_plan(Plan& p, int64_t m, int64_t n, const int64_t* rowptr, const int32_t* col,
+               const double* val, double alpha, double k) {
+    if (!(alpha > 0.0 && alpha <= 1.0)) {
+        set_error("alpha must lie in (0, 1]");
+        return FASTPI_EINVAL;
+    }
+    int st = validate_csr(m, n, rowptr, col, val);
+    if (st != FASTPI_OK) return st;
+    st = reorder_pattern(m, n, rowptr, col, val, k, p.ro);
+    if (st != FASTPI_OK) return st;
+    p.m = m;
+    p.n = n;
+    p.nnz = rowptr[m];
+    p.alpha = alpha;
+    p.k = k;
+    const ReorderOut& R = p.ro;
+    const int64_t m1 = R.m1, n1 = R.n1, m2 = R.m2, n2 = R.n2;
+    const int64_t B = static_cast<int64_t>(R.blocks.size());
+
+    // ranks: s_i = min(ceil(alpha n_i), m_i, n_i); s = min(ceil(alpha n1), s_b + m2, n1);
+    // r = min(ceil(alpha min(m, n)), s + n2, m)
+    p.block_rank.assign(B, 0);
+    p.work.clear();
+    int64_t blk = 0, u1 = 0, v1 = 0, sb = 0;
+    for (int64_t b = 0; b < B; ++b) {
+        const BlockDesc& d = R.blocks[b];
+        if (d.rows == 0 || d.cols == 0) continue;
+        const int64_t si = std::min({target_rank(alpha, d.cols), d.rows, d.cols});
+        p.block_rank[b] = si;
+        BlockWork w{};
+        w.data_off = blk;
+        w.u_off = u1;
+        w.v_off = v1;
+        w.rows = static_cast<int32_t>(d.rows);
+        w.cols = static_cast<int32_t>(d.cols);
+        w.rank = static_cast<int32_t>(si);
+        w.sig_off = static_cast<int32_t>(sb);
+        w.row0 = static_cast<int32_t>(d.row0);
+        w.col0 = static_cast<int32_t>(d.col0);
+        p.work.push_back(w);
+        blk += d.rows * d.cols;
+        u1 += d.rows * si;
+        v1 += d.cols * si;
+        sb += si;
+    }
+    p.B_dense = static_cast<int64_t>(p.work.size());
+    p.blk_elems = blk;
+    p.u1_elems = u1;
+    p.v1_elems = v1;
+    p.s_b = sb;
+    p.s = std::min({target_rank(alpha, n1), sb + m2, n1});
+    p.r = std::min({target_rank(alpha, std::min(m, n)), p.s + n2, m});
+    // largest Jacobi cost first (p q^2 with p >= q), ties by block order
+    std::stable_sort(p.work.begin(), p.work.end(), [](const BlockWork& a, const BlockWork& b) {
+        auto cost = [](const BlockWork& w) {
+            const int64_t pp = std::max(w.rows, w.cols), qq = std::min(w.rows, w.cols);
+            return pp * qq * qq;
+        };
+        return cost(a) > cost(b);
+    });
+
+    // inverse permutations and the block id of every spoke row
+    p.invT.assign(m, 0);
+    p.invF.assign(n, 0);
+    for (int64_t i = 0; i < m; ++i) p.invT[R.piT[i]] = static_cast<int32_t>(i);
+    for (int64_t j = 0; j < n; ++j) p.invF[R.piF[j]] = static_cast<int32_t>(j);
+    std::vector<int64_t> row_blk(m1, -1), blk_data(B, -1);
+    for (int64_t b = 0; b < B; ++b) {
+        const BlockDesc& d = R.blocks[b];
+        for (int64_t i = d.row0; i < d.row0 + d.rows; ++i) row_blk[i] = b;
+    }
+    {
+        int64_t off = 0;
+        for (int64_t b = 0; b < B; ++b) {
+            const BlockDesc& d = R.blocks[b];
+            if (d.rows == 0 || d.cols == 0) continue;
+            blk_data[b] = off;
+            off += d.rows * d.cols;
+        }
+    }
+
+    // count A21 and T entries per row / column (new ids), skipping stored zeros
+    const int64_t nnz = rowptr[m];
+    p.dst0.assign(nnz, -1);
+    p.dst1.assign(nnz, -1);
+    p.a21_rowptr.assign(m2 + 1, 0);
+    p.a21_colptr.assign(n1 + 1, 0);
+    p.t_rowptr.assign(m + 1, 0);
+    p.t_colptr.assign(n2 + 1, 0);
+    for (int64_t i = 0; i < m; ++i) {
+        const int64_t ni = R.piT[i];
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            if (val && val[e] == 0.0) continue;
+            const int64_t nj = R.piF[col[e]];
+            if (nj >= n1) {
+                p.t_rowptr[ni + 1]++;
+                p.t_colptr[nj - n1 + 1]++;
+            } else if (ni >= m1) {
+                p.a21_rowptr[ni - m1 + 1]++;
+                p.a21_colptr[nj + 1]++;
+            }
+        }
+    }
+    for (int64_t i = 0; i < m2; ++i) p.a21_rowptr[i + 1] += p.a21_rowptr[i];
+    for (int64_t j = 0; j < n1; ++j) p.a21_colptr[j + 1] += p.a21_colptr[j];
+    for (int64_t i = 0; i < m; ++i) p.t_rowptr[i + 1] += p.t_rowptr[i];
+    for (int64_t j = 0; j < n2; ++j) p.t_colptr[j + 1] += p.t_colptr[j];
+    const int64_t nnz21 = p.a21_rowptr[m2], nnzT = p.t_rowptr[m];
+    p.off_a21r = blk;
+    p.off_a21c = p.off_a21r + nnz21;
+    p.off_tr = p.off_a21c + nnz21;
+    p.off_tc = p.off_tr + nnzT;
+    p.val_elems = p.off_tc + nnzT;
+    p.a21_colidx.assign(nnz21, 0);
+    p.a21_rowidx.assign(nnz21, 0);
+    p.t_colidx.assign(nnzT, 0);
+    p.t_rowidx.assign(nnzT, 0);
+
+    // Row-major fill: visiting new rows in ascending order and, inside a row, columns in
+    // ascending new id gives sorted CSR rows; the CSC fill in the same visiting order gives
+    // ascending row ids inside every column.
+    std::vector<int64_t> fill21r(p.a21_rowptr.begin(), p.a21_rowptr.end() - 1);
+    std::vector<int64_t> fill21c(p.a21_colptr.begin(), p.a21_colptr.end() - 1);
+    std::vector<int64_t> filltr(p.t_rowptr.begin(), p.t_rowptr.end() - 1);
+    std::vector<int64_t> filltc(p.t_colptr.begin(), p.t_colptr.end() - 1);
+    std::vector<std::pair<int32_t, int64_t>> rowbuf;
+    for (int64_t ni = 0; ni < m; ++ni) {
+        const int64_t i = p.invT[ni];
+        rowbuf.clear();
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            if (val && val[e] == 0.0) continue;
+            rowbuf.emplace_back(R.piF[col[e]], e);
+        }
+        std::sort(rowbuf.begin(), rowbuf.end());
+        for (const auto& pr : rowbuf) {
+            const int64_t nj = pr.first, e = pr.second;
+            if (nj >= n1) {
+                const int64_t tr = filltr[ni]++, tc = filltc[nj - n1]++;
+                p.t_colidx[tr] = static_cast<int32_t>(nj - n1);
+                p.t_rowidx[tc] = static_cast<int32_t>(ni);
+                p.dst0[e] = p.off_tr + tr;
+                p.dst1[e] = p.off_tc + tc;
+            } else if (ni >= m1) {
+                const int64_t ar = fill21r[ni - m1]++, ac = fill21c[nj]++;
+                p.a21_colidx[ar] = static_cast<int32_t>(nj);
+                p.a21_rowidx[ac] = static_cast<int32_t>(ni - m1);
+                p.dst0[e] = p.off_a21r + ar;
+                p.dst1[e] = p.off_a21c + ac;
+            } else {
+                const int64_t b = row_blk[ni];
+                const BlockDesc& d = R.blocks[b];
+                if (b < 0 || nj < d.col0 || nj >= d.col0 + d.cols) {
+                    set_error("internal: A11 entry outside its diagonal block");
+                    return FASTPI_EINTERNAL;
+                }
+                p.dst0[e] = blk_data[b] + (nj - d.col0) * d.rows + (ni - d.row0);
+            }
+        }
+    }
+    return FASTPI_OK;
+}
+
+}  // namespace fastpi

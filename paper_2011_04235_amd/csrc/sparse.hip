@@ -1,0 +1,307 @@
+// Sparse and block-structured kernels of the incremental updates (Eqs. 2 and 3).
+// Every reduction runs in a fixed order (no floating-point atomics), so results are
+// reproducible bit for bit.
+#include "device_common.h"
+#include "kernels.h"
+
+namespace fastpi {
+
+// G[a, c0:c1] (+)= sum_h S[h, a] S[h, c0:c1] for a sparse S given as CSC (colptr, rowidx,
+// cval) and CSR (rowptr, colidx, rval). One wave owns one (row a, column chunk) of G and
+// accumulates it in LDS, visiting the rows h of column a in ascending order.
+constexpr int SG_WAVES = 4;
+__global__ __launch_bounds__(SG_WAVES * 64) void k_sparse_gram(
+    const int64_t* __restrict__ colptr, const int* __restrict__ rowidx, const double* __restrict__ cval,
+    const int64_t* __restrict__ rowptr, const int* __restrict__ colidx, const double* __restrict__ rval,
+    int64_t q, int64_t chunk, double* __restrict__ G, int64_t ldg, int accumulate) {
+    extern __shared__ double buf_all[];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t nchunks = (q + chunk - 1) / chunk;
+    const int64_t task = static_cast<int64_t>(blockIdx.x) * SG_WAVES + wave;
+    if (task >= q * nchunks) return;
+    const int64_t a = task / nchunks;
+    const int64_t c0 = (task % nchunks) * chunk;
+    const int64_t c1 = min(q, c0 + chunk);
+    double* buf = buf_all + static_cast<int64_t>(wave) * chunk;
+    double* Grow = G + a * ldg;
+    for (int64_t c = c0 + lane; c < c1; c += kWave) buf[c - c0] = accumulate ? Grow[c] : 0.0;
+    __builtin_amdgcn_wave_barrier();
+    for (int64_t e = colptr[a]; e < colptr[a + 1]; ++e) {
+        const int64_t h = rowidx[e];
+        const double va = cval[e];
+        for (int64_t f = rowptr[h] + lane; f < rowptr[h + 1]; f += kWave) {
+            const int64_t b = colidx[f];
+            if (b >= c0 && b < c1) buf[b - c0] += va * rval[f];
+        }
+        // the next row may touch the same entries from other lanes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    for (int64_t c = c0 + lane; c < c1; c += kWave) Grow[c] = buf[c - c0];
+}
+
+void launch_sparse_gram(const int64_t* colptr, const int* rowidx, const double* cval,
+                        const int64_t* rowptr, const int* colidx, const double* rval, int64_t q,
+                        double* G, int64_t ldg, bool accumulate, hipStream_t st) {
+    if (q <= 0) return;
+    const int64_t chunk = std::min<int64_t>(q, 2048);
+    const int64_t tasks = q * ((q + chunk - 1) / chunk);
+    const size_t lds = static_cast<size_t>(SG_WAVES) * chunk * sizeof(double);
+    hipLaunchKernelGGL(k_sparse_gram, dim3(static_cast<unsigned>((tasks + SG_WAVES - 1) / SG_WAVES)),
+                       dim3(SG_WAVES * 64), lds, st, colptr, rowidx, cval, rowptr, colidx, rval, q,
+                       chunk, G, ldg, accumulate ? 1 : 0);
+}
+
+// P[:, j] = sigma .* (U^T S[:, j]) for a sparse S (CSC) and row-major U (rows x s); written
+// into G at G[k, off + j] and mirrored at G[off + j, k]. One wave per column j; the lanes
+// run over k, the rows of column j in ascending order.
+__global__ __launch_bounds__(256) void k_sparse_proj(const int64_t* __restrict__ colptr,
+                                                     const int* __restrict__ rowidx,
+                                                     const double* __restrict__ cval,
+                                                     int64_t ncols, const double* __restrict__ U,
+                                                     int64_t s, const double* __restrict__ sigma,
+                                                     double* __restrict__ G, int64_t ldg, int64_t off) {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * 4 + wave;
+    if (j >= ncols) return;
+    for (int64_t k0 = 0; k0 < s; k0 += 8 * kWave) {
+        double acc[8] = {};
+        for (int64_t e = colptr[j]; e < colptr[j + 1]; ++e) {
+            const int64_t h = rowidx[e];
+            const double v = cval[e];
+            const double* Uh = U + h * s;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t k = k0 + u * kWave + lane;
+                if (k < s) acc[u] += v * Uh[k];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t k = k0 + u * kWave + lane;
+            if (k < s) {
+                const double val = acc[u] * sigma[k];
+                G[k * ldg + off + j] = val;
+                G[(off + j) * ldg + k] = val;
+            }
+        }
+    }
+}
+
+void launch_sparse_proj(const int64_t* colptr, const int* rowidx, const double* cval, int64_t ncols,
+                        const double* U, int64_t s, const double* sigma, double* G, int64_t ldg,
+                        int64_t off, hipStream_t st) {
+    if (ncols <= 0 || s <= 0) return;
+    hipLaunchKernelGGL(k_sparse_proj, dim3(static_cast<unsigned>((ncols + 3) / 4)), dim3(256), 0, st,
+                       colptr, rowidx, cval, ncols, U, s, sigma, G, ldg, off);
+}
+
+// C[crow(i), :] (+)= cs .* (S[srow(i), :] B) for a sparse S (CSR) and row-major B (K x N).
+// One wave per output row; lanes over the N columns.
+__global__ __launch_bounds__(256) void k_spmm_rows(const int64_t* __restrict__ rowptr,
+                                                   const int* __restrict__ colidx,
+                                                   const double* __restrict__ rval, int64_t M,
+                                                   const int* __restrict__ srow,
+                                                   const double* __restrict__ B, int64_t N,
+                                                   const double* __restrict__ cs,
+                                                   double* __restrict__ C, int64_t ldc,
+                                                   const int* __restrict__ crow, int accumulate) {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 4 + wave;
+    if (i >= M) return;
+    const int64_t h = srow ? srow[i] : i;
+    const int64_t ci = crow ? crow[i] : i;
+    double* Crow = C + ci * ldc;
+    for (int64_t k0 = 0; k0 < N; k0 += 8 * kWave) {
+        double acc[8] = {};
+        for (int64_t e = rowptr[h]; e < rowptr[h + 1]; ++e) {
+            const double v = rval[e];
+            const double* Bb = B + static_cast<int64_t>(colidx[e]) * N;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t k = k0 + u * kWave + lane;
+                if (k < N) acc[u] += v * Bb[k];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t k = k0 + u * kWave + lane;
+            if (k < N) {
+                double val = acc[u];
+                if (cs) val *= cs[k];
+                Crow[k] = accumulate ? Crow[k] + val : val;
+            }
+        }
+    }
+}
+
+void launch_spmm_rows(const int64_t* rowptr, const int* colidx, const double* rval, int64_t M,
+                      const int* srow, const double* B, int64_t N, const double* cs, double* C,
+                      int64_t ldc, const int* crow, bool accumulate, hipStream_t st) {
+    if (M <= 0 || N <= 0) return;
+    hipLaunchKernelGGL(k_spmm_rows, dim3(static_cast<unsigned>((M + 3) / 4)), dim3(256), 0, st, rowptr,
+                       colidx, rval, M, srow, B, N, cs, C, ldc, crow, accumulate ? 1 : 0);
+}
+
+// Diagonal blocks of V1 Sigma1^2 V1^T into G2 (n1 x n1): one workgroup per dense block.
+__global__ __launch_bounds__(256) void k_blockdiag_gram(const BlockWork* __restrict__ work,
+                                                        const double* __restrict__ V1,
+                                                        const double* __restrict__ sig1,
+                                                        double* __restrict__ G, int64_t ldg) {
+    const BlockWork w = work[blockIdx.x];
+    const int nb = w.cols, sb = w.rank;
+    const double* Vb = V1 + w.v_off;   // nb x sb, column-major
+    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+        const int a = e / nb, b = e % nb;
+        double acc = 0;
+        for (int k = 0; k < sb; ++k) {
+            const double sk = sig1[w.sig_off + k];
+            acc += Vb[static_cast<int64_t>(k) * nb + a] * (sk * sk) * Vb[static_cast<int64_t>(k) * nb + b];
+        }
+        G[static_cast<int64_t>(w.col0 + a) * ldg + w.col0 + b] = acc;
+    }
+}
+
+void launch_blockdiag_gram(const BlockWork* work, int nwork, const double* V1, const double* sig1,
+                           double* G, int64_t ldg, hipStream_t st) {
+    if (nwork <= 0) return;
+    hipLaunchKernelGGL(k_blockdiag_gram, dim3(nwork), dim3(256), 0, st, work, V1, sig1, G, ldg);
+}
+
+// Top rows of U2 (Eq. 2): for block i, U2[row0 + r, :] = U_i[r, :] (Sigma_i V_i^T V2[col0:, :]
+// Sigma2^-1). The KC x S_CH intermediate lives in LDS; the block rank runs in chunks of KC
+// and the columns of U2 in chunks of S_CH.
+constexpr int S_CH = 128;
+constexpr int KC = 32;
+__global__ __launch_bounds__(256) void k_u2_top(const BlockWork* __restrict__ work,
+                                                const double* __restrict__ U1,
+                                                const double* __restrict__ sig1,
+                                                const double* __restrict__ V1,
+                                                const double* __restrict__ V2, int64_t s,
+                                                const double* __restrict__ inv_sig2,
+                                                double* __restrict__ U2, int* status) {
+    __shared__ double Tm[KC][S_CH + 1];
+    const BlockWork w = work[blockIdx.x];
+    const int mb = w.rows, nb = w.cols, sb = w.rank;
+    (void)status;
+    const double* Ub = U1 + w.u_off;   // mb x sb col-major
+    const double* Vb = V1 + w.v_off;   // nb x sb col-major
+    for (int64_t c0 = 0; c0 < s; c0 += S_CH) {
+        const int nc = static_cast<int>(min<int64_t>(S_CH, s - c0));
+        for (int k0 = 0; k0 < sb || k0 == 0; k0 += KC) {
+            const int kc = min(KC, sb - k0);
+            for (int e = threadIdx.x; e < kc * nc; e += blockDim.x) {
+                const int k = e / nc, c = e % nc;
+                double acc = 0;
+                for (int a = 0; a < nb; ++a)
+                    acc += Vb[static_cast<int64_t>(k0 + k) * nb + a] *
+                           V2[static_cast<int64_t>(w.col0 + a) * s + c0 + c];
+                Tm[k][c] = acc * sig1[w.sig_off + k0 + k] * inv_sig2[c0 + c];
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < mb * nc; e += blockDim.x) {
+                const int r = e / nc, c = e % nc;
+                double acc = 0;
+                for (int k = 0; k < kc; ++k) acc += Ub[static_cast<int64_t>(k0 + k) * mb + r] * Tm[k][c];
+                double* dst = U2 + static_cast<int64_t>(w.row0 + r) * s + c0 + c;
+                *dst = k0 == 0 ? acc : *dst + acc;
+            }
+            __syncthreads();
+            if (sb == 0) break;
+        }
+    }
+}
+
+void launch_u2_top(const BlockWork* work, int nwork, const double* U1, const double* sig1,
+                   const double* V1, const double* V2, int64_t s, const double* inv_sig2,
+                   double* U2, int* status, hipStream_t st) {
+    if (nwork <= 0 || s <= 0) return;
+    hipLaunchKernelGGL(k_u2_top, dim3(nwork), dim3(256), 0, st, work, U1, sig1, V1, V2, s, inv_sig2,
+                       U2, status);
+}
+
+// sigma = sqrt(max(lam, 0)); inv = 1/sigma above the cut-off (else 0) -- for the rank
+// deficient case the corresponding columns are zero (their singular value is 0 in effect)
+__global__ void k_sqrt_inv(const double* __restrict__ lam, int64_t t, double rel_cut,
+                           double* __restrict__ sigma, double* __restrict__ inv) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= t) return;
+    const double l0 = lam[0] > 0 ? lam[0] : 0.0;
+    const double l = lam[k] > 0 ? lam[k] : 0.0;
+    const double sg = sqrt(l);
+    const bool keep = sg > rel_cut * sqrt(l0);
+    sigma[k] = keep ? sg : 0.0;
+    inv[k] = keep ? 1.0 / sg : 0.0;
+}
+
+void launch_sqrt_inv(const double* lam, int64_t t, double rel_cut, double* sigma, double* inv,
+                     hipStream_t st) {
+    if (t <= 0) return;
+    hipLaunchKernelGGL(k_sqrt_inv, dim3(static_cast<unsigned>((t + 255) / 256)), dim3(256), 0, st, lam, t,
+                       rel_cut, sigma, inv);
+}
+
+// C1 = diag(sig2) Vt[0:s, :] diag(inv3) (s x r) and C2 = Vt[s:, :] diag(inv3) (n2 x r)
+__global__ void k_col_coeffs(const double* __restrict__ Vt, int64_t s, int64_t n2, int64_t r,
+                             const double* __restrict__ sig2, const double* __restrict__ inv3,
+                             double* __restrict__ C1, double* __restrict__ C2) {
+    const int64_t n = (s + n2) * r;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += stride) {
+        const int64_t i = e / r, k = e % r;
+        const double v = Vt[e] * inv3[k];
+        if (i < s) C1[i * r + k] = v * sig2[i];
+        else C2[(i - s) * r + k] = v;
+    }
+}
+
+void launch_col_coeffs(const double* Vt, int64_t s, int64_t n2, int64_t r, const double* sig2,
+                       const double* inv3, double* C1, double* C2, hipStream_t st) {
+    const int64_t n = (s + n2) * r;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_col_coeffs, dim3(static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 8192))),
+                       dim3(256), 0, st, Vt, s, n2, r, sig2, inv3, C1, C2);
+}
+
+// V rows of the hub columns: V[invF[n1 + j], :] = Vt[s + j, :]
+__global__ void k_copy_rows(const double* __restrict__ src, int64_t rows, int64_t cols,
+                            const int* __restrict__ dst_row, double* __restrict__ dst) {
+    const int64_t n = rows * cols;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += stride) {
+        const int64_t i = e / cols, k = e % cols;
+        dst[static_cast<int64_t>(dst_row[i]) * cols + k] = src[e];
+    }
+}
+
+void launch_copy_rows(const double* src, int64_t rows, int64_t cols, const int* dst_row, double* dst,
+                      hipStream_t st) {
+    const int64_t n = rows * cols;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_copy_rows, dim3(static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 8192))),
+                       dim3(256), 0, st, src, rows, cols, dst_row, dst);
+}
+
+// S^+ for the apply: inv[k] = 1/S[k] if S[k] > cut * max(S) else 0
+__global__ void k_pinv_sigma(const double* __restrict__ S, int64_t r, double cut,
+                             double* __restrict__ inv) {
+    __shared__ double smax;
+    if (threadIdx.x == 0) {
+        double mx = 0;
+        for (int64_t k = 0; k < r; ++k) mx = S[k] > mx ? S[k] : mx;
+        smax = mx;
+    }
+    __syncthreads();
+    for (int64_t k = threadIdx.x; k < r; k += blockDim.x) {
+        const double v = S[k];
+        inv[k] = v > cut * smax ? 1.0 / v : 0.0;
+    }
+}
+
+void launch_pinv_sigma(const double* S, int64_t r, double cut, double* inv, hipStream_t st) {
+    if (r <= 0) return;
+    hipLaunchKernelGGL(k_pinv_sigma, dim3(1), dim3(256), 0, st, S, r, cut, inv);
+}
+
+}  // namespace fastpi
