@@ -43,8 +43,9 @@ struct DevicePlan {
     int64_t *dst0 = nullptr, *dst1 = nullptr, *gscratch_off = nullptr;
     int64_t *a21_rowptr = nullptr, *a21_colptr = nullptr, *t_rowptr = nullptr, *t_colptr = nullptr;
     int *a21_colidx = nullptr, *a21_rowidx = nullptr, *t_colidx = nullptr, *t_rowidx = nullptr;
-    int *piT = nullptr, *invF = nullptr;
+    int *piT = nullptr, *invT = nullptr, *invF = nullptr;
     int2 *pairs2 = nullptr, *pairs3 = nullptr;
+    SegDev seg_a21c{}, seg_a21r{}, seg_tc{}, seg_tr{};
 };
 
 constexpr int kSmallLds = 16 * 1024;
@@ -55,6 +56,7 @@ constexpr int kBigLds = 60 * 1024;
 struct fastpi_handle {
     int device = 0;
     hipStream_t stream = nullptr;
+    hipStream_t copy_stream = nullptr;   // side stream for reading convergence counters
     fastpi_options opts{};
     DevicePlan dp;
     std::vector<void*> plan_allocs;
@@ -67,7 +69,7 @@ struct fastpi_handle {
     int32_t sweeps[3] = {0, 0, 0};
     // offsets (in doubles) of the stage buffers inside ws
     int64_t o_vals, o_u1, o_v1, o_sig1, o_g2, o_v2, o_lam2, o_sig2, o_inv2, o_u2, o_g3, o_vt, o_lam3,
-        o_sig3, o_inv3, o_c1, o_c2, o_eig, o_part, o_gs, o_end;
+        o_sig3, o_inv3, o_c1, o_c2, o_eig, o_part, o_gs, o_spart, o_end;
     // apply scratch
     double* aws = nullptr;
     size_t aws_bytes = 0;
@@ -152,6 +154,37 @@ int ensure_iws(fastpi_handle* h, size_t bytes) {
     }
     h->iws = static_cast<int*>(p);
     h->iws_bytes = bytes;
+    return FASTPI_OK;
+}
+
+int upload_segments(fastpi_handle* h, const Segments& s, SegDev& d) {
+    int st;
+    const int32_t* p32 = nullptr;
+    const int64_t* p64 = nullptr;
+    d = SegDev{};
+    int32_t* owner = nullptr;
+    int32_t* pidx = nullptr;
+    int32_t* mo = nullptr;
+    int32_t* mp = nullptr;
+    int64_t* b = nullptr;
+    int64_t* e = nullptr;
+    (void)p32;
+    (void)p64;
+    if ((st = upload(h, owner, s.owner.data(), s.owner.size())) != FASTPI_OK) return st;
+    if ((st = upload(h, pidx, s.pidx.data(), s.pidx.size())) != FASTPI_OK) return st;
+    if ((st = upload(h, b, s.begin.data(), s.begin.size())) != FASTPI_OK) return st;
+    if ((st = upload(h, e, s.end.data(), s.end.size())) != FASTPI_OK) return st;
+    if ((st = upload(h, mo, s.multi_owner.data(), s.multi_owner.size())) != FASTPI_OK) return st;
+    if ((st = upload(h, mp, s.multi_ptr.data(), s.multi_ptr.size())) != FASTPI_OK) return st;
+    d.owner = owner;
+    d.pidx = pidx;
+    d.begin = b;
+    d.end = e;
+    d.multi_owner = mo;
+    d.multi_ptr = mp;
+    d.nseg = static_cast<int64_t>(s.owner.size());
+    d.nmulti = static_cast<int64_t>(s.multi_owner.size());
+    d.npart = s.npart;
     return FASTPI_OK;
 }
 
@@ -331,6 +364,13 @@ int fastpi_create(fastpi_handle** h, int device, void* hip_stream, const fastpi_
         return FASTPI_ENOMEM;
     }
     H->host_pinned = static_cast<int*>(p);
+    if (hipStreamCreateWithFlags(&H->copy_stream, hipStreamNonBlocking) != hipSuccess) {
+        hipFree(H->status);
+        hipHostFree(H->host_pinned);
+        delete H;
+        set_error("stream creation failed");
+        return FASTPI_EHIP;
+    }
     launch_fill_i32(H->status, 16, 0, H->stream);
     *h = H;
     return check_launch();
@@ -355,6 +395,7 @@ void fastpi_destroy(fastpi_handle* h) {
     if (h->aws) hipFree(h->aws);
     if (h->status) hipFree(h->status);
     if (h->host_pinned) hipHostFree(h->host_pinned);
+    if (h->copy_stream) hipStreamDestroy(h->copy_stream);
     delete h;
 }
 
@@ -421,6 +462,11 @@ int fastpi_upload_plan(fastpi_handle* h, const fastpi_plan* plan) {
     if ((st = upload(h, d.t_rowidx, p.t_rowidx.data(), p.t_rowidx.size())) != FASTPI_OK) return st;
     if ((st = upload(h, d.piT, p.ro.piT.data(), p.ro.piT.size())) != FASTPI_OK) return st;
     if ((st = upload(h, d.invF, p.invF.data(), p.invF.size())) != FASTPI_OK) return st;
+    if ((st = upload(h, d.invT, p.invT.data(), p.invT.size())) != FASTPI_OK) return st;
+    if ((st = upload_segments(h, p.seg_a21c, d.seg_a21c)) != FASTPI_OK) return st;
+    if ((st = upload_segments(h, p.seg_a21r, d.seg_a21r)) != FASTPI_OK) return st;
+    if ((st = upload_segments(h, p.seg_tc, d.seg_tc)) != FASTPI_OK) return st;
+    if ((st = upload_segments(h, p.seg_tr, d.seg_tr)) != FASTPI_OK) return st;
     std::vector<int2> t2, t3;
     if (d.n1 > 0) eig_pair_table(d.n1, t2);
     const int64_t q3 = d.s + d.n2;
@@ -458,11 +504,14 @@ int fastpi_upload_plan(fastpi_handle* h, const fastpi_plan* plan) {
     const int sp = gemm_tn_splits(s, s, m);
     h->o_part = take(static_cast<int64_t>(sp) * s * s);
     h->o_gs = take(gs);
+    const int64_t spart = std::max({p.seg_a21c.npart * n1, p.seg_tc.npart * std::max(n2, s),
+                                    p.seg_a21r.npart * s, p.seg_tr.npart * r, int64_t(1)});
+    h->o_spart = take(spart);
     h->o_end = o;
     st = ensure_ws(h, static_cast<size_t>(o) * sizeof(double));
     if (st != FASTPI_OK) return st;
-    const int64_t ld = std::max(eig_padded_order(std::max<int64_t>(n1, 1)), eig_padded_order(std::max<int64_t>(q3, 1)));
-    st = ensure_iws(h, static_cast<size_t>(ld + 4 + ld + 64) * sizeof(int));
+    st = ensure_iws(h, std::max(eig_int_workspace(std::max<int64_t>(n1, 1), h->opts.max_sweeps),
+                                eig_int_workspace(std::max<int64_t>(q3, 1), h->opts.max_sweeps)) * sizeof(int));
     if (st != FASTPI_OK) return st;
     d.valid = true;
     return check_launch();
@@ -507,6 +556,7 @@ int fastpi_svd(fastpi_handle* h, const int64_t* rowptr, const int32_t* col, cons
     double* eigws = ws + h->o_eig;
     double* part = ws + h->o_part;
     double* gsc = ws + h->o_gs;
+    double* spart = ws + h->o_spart;
     const double tol = h->opts.tol;
     const int max_sweeps = h->opts.max_sweeps;
     // Singular values below this fraction of the largest are not resolved by the Gram route
@@ -528,37 +578,38 @@ int fastpi_svd(fastpi_handle* h, const int64_t* rowptr, const int32_t* col, cons
     if (n1 > 0 && s > 0) {
         launch_fill(G2, n1 * n1, 0.0, st);
         launch_blockdiag_gram(d.work, static_cast<int>(d.B_dense), V1, sig1, G2, n1, st);
-        launch_sparse_gram(d.a21_colptr, d.a21_rowidx, vals + d.off_a21c, d.a21_rowptr, d.a21_colidx,
-                           vals + d.off_a21r, n1, G2, n1, true, st);
+        launch_sparse_gram(d.seg_a21c, d.a21_rowidx, vals + d.off_a21c, d.a21_rowptr, d.a21_colidx,
+                           vals + d.off_a21r, n1, G2, n1, true, spart, st);
         rc = eig_top(G2, n1, s, lam2, V2, eigws, h->iws, d.pairs2, max_sweeps, 0.0, 1,
-                     &h->sweeps[1], h->host_pinned, st);
+                     &h->sweeps[1], h->host_pinned, st, h->copy_stream);
         if (rc != FASTPI_OK && rc != FASTPI_ENOCONV) return rc;
         if (rc == FASTPI_ENOCONV) launch_fill_i32(h->status, 1, 2, st);
         launch_sqrt_inv(lam2, s, rel_cut, sig2, inv2, st);
-        launch_fill(U2, m1 * s, 0.0, st);
+        launch_fill(U2, m * s, 0.0, st);
         launch_u2_top(d.work, static_cast<int>(d.B_dense), U1, sig1, V1, V2, s, inv2, U2, h->status, st);
-        launch_spmm_rows(d.a21_rowptr, d.a21_colidx, vals + d.off_a21r, m2, nullptr, V2, s, inv2,
-                         U2 + m1 * s, s, nullptr, false, st);
+        launch_spmm_rows(d.seg_a21r, d.a21_colidx, vals + d.off_a21r, V2, s, inv2, U2 + m1 * s, s,
+                         nullptr, false, spart, st);
     }
     // a4: column update (Eq. 3) -- top r eigenpairs of X3^T X3, X3 = [U2 Sigma2, T]
     if (q3 > 0 && r > 0) {
+        launch_fill(G3, q3 * q3, 0.0, st);
         if (s > 0) {
             const int sp = gemm_tn_splits(s, s, m);
             launch_gemm_tn(U2, s, U2, s, s, s, m, G3, q3, sig2, sig2, part, sp, st);
-            launch_sparse_proj(d.t_colptr, d.t_rowidx, vals + d.off_tc, n2, U2, s, sig2, G3, q3, s, st);
+            launch_sparse_proj(d.seg_tc, d.t_rowidx, vals + d.off_tc, U2, s, sig2, G3, q3, s, spart, st);
         }
-        launch_sparse_gram(d.t_colptr, d.t_rowidx, vals + d.off_tc, d.t_rowptr, d.t_colidx,
-                           vals + d.off_tr, n2, G3 + s * q3 + s, q3, false, st);
+        launch_sparse_gram(d.seg_tc, d.t_rowidx, vals + d.off_tc, d.t_rowptr, d.t_colidx,
+                           vals + d.off_tr, n2, G3 + s * q3 + s, q3, false, spart, st);
         rc = eig_top(G3, q3, r, lam3, Vt, eigws, h->iws, d.pairs3, max_sweeps, 0.0, 1, &h->sweeps[2],
-                     h->host_pinned, st);
+                     h->host_pinned, st, h->copy_stream);
         if (rc != FASTPI_OK && rc != FASTPI_ENOCONV) return rc;
         if (rc == FASTPI_ENOCONV) launch_fill_i32(h->status, 1, 2, st);
         launch_sqrt_inv(lam3, r, rel_cut, sig3, inv3, st);
         launch_col_coeffs(Vt, s, n2, r, sig2, inv3, C1, C2, st);
         // a5: U and V in the caller's order
         launch_gemm_nn(U2, s, d.piT, C1, r, m, r, s, U, r, nullptr, st);
-        launch_spmm_rows(d.t_rowptr, d.t_colidx, vals + d.off_tr, m, d.piT, C2, r, nullptr, U, r,
-                         nullptr, true, st);
+        launch_spmm_rows(d.seg_tr, d.t_colidx, vals + d.off_tr, C2, r, nullptr, U, r, d.invT, true,
+                         spart, st);
         launch_gemm_nn(V2, s, nullptr, Vt, r, n1, r, s, V, r, d.invF, st);
         launch_copy_rows(Vt + s * r, n2, r, d.invF + n1, V, st);
         HIP_TRY(hipMemcpyAsync(S, sig3, sizeof(double) * r, hipMemcpyDeviceToDevice, st));
@@ -648,8 +699,7 @@ int fastpi_syev_top(fastpi_handle* h, int64_t q, const double* G, int64_t t, dou
         return st;
     }
     double* ws = h->dp.valid ? h->ws + h->o_eig : h->ws;
-    const int64_t ld = eig_padded_order(q);
-    if ((st = ensure_iws(h, static_cast<size_t>(2 * ld + 128) * sizeof(int))) != FASTPI_OK) return st;
+    if ((st = ensure_iws(h, eig_int_workspace(q, h->opts.max_sweeps) * sizeof(int))) != FASTPI_OK) return st;
     std::vector<int2> tab;
     eig_pair_table(q, tab);
     void* p = nullptr;
@@ -660,7 +710,7 @@ int fastpi_syev_top(fastpi_handle* h, int64_t q, const double* G, int64_t t, dou
     HIP_TRY(hipMemcpyAsync(p, tab.data(), tab.size() * sizeof(int2), hipMemcpyHostToDevice, h->stream));
     int sw = 0;
     st = eig_top(G, q, t, vals, vecs, ws, h->iws, static_cast<int2*>(p), h->opts.max_sweeps,
-                 h->opts.tol, 1, &sw, h->host_pinned, h->stream);
+                 h->opts.tol, 1, &sw, h->host_pinned, h->stream, h->copy_stream);
     hipStreamSynchronize(h->stream);
     hipFree(p);
     h->sweeps[1] = sw;

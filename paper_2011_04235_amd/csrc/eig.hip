@@ -1,12 +1,13 @@
 // Dense symmetric eigensolver for the cores of the incremental updates (Eqs. 2 and 3):
 // block one-sided Jacobi on the Gram matrix G, FP64.
 //
-// X starts as G (padded to a multiple of 16 with zero columns) and V as I. The columns are
-// cut into blocks of BW = 16; every round of the round robin pairs the blocks, and for each
-// pair (I, J) the 32 x 32 Gram H = [X_I X_J]^T [X_I X_J] is diagonalised by a two-sided
-// Jacobi sweep, H = W diag W^T, after which X[:, I u J] <- X[:, I u J] W and
-// V[:, I u J] <- V[:, I u J] W. At convergence the columns of X = G V are orthogonal, so V
-// holds eigenvectors of G, and the eigenvalues are the Rayleigh quotients v_c^T x_c.
+// X starts as G (padded to a multiple of 16 with zero columns). The columns are cut into
+// blocks of BW = 16; every round of the round robin pairs the blocks, and for each pair
+// (I, J) the 32 x 32 Gram H = [X_I X_J]^T [X_I X_J] is diagonalised by a two-sided Jacobi
+// sweep, H = W diag W^T, after which X[:, I u J] <- X[:, I u J] W. X stays equal to G V for
+// the orthogonal V that the rotations build; when the columns of X are orthogonal, V
+// diagonalises G^2 and hence the positive semidefinite G, so X = V Lambda: the eigenvalues
+// are the column norms of X and the eigenvectors its normalised columns (V is never formed).
 // A pair whose columns are already orthogonal to `tol` (cosine) is left alone; the sweep
 // loop ends after a sweep with no rotated pair.
 #include <cfloat>
@@ -22,17 +23,38 @@ constexpr int GRAM_ROWS = 128;     // rows per partial-Gram workgroup
 constexpr int UPD_ROWS = 256;      // rows per update workgroup
 
 __global__ void k_eig_init(const double* __restrict__ G, int64_t q, int64_t ld,
-                           double* __restrict__ X, double* __restrict__ V) {
+                           double* __restrict__ X) {
     const int64_t n = ld * ld;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += stride) {
         const int64_t r = e % ld, c = e / ld;
         X[e] = (r < q && c < q) ? G[r * q + c] : 0.0;
-        V[e] = (r == c) ? 1.0 : 0.0;
     }
 }
 
-// partial Gram of one pair over one row chunk
+// pair k of step `step` of the round robin over the PW columns of a pair, p < q
+__device__ __forceinline__ void inner_pair(int step, int k, int& p, int& q) {
+    int a, b;
+    if (k == 0) {
+        a = PW - 1;
+        b = step;
+    } else {
+        a = step + k;
+        if (a >= PW - 1) a -= PW - 1;
+        b = step - k;
+        if (b < 0) b += PW - 1;
+    }
+    p = a < b ? a : b;
+    q = a < b ? b : a;
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Partial Gram of one pair over one row chunk of X.
 __global__ __launch_bounds__(256) void k_eig_gram(const double* __restrict__ X, int64_t ld,
                                                   const int2* __restrict__ pairs, int nblk,
                                                   double* __restrict__ Hpart, int nchunk) {
@@ -58,115 +80,144 @@ __global__ __launch_bounds__(256) void k_eig_gram(const double* __restrict__ X, 
         acc2 += ya * Y[r][b0 + 2];
         acc3 += ya * Y[r][b0 + 3];
     }
-    double* H = Hpart + (static_cast<int64_t>(pair) * nchunk + ch) * (PW * PW) + a * PW + b0;
-    H[0] = acc0;
-    H[1] = acc1;
-    H[2] = acc2;
-    H[3] = acc3;
+    double* Hp = Hpart + (static_cast<int64_t>(pair) * nchunk + ch) * (PW * PW) + a * PW + b0;
+    Hp[0] = acc0;
+    Hp[1] = acc1;
+    Hp[2] = acc2;
+    Hp[3] = acc3;
 }
 
-// sum the partials of one pair, test orthogonality, diagonalise with one or more Jacobi
-// sweeps (16 disjoint rotations per step), write W
-__global__ __launch_bounds__(64) void k_eig_solve(const double* __restrict__ Hpart, int nchunk,
-                                                  const int2* __restrict__ pairs, int nblk,
-                                                  double* __restrict__ Wout, int* __restrict__ flag,
-                                                  int* __restrict__ rot_count, double tol,
-                                                  int inner_sweeps) {
-    __shared__ double H[PW][PW + 1];
-    __shared__ double W[PW][PW + 1];
-    __shared__ double cs[PW / 2][3];
+// Rotation of the symmetric 2x2 [[hpp, hpq], [hpq, hqq]] for the inner sweeps. The angle
+// is only needed approximately (the outer sweeps continue until every pair is orthogonal),
+// but c and s must form an exactly orthogonal pair: tan(theta) is taken in FP32 from the
+// FP64 entries, then (c, s) is renormalised in FP64 with a Newton-corrected reciprocal
+// square root so that c^2 + s^2 = 1 to FP64 rounding.
+__device__ __forceinline__ void fast_rotation(double hpp, double hqq, double hpq, double& c, double& s) {
+    c = 1.0;
+    s = 0.0;
+    const double ahpq = fabs(hpq);
+    const double dd = hqq - hpp;
+    // negligible coupling (also covers hpq == 0 and non-finite input)
+    if (!(ahpq > 1e-17 * (fabs(hpp) + fabs(hqq)))) return;
+    const double zeta64 = dd / (2.0 * hpq);
+    const float zeta = static_cast<float>(zeta64);
+    const float az = fabsf(zeta);
+    float t;
+    if (az > 1e15f || !(az == az)) {
+        t = static_cast<float>(0.5 / zeta64);
+    } else {
+        t = 1.0f / (az + sqrtf(1.0f + zeta * zeta));
+        if (zeta < 0) t = -t;
+    }
+    const double td = static_cast<double>(t);
+    const double x = 1.0 + td * td;
+    double y = static_cast<double>(rsqrtf(static_cast<float>(x)));
+    y = y * (1.5 - 0.5 * x * y * y);
+    y = y * (1.5 - 0.5 * x * y * y);
+    c = y;
+    s = y * td;
+}
+
+// position of index i in the round robin of step `step`: returns its partner and whether
+// it is the lower index of its pair
+__device__ __forceinline__ void inner_partner(int step, int i, int& partner, bool& lower) {
+    int k;
+    if (i == PW - 1 || i == step) {
+        k = 0;
+    } else {
+        int d = i - step;
+        if (d < 0) d += PW - 1;
+        k = d < (PW - 1) - d ? d : (PW - 1) - d;
+    }
+    int p, q;
+    inner_pair(step, k, p, q);
+    lower = (i == p);
+    partner = lower ? q : p;
+}
+
+// One workgroup of PW * PW threads per pair, thread (i, j) owning H[i][j] and W[i][j] in
+// registers. The partials are summed in chunk order; if the pair is not yet orthogonal
+// to `tol`, `inner_sweeps` cyclic Jacobi sweeps (31 steps of 16 disjoint rotations) make
+// H diagonal and W accumulates the rotations. In each step every wave derives the
+// rotations of rows i and j itself from the shared copy of H, then thread (i, j) forms
+// (J^T H J)[i][j] from H[i][j], H[i][j'], H[i'][j], H[i'][j'] and (W J)[i][j] from
+// W[i][j], W[i][j'], writing into the other half of a double buffer: one barrier a step.
+__global__ __launch_bounds__(PW * PW) void k_eig_solve(const double* __restrict__ Hpart, int nchunk,
+                                                       const int2* __restrict__ pairs, int nblk,
+                                                       double* __restrict__ Wout,
+                                                       int* __restrict__ flag,
+                                                       int* __restrict__ rot_count, double tol,
+                                                       int inner_sweeps) {
+    __shared__ double Hs[2][PW][PW + 1];
+    __shared__ double Ws[2][PW][PW + 1];
     __shared__ int s_need;
     const int pair = blockIdx.x;
     const int2 pb = pairs[pair];
-    const int lane = threadIdx.x;
     if (pb.x >= nblk) {
-        if (lane == 0) flag[pair] = 0;
+        if (threadIdx.x == 0) flag[pair] = 0;
         return;
     }
-    const double* Hp = Hpart + static_cast<int64_t>(pair) * nchunk * (PW * PW);
-    for (int e = lane; e < PW * PW; e += 64) {
-        double acc = 0;
-        for (int c = 0; c < nchunk; ++c) acc += Hp[static_cast<int64_t>(c) * PW * PW + e];
-        H[e / PW][e % PW] = acc;
-        W[e / PW][e % PW] = (e / PW == e % PW) ? 1.0 : 0.0;
-    }
-    if (lane == 0) s_need = 0;
+    const int i = threadIdx.x / PW, j = threadIdx.x % PW;
+    const double* Hp = Hpart + static_cast<int64_t>(pair) * nchunk * (PW * PW) + threadIdx.x;
+    double h = 0;
+    for (int c = 0; c < nchunk; ++c) h += Hp[static_cast<int64_t>(c) * PW * PW];
+    double w = (i == j) ? 1.0 : 0.0;
+    Hs[0][i][j] = h;
+    Ws[0][i][j] = w;
+    if (threadIdx.x == 0) s_need = 0;
     __syncthreads();
-    // off-diagonal test in the cosine sense
-    int need = 0;
-    for (int e = lane; e < PW * PW; e += 64) {
-        const int i = e / PW, j = e % PW;
-        if (i < j) {
-            const double hii = H[i][i], hjj = H[j][j], hij = H[i][j];
-            if (hii > 0 && hjj > 0 && fabs(hij) > tol * sqrt(hii) * sqrt(hjj)) need = 1;
-        }
+    if (i < j) {
+        const double hii = Hs[0][i][i], hjj = Hs[0][j][j];
+        if (hii > 0 && hjj > 0 && fabs(h) > tol * sqrt(hii) * sqrt(hjj)) s_need = 1;
     }
-    if (need) s_need = 1;
     __syncthreads();
     if (!s_need) {
-        if (lane == 0) flag[pair] = 0;
+        if (threadIdx.x == 0) flag[pair] = 0;
         return;
     }
+    int cur = 0;
     for (int sw = 0; sw < inner_sweeps; ++sw) {
         for (int step = 0; step < PW - 1; ++step) {
-            if (lane < PW / 2) {
-                int p, q;
-                round_robin_pair(step, lane, PW, p, q);
-                const double hpp = H[p][p], hqq = H[q][q], hpq = H[p][q];
-                double c = 1, s = 0, t = 0;
-                if (hpq != 0.0 && fabs(hpq) > 0.5 * DBL_EPSILON * sqrt(fabs(hpp)) * sqrt(fabs(hqq)))
-                    jacobi_rotation(hpp, hqq, hpq, c, s, t);
-                cs[lane][0] = c;
-                cs[lane][1] = s;
-                cs[lane][2] = t;
+            int ip, jp;
+            bool il, jl;
+            inner_partner(step, i, ip, il);
+            inner_partner(step, j, jp, jl);
+            double ci, si, cj, sj;
+            {
+                const int a = il ? i : ip, b = il ? ip : i;
+                fast_rotation(Hs[cur][a][a], Hs[cur][b][b], Hs[cur][a][b], ci, si);
+                if (il) si = -si;   // lower index: new = c * own - s * partner
             }
-            __syncthreads();
-            // rows: H <- J^T H
-            for (int e = lane; e < (PW / 2) * PW; e += 64) {
-                const int k = e / PW, j = e % PW;
-                int p, q;
-                round_robin_pair(step, k, PW, p, q);
-                const double c = cs[k][0], s = cs[k][1];
-                const double hp = H[p][j], hq = H[q][j];
-                H[p][j] = c * hp - s * hq;
-                H[q][j] = s * hp + c * hq;
+            {
+                const int a = jl ? j : jp, b = jl ? jp : j;
+                fast_rotation(Hs[cur][a][a], Hs[cur][b][b], Hs[cur][a][b], cj, sj);
+                if (jl) sj = -sj;
             }
+            const double h_ij = h;
+            const double h_ijp = Hs[cur][i][jp];
+            const double h_ipj = Hs[cur][ip][j];
+            const double h_ipjp = Hs[cur][ip][jp];
+            const double w_ijp = Ws[cur][i][jp];
+            h = ci * (cj * h_ij + sj * h_ijp) + si * (cj * h_ipj + sj * h_ipjp);
+            w = cj * w + sj * w_ijp;
+            const int nxt = cur ^ 1;
+            Hs[nxt][i][j] = h;
+            Ws[nxt][i][j] = w;
             __syncthreads();
-            // columns: H <- H J, W <- W J
-            for (int e = lane; e < (PW / 2) * PW; e += 64) {
-                const int k = e / PW, i = e % PW;
-                int p, q;
-                round_robin_pair(step, k, PW, p, q);
-                const double c = cs[k][0], s = cs[k][1];
-                const double hp = H[i][p], hq = H[i][q];
-                H[i][p] = c * hp - s * hq;
-                H[i][q] = s * hp + c * hq;
-                const double wp = W[i][p], wq = W[i][q];
-                W[i][p] = c * wp - s * wq;
-                W[i][q] = s * wp + c * wq;
-            }
-            __syncthreads();
-            if (lane < PW / 2 && cs[lane][1] != 0.0) {
-                int p, q;
-                round_robin_pair(step, lane, PW, p, q);
-                H[p][q] = 0.0;
-                H[q][p] = 0.0;
-            }
-            __syncthreads();
+            cur = nxt;
         }
     }
-    double* Wg = Wout + static_cast<int64_t>(pair) * PW * PW;
-    for (int e = lane; e < PW * PW; e += 64) Wg[e] = W[e / PW][e % PW];
-    if (lane == 0) {
+    Wout[static_cast<int64_t>(pair) * PW * PW + threadIdx.x] = w;
+    if (threadIdx.x == 0) {
         flag[pair] = 1;
         atomicAdd(rot_count, 1);
     }
 }
 
-// X[:, I u J] <- X[:, I u J] W and V likewise (blockIdx.z selects X or V)
-__global__ __launch_bounds__(UPD_ROWS) void k_eig_update(double* __restrict__ X, double* __restrict__ V,
-                                                         int64_t ld, const int2* __restrict__ pairs,
-                                                         int nblk, const double* __restrict__ Wall,
+// X[:, I u J] <- X[:, I u J] W, one thread per row
+__global__ __launch_bounds__(UPD_ROWS) void k_eig_update(double* __restrict__ X, int64_t ld,
+                                                         const int2* __restrict__ pairs, int nblk,
+                                                         const double* __restrict__ Wall,
                                                          const int* __restrict__ flag) {
     __shared__ double W[PW][PW];
     const int pair = blockIdx.x;
@@ -174,7 +225,6 @@ __global__ __launch_bounds__(UPD_ROWS) void k_eig_update(double* __restrict__ X,
     if (pb.x >= nblk) return;
     if (flag[pair] == 0) return;
     const bool hasJ = pb.y < nblk;
-    double* M = blockIdx.z == 0 ? X : V;
     const double* Wg = Wall + static_cast<int64_t>(pair) * PW * PW;
     for (int e = threadIdx.x; e < PW * PW; e += blockDim.x) W[e / PW][e % PW] = Wg[e];
     __syncthreads();
@@ -184,7 +234,7 @@ __global__ __launch_bounds__(UPD_ROWS) void k_eig_update(double* __restrict__ X,
 #pragma unroll
     for (int c = 0; c < PW; ++c) {
         const int col = c < BW ? pb.x * BW + c : pb.y * BW + (c - BW);
-        y[c] = (c < BW || hasJ) ? M[static_cast<int64_t>(col) * ld + r] : 0.0;
+        y[c] = (c < BW || hasJ) ? X[static_cast<int64_t>(col) * ld + r] : 0.0;
     }
     const int jend = hasJ ? PW : BW;
 #pragma unroll 4
@@ -193,21 +243,24 @@ __global__ __launch_bounds__(UPD_ROWS) void k_eig_update(double* __restrict__ X,
 #pragma unroll
         for (int k = 0; k < PW; ++k) acc += y[k] * W[k][j];
         const int col = j < BW ? pb.x * BW + j : pb.y * BW + (j - BW);
-        M[static_cast<int64_t>(col) * ld + r] = acc;
+        X[static_cast<int64_t>(col) * ld + r] = acc;
     }
 }
 
-// eigenvalue estimates: Rayleigh quotients v_c^T x_c (x_c = G v_c)
-__global__ void k_eig_rayleigh(const double* __restrict__ X, const double* __restrict__ V,
-                               int64_t ld, int64_t q, double* __restrict__ lam) {
+// eigenvalues: column norms of X (non-finite values sort last so the order stays a
+// permutation)
+__global__ void k_eig_norms(const double* __restrict__ X, int64_t ld, int64_t q,
+                            double* __restrict__ lam) {
     const int lane = threadIdx.x % kWave;
     const int64_t c = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (c >= ld) return;
     double acc = 0;
-    for (int64_t r = lane; r < q; r += kWave) acc += V[c * ld + r] * X[c * ld + r];
+    for (int64_t r = lane; r < q; r += kWave) {
+        const double v = X[c * ld + r];
+        acc += v * v;
+    }
     acc = wave_sum(acc);
-    // non-finite values (from a non-finite input) sort last, keeping the order a permutation
-    if (lane == 0) lam[c] = (c < q && isfinite(acc)) ? acc : -DBL_MAX;
+    if (lane == 0) lam[c] = (c < q && isfinite(acc)) ? sqrt(acc) : -DBL_MAX;
 }
 
 // order of the t largest eigenvalues (descending, ties to the lower column)
@@ -224,16 +277,18 @@ __global__ __launch_bounds__(1024) void k_eig_select(const double* __restrict__ 
     }
 }
 
-// vecs (q x t, row-major) and vals (t)
-__global__ void k_eig_output(const double* __restrict__ V, int64_t ld, int64_t q, int64_t t,
+// vecs (q x t, row-major): the normalised columns of X; vals (t): their norms
+__global__ void k_eig_output(const double* __restrict__ X, int64_t ld, int64_t q, int64_t t,
                              const int* __restrict__ order, const double* __restrict__ lam,
                              double* __restrict__ vals, double* __restrict__ vecs) {
     const int64_t n = q * t;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += stride) {
         const int64_t r = e / t, k = e % t;
-        vecs[e] = V[static_cast<int64_t>(order[k]) * ld + r];
-        if (r == 0) vals[k] = lam[order[k]];
+        const double l = lam[order[k]];
+        const double inv = l > 0 ? 1.0 / l : 0.0;
+        vecs[e] = X[static_cast<int64_t>(order[k]) * ld + r] * inv;
+        if (r == 0) vals[k] = l > 0 ? l : 0.0;
     }
 }
 
@@ -244,14 +299,22 @@ size_t eig_workspace_doubles(int64_t q) {
     const int64_t nblk = ld / BW;
     const int64_t npairs = (nblk + 1) / 2;
     const int64_t nchunk = (ld + GRAM_ROWS - 1) / GRAM_ROWS;
-    return static_cast<size_t>(2 * ld * ld + npairs * nchunk * PW * PW + npairs * PW * PW + 2 * ld + 64);
+    return static_cast<size_t>(ld * ld + npairs * nchunk * PW * PW + npairs * PW * PW + 2 * ld + 64);
 }
 
-// Host driver. ws holds eig_workspace_doubles(q) doubles; iws holds ints for flags and the
-// ordering; pair_tables is the device copy of the round-robin tables for nblk blocks.
+size_t eig_int_workspace(int64_t q, int max_sweeps) {
+    const int64_t ld = eig_padded_order(q);
+    const int64_t npairs = (ld / BW + 1) / 2;
+    return static_cast<size_t>(2 * npairs + ld + max_sweeps + 64);
+}
+
+// Host driver. ws holds eig_workspace_doubles(q) doubles, iws eig_int_workspace(q, max_sweeps)
+// ints; pair_tables is the device copy of the round-robin tables for the padded order.
+// The rotation count of sweep k is read back while sweep k+1 is already queued, so the
+// device never waits on the host; a sweep queued after convergence finds nothing to do.
 int eig_top(const double* G, int64_t q, int64_t t, double* vals, double* vecs, double* ws,
             int* iws, const int2* pair_tables, int max_sweeps, double tol, int inner_sweeps,
-            int* sweeps_out, int* host_counter, hipStream_t st) {
+            int* sweeps_out, int* host_counter, hipStream_t st, hipStream_t copy_st) {
     const int64_t ld = eig_padded_order(q);
     const int nblk = static_cast<int>(ld / BW);
     const int nbe = nblk + (nblk & 1);     // even number of slots (the extra one is a dummy)
@@ -260,40 +323,61 @@ int eig_top(const double* G, int64_t q, int64_t t, double* vals, double* vecs, d
     const int nchunk = static_cast<int>((ld + GRAM_ROWS - 1) / GRAM_ROWS);
     const int nupd = static_cast<int>((ld + UPD_ROWS - 1) / UPD_ROWS);
     double* X = ws;
-    double* V = X + ld * ld;
-    double* Hpart = V + ld * ld;
+    double* Hpart = X + ld * ld;
     double* W = Hpart + static_cast<int64_t>(npairs) * nchunk * PW * PW;
     double* lam = W + static_cast<int64_t>(npairs) * PW * PW;
     int* flag = iws;
-    int* rot = flag + npairs;
-    int* order = rot + 4;
+    int* arrive = flag + npairs;
+    int* order = arrive + npairs;
+    int* rot = order + ld;                 // one counter per sweep
+    // reads the rotation counter of sweep k on the side stream once sweep k has finished
+    auto read_counter = [&](int k, hipEvent_t e) -> int {
+        if (hipStreamWaitEvent(copy_st, e, 0) != hipSuccess) return FASTPI_EHIP;
+        if (hipMemcpyAsync(host_counter, rot + k, sizeof(int), hipMemcpyDeviceToHost, copy_st) != hipSuccess)
+            return FASTPI_EHIP;
+        if (hipStreamSynchronize(copy_st) != hipSuccess) return FASTPI_EHIP;
+        return FASTPI_OK;
+    };
     hipLaunchKernelGGL(k_eig_init, dim3(static_cast<int>(std::min<int64_t>((ld * ld + 255) / 256, 8192))),
-                       dim3(256), 0, st, G, q, ld, X, V);
+                       dim3(256), 0, st, G, q, ld, X);
+    launch_fill_i32(rot, max_sweeps, 0, st);
     if (tol <= 0) tol = static_cast<double>(ld) * DBL_EPSILON;
-    int sweep = 0;
-    bool converged = nblk <= 0;
-    for (; sweep < max_sweeps && !converged; ++sweep) {
-        launch_fill_i32(rot, 1, 0, st);
+    hipEvent_t ev[2];
+    if (hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) != hipSuccess) return FASTPI_EHIP;
+    if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) return FASTPI_EHIP;
+    int sweeps_done = 0;
+    bool converged = false;
+    int checked = 0;   // sweeps whose counter has been read
+    for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
         for (int round = 0; round < rounds; ++round) {
             const int2* pr = pair_tables + static_cast<int64_t>(round) * npairs;
-            hipLaunchKernelGGL(k_eig_gram, dim3(npairs, nchunk), dim3(256), 0, st, X, ld, pr, nblk,
-                               Hpart, nchunk);
-            hipLaunchKernelGGL(k_eig_solve, dim3(npairs), dim3(64), 0, st, Hpart, nchunk, pr, nblk,
-                               W, flag, rot, tol, inner_sweeps);
-            hipLaunchKernelGGL(k_eig_update, dim3(npairs, nupd, 2), dim3(UPD_ROWS), 0, st, X, V, ld,
-                               pr, nblk, W, flag);
+            hipLaunchKernelGGL(k_eig_gram, dim3(npairs, nchunk), dim3(256), 0, st, X, ld, pr, nblk, Hpart,
+                               nchunk);
+            hipLaunchKernelGGL(k_eig_solve, dim3(npairs), dim3(PW * PW), 0, st, Hpart, nchunk, pr, nblk, W,
+                               flag, rot + sweep, tol, inner_sweeps);
+            hipLaunchKernelGGL(k_eig_update, dim3(npairs, nupd), dim3(UPD_ROWS), 0, st, X, ld, pr, nblk,
+                               W, flag);
         }
-        if (hipMemcpyAsync(host_counter, rot, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
-            return FASTPI_EHIP;
-        if (hipStreamSynchronize(st) != hipSuccess) return FASTPI_EHIP;
+        hipEventRecord(ev[sweep & 1], st);
+        sweeps_done = sweep + 1;
+        if (sweep >= 1) {
+            // read the previous sweep's counter while this one runs
+            if (read_counter(sweep - 1, ev[(sweep - 1) & 1]) != FASTPI_OK) return FASTPI_EHIP;
+            checked = sweep;
+            if (*host_counter == 0) converged = true;
+        }
+    }
+    if (!converged && checked < sweeps_done) {
+        if (read_counter(sweeps_done - 1, ev[(sweeps_done - 1) & 1]) != FASTPI_OK) return FASTPI_EHIP;
         if (*host_counter == 0) converged = true;
     }
-    if (sweeps_out) *sweeps_out = sweep;
-    hipLaunchKernelGGL(k_eig_rayleigh, dim3(static_cast<int>((ld + 3) / 4)), dim3(256), 0, st, X, V, ld,
-                       q, lam);
+    hipEventDestroy(ev[0]);
+    hipEventDestroy(ev[1]);
+    if (sweeps_out) *sweeps_out = sweeps_done;
+    hipLaunchKernelGGL(k_eig_norms, dim3(static_cast<int>((ld + 3) / 4)), dim3(256), 0, st, X, ld, q, lam);
     hipLaunchKernelGGL(k_eig_select, dim3(1), dim3(1024), 0, st, lam, q, t, order);
     hipLaunchKernelGGL(k_eig_output, dim3(static_cast<int>(std::min<int64_t>((q * t + 255) / 256, 8192))),
-                       dim3(256), 0, st, V, ld, q, t, order, lam, vals, vecs);
+                       dim3(256), 0, st, X, ld, q, t, order, lam, vals, vecs);
     return converged ? FASTPI_OK : FASTPI_ENOCONV;
 }
 

@@ -44,6 +44,20 @@ struct BlockWork {
     int32_t row0, col0, pad0, pad1;
 };
 
+// Work split of a compressed sparse structure (CSR or CSC, pointer array over `owners`
+// rows or columns): every owner's entries are cut into segments of at most kSegLen entries.
+// An owner with one segment is written directly; the segments of an owner with several
+// write partial rows (pidx >= 0) that a second pass sums in segment order.
+constexpr int64_t kSegLen = 64;
+struct Segments {
+    std::vector<int32_t> owner, pidx;
+    std::vector<int64_t> begin, end;
+    std::vector<int32_t> multi_owner;   // owners with several segments
+    std::vector<int32_t> multi_ptr;     // their partial-row ranges (size multi_owner + 1)
+    int64_t npart = 0;
+};
+void build_segments(const std::vector<int64_t>& ptr, Segments& out);
+
 struct Plan {
     int64_t m = 0, n = 0, nnz = 0;   // nnz of the caller's CSR (including stored zeros)
     double alpha = 0, k = 0;
@@ -59,6 +73,7 @@ struct Plan {
     // A21 (m2 x n1) and T (m x n2) patterns in new ids
     std::vector<int64_t> a21_rowptr, a21_colptr, t_rowptr, t_colptr;
     std::vector<int32_t> a21_colidx, a21_rowidx, t_colidx, t_rowidx;
+    Segments seg_a21c, seg_a21r, seg_tc, seg_tr;   // A21 CSC/CSR, T CSC/CSR
     std::vector<int32_t> invT;   // new row -> original row
     std::vector<int32_t> invF;   // new column -> original column
 };

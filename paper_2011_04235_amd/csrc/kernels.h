@@ -12,6 +12,17 @@
 
 namespace fastpi {
 
+// device view of a Segments table (pointers into device memory)
+struct SegDev {
+    const int32_t* owner;
+    const int64_t* begin;
+    const int64_t* end;
+    const int32_t* pidx;
+    const int32_t* multi_owner;
+    const int32_t* multi_ptr;
+    int64_t nseg, nmulti, npart;
+};
+
 void launch_fill(double* p, int64_t n, double v, hipStream_t st);
 void launch_fill_i32(int* p, int64_t n, int v, hipStream_t st);
 void launch_gather(const double* val, const int64_t* dst0, const int64_t* dst1, int64_t nnz,
@@ -25,10 +36,11 @@ void launch_block_svd(bool fp32, const BlockWork* work, int first, int count, co
 // eigensolver (eig.hip)
 int64_t eig_padded_order(int64_t q);
 size_t eig_workspace_doubles(int64_t q);
+size_t eig_int_workspace(int64_t q, int max_sweeps);
 void eig_pair_table(int64_t q, std::vector<int2>& out);
 int eig_top(const double* G, int64_t q, int64_t t, double* vals, double* vecs, double* ws,
             int* iws, const int2* pair_tables, int max_sweeps, double tol, int inner_sweeps,
-            int* sweeps_out, int* host_counter, hipStream_t st);
+            int* sweeps_out, int* host_counter, hipStream_t st, hipStream_t copy_st);
 
 // dense (dense.hip)
 int gemm_tn_splits(int64_t M, int64_t N, int64_t K);
@@ -40,15 +52,15 @@ void launch_gemm_nn(const double* A, int64_t lda, const int* arow, const double*
                     hipStream_t st);
 
 // sparse and block-structured (sparse.hip)
-void launch_sparse_gram(const int64_t* colptr, const int* rowidx, const double* cval,
+void launch_sparse_gram(const SegDev& sg, const int* rowidx, const double* cval,
                         const int64_t* rowptr, const int* colidx, const double* rval, int64_t q,
-                        double* G, int64_t ldg, bool accumulate, hipStream_t st);
-void launch_sparse_proj(const int64_t* colptr, const int* rowidx, const double* cval, int64_t ncols,
-                        const double* U, int64_t s, const double* sigma, double* G, int64_t ldg,
-                        int64_t off, hipStream_t st);
-void launch_spmm_rows(const int64_t* rowptr, const int* colidx, const double* rval, int64_t M,
-                      const int* srow, const double* B, int64_t N, const double* cs, double* C,
-                      int64_t ldc, const int* crow, bool accumulate, hipStream_t st);
+                        double* G, int64_t ldg, bool accumulate, double* part, hipStream_t st);
+void launch_sparse_proj(const SegDev& sg, const int* rowidx, const double* cval, const double* U,
+                        int64_t s, const double* sigma, double* G, int64_t ldg, int64_t off,
+                        double* part, hipStream_t st);
+void launch_spmm_rows(const SegDev& sg, const int* colidx, const double* rval, const double* B,
+                      int64_t N, const double* cs, double* C, int64_t ldc, const int* crow,
+                      bool accumulate, double* part, hipStream_t st);
 void launch_blockdiag_gram(const BlockWork* work, int nwork, const double* V1, const double* sig1,
                            double* G, int64_t ldg, hipStream_t st);
 void launch_u2_top(const BlockWork* work, int nwork, const double* U1, const double* sig1,

@@ -7,6 +7,27 @@
 
 namespace fastpi {
 
+void build_segments(const std::vector<int64_t>& ptr, Segments& out) {
+    out = Segments{};
+    const int64_t owners = static_cast<int64_t>(ptr.size()) - 1;
+    out.multi_ptr.push_back(0);
+    for (int64_t o = 0; o < owners; ++o) {
+        const int64_t b = ptr[o], e = ptr[o + 1];
+        if (e <= b) continue;
+        const int64_t nseg = (e - b + kSegLen - 1) / kSegLen;
+        for (int64_t k = 0; k < nseg; ++k) {
+            out.owner.push_back(static_cast<int32_t>(o));
+            out.begin.push_back(b + k * kSegLen);
+            out.end.push_back(std::min(e, b + (k + 1) * kSegLen));
+            out.pidx.push_back(nseg > 1 ? static_cast<int32_t>(out.npart++) : -1);
+        }
+        if (nseg > 1) {
+            out.multi_owner.push_back(static_cast<int32_t>(o));
+            out.multi_ptr.push_back(static_cast<int32_t>(out.npart));
+        }
+    }
+}
+
 int build_plan(Plan& p, int64_t m, int64_t n, const int64_t* rowptr, const int32_t* col,
                const double* val, double alpha, double k) {
     if (!(alpha > 0.0 && alpha <= 1.0)) {
@@ -166,6 +187,10 @@ int build_plan(Plan& p, int64_t m, int64_t n, const int64_t* rowptr, const int32
             }
         }
     }
+    build_segments(p.a21_colptr, p.seg_a21c);
+    build_segments(p.a21_rowptr, p.seg_a21r);
+    build_segments(p.t_colptr, p.seg_tc);
+    build_segments(p.t_rowptr, p.seg_tr);
     return FASTPI_OK;
 }
 

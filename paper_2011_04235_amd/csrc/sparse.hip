@@ -6,68 +6,94 @@
 
 namespace fastpi {
 
-// G[a, c0:c1] (+)= sum_h S[h, a] S[h, c0:c1] for a sparse S given as CSC (colptr, rowidx,
-// cval) and CSR (rowptr, colidx, rval). One wave owns one (row a, column chunk) of G and
-// accumulates it in LDS, visiting the rows h of column a in ascending order.
+// All sparse products below run over the segments of a compressed structure (see
+// Segments): one wave per segment visits its entries in order; owners with one segment are
+// written directly, the others through partial rows that k_seg_reduce_* sum in segment
+// order. No floating-point atomics, so results are reproducible bit for bit.
+
+// G[a, :] (+)= sum_h S[h, a] S[h, :] for a sparse S given as CSC (segments over its
+// columns, rowidx, cval) and CSR (rowptr, colidx, rval): the Gram S^T S, q x q.
 constexpr int SG_WAVES = 4;
 __global__ __launch_bounds__(SG_WAVES * 64) void k_sparse_gram(
-    const int64_t* __restrict__ colptr, const int* __restrict__ rowidx, const double* __restrict__ cval,
+    SegDev sg, const int* __restrict__ rowidx, const double* __restrict__ cval,
     const int64_t* __restrict__ rowptr, const int* __restrict__ colidx, const double* __restrict__ rval,
-    int64_t q, int64_t chunk, double* __restrict__ G, int64_t ldg, int accumulate) {
+    int64_t q, int64_t chunk, double* __restrict__ G, int64_t ldg, int accumulate,
+    double* __restrict__ part) {
     extern __shared__ double buf_all[];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t nchunks = (q + chunk - 1) / chunk;
     const int64_t task = static_cast<int64_t>(blockIdx.x) * SG_WAVES + wave;
-    if (task >= q * nchunks) return;
-    const int64_t a = task / nchunks;
+    if (task >= sg.nseg * nchunks) return;
+    const int64_t seg = task / nchunks;
     const int64_t c0 = (task % nchunks) * chunk;
     const int64_t c1 = min(q, c0 + chunk);
+    const int64_t a = sg.owner[seg];
+    const int pidx = sg.pidx[seg];
     double* buf = buf_all + static_cast<int64_t>(wave) * chunk;
-    double* Grow = G + a * ldg;
-    for (int64_t c = c0 + lane; c < c1; c += kWave) buf[c - c0] = accumulate ? Grow[c] : 0.0;
+    double* dst = pidx < 0 ? G + a * ldg : part + static_cast<int64_t>(pidx) * q;
+    for (int64_t c = c0 + lane; c < c1; c += kWave)
+        buf[c - c0] = (pidx < 0 && accumulate) ? dst[c] : 0.0;
     __builtin_amdgcn_wave_barrier();
-    for (int64_t e = colptr[a]; e < colptr[a + 1]; ++e) {
+    for (int64_t e = sg.begin[seg]; e < sg.end[seg]; ++e) {
         const int64_t h = rowidx[e];
         const double va = cval[e];
         for (int64_t f = rowptr[h] + lane; f < rowptr[h + 1]; f += kWave) {
             const int64_t b = colidx[f];
             if (b >= c0 && b < c1) buf[b - c0] += va * rval[f];
         }
-        // the next row may touch the same entries from other lanes
+        // the next entry may touch the same columns from other lanes
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    for (int64_t c = c0 + lane; c < c1; c += kWave) Grow[c] = buf[c - c0];
+    for (int64_t c = c0 + lane; c < c1; c += kWave) dst[c] = buf[c - c0];
 }
 
-void launch_sparse_gram(const int64_t* colptr, const int* rowidx, const double* cval,
+// rows of owners with several segments: G[a, :] = (accumulate ? G[a, :] : 0) + sum part
+__global__ void k_seg_reduce_rows(SegDev sg, const double* __restrict__ part, int64_t q,
+                                  double* __restrict__ G, int64_t ldg, int accumulate) {
+    const int64_t o = blockIdx.x;
+    const int64_t c = static_cast<int64_t>(blockIdx.y) * blockDim.x + threadIdx.x;
+    if (o >= sg.nmulti || c >= q) return;
+    const int64_t a = sg.multi_owner[o];
+    double acc = accumulate ? G[a * ldg + c] : 0.0;
+    for (int64_t p = sg.multi_ptr[o]; p < sg.multi_ptr[o + 1]; ++p) acc += part[p * q + c];
+    G[a * ldg + c] = acc;
+}
+
+void launch_sparse_gram(const SegDev& sg, const int* rowidx, const double* cval,
                         const int64_t* rowptr, const int* colidx, const double* rval, int64_t q,
-                        double* G, int64_t ldg, bool accumulate, hipStream_t st) {
-    if (q <= 0) return;
+                        double* G, int64_t ldg, bool accumulate, double* part, hipStream_t st) {
+    if (q <= 0 || sg.nseg <= 0) return;
     const int64_t chunk = std::min<int64_t>(q, 2048);
-    const int64_t tasks = q * ((q + chunk - 1) / chunk);
+    const int64_t tasks = sg.nseg * ((q + chunk - 1) / chunk);
     const size_t lds = static_cast<size_t>(SG_WAVES) * chunk * sizeof(double);
     hipLaunchKernelGGL(k_sparse_gram, dim3(static_cast<unsigned>((tasks + SG_WAVES - 1) / SG_WAVES)),
-                       dim3(SG_WAVES * 64), lds, st, colptr, rowidx, cval, rowptr, colidx, rval, q,
-                       chunk, G, ldg, accumulate ? 1 : 0);
+                       dim3(SG_WAVES * 64), lds, st, sg, rowidx, cval, rowptr, colidx, rval, q,
+                       chunk, G, ldg, accumulate ? 1 : 0, part);
+    if (sg.nmulti > 0)
+        hipLaunchKernelGGL(k_seg_reduce_rows, dim3(static_cast<unsigned>(sg.nmulti),
+                                                   static_cast<unsigned>((q + 255) / 256)),
+                           dim3(256), 0, st, sg, part, q, G, ldg, accumulate ? 1 : 0);
 }
 
-// P[:, j] = sigma .* (U^T S[:, j]) for a sparse S (CSC) and row-major U (rows x s); written
-// into G at G[k, off + j] and mirrored at G[off + j, k]. One wave per column j; the lanes
-// run over k, the rows of column j in ascending order.
-__global__ __launch_bounds__(256) void k_sparse_proj(const int64_t* __restrict__ colptr,
-                                                     const int* __restrict__ rowidx,
+// P[:, a] = sigma .* (U^T S[:, a]) for a sparse S (CSC segments) and row-major U (rows x s),
+// written into G at G[k, off + a] and mirrored at G[off + a, k].
+__global__ __launch_bounds__(256) void k_sparse_proj(SegDev sg, const int* __restrict__ rowidx,
                                                      const double* __restrict__ cval,
-                                                     int64_t ncols, const double* __restrict__ U,
-                                                     int64_t s, const double* __restrict__ sigma,
-                                                     double* __restrict__ G, int64_t ldg, int64_t off) {
+                                                     const double* __restrict__ U, int64_t s,
+                                                     const double* __restrict__ sigma,
+                                                     double* __restrict__ G, int64_t ldg, int64_t off,
+                                                     double* __restrict__ part) {
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t j = static_cast<int64_t>(blockIdx.x) * 4 + wave;
-    if (j >= ncols) return;
+    const int64_t seg = static_cast<int64_t>(blockIdx.x) * 4 + wave;
+    if (seg >= sg.nseg) return;
+    const int64_t a = sg.owner[seg];
+    const int pidx = sg.pidx[seg];
+    const int64_t eb = sg.begin[seg], ee = sg.end[seg];
     for (int64_t k0 = 0; k0 < s; k0 += 8 * kWave) {
         double acc[8] = {};
-        for (int64_t e = colptr[j]; e < colptr[j + 1]; ++e) {
+        for (int64_t e = eb; e < ee; ++e) {
             const int64_t h = rowidx[e];
             const double v = cval[e];
             const double* Uh = U + h * s;
@@ -80,42 +106,64 @@ __global__ __launch_bounds__(256) void k_sparse_proj(const int64_t* __restrict__
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int64_t k = k0 + u * kWave + lane;
-            if (k < s) {
+            if (k >= s) continue;
+            if (pidx < 0) {
                 const double val = acc[u] * sigma[k];
-                G[k * ldg + off + j] = val;
-                G[(off + j) * ldg + k] = val;
+                G[k * ldg + off + a] = val;
+                G[(off + a) * ldg + k] = val;
+            } else {
+                part[static_cast<int64_t>(pidx) * s + k] = acc[u];
             }
         }
     }
 }
 
-void launch_sparse_proj(const int64_t* colptr, const int* rowidx, const double* cval, int64_t ncols,
-                        const double* U, int64_t s, const double* sigma, double* G, int64_t ldg,
-                        int64_t off, hipStream_t st) {
-    if (ncols <= 0 || s <= 0) return;
-    hipLaunchKernelGGL(k_sparse_proj, dim3(static_cast<unsigned>((ncols + 3) / 4)), dim3(256), 0, st,
-                       colptr, rowidx, cval, ncols, U, s, sigma, G, ldg, off);
+__global__ void k_seg_reduce_proj(SegDev sg, const double* __restrict__ part, int64_t s,
+                                  const double* __restrict__ sigma, double* __restrict__ G,
+                                  int64_t ldg, int64_t off) {
+    const int64_t o = blockIdx.x;
+    const int64_t k = static_cast<int64_t>(blockIdx.y) * blockDim.x + threadIdx.x;
+    if (o >= sg.nmulti || k >= s) return;
+    const int64_t a = sg.multi_owner[o];
+    double acc = 0;
+    for (int64_t p = sg.multi_ptr[o]; p < sg.multi_ptr[o + 1]; ++p) acc += part[p * s + k];
+    const double val = acc * sigma[k];
+    G[k * ldg + off + a] = val;
+    G[(off + a) * ldg + k] = val;
 }
 
-// C[crow(i), :] (+)= cs .* (S[srow(i), :] B) for a sparse S (CSR) and row-major B (K x N).
-// One wave per output row; lanes over the N columns.
-__global__ __launch_bounds__(256) void k_spmm_rows(const int64_t* __restrict__ rowptr,
-                                                   const int* __restrict__ colidx,
-                                                   const double* __restrict__ rval, int64_t M,
-                                                   const int* __restrict__ srow,
+void launch_sparse_proj(const SegDev& sg, const int* rowidx, const double* cval, const double* U,
+                        int64_t s, const double* sigma, double* G, int64_t ldg, int64_t off,
+                        double* part, hipStream_t st) {
+    if (sg.nseg <= 0 || s <= 0) return;
+    hipLaunchKernelGGL(k_sparse_proj, dim3(static_cast<unsigned>((sg.nseg + 3) / 4)), dim3(256), 0, st,
+                       sg, rowidx, cval, U, s, sigma, G, ldg, off, part);
+    if (sg.nmulti > 0)
+        hipLaunchKernelGGL(k_seg_reduce_proj, dim3(static_cast<unsigned>(sg.nmulti),
+                                                   static_cast<unsigned>((s + 255) / 256)),
+                           dim3(256), 0, st, sg, part, s, sigma, G, ldg, off);
+}
+
+// C[crow(h), :] (+)= cs .* (S[h, :] B) for a sparse S (CSR segments over its rows) and a
+// row-major B (K x N).
+__global__ __launch_bounds__(256) void k_spmm_rows(SegDev sg, const int* __restrict__ colidx,
+                                                   const double* __restrict__ rval,
                                                    const double* __restrict__ B, int64_t N,
                                                    const double* __restrict__ cs,
                                                    double* __restrict__ C, int64_t ldc,
-                                                   const int* __restrict__ crow, int accumulate) {
+                                                   const int* __restrict__ crow, int accumulate,
+                                                   double* __restrict__ part) {
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * 4 + wave;
-    if (i >= M) return;
-    const int64_t h = srow ? srow[i] : i;
-    const int64_t ci = crow ? crow[i] : i;
+    const int64_t seg = static_cast<int64_t>(blockIdx.x) * 4 + wave;
+    if (seg >= sg.nseg) return;
+    const int64_t h = sg.owner[seg];
+    const int pidx = sg.pidx[seg];
+    const int64_t ci = crow ? crow[h] : h;
     double* Crow = C + ci * ldc;
+    const int64_t eb = sg.begin[seg], ee = sg.end[seg];
     for (int64_t k0 = 0; k0 < N; k0 += 8 * kWave) {
         double acc[8] = {};
-        for (int64_t e = rowptr[h]; e < rowptr[h + 1]; ++e) {
+        for (int64_t e = eb; e < ee; ++e) {
             const double v = rval[e];
             const double* Bb = B + static_cast<int64_t>(colidx[e]) * N;
 #pragma unroll
@@ -127,21 +175,43 @@ __global__ __launch_bounds__(256) void k_spmm_rows(const int64_t* __restrict__ r
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int64_t k = k0 + u * kWave + lane;
-            if (k < N) {
+            if (k >= N) continue;
+            if (pidx < 0) {
                 double val = acc[u];
                 if (cs) val *= cs[k];
                 Crow[k] = accumulate ? Crow[k] + val : val;
+            } else {
+                part[static_cast<int64_t>(pidx) * N + k] = acc[u];
             }
         }
     }
 }
 
-void launch_spmm_rows(const int64_t* rowptr, const int* colidx, const double* rval, int64_t M,
-                      const int* srow, const double* B, int64_t N, const double* cs, double* C,
-                      int64_t ldc, const int* crow, bool accumulate, hipStream_t st) {
-    if (M <= 0 || N <= 0) return;
-    hipLaunchKernelGGL(k_spmm_rows, dim3(static_cast<unsigned>((M + 3) / 4)), dim3(256), 0, st, rowptr,
-                       colidx, rval, M, srow, B, N, cs, C, ldc, crow, accumulate ? 1 : 0);
+__global__ void k_seg_reduce_spmm(SegDev sg, const double* __restrict__ part, int64_t N,
+                                  const double* __restrict__ cs, double* __restrict__ C,
+                                  int64_t ldc, const int* __restrict__ crow, int accumulate) {
+    const int64_t o = blockIdx.x;
+    const int64_t k = static_cast<int64_t>(blockIdx.y) * blockDim.x + threadIdx.x;
+    if (o >= sg.nmulti || k >= N) return;
+    const int64_t h = sg.multi_owner[o];
+    double acc = 0;
+    for (int64_t p = sg.multi_ptr[o]; p < sg.multi_ptr[o + 1]; ++p) acc += part[p * N + k];
+    if (cs) acc *= cs[k];
+    const int64_t ci = crow ? crow[h] : h;
+    double* dst = C + ci * ldc + k;
+    *dst = accumulate ? *dst + acc : acc;
+}
+
+void launch_spmm_rows(const SegDev& sg, const int* colidx, const double* rval, const double* B,
+                      int64_t N, const double* cs, double* C, int64_t ldc, const int* crow,
+                      bool accumulate, double* part, hipStream_t st) {
+    if (sg.nseg <= 0 || N <= 0) return;
+    hipLaunchKernelGGL(k_spmm_rows, dim3(static_cast<unsigned>((sg.nseg + 3) / 4)), dim3(256), 0, st, sg,
+                       colidx, rval, B, N, cs, C, ldc, crow, accumulate ? 1 : 0, part);
+    if (sg.nmulti > 0)
+        hipLaunchKernelGGL(k_seg_reduce_spmm, dim3(static_cast<unsigned>(sg.nmulti),
+                                                   static_cast<unsigned>((N + 255) / 256)),
+                           dim3(256), 0, st, sg, part, N, cs, C, ldc, crow, accumulate ? 1 : 0);
 }
 
 // Diagonal blocks of V1 Sigma1^2 V1^T into G2 (n1 x n1): one workgroup per dense block.
