@@ -46,6 +46,36 @@ def flop_model(plan, blocks, ranks, L):
     return {"a2": f2, "a3": f3, "a4": f4, "a6": f6, "total": f2 + f3 + f4 + f6}
 
 
+# Per-unit algorithmic work of the eigensolver's pair solve (k_eig_solve): one cyclic Jacobi
+# sweep of a 32 x 32 symmetric pair matrix = 31 steps, each updating all 1024 entries of H
+# (4 multiplies + 3 adds) and of W (2 multiplies + 1 add): 31 * 1024 * 10 flops; the
+# partial-Gram sum adds nchunk * 1024 flops.
+PAIR_SWEEP_FLOPS = 31 * 1024 * 10
+GRAM_ROWS = 128          # rows per partial Gram (eigensolver)
+BW = 16                  # eigensolver column block
+
+
+def eig_shape(q):
+    ld = (q + BW - 1) // BW * BW
+    nblk = ld // BW
+    nbe = nblk + (nblk & 1)
+    return ld, nblk, nbe // 2, nbe - 1, (ld + GRAM_ROWS - 1) // GRAM_ROWS
+
+
+def solve_flops_per_launch(info, sweeps):
+    """Launch-weighted average algorithmic flops of one k_eig_solve launch (all real pairs)."""
+    tot_f = tot_n = 0.0
+    for q, sw in ((info["n1"], sweeps[1]), (info["s"] + info["n2"], sweeps[2])):
+        if q <= 0 or sw <= 0:
+            continue
+        ld, nblk, npairs, rounds, nchunk = eig_shape(q)
+        real_pairs = nblk // 2 + (nblk & 1)          # the odd block out still solves alone
+        f = real_pairs * (PAIR_SWEEP_FLOPS + nchunk * 1024)
+        tot_f += f * rounds * sw
+        tot_n += rounds * sw
+    return tot_f / tot_n if tot_n else 0.0
+
+
 def cpu_baseline(prob, alpha, F, budget_s):
     """The oracle as it stands, on the host cores, repeated on the same workload until
     about budget_s seconds have passed (at least once)."""
@@ -79,6 +109,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64"])
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--roofline-kernel", default="eig_solve",
+                    choices=["eig_solve", "eig_gram", "eig_update", "block_svd"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
@@ -121,15 +153,30 @@ def main():
         step()
     h.sync()
     torch.cuda.synchronize()
+    # the dominant kernel is timed launch by launch with HIP events on the library's stream
+    h.timing_start(args.roofline_kernel)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     h.sync()
+    n_launch, k_ms = h.timing_read()
+    h.timing_start(None)
     ms = dt / args.steps * 1e3
     tflops = F["total"] / (ms * 1e-3) / 1e12
 
+    sweeps = h.last_sweeps()
+    roof = None
+    if n_launch > 0 and args.roofline_kernel == "eig_solve":
+        per_launch = solve_flops_per_launch(plan.info, sweeps)
+        avg_s = k_ms / n_launch * 1e-3
+        achieved = per_launch / avg_s / 1e12
+        peak = 78.6   # MI355X FP64 vector peak, TFLOP/s
+        roof = {"bound": "alu", "kernel": "k_eig_solve", "achieved": round(achieved, 5),
+                "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 6),
+                "traffic": None, "launches": n_launch, "avg_us": round(avg_s * 1e6, 3),
+                "flops_per_launch": per_launch}
     base = None
     if not args.no_cpu_baseline:
         base = cpu_baseline(prob, cfg.alpha, F["total"], args.cpu_budget)
@@ -153,8 +200,8 @@ def main():
                    "alpha": cfg.alpha, "shape": plan.info},
         "flop_model": F,
         "plan_s": round(plan_s, 4),
-        "sweeps": h.last_sweeps(),
-        "roofline": None,
+        "sweeps": sweeps,
+        "roofline": roof,
         "cpu_baseline": base,
     }
     print(json.dumps(out), flush=True)

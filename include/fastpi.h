@@ -177,6 +177,17 @@ int fastpi_sync(fastpi_handle* h);
  * out[0] = block stage (max over blocks), out[1] = row-update core, out[2] = column-update core. */
 int fastpi_last_sweeps(fastpi_handle* h, int32_t* out3);
 
+/*
+ * Measurement hook: times every launch of one kernel of the device path with a HIP event
+ * pair on the handle's stream (each timed launch costs an extra event record).
+ * kind: 0 = eigensolver partial Gram, 1 = eigensolver pair solve, 2 = eigensolver column
+ * update, 3 = block SVD launches, -1 = off. Starting discards earlier timings.
+ */
+int fastpi_timing_start(fastpi_handle* h, int kind);
+/* Waits for the stream; returns the number of timed launches and their summed duration in
+ * milliseconds since fastpi_timing_start, and clears them (timing stays on). */
+int fastpi_timing_read(fastpi_handle* h, int64_t* launches, double* total_ms);
+
 const char* fastpi_last_error(void);
 
 #ifdef __cplusplus

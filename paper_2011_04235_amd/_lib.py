@@ -64,6 +64,8 @@ SIGNATURES = [
     ("fastpi_syev_top", c_int, [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p]),
     ("fastpi_sync", c_int, [c_void_p]),
     ("fastpi_last_sweeps", c_int, [c_void_p, c_void_p]),
+    ("fastpi_timing_start", c_int, [c_void_p, c_int]),
+    ("fastpi_timing_read", c_int, [c_void_p, POINTER(c_int64), POINTER(c_double)]),
     ("fastpi_last_error", ctypes.c_char_p, []),
 ]
 
@@ -253,6 +255,17 @@ class Handle:
         out = np.zeros(3, dtype=np.int32)
         _check(load().fastpi_last_sweeps(self._h, _ptr(out)))
         return out.tolist()
+
+    KERNELS = {"eig_gram": 0, "eig_solve": 1, "eig_update": 2, "block_svd": 3}
+
+    def timing_start(self, kernel):
+        _check(load().fastpi_timing_start(self._h, self.KERNELS[kernel] if kernel else -1))
+
+    def timing_read(self):
+        n = c_int64(0)
+        ms = c_double(0.0)
+        _check(load().fastpi_timing_read(self._h, ctypes.byref(n), ctypes.byref(ms)))
+        return int(n.value), float(ms.value)
 
     def __del__(self):
         h = self.__dict__.get("_h")

@@ -73,6 +73,7 @@ struct fastpi_handle {
     // apply scratch
     double* aws = nullptr;
     size_t aws_bytes = 0;
+    KernelTimer timer;
 };
 
 namespace {
@@ -396,6 +397,7 @@ void fastpi_destroy(fastpi_handle* h) {
     if (h->status) hipFree(h->status);
     if (h->host_pinned) hipHostFree(h->host_pinned);
     if (h->copy_stream) hipStreamDestroy(h->copy_stream);
+    for (hipEvent_t e : h->timer.pool) hipEventDestroy(e);
     delete h;
 }
 
@@ -569,11 +571,15 @@ int fastpi_svd(fastpi_handle* h, const int64_t* rowptr, const int32_t* col, cons
     launch_fill(vals, d.blk_elems, 0.0, st);
     launch_gather(val, d.dst0, d.dst1, d.nnz, vals, h->status, st);
     // a2: block SVDs (Eq. 1)
-    launch_block_svd(mixed, d.work, 0, d.nbig, vals, gsc, d.gscratch_off, kBigLds, U1, sig1, V1,
-                     max_sweeps, tol, h->status + 1, h->status, st);
-    launch_block_svd(mixed, d.work, d.nbig, static_cast<int>(d.B_dense - d.nbig), vals, gsc,
-                     d.gscratch_off, kSmallLds, U1, sig1, V1, max_sweeps, tol, h->status + 1,
-                     h->status, st);
+    {
+        const long ts = h->timer.begin(KT_BLOCK_SVD, st);
+        launch_block_svd(mixed, d.work, 0, d.nbig, vals, gsc, d.gscratch_off, kBigLds, U1, sig1, V1,
+                         max_sweeps, tol, h->status + 1, h->status, st);
+        launch_block_svd(mixed, d.work, d.nbig, static_cast<int>(d.B_dense - d.nbig), vals, gsc,
+                         d.gscratch_off, kSmallLds, U1, sig1, V1, max_sweeps, tol, h->status + 1,
+                         h->status, st);
+        h->timer.end(ts, st);
+    }
     // a3: row update (Eq. 2) -- top s eigenpairs of M2^T M2 = V1 Sigma1^2 V1^T + A21^T A21
     if (n1 > 0 && s > 0) {
         launch_fill(G2, n1 * n1, 0.0, st);
@@ -581,7 +587,7 @@ int fastpi_svd(fastpi_handle* h, const int64_t* rowptr, const int32_t* col, cons
         launch_sparse_gram(d.seg_a21c, d.a21_rowidx, vals + d.off_a21c, d.a21_rowptr, d.a21_colidx,
                            vals + d.off_a21r, n1, G2, n1, true, spart, st);
         rc = eig_top(G2, n1, s, lam2, V2, eigws, h->iws, d.pairs2, max_sweeps, 0.0, 1,
-                     &h->sweeps[1], h->host_pinned, st, h->copy_stream);
+                     &h->sweeps[1], h->host_pinned, st, h->copy_stream, &h->timer);
         if (rc != FASTPI_OK && rc != FASTPI_ENOCONV) return rc;
         if (rc == FASTPI_ENOCONV) launch_fill_i32(h->status, 1, 2, st);
         launch_sqrt_inv(lam2, s, rel_cut, sig2, inv2, st);
@@ -601,7 +607,7 @@ int fastpi_svd(fastpi_handle* h, const int64_t* rowptr, const int32_t* col, cons
         launch_sparse_gram(d.seg_tc, d.t_rowidx, vals + d.off_tc, d.t_rowptr, d.t_colidx,
                            vals + d.off_tr, n2, G3 + s * q3 + s, q3, false, spart, st);
         rc = eig_top(G3, q3, r, lam3, Vt, eigws, h->iws, d.pairs3, max_sweeps, 0.0, 1, &h->sweeps[2],
-                     h->host_pinned, st, h->copy_stream);
+                     h->host_pinned, st, h->copy_stream, &h->timer);
         if (rc != FASTPI_OK && rc != FASTPI_ENOCONV) return rc;
         if (rc == FASTPI_ENOCONV) launch_fill_i32(h->status, 1, 2, st);
         launch_sqrt_inv(lam3, r, rel_cut, sig3, inv3, st);
@@ -710,7 +716,7 @@ int fastpi_syev_top(fastpi_handle* h, int64_t q, const double* G, int64_t t, dou
     HIP_TRY(hipMemcpyAsync(p, tab.data(), tab.size() * sizeof(int2), hipMemcpyHostToDevice, h->stream));
     int sw = 0;
     st = eig_top(G, q, t, vals, vecs, ws, h->iws, static_cast<int2*>(p), h->opts.max_sweeps,
-                 h->opts.tol, 1, &sw, h->host_pinned, h->stream, h->copy_stream);
+                 h->opts.tol, 1, &sw, h->host_pinned, h->stream, h->copy_stream, &h->timer);
     hipStreamSynchronize(h->stream);
     hipFree(p);
     h->sweeps[1] = sw;
@@ -743,6 +749,43 @@ int fastpi_sync(fastpi_handle* h) {
         set_error("internal: block rank above the supported bound");
         return FASTPI_EINTERNAL;
     }
+    return FASTPI_OK;
+}
+
+int fastpi_timing_start(fastpi_handle* h, int kind) {
+    if (!h || kind < KT_NONE || kind > KT_BLOCK_SVD) {
+        set_error("bad handle or kernel kind");
+        return FASTPI_EINVAL;
+    }
+    HIP_TRY(hipSetDevice(h->device));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->timer.target = kind;
+    h->timer.used = 0;
+    h->timer.failed = false;
+    return FASTPI_OK;
+}
+
+int fastpi_timing_read(fastpi_handle* h, int64_t* launches, double* total_ms) {
+    if (!h || !launches || !total_ms) {
+        set_error("null pointer");
+        return FASTPI_EINVAL;
+    }
+    HIP_TRY(hipSetDevice(h->device));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (h->timer.failed) {
+        set_error("event creation failed while timing");
+        return FASTPI_EHIP;
+    }
+    double tot = 0;
+    const size_t pairs = h->timer.used / 2;
+    for (size_t k = 0; k < pairs; ++k) {
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, h->timer.pool[2 * k], h->timer.pool[2 * k + 1]));
+        tot += ms;
+    }
+    *launches = static_cast<int64_t>(pairs);
+    *total_ms = tot;
+    h->timer.used = 0;
     return FASTPI_OK;
 }
 

@@ -87,35 +87,38 @@ __global__ __launch_bounds__(256) void k_eig_gram(const double* __restrict__ X, 
     Hp[3] = acc3;
 }
 
-// Rotation of the symmetric 2x2 [[hpp, hpq], [hpq, hqq]] for the inner sweeps. The angle
-// is only needed approximately (the outer sweeps continue until every pair is orthogonal),
-// but c and s must form an exactly orthogonal pair: tan(theta) is taken in FP32 from the
-// FP64 entries, then (c, s) is renormalised in FP64 with a Newton-corrected reciprocal
-// square root so that c^2 + s^2 = 1 to FP64 rounding.
+// Rotation of the symmetric 2x2 [[hpp, hpq], [hpq, hqq]] for the inner sweeps, in FP64 but
+// with the hardware reciprocal and reciprocal square root, each refined by Newton steps to
+// FP64 accuracy (the IEEE division and square root sequences would sit on the critical path
+// of every step). The angle must be FP64-accurate: an angle taken in FP32 leaves couplings of
+// about 1e-7 (h_pp - h_qq), which stall the outer iteration on graded Grams.
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = r * (2.0 - x * r);
+    return r * (2.0 - x * r);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * (1.5 - 0.5 * x * y * y);
+    return y * (1.5 - 0.5 * x * y * y);
+}
 __device__ __forceinline__ void fast_rotation(double hpp, double hqq, double hpq, double& c, double& s) {
     c = 1.0;
     s = 0.0;
     const double ahpq = fabs(hpq);
-    const double dd = hqq - hpp;
-    // negligible coupling (also covers hpq == 0 and non-finite input)
-    if (!(ahpq > 1e-17 * (fabs(hpp) + fabs(hqq)))) return;
-    const double zeta64 = dd / (2.0 * hpq);
-    const float zeta = static_cast<float>(zeta64);
-    const float az = fabsf(zeta);
-    float t;
-    if (az > 1e15f || !(az == az)) {
-        t = static_cast<float>(0.5 / zeta64);
+    if (hpq == 0.0 || !(ahpq * ahpq > 0.25 * DBL_EPSILON * DBL_EPSILON * fabs(hpp) * fabs(hqq))) return;
+    const double zeta = (hqq - hpp) * rcp_nr(2.0 * hpq);
+    const double az = fabs(zeta);
+    double t;
+    if (az > 1e150) {
+        t = 0.5 * rcp_nr(az);
     } else {
-        t = 1.0f / (az + sqrtf(1.0f + zeta * zeta));
-        if (zeta < 0) t = -t;
+        const double x = 1.0 + zeta * zeta;
+        t = rcp_nr(az + x * rsq_nr(x));   // 1 / (|zeta| + sqrt(1 + zeta^2))
     }
-    const double td = static_cast<double>(t);
-    const double x = 1.0 + td * td;
-    double y = static_cast<double>(rsqrtf(static_cast<float>(x)));
-    y = y * (1.5 - 0.5 * x * y * y);
-    y = y * (1.5 - 0.5 * x * y * y);
-    c = y;
-    s = y * td;
+    if (zeta < 0) t = -t;
+    c = rsq_nr(1.0 + t * t);
+    s = c * t;
 }
 
 // position of index i in the round robin of step `step`: returns its partner and whether
@@ -135,21 +138,34 @@ __device__ __forceinline__ void inner_partner(int step, int i, int& partner, boo
     partner = lower ? q : p;
 }
 
-// One workgroup of PW * PW threads per pair, thread (i, j) owning H[i][j] and W[i][j] in
-// registers. The partials are summed in chunk order; if the pair is not yet orthogonal
-// to `tol`, `inner_sweeps` cyclic Jacobi sweeps (31 steps of 16 disjoint rotations) make
-// H diagonal and W accumulates the rotations. In each step every wave derives the
-// rotations of rows i and j itself from the shared copy of H, then thread (i, j) forms
-// (J^T H J)[i][j] from H[i][j], H[i][j'], H[i'][j], H[i'][j'] and (W J)[i][j] from
-// W[i][j], W[i][j'], writing into the other half of a double buffer: one barrier a step.
-__global__ __launch_bounds__(PW * PW) void k_eig_solve(const double* __restrict__ Hpart, int nchunk,
-                                                       const int2* __restrict__ pairs, int nblk,
-                                                       double* __restrict__ Wout,
-                                                       int* __restrict__ flag,
-                                                       int* __restrict__ rot_count, double tol,
-                                                       int inner_sweeps) {
+// Slot permutation between inner steps. Slots 0..31 hold the 32 columns of a pair; step
+// pairs are always the adjacent slots (2k, 2k+1). Slot 0 keeps the fixed player of the
+// circle-method round robin, slot 1 the player at circle offset 0 and slots 2d, 2d+1 the
+// players at offsets +d and -d; a step moves every circle player one offset down, so the
+// next step pairs the next round-robin partners. After 31 steps every slot is back home.
+__device__ __forceinline__ int inner_next_slot(int x) {
+    if (x == 0) return 0;
+    if (x == 1) return 3;
+    if (x == 2) return 1;
+    if ((x & 1) == 0) return x - 2;   // offset +d -> +(d-1)
+    if (x == PW - 1) return PW - 2;   // offset -15 -> +15
+    return x + 2;                     // offset -d -> -(d+1)
+}
+
+// One workgroup of 256 threads per pair. Thread (a, b) keeps the 2x2 blocks
+// H[2a:2a+2][2b:2b+2] and W[2a:2a+2][2b:2b+2] in registers (H indexed by slots on both
+// sides, W by input column and slot). In a step the 16 diagonal threads compute the rotation
+// of their slot pair, every thread applies J_a^T (.) J_b to its H block and (.) J_b to its W
+// block in registers, and the blocks are scattered to their next slots through LDS.
+__global__ __launch_bounds__(256) void k_eig_solve(const double* __restrict__ Hpart, int nchunk,
+                                                   const int2* __restrict__ pairs, int nblk,
+                                                   double* __restrict__ Wout,
+                                                   int* __restrict__ flag,
+                                                   int* __restrict__ rot_count, double tol,
+                                                   int inner_sweeps) {
     __shared__ double Hs[2][PW][PW + 1];
     __shared__ double Ws[2][PW][PW + 1];
+    __shared__ double rot[PW / 2][2];
     __shared__ int s_need;
     const int pair = blockIdx.x;
     const int2 pb = pairs[pair];
@@ -157,57 +173,89 @@ __global__ __launch_bounds__(PW * PW) void k_eig_solve(const double* __restrict_
         if (threadIdx.x == 0) flag[pair] = 0;
         return;
     }
-    const int i = threadIdx.x / PW, j = threadIdx.x % PW;
-    const double* Hp = Hpart + static_cast<int64_t>(pair) * nchunk * (PW * PW) + threadIdx.x;
-    double h = 0;
-    for (int c = 0; c < nchunk; ++c) h += Hp[static_cast<int64_t>(c) * PW * PW];
-    double w = (i == j) ? 1.0 : 0.0;
-    Hs[0][i][j] = h;
-    Ws[0][i][j] = w;
+    const double* Hp = Hpart + static_cast<int64_t>(pair) * nchunk * (PW * PW);
+    for (int e = threadIdx.x; e < PW * PW; e += 256) {
+        double acc = 0;
+        for (int c = 0; c < nchunk; ++c) acc += Hp[static_cast<int64_t>(c) * PW * PW + e];
+        Hs[0][e / PW][e % PW] = acc;
+    }
     if (threadIdx.x == 0) s_need = 0;
     __syncthreads();
-    if (i < j) {
-        const double hii = Hs[0][i][i], hjj = Hs[0][j][j];
-        if (hii > 0 && hjj > 0 && fabs(h) > tol * sqrt(hii) * sqrt(hjj)) s_need = 1;
+    {
+        int need = 0;
+        for (int e = threadIdx.x; e < PW * PW; e += 256) {
+            const int i = e / PW, j = e % PW;
+            if (i < j) {
+                const double hii = Hs[0][i][i], hjj = Hs[0][j][j], hij = Hs[0][i][j];
+                if (hii > 0 && hjj > 0 && fabs(hij) > tol * sqrt(hii) * sqrt(hjj)) need = 1;
+            }
+        }
+        if (need) s_need = 1;
     }
     __syncthreads();
     if (!s_need) {
         if (threadIdx.x == 0) flag[pair] = 0;
         return;
     }
-    int cur = 0;
+    const int a = threadIdx.x / (PW / 2), b = threadIdx.x % (PW / 2);
+    const int r0 = 2 * a, r1 = 2 * a + 1, c0 = 2 * b, c1 = 2 * b + 1;
+    double h00 = Hs[0][r0][c0], h01 = Hs[0][r0][c1], h10 = Hs[0][r1][c0], h11 = Hs[0][r1][c1];
+    double w00 = (r0 == c0), w01 = (r0 == c1), w10 = (r1 == c0), w11 = (r1 == c1);
+    // slot permutation of the four rows/columns this thread owns
+    const int pr0 = inner_next_slot(r0), pr1 = inner_next_slot(r1);
+    const int pc0 = inner_next_slot(c0), pc1 = inner_next_slot(c1);
+    int buf = 1;
     for (int sw = 0; sw < inner_sweeps; ++sw) {
         for (int step = 0; step < PW - 1; ++step) {
-            int ip, jp;
-            bool il, jl;
-            inner_partner(step, i, ip, il);
-            inner_partner(step, j, jp, jl);
-            double ci, si, cj, sj;
-            {
-                const int a = il ? i : ip, b = il ? ip : i;
-                fast_rotation(Hs[cur][a][a], Hs[cur][b][b], Hs[cur][a][b], ci, si);
-                if (il) si = -si;   // lower index: new = c * own - s * partner
+            if (a == b) {
+                double c, s;
+                fast_rotation(h00, h11, h01, c, s);
+                rot[a][0] = c;
+                rot[a][1] = s;
             }
-            {
-                const int a = jl ? j : jp, b = jl ? jp : j;
-                fast_rotation(Hs[cur][a][a], Hs[cur][b][b], Hs[cur][a][b], cj, sj);
-                if (jl) sj = -sj;
-            }
-            const double h_ij = h;
-            const double h_ijp = Hs[cur][i][jp];
-            const double h_ipj = Hs[cur][ip][j];
-            const double h_ipjp = Hs[cur][ip][jp];
-            const double w_ijp = Ws[cur][i][jp];
-            h = ci * (cj * h_ij + sj * h_ijp) + si * (cj * h_ipj + sj * h_ipjp);
-            w = cj * w + sj * w_ijp;
-            const int nxt = cur ^ 1;
-            Hs[nxt][i][j] = h;
-            Ws[nxt][i][j] = w;
             __syncthreads();
-            cur = nxt;
+            const double ca = rot[a][0], sa = rot[a][1], cb = rot[b][0], sb = rot[b][1];
+            // rows: new row p = c row_p - s row_q, new row q = s row_p + c row_q
+            const double x00 = ca * h00 - sa * h10, x01 = ca * h01 - sa * h11;
+            const double x10 = sa * h00 + ca * h10, x11 = sa * h01 + ca * h11;
+            // columns, likewise
+            h00 = cb * x00 - sb * x01;
+            h01 = sb * x00 + cb * x01;
+            h10 = cb * x10 - sb * x11;
+            h11 = sb * x10 + cb * x11;
+            const double y00 = cb * w00 - sb * w01, y01 = sb * w00 + cb * w01;
+            const double y10 = cb * w10 - sb * w11, y11 = sb * w10 + cb * w11;
+            w00 = y00;
+            w01 = y01;
+            w10 = y10;
+            w11 = y11;
+            // move to the next step's slots (W rows are input columns and stay)
+            Hs[buf][pr0][pc0] = h00;
+            Hs[buf][pr0][pc1] = h01;
+            Hs[buf][pr1][pc0] = h10;
+            Hs[buf][pr1][pc1] = h11;
+            Ws[buf][r0][pc0] = w00;
+            Ws[buf][r0][pc1] = w01;
+            Ws[buf][r1][pc0] = w10;
+            Ws[buf][r1][pc1] = w11;
+            __syncthreads();
+            h00 = Hs[buf][r0][c0];
+            h01 = Hs[buf][r0][c1];
+            h10 = Hs[buf][r1][c0];
+            h11 = Hs[buf][r1][c1];
+            w00 = Ws[buf][r0][c0];
+            w01 = Ws[buf][r0][c1];
+            w10 = Ws[buf][r1][c0];
+            w11 = Ws[buf][r1][c1];
+            buf ^= 1;
         }
     }
-    Wout[static_cast<int64_t>(pair) * PW * PW + threadIdx.x] = w;
+    // after whole sweeps every slot holds its own column again
+    double* Wg = Wout + static_cast<int64_t>(pair) * PW * PW;
+    Wg[r0 * PW + c0] = w00;
+    Wg[r0 * PW + c1] = w01;
+    Wg[r1 * PW + c0] = w10;
+    Wg[r1 * PW + c1] = w11;
     if (threadIdx.x == 0) {
         flag[pair] = 1;
         atomicAdd(rot_count, 1);
@@ -314,7 +362,8 @@ size_t eig_int_workspace(int64_t q, int max_sweeps) {
 // device never waits on the host; a sweep queued after convergence finds nothing to do.
 int eig_top(const double* G, int64_t q, int64_t t, double* vals, double* vecs, double* ws,
             int* iws, const int2* pair_tables, int max_sweeps, double tol, int inner_sweeps,
-            int* sweeps_out, int* host_counter, hipStream_t st, hipStream_t copy_st) {
+            int* sweeps_out, int* host_counter, hipStream_t st, hipStream_t copy_st,
+            KernelTimer* timer) {
     const int64_t ld = eig_padded_order(q);
     const int nblk = static_cast<int>(ld / BW);
     const int nbe = nblk + (nblk & 1);     // even number of slots (the extra one is a dummy)
@@ -351,12 +400,18 @@ int eig_top(const double* G, int64_t q, int64_t t, double* vals, double* vecs, d
     for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
         for (int round = 0; round < rounds; ++round) {
             const int2* pr = pair_tables + static_cast<int64_t>(round) * npairs;
+            long ts = timer ? timer->begin(KT_EIG_GRAM, st) : -1;
             hipLaunchKernelGGL(k_eig_gram, dim3(npairs, nchunk), dim3(256), 0, st, X, ld, pr, nblk, Hpart,
                                nchunk);
-            hipLaunchKernelGGL(k_eig_solve, dim3(npairs), dim3(PW * PW), 0, st, Hpart, nchunk, pr, nblk, W,
+            if (timer) timer->end(ts, st);
+            ts = timer ? timer->begin(KT_EIG_SOLVE, st) : -1;
+            hipLaunchKernelGGL(k_eig_solve, dim3(npairs), dim3(256), 0, st, Hpart, nchunk, pr, nblk, W,
                                flag, rot + sweep, tol, inner_sweeps);
+            if (timer) timer->end(ts, st);
+            ts = timer ? timer->begin(KT_EIG_UPDATE, st) : -1;
             hipLaunchKernelGGL(k_eig_update, dim3(npairs, nupd), dim3(UPD_ROWS), 0, st, X, ld, pr, nblk,
                                W, flag);
+            if (timer) timer->end(ts, st);
         }
         hipEventRecord(ev[sweep & 1], st);
         sweeps_done = sweep + 1;

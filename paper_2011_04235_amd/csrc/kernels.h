@@ -23,6 +23,41 @@ struct SegDev {
     int64_t nseg, nmulti, npart;
 };
 
+// Per-launch timing of one kernel kind with HIP events on the launch stream (measurement
+// only; each timed launch gets an event pair).
+enum KernelKind { KT_NONE = -1, KT_EIG_GRAM = 0, KT_EIG_SOLVE = 1, KT_EIG_UPDATE = 2, KT_BLOCK_SVD = 3 };
+struct KernelTimer {
+    int target = KT_NONE;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    bool failed = false;
+    hipEvent_t take() {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) {
+                failed = true;
+                return nullptr;
+            }
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    // records the start event if `kind` is the timed one; returns the slot index or -1
+    long begin(int kind, hipStream_t st) {
+        if (kind != target || failed) return -1;
+        hipEvent_t e = take();
+        if (!e) return -1;
+        hipEventRecord(e, st);
+        return static_cast<long>(used - 1);
+    }
+    void end(long slot, hipStream_t st) {
+        if (slot < 0) return;
+        hipEvent_t e = take();
+        if (!e) return;
+        hipEventRecord(e, st);
+    }
+};
+
 void launch_fill(double* p, int64_t n, double v, hipStream_t st);
 void launch_fill_i32(int* p, int64_t n, int v, hipStream_t st);
 void launch_gather(const double* val, const int64_t* dst0, const int64_t* dst1, int64_t nnz,
@@ -40,7 +75,8 @@ size_t eig_int_workspace(int64_t q, int max_sweeps);
 void eig_pair_table(int64_t q, std::vector<int2>& out);
 int eig_top(const double* G, int64_t q, int64_t t, double* vals, double* vecs, double* ws,
             int* iws, const int2* pair_tables, int max_sweeps, double tol, int inner_sweeps,
-            int* sweeps_out, int* host_counter, hipStream_t st, hipStream_t copy_st);
+            int* sweeps_out, int* host_counter, hipStream_t st, hipStream_t copy_st,
+            KernelTimer* timer);
 
 // dense (dense.hip)
 int gemm_tn_splits(int64_t M, int64_t N, int64_t K);
