@@ -23,6 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
+import scipy.sparse as sp  # noqa: E402
 
 
 def svd_thin_flops(p, q):
@@ -76,6 +77,16 @@ def solve_flops_per_launch(info, sweeps):
     return tot_f / tot_n if tot_n else 0.0
 
 
+def recon_error(A, U, S, V):
+    """||A - U S V^T||_F / ||A||_F via ||A||^2 - 2 tr(S U^T A V) + tr((U^T U) S (V^T V) S)."""
+    a2 = float(np.sum(A.data ** 2))
+    cross = float(np.sum(S * np.einsum("ij,ij->j", U, A @ V)))
+    G = (U.T @ U) * S[None, :]
+    H = (V.T @ V) * S[None, :]
+    e2 = max(a2 - 2.0 * cross + float(np.sum(G * H.T)), 0.0)
+    return math.sqrt(e2 / a2)
+
+
 def cpu_baseline(prob, alpha, F, budget_s):
     """The oracle as it stands, on the host cores, repeated on the same workload until
     about budget_s seconds have passed (at least once)."""
@@ -106,7 +117,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c2")
-    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--roofline-kernel", default="eig_solve",
@@ -133,40 +144,52 @@ def main():
     F = flop_model(plan, blocks, ranks, cfg.L)
 
     dev = torch.device("cuda", 0)
-    h = fp.Handle(0, precision=args.precision)
-    h.upload_plan(plan)
     rowptr = torch.from_numpy(prob.indptr).to(dev)
     col = torch.from_numpy(prob.indices).to(dev)
     val = torch.from_numpy(prob.data).to(dev)
     Y = torch.from_numpy(prob.Y).to(dev)
     m, n, r = plan.m, plan.n, plan.r
-    U = torch.empty((m, r), dtype=torch.float64, device=dev)
-    S = torch.empty((r,), dtype=torch.float64, device=dev)
-    V = torch.empty((n, r), dtype=torch.float64, device=dev)
-    Z = torch.empty((n, cfg.L), dtype=torch.float64, device=dev)
+    A_host = sp.csr_matrix((prob.data, prob.indices, prob.indptr), shape=(m, n))
 
-    def step():
-        h.svd(rowptr, col, val, out=(U, S, V))
-        h.apply(U, S, V, Y, out=Z)
+    def run_path(precision):
+        h = fp.Handle(0, precision=precision)
+        h.upload_plan(plan)
+        U = torch.empty((m, r), dtype=torch.float64, device=dev)
+        S = torch.empty((r,), dtype=torch.float64, device=dev)
+        V = torch.empty((n, r), dtype=torch.float64, device=dev)
+        Z = torch.empty((n, cfg.L), dtype=torch.float64, device=dev)
 
-    for _ in range(args.warmup):
-        step()
-    h.sync()
-    torch.cuda.synchronize()
-    # the dominant kernel is timed launch by launch with HIP events on the library's stream
-    h.timing_start(args.roofline_kernel)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    h.sync()
-    n_launch, k_ms = h.timing_read()
-    h.timing_start(None)
-    ms = dt / args.steps * 1e3
+        def step():
+            h.svd(rowptr, col, val, out=(U, S, V))
+            h.apply(U, S, V, Y, out=Z)
+
+        for _ in range(args.warmup):
+            step()
+        h.sync()
+        torch.cuda.synchronize()
+        # the dominant kernel is timed launch by launch with HIP events on the library's stream
+        h.timing_start(args.roofline_kernel)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        h.sync()
+        n_launch, k_ms = h.timing_read()
+        h.timing_start(None)
+        sweeps = h.last_sweeps()
+        Uh, Sh, Vh = U.cpu().numpy(), S.cpu().numpy(), V.cpu().numpy()
+        return {"ms": dt / args.steps * 1e3, "sweeps": sweeps, "n_launch": n_launch, "k_ms": k_ms,
+                "recon": recon_error(A_host, Uh, Sh, Vh), "sigma": Sh}
+
+    precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    res = {p: run_path(p) for p in precs}
+    head = res["mixed"] if "mixed" in res else res["fp64"]
+    ms = head["ms"]
     tflops = F["total"] / (ms * 1e-3) / 1e12
+    sweeps = head["sweeps"]
+    n_launch, k_ms = head["n_launch"], head["k_ms"]
 
-    sweeps = h.last_sweeps()
     roof = None
     if n_launch > 0 and args.roofline_kernel == "eig_solve":
         per_launch = solve_flops_per_launch(plan.info, sweeps)
@@ -180,6 +203,14 @@ def main():
     base = None
     if not args.no_cpu_baseline:
         base = cpu_baseline(prob, cfg.alpha, F["total"], args.cpu_budget)
+    compare = {p: {"ms_per_step": round(v["ms"], 3), "tflops": round(F["total"] / v["ms"] / 1e9, 4),
+                   "recon_error": v["recon"], "sweeps": v["sweeps"]} for p, v in res.items()}
+    if "fp64" in res and "mixed" in res:
+        compare["speedup_mixed_vs_fp64"] = round(res["fp64"]["ms"] / res["mixed"]["ms"], 4)
+        compare["recon_error_diff"] = abs(res["fp64"]["recon"] - res["mixed"]["recon"])
+        s64, s32 = res["fp64"]["sigma"], res["mixed"]["sigma"]
+        keep = s64 > 1e-6 * s64[0]
+        compare["sigma_rel_diff"] = float(np.max(np.abs(s64[keep] - s32[keep]) / s64[keep]))
 
     out = {
         "metric": "Ã⁺Y time & TFLOP/s, mixed-precision vs FP64 GPU at equal recon error",
@@ -192,15 +223,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if "mixed" in res else "f64",
         "data": "synthetic",
         "config": {"workload": f"fastpi {cfg.name}: A {m}x{n} ({prob.nnz} nnz, power-law "
                                f"{cfg.gamma}, {cfg.values}), Y {m}x{cfg.L}, alpha {cfg.alpha}",
-                   "precision": args.precision, "m": m, "n": n, "nnz": prob.nnz, "L": cfg.L,
+                   "precision": "mixed" if "mixed" in res else "fp64", "m": m, "n": n,
+                   "nnz": prob.nnz, "L": cfg.L,
                    "alpha": cfg.alpha, "shape": plan.info},
         "flop_model": F,
         "plan_s": round(plan_s, 4),
         "sweeps": sweeps,
+        "precision_compare": compare,
         "roofline": roof,
         "cpu_baseline": base,
     }

@@ -601,7 +601,7 @@ int fastpi_svd(fastpi_handle* h, const int64_t* rowptr, const int32_t* col, cons
         launch_fill(G3, q3 * q3, 0.0, st);
         if (s > 0) {
             const int sp = gemm_tn_splits(s, s, m);
-            launch_gemm_tn(U2, s, U2, s, s, s, m, G3, q3, sig2, sig2, part, sp, st);
+            launch_gemm_tn(U2, s, U2, s, s, s, m, G3, q3, sig2, sig2, part, sp, st, mixed);
             launch_sparse_proj(d.seg_tc, d.t_rowidx, vals + d.off_tc, U2, s, sig2, G3, q3, s, spart, st);
         }
         launch_sparse_gram(d.seg_tc, d.t_rowidx, vals + d.off_tc, d.t_rowptr, d.t_colidx,
@@ -613,10 +613,10 @@ int fastpi_svd(fastpi_handle* h, const int64_t* rowptr, const int32_t* col, cons
         launch_sqrt_inv(lam3, r, rel_cut, sig3, inv3, st);
         launch_col_coeffs(Vt, s, n2, r, sig2, inv3, C1, C2, st);
         // a5: U and V in the caller's order
-        launch_gemm_nn(U2, s, d.piT, C1, r, m, r, s, U, r, nullptr, st);
+        launch_gemm_nn(U2, s, d.piT, C1, r, m, r, s, U, r, nullptr, st, mixed);
         launch_spmm_rows(d.seg_tr, d.t_colidx, vals + d.off_tr, C2, r, nullptr, U, r, d.invT, true,
                          spart, st);
-        launch_gemm_nn(V2, s, nullptr, Vt, r, n1, r, s, V, r, d.invF, st);
+        launch_gemm_nn(V2, s, nullptr, Vt, r, n1, r, s, V, r, d.invF, st, mixed);
         launch_copy_rows(Vt + s * r, n2, r, d.invF + n1, V, st);
         HIP_TRY(hipMemcpyAsync(S, sig3, sizeof(double) * r, hipMemcpyDeviceToDevice, st));
     }
@@ -657,8 +657,9 @@ int fastpi_apply(fastpi_handle* h, int64_t m, int64_t n, int64_t r, const double
     double* W = inv + r;
     double* part = W + r * L;
     launch_pinv_sigma(S, r, static_cast<double>(std::max(m, n)) * DBL_EPSILON, inv, st);
-    launch_gemm_tn(U, r, Y, L, r, L, m, W, L, inv, nullptr, part, sp, st);
-    launch_gemm_nn(V, r, nullptr, W, L, n, L, r, Z, L, nullptr, st);
+    const bool mixed = h->opts.precision == FASTPI_MIXED;
+    launch_gemm_tn(U, r, Y, L, r, L, m, W, L, inv, nullptr, part, sp, st, mixed);
+    launch_gemm_nn(V, r, nullptr, W, L, n, L, r, Z, L, nullptr, st, mixed);
     return check_launch();
 }
 

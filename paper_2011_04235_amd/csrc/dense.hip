@@ -2,7 +2,9 @@
 //
 // On gfx950 the FP64 matrix-core peak equals the FP64 vector-FMA peak (78.6 TFLOP/s), so
 // these are register-tiled FMA kernels: a 256-thread workgroup computes a 64 x 64 tile of C,
-// each thread a 4 x 4 micro-tile, with 16-deep slices of A and B staged in LDS.
+// each thread a 4 x 4 micro-tile, with 16-deep slices of A and B staged in LDS. The compute
+// type Tc is double (FP64 path) or float (mixed path: operands rounded to FP32 on load,
+// products accumulated in FP32, results stored as FP64).
 //
 //   gemm_tn : C_part[z] = A[kz]^T B[kz]  (A: K x M, B: K x N, both row-major; split over K)
 //   gemm_nn : C[ci(i)] = A[ai(i)] B        (A: M x K row-major with optional row gather,
@@ -14,33 +16,34 @@ namespace fastpi {
 
 constexpr int TM = 64, TN = 64, TK = 16;
 
+template <typename Tc>
 __global__ __launch_bounds__(256) void k_gemm_tn(const double* __restrict__ A, int64_t lda,
                                                  const double* __restrict__ B, int64_t ldb,
                                                  int64_t M, int64_t N, int64_t K, int64_t kchunk,
                                                  double* __restrict__ Cpart) {
-    __shared__ double As[TK][TM + 2];
-    __shared__ double Bs[TK][TN + 2];
+    __shared__ Tc As[TK][TM + 2];
+    __shared__ Tc Bs[TK][TN + 2];
     const int64_t i0 = static_cast<int64_t>(blockIdx.x) * TM;
     const int64_t j0 = static_cast<int64_t>(blockIdx.y) * TN;
     const int64_t kb = static_cast<int64_t>(blockIdx.z) * kchunk;
     const int64_t ke = min(K, kb + kchunk);
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    double acc[4][4] = {};
+    Tc acc[4][4] = {};
     for (int64_t k0 = kb; k0 < ke; k0 += TK) {
         for (int e = threadIdx.x; e < TK * TM; e += 256) {
             const int kk = e / TM, ii = e % TM;
             const int64_t k = k0 + kk, i = i0 + ii;
-            As[kk][ii] = (k < ke && i < M) ? A[k * lda + i] : 0.0;
+            As[kk][ii] = static_cast<Tc>((k < ke && i < M) ? A[k * lda + i] : 0.0);
         }
         for (int e = threadIdx.x; e < TK * TN; e += 256) {
             const int kk = e / TN, jj = e % TN;
             const int64_t k = k0 + kk, j = j0 + jj;
-            Bs[kk][jj] = (k < ke && j < N) ? B[k * ldb + j] : 0.0;
+            Bs[kk][jj] = static_cast<Tc>((k < ke && j < N) ? B[k * ldb + j] : 0.0);
         }
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < TK; ++kk) {
-            double a[4], b[4];
+            Tc a[4], b[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 a[u] = As[kk][ty * 4 + u];
@@ -61,7 +64,7 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const double* __restrict__ A, i
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int64_t j = j0 + tx * 4 + v;
-            if (j < N) C[i * N + j] = acc[u][v];
+            if (j < N) C[i * N + j] = static_cast<double>(acc[u][v]);
         }
     }
 }
@@ -82,18 +85,19 @@ __global__ void k_reduce_parts(const double* __restrict__ Cpart, int nsplit, int
     }
 }
 
+template <typename Tc>
 __global__ __launch_bounds__(256) void k_gemm_nn(const double* __restrict__ A, int64_t lda,
                                                  const int* __restrict__ arow,
                                                  const double* __restrict__ B, int64_t ldb,
                                                  int64_t M, int64_t N, int64_t K,
                                                  double* __restrict__ C, int64_t ldc,
                                                  const int* __restrict__ crow) {
-    __shared__ double As[TK][TM + 2];
-    __shared__ double Bs[TK][TN + 2];
+    __shared__ Tc As[TK][TM + 2];
+    __shared__ Tc Bs[TK][TN + 2];
     const int64_t i0 = static_cast<int64_t>(blockIdx.x) * TM;
     const int64_t j0 = static_cast<int64_t>(blockIdx.y) * TN;
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    double acc[4][4] = {};
+    Tc acc[4][4] = {};
     for (int64_t k0 = 0; k0 < K; k0 += TK) {
         for (int e = threadIdx.x; e < TK * TM; e += 256) {
             const int ii = e / TK, kk = e % TK;
@@ -103,17 +107,17 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const double* __restrict__ A, i
                 const int64_t ar = arow ? arow[i] : i;
                 v = A[ar * lda + k];
             }
-            As[kk][ii] = v;
+            As[kk][ii] = static_cast<Tc>(v);
         }
         for (int e = threadIdx.x; e < TK * TN; e += 256) {
             const int kk = e / TN, jj = e % TN;
             const int64_t k = k0 + kk, j = j0 + jj;
-            Bs[kk][jj] = (k < K && j < N) ? B[k * ldb + j] : 0.0;
+            Bs[kk][jj] = static_cast<Tc>((k < K && j < N) ? B[k * ldb + j] : 0.0);
         }
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < TK; ++kk) {
-            double a[4], b[4];
+            Tc a[4], b[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 a[u] = As[kk][ty * 4 + u];
@@ -134,7 +138,7 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const double* __restrict__ A, i
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int64_t j = j0 + tx * 4 + v;
-            if (j < N) C[ci * ldc + j] = acc[u][v];
+            if (j < N) C[ci * ldc + j] = static_cast<double>(acc[u][v]);
         }
     }
 }
@@ -149,13 +153,17 @@ int gemm_tn_splits(int64_t M, int64_t N, int64_t K) {
 
 void launch_gemm_tn(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M,
                     int64_t N, int64_t K, double* C, int64_t ldc, const double* rs,
-                    const double* cs, double* part, int nsplit, hipStream_t st) {
+                    const double* cs, double* part, int nsplit, hipStream_t st, bool fp32) {
     if (M <= 0 || N <= 0) return;
     const int64_t kchunk = ((K + nsplit - 1) / nsplit + TK - 1) / TK * TK;
     dim3 grid(static_cast<unsigned>((M + TM - 1) / TM), static_cast<unsigned>((N + TN - 1) / TN),
               static_cast<unsigned>(nsplit));
-    hipLaunchKernelGGL(k_gemm_tn, grid, dim3(256), 0, st, A, lda, B, ldb, M, N, K,
-                       std::max<int64_t>(kchunk, TK), part);
+    if (fp32)
+        hipLaunchKernelGGL(k_gemm_tn<float>, grid, dim3(256), 0, st, A, lda, B, ldb, M, N, K,
+                           std::max<int64_t>(kchunk, TK), part);
+    else
+        hipLaunchKernelGGL(k_gemm_tn<double>, grid, dim3(256), 0, st, A, lda, B, ldb, M, N, K,
+                           std::max<int64_t>(kchunk, TK), part);
     const int64_t n = M * N;
     hipLaunchKernelGGL(k_reduce_parts, dim3(static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 8192))),
                        dim3(256), 0, st, part, nsplit, M, N, C, ldc, rs, cs);
@@ -163,10 +171,15 @@ void launch_gemm_tn(const double* A, int64_t lda, const double* B, int64_t ldb, 
 
 void launch_gemm_nn(const double* A, int64_t lda, const int* arow, const double* B, int64_t ldb,
                     int64_t M, int64_t N, int64_t K, double* C, int64_t ldc, const int* crow,
-                    hipStream_t st) {
+                    hipStream_t st, bool fp32) {
     if (M <= 0 || N <= 0) return;
     dim3 grid(static_cast<unsigned>((M + TM - 1) / TM), static_cast<unsigned>((N + TN - 1) / TN));
-    hipLaunchKernelGGL(k_gemm_nn, grid, dim3(256), 0, st, A, lda, arow, B, ldb, M, N, K, C, ldc, crow);
+    if (fp32)
+        hipLaunchKernelGGL(k_gemm_nn<float>, grid, dim3(256), 0, st, A, lda, arow, B, ldb, M, N, K, C, ldc,
+                           crow);
+    else
+        hipLaunchKernelGGL(k_gemm_nn<double>, grid, dim3(256), 0, st, A, lda, arow, B, ldb, M, N, K, C, ldc,
+                           crow);
 }
 
 }  // namespace fastpi

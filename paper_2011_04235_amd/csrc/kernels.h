@@ -82,10 +82,10 @@ int eig_top(const double* G, int64_t q, int64_t t, double* vals, double* vecs, d
 int gemm_tn_splits(int64_t M, int64_t N, int64_t K);
 void launch_gemm_tn(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M,
                     int64_t N, int64_t K, double* C, int64_t ldc, const double* rs,
-                    const double* cs, double* part, int nsplit, hipStream_t st);
+                    const double* cs, double* part, int nsplit, hipStream_t st, bool fp32 = false);
 void launch_gemm_nn(const double* A, int64_t lda, const int* arow, const double* B, int64_t ldb,
                     int64_t M, int64_t N, int64_t K, double* C, int64_t ldc, const int* crow,
-                    hipStream_t st);
+                    hipStream_t st, bool fp32 = false);
 
 // sparse and block-structured (sparse.hip)
 void launch_sparse_gram(const SegDev& sg, const int* rowidx, const double* cval,

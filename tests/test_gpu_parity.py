@@ -164,3 +164,31 @@ def test_nonfinite_value_is_reported(fp, torch):
     with pytest.raises(fp.FastPIError) as ei:
         h.sync()
     assert ei.value.status == "ENONFINITE"
+
+
+# ------------------------------------------------------------------ mixed precision -----
+MIXED = [
+    ("c1", "c1", 0.3),
+    ("small-a1", small_config(300, 80, 0.05, alpha=1.0, seed=7, k=0.05, L=6), 1.0),
+    ("c2", "c2", 0.2),
+]
+
+
+@pytest.mark.parametrize("name,cfg,alpha", MIXED, ids=[s[0] for s in MIXED])
+def test_mixed_precision_meets_gates(fp, torch, name, cfg, alpha):
+    """FP32 block Jacobi and FP32 GEMMs with the FP64 cores: sigma within 1e-5, the
+    reconstruction error within 1e-5 of the oracle's, the regression residual within 1e-4."""
+    prob = make_problem(cfg)
+    say(f"mixed {name} m={prob.m} n={prob.n} alpha={alpha}")
+    h, plan, U, S, V = run_gpu(fp, torch, prob, alpha, precision="mixed")
+    ores = run_oracle(prob, alpha)
+    ok, info = compare_svd(prob, to_np(U), to_np(S), to_np(V), ores,
+                           sigma_rtol=MIXED_SIGMA_RTOL, product_rtol=1e-4,
+                           recon_atol=MIXED_RECON_ATOL, orth_atol=1e-5)
+    say(f"  {info}")
+    assert ok, info
+    Z = h.apply(U, S, V, torch.from_numpy(prob.Y).cuda())
+    torch.cuda.synchronize()
+    _, zinfo = compare_apply(prob, to_np(Z), ores)
+    say(f"  {zinfo}")
+    assert zinfo["ls_rel"] <= MIXED_LS_RTOL, zinfo
