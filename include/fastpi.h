@@ -58,7 +58,7 @@ typedef struct {
 
 typedef struct {
     fastpi_precision precision;   /* FASTPI_FP64 (default) or FASTPI_MIXED                  */
-    int max_sweeps;               /* Jacobi sweep cap (0 = default 40)                       */
+    int max_sweeps;               /* Jacobi sweep cap (0 = default 60)                       */
     double tol;                   /* Jacobi rotation threshold (0 = default, size * eps)     */
     size_t max_workspace_bytes;   /* 0 = unlimited; larger needs fail with FASTPI_ENOMEM     */
 } fastpi_options;
@@ -112,6 +112,41 @@ int fastpi_plan_blocks(const fastpi_plan* plan, int64_t* blocks);
 /* Copies the rank s_i of every block (host int64[B]). */
 int fastpi_plan_block_ranks(const fastpi_plan* plan, int64_t* ranks);
 void fastpi_plan_destroy(fastpi_plan* plan);
+
+/*
+ * The 16 features of every dense diagonal block (height and width > 0), in block order, as
+ * rows of out (host double[B_dense * 16]); val is the caller's host CSR values (the plan's
+ * pattern). Features: log rows, log cols, log nnz, density, log ||A_i||_F^2, log max / log min
+ * / mean / std of the log squared column norms (in that order: max, min, mean, std),
+ * log max squared row norm, ||A_i||_F^2 / max squared column norm, the block's share of
+ * ||A11||_F^2, alpha, cols / n1, log(1 + edges from the block into hub rows and columns),
+ * block index / number of blocks. Used by the learned rank predictor.
+ */
+int fastpi_block_features(const fastpi_plan* plan, const double* val, double* out);
+
+/*
+ * Replaces the per-block ranks of Eq. 1 (host int64[B], one per block, 0 for blocks of height
+ * or width 0) and recomputes s_b, s and r; each rank is clamped to min(rows, cols). Lets a
+ * learned allocation replace the ceil(alpha n_i) rule. Upload the plan again afterwards.
+ */
+int fastpi_plan_set_block_ranks(fastpi_plan* plan, const int64_t* ranks);
+
+/*
+ * Learned rank predictor: a 16-64-64-1 network (ReLU, ReLU, sigmoid), FP32, predicting a
+ * block's kept fraction s_i / min(rows, cols). Packed parameters (device float[5313]):
+ * W1 (64x16 row-major), b1 (64), W2 (64x64), b2 (64), W3 (64), b3.
+ *   fastpi_mlp_forward : f = net(X) for X device float[N*16] (row-major), f device float[N];
+ *   fastpi_mlp_gradient: gradient of mean((f - y)^2) over the N samples, grad device
+ *                        float[5313], summed in a fixed order (bitwise reproducible);
+ *   fastpi_mlp_adam    : one Adam step (beta1 0.9, beta2 0.999, eps 1e-8; step counts from 1)
+ *                        on theta, with moment buffers m, v (device float[5313], start at 0).
+ */
+int fastpi_mlp_param_count(void);
+int fastpi_mlp_forward(fastpi_handle* h, int64_t N, const float* X, const float* theta, float* f);
+int fastpi_mlp_gradient(fastpi_handle* h, int64_t N, const float* X, const float* y,
+                        const float* theta, float* grad);
+int fastpi_mlp_adam(fastpi_handle* h, float* theta, const float* grad, float* m, float* v,
+                    int64_t step, float lr);
 
 /*
  * Device handle: binds a HIP device and stream (stream may be NULL for the default stream)

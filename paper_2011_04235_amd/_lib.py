@@ -64,6 +64,13 @@ SIGNATURES = [
     ("fastpi_syev_top", c_int, [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p]),
     ("fastpi_sync", c_int, [c_void_p]),
     ("fastpi_last_sweeps", c_int, [c_void_p, c_void_p]),
+    ("fastpi_block_features", c_int, [c_void_p, c_void_p, c_void_p]),
+    ("fastpi_plan_set_block_ranks", c_int, [c_void_p, c_void_p]),
+    ("fastpi_mlp_param_count", c_int, []),
+    ("fastpi_mlp_forward", c_int, [c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
+    ("fastpi_mlp_gradient", c_int, [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
+    ("fastpi_mlp_adam", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int64,
+                                ctypes.c_float]),
     ("fastpi_timing_start", c_int, [c_void_p, c_int]),
     ("fastpi_timing_read", c_int, [c_void_p, POINTER(c_int64), POINTER(c_double)]),
     ("fastpi_last_error", ctypes.c_char_p, []),
@@ -163,6 +170,23 @@ class Plan:
             _check(load().fastpi_plan_block_ranks(self._h, _ptr(out)))
         return out
 
+    def block_features(self, data):
+        """16 features of every dense diagonal block, in block order (host)."""
+        data = np.ascontiguousarray(data, dtype=np.float64)
+        out = np.empty((self.info["B_dense"], 16), dtype=np.float64)
+        if out.size:
+            _check(load().fastpi_block_features(self._h, _ptr(data), _ptr(out)))
+        return out
+
+    def set_block_ranks(self, ranks):
+        """Per-block ranks (one per block of the block table); refreshes the shape info."""
+        ranks = np.ascontiguousarray(ranks, dtype=np.int64)
+        assert ranks.shape == (self.info["B"],)
+        _check(load().fastpi_plan_set_block_ranks(self._h, _ptr(ranks)))
+        sp = Split()
+        _check(load().fastpi_plan_info(self._h, ctypes.byref(sp)))
+        self.info = sp.as_dict()
+
     def __del__(self):
         h = self.__dict__.get("_h")
         if h is not None and _lib is not None:
@@ -257,6 +281,22 @@ class Handle:
         return out.tolist()
 
     KERNELS = {"eig_gram": 0, "eig_solve": 1, "eig_update": 2, "block_svd": 3}
+
+    # ---- learned rank predictor (device float32 tensors) ----
+    def mlp_forward(self, X, theta):
+        f = self.torch.empty((X.shape[0],), dtype=self.torch.float32, device=self.device)
+        _check(load().fastpi_mlp_forward(self._h, X.shape[0], _dptr(X), _dptr(theta), _dptr(f)))
+        return f
+
+    def mlp_gradient(self, X, y, theta, out=None):
+        g = out if out is not None else self.torch.empty_like(theta)
+        _check(load().fastpi_mlp_gradient(self._h, X.shape[0], _dptr(X), _dptr(y), _dptr(theta),
+                                          _dptr(g)))
+        return g
+
+    def mlp_adam(self, theta, grad, m, v, step, lr):
+        _check(load().fastpi_mlp_adam(self._h, _dptr(theta), _dptr(grad), _dptr(m), _dptr(v),
+                                      int(step), float(lr)))
 
     def timing_start(self, kernel):
         _check(load().fastpi_timing_start(self._h, self.KERNELS[kernel] if kernel else -1))

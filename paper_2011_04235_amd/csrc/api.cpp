@@ -74,6 +74,9 @@ struct fastpi_handle {
     double* aws = nullptr;
     size_t aws_bytes = 0;
     KernelTimer timer;
+    // rank-predictor scratch
+    float* mws = nullptr;
+    size_t mws_bytes = 0;
 };
 
 namespace {
@@ -350,7 +353,7 @@ int fastpi_create(fastpi_handle** h, int device, void* hip_stream, const fastpi_
     H->device = device;
     H->stream = static_cast<hipStream_t>(hip_stream);
     if (opts) H->opts = *opts;
-    if (H->opts.max_sweeps <= 0) H->opts.max_sweeps = 40;
+    if (H->opts.max_sweeps <= 0) H->opts.max_sweeps = 60;
     void* p = nullptr;
     if (hipMalloc(&p, 64) != hipSuccess) {
         delete H;
@@ -394,6 +397,7 @@ void fastpi_destroy(fastpi_handle* h) {
     if (h->ws) hipFree(h->ws);
     if (h->iws) hipFree(h->iws);
     if (h->aws) hipFree(h->aws);
+    if (h->mws) hipFree(h->mws);
     if (h->status) hipFree(h->status);
     if (h->host_pinned) hipHostFree(h->host_pinned);
     if (h->copy_stream) hipStreamDestroy(h->copy_stream);
@@ -751,6 +755,80 @@ int fastpi_sync(fastpi_handle* h) {
         return FASTPI_EINTERNAL;
     }
     return FASTPI_OK;
+}
+
+int fastpi_block_features(const fastpi_plan* plan, const double* val, double* out) {
+    if (!plan || !val || !out) {
+        set_error("null pointer");
+        return FASTPI_EINVAL;
+    }
+    return block_features(plan->p, val, out);
+}
+
+int fastpi_plan_set_block_ranks(fastpi_plan* plan, const int64_t* ranks) {
+    if (!plan || !ranks) {
+        set_error("null pointer");
+        return FASTPI_EINVAL;
+    }
+    const size_t B = plan->p.ro.blocks.size();
+    std::vector<int64_t> r(ranks, ranks + B);
+    for (int64_t v : r)
+        if (v < 0) {
+            set_error("negative block rank");
+            return FASTPI_EINVAL;
+        }
+    assign_ranks(plan->p, r);
+    return FASTPI_OK;
+}
+
+int fastpi_mlp_param_count(void) { return mlp_param_count(); }
+
+int fastpi_mlp_forward(fastpi_handle* h, int64_t N, const float* X, const float* theta, float* f) {
+    if (!h || N < 0 || (N > 0 && (!X || !theta || !f))) {
+        set_error("bad arguments");
+        return FASTPI_EINVAL;
+    }
+    HIP_TRY(hipSetDevice(h->device));
+    launch_mlp_forward(N, X, theta, f, nullptr, h->stream);
+    return check_launch();
+}
+
+int fastpi_mlp_gradient(fastpi_handle* h, int64_t N, const float* X, const float* y,
+                        const float* theta, float* grad) {
+    if (!h || N <= 0 || !X || !y || !theta || !grad) {
+        set_error("bad arguments");
+        return FASTPI_EINVAL;
+    }
+    HIP_TRY(hipSetDevice(h->device));
+    const size_t need = mlp_scratch_floats(N) * sizeof(float);
+    if (need > h->mws_bytes) {
+        if (h->mws) {
+            hipStreamSynchronize(h->stream);
+            hipFree(h->mws);
+            h->mws = nullptr;
+            h->mws_bytes = 0;
+        }
+        void* p = nullptr;
+        if (hipMalloc(&p, need) != hipSuccess) {
+            set_error("device allocation failed (rank-predictor scratch)");
+            return FASTPI_ENOMEM;
+        }
+        h->mws = static_cast<float*>(p);
+        h->mws_bytes = need;
+    }
+    launch_mlp_gradient(N, X, y, theta, grad, h->mws, h->stream);
+    return check_launch();
+}
+
+int fastpi_mlp_adam(fastpi_handle* h, float* theta, const float* grad, float* m, float* v,
+                    int64_t step, float lr) {
+    if (!h || !theta || !grad || !m || !v || step < 1) {
+        set_error("bad arguments");
+        return FASTPI_EINVAL;
+    }
+    HIP_TRY(hipSetDevice(h->device));
+    launch_mlp_adam(theta, grad, m, v, step, lr, h->stream);
+    return check_launch();
 }
 
 int fastpi_timing_start(fastpi_handle* h, int kind) {

@@ -32,6 +32,27 @@ __global__ void k_eig_init(const double* __restrict__ G, int64_t q, int64_t ld,
     }
 }
 
+// floor[0] = (ld eps)^2 ld max_c ||G_c||^2: columns of X = G V whose squared norm is below
+// it are rounding noise of a (numerically) zero eigenvalue -- ||x_c|| = lambda_c, whose
+// rounding level is ~ ld eps lambda_1, and lambda_1 <= sqrt(ld) max_c ||G_c|| -- and are
+// treated as converged (their cosines with anything are meaningless).
+__global__ __launch_bounds__(256) void k_eig_floor(const double* __restrict__ norms, int64_t ld,
+                                                   double* __restrict__ floor_out) {
+    __shared__ double red[256];
+    double mx = 0;
+    for (int64_t c = threadIdx.x; c < ld; c += blockDim.x) mx = norms[c] > mx ? norms[c] : mx;
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w && red[threadIdx.x + w] > red[threadIdx.x]) red[threadIdx.x] = red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double e = static_cast<double>(ld) * DBL_EPSILON;
+        floor_out[0] = isfinite(red[0]) ? e * e * static_cast<double>(ld) * red[0] * red[0] : 0.0;
+    }
+}
+
 // pair k of step `step` of the round robin over the PW columns of a pair, p < q
 __device__ __forceinline__ void inner_pair(int step, int k, int& p, int& q) {
     int a, b;
@@ -162,7 +183,8 @@ __global__ __launch_bounds__(256) void k_eig_solve(const double* __restrict__ Hp
                                                    double* __restrict__ Wout,
                                                    int* __restrict__ flag,
                                                    int* __restrict__ rot_count, double tol,
-                                                   int inner_sweeps) {
+                                                   int inner_sweeps,
+                                                   const double* __restrict__ noise_floor) {
     __shared__ double Hs[2][PW][PW + 1];
     __shared__ double Ws[2][PW][PW + 1];
     __shared__ double rot[PW / 2][2];
@@ -181,13 +203,14 @@ __global__ __launch_bounds__(256) void k_eig_solve(const double* __restrict__ Hp
     }
     if (threadIdx.x == 0) s_need = 0;
     __syncthreads();
+    const double nf = noise_floor[0];
     {
         int need = 0;
         for (int e = threadIdx.x; e < PW * PW; e += 256) {
             const int i = e / PW, j = e % PW;
             if (i < j) {
                 const double hii = Hs[0][i][i], hjj = Hs[0][j][j], hij = Hs[0][i][j];
-                if (hii > 0 && hjj > 0 && fabs(hij) > tol * sqrt(hii) * sqrt(hjj)) need = 1;
+                if (hii > nf && hjj > nf && fabs(hij) > tol * sqrt(hii) * sqrt(hjj)) need = 1;
             }
         }
         if (need) s_need = 1;
@@ -208,8 +231,8 @@ __global__ __launch_bounds__(256) void k_eig_solve(const double* __restrict__ Hp
     for (int sw = 0; sw < inner_sweeps; ++sw) {
         for (int step = 0; step < PW - 1; ++step) {
             if (a == b) {
-                double c, s;
-                fast_rotation(h00, h11, h01, c, s);
+                double c = 1.0, s = 0.0;
+                if (h00 > nf && h11 > nf) fast_rotation(h00, h11, h01, c, s);
                 rot[a][0] = c;
                 rot[a][1] = s;
             }
@@ -390,6 +413,8 @@ int eig_top(const double* G, int64_t q, int64_t t, double* vals, double* vecs, d
     hipLaunchKernelGGL(k_eig_init, dim3(static_cast<int>(std::min<int64_t>((ld * ld + 255) / 256, 8192))),
                        dim3(256), 0, st, G, q, ld, X);
     launch_fill_i32(rot, max_sweeps, 0, st);
+    hipLaunchKernelGGL(k_eig_norms, dim3(static_cast<int>((ld + 3) / 4)), dim3(256), 0, st, X, ld, q, lam);
+    hipLaunchKernelGGL(k_eig_floor, dim3(1), dim3(256), 0, st, lam, ld, lam + ld);
     if (tol <= 0) tol = static_cast<double>(ld) * DBL_EPSILON;
     hipEvent_t ev[2];
     if (hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) != hipSuccess) return FASTPI_EHIP;
@@ -406,7 +431,7 @@ int eig_top(const double* G, int64_t q, int64_t t, double* vals, double* vecs, d
             if (timer) timer->end(ts, st);
             ts = timer ? timer->begin(KT_EIG_SOLVE, st) : -1;
             hipLaunchKernelGGL(k_eig_solve, dim3(npairs), dim3(256), 0, st, Hpart, nchunk, pr, nblk, W,
-                               flag, rot + sweep, tol, inner_sweeps);
+                               flag, rot + sweep, tol, inner_sweeps, lam + ld);
             if (timer) timer->end(ts, st);
             ts = timer ? timer->begin(KT_EIG_UPDATE, st) : -1;
             hipLaunchKernelGGL(k_eig_update, dim3(npairs, nupd), dim3(UPD_ROWS), 0, st, X, ld, pr, nblk,

@@ -1,6 +1,7 @@
 // Host-side structures shared by the reordering, the planner and the C ABI.
 #pragma once
 
+#include <cmath>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -80,5 +81,7 @@ struct Plan {
 
 int build_plan(Plan& p, int64_t m, int64_t n, const int64_t* rowptr, const int32_t* col,
                const double* val, double alpha, double k);
+void assign_ranks(Plan& p, const std::vector<int64_t>& ranks);
+int block_features(const Plan& p, const double* val, double* out);
 
 }  // namespace fastpi

@@ -110,4 +110,14 @@ void launch_copy_rows(const double* src, int64_t rows, int64_t cols, const int* 
                       hipStream_t st);
 void launch_pinv_sigma(const double* S, int64_t r, double cut, double* inv, hipStream_t st);
 
+// rank predictor (mlp.hip)
+int mlp_param_count();
+size_t mlp_scratch_floats(int64_t N);
+void launch_mlp_forward(int64_t N, const float* X, const float* th, float* f, float* act,
+                        hipStream_t st);
+void launch_mlp_gradient(int64_t N, const float* X, const float* y, const float* th, float* grad,
+                         float* scratch, hipStream_t st);
+void launch_mlp_adam(float* th, const float* g, float* m, float* v, int64_t step, float lr,
+                     hipStream_t st);
+
 }  // namespace fastpi

@@ -28,34 +28,18 @@ void build_segments(const std::vector<int64_t>& ptr, Segments& out) {
     }
 }
 
-int build_plan(Plan& p, int64_t m, int64_t n, const int64_t* rowptr, const int32_t* col,
-               const double* val, double alpha, double k) {
-    if (!(alpha > 0.0 && alpha <= 1.0)) {
-        set_error("alpha must lie in (0, 1]");
-        return FASTPI_EINVAL;
-    }
-    int st = validate_csr(m, n, rowptr, col, val);
-    if (st != FASTPI_OK) return st;
-    st = reorder_pattern(m, n, rowptr, col, val, k, p.ro);
-    if (st != FASTPI_OK) return st;
-    p.m = m;
-    p.n = n;
-    p.nnz = rowptr[m];
-    p.alpha = alpha;
-    p.k = k;
+// Block work list, packed-output offsets and stage ranks for the given per-block ranks:
+// s = min(ceil(alpha n1), s_b + m2, n1) and r = min(ceil(alpha min(m, n)), s + n2, m).
+void assign_ranks(Plan& p, const std::vector<int64_t>& ranks) {
     const ReorderOut& R = p.ro;
-    const int64_t m1 = R.m1, n1 = R.n1, m2 = R.m2, n2 = R.n2;
     const int64_t B = static_cast<int64_t>(R.blocks.size());
-
-    // ranks: s_i = min(ceil(alpha n_i), m_i, n_i); s = min(ceil(alpha n1), s_b + m2, n1);
-    // r = min(ceil(alpha min(m, n)), s + n2, m)
     p.block_rank.assign(B, 0);
     p.work.clear();
     int64_t blk = 0, u1 = 0, v1 = 0, sb = 0;
     for (int64_t b = 0; b < B; ++b) {
         const BlockDesc& d = R.blocks[b];
         if (d.rows == 0 || d.cols == 0) continue;
-        const int64_t si = std::min({target_rank(alpha, d.cols), d.rows, d.cols});
+        const int64_t si = std::max<int64_t>(0, std::min({ranks[b], d.rows, d.cols}));
         p.block_rank[b] = si;
         BlockWork w{};
         w.data_off = blk;
@@ -78,8 +62,8 @@ int build_plan(Plan& p, int64_t m, int64_t n, const int64_t* rowptr, const int32
     p.u1_elems = u1;
     p.v1_elems = v1;
     p.s_b = sb;
-    p.s = std::min({target_rank(alpha, n1), sb + m2, n1});
-    p.r = std::min({target_rank(alpha, std::min(m, n)), p.s + n2, m});
+    p.s = std::min({target_rank(p.alpha, R.n1), sb + R.m2, R.n1});
+    p.r = std::min({target_rank(p.alpha, std::min(p.m, p.n)), p.s + R.n2, p.m});
     // largest Jacobi cost first (p q^2 with p >= q), ties by block order
     std::stable_sort(p.work.begin(), p.work.end(), [](const BlockWork& a, const BlockWork& b) {
         auto cost = [](const BlockWork& w) {
@@ -88,6 +72,97 @@ int build_plan(Plan& p, int64_t m, int64_t n, const int64_t* rowptr, const int32
         };
         return cost(a) > cost(b);
     });
+}
+
+int block_features(const Plan& p, const double* val, double* out) {
+    const ReorderOut& R = p.ro;
+    // dense blocks rebuilt from the value maps (block order, column-major per block)
+    std::vector<double> blk(static_cast<size_t>(p.blk_elems), 0.0);
+    for (int64_t e = 0; e < p.nnz; ++e)
+        if (p.dst0[e] >= 0 && p.dst0[e] < p.blk_elems) blk[p.dst0[e]] = val[e];
+    double a11 = 0;
+    for (double v : blk) a11 += v * v;
+    const double tiny = 1e-300;
+    const int64_t B = static_cast<int64_t>(R.blocks.size());
+    int64_t off = 0, k = 0;
+    for (int64_t b = 0; b < B; ++b) {
+        const BlockDesc& d = R.blocks[b];
+        if (d.rows == 0 || d.cols == 0) continue;
+        const int64_t mi = d.rows, ni = d.cols;
+        const double* A = blk.data() + off;
+        int64_t nnz = 0;
+        double fro2 = 0, cmax = 0, cmin = 0, lsum = 0, rmax = 0;
+        std::vector<double> lc(ni), row2(mi, 0.0);
+        for (int64_t c = 0; c < ni; ++c) {
+            double s = 0;
+            for (int64_t r = 0; r < mi; ++r) {
+                const double v = A[c * mi + r];
+                nnz += (v != 0.0);
+                s += v * v;
+                row2[r] += v * v;
+            }
+            fro2 += s;
+            cmax = c == 0 ? s : std::max(cmax, s);
+            cmin = c == 0 ? s : std::min(cmin, s);
+            lc[c] = std::log(std::max(s, tiny));
+            lsum += lc[c];
+        }
+        for (int64_t r = 0; r < mi; ++r) rmax = std::max(rmax, row2[r]);
+        const double lmean = lsum / static_cast<double>(ni);
+        double var = 0;
+        for (int64_t c = 0; c < ni; ++c) var += (lc[c] - lmean) * (lc[c] - lmean);
+        var /= static_cast<double>(ni);
+        int64_t hub = 0;
+        for (int64_t r = d.row0; r < d.row0 + mi; ++r) hub += p.t_rowptr[r + 1] - p.t_rowptr[r];
+        for (int64_t c = d.col0; c < d.col0 + ni; ++c) hub += p.a21_colptr[c + 1] - p.a21_colptr[c];
+        double* f = out + k * 16;
+        f[0] = std::log(static_cast<double>(mi));
+        f[1] = std::log(static_cast<double>(ni));
+        f[2] = std::log(static_cast<double>(std::max<int64_t>(nnz, 1)));
+        f[3] = static_cast<double>(nnz) / static_cast<double>(mi * ni);
+        f[4] = std::log(std::max(fro2, tiny));
+        f[5] = std::log(std::max(cmax, tiny));
+        f[6] = std::log(std::max(cmin, tiny));
+        f[7] = lmean;
+        f[8] = std::sqrt(var);
+        f[9] = std::log(std::max(rmax, tiny));
+        f[10] = fro2 / std::max(cmax, tiny);
+        f[11] = fro2 / std::max(a11, tiny);
+        f[12] = p.alpha;
+        f[13] = static_cast<double>(ni) / static_cast<double>(std::max<int64_t>(R.n1, 1));
+        f[14] = std::log1p(static_cast<double>(hub));
+        f[15] = static_cast<double>(b) / static_cast<double>(std::max<int64_t>(B, 1));
+        off += mi * ni;
+        ++k;
+    }
+    return FASTPI_OK;
+}
+
+int build_plan(Plan& p, int64_t m, int64_t n, const int64_t* rowptr, const int32_t* col,
+               const double* val, double alpha, double k) {
+    if (!(alpha > 0.0 && alpha <= 1.0)) {
+        set_error("alpha must lie in (0, 1]");
+        return FASTPI_EINVAL;
+    }
+    int st = validate_csr(m, n, rowptr, col, val);
+    if (st != FASTPI_OK) return st;
+    st = reorder_pattern(m, n, rowptr, col, val, k, p.ro);
+    if (st != FASTPI_OK) return st;
+    p.m = m;
+    p.n = n;
+    p.nnz = rowptr[m];
+    p.alpha = alpha;
+    p.k = k;
+    const ReorderOut& R = p.ro;
+    const int64_t m1 = R.m1, n1 = R.n1, m2 = R.m2, n2 = R.n2;
+    const int64_t B = static_cast<int64_t>(R.blocks.size());
+
+    std::vector<int64_t> ranks(B, 0);
+    for (int64_t b = 0; b < B; ++b) {
+        const BlockDesc& d = R.blocks[b];
+        if (d.rows > 0 && d.cols > 0) ranks[b] = std::min({target_rank(alpha, d.cols), d.rows, d.cols});
+    }
+    assign_ranks(p, ranks);
 
     // inverse permutations and the block id of every spoke row
     p.invT.assign(m, 0);
@@ -136,7 +211,7 @@ int build_plan(Plan& p, int64_t m, int64_t n, const int64_t* rowptr, const int32
     for (int64_t i = 0; i < m; ++i) p.t_rowptr[i + 1] += p.t_rowptr[i];
     for (int64_t j = 0; j < n2; ++j) p.t_colptr[j + 1] += p.t_colptr[j];
     const int64_t nnz21 = p.a21_rowptr[m2], nnzT = p.t_rowptr[m];
-    p.off_a21r = blk;
+    p.off_a21r = p.blk_elems;
     p.off_a21c = p.off_a21r + nnz21;
     p.off_tr = p.off_a21c + nnz21;
     p.off_tc = p.off_tr + nnzT;
