@@ -63,8 +63,18 @@ typedef struct {
     size_t max_workspace_bytes;   /* 0 = unlimited; larger needs fail with FASTPI_ENOMEM     */
 } fastpi_options;
 
+/* Schedule of the batched kernels (all values must be from the listed sets). */
+typedef struct {
+    int32_t block_lds;          /* LDS bytes of a block-SVD workgroup, 4096..61440; blocks whose  */
+                                /* Jacobi state does not fit work in global scratch               */
+    int32_t block_wgs_per_cu;   /* persistent block-SVD workgroups per compute unit, 1..16         */
+    int32_t gram_rows;          /* rows of X per eigensolver partial-Gram workgroup: 64, 128, 256  */
+    int32_t inner_sweeps;       /* Jacobi sweeps per 32 x 32 pair solve: 1 or 2                    */
+} fastpi_tuning;
+
 typedef struct fastpi_plan fastpi_plan;
 typedef struct fastpi_handle fastpi_handle;
+typedef struct fastpi_batch fastpi_batch;
 
 /* ceil(alpha * x) evaluated in IEEE double, clamped at 0 (Table 1: r = ceil(alpha n)). */
 int64_t fastpi_target_rank(double alpha, int64_t x);
@@ -172,6 +182,9 @@ int fastpi_upload_plan(fastpi_handle* h, const fastpi_plan* plan);
  *   V : device double[n * r] row-major;  r = fastpi_split.r of the plan.
  * Columns whose singular value is at or below max(m, n) * eps * S[0] carry no information
  * and may be zero.
+ * The two incremental cores are solved by Jacobi sweeps whose number depends on the data:
+ * the host reads each sweep's convergence state (one sweep behind, on a side stream), so
+ * the call returns once the last sweep is queued; the final stages are queued, not finished.
  */
 int fastpi_svd(fastpi_handle* h, const int64_t* rowptr, const int32_t* col, const double* val,
                double* U, double* S, double* V);
@@ -222,6 +235,71 @@ int fastpi_timing_start(fastpi_handle* h, int kind);
 /* Waits for the stream; returns the number of timed launches and their summed duration in
  * milliseconds since fastpi_timing_start, and clears them (timing stays on). */
 int fastpi_timing_read(fastpi_handle* h, int64_t* launches, double* total_ms);
+
+/*
+ * Graph mode (batching form of the path): when enabled, fastpi_svd replays HIP graphs of
+ * the stage chain instead of launching each kernel -- one graph for the stages before,
+ * between and after the two eigensolvers and one per eigensolver sweep, since the number
+ * of sweeps is data dependent. The graphs are captured on the first call and captured
+ * again whenever a pointer, the precision or a Jacobi option changes. The results are
+ * bitwise identical to the eager launches. Kernel timing (fastpi_timing_*) sees eager runs
+ * only.
+ */
+int fastpi_set_graph(fastpi_handle* h, int enable);
+/* Graph launches of the last fastpi_svd (0 for an eager run, -1 for a null handle). */
+int64_t fastpi_last_graph_launches(const fastpi_handle* h);
+
+/* Schedule of the handle's batched kernels (the defaults, or what the autotuner chose). */
+int fastpi_set_tuning(fastpi_handle* h, const fastpi_tuning* t);
+int fastpi_get_tuning(const fastpi_handle* h, fastpi_tuning* t);
+/*
+ * Tuning cache: a text file of "key|block_lds wgs_per_cu gram_rows inner_sweeps" lines, the
+ * key naming the GPU architecture, the precision and the shape bucket (log2 of the number
+ * of matrices, of blocks and of the two core orders). Plans uploaded (and batches created)
+ * afterwards take a matching entry; fastpi_autotune reads and writes it. NULL clears it.
+ */
+int fastpi_set_tuning_cache(fastpi_handle* h, const char* path);
+/*
+ * Autotuner: runs the uploaded plan's path with every candidate schedule (three block-SVD
+ * LDS/occupancy pairs timed on the block launch alone, then six eigensolver schedules timed
+ * over whole runs), keeps the fastest and stores it in the tuning cache when one is set.
+ * Arguments as for fastpi_svd (the outputs hold a valid result afterwards). report, when
+ * not NULL, receives a one-line summary of the timings (truncated to report_cap bytes).
+ * Synchronous. A cache hit skips the trials.
+ */
+int fastpi_autotune(fastpi_handle* h, const double* val, double* U, double* S, double* V,
+                    char* report, int64_t report_cap);
+
+/*
+ * Batches: several independent matrices that run together on the handle's device and
+ * stream. Every diagonal block of every matrix goes through one persistent block-SVD launch
+ * (an atomic work queue, largest blocks first), the row-update and the column-update cores
+ * of all matrices through one batched eigensolver each (one launch per kernel and round for
+ * all matrices), and the other stages per matrix. The batch keeps its own device copy of
+ * every plan; the plans may be destroyed afterwards. The handle must outlive the batch.
+ */
+int fastpi_batch_create(fastpi_batch** b, fastpi_handle* h, int64_t count,
+                        const fastpi_plan* const* plans);
+void fastpi_batch_destroy(fastpi_batch* b);
+/*
+ * fastpi_svd for every matrix of the batch. val, U, S, V are HOST arrays of count DEVICE
+ * pointers, laid out per matrix as in fastpi_svd. Uses the handle's precision and options.
+ */
+int fastpi_batch_svd(fastpi_batch* b, const double* const* val, double* const* U,
+                     double* const* S, double* const* V);
+/*
+ * Waits for the stream. status (host int32[count], may be NULL) receives each matrix's own
+ * fastpi_status, so that one failing matrix (e.g. a non-finite value) leaves the others'
+ * results and codes intact; sweeps (host int32[3*count], may be NULL) the sweep counts as
+ * in fastpi_last_sweeps. Returns the first non-OK code, or FASTPI_OK.
+ */
+int fastpi_batch_sync(fastpi_batch* b, int32_t* status, int32_t* sweeps);
+int fastpi_batch_set_graph(fastpi_batch* b, int enable);
+int64_t fastpi_batch_last_graph_launches(const fastpi_batch* b);
+int fastpi_batch_set_tuning(fastpi_batch* b, const fastpi_tuning* t);
+int fastpi_batch_get_tuning(const fastpi_batch* b, fastpi_tuning* t);
+int fastpi_batch_autotune(fastpi_batch* b, const double* const* val, double* const* U,
+                          double* const* S, double* const* V, char* report, int64_t report_cap);
 
 const char* fastpi_last_error(void);
 

@@ -41,6 +41,14 @@ class Options(ctypes.Structure):
                 ("max_workspace_bytes", c_size_t)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("block_lds", c_int32), ("block_wgs_per_cu", c_int32), ("gram_rows", c_int32),
+                ("inner_sweeps", c_int32)]
+
+    def as_dict(self):
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
 # (name, restype, argtypes) of every symbol declared in include/fastpi.h
 SIGNATURES = [
     ("fastpi_target_rank", c_int64, [c_double, c_int64]),
@@ -73,6 +81,24 @@ SIGNATURES = [
                                 ctypes.c_float]),
     ("fastpi_timing_start", c_int, [c_void_p, c_int]),
     ("fastpi_timing_read", c_int, [c_void_p, POINTER(c_int64), POINTER(c_double)]),
+    ("fastpi_set_graph", c_int, [c_void_p, c_int]),
+    ("fastpi_last_graph_launches", c_int64, [c_void_p]),
+    ("fastpi_set_tuning", c_int, [c_void_p, POINTER(Tuning)]),
+    ("fastpi_get_tuning", c_int, [c_void_p, POINTER(Tuning)]),
+    ("fastpi_set_tuning_cache", c_int, [c_void_p, ctypes.c_char_p]),
+    ("fastpi_autotune", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_char_p,
+                                c_int64]),
+    ("fastpi_batch_create", c_int, [POINTER(c_void_p), c_void_p, c_int64, POINTER(c_void_p)]),
+    ("fastpi_batch_destroy", None, [c_void_p]),
+    ("fastpi_batch_svd", c_int, [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
+                                 POINTER(c_void_p)]),
+    ("fastpi_batch_sync", c_int, [c_void_p, c_void_p, c_void_p]),
+    ("fastpi_batch_set_graph", c_int, [c_void_p, c_int]),
+    ("fastpi_batch_last_graph_launches", c_int64, [c_void_p]),
+    ("fastpi_batch_set_tuning", c_int, [c_void_p, POINTER(Tuning)]),
+    ("fastpi_batch_get_tuning", c_int, [c_void_p, POINTER(Tuning)]),
+    ("fastpi_batch_autotune", c_int, [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
+                                      POINTER(c_void_p), ctypes.c_char_p, c_int64]),
     ("fastpi_last_error", ctypes.c_char_p, []),
 ]
 
@@ -282,6 +308,41 @@ class Handle:
 
     KERNELS = {"eig_gram": 0, "eig_solve": 1, "eig_update": 2, "block_svd": 3}
 
+    # ---- batching form: graphs and schedules ----
+    def set_graph(self, enable=True):
+        _check(load().fastpi_set_graph(self._h, 1 if enable else 0))
+
+    def last_graph_launches(self):
+        return int(load().fastpi_last_graph_launches(self._h))
+
+    def set_tuning(self, **kw):
+        t = Tuning(**{**self.get_tuning(), **kw})
+        _check(load().fastpi_set_tuning(self._h, ctypes.byref(t)))
+
+    def get_tuning(self):
+        t = Tuning()
+        _check(load().fastpi_get_tuning(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning_cache(self, path):
+        _check(load().fastpi_set_tuning_cache(self._h, None if path is None else str(path).encode()))
+
+    def autotune(self, rowptr, col, val, out=None):
+        """Times the candidate schedules on this matrix and keeps the fastest (synchronous).
+        Returns the timing report."""
+        U, S, V = out if out is not None else self._outputs()
+        buf = ctypes.create_string_buffer(4096)
+        _check(load().fastpi_autotune(self._h, _dptr(val), _dptr(U), _dptr(S), _dptr(V), buf, 4096))
+        return buf.value.decode()
+
+    def _outputs(self):
+        torch = self.torch
+        info = self.plan.info
+        m, n, r = info["m"], info["n"], info["r"]
+        return (torch.empty((m, r), dtype=torch.float64, device=self.device),
+                torch.empty((r,), dtype=torch.float64, device=self.device),
+                torch.empty((n, r), dtype=torch.float64, device=self.device))
+
     # ---- learned rank predictor (device float32 tensors) ----
     def mlp_forward(self, X, theta):
         f = self.torch.empty((X.shape[0],), dtype=self.torch.float32, device=self.device)
@@ -312,3 +373,85 @@ class Handle:
         if h is not None and _lib is not None:
             _lib.fastpi_destroy(h)
             self._h = None
+
+
+def _ptr_array(tensors):
+    arr = (c_void_p * len(tensors))()
+    for i, t in enumerate(tensors):
+        arr[i] = t.data_ptr()
+    return arr
+
+
+class Batch:
+    """Several matrices run together on one handle (one persistent block-SVD launch, batched
+    eigensolvers, optional graph replay). The plans' device copies are owned by the batch."""
+
+    def __init__(self, handle: Handle, plans):
+        lib = load()
+        self.handle = handle
+        self.plans = list(plans)
+        arr = (c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        b = c_void_p()
+        _check(lib.fastpi_batch_create(ctypes.byref(b), handle._h, len(self.plans), arr))
+        self._b = b
+
+    def __len__(self):
+        return len(self.plans)
+
+    def outputs(self):
+        torch = self.handle.torch
+        dev = self.handle.device
+        out = []
+        for p in self.plans:
+            m, n, r = p.info["m"], p.info["n"], p.info["r"]
+            out.append((torch.empty((m, r), dtype=torch.float64, device=dev),
+                        torch.empty((r,), dtype=torch.float64, device=dev),
+                        torch.empty((n, r), dtype=torch.float64, device=dev)))
+        return out
+
+    def svd(self, vals, out=None):
+        """vals: one device float64 tensor of CSR values per matrix. Returns [(U, S, V)]."""
+        out = out if out is not None else self.outputs()
+        assert len(vals) == len(self.plans) == len(out)
+        for v in vals:
+            assert v.is_contiguous() and v.dtype == self.handle.torch.float64
+        _check(load().fastpi_batch_svd(self._b, _ptr_array(vals), _ptr_array([o[0] for o in out]),
+                                       _ptr_array([o[1] for o in out]), _ptr_array([o[2] for o in out])))
+        self._keep = (vals, out)
+        return out
+
+    def sync(self):
+        """Waits; returns (per-matrix status names, sweeps[count, 3]). Raises nothing."""
+        st = np.zeros(len(self.plans), dtype=np.int32)
+        sw = np.zeros((len(self.plans), 3), dtype=np.int32)
+        load().fastpi_batch_sync(self._b, _ptr(st), _ptr(sw))
+        return [STATUS.get(int(c), str(int(c))) for c in st], sw
+
+    def set_graph(self, enable=True):
+        _check(load().fastpi_batch_set_graph(self._b, 1 if enable else 0))
+
+    def last_graph_launches(self):
+        return int(load().fastpi_batch_last_graph_launches(self._b))
+
+    def set_tuning(self, **kw):
+        t = Tuning(**{**self.get_tuning(), **kw})
+        _check(load().fastpi_batch_set_tuning(self._b, ctypes.byref(t)))
+
+    def get_tuning(self):
+        t = Tuning()
+        _check(load().fastpi_batch_get_tuning(self._b, ctypes.byref(t)))
+        return t.as_dict()
+
+    def autotune(self, vals, out=None):
+        out = out if out is not None else self.outputs()
+        buf = ctypes.create_string_buffer(8192)
+        _check(load().fastpi_batch_autotune(self._b, _ptr_array(vals), _ptr_array([o[0] for o in out]),
+                                            _ptr_array([o[1] for o in out]), _ptr_array([o[2] for o in out]),
+                                            buf, 8192))
+        return buf.value.decode()
+
+    def __del__(self):
+        b = self.__dict__.get("_b")
+        if b is not None and _lib is not None:
+            _lib.fastpi_batch_destroy(b)
+            self._b = None

@@ -129,15 +129,12 @@ __device__ void jacobi_sweeps(T* X, T* J, int p, int q, int max_sweeps, T tol,
 }
 
 template <typename T>
-__device__ void block_svd_one(const BlockWork& w, const double* __restrict__ blk, T* X, T* J,
-                              double* __restrict__ U1, double* __restrict__ sig1,
-                              double* __restrict__ V1, int max_sweeps, T tol, int* sweeps_used,
-                              int* status) {
+__device__ void block_svd_one(const BlockTask& w, T* X, T* J, int max_sweeps, T tol) {
     const int rows = w.rows, cols = w.cols;
     const bool trans = rows < cols;
     const int p = trans ? cols : rows;
     const int q = trans ? rows : cols;
-    const double* A = blk + w.data_off;
+    const double* A = w.A;
     // X (p x q, column-major) and J = I
     for (int64_t e = threadIdx.x; e < static_cast<int64_t>(p) * q; e += blockDim.x) {
         const int r = static_cast<int>(e % p), c = static_cast<int>(e / p);
@@ -146,12 +143,10 @@ __device__ void block_svd_one(const BlockWork& w, const double* __restrict__ blk
     }
     for (int e = threadIdx.x; e < q * q; e += blockDim.x) J[e] = (e % q == e / q) ? T(1) : T(0);
     __syncthreads();
-    if (q > 1) jacobi_sweeps<T>(X, J, p, q, max_sweeps, tol, sweeps_used, status);
-    else if (threadIdx.x == 0) atomicMax(sweeps_used, 0);
+    if (q > 1) jacobi_sweeps<T>(X, J, p, q, max_sweeps, tol, w.status + 1, w.status);
     __syncthreads();
 
     // column norms, then the descending rank of every column (ties: lower column first)
-    extern __shared__ unsigned char smem_raw[];
     __shared__ double s_sig[256];
     __shared__ int s_rank[256];
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
@@ -185,63 +180,67 @@ __device__ void block_svd_one(const BlockWork& w, const double* __restrict__ blk
         const T* xc = X + static_cast<int64_t>(c) * p;
         const T* jc = J + static_cast<int64_t>(c) * q;
         // W column -> the p-long factor, J column -> the q-long factor
-        double* Wout = trans ? (V1 + w.v_off + static_cast<int64_t>(k) * cols)
-                             : (U1 + w.u_off + static_cast<int64_t>(k) * rows);
-        double* Jout = trans ? (U1 + w.u_off + static_cast<int64_t>(k) * rows)
-                             : (V1 + w.v_off + static_cast<int64_t>(k) * cols);
+        double* Wout = trans ? (w.V + static_cast<int64_t>(k) * cols) : (w.U + static_cast<int64_t>(k) * rows);
+        double* Jout = trans ? (w.U + static_cast<int64_t>(k) * rows) : (w.V + static_cast<int64_t>(k) * cols);
         for (int r = threadIdx.x; r < p; r += blockDim.x) Wout[r] = static_cast<double>(xc[r]) * inv;
         for (int r = threadIdx.x; r < q; r += blockDim.x) Jout[r] = static_cast<double>(jc[r]);
-        if (threadIdx.x == 0) sig1[w.sig_off + k] = sc;
+        if (threadIdx.x == 0) w.sig[k] = sc;
     }
-    (void)smem_raw;
 }
 
+// Persistent form: every workgroup takes the next task from the queue until it is empty.
+// Tasks are listed largest cost first, so the long blocks start early and the short ones
+// fill in behind them. A block whose X and J fit the LDS budget works there, otherwise in
+// its global scratch.
 template <typename T>
-__global__ __launch_bounds__(256) void k_block_svd(const BlockWork* __restrict__ work, int first,
-                                                   int count, const double* __restrict__ blk,
-                                                   T* __restrict__ gscratch,
-                                                   const int64_t* __restrict__ gscratch_off,
-                                                   int64_t lds_elems, double* __restrict__ U1,
-                                                   double* __restrict__ sig1,
-                                                   double* __restrict__ V1, int max_sweeps,
-                                                   T tol_scale, int* sweeps_used, int* status) {
+__global__ __launch_bounds__(256) void k_block_svd(const BlockTask* __restrict__ tasks, int ntasks,
+                                                   int* __restrict__ counter, int64_t lds_elems,
+                                                   int max_sweeps, T tol_scale) {
     extern __shared__ unsigned char smem_raw[];
-    const int item = first + blockIdx.x;
-    if (blockIdx.x >= count) return;
-    const BlockWork w = work[item];
-    const int p = w.rows > w.cols ? w.rows : w.cols;
-    const int q = w.rows > w.cols ? w.cols : w.rows;
-    const int64_t need = static_cast<int64_t>(p) * q + static_cast<int64_t>(q) * q;
-    const T tol = tol_scale * static_cast<T>(p);
-    if (need <= lds_elems) {
-        T* X = reinterpret_cast<T*>(smem_raw);
+    __shared__ int s_item;
+    for (;;) {
+        __syncthreads();   // the previous task is finished with LDS and s_item
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int item = s_item;
+        if (item >= ntasks) break;
+        const BlockTask w = tasks[item];
+        const int p = w.rows > w.cols ? w.rows : w.cols;
+        const int q = w.rows > w.cols ? w.cols : w.rows;
+        const int64_t need = static_cast<int64_t>(p) * q + static_cast<int64_t>(q) * q;
+        const T tol = tol_scale * static_cast<T>(p);
+        T* X = need <= lds_elems ? reinterpret_cast<T*>(smem_raw) : static_cast<T*>(w.scratch);
         T* J = X + static_cast<int64_t>(p) * q;
-        block_svd_one<T>(w, blk, X, J, U1, sig1, V1, max_sweeps, tol, sweeps_used, status);
-    } else {
-        T* X = gscratch + gscratch_off[item];
-        T* J = X + static_cast<int64_t>(p) * q;
-        block_svd_one<T>(w, blk, X, J, U1, sig1, V1, max_sweeps, tol, sweeps_used, status);
+        block_svd_one<T>(w, X, J, max_sweeps, tol);
     }
 }
 
-void launch_block_svd(bool fp32, const BlockWork* work, int first, int count, const double* blk,
-                      void* gscratch, const int64_t* gscratch_off, int lds_bytes, double* U1,
-                      double* sig1, double* V1, int max_sweeps, double tol_scale,
-                      int* sweeps_used, int* status, hipStream_t st) {
-    if (count <= 0) return;
+__global__ void k_copy(const double* __restrict__ src, int64_t n, double* __restrict__ dst) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+        dst[i] = src[i];
+}
+
+void launch_copy(const double* src, int64_t n, double* dst, hipStream_t st) {
+    if (n <= 0) return;
+    const int blocks = static_cast<int>(std::min<int64_t>((n + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, st, src, n, dst);
+}
+
+void launch_block_svd_tasks(bool fp32, const BlockTask* tasks, int ntasks, int* counter, int lds_bytes,
+                            int grid, int max_sweeps, double tol_scale, hipStream_t st) {
+    if (ntasks <= 0) return;
+    launch_fill_i32(counter, 1, 0, st);
+    grid = std::max(1, std::min(grid, ntasks));
     if (fp32) {
         const int64_t lds_elems = lds_bytes / static_cast<int>(sizeof(float));
-        hipLaunchKernelGGL(k_block_svd<float>, dim3(count), dim3(256), lds_bytes, st, work, first,
-                           count, blk, static_cast<float*>(gscratch), gscratch_off, lds_elems, U1,
-                           sig1, V1, max_sweeps,
-                           static_cast<float>(tol_scale > 0 ? tol_scale : FLT_EPSILON),
-                           sweeps_used, status);
+        hipLaunchKernelGGL(k_block_svd<float>, dim3(grid), dim3(256), lds_bytes, st, tasks, ntasks, counter,
+                           lds_elems, max_sweeps,
+                           static_cast<float>(tol_scale > 0 ? tol_scale : FLT_EPSILON));
     } else {
         const int64_t lds_elems = lds_bytes / static_cast<int>(sizeof(double));
-        hipLaunchKernelGGL(k_block_svd<double>, dim3(count), dim3(256), lds_bytes, st, work, first,
-                           count, blk, static_cast<double*>(gscratch), gscratch_off, lds_elems, U1,
-                           sig1, V1, max_sweeps, tol_scale > 0 ? tol_scale : DBL_EPSILON,
-                           sweeps_used, status);
+        hipLaunchKernelGGL(k_block_svd<double>, dim3(grid), dim3(256), lds_bytes, st, tasks, ntasks, counter,
+                           lds_elems, max_sweeps, tol_scale > 0 ? tol_scale : DBL_EPSILON);
     }
 }
 

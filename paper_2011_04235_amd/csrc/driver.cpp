@@ -1,0 +1,709 @@
+// Device-side driver: instance upload, the staged run of a group of instances (eager or
+// from captured graphs) and the autotuner of the batched kernels' schedules.
+#include "driver.h"
+
+#include <algorithm>
+#include <cfloat>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+
+namespace fastpi {
+
+namespace {
+
+#define HIP_TRY(expr)                                                               \
+    do {                                                                            \
+        hipError_t _e = (expr);                                                     \
+        if (_e != hipSuccess) {                                                     \
+            set_error(std::string("HIP error: ") + hipGetErrorString(_e) + " at " + \
+                      #expr);                                                       \
+            return FASTPI_EHIP;                                                     \
+        }                                                                           \
+    } while (0)
+
+// Singular values below this fraction of the largest are not resolved by the Gram route
+// (about sqrt(q eps)); they are returned as zero.
+constexpr double kRelCut = 1e-7;
+
+int launch_status() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error(std::string("HIP launch error: ") + hipGetErrorString(e));
+        return FASTPI_EHIP;
+    }
+    return FASTPI_OK;
+}
+
+template <typename T>
+int upload(Instance& I, T*& dst, const T* src, size_t count, hipStream_t st) {
+    dst = nullptr;
+    if (count == 0) return FASTPI_OK;
+    void* p = nullptr;
+    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
+        set_error("device allocation failed for a plan table");
+        return FASTPI_ENOMEM;
+    }
+    I.allocs.push_back(p);
+    dst = static_cast<T*>(p);
+    HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyHostToDevice, st));
+    return FASTPI_OK;
+}
+
+int upload_segments(Instance& I, const Segments& s, SegDev& d, hipStream_t st) {
+    int rc;
+    d = SegDev{};
+    int32_t *owner = nullptr, *pidx = nullptr, *mo = nullptr, *mp = nullptr;
+    int64_t *b = nullptr, *e = nullptr;
+    if ((rc = upload(I, owner, s.owner.data(), s.owner.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I, pidx, s.pidx.data(), s.pidx.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I, b, s.begin.data(), s.begin.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I, e, s.end.data(), s.end.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I, mo, s.multi_owner.data(), s.multi_owner.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I, mp, s.multi_ptr.data(), s.multi_ptr.size(), st)) != FASTPI_OK) return rc;
+    d.owner = owner;
+    d.pidx = pidx;
+    d.begin = b;
+    d.end = e;
+    d.multi_owner = mo;
+    d.multi_ptr = mp;
+    d.nseg = static_cast<int64_t>(s.owner.size());
+    d.nmulti = static_cast<int64_t>(s.multi_owner.size());
+    d.npart = s.npart;
+    return FASTPI_OK;
+}
+
+template <typename T>
+int ensure(T*& buf, size_t& have, size_t bytes, size_t cap, hipStream_t st) {
+    if (bytes <= have) return FASTPI_OK;
+    if (cap && bytes > cap) {
+        set_error("workspace of " + std::to_string(bytes) + " bytes exceeds the cap");
+        return FASTPI_ENOMEM;
+    }
+    if (buf) {
+        hipStreamSynchronize(st);
+        hipFree(buf);
+        buf = nullptr;
+        have = 0;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        set_error("device workspace allocation of " + std::to_string(bytes) + " bytes failed");
+        return FASTPI_ENOMEM;
+    }
+    buf = static_cast<T*>(p);
+    have = bytes;
+    return FASTPI_OK;
+}
+
+// the smallest partial-Gram height any schedule may pick (largest eigensolver workspace)
+constexpr int kMinGramRows = 64;
+
+}  // namespace
+
+bool tuning_valid(const Tuning& t) {
+    return t.block_lds >= 4096 && t.block_lds <= 60 * 1024 && t.block_wgs_per_cu >= 1 &&
+           t.block_wgs_per_cu <= 16 && eig_gram_rows_valid(t.gram_rows) &&
+           (t.inner_sweeps == 1 || t.inner_sweeps == 2);
+}
+
+void instance_free(Instance& I, hipStream_t st) {
+    if (!I.allocs.empty() || I.ws || I.iws) hipStreamSynchronize(st);
+    for (void* p : I.allocs) hipFree(p);
+    if (I.ws) hipFree(I.ws);
+    if (I.iws) hipFree(I.iws);
+    int* status = I.status;
+    I = Instance{};
+    I.status = status;
+}
+
+int instance_upload(Instance& I, const Plan& p, size_t ws_cap, hipStream_t st) {
+    if (!I.allocs.empty()) hipStreamSynchronize(st);
+    for (void* a : I.allocs) hipFree(a);
+    I.allocs.clear();
+    I.dp = DevicePlan{};
+    DevicePlan& d = I.dp;
+    d.m = p.m;
+    d.n = p.n;
+    d.nnz = p.nnz;
+    d.m1 = p.ro.m1;
+    d.n1 = p.ro.n1;
+    d.m2 = p.ro.m2;
+    d.n2 = p.ro.n2;
+    d.s_b = p.s_b;
+    d.s = p.s;
+    d.r = p.r;
+    d.B_dense = p.B_dense;
+    d.val_elems = p.val_elems;
+    d.blk_elems = p.blk_elems;
+    d.u1 = p.u1_elems;
+    d.v1 = p.v1_elems;
+    d.off_a21r = p.off_a21r;
+    d.off_a21c = p.off_a21c;
+    d.off_tr = p.off_tr;
+    d.off_tc = p.off_tc;
+    // Every block gets global scratch for its X and J, so any LDS budget of the persistent
+    // launch can fall back to it.
+    I.work = p.work;
+    I.scratch_off.assign(p.work.size(), 0);
+    int64_t gs = 0;
+    for (size_t i = 0; i < p.work.size(); ++i) {
+        const BlockWork& w = p.work[i];
+        const int64_t pp = std::max(w.rows, w.cols), qq = std::min(w.rows, w.cols);
+        if (qq > 256) {
+            set_error("a diagonal block has both sides above 256; not supported");
+            return FASTPI_EINTERNAL;
+        }
+        I.scratch_off[i] = gs;
+        gs += ((pp * qq + qq * qq + 31) / 32) * 32;
+    }
+    int rc;
+    if ((rc = upload(I, d.work, p.work.data(), p.work.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I, d.dst0, p.dst0.data(), p.dst0.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I, d.dst1, p.dst1.data(), p.dst1.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I, d.a21_rowptr, p.a21_rowptr.data(), p.a21_rowptr.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I, d.a21_colptr, p.a21_colptr.data(), p.a21_colptr.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I, d.t_rowptr, p.t_rowptr.data(), p.t_rowptr.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I, d.t_colptr, p.t_colptr.data(), p.t_colptr.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I, d.a21_colidx, p.a21_colidx.data(), p.a21_colidx.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I, d.a21_rowidx, p.a21_rowidx.data(), p.a21_rowidx.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I, d.t_colidx, p.t_colidx.data(), p.t_colidx.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I, d.t_rowidx, p.t_rowidx.data(), p.t_rowidx.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I, d.piT, p.ro.piT.data(), p.ro.piT.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I, d.invF, p.invF.data(), p.invF.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I, d.invT, p.invT.data(), p.invT.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload_segments(I, p.seg_a21c, d.seg_a21c, st)) != FASTPI_OK) return rc;
+    if ((rc = upload_segments(I, p.seg_a21r, d.seg_a21r, st)) != FASTPI_OK) return rc;
+    if ((rc = upload_segments(I, p.seg_tc, d.seg_tc, st)) != FASTPI_OK) return rc;
+    if ((rc = upload_segments(I, p.seg_tr, d.seg_tr, st)) != FASTPI_OK) return rc;
+
+    // workspace layout (doubles)
+    const int64_t m = d.m, n1 = d.n1, n2 = d.n2, s = d.s, r = d.r;
+    const int64_t q3 = s + n2;
+    int64_t o = 0;
+    auto take = [&o](int64_t cnt) {
+        const int64_t at = o;
+        o += ((cnt + 31) / 32) * 32;
+        return at;
+    };
+    I.o_vals = take(d.val_elems);
+    I.o_u1 = take(d.u1);
+    I.o_v1 = take(d.v1);
+    I.o_sig1 = take(d.s_b);
+    I.o_g2 = take(n1 * n1);
+    I.o_v2 = take(n1 * s);
+    I.o_lam2 = take(s);
+    I.o_sig2 = take(s);
+    I.o_inv2 = take(s);
+    I.o_u2 = take(m * s);
+    I.o_g3 = take(q3 * q3);
+    I.o_vt = take(q3 * r);
+    I.o_lam3 = take(r);
+    I.o_sig3 = take(r);
+    I.o_inv3 = take(r);
+    I.o_c1 = take(s * r);
+    I.o_c2 = take(n2 * r);
+    I.o_eig = take(static_cast<int64_t>(std::max(eig_job_doubles(std::max<int64_t>(n1, 1), kMinGramRows),
+                                                 eig_job_doubles(std::max<int64_t>(q3, 1), kMinGramRows))));
+    const int sp = gemm_tn_splits(s, s, m);
+    I.o_part = take(static_cast<int64_t>(sp) * s * s);
+    I.o_gs = take(gs);
+    const int64_t spart = std::max({p.seg_a21c.npart * n1, p.seg_tc.npart * std::max(n2, s),
+                                    p.seg_a21r.npart * s, p.seg_tr.npart * r, int64_t(1)});
+    I.o_spart = take(spart);
+    I.o_end = o;
+    if ((rc = ensure(I.ws, I.ws_bytes, static_cast<size_t>(o) * sizeof(double), ws_cap, st)) != FASTPI_OK)
+        return rc;
+    const size_t ints = std::max(eig_job_ints(std::max<int64_t>(n1, 1)), eig_job_ints(std::max<int64_t>(q3, 1)));
+    if ((rc = ensure(I.iws, I.iws_bytes, ints * sizeof(int), 0, st)) != FASTPI_OK) return rc;
+    HIP_TRY(hipStreamSynchronize(st));
+    d.valid = true;
+    return launch_status();
+}
+
+// ---------------------------------------------------------------------------------------
+// group
+// ---------------------------------------------------------------------------------------
+void group_drop_graphs(Group& g) {
+    for (hipGraphExec_t* e : {&g.g_front, &g.g_sw2, &g.g_mid, &g.g_sw3, &g.g_back}) {
+        if (*e) hipGraphExecDestroy(*e);
+        *e = nullptr;
+    }
+    g.key.clear();
+}
+
+void group_free(Group& g) {
+    group_drop_graphs(g);
+    if (g.tasks) hipFree(g.tasks);
+    if (g.counter) hipFree(g.counter);
+    g.tasks = nullptr;
+    g.counter = nullptr;
+    g.ntasks = 0;
+    eig_set_free(g.set2);
+    eig_set_free(g.set3);
+    if (g.cap) hipStreamDestroy(g.cap);
+    g.cap = nullptr;
+}
+
+static int build_sets(Group& g, hipStream_t st) {
+    std::vector<EigJob> j2, j3;
+    for (size_t i = 0; i < g.inst.size(); ++i) {
+        Instance& I = *g.inst[i];
+        const DevicePlan& d = I.dp;
+        double* ws = I.ws;
+        const int64_t q3 = d.s + d.n2;
+        if (d.n1 > 0 && d.s > 0)
+            j2.push_back(eig_make_job(ws + I.o_g2, d.n1, d.s, ws + I.o_lam2, ws + I.o_v2, ws + I.o_eig, I.iws,
+                                      I.status, 0.0, g.tune.gram_rows, static_cast<int>(i)));
+        if (q3 > 0 && d.r > 0)
+            j3.push_back(eig_make_job(ws + I.o_g3, q3, d.r, ws + I.o_lam3, ws + I.o_vt, ws + I.o_eig, I.iws,
+                                      I.status, 0.0, g.tune.gram_rows, static_cast<int>(i)));
+    }
+    int rc = eig_set_create(g.set2, j2, g.tune.gram_rows, st);
+    if (rc == FASTPI_OK) rc = eig_set_create(g.set3, j3, g.tune.gram_rows, st);
+    if (rc != FASTPI_OK) set_error("eigensolver set allocation failed");
+    return rc;
+}
+
+int group_build(Group& g, int device, hipStream_t st) {
+    Group fresh;
+    fresh.inst = g.inst;
+    fresh.tune = g.tune;
+    group_free(g);
+    g = fresh;
+    HIP_TRY(hipDeviceGetAttribute(&g.ncu, hipDeviceAttributeMultiprocessorCount, device));
+    if (g.ncu <= 0) g.ncu = 256;
+    // all blocks of all instances, largest cost (p q^2) first
+    std::vector<std::pair<double, BlockTask>> all;
+    for (Instance* Ip : g.inst) {
+        Instance& I = *Ip;
+        if (!I.dp.valid) {
+            set_error("instance without an uploaded plan");
+            return FASTPI_EINVAL;
+        }
+        double* ws = I.ws;
+        for (size_t k = 0; k < I.work.size(); ++k) {
+            const BlockWork& w = I.work[k];
+            BlockTask t{};
+            t.A = ws + I.o_vals + w.data_off;
+            t.U = ws + I.o_u1 + w.u_off;
+            t.V = ws + I.o_v1 + w.v_off;
+            t.sig = ws + I.o_sig1 + w.sig_off;
+            t.scratch = ws + I.o_gs + I.scratch_off[k];
+            t.status = I.status;
+            t.rows = w.rows;
+            t.cols = w.cols;
+            t.rank = w.rank;
+            const double pp = std::max(w.rows, w.cols), qq = std::min(w.rows, w.cols);
+            all.emplace_back(pp * qq * qq, t);
+        }
+    }
+    std::stable_sort(all.begin(), all.end(),
+                     [](const std::pair<double, BlockTask>& a, const std::pair<double, BlockTask>& b) {
+                         return a.first > b.first;
+                     });
+    std::vector<BlockTask> tasks;
+    tasks.reserve(all.size());
+    for (auto& e : all) tasks.push_back(e.second);
+    g.ntasks = static_cast<int>(tasks.size());
+    void* p = nullptr;
+    if (hipMalloc(&p, sizeof(int) * 64) != hipSuccess) {
+        set_error("device allocation failed (work queue)");
+        return FASTPI_ENOMEM;
+    }
+    g.counter = static_cast<int*>(p);
+    if (!tasks.empty()) {
+        if (hipMalloc(&p, sizeof(BlockTask) * tasks.size()) != hipSuccess) {
+            set_error("device allocation failed (block tasks)");
+            return FASTPI_ENOMEM;
+        }
+        g.tasks = static_cast<BlockTask*>(p);
+        HIP_TRY(hipMemcpyAsync(g.tasks, tasks.data(), sizeof(BlockTask) * tasks.size(), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    int rc = build_sets(g, st);
+    if (rc != FASTPI_OK) return rc;
+    HIP_TRY(hipStreamCreateWithFlags(&g.cap, hipStreamNonBlocking));
+    return launch_status();
+}
+
+int group_set_tuning(Group& g, const Tuning& t, hipStream_t st) {
+    if (!tuning_valid(t)) {
+        set_error("invalid schedule parameters");
+        return FASTPI_EINVAL;
+    }
+    const bool resize = t.gram_rows != g.tune.gram_rows;
+    g.tune = t;
+    group_drop_graphs(g);
+    if (resize && !g.inst.empty()) {
+        HIP_TRY(hipStreamSynchronize(st));
+        return build_sets(g, st);
+    }
+    return FASTPI_OK;
+}
+
+// ---- stages ----------------------------------------------------------------------------
+static void stage_front(Group& g, const double* const* val, const RunCfg& c, hipStream_t st, KernelTimer* timer) {
+    for (size_t i = 0; i < g.inst.size(); ++i) {
+        Instance& I = *g.inst[i];
+        const DevicePlan& d = I.dp;
+        double* vals = I.ws + I.o_vals;
+        launch_fill_i32(I.status, 2, 0, st);
+        // a1: split the reordered matrix into dense A11 blocks, A21 and T
+        launch_fill(vals, d.blk_elems, 0.0, st);
+        launch_gather(val[i], d.dst0, d.dst1, d.nnz, vals, I.status, st);
+    }
+    // a2: block SVDs (Eq. 1), every block of every instance in one persistent launch
+    {
+        const long ts = timer ? timer->begin(KT_BLOCK_SVD, st) : -1;
+        launch_block_svd_tasks(c.mixed, g.tasks, g.ntasks, g.counter, g.tune.block_lds,
+                               g.ncu * g.tune.block_wgs_per_cu, c.max_sweeps, c.tol, st);
+        if (timer) timer->end(ts, st);
+    }
+    // a3, first half: M2^T M2 = V1 Sigma1^2 V1^T + A21^T A21
+    for (Instance* Ip : g.inst) {
+        Instance& I = *Ip;
+        const DevicePlan& d = I.dp;
+        if (!(d.n1 > 0 && d.s > 0)) continue;
+        double* ws = I.ws;
+        const int64_t n1 = d.n1;
+        double* G2 = ws + I.o_g2;
+        launch_fill(G2, n1 * n1, 0.0, st);
+        launch_blockdiag_gram(d.work, static_cast<int>(d.B_dense), ws + I.o_v1, ws + I.o_sig1, G2, n1, st);
+        launch_sparse_gram(d.seg_a21c, d.a21_rowidx, ws + I.o_vals + d.off_a21c, d.a21_rowptr, d.a21_colidx,
+                           ws + I.o_vals + d.off_a21r, n1, G2, n1, true, ws + I.o_spart, st);
+    }
+    eig_begin(g.set2, st);
+}
+
+static void stage_mid(Group& g, const RunCfg& c, hipStream_t st) {
+    eig_end(g.set2, st);
+    for (Instance* Ip : g.inst) {
+        Instance& I = *Ip;
+        const DevicePlan& d = I.dp;
+        double* ws = I.ws;
+        double* vals = ws + I.o_vals;
+        const int64_t m = d.m, m1 = d.m1, n2 = d.n2, s = d.s, r = d.r, q3 = s + n2;
+        double* U2 = ws + I.o_u2;
+        double* sig2 = ws + I.o_sig2;
+        double* inv2 = ws + I.o_inv2;
+        // a3, second half: sigma2 and U2 = M2 V2 Sigma2^-1 (block part and A21 part)
+        if (d.n1 > 0 && s > 0) {
+            launch_sqrt_inv(ws + I.o_lam2, s, kRelCut, sig2, inv2, st);
+            launch_fill(U2, m * s, 0.0, st);
+            launch_u2_top(d.work, static_cast<int>(d.B_dense), ws + I.o_u1, ws + I.o_sig1, ws + I.o_v1,
+                          ws + I.o_v2, s, inv2, U2, I.status, st);
+            launch_spmm_rows(d.seg_a21r, d.a21_colidx, vals + d.off_a21r, ws + I.o_v2, s, inv2, U2 + m1 * s, s,
+                             nullptr, false, ws + I.o_spart, st);
+        }
+        // a4, first half: X3^T X3 for X3 = [U2 Sigma2, T]
+        if (q3 > 0 && r > 0) {
+            double* G3 = ws + I.o_g3;
+            launch_fill(G3, q3 * q3, 0.0, st);
+            if (s > 0) {
+                const int sp = gemm_tn_splits(s, s, m);
+                launch_gemm_tn(U2, s, U2, s, s, s, m, G3, q3, sig2, sig2, ws + I.o_part, sp, st, c.mixed);
+                launch_sparse_proj(d.seg_tc, d.t_rowidx, vals + d.off_tc, U2, s, sig2, G3, q3, s, ws + I.o_spart,
+                                   st);
+            }
+            launch_sparse_gram(d.seg_tc, d.t_rowidx, vals + d.off_tc, d.t_rowptr, d.t_colidx, vals + d.off_tr, n2,
+                               G3 + s * q3 + s, q3, false, ws + I.o_spart, st);
+        }
+    }
+    eig_begin(g.set3, st);
+}
+
+static void stage_back(Group& g, double* const* U, double* const* S, double* const* V, const RunCfg& c,
+                       hipStream_t st) {
+    eig_end(g.set3, st);
+    for (size_t i = 0; i < g.inst.size(); ++i) {
+        Instance& I = *g.inst[i];
+        const DevicePlan& d = I.dp;
+        double* ws = I.ws;
+        double* vals = ws + I.o_vals;
+        const int64_t m = d.m, n1 = d.n1, n2 = d.n2, s = d.s, r = d.r, q3 = s + n2;
+        if (!(q3 > 0 && r > 0)) continue;
+        double* Vt = ws + I.o_vt;
+        double* C1 = ws + I.o_c1;
+        double* C2 = ws + I.o_c2;
+        double* sig3 = ws + I.o_sig3;
+        double* inv3 = ws + I.o_inv3;
+        launch_sqrt_inv(ws + I.o_lam3, r, kRelCut, sig3, inv3, st);
+        launch_col_coeffs(Vt, s, n2, r, ws + I.o_sig2, inv3, C1, C2, st);
+        // a4, second half, and a5: U and V in the caller's order
+        launch_gemm_nn(ws + I.o_u2, s, d.piT, C1, r, m, r, s, U[i], r, nullptr, st, c.mixed);
+        launch_spmm_rows(d.seg_tr, d.t_colidx, vals + d.off_tr, C2, r, nullptr, U[i], r, d.invT, true,
+                         ws + I.o_spart, st);
+        launch_gemm_nn(ws + I.o_v2, s, nullptr, Vt, r, n1, r, s, V[i], r, d.invF, st, c.mixed);
+        launch_copy_rows(Vt + s * r, n2, r, d.invF + n1, V[i], st);
+        launch_copy(sig3, r, S[i], st);
+    }
+}
+
+template <typename F>
+static int capture(Group& g, F&& fn, hipGraphExec_t& out) {
+    out = nullptr;
+    (void)hipGetLastError();
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(g.cap, hipStreamCaptureModeThreadLocal));
+    fn(g.cap);
+    const hipError_t le = hipGetLastError();
+    const hipError_t ee = hipStreamEndCapture(g.cap, &graph);
+    if (le != hipSuccess || ee != hipSuccess) {
+        if (graph) hipGraphDestroy(graph);
+        set_error(std::string("graph capture failed: ") + hipGetErrorString(le != hipSuccess ? le : ee));
+        return FASTPI_EHIP;
+    }
+    size_t nodes = 0;
+    HIP_TRY(hipGraphGetNodes(graph, nullptr, &nodes));
+    if (nodes > 0) {
+        const hipError_t ie = hipGraphInstantiate(&out, graph, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+            hipGraphDestroy(graph);
+            set_error(std::string("graph instantiation failed: ") + hipGetErrorString(ie));
+            return FASTPI_EHIP;
+        }
+    }
+    hipGraphDestroy(graph);
+    return FASTPI_OK;
+}
+
+static int launch_graph(Group& g, hipGraphExec_t e, hipStream_t st) {
+    if (!e) return FASTPI_OK;
+    ++g.graph_launches;
+    HIP_TRY(hipGraphLaunch(e, st));
+    return FASTPI_OK;
+}
+
+static void record_sweeps(Group& g) {
+    for (Instance* I : g.inst) I->sweeps[1] = I->sweeps[2] = 0;
+    const EigSet* sets[2] = {&g.set2, &g.set3};
+    for (int k = 0; k < 2; ++k) {
+        const EigSet& es = *sets[k];
+        for (int j = 0; j < es.njobs; ++j)
+            g.inst[es.host[j].tag]->sweeps[1 + k] = es.host_state[4 * j + 2];
+    }
+}
+
+int group_svd(Group& g, const double* const* val, double* const* U, double* const* S, double* const* V,
+              const RunCfg& c) {
+    hipStream_t st = c.st;
+    int rc;
+    g.graph_launches = 0;
+    if (!c.use_graph) {
+        stage_front(g, val, c, st, c.timer);
+        if ((rc = eig_iterate(g.set2, c.max_sweeps, g.tune.inner_sweeps, st, c.copy_st, c.timer, nullptr)) !=
+            FASTPI_OK)
+            return rc;
+        stage_mid(g, c, st);
+        if ((rc = eig_iterate(g.set3, c.max_sweeps, g.tune.inner_sweeps, st, c.copy_st, c.timer, nullptr)) !=
+            FASTPI_OK)
+            return rc;
+        stage_back(g, U, S, V, c, st);
+        record_sweeps(g);
+        return launch_status();
+    }
+    // graphs bake in every pointer and scalar: recapture when any of them changes
+    std::vector<uint64_t> key;
+    for (size_t i = 0; i < g.inst.size(); ++i) {
+        key.push_back(reinterpret_cast<uintptr_t>(val[i]));
+        key.push_back(reinterpret_cast<uintptr_t>(U[i]));
+        key.push_back(reinterpret_cast<uintptr_t>(S[i]));
+        key.push_back(reinterpret_cast<uintptr_t>(V[i]));
+    }
+    uint64_t tol_bits = 0;
+    std::memcpy(&tol_bits, &c.tol, sizeof(tol_bits));
+    key.push_back(c.mixed ? 1u : 0u);
+    key.push_back(static_cast<uint64_t>(c.max_sweeps));
+    key.push_back(tol_bits);
+    if (key != g.key || !g.g_front) {
+        group_drop_graphs(g);
+        HIP_TRY(hipStreamSynchronize(st));
+        if ((rc = capture(g, [&](hipStream_t s) { stage_front(g, val, c, s, nullptr); }, g.g_front)) != FASTPI_OK)
+            return rc;
+        if (g.set2.njobs > 0 &&
+            (rc = capture(g, [&](hipStream_t s) { eig_sweep(g.set2, c.max_sweeps, g.tune.inner_sweeps, s, nullptr); },
+                          g.g_sw2)) != FASTPI_OK)
+            return rc;
+        if ((rc = capture(g, [&](hipStream_t s) { stage_mid(g, c, s); }, g.g_mid)) != FASTPI_OK) return rc;
+        if (g.set3.njobs > 0 &&
+            (rc = capture(g, [&](hipStream_t s) { eig_sweep(g.set3, c.max_sweeps, g.tune.inner_sweeps, s, nullptr); },
+                          g.g_sw3)) != FASTPI_OK)
+            return rc;
+        if ((rc = capture(g, [&](hipStream_t s) { stage_back(g, U, S, V, c, s); }, g.g_back)) != FASTPI_OK)
+            return rc;
+        g.key = key;
+    }
+    if ((rc = launch_graph(g, g.g_front, st)) != FASTPI_OK) return rc;
+    if ((rc = eig_iterate(g.set2, c.max_sweeps, g.tune.inner_sweeps, st, c.copy_st, nullptr, g.g_sw2)) != FASTPI_OK)
+        return rc;
+    if ((rc = launch_graph(g, g.g_mid, st)) != FASTPI_OK) return rc;
+    if ((rc = eig_iterate(g.set3, c.max_sweeps, g.tune.inner_sweeps, st, c.copy_st, nullptr, g.g_sw3)) != FASTPI_OK)
+        return rc;
+    if ((rc = launch_graph(g, g.g_back, st)) != FASTPI_OK) return rc;
+    record_sweeps(g);
+    return launch_status();
+}
+
+// ---------------------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------------------
+static int log2_bucket(int64_t x) {
+    int b = 0;
+    while (x > 1) {
+        x >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+static std::string tuning_key(const Group& g, int device, bool mixed) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t colon = arch.find(':');
+        if (colon != std::string::npos) arch = arch.substr(0, colon);
+    }
+    std::ostringstream k;
+    k << arch << ' ' << (mixed ? "mixed" : "fp64") << " inst" << log2_bucket(static_cast<int64_t>(g.inst.size()))
+      << " blk" << log2_bucket(g.ntasks) << " g2_" << log2_bucket(g.set2.max_ld) << " g3_"
+      << log2_bucket(g.set3.max_ld);
+    return k.str();
+}
+
+int tuning_lookup(const Group& g, const char* cache, int device, bool mixed, Tuning& out) {
+    if (!cache) return 0;
+    std::ifstream f(cache);
+    if (!f) return 0;
+    const std::string key = tuning_key(g, device, mixed);
+    std::string line;
+    int found = 0;
+    while (std::getline(f, line)) {
+        const size_t bar = line.find('|');
+        if (bar == std::string::npos || line.substr(0, bar) != key) continue;
+        std::istringstream v(line.substr(bar + 1));
+        Tuning t;
+        if (v >> t.block_lds >> t.block_wgs_per_cu >> t.gram_rows >> t.inner_sweeps && tuning_valid(t)) {
+            out = t;
+            found = 1;   // the last matching line wins
+        }
+    }
+    return found;
+}
+
+static int store_tuning(const Group& g, const char* cache, int device, bool mixed, const Tuning& t) {
+    const std::string key = tuning_key(g, device, mixed);
+    std::vector<std::string> keep;
+    {
+        std::ifstream f(cache);
+        std::string line;
+        while (f && std::getline(f, line)) {
+            const size_t bar = line.find('|');
+            if (bar != std::string::npos && line.substr(0, bar) == key) continue;
+            if (!line.empty()) keep.push_back(line);
+        }
+    }
+    std::ofstream o(cache, std::ios::trunc);
+    if (!o) {
+        set_error(std::string("cannot write the tuning cache ") + cache);
+        return FASTPI_EINVAL;
+    }
+    for (const std::string& l : keep) o << l << '\n';
+    o << key << '|' << t.block_lds << ' ' << t.block_wgs_per_cu << ' ' << t.gram_rows << ' ' << t.inner_sweeps
+      << '\n';
+    return FASTPI_OK;
+}
+
+int group_autotune(Group& g, const double* const* val, double* const* U, double* const* S, double* const* V,
+                   const RunCfg& c0, const char* cache, int device, std::string* report) {
+    RunCfg c = c0;
+    c.use_graph = false;
+    c.timer = nullptr;
+    hipStream_t st = c.st;
+    std::ostringstream rep;
+    Tuning t;
+    if (tuning_lookup(g, cache, device, c.mixed, t)) {
+        rep << "cached " << tuning_key(g, device, c.mixed);
+        if (report) *report = rep.str();
+        return group_set_tuning(g, t, st);
+    }
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    int rc = FASTPI_OK;
+    auto elapsed = [&](float& ms) -> bool {
+        if (hipEventSynchronize(e1) != hipSuccess) return false;
+        return hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    };
+    Tuning best = g.tune;
+    do {
+        // one full run puts the gathered values in place for the block-SVD trials
+        if ((rc = group_set_tuning(g, best, st)) != FASTPI_OK) break;
+        if ((rc = group_svd(g, val, U, S, V, c)) != FASTPI_OK) break;
+        // 1) block SVD: LDS budget and persistent occupancy
+        const int cand_blk[][2] = {{16 * 1024, 8}, {32 * 1024, 4}, {56 * 1024, 2}};
+        float best_ms = 1e30f;
+        for (const auto& cb : cand_blk) {
+            float tmin = 1e30f;
+            for (int rep_i = 0; rep_i < 3; ++rep_i) {
+                hipEventRecord(e0, st);
+                launch_block_svd_tasks(c.mixed, g.tasks, g.ntasks, g.counter, cb[0], g.ncu * cb[1], c.max_sweeps,
+                                       c.tol, st);
+                hipEventRecord(e1, st);
+                float ms = 0;
+                if (!elapsed(ms)) {
+                    rc = FASTPI_EHIP;
+                    break;
+                }
+                tmin = std::min(tmin, ms);
+            }
+            if (rc != FASTPI_OK) break;
+            rep << "block lds=" << cb[0] << " wgs/cu=" << cb[1] << " " << tmin << " ms; ";
+            if (tmin < best_ms) {
+                best_ms = tmin;
+                best.block_lds = cb[0];
+                best.block_wgs_per_cu = cb[1];
+            }
+        }
+        if (rc != FASTPI_OK) break;
+        // 2) eigensolver: partial-Gram height and inner sweeps, timed over whole runs (the
+        // inner sweeps change the number of outer sweeps)
+        best_ms = 1e30f;
+        Tuning eig_best = best;
+        for (int rows : {64, 128, 256}) {
+            for (int inner : {1, 2}) {
+                Tuning cand = best;
+                cand.gram_rows = rows;
+                cand.inner_sweeps = inner;
+                if ((rc = group_set_tuning(g, cand, st)) != FASTPI_OK) break;
+                hipEventRecord(e0, st);
+                if ((rc = group_svd(g, val, U, S, V, c)) != FASTPI_OK) break;
+                hipEventRecord(e1, st);
+                float ms = 0;
+                if (!elapsed(ms)) {
+                    rc = FASTPI_EHIP;
+                    break;
+                }
+                rep << "eig rows=" << rows << " inner=" << inner << " " << ms << " ms; ";
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    eig_best = cand;
+                }
+            }
+            if (rc != FASTPI_OK) break;
+        }
+        if (rc != FASTPI_OK) break;
+        best = eig_best;
+        if ((rc = group_set_tuning(g, best, st)) != FASTPI_OK) break;
+        rep << "chose lds=" << best.block_lds << " wgs/cu=" << best.block_wgs_per_cu << " rows=" << best.gram_rows
+            << " inner=" << best.inner_sweeps;
+        if (cache) rc = store_tuning(g, cache, device, c.mixed, best);
+    } while (false);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (report) *report = rep.str();
+    return rc;
+}
+
+}  // namespace fastpi

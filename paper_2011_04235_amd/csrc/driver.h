@@ -1,0 +1,104 @@
+// Device-side driver of the path: per-matrix device plans and workspaces ("instances") and
+// the group runner that takes any number of instances through the stages together.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "host_internal.h"
+#include "kernels.h"
+
+namespace fastpi {
+
+// Schedule parameters of the batched kernels (chosen by the autotuner, or defaults).
+struct Tuning {
+    int block_lds = 32 * 1024;   // dynamic LDS bytes of a block-SVD workgroup
+    int block_wgs_per_cu = 4;    // persistent block-SVD workgroups per compute unit
+    int gram_rows = 128;         // rows per partial-Gram workgroup in the eigensolver
+    int inner_sweeps = 1;        // inner Jacobi sweeps per pair solve
+};
+bool tuning_valid(const Tuning& t);
+
+struct DevicePlan {
+    bool valid = false;
+    int64_t m = 0, n = 0, nnz = 0, m1 = 0, n1 = 0, m2 = 0, n2 = 0, s_b = 0, s = 0, r = 0;
+    int64_t B_dense = 0, val_elems = 0, blk_elems = 0, u1 = 0, v1 = 0;
+    int64_t off_a21r = 0, off_a21c = 0, off_tr = 0, off_tc = 0;
+    BlockWork* work = nullptr;
+    int64_t *dst0 = nullptr, *dst1 = nullptr;
+    int64_t *a21_rowptr = nullptr, *a21_colptr = nullptr, *t_rowptr = nullptr, *t_colptr = nullptr;
+    int *a21_colidx = nullptr, *a21_rowidx = nullptr, *t_colidx = nullptr, *t_rowidx = nullptr;
+    int *piT = nullptr, *invT = nullptr, *invF = nullptr;
+    SegDev seg_a21c{}, seg_a21r{}, seg_tc{}, seg_tr{};
+};
+
+// One matrix: its device plan, workspace and status words.
+struct Instance {
+    DevicePlan dp;
+    std::vector<void*> allocs;          // device plan tables
+    std::vector<BlockWork> work;        // host copy of the block work list
+    std::vector<int64_t> scratch_off;   // per work item, in doubles, inside the scratch region
+    double* ws = nullptr;
+    size_t ws_bytes = 0;
+    int* iws = nullptr;
+    size_t iws_bytes = 0;
+    int* status = nullptr;   // device [0] status bits, [1] block sweeps (not owned)
+    int32_t sweeps[3] = {0, 0, 0};
+    // offsets (in doubles) of the stage buffers inside ws
+    int64_t o_vals = 0, o_u1 = 0, o_v1 = 0, o_sig1 = 0, o_g2 = 0, o_v2 = 0, o_lam2 = 0, o_sig2 = 0,
+            o_inv2 = 0, o_u2 = 0, o_g3 = 0, o_vt = 0, o_lam3 = 0, o_sig3 = 0, o_inv3 = 0, o_c1 = 0,
+            o_c2 = 0, o_eig = 0, o_part = 0, o_gs = 0, o_spart = 0, o_end = 0;
+};
+
+// Uploads the plan's tables and sizes the workspace (cap: 0 = none). Synchronises `st`.
+int instance_upload(Instance& I, const Plan& p, size_t ws_cap, hipStream_t st);
+void instance_free(Instance& I, hipStream_t st);
+
+struct RunCfg {
+    hipStream_t st = nullptr;
+    hipStream_t copy_st = nullptr;
+    KernelTimer* timer = nullptr;   // eager runs only
+    bool mixed = false;
+    int max_sweeps = 60;
+    double tol = 0;
+    bool use_graph = false;
+};
+
+// A set of instances that run together: one persistent block-SVD launch over all their
+// blocks, one batched eigensolver per update step, and the remaining stages per instance.
+struct Group {
+    std::vector<Instance*> inst;
+    int ncu = 256;
+    Tuning tune;
+    BlockTask* tasks = nullptr;
+    int ntasks = 0;
+    int* counter = nullptr;
+    EigSet set2, set3;
+    // captured graphs: stages before, between and after the two eigensolvers, and one
+    // sweep of each eigensolver
+    hipStream_t cap = nullptr;
+    hipGraphExec_t g_front = nullptr, g_sw2 = nullptr, g_mid = nullptr, g_sw3 = nullptr, g_back = nullptr;
+    std::vector<uint64_t> key;
+    int graph_launches = 0;   // graph launches of the last run
+};
+
+int group_build(Group& g, int device, hipStream_t st);
+void group_free(Group& g);
+void group_drop_graphs(Group& g);
+int group_set_tuning(Group& g, const Tuning& t, hipStream_t st);
+// Computes U, S, V of every instance (arrays of device pointers, one per instance).
+int group_svd(Group& g, const double* const* val, double* const* U, double* const* S,
+              double* const* V, const RunCfg& c);
+
+// Autotuner: times the candidate schedules on the group's own data and keeps the fastest.
+// The result is stored in (and first looked up from) a text cache keyed by the device
+// architecture, the precision and the shape bucket of the group, when `cache` is not null.
+int group_autotune(Group& g, const double* const* val, double* const* U, double* const* S,
+                   double* const* V, const RunCfg& c, const char* cache, int device,
+                   std::string* report);
+int tuning_lookup(const Group& g, const char* cache, int device, bool mixed, Tuning& out);
+
+}  // namespace fastpi

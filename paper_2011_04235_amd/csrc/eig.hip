@@ -8,8 +8,16 @@
 // the orthogonal V that the rotations build; when the columns of X are orthogonal, V
 // diagonalises G^2 and hence the positive semidefinite G, so X = V Lambda: the eigenvalues
 // are the column norms of X and the eigenvectors its normalised columns (V is never formed).
-// A pair whose columns are already orthogonal to `tol` (cosine) is left alone; the sweep
-// loop ends after a sweep with no rotated pair.
+// A pair whose columns are already orthogonal to `tol` (cosine) is left alone; a problem is
+// done after a sweep with no rotated pair.
+//
+// Several independent problems ("jobs") advance together: each round is three launches
+// (partial Grams, pair solves, column updates) whose workgroups are spread over the jobs
+// still inside their sweep, found from prefix sums of the per-job workgroup counts. Jobs
+// with fewer blocks have fewer rounds per sweep and sit out the remaining rounds. A done job
+// returns at once from every kernel, so a fixed launch sequence per sweep serves any mix of
+// converged and running jobs (and can be replayed from a captured graph).
+#include <algorithm>
 #include <cfloat>
 
 #include "device_common.h"
@@ -19,28 +27,55 @@ namespace fastpi {
 
 constexpr int BW = 16;
 constexpr int PW = 2 * BW;         // columns in a pair
-constexpr int GRAM_ROWS = 128;     // rows per partial-Gram workgroup
 constexpr int UPD_ROWS = 256;      // rows per update workgroup
+constexpr int ST_ROT = 0, ST_DONE = 1, ST_SWEEPS = 2, ST_CAPPED = 3, ST_WORDS = 4;
 
-__global__ void k_eig_init(const double* __restrict__ G, int64_t q, int64_t ld,
-                           double* __restrict__ X) {
-    const int64_t n = ld * ld;
+// largest j < nact with pre[j] <= bid (the job owning flattened workgroup bid)
+__device__ __forceinline__ int job_of(const int* __restrict__ pre, int nact, int bid) {
+    int lo = 0, hi = nact - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= bid) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void k_eig_init(const EigJob* __restrict__ jobs) {
+    const EigJob& J = jobs[blockIdx.y];
+    const int64_t n = J.ld * J.ld;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += stride) {
-        const int64_t r = e % ld, c = e / ld;
-        X[e] = (r < q && c < q) ? G[r * q + c] : 0.0;
+        const int64_t r = e % J.ld, c = e / J.ld;
+        J.X[e] = (r < J.q && c < J.q) ? J.G[r * J.q + c] : 0.0;
     }
 }
 
-// floor[0] = (ld eps)^2 ld max_c ||G_c||^2: columns of X = G V whose squared norm is below
+// eigenvalue estimates: column norms of X (non-finite values sort last so the order stays
+// a permutation)
+__global__ void k_eig_norms(const EigJob* __restrict__ jobs) {
+    const EigJob& J = jobs[blockIdx.y];
+    const int lane = threadIdx.x % kWave;
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (c >= J.ld) return;
+    double acc = 0;
+    for (int64_t r = lane; r < J.q; r += kWave) {
+        const double v = J.X[c * J.ld + r];
+        acc += v * v;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) J.lam[c] = (c < J.q && isfinite(acc)) ? sqrt(acc) : -DBL_MAX;
+}
+
+// lam[ld] = (ld eps)^2 ld max_c ||G_c||^2: columns of X = G V whose squared norm is below
 // it are rounding noise of a (numerically) zero eigenvalue -- ||x_c|| = lambda_c, whose
 // rounding level is ~ ld eps lambda_1, and lambda_1 <= sqrt(ld) max_c ||G_c|| -- and are
 // treated as converged (their cosines with anything are meaningless).
-__global__ __launch_bounds__(256) void k_eig_floor(const double* __restrict__ norms, int64_t ld,
-                                                   double* __restrict__ floor_out) {
+__global__ __launch_bounds__(256) void k_eig_floor(const EigJob* __restrict__ jobs) {
+    const EigJob& J = jobs[blockIdx.x];
     __shared__ double red[256];
     double mx = 0;
-    for (int64_t c = threadIdx.x; c < ld; c += blockDim.x) mx = norms[c] > mx ? norms[c] : mx;
+    for (int64_t c = threadIdx.x; c < J.ld; c += blockDim.x) mx = J.lam[c] > mx ? J.lam[c] : mx;
     red[threadIdx.x] = mx;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
@@ -48,47 +83,32 @@ __global__ __launch_bounds__(256) void k_eig_floor(const double* __restrict__ no
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const double e = static_cast<double>(ld) * DBL_EPSILON;
-        floor_out[0] = isfinite(red[0]) ? e * e * static_cast<double>(ld) * red[0] * red[0] : 0.0;
+        const double e = static_cast<double>(J.ld) * DBL_EPSILON;
+        J.lam[J.ld] = isfinite(red[0]) ? e * e * static_cast<double>(J.ld) * red[0] * red[0] : 0.0;
     }
-}
-
-// pair k of step `step` of the round robin over the PW columns of a pair, p < q
-__device__ __forceinline__ void inner_pair(int step, int k, int& p, int& q) {
-    int a, b;
-    if (k == 0) {
-        a = PW - 1;
-        b = step;
-    } else {
-        a = step + k;
-        if (a >= PW - 1) a -= PW - 1;
-        b = step - k;
-        if (b < 0) b += PW - 1;
-    }
-    p = a < b ? a : b;
-    q = a < b ? b : a;
-}
-
-__device__ __forceinline__ void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Partial Gram of one pair over one row chunk of X.
-__global__ __launch_bounds__(256) void k_eig_gram(const double* __restrict__ X, int64_t ld,
-                                                  const int2* __restrict__ pairs, int nblk,
-                                                  double* __restrict__ Hpart, int nchunk) {
-    __shared__ double Y[GRAM_ROWS][PW + 1];
-    const int pair = blockIdx.x, ch = blockIdx.y;
-    const int2 pb = pairs[pair];
-    if (pb.x >= nblk) return;
-    const bool hasJ = pb.y < nblk;   // the odd block out is paired with 16 zero columns
-    const int64_t r0 = static_cast<int64_t>(ch) * GRAM_ROWS;
-    const int nr = static_cast<int>(min<int64_t>(GRAM_ROWS, ld - r0));
-    for (int e = threadIdx.x; e < GRAM_ROWS * PW; e += blockDim.x) {
-        const int c = e / GRAM_ROWS, r = e % GRAM_ROWS;
-        const int col = c < BW ? pb.x * BW + c : pb.y * BW + (c - BW);
+template <int ROWS>
+__global__ __launch_bounds__(256) void k_eig_gram(const EigJob* __restrict__ jobs,
+                                                  const int* __restrict__ pre, int nact,
+                                                  const int* __restrict__ state, int round) {
+    __shared__ double Y[ROWS][PW + 1];
+    const int j = job_of(pre, nact, blockIdx.x);
+    if (state[ST_WORDS * j + ST_DONE]) return;
+    const EigJob& J = jobs[j];
+    const int local = blockIdx.x - pre[j];
+    const int pair = local / J.nchunk, ch = local % J.nchunk;
+    int bi, bj;
+    round_robin_pair(round, pair, J.nbe, bi, bj);
+    const bool hasJ = bj < J.nblk;   // the odd block out is paired with 16 zero columns
+    const int64_t ld = J.ld;
+    const int64_t r0 = static_cast<int64_t>(ch) * ROWS;
+    const int nr = static_cast<int>(min<int64_t>(ROWS, ld - r0));
+    const double* X = J.X;
+    for (int e = threadIdx.x; e < ROWS * PW; e += blockDim.x) {
+        const int c = e / ROWS, r = e % ROWS;
+        const int col = c < BW ? bi * BW + c : bj * BW + (c - BW);
         Y[r][c] = (r < nr && (c < BW || hasJ)) ? X[static_cast<int64_t>(col) * ld + r0 + r] : 0.0;
     }
     __syncthreads();
@@ -101,7 +121,7 @@ __global__ __launch_bounds__(256) void k_eig_gram(const double* __restrict__ X, 
         acc2 += ya * Y[r][b0 + 2];
         acc3 += ya * Y[r][b0 + 3];
     }
-    double* Hp = Hpart + (static_cast<int64_t>(pair) * nchunk + ch) * (PW * PW) + a * PW + b0;
+    double* Hp = J.Hpart + (static_cast<int64_t>(pair) * J.nchunk + ch) * (PW * PW) + a * PW + b0;
     Hp[0] = acc0;
     Hp[1] = acc1;
     Hp[2] = acc2;
@@ -142,23 +162,6 @@ __device__ __forceinline__ void fast_rotation(double hpp, double hqq, double hpq
     s = c * t;
 }
 
-// position of index i in the round robin of step `step`: returns its partner and whether
-// it is the lower index of its pair
-__device__ __forceinline__ void inner_partner(int step, int i, int& partner, bool& lower) {
-    int k;
-    if (i == PW - 1 || i == step) {
-        k = 0;
-    } else {
-        int d = i - step;
-        if (d < 0) d += PW - 1;
-        k = d < (PW - 1) - d ? d : (PW - 1) - d;
-    }
-    int p, q;
-    inner_pair(step, k, p, q);
-    lower = (i == p);
-    partner = lower ? q : p;
-}
-
 // Slot permutation between inner steps. Slots 0..31 hold the 32 columns of a pair; step
 // pairs are always the adjacent slots (2k, 2k+1). Slot 0 keeps the fixed player of the
 // circle-method round robin, slot 1 the player at circle offset 0 and slots 2d, 2d+1 the
@@ -178,24 +181,20 @@ __device__ __forceinline__ int inner_next_slot(int x) {
 // sides, W by input column and slot). In a step the 16 diagonal threads compute the rotation
 // of their slot pair, every thread applies J_a^T (.) J_b to its H block and (.) J_b to its W
 // block in registers, and the blocks are scattered to their next slots through LDS.
-__global__ __launch_bounds__(256) void k_eig_solve(const double* __restrict__ Hpart, int nchunk,
-                                                   const int2* __restrict__ pairs, int nblk,
-                                                   double* __restrict__ Wout,
-                                                   int* __restrict__ flag,
-                                                   int* __restrict__ rot_count, double tol,
-                                                   int inner_sweeps,
-                                                   const double* __restrict__ noise_floor) {
+__global__ __launch_bounds__(256) void k_eig_solve(const EigJob* __restrict__ jobs,
+                                                   const int* __restrict__ pre, int nact,
+                                                   int* __restrict__ state, int inner_sweeps) {
     __shared__ double Hs[2][PW][PW + 1];
     __shared__ double Ws[2][PW][PW + 1];
     __shared__ double rot[PW / 2][2];
     __shared__ int s_need;
-    const int pair = blockIdx.x;
-    const int2 pb = pairs[pair];
-    if (pb.x >= nblk) {
-        if (threadIdx.x == 0) flag[pair] = 0;
-        return;
-    }
-    const double* Hp = Hpart + static_cast<int64_t>(pair) * nchunk * (PW * PW);
+    const int j = job_of(pre, nact, blockIdx.x);
+    if (state[ST_WORDS * j + ST_DONE]) return;
+    const EigJob& J = jobs[j];
+    const int pair = blockIdx.x - pre[j];
+    const int nchunk = J.nchunk;
+    const double tol = J.tol;
+    const double* Hp = J.Hpart + static_cast<int64_t>(pair) * nchunk * (PW * PW);
     for (int e = threadIdx.x; e < PW * PW; e += 256) {
         double acc = 0;
         for (int c = 0; c < nchunk; ++c) acc += Hp[static_cast<int64_t>(c) * PW * PW + e];
@@ -203,21 +202,21 @@ __global__ __launch_bounds__(256) void k_eig_solve(const double* __restrict__ Hp
     }
     if (threadIdx.x == 0) s_need = 0;
     __syncthreads();
-    const double nf = noise_floor[0];
+    const double nf = J.lam[J.ld];
     {
         int need = 0;
         for (int e = threadIdx.x; e < PW * PW; e += 256) {
-            const int i = e / PW, j = e % PW;
-            if (i < j) {
-                const double hii = Hs[0][i][i], hjj = Hs[0][j][j], hij = Hs[0][i][j];
-                if (hii > nf && hjj > nf && fabs(hij) > tol * sqrt(hii) * sqrt(hjj)) need = 1;
+            const int i = e / PW, k = e % PW;
+            if (i < k) {
+                const double hii = Hs[0][i][i], hkk = Hs[0][k][k], hik = Hs[0][i][k];
+                if (hii > nf && hkk > nf && fabs(hik) > tol * sqrt(hii) * sqrt(hkk)) need = 1;
             }
         }
         if (need) s_need = 1;
     }
     __syncthreads();
     if (!s_need) {
-        if (threadIdx.x == 0) flag[pair] = 0;
+        if (threadIdx.x == 0) J.flag[pair] = 0;
         return;
     }
     const int a = threadIdx.x / (PW / 2), b = threadIdx.x % (PW / 2);
@@ -274,214 +273,325 @@ __global__ __launch_bounds__(256) void k_eig_solve(const double* __restrict__ Hp
         }
     }
     // after whole sweeps every slot holds its own column again
-    double* Wg = Wout + static_cast<int64_t>(pair) * PW * PW;
+    double* Wg = J.W + static_cast<int64_t>(pair) * PW * PW;
     Wg[r0 * PW + c0] = w00;
     Wg[r0 * PW + c1] = w01;
     Wg[r1 * PW + c0] = w10;
     Wg[r1 * PW + c1] = w11;
     if (threadIdx.x == 0) {
-        flag[pair] = 1;
-        atomicAdd(rot_count, 1);
+        J.flag[pair] = 1;
+        atomicAdd(state + ST_WORDS * j + ST_ROT, 1);
     }
 }
 
 // X[:, I u J] <- X[:, I u J] W, one thread per row
-__global__ __launch_bounds__(UPD_ROWS) void k_eig_update(double* __restrict__ X, int64_t ld,
-                                                         const int2* __restrict__ pairs, int nblk,
-                                                         const double* __restrict__ Wall,
-                                                         const int* __restrict__ flag) {
+__global__ __launch_bounds__(UPD_ROWS) void k_eig_update(const EigJob* __restrict__ jobs,
+                                                         const int* __restrict__ pre, int nact,
+                                                         const int* __restrict__ state, int round) {
     __shared__ double W[PW][PW];
-    const int pair = blockIdx.x;
-    const int2 pb = pairs[pair];
-    if (pb.x >= nblk) return;
-    if (flag[pair] == 0) return;
-    const bool hasJ = pb.y < nblk;
-    const double* Wg = Wall + static_cast<int64_t>(pair) * PW * PW;
+    const int j = job_of(pre, nact, blockIdx.x);
+    if (state[ST_WORDS * j + ST_DONE]) return;
+    const EigJob& J = jobs[j];
+    const int local = blockIdx.x - pre[j];
+    const int pair = local / J.nupd, rb = local % J.nupd;
+    if (J.flag[pair] == 0) return;
+    int bi, bj;
+    round_robin_pair(round, pair, J.nbe, bi, bj);
+    const bool hasJ = bj < J.nblk;
+    const double* Wg = J.W + static_cast<int64_t>(pair) * PW * PW;
     for (int e = threadIdx.x; e < PW * PW; e += blockDim.x) W[e / PW][e % PW] = Wg[e];
     __syncthreads();
-    const int64_t r = static_cast<int64_t>(blockIdx.y) * UPD_ROWS + threadIdx.x;
+    const int64_t ld = J.ld;
+    const int64_t r = static_cast<int64_t>(rb) * UPD_ROWS + threadIdx.x;
     if (r >= ld) return;
+    double* X = J.X;
     double y[PW];
 #pragma unroll
     for (int c = 0; c < PW; ++c) {
-        const int col = c < BW ? pb.x * BW + c : pb.y * BW + (c - BW);
+        const int col = c < BW ? bi * BW + c : bj * BW + (c - BW);
         y[c] = (c < BW || hasJ) ? X[static_cast<int64_t>(col) * ld + r] : 0.0;
     }
     const int jend = hasJ ? PW : BW;
 #pragma unroll 4
-    for (int j = 0; j < jend; ++j) {
+    for (int k = 0; k < jend; ++k) {
         double acc = 0;
 #pragma unroll
-        for (int k = 0; k < PW; ++k) acc += y[k] * W[k][j];
-        const int col = j < BW ? pb.x * BW + j : pb.y * BW + (j - BW);
+        for (int c = 0; c < PW; ++c) acc += y[c] * W[c][k];
+        const int col = k < BW ? bi * BW + k : bj * BW + (k - BW);
         X[static_cast<int64_t>(col) * ld + r] = acc;
     }
 }
 
-// eigenvalues: column norms of X (non-finite values sort last so the order stays a
-// permutation)
-__global__ void k_eig_norms(const double* __restrict__ X, int64_t ld, int64_t q,
-                            double* __restrict__ lam) {
-    const int lane = threadIdx.x % kWave;
-    const int64_t c = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
-    if (c >= ld) return;
-    double acc = 0;
-    for (int64_t r = lane; r < q; r += kWave) {
-        const double v = X[c * ld + r];
-        acc += v * v;
+// End of a sweep: a job whose sweep rotated nothing is done; one that reached the sweep cap
+// is done and flagged. The last word says whether every job is done.
+__global__ __launch_bounds__(256) void k_eig_sweep_end(const EigJob* __restrict__ jobs, int njobs,
+                                                       int* __restrict__ state, int max_sweeps) {
+    __shared__ int s_all;
+    if (threadIdx.x == 0) s_all = 1;
+    __syncthreads();
+    for (int j = threadIdx.x; j < njobs; j += blockDim.x) {
+        int* sj = state + ST_WORDS * j;
+        if (!sj[ST_DONE]) {
+            sj[ST_SWEEPS] += 1;
+            if (sj[ST_ROT] == 0) {
+                sj[ST_DONE] = 1;
+            } else if (sj[ST_SWEEPS] >= max_sweeps) {
+                sj[ST_DONE] = 1;
+                sj[ST_CAPPED] = 1;
+                if (jobs[j].status) atomicOr(jobs[j].status, 2);
+            }
+            sj[ST_ROT] = 0;
+        }
+        if (!sj[ST_DONE]) s_all = 0;   // every writer stores 0
     }
-    acc = wave_sum(acc);
-    if (lane == 0) lam[c] = (c < q && isfinite(acc)) ? sqrt(acc) : -DBL_MAX;
+    __syncthreads();
+    if (threadIdx.x == 0) state[ST_WORDS * njobs] = s_all;
 }
 
 // order of the t largest eigenvalues (descending, ties to the lower column)
-__global__ __launch_bounds__(1024) void k_eig_select(const double* __restrict__ lam, int64_t q,
-                                                     int64_t t, int* __restrict__ order) {
-    for (int64_t c = threadIdx.x; c < q; c += blockDim.x) {
+__global__ __launch_bounds__(1024) void k_eig_select(const EigJob* __restrict__ jobs) {
+    const EigJob& J = jobs[blockIdx.x];
+    const double* lam = J.lam;
+    for (int64_t c = threadIdx.x; c < J.q; c += blockDim.x) {
         const double lc = lam[c];
         int64_t rk = 0;
-        for (int64_t d = 0; d < q; ++d) {
+        for (int64_t d = 0; d < J.q; ++d) {
             const double ld_ = lam[d];
             rk += (ld_ > lc) || (ld_ == lc && d < c);
         }
-        if (rk < t) order[rk] = static_cast<int>(c);
+        if (rk < J.t) J.order[rk] = static_cast<int>(c);
     }
 }
 
 // vecs (q x t, row-major): the normalised columns of X; vals (t): their norms
-__global__ void k_eig_output(const double* __restrict__ X, int64_t ld, int64_t q, int64_t t,
-                             const int* __restrict__ order, const double* __restrict__ lam,
-                             double* __restrict__ vals, double* __restrict__ vecs) {
-    const int64_t n = q * t;
+__global__ void k_eig_output(const EigJob* __restrict__ jobs) {
+    const EigJob& J = jobs[blockIdx.y];
+    const int64_t n = J.q * J.t;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += stride) {
-        const int64_t r = e / t, k = e % t;
-        const double l = lam[order[k]];
+        const int64_t r = e / J.t, k = e % J.t;
+        const int oc = J.order[k];
+        const double l = J.lam[oc];
         const double inv = l > 0 ? 1.0 / l : 0.0;
-        vecs[e] = X[static_cast<int64_t>(order[k]) * ld + r] * inv;
-        if (r == 0) vals[k] = l > 0 ? l : 0.0;
+        J.vecs[e] = J.X[static_cast<int64_t>(oc) * J.ld + r] * inv;
+        if (r == 0) J.vals[k] = l > 0 ? l : 0.0;
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------------------
 int64_t eig_padded_order(int64_t q) { return ((q + BW - 1) / BW) * BW; }
 
-size_t eig_workspace_doubles(int64_t q) {
-    const int64_t ld = eig_padded_order(q);
-    const int64_t nblk = ld / BW;
-    const int64_t npairs = (nblk + 1) / 2;
-    const int64_t nchunk = (ld + GRAM_ROWS - 1) / GRAM_ROWS;
-    return static_cast<size_t>(ld * ld + npairs * nchunk * PW * PW + npairs * PW * PW + 2 * ld + 64);
+int eig_gram_rows_valid(int rows) { return rows == 64 || rows == 128 || rows == 256; }
+
+static void job_shape(int64_t q, int gram_rows, int64_t& ld, int& nblk, int& nbe, int& npairs,
+                      int& nchunk, int& nupd) {
+    ld = eig_padded_order(q);
+    nblk = static_cast<int>(ld / BW);
+    nbe = nblk + (nblk & 1);   // even number of slots (the extra one is a dummy)
+    npairs = nbe / 2;
+    nchunk = static_cast<int>((ld + gram_rows - 1) / gram_rows);
+    nupd = static_cast<int>((ld + UPD_ROWS - 1) / UPD_ROWS);
 }
 
-size_t eig_int_workspace(int64_t q, int max_sweeps) {
+size_t eig_job_doubles(int64_t q, int gram_rows) {
+    int64_t ld;
+    int nblk, nbe, npairs, nchunk, nupd;
+    job_shape(q, gram_rows, ld, nblk, nbe, npairs, nchunk, nupd);
+    return static_cast<size_t>(ld * ld + static_cast<int64_t>(npairs) * nchunk * PW * PW +
+                               static_cast<int64_t>(npairs) * PW * PW + ld + 32);
+}
+
+size_t eig_job_ints(int64_t q) {
     const int64_t ld = eig_padded_order(q);
     const int64_t npairs = (ld / BW + 1) / 2;
-    return static_cast<size_t>(2 * npairs + ld + max_sweeps + 64);
+    return static_cast<size_t>(npairs + ld + 32);
 }
 
-// Host driver. ws holds eig_workspace_doubles(q) doubles, iws eig_int_workspace(q, max_sweeps)
-// ints; pair_tables is the device copy of the round-robin tables for the padded order.
-// The rotation count of sweep k is read back while sweep k+1 is already queued, so the
-// device never waits on the host; a sweep queued after convergence finds nothing to do.
-int eig_top(const double* G, int64_t q, int64_t t, double* vals, double* vecs, double* ws,
-            int* iws, const int2* pair_tables, int max_sweeps, double tol, int inner_sweeps,
-            int* sweeps_out, int* host_counter, hipStream_t st, hipStream_t copy_st,
-            KernelTimer* timer) {
-    const int64_t ld = eig_padded_order(q);
-    const int nblk = static_cast<int>(ld / BW);
-    const int nbe = nblk + (nblk & 1);     // even number of slots (the extra one is a dummy)
-    const int npairs = nbe / 2;
-    const int rounds = nbe - 1;
-    const int nchunk = static_cast<int>((ld + GRAM_ROWS - 1) / GRAM_ROWS);
-    const int nupd = static_cast<int>((ld + UPD_ROWS - 1) / UPD_ROWS);
-    double* X = ws;
-    double* Hpart = X + ld * ld;
-    double* W = Hpart + static_cast<int64_t>(npairs) * nchunk * PW * PW;
-    double* lam = W + static_cast<int64_t>(npairs) * PW * PW;
-    int* flag = iws;
-    int* arrive = flag + npairs;
-    int* order = arrive + npairs;
-    int* rot = order + ld;                 // one counter per sweep
-    // reads the rotation counter of sweep k on the side stream once sweep k has finished
-    auto read_counter = [&](int k, hipEvent_t e) -> int {
-        if (hipStreamWaitEvent(copy_st, e, 0) != hipSuccess) return FASTPI_EHIP;
-        if (hipMemcpyAsync(host_counter, rot + k, sizeof(int), hipMemcpyDeviceToHost, copy_st) != hipSuccess)
-            return FASTPI_EHIP;
-        if (hipStreamSynchronize(copy_st) != hipSuccess) return FASTPI_EHIP;
-        return FASTPI_OK;
-    };
-    hipLaunchKernelGGL(k_eig_init, dim3(static_cast<int>(std::min<int64_t>((ld * ld + 255) / 256, 8192))),
-                       dim3(256), 0, st, G, q, ld, X);
-    launch_fill_i32(rot, max_sweeps, 0, st);
-    hipLaunchKernelGGL(k_eig_norms, dim3(static_cast<int>((ld + 3) / 4)), dim3(256), 0, st, X, ld, q, lam);
-    hipLaunchKernelGGL(k_eig_floor, dim3(1), dim3(256), 0, st, lam, ld, lam + ld);
-    if (tol <= 0) tol = static_cast<double>(ld) * DBL_EPSILON;
+EigJob eig_make_job(const double* G, int64_t q, int64_t t, double* vals, double* vecs,
+                    double* ws, int* iws, int* status, double tol, int gram_rows, int tag) {
+    EigJob J{};
+    job_shape(q, gram_rows, J.ld, J.nblk, J.nbe, J.npairs, J.nchunk, J.nupd);
+    J.G = G;
+    J.vals = vals;
+    J.vecs = vecs;
+    J.q = q;
+    J.t = t;
+    J.X = ws;
+    J.Hpart = J.X + J.ld * J.ld;
+    J.W = J.Hpart + static_cast<int64_t>(J.npairs) * J.nchunk * PW * PW;
+    J.lam = J.W + static_cast<int64_t>(J.npairs) * PW * PW;
+    J.flag = iws;
+    J.order = iws + J.npairs;
+    J.status = status;
+    J.tol = tol > 0 ? tol : static_cast<double>(J.ld) * DBL_EPSILON;
+    J.tag = tag;
+    return J;
+}
+
+void eig_set_free(EigSet& es) {
+    if (es.jobs) hipFree(es.jobs);
+    if (es.pre) hipFree(es.pre);
+    if (es.state) hipFree(es.state);
+    if (es.host_state) hipHostFree(es.host_state);
+    es = EigSet{};
+}
+
+int eig_set_create(EigSet& es, std::vector<EigJob> jobs, int gram_rows, hipStream_t st) {
+    eig_set_free(es);
+    es.gram_rows = gram_rows;
+    std::stable_sort(jobs.begin(), jobs.end(),
+                     [](const EigJob& x, const EigJob& y) { return x.nbe > y.nbe; });
+    const int nj = static_cast<int>(jobs.size());
+    es.njobs = nj;
+    es.host = jobs;
+    if (nj == 0) return FASTPI_OK;
+    es.rounds = jobs[0].nbe - 1;
+    std::vector<int> pre(3 * (nj + 1), 0);
+    for (int j = 0; j < nj; ++j) {
+        const EigJob& J = jobs[j];
+        pre[j + 1] = pre[j] + J.npairs * J.nchunk;
+        pre[(nj + 1) + j + 1] = pre[(nj + 1) + j] + J.npairs;
+        pre[2 * (nj + 1) + j + 1] = pre[2 * (nj + 1) + j] + J.npairs * J.nupd;
+        es.max_ld = std::max(es.max_ld, J.ld);
+    }
+    for (int t = 0; t < es.rounds; ++t) {
+        int na = 0;
+        while (na < nj && jobs[na].nbe - 1 > t) ++na;
+        es.nact.push_back(na);
+        es.g_gram.push_back(pre[na]);
+        es.g_solve.push_back(pre[(nj + 1) + na]);
+        es.g_upd.push_back(pre[2 * (nj + 1) + na]);
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, sizeof(EigJob) * nj) != hipSuccess) return FASTPI_ENOMEM;
+    es.jobs = static_cast<EigJob*>(p);
+    if (hipMalloc(&p, sizeof(int) * pre.size()) != hipSuccess) return FASTPI_ENOMEM;
+    es.pre = static_cast<int*>(p);
+    if (hipMalloc(&p, sizeof(int) * (ST_WORDS * nj + ST_WORDS)) != hipSuccess) return FASTPI_ENOMEM;
+    es.state = static_cast<int*>(p);
+    if (hipHostMalloc(&p, sizeof(int) * (ST_WORDS * nj + ST_WORDS), hipHostMallocDefault) != hipSuccess)
+        return FASTPI_ENOMEM;
+    es.host_state = static_cast<int*>(p);
+    std::fill(es.host_state, es.host_state + ST_WORDS * nj + ST_WORDS, 0);
+    if (hipMemcpyAsync(es.jobs, es.host.data(), sizeof(EigJob) * nj, hipMemcpyHostToDevice, st) != hipSuccess)
+        return FASTPI_EHIP;
+    if (hipMemcpyAsync(es.pre, pre.data(), sizeof(int) * pre.size(), hipMemcpyHostToDevice, st) != hipSuccess)
+        return FASTPI_EHIP;
+    // the pageable sources above must outlive the copies
+    if (hipStreamSynchronize(st) != hipSuccess) return FASTPI_EHIP;
+    return FASTPI_OK;
+}
+
+void eig_begin(const EigSet& es, hipStream_t st) {
+    if (es.njobs == 0) return;
+    const unsigned nj = static_cast<unsigned>(es.njobs);
+    launch_fill_i32(es.state, ST_WORDS * es.njobs + ST_WORDS, 0, st);
+    const unsigned gx = static_cast<unsigned>(std::min<int64_t>((es.max_ld * es.max_ld + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_eig_init, dim3(gx, nj), dim3(256), 0, st, es.jobs);
+    hipLaunchKernelGGL(k_eig_norms, dim3(static_cast<unsigned>((es.max_ld + 3) / 4), nj), dim3(256), 0, st,
+                       es.jobs);
+    hipLaunchKernelGGL(k_eig_floor, dim3(nj), dim3(256), 0, st, es.jobs);
+}
+
+void eig_sweep(const EigSet& es, int max_sweeps, int inner_sweeps, hipStream_t st, KernelTimer* timer) {
+    if (es.njobs == 0) return;
+    const int nj = es.njobs;
+    const int* pg = es.pre;
+    const int* ps = es.pre + (nj + 1);
+    const int* pu = es.pre + 2 * (nj + 1);
+    for (int t = 0; t < es.rounds; ++t) {
+        const int na = es.nact[t];
+        long ts = timer ? timer->begin(KT_EIG_GRAM, st) : -1;
+        switch (es.gram_rows) {
+            case 64:
+                hipLaunchKernelGGL(k_eig_gram<64>, dim3(es.g_gram[t]), dim3(256), 0, st, es.jobs, pg, na,
+                                   es.state, t);
+                break;
+            case 256:
+                hipLaunchKernelGGL(k_eig_gram<256>, dim3(es.g_gram[t]), dim3(256), 0, st, es.jobs, pg, na,
+                                   es.state, t);
+                break;
+            default:
+                hipLaunchKernelGGL(k_eig_gram<128>, dim3(es.g_gram[t]), dim3(256), 0, st, es.jobs, pg, na,
+                                   es.state, t);
+        }
+        if (timer) timer->end(ts, st);
+        ts = timer ? timer->begin(KT_EIG_SOLVE, st) : -1;
+        hipLaunchKernelGGL(k_eig_solve, dim3(es.g_solve[t]), dim3(256), 0, st, es.jobs, ps, na, es.state,
+                           inner_sweeps);
+        if (timer) timer->end(ts, st);
+        ts = timer ? timer->begin(KT_EIG_UPDATE, st) : -1;
+        hipLaunchKernelGGL(k_eig_update, dim3(es.g_upd[t]), dim3(UPD_ROWS), 0, st, es.jobs, pu, na, es.state,
+                           t);
+        if (timer) timer->end(ts, st);
+    }
+    hipLaunchKernelGGL(k_eig_sweep_end, dim3(1), dim3(256), 0, st, es.jobs, nj, es.state, max_sweeps);
+}
+
+void eig_end(const EigSet& es, hipStream_t st) {
+    if (es.njobs == 0) return;
+    const unsigned nj = static_cast<unsigned>(es.njobs);
+    int64_t max_qt = 0;
+    for (const EigJob& J : es.host) max_qt = std::max(max_qt, J.q * J.t);
+    hipLaunchKernelGGL(k_eig_norms, dim3(static_cast<unsigned>((es.max_ld + 3) / 4), nj), dim3(256), 0, st,
+                       es.jobs);
+    hipLaunchKernelGGL(k_eig_select, dim3(nj), dim3(1024), 0, st, es.jobs);
+    const unsigned gx = static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>((max_qt + 255) / 256, 4096)));
+    hipLaunchKernelGGL(k_eig_output, dim3(gx, nj), dim3(256), 0, st, es.jobs);
+}
+
+int eig_iterate(const EigSet& es, int max_sweeps, int inner_sweeps, hipStream_t st, hipStream_t copy_st,
+                KernelTimer* timer, hipGraphExec_t sweep_graph) {
+    if (es.njobs == 0) return FASTPI_OK;
+    const size_t words = ST_WORDS * es.njobs + ST_WORDS;
     hipEvent_t ev[2];
     if (hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) != hipSuccess) return FASTPI_EHIP;
-    if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) return FASTPI_EHIP;
-    int sweeps_done = 0;
-    bool converged = false;
-    int checked = 0;   // sweeps whose counter has been read
-    for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
-        for (int round = 0; round < rounds; ++round) {
-            const int2* pr = pair_tables + static_cast<int64_t>(round) * npairs;
-            long ts = timer ? timer->begin(KT_EIG_GRAM, st) : -1;
-            hipLaunchKernelGGL(k_eig_gram, dim3(npairs, nchunk), dim3(256), 0, st, X, ld, pr, nblk, Hpart,
-                               nchunk);
-            if (timer) timer->end(ts, st);
-            ts = timer ? timer->begin(KT_EIG_SOLVE, st) : -1;
-            hipLaunchKernelGGL(k_eig_solve, dim3(npairs), dim3(256), 0, st, Hpart, nchunk, pr, nblk, W,
-                               flag, rot + sweep, tol, inner_sweeps, lam + ld);
-            if (timer) timer->end(ts, st);
-            ts = timer ? timer->begin(KT_EIG_UPDATE, st) : -1;
-            hipLaunchKernelGGL(k_eig_update, dim3(npairs, nupd), dim3(UPD_ROWS), 0, st, X, ld, pr, nblk,
-                               W, flag);
-            if (timer) timer->end(ts, st);
+    if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
+        hipEventDestroy(ev[0]);
+        return FASTPI_EHIP;
+    }
+    int rc = FASTPI_OK;
+    // reads the state after sweep k (event e) on the side stream
+    auto read_state = [&](hipEvent_t e) -> bool {
+        if (hipStreamWaitEvent(copy_st, e, 0) != hipSuccess) return false;
+        if (hipMemcpyAsync(es.host_state, es.state, sizeof(int) * words, hipMemcpyDeviceToHost, copy_st) !=
+            hipSuccess)
+            return false;
+        return hipStreamSynchronize(copy_st) == hipSuccess;
+    };
+    bool all_done = false;
+    int queued = 0;
+    // every job is done after at most max_sweeps sweeps (the cap marks it done)
+    for (int sweep = 0; sweep < max_sweeps && !all_done; ++sweep) {
+        if (sweep_graph) {
+            if (hipGraphLaunch(sweep_graph, st) != hipSuccess) {
+                rc = FASTPI_EHIP;
+                break;
+            }
+        } else {
+            eig_sweep(es, max_sweeps, inner_sweeps, st, timer);
         }
-        hipEventRecord(ev[sweep & 1], st);
-        sweeps_done = sweep + 1;
+        if (hipEventRecord(ev[sweep & 1], st) != hipSuccess) {
+            rc = FASTPI_EHIP;
+            break;
+        }
+        queued = sweep + 1;
         if (sweep >= 1) {
-            // read the previous sweep's counter while this one runs
-            if (read_counter(sweep - 1, ev[(sweep - 1) & 1]) != FASTPI_OK) return FASTPI_EHIP;
-            checked = sweep;
-            if (*host_counter == 0) converged = true;
+            // read the previous sweep's state while this one runs
+            if (!read_state(ev[(sweep - 1) & 1])) {
+                rc = FASTPI_EHIP;
+                break;
+            }
+            all_done = es.host_state[ST_WORDS * es.njobs] != 0;
         }
     }
-    if (!converged && checked < sweeps_done) {
-        if (read_counter(sweeps_done - 1, ev[(sweeps_done - 1) & 1]) != FASTPI_OK) return FASTPI_EHIP;
-        if (*host_counter == 0) converged = true;
-    }
+    // the final state (a sweep queued after convergence changes nothing)
+    if (rc == FASTPI_OK && queued > 0 && !read_state(ev[(queued - 1) & 1])) rc = FASTPI_EHIP;
     hipEventDestroy(ev[0]);
     hipEventDestroy(ev[1]);
-    if (sweeps_out) *sweeps_out = sweeps_done;
-    hipLaunchKernelGGL(k_eig_norms, dim3(static_cast<int>((ld + 3) / 4)), dim3(256), 0, st, X, ld, q, lam);
-    hipLaunchKernelGGL(k_eig_select, dim3(1), dim3(1024), 0, st, lam, q, t, order);
-    hipLaunchKernelGGL(k_eig_output, dim3(static_cast<int>(std::min<int64_t>((q * t + 255) / 256, 8192))),
-                       dim3(256), 0, st, X, ld, q, t, order, lam, vals, vecs);
-    return converged ? FASTPI_OK : FASTPI_ENOCONV;
-}
-
-// circle-method tables for nblk blocks: rounds x npairs entries (dummy slot = nblk)
-void eig_pair_table(int64_t q, std::vector<int2>& out) {
-    const int64_t ld = eig_padded_order(q);
-    const int nblk = static_cast<int>(ld / BW);
-    const int nbe = nblk + (nblk & 1);
-    const int npairs = nbe / 2;
-    out.clear();
-    for (int round = 0; round < nbe - 1; ++round) {
-        for (int pr = 0; pr < npairs; ++pr) {
-            int a, b;
-            if (pr == 0) {
-                a = nbe - 1;
-                b = round;
-            } else {
-                a = (round + pr) % (nbe - 1);
-                b = (round - pr + nbe - 1) % (nbe - 1);
-            }
-            if (a > b) std::swap(a, b);
-            out.push_back(make_int2(a, b));
-        }
-    }
+    return rc;
 }
 
 }  // namespace fastpi

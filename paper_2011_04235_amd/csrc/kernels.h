@@ -63,20 +63,71 @@ void launch_fill_i32(int* p, int64_t n, int v, hipStream_t st);
 void launch_gather(const double* val, const int64_t* dst0, const int64_t* dst1, int64_t nnz,
                    double* out, int* status, hipStream_t st);
 
-void launch_block_svd(bool fp32, const BlockWork* work, int first, int count, const double* blk,
-                      void* gscratch, const int64_t* gscratch_off, int lds_bytes, double* U1,
-                      double* sig1, double* V1, int max_sweeps, double tol_scale,
-                      int* sweeps_used, int* status, hipStream_t st);
+// One diagonal block for the persistent block-SVD launch: absolute device addresses, so the
+// blocks of several matrices can share one launch. `scratch` holds rows*cols + q*q elements
+// of the compute type for blocks that do not fit the launch's LDS budget.
+struct BlockTask {
+    const double* A;    // dense block, column-major rows x cols
+    double* U;          // rows x rank, column-major
+    double* V;          // cols x rank, column-major
+    double* sig;        // rank values, descending
+    void* scratch;
+    int* status;        // [0] status bits, [1] maximum sweeps used
+    int32_t rows, cols, rank, pad;
+};
 
-// eigensolver (eig.hip)
+// Persistent batched Jacobi: `grid` workgroups take tasks from an atomic queue (`counter`
+// must hold 0 at launch; the launcher clears it with a fill kernel first).
+void launch_block_svd_tasks(bool fp32, const BlockTask* tasks, int ntasks, int* counter,
+                            int lds_bytes, int grid, int max_sweeps, double tol_scale,
+                            hipStream_t st);
+void launch_copy(const double* src, int64_t n, double* dst, hipStream_t st);
+
+// eigensolver (eig.hip): block one-sided Jacobi on a set of independent symmetric PSD
+// problems ("jobs") that advance together, one launch per kernel and round for all jobs.
+struct EigJob {
+    const double* G;    // q x q row-major input
+    double* vals;       // t eigenvalues, descending
+    double* vecs;       // q x t row-major eigenvectors
+    double* X;          // ld x ld column-major iterate
+    double* Hpart;      // npairs * nchunk partial 32 x 32 Grams
+    double* W;          // npairs 32 x 32 rotations
+    double* lam;        // ld column norms, then the noise floor
+    int* flag;          // npairs: pair rotated in this round
+    int* order;         // t: columns of the t largest norms
+    int* status;        // status word of the owner (bit 1 when the sweep cap is hit), or null
+    double tol;         // cosine threshold of the outer pairs
+    int64_t q, t, ld;
+    int nblk, nbe, npairs, nchunk, nupd, tag;
+};
+struct EigSet {
+    int njobs = 0, rounds = 0, gram_rows = 128;
+    EigJob* jobs = nullptr;       // device, jobs sorted by rounds per sweep (descending)
+    int* pre = nullptr;           // device prefix sums of the per-job workgroup counts:
+                                  // gram, solve, update (each njobs + 1)
+    int* state = nullptr;         // device, per job {rotations, done, sweeps, capped}, then
+                                  // the all-done word
+    int* host_state = nullptr;    // pinned mirror of state
+    std::vector<EigJob> host;     // host copy, same order
+    std::vector<int> nact, g_gram, g_solve, g_upd;   // per round: active jobs and grids
+    int64_t max_ld = 0;
+};
 int64_t eig_padded_order(int64_t q);
-size_t eig_workspace_doubles(int64_t q);
-size_t eig_int_workspace(int64_t q, int max_sweeps);
-void eig_pair_table(int64_t q, std::vector<int2>& out);
-int eig_top(const double* G, int64_t q, int64_t t, double* vals, double* vecs, double* ws,
-            int* iws, const int2* pair_tables, int max_sweeps, double tol, int inner_sweeps,
-            int* sweeps_out, int* host_counter, hipStream_t st, hipStream_t copy_st,
-            KernelTimer* timer);
+int eig_gram_rows_valid(int rows);
+size_t eig_job_doubles(int64_t q, int gram_rows);
+size_t eig_job_ints(int64_t q);
+EigJob eig_make_job(const double* G, int64_t q, int64_t t, double* vals, double* vecs,
+                    double* ws, int* iws, int* status, double tol, int gram_rows, int tag);
+int eig_set_create(EigSet& es, std::vector<EigJob> jobs, int gram_rows, hipStream_t st);
+void eig_set_free(EigSet& es);
+void eig_begin(const EigSet& es, hipStream_t st);
+void eig_sweep(const EigSet& es, int max_sweeps, int inner_sweeps, hipStream_t st,
+               KernelTimer* timer);
+void eig_end(const EigSet& es, hipStream_t st);
+// Runs sweeps (eagerly, or by replaying `sweep_graph`) until every job is done; the state of
+// sweep k is read on copy_st while sweep k+1 is queued. On return es.host_state is final.
+int eig_iterate(const EigSet& es, int max_sweeps, int inner_sweeps, hipStream_t st,
+                hipStream_t copy_st, KernelTimer* timer, hipGraphExec_t sweep_graph);
 
 // dense (dense.hip)
 int gemm_tn_splits(int64_t M, int64_t N, int64_t K);
