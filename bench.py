@@ -52,26 +52,27 @@ def flop_model(plan, blocks, ranks, L):
 # (4 multiplies + 3 adds) and of W (2 multiplies + 1 add): 31 * 1024 * 10 flops; the
 # partial-Gram sum adds nchunk * 1024 flops.
 PAIR_SWEEP_FLOPS = 31 * 1024 * 10
-GRAM_ROWS = 128          # rows per partial Gram (eigensolver)
+GRAM_ROWS = 128          # default rows per partial Gram (eigensolver)
 BW = 16                  # eigensolver column block
 
 
-def eig_shape(q):
+def eig_shape(q, gram_rows=128):
     ld = (q + BW - 1) // BW * BW
     nblk = ld // BW
     nbe = nblk + (nblk & 1)
-    return ld, nblk, nbe // 2, nbe - 1, (ld + GRAM_ROWS - 1) // GRAM_ROWS
+    return ld, nblk, nbe // 2, nbe - 1, (ld + gram_rows - 1) // gram_rows
 
 
-def solve_flops_per_launch(info, sweeps):
+def solve_flops_per_launch(info, sweeps, tuning):
     """Launch-weighted average algorithmic flops of one k_eig_solve launch (all real pairs)."""
     tot_f = tot_n = 0.0
+    inner = tuning.get("inner_sweeps", 1)
     for q, sw in ((info["n1"], sweeps[1]), (info["s"] + info["n2"], sweeps[2])):
         if q <= 0 or sw <= 0:
             continue
-        ld, nblk, npairs, rounds, nchunk = eig_shape(q)
+        ld, nblk, npairs, rounds, nchunk = eig_shape(q, tuning.get("gram_rows", GRAM_ROWS))
         real_pairs = nblk // 2 + (nblk & 1)          # the odd block out still solves alone
-        f = real_pairs * (PAIR_SWEEP_FLOPS + nchunk * 1024)
+        f = real_pairs * (inner * PAIR_SWEEP_FLOPS + nchunk * 1024)
         tot_f += f * rounds * sw
         tot_n += rounds * sw
     return tot_f / tot_n if tot_n else 0.0
@@ -118,6 +119,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c2")
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
+    ap.add_argument("--form", default="both", choices=["plain", "batched", "both"])
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--roofline-kernel", default="eig_solve",
@@ -151,40 +153,65 @@ def main():
     m, n, r = plan.m, plan.n, plan.r
     A_host = sp.csr_matrix((prob.data, prob.indices, prob.indptr), shape=(m, n))
 
-    def run_path(precision):
+    def run_path(precision, batched):
+        """Plain form: eager launches with the default schedule. Batched form: the
+        autotuned schedule and the stage chain replayed from HIP graphs."""
         h = fp.Handle(0, precision=precision)
         h.upload_plan(plan)
         U = torch.empty((m, r), dtype=torch.float64, device=dev)
         S = torch.empty((r,), dtype=torch.float64, device=dev)
         V = torch.empty((n, r), dtype=torch.float64, device=dev)
         Z = torch.empty((n, cfg.L), dtype=torch.float64, device=dev)
+        tune_report = None
+        if batched:
+            tune_report = h.autotune(rowptr, col, val, out=(U, S, V))
+            h.set_graph(True)
 
         def step():
             h.svd(rowptr, col, val, out=(U, S, V))
             h.apply(U, S, V, Y, out=Z)
 
+        def timed(k):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(k):
+                step()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / k
+
         for _ in range(args.warmup):
             step()
         h.sync()
-        torch.cuda.synchronize()
-        # the dominant kernel is timed launch by launch with HIP events on the library's stream
-        h.timing_start(args.roofline_kernel)
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            step()
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        # the dominant kernel is timed launch by launch with HIP events on the library's
+        # stream; graph replays carry no per-kernel events, so a batched leg times it in an
+        # eager pass of the same schedule right after its timed region
+        if not batched:
+            h.timing_start(args.roofline_kernel)
+        dt = timed(args.steps)
         h.sync()
+        graph_launches = h.last_graph_launches()
+        if batched:
+            h.set_graph(False)
+            h.timing_start(args.roofline_kernel)
+            eager_dt = timed(args.steps)
+            h.set_graph(True)
         n_launch, k_ms = h.timing_read()
         h.timing_start(None)
         sweeps = h.last_sweeps()
         Uh, Sh, Vh = U.cpu().numpy(), S.cpu().numpy(), V.cpu().numpy()
-        return {"ms": dt / args.steps * 1e3, "sweeps": sweeps, "n_launch": n_launch, "k_ms": k_ms,
-                "recon": recon_error(A_host, Uh, Sh, Vh), "sigma": Sh}
+        out = {"ms": dt * 1e3, "sweeps": sweeps, "n_launch": n_launch, "k_ms": k_ms,
+               "recon": recon_error(A_host, Uh, Sh, Vh), "sigma": Sh, "tuning": h.get_tuning(),
+               "graph_launches_per_step": graph_launches}
+        if batched:
+            out["tune_report"] = tune_report
+            out["eager_ms"] = eager_dt * 1e3
+        return out
 
     precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
-    res = {p: run_path(p) for p in precs}
-    head = res["mixed"] if "mixed" in res else res["fp64"]
+    forms = {"plain": False, "batched": True} if args.form == "both" else {args.form: args.form == "batched"}
+    res = {f"{p}-{f}": run_path(p, b) for p in precs for f, b in forms.items()}
+    head_key = [k for k in ("mixed-batched", "mixed-plain", "fp64-batched", "fp64-plain") if k in res][0]
+    head = res[head_key]
     ms = head["ms"]
     tflops = F["total"] / (ms * 1e-3) / 1e12
     sweeps = head["sweeps"]
@@ -192,25 +219,35 @@ def main():
 
     roof = None
     if n_launch > 0 and args.roofline_kernel == "eig_solve":
-        per_launch = solve_flops_per_launch(plan.info, sweeps)
+        per_launch = solve_flops_per_launch(plan.info, sweeps, head["tuning"])
         avg_s = k_ms / n_launch * 1e-3
         achieved = per_launch / avg_s / 1e12
         peak = 78.6   # MI355X FP64 vector peak, TFLOP/s
         roof = {"bound": "alu", "kernel": "k_eig_solve", "achieved": round(achieved, 5),
                 "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 6),
                 "traffic": None, "launches": n_launch, "avg_us": round(avg_s * 1e6, 3),
-                "flops_per_launch": per_launch}
+                "flops_per_launch": per_launch,
+                "timed_in": head_key + (" (eager pass of the same schedule)" if "batched" in head_key else "")}
     base = None
     if not args.no_cpu_baseline:
         base = cpu_baseline(prob, cfg.alpha, F["total"], args.cpu_budget)
     compare = {p: {"ms_per_step": round(v["ms"], 3), "tflops": round(F["total"] / v["ms"] / 1e9, 4),
-                   "recon_error": v["recon"], "sweeps": v["sweeps"]} for p, v in res.items()}
-    if "fp64" in res and "mixed" in res:
-        compare["speedup_mixed_vs_fp64"] = round(res["fp64"]["ms"] / res["mixed"]["ms"], 4)
-        compare["recon_error_diff"] = abs(res["fp64"]["recon"] - res["mixed"]["recon"])
-        s64, s32 = res["fp64"]["sigma"], res["mixed"]["sigma"]
-        keep = s64 > 1e-6 * s64[0]
-        compare["sigma_rel_diff"] = float(np.max(np.abs(s64[keep] - s32[keep]) / s64[keep]))
+                   "recon_error": v["recon"], "sweeps": v["sweeps"], "tuning": v["tuning"],
+                   "graph_launches_per_step": v["graph_launches_per_step"],
+                   **({"eager_ms_per_step": round(v["eager_ms"], 3), "tune_report": v["tune_report"]}
+                      if "eager_ms" in v else {})}
+               for p, v in res.items()}
+    ref_key = "fp64-plain" if "fp64-plain" in res else None
+    if ref_key:
+        ref = res[ref_key]
+        for k, v in res.items():
+            if k == ref_key:
+                continue
+            compare[f"speedup_{k}_vs_{ref_key}"] = round(ref["ms"] / v["ms"], 4)
+            compare[f"recon_error_diff_{k}"] = abs(ref["recon"] - v["recon"])
+            s64, sx = ref["sigma"], v["sigma"]
+            keep = s64 > 1e-6 * s64[0]
+            compare[f"sigma_rel_diff_{k}"] = float(np.max(np.abs(s64[keep] - sx[keep]) / s64[keep]))
 
     out = {
         "metric": "Ã⁺Y time & TFLOP/s, mixed-precision vs FP64 GPU at equal recon error",
@@ -223,11 +260,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if "mixed" in res else "f64",
+        "dtype": "f32+f64" if head_key.startswith("mixed") else "f64",
         "data": "synthetic",
         "config": {"workload": f"fastpi {cfg.name}: A {m}x{n} ({prob.nnz} nnz, power-law "
                                f"{cfg.gamma}, {cfg.values}), Y {m}x{cfg.L}, alpha {cfg.alpha}",
-                   "precision": "mixed" if "mixed" in res else "fp64", "m": m, "n": n,
+                   "form": head_key, "m": m, "n": n,
                    "nnz": prob.nnz, "L": cfg.L,
                    "alpha": cfg.alpha, "shape": plan.info},
         "flop_model": F,

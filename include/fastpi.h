@@ -70,6 +70,8 @@ typedef struct {
     int32_t block_wgs_per_cu;   /* persistent block-SVD workgroups per compute unit, 1..16         */
     int32_t gram_rows;          /* rows of X per eigensolver partial-Gram workgroup: 64, 128, 256  */
     int32_t inner_sweeps;       /* Jacobi sweeps per 32 x 32 pair solve: 1 or 2                    */
+    int32_t precond;            /* 1: run the core Jacobi on R^T of a pivoted Cholesky G = R^T R  */
+                                /* (fewer sweeps); 0: on G itself                                 */
 } fastpi_tuning;
 
 typedef struct fastpi_plan fastpi_plan;
@@ -208,7 +210,8 @@ int fastpi_apply(fastpi_handle* h, int64_t m, int64_t n, int64_t r, const double
 int fastpi_stage_output(fastpi_handle* h, int which, double* dst, int64_t count);
 
 /*
- * Dense symmetric eigensolver used for the incremental cores (FP64 block Jacobi).
+ * Dense symmetric eigensolver used for the incremental cores (FP64 block Jacobi, started
+ * from a pivoted Cholesky factor of G unless the handle's schedule sets precond = 0).
  *   q    : order; G : device double[q*q] (symmetric, read only);
  *   t    : number of leading eigenpairs wanted (0 < t <= q);
  *   vals : device double[t], descending; vecs : device double[q*t] row-major, column k is
@@ -253,7 +256,7 @@ int64_t fastpi_last_graph_launches(const fastpi_handle* h);
 int fastpi_set_tuning(fastpi_handle* h, const fastpi_tuning* t);
 int fastpi_get_tuning(const fastpi_handle* h, fastpi_tuning* t);
 /*
- * Tuning cache: a text file of "key|block_lds wgs_per_cu gram_rows inner_sweeps" lines, the
+ * Tuning cache: a text file of "key|block_lds wgs_per_cu gram_rows inner_sweeps precond" lines, the
  * key naming the GPU architecture, the precision and the shape bucket (log2 of the number
  * of matrices, of blocks and of the two core orders). Plans uploaded (and batches created)
  * afterwards take a matching entry; fastpi_autotune reads and writes it. NULL clears it.
@@ -261,8 +264,8 @@ int fastpi_get_tuning(const fastpi_handle* h, fastpi_tuning* t);
 int fastpi_set_tuning_cache(fastpi_handle* h, const char* path);
 /*
  * Autotuner: runs the uploaded plan's path with every candidate schedule (three block-SVD
- * LDS/occupancy pairs timed on the block launch alone, then six eigensolver schedules timed
- * over whole runs), keeps the fastest and stores it in the tuning cache when one is set.
+ * LDS/occupancy pairs timed on the block launch alone, then six eigensolver schedules --
+ * partial-Gram height, inner sweeps, preconditioner -- timed over whole runs), keeps the fastest and stores it in the tuning cache when one is set.
  * Arguments as for fastpi_svd (the outputs hold a valid result afterwards). report, when
  * not NULL, receives a one-line summary of the timings (truncated to report_cap bytes).
  * Synchronous. A cache hit skips the trials.

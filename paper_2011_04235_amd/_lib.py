@@ -43,7 +43,7 @@ class Options(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("block_lds", c_int32), ("block_wgs_per_cu", c_int32), ("gram_rows", c_int32),
-                ("inner_sweeps", c_int32)]
+                ("inner_sweeps", c_int32), ("precond", c_int32)]
 
     def as_dict(self):
         return {name: int(getattr(self, name)) for name, _ in self._fields_}

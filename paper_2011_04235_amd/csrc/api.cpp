@@ -44,6 +44,8 @@ struct fastpi_handle {
     size_t sws_bytes = 0;
     int* siws = nullptr;
     size_t siws_bytes = 0;
+    double* sa = nullptr;        // its pivoted-Cholesky scratch (the caller's G stays intact)
+    size_t sa_bytes = 0;
     int32_t syev_sweeps = 0;
     KernelTimer timer;
     // rank-predictor scratch
@@ -135,6 +137,7 @@ Tuning from_c(const fastpi_tuning& t) {
     o.block_wgs_per_cu = t.block_wgs_per_cu;
     o.gram_rows = t.gram_rows;
     o.inner_sweeps = t.inner_sweeps;
+    o.precond = t.precond;
     return o;
 }
 
@@ -143,6 +146,7 @@ void to_c(const Tuning& t, fastpi_tuning* o) {
     o->block_wgs_per_cu = t.block_wgs_per_cu;
     o->gram_rows = t.gram_rows;
     o->inner_sweeps = t.inner_sweeps;
+    o->precond = t.precond;
 }
 
 void copy_report(const std::string& rep, char* out, int64_t cap) {
@@ -353,6 +357,7 @@ void fastpi_destroy(fastpi_handle* h) {
     if (h->aws) hipFree(h->aws);
     if (h->sws) hipFree(h->sws);
     if (h->siws) hipFree(h->siws);
+    if (h->sa) hipFree(h->sa);
     if (h->mws) hipFree(h->mws);
     if (h->status) hipFree(h->status);
     if (h->host_pinned) hipHostFree(h->host_pinned);
@@ -460,9 +465,15 @@ int fastpi_syev_top(fastpi_handle* h, int64_t q, const double* G, int64_t t, dou
     if (st != FASTPI_OK) return st;
     if ((st = grow(h->siws, h->siws_bytes, eig_job_ints(q) * sizeof(int), h->stream, "eigensolver")) != FASTPI_OK)
         return st;
+    const bool precond = h->grp.tune.precond != 0;
+    if (precond &&
+        (st = grow(h->sa, h->sa_bytes, static_cast<size_t>(q * q) * sizeof(double), h->stream, "eigensolver")) !=
+            FASTPI_OK)
+        return st;
     EigSet es;
-    std::vector<EigJob> jobs{eig_make_job(G, q, t, vals, vecs, h->sws, h->siws, nullptr, h->opts.tol, rows, 0)};
-    if ((st = eig_set_create(es, jobs, rows, h->stream)) != FASTPI_OK) {
+    std::vector<EigJob> jobs{eig_make_job(G, precond ? h->sa : nullptr, q, t, vals, vecs, h->sws, h->siws, nullptr,
+                                          h->opts.tol, rows, 0)};
+    if ((st = eig_set_create(es, jobs, rows, precond, h->stream)) != FASTPI_OK) {
         eig_set_free(es);
         set_error("eigensolver allocation failed");
         return st;

@@ -104,7 +104,7 @@ constexpr int kMinGramRows = 64;
 bool tuning_valid(const Tuning& t) {
     return t.block_lds >= 4096 && t.block_lds <= 60 * 1024 && t.block_wgs_per_cu >= 1 &&
            t.block_wgs_per_cu <= 16 && eig_gram_rows_valid(t.gram_rows) &&
-           (t.inner_sweeps == 1 || t.inner_sweeps == 2);
+           (t.inner_sweeps == 1 || t.inner_sweeps == 2) && (t.precond == 0 || t.precond == 1);
 }
 
 void instance_free(Instance& I, hipStream_t st) {
@@ -253,14 +253,15 @@ static int build_sets(Group& g, hipStream_t st) {
         double* ws = I.ws;
         const int64_t q3 = d.s + d.n2;
         if (d.n1 > 0 && d.s > 0)
-            j2.push_back(eig_make_job(ws + I.o_g2, d.n1, d.s, ws + I.o_lam2, ws + I.o_v2, ws + I.o_eig, I.iws,
+            j2.push_back(eig_make_job(ws + I.o_g2, ws + I.o_g2, d.n1, d.s, ws + I.o_lam2, ws + I.o_v2, ws + I.o_eig, I.iws,
                                       I.status, 0.0, g.tune.gram_rows, static_cast<int>(i)));
         if (q3 > 0 && d.r > 0)
-            j3.push_back(eig_make_job(ws + I.o_g3, q3, d.r, ws + I.o_lam3, ws + I.o_vt, ws + I.o_eig, I.iws,
+            j3.push_back(eig_make_job(ws + I.o_g3, ws + I.o_g3, q3, d.r, ws + I.o_lam3, ws + I.o_vt, ws + I.o_eig, I.iws,
                                       I.status, 0.0, g.tune.gram_rows, static_cast<int>(i)));
     }
-    int rc = eig_set_create(g.set2, j2, g.tune.gram_rows, st);
-    if (rc == FASTPI_OK) rc = eig_set_create(g.set3, j3, g.tune.gram_rows, st);
+    // the cores are rebuilt by every run, so the factorisation may overwrite them
+    int rc = eig_set_create(g.set2, j2, g.tune.gram_rows, g.tune.precond != 0, st);
+    if (rc == FASTPI_OK) rc = eig_set_create(g.set3, j3, g.tune.gram_rows, g.tune.precond != 0, st);
     if (rc != FASTPI_OK) set_error("eigensolver set allocation failed");
     return rc;
 }
@@ -332,7 +333,7 @@ int group_set_tuning(Group& g, const Tuning& t, hipStream_t st) {
         set_error("invalid schedule parameters");
         return FASTPI_EINVAL;
     }
-    const bool resize = t.gram_rows != g.tune.gram_rows;
+    const bool resize = t.gram_rows != g.tune.gram_rows || t.precond != g.tune.precond;
     g.tune = t;
     group_drop_graphs(g);
     if (resize && !g.inst.empty()) {
@@ -584,7 +585,8 @@ int tuning_lookup(const Group& g, const char* cache, int device, bool mixed, Tun
         if (bar == std::string::npos || line.substr(0, bar) != key) continue;
         std::istringstream v(line.substr(bar + 1));
         Tuning t;
-        if (v >> t.block_lds >> t.block_wgs_per_cu >> t.gram_rows >> t.inner_sweeps && tuning_valid(t)) {
+        if (v >> t.block_lds >> t.block_wgs_per_cu >> t.gram_rows >> t.inner_sweeps >> t.precond &&
+            tuning_valid(t)) {
             out = t;
             found = 1;   // the last matching line wins
         }
@@ -611,7 +613,7 @@ static int store_tuning(const Group& g, const char* cache, int device, bool mixe
     }
     for (const std::string& l : keep) o << l << '\n';
     o << key << '|' << t.block_lds << ' ' << t.block_wgs_per_cu << ' ' << t.gram_rows << ' ' << t.inner_sweeps
-      << '\n';
+      << ' ' << t.precond << '\n';
     return FASTPI_OK;
 }
 
@@ -667,37 +669,36 @@ int group_autotune(Group& g, const double* const* val, double* const* U, double*
             }
         }
         if (rc != FASTPI_OK) break;
-        // 2) eigensolver: partial-Gram height and inner sweeps, timed over whole runs (the
-        // inner sweeps change the number of outer sweeps)
+        // 2) eigensolver: partial-Gram height, inner sweeps and the preconditioner, timed
+        // over whole runs (the inner sweeps and the start change the number of outer sweeps)
         best_ms = 1e30f;
         Tuning eig_best = best;
-        for (int rows : {64, 128, 256}) {
-            for (int inner : {1, 2}) {
-                Tuning cand = best;
-                cand.gram_rows = rows;
-                cand.inner_sweeps = inner;
-                if ((rc = group_set_tuning(g, cand, st)) != FASTPI_OK) break;
-                hipEventRecord(e0, st);
-                if ((rc = group_svd(g, val, U, S, V, c)) != FASTPI_OK) break;
-                hipEventRecord(e1, st);
-                float ms = 0;
-                if (!elapsed(ms)) {
-                    rc = FASTPI_EHIP;
-                    break;
-                }
-                rep << "eig rows=" << rows << " inner=" << inner << " " << ms << " ms; ";
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    eig_best = cand;
-                }
+        const int cand_eig[][3] = {{64, 1, 1}, {128, 1, 1}, {256, 1, 1}, {128, 2, 1}, {128, 1, 0}, {64, 1, 0}};
+        for (const auto& ce : cand_eig) {
+            Tuning cand = best;
+            cand.gram_rows = ce[0];
+            cand.inner_sweeps = ce[1];
+            cand.precond = ce[2];
+            if ((rc = group_set_tuning(g, cand, st)) != FASTPI_OK) break;
+            hipEventRecord(e0, st);
+            if ((rc = group_svd(g, val, U, S, V, c)) != FASTPI_OK) break;
+            hipEventRecord(e1, st);
+            float ms = 0;
+            if (!elapsed(ms)) {
+                rc = FASTPI_EHIP;
+                break;
             }
-            if (rc != FASTPI_OK) break;
+            rep << "eig rows=" << ce[0] << " inner=" << ce[1] << " precond=" << ce[2] << " " << ms << " ms; ";
+            if (ms < best_ms) {
+                best_ms = ms;
+                eig_best = cand;
+            }
         }
         if (rc != FASTPI_OK) break;
         best = eig_best;
         if ((rc = group_set_tuning(g, best, st)) != FASTPI_OK) break;
         rep << "chose lds=" << best.block_lds << " wgs/cu=" << best.block_wgs_per_cu << " rows=" << best.gram_rows
-            << " inner=" << best.inner_sweeps;
+            << " inner=" << best.inner_sweeps << " precond=" << best.precond;
         if (cache) rc = store_tuning(g, cache, device, c.mixed, best);
     } while (false);
     hipEventDestroy(e0);

@@ -19,6 +19,7 @@ struct Tuning {
     int block_wgs_per_cu = 4;    // persistent block-SVD workgroups per compute unit
     int gram_rows = 128;         // rows per partial-Gram workgroup in the eigensolver
     int inner_sweeps = 1;        // inner Jacobi sweeps per pair solve
+    int precond = 1;             // pivoted-Cholesky start of the core eigensolvers
 };
 bool tuning_valid(const Tuning& t);
 

@@ -64,13 +64,14 @@ __global__ void k_eig_norms(const EigJob* __restrict__ jobs) {
         acc += v * v;
     }
     acc = wave_sum(acc);
-    if (lane == 0) J.lam[c] = (c < J.q && isfinite(acc)) ? sqrt(acc) : -DBL_MAX;
+    if (lane == 0) J.lam[c] = (c < J.q && isfinite(acc)) ? (J.squared ? acc : sqrt(acc)) : -DBL_MAX;
 }
 
-// lam[ld] = (ld eps)^2 ld max_c ||G_c||^2: columns of X = G V whose squared norm is below
-// it are rounding noise of a (numerically) zero eigenvalue -- ||x_c|| = lambda_c, whose
-// rounding level is ~ ld eps lambda_1, and lambda_1 <= sqrt(ld) max_c ||G_c|| -- and are
-// treated as converged (their cosines with anything are meaningless).
+// lam[ld] = (ld eps)^2 ld max_c ||x_c||^2 over the starting columns: columns of X whose
+// squared norm is below it are rounding noise of a (numerically) zero eigenvalue and are
+// treated as converged (their cosines with anything are meaningless). For X = G V,
+// ||x_c|| = lambda_c, whose rounding level is ~ ld eps lambda_1 with lambda_1 <=
+// sqrt(ld) max_c ||G_c||; for X = R^T the columns are at most as large.
 __global__ __launch_bounds__(256) void k_eig_floor(const EigJob* __restrict__ jobs) {
     const EigJob& J = jobs[blockIdx.x];
     __shared__ double red[256];
@@ -84,7 +85,8 @@ __global__ __launch_bounds__(256) void k_eig_floor(const EigJob* __restrict__ jo
     }
     if (threadIdx.x == 0) {
         const double e = static_cast<double>(J.ld) * DBL_EPSILON;
-        J.lam[J.ld] = isfinite(red[0]) ? e * e * static_cast<double>(J.ld) * red[0] * red[0] : 0.0;
+        const double mx2 = J.squared ? red[0] : red[0] * red[0];   // largest squared column norm
+        J.lam[J.ld] = isfinite(red[0]) ? e * e * static_cast<double>(J.ld) * mx2 : 0.0;
     }
 }
 
@@ -106,10 +108,20 @@ __global__ __launch_bounds__(256) void k_eig_gram(const EigJob* __restrict__ job
     const int64_t r0 = static_cast<int64_t>(ch) * ROWS;
     const int nr = static_cast<int>(min<int64_t>(ROWS, ld - r0));
     const double* X = J.X;
-    for (int e = threadIdx.x; e < ROWS * PW; e += blockDim.x) {
+    // all loads of the tile in flight at once, then the LDS stores
+    constexpr int PER = ROWS * PW / 256;
+    double v[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = threadIdx.x + k * 256;
         const int c = e / ROWS, r = e % ROWS;
         const int col = c < BW ? bi * BW + c : bj * BW + (c - BW);
-        Y[r][c] = (r < nr && (c < BW || hasJ)) ? X[static_cast<int64_t>(col) * ld + r0 + r] : 0.0;
+        v[k] = (r < nr && (c < BW || hasJ)) ? X[static_cast<int64_t>(col) * ld + r0 + r] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = threadIdx.x + k * 256;
+        Y[e % ROWS][e / ROWS] = v[k];
     }
     __syncthreads();
     const int a = threadIdx.x / 8, b0 = (threadIdx.x % 8) * 4;
@@ -195,10 +207,33 @@ __global__ __launch_bounds__(256) void k_eig_solve(const EigJob* __restrict__ jo
     const int nchunk = J.nchunk;
     const double tol = J.tol;
     const double* Hp = J.Hpart + static_cast<int64_t>(pair) * nchunk * (PW * PW);
-    for (int e = threadIdx.x; e < PW * PW; e += 256) {
-        double acc = 0;
-        for (int c = 0; c < nchunk; ++c) acc += Hp[static_cast<int64_t>(c) * PW * PW + e];
-        Hs[0][e / PW][e % PW] = acc;
+    {
+        // H = sum of the partial Grams in chunk order; four chunks' loads in flight at once
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        int c = 0;
+        for (; c + 4 <= nchunk; c += 4) {
+            double v[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) v[u][k] = Hp[static_cast<int64_t>(c + u) * PW * PW + threadIdx.x + k * 256];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) acc[k] += v[u][k];
+        }
+        for (; c < nchunk; ++c) {
+            double v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = Hp[static_cast<int64_t>(c) * PW * PW + threadIdx.x + k * 256];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[k] += v[k];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int e = threadIdx.x + k * 256;
+            Hs[0][e / PW][e % PW] = acc[k];
+        }
     }
     if (threadIdx.x == 0) s_need = 0;
     __syncthreads();
@@ -299,7 +334,16 @@ __global__ __launch_bounds__(UPD_ROWS) void k_eig_update(const EigJob* __restric
     round_robin_pair(round, pair, J.nbe, bi, bj);
     const bool hasJ = bj < J.nblk;
     const double* Wg = J.W + static_cast<int64_t>(pair) * PW * PW;
-    for (int e = threadIdx.x; e < PW * PW; e += blockDim.x) W[e / PW][e % PW] = Wg[e];
+    {
+        double v[PW * PW / UPD_ROWS];
+#pragma unroll
+        for (int k = 0; k < PW * PW / UPD_ROWS; ++k) v[k] = Wg[threadIdx.x + k * UPD_ROWS];
+#pragma unroll
+        for (int k = 0; k < PW * PW / UPD_ROWS; ++k) {
+            const int e = threadIdx.x + k * UPD_ROWS;
+            W[e / PW][e % PW] = v[k];
+        }
+    }
     __syncthreads();
     const int64_t ld = J.ld;
     const int64_t r = static_cast<int64_t>(rb) * UPD_ROWS + threadIdx.x;
@@ -372,7 +416,7 @@ __global__ void k_eig_output(const EigJob* __restrict__ jobs) {
         const int64_t r = e / J.t, k = e % J.t;
         const int oc = J.order[k];
         const double l = J.lam[oc];
-        const double inv = l > 0 ? 1.0 / l : 0.0;
+        const double inv = l > 0 ? (J.squared ? 1.0 / sqrt(l) : 1.0 / l) : 0.0;
         J.vecs[e] = J.X[static_cast<int64_t>(oc) * J.ld + r] * inv;
         if (r == 0) J.vals[k] = l > 0 ? l : 0.0;
     }
@@ -409,11 +453,12 @@ size_t eig_job_ints(int64_t q) {
     return static_cast<size_t>(npairs + ld + 32);
 }
 
-EigJob eig_make_job(const double* G, int64_t q, int64_t t, double* vals, double* vecs,
+EigJob eig_make_job(const double* G, double* A, int64_t q, int64_t t, double* vals, double* vecs,
                     double* ws, int* iws, int* status, double tol, int gram_rows, int tag) {
     EigJob J{};
     job_shape(q, gram_rows, J.ld, J.nblk, J.nbe, J.npairs, J.nchunk, J.nupd);
     J.G = G;
+    J.A = A;
     J.vals = vals;
     J.vecs = vecs;
     J.q = q;
@@ -434,13 +479,18 @@ void eig_set_free(EigSet& es) {
     if (es.jobs) hipFree(es.jobs);
     if (es.pre) hipFree(es.pre);
     if (es.state) hipFree(es.state);
+    if (es.pstate) hipFree(es.pstate);
     if (es.host_state) hipHostFree(es.host_state);
     es = EigSet{};
 }
 
-int eig_set_create(EigSet& es, std::vector<EigJob> jobs, int gram_rows, hipStream_t st) {
+int eig_set_create(EigSet& es, std::vector<EigJob> jobs, int gram_rows, bool precond, hipStream_t st) {
     eig_set_free(es);
     es.gram_rows = gram_rows;
+    for (const EigJob& J : jobs)
+        if (!J.A) precond = false;
+    es.precond = precond ? 1 : 0;
+    for (EigJob& J : jobs) J.squared = es.precond;
     std::stable_sort(jobs.begin(), jobs.end(),
                      [](const EigJob& x, const EigJob& y) { return x.nbe > y.nbe; });
     const int nj = static_cast<int>(jobs.size());
@@ -455,6 +505,7 @@ int eig_set_create(EigSet& es, std::vector<EigJob> jobs, int gram_rows, hipStrea
         pre[(nj + 1) + j + 1] = pre[(nj + 1) + j] + J.npairs;
         pre[2 * (nj + 1) + j + 1] = pre[2 * (nj + 1) + j] + J.npairs * J.nupd;
         es.max_ld = std::max(es.max_ld, J.ld);
+        es.max_q = std::max(es.max_q, J.q);
     }
     for (int t = 0; t < es.rounds; ++t) {
         int na = 0;
@@ -471,6 +522,8 @@ int eig_set_create(EigSet& es, std::vector<EigJob> jobs, int gram_rows, hipStrea
     es.pre = static_cast<int*>(p);
     if (hipMalloc(&p, sizeof(int) * (ST_WORDS * nj + ST_WORDS)) != hipSuccess) return FASTPI_ENOMEM;
     es.state = static_cast<int*>(p);
+    if (hipMalloc(&p, sizeof(int) * (2 * nj + 2)) != hipSuccess) return FASTPI_ENOMEM;
+    es.pstate = static_cast<int*>(p);
     if (hipHostMalloc(&p, sizeof(int) * (ST_WORDS * nj + ST_WORDS), hipHostMallocDefault) != hipSuccess)
         return FASTPI_ENOMEM;
     es.host_state = static_cast<int*>(p);
@@ -488,8 +541,12 @@ void eig_begin(const EigSet& es, hipStream_t st) {
     if (es.njobs == 0) return;
     const unsigned nj = static_cast<unsigned>(es.njobs);
     launch_fill_i32(es.state, ST_WORDS * es.njobs + ST_WORDS, 0, st);
-    const unsigned gx = static_cast<unsigned>(std::min<int64_t>((es.max_ld * es.max_ld + 255) / 256, 4096));
-    hipLaunchKernelGGL(k_eig_init, dim3(gx, nj), dim3(256), 0, st, es.jobs);
+    if (es.precond) {
+        pchol_run(es, st);
+    } else {
+        const unsigned gx = static_cast<unsigned>(std::min<int64_t>((es.max_ld * es.max_ld + 255) / 256, 4096));
+        hipLaunchKernelGGL(k_eig_init, dim3(gx, nj), dim3(256), 0, st, es.jobs);
+    }
     hipLaunchKernelGGL(k_eig_norms, dim3(static_cast<unsigned>((es.max_ld + 3) / 4), nj), dim3(256), 0, st,
                        es.jobs);
     hipLaunchKernelGGL(k_eig_floor, dim3(nj), dim3(256), 0, st, es.jobs);

@@ -87,6 +87,7 @@ void launch_copy(const double* src, int64_t n, double* dst, hipStream_t st);
 // problems ("jobs") that advance together, one launch per kernel and round for all jobs.
 struct EigJob {
     const double* G;    // q x q row-major input
+    double* A;          // q x q scratch of the pivoted Cholesky (may be G itself), or null
     double* vals;       // t eigenvalues, descending
     double* vecs;       // q x t row-major eigenvectors
     double* X;          // ld x ld column-major iterate
@@ -99,6 +100,8 @@ struct EigJob {
     double tol;         // cosine threshold of the outer pairs
     int64_t q, t, ld;
     int nblk, nbe, npairs, nchunk, nupd, tag;
+    int squared;        // X = R^T of a pivoted Cholesky: eigenvalues are squared column norms
+    int pad;
 };
 struct EigSet {
     int njobs = 0, rounds = 0, gram_rows = 128;
@@ -108,17 +111,23 @@ struct EigSet {
     int* state = nullptr;         // device, per job {rotations, done, sweeps, capped}, then
                                   // the all-done word
     int* host_state = nullptr;    // pinned mirror of state
+    int* pstate = nullptr;        // device, per job {pivots taken, factorisation done}
+    int precond = 0;              // start from the pivoted Cholesky factor instead of G
     std::vector<EigJob> host;     // host copy, same order
     std::vector<int> nact, g_gram, g_solve, g_upd;   // per round: active jobs and grids
-    int64_t max_ld = 0;
+    int64_t max_ld = 0, max_q = 0;
 };
 int64_t eig_padded_order(int64_t q);
 int eig_gram_rows_valid(int rows);
 size_t eig_job_doubles(int64_t q, int gram_rows);
 size_t eig_job_ints(int64_t q);
-EigJob eig_make_job(const double* G, int64_t q, int64_t t, double* vals, double* vecs,
+// A: writable q x q scratch for the pivoted-Cholesky preconditioner (may alias G), or null
+EigJob eig_make_job(const double* G, double* A, int64_t q, int64_t t, double* vals, double* vecs,
                     double* ws, int* iws, int* status, double tol, int gram_rows, int tag);
-int eig_set_create(EigSet& es, std::vector<EigJob> jobs, int gram_rows, hipStream_t st);
+// precond: factor every job's G first (every job needs A) and iterate on R^T
+int eig_set_create(EigSet& es, std::vector<EigJob> jobs, int gram_rows, bool precond, hipStream_t st);
+// pivoted Cholesky of every job of the set into its X (pchol.hip)
+void pchol_run(const EigSet& es, hipStream_t st);
 void eig_set_free(EigSet& es);
 void eig_begin(const EigSet& es, hipStream_t st);
 void eig_sweep(const EigSet& es, int max_sweeps, int inner_sweeps, hipStream_t st,

@@ -1,0 +1,220 @@
+// Preconditioner of the core eigensolver: Cholesky factorisation with diagonal pivoting of
+// the positive semidefinite core G, G = R^T R, computed in the original index order (row j
+// of R is the j-th pivot step; its entries at indices pivoted earlier are zero). One-sided
+// Jacobi then runs on the columns of X = R^T instead of on G: R^T R = G, so the columns
+// converge to u_c sqrt(lambda_c) with u_c the eigenvectors of G, and lambda_c = ||x_c||^2.
+// Pivoting on the largest remaining diagonal makes R strongly graded and R^T close to
+// orthogonal columns scaled by the pivots, so far fewer Jacobi sweeps are needed than on G
+// itself (the pivoted-QR preconditioning of one-sided Jacobi, applied through the Gram
+// matrix). The factorisation stops when the largest remaining diagonal falls below
+// (ld eps)^2 of the largest initial one; the columns past that point stay zero and the
+// neglected trailing part is far below the rounding level of G.
+//
+// Blocked by panels of PB pivot steps: one workgroup per job factors a panel (each step:
+// arg-max of the remaining diagonal, then the new column from the trailing matrix minus the
+// panel's earlier columns), and a tiled kernel subtracts the panel's outer product from the
+// trailing matrix. Every thread owns fixed rows (i = tid + k * PT), so it only re-reads
+// global values it wrote itself; the only cross-thread data (the pivot and the pivot row's
+// panel entries) goes through LDS.
+#include <cfloat>
+
+#include "device_common.h"
+#include "kernels.h"
+
+namespace fastpi {
+
+constexpr int PB = 16;      // pivot steps per panel
+constexpr int PT = 1024;    // threads of the panel kernel
+constexpr int UT = 64;      // trailing-update tile
+
+__global__ void k_pchol_init(const EigJob* __restrict__ jobs, int* __restrict__ pstate) {
+    const int jb = blockIdx.y;
+    const EigJob& J = jobs[jb];
+    const int64_t q = J.q, ld = J.ld;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    const int64_t t0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (int64_t e = t0; e < ld * ld; e += stride) J.X[e] = 0.0;
+    if (J.A != J.G)
+        for (int64_t e = t0; e < q * q; e += stride) J.A[e] = J.G[e];
+    double* d = J.Hpart;
+    for (int64_t i = t0; i < q; i += stride) d[i] = J.G[i * q + i];
+    if (t0 == 0) {
+        pstate[2 * jb] = 0;
+        pstate[2 * jb + 1] = 0;
+    }
+}
+
+// (value, index) arg-max with ties to the lower index
+__device__ __forceinline__ void better(double& v, int& i, double ov, int oi) {
+    if (ov > v || (ov == v && oi < i)) {
+        v = ov;
+        i = oi;
+    }
+}
+
+__global__ __launch_bounds__(PT) void k_pchol_panel(const EigJob* __restrict__ jobs, int* __restrict__ pstate,
+                                                    int j0) {
+    const int jb = blockIdx.x;
+    const EigJob& J = jobs[jb];
+    const int q = static_cast<int>(J.q);
+    if (j0 >= q || pstate[2 * jb + 1]) return;
+    const int64_t ld = J.ld;
+    double* X = J.X;
+    const double* A = J.A;
+    double* d = J.Hpart;
+    __shared__ double s_v[PT / kWave];
+    __shared__ int s_i[PT / kWave];
+    __shared__ double s_piv[PB];
+    __shared__ double s_dp, s_floor;
+    __shared__ int s_p;
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+
+    if (j0 == 0) {
+        // stop threshold from the largest initial diagonal
+        double mx = 0.0;
+        for (int i = threadIdx.x; i < q; i += PT) mx = d[i] > mx ? d[i] : mx;
+        mx = wave_max(mx);
+        if (lane == 0) s_v[wave] = mx;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double m = 0.0;
+            for (int w = 0; w < PT / kWave; ++w) m = s_v[w] > m ? s_v[w] : m;
+            const double e = static_cast<double>(ld) * DBL_EPSILON;
+            J.lam[ld + 1] = e * e * m;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) s_floor = J.lam[ld + 1];
+    const int j1 = min(q, j0 + PB);
+    for (int j = j0; j < j1; ++j) {
+        // pivot: the largest remaining diagonal (pivoted indices hold -DBL_MAX)
+        double bv = -DBL_MAX;
+        int bi = q;
+        for (int i = threadIdx.x; i < q; i += PT) better(bv, bi, d[i], i);
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(bv, off, kWave);
+            const int oi = __shfl_xor(bi, off, kWave);
+            better(bv, bi, ov, oi);
+        }
+        if (lane == 0) {
+            s_v[wave] = bv;
+            s_i[wave] = bi;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double v = s_v[0];
+            int ix = s_i[0];
+            for (int w = 1; w < PT / kWave; ++w) better(v, ix, s_v[w], s_i[w]);
+            s_p = ix;
+            s_dp = v;
+        }
+        __syncthreads();
+        const int p = s_p;
+        const double dp = s_dp;
+        if (!(dp > s_floor) || p >= q) {
+            if (threadIdx.x == 0) {
+                pstate[2 * jb] = j;       // rank found
+                pstate[2 * jb + 1] = 1;   // done
+            }
+            return;
+        }
+        // the pivot row's entries in this panel's earlier columns (written by its owner)
+        if (threadIdx.x == p % PT)
+            for (int l = j0; l < j; ++l) s_piv[l - j0] = X[p + ld * l];
+        __syncthreads();
+        const double r = sqrt(dp);
+        const double rinv = 1.0 / r;
+        const double* Ap = A + static_cast<int64_t>(p) * q;   // column p of the symmetric A
+        for (int i = threadIdx.x; i < q; i += PT) {
+            const double di = d[i];
+            double x;
+            if (i == p) {
+                x = r;
+                d[i] = -DBL_MAX;
+            } else if (di == -DBL_MAX) {
+                x = 0.0;
+            } else {
+                double s = Ap[i];
+                for (int l = j0; l < j; ++l) s -= X[i + ld * l] * s_piv[l - j0];
+                x = s * rinv;
+                d[i] = di - x * x;
+            }
+            X[i + ld * j] = x;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        pstate[2 * jb] = j1;
+        if (j1 >= q) pstate[2 * jb + 1] = 1;
+    }
+}
+
+// A -= X[:, j0:j0+PB] X[:, j0:j0+PB]^T over the job's q x q trailing matrix (64 x 64 tiles).
+// Skipped once the factorisation is done (no later panel reads A).
+__global__ __launch_bounds__(256) void k_pchol_update(const EigJob* __restrict__ jobs,
+                                                      const int* __restrict__ pstate, int j0) {
+    const int jb = blockIdx.y;
+    const EigJob& J = jobs[jb];
+    const int64_t q = J.q;
+    if (j0 >= q || pstate[2 * jb + 1]) return;
+    const int tiles = static_cast<int>((q + UT - 1) / UT);
+    if (static_cast<int>(blockIdx.x) >= tiles * tiles) return;
+    const int64_t i0 = static_cast<int64_t>(blockIdx.x % tiles) * UT;
+    const int64_t c0 = static_cast<int64_t>(blockIdx.x / tiles) * UT;
+    const int64_t ld = J.ld;
+    const double* X = J.X;
+    __shared__ double Xi[PB][UT + 1];
+    __shared__ double Xc[PB][UT + 1];
+    for (int e = threadIdx.x; e < PB * UT; e += 256) {
+        const int l = e / UT, t = e % UT;
+        Xi[l][t] = (i0 + t < q) ? X[i0 + t + ld * (j0 + l)] : 0.0;
+        Xc[l][t] = (c0 + t < q) ? X[c0 + t + ld * (j0 + l)] : 0.0;
+    }
+    __syncthreads();
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    double acc[4][4] = {};
+#pragma unroll
+    for (int l = 0; l < PB; ++l) {
+        double a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a[u] = Xi[l][tx * 4 + u];
+            b[u] = Xc[l][ty * 4 + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+    }
+    // A is symmetric and addressed as A[i + q c]; consecutive threads take consecutive i
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int64_t c = c0 + ty * 4 + v;
+        if (c >= q) continue;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = i0 + tx * 4 + u;
+            if (i < q) J.A[i + q * c] -= acc[u][v];
+        }
+    }
+}
+
+int pchol_panels(int64_t max_q) { return static_cast<int>((max_q + PB - 1) / PB); }
+
+void pchol_run(const EigSet& es, hipStream_t st) {
+    if (es.njobs == 0) return;
+    const unsigned nj = static_cast<unsigned>(es.njobs);
+    const unsigned gx = static_cast<unsigned>(std::min<int64_t>((es.max_ld * es.max_ld + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_pchol_init, dim3(gx, nj), dim3(256), 0, st, es.jobs, es.pstate);
+    const int64_t tiles = (es.max_q + UT - 1) / UT;
+    const unsigned tgrid = static_cast<unsigned>(tiles * tiles);
+    const int panels = pchol_panels(es.max_q);
+    for (int pnl = 0; pnl < panels; ++pnl) {
+        const int j0 = pnl * PB;
+        hipLaunchKernelGGL(k_pchol_panel, dim3(nj), dim3(PT), 0, st, es.jobs, es.pstate, j0);
+        if (pnl + 1 < panels) hipLaunchKernelGGL(k_pchol_update, dim3(tgrid, nj), dim3(256), 0, st, es.jobs, es.pstate, j0);
+    }
+}
+
+}  // namespace fastpi
