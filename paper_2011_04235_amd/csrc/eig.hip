@@ -27,7 +27,7 @@ namespace fastpi {
 
 constexpr int BW = 16;
 constexpr int PW = 2 * BW;         // columns in a pair
-constexpr int UPD_ROWS = 256;      // rows per update workgroup
+constexpr int UPD_ROWS = 128;      // rows per update workgroup
 constexpr int ST_ROT = 0, ST_DONE = 1, ST_SWEEPS = 2, ST_CAPPED = 3, ST_WORDS = 4;
 
 // largest j < nact with pre[j] <= bid (the job owning flattened workgroup bid)
@@ -90,12 +90,17 @@ __global__ __launch_bounds__(256) void k_eig_floor(const EigJob* __restrict__ jo
     }
 }
 
-// Partial Gram of one pair over one row chunk of X.
+// Partial Gram of one pair over one row chunk of X. Wave w accumulates the 32 x 32 product
+// over a quarter of the chunk's rows in 4 x 4 register blocks (lane -> block); the four wave
+// partials are then summed in wave order.
 template <int ROWS>
 __global__ __launch_bounds__(256) void k_eig_gram(const EigJob* __restrict__ jobs,
                                                   const int* __restrict__ pre, int nact,
                                                   const int* __restrict__ state, int round) {
-    __shared__ double Y[ROWS][PW + 1];
+    constexpr int YS = ROWS * (PW + 1);
+    constexpr int RS = 4 * PW * PW;
+    __shared__ double smem[YS > RS ? YS : RS];
+    double (*Y)[PW + 1] = reinterpret_cast<double (*)[PW + 1]>(smem);
     const int j = job_of(pre, nact, blockIdx.x);
     if (state[ST_WORDS * j + ST_DONE]) return;
     const EigJob& J = jobs[j];
@@ -124,20 +129,35 @@ __global__ __launch_bounds__(256) void k_eig_gram(const EigJob* __restrict__ job
         Y[e % ROWS][e / ROWS] = v[k];
     }
     __syncthreads();
-    const int a = threadIdx.x / 8, b0 = (threadIdx.x % 8) * 4;
-    double acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
-    for (int r = 0; r < nr; ++r) {
-        const double ya = Y[r][a];
-        acc0 += ya * Y[r][b0];
-        acc1 += ya * Y[r][b0 + 1];
-        acc2 += ya * Y[r][b0 + 2];
-        acc3 += ya * Y[r][b0 + 3];
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const int ra = (lane / 8) * 4, cb = (lane % 8) * 4;
+    double acc[4][4] = {};
+    constexpr int QR = ROWS / 4;
+    for (int r = wave * QR; r < wave * QR + QR; ++r) {
+        double x[4], y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            x[u] = Y[r][ra + u];
+            y[u] = Y[r][cb + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int w = 0; w < 4; ++w) acc[u][w] += x[u] * y[w];
     }
-    double* Hp = J.Hpart + (static_cast<int64_t>(pair) * J.nchunk + ch) * (PW * PW) + a * PW + b0;
-    Hp[0] = acc0;
-    Hp[1] = acc1;
-    Hp[2] = acc2;
-    Hp[3] = acc3;
+    __syncthreads();   // Y is reused for the wave partials
+    double* part = smem + wave * PW * PW;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) part[(ra + u) * PW + cb + w] = acc[u][w];
+    __syncthreads();
+    double* Hp = J.Hpart + (static_cast<int64_t>(pair) * J.nchunk + ch) * (PW * PW);
+#pragma unroll
+    for (int k = 0; k < PW * PW / 256; ++k) {
+        const int e = threadIdx.x + k * 256;
+        Hp[e] = ((smem[e] + smem[PW * PW + e]) + smem[2 * PW * PW + e]) + smem[3 * PW * PW + e];
+    }
 }
 
 // Rotation of the symmetric 2x2 [[hpp, hpq], [hpq, hqq]] for the inner sweeps, in FP64 but
@@ -155,11 +175,16 @@ __device__ __forceinline__ double rsq_nr(double x) {
     y = y * (1.5 - 0.5 * x * y * y);
     return y * (1.5 - 0.5 * x * y * y);
 }
-__device__ __forceinline__ void fast_rotation(double hpp, double hqq, double hpq, double& c, double& s) {
-    c = 1.0;
-    s = 0.0;
-    const double ahpq = fabs(hpq);
-    if (hpq == 0.0 || !(ahpq * ahpq > 0.25 * DBL_EPSILON * DBL_EPSILON * fabs(hpp) * fabs(hqq))) return;
+// 1/sqrt(x) from the hardware estimate (relative error ~2^-24) with one third-order
+// correction y (1 + e/2 + 3e^2/8), e = 1 - x y^2: error O(e^3), to FP64 rounding, in four
+// dependent operations instead of the eight of two Newton steps.
+__device__ __forceinline__ double rsq3(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-(x * y), y, 1.0);
+    const double p = fma(0.375, e, 0.5);
+    return fma(y * e, p, y);
+}
+__device__ __forceinline__ void rutishauser_rotation(double hpp, double hqq, double hpq, double& c, double& s) {
     const double zeta = (hqq - hpp) * rcp_nr(2.0 * hpq);
     const double az = fabs(zeta);
     double t;
@@ -172,6 +197,27 @@ __device__ __forceinline__ void fast_rotation(double hpp, double hqq, double hpq
     if (zeta < 0) t = -t;
     c = rsq_nr(1.0 + t * t);
     s = c * t;
+}
+// The same (smaller) rotation from the double angle, with a shorter dependency chain: for
+// d = hqq - hpp and r = sqrt(d^2 + 4 hpq^2), cos 2theta = |d| / r in [0, 1], so
+// c^2 = (1 + cos 2theta) / 2 and s = sign(d) hpq / (r c) (sign(0) = +1), c^2 + s^2 = 1.
+// Falls back to the tangent form when d^2 + 4 hpq^2 leaves the normal range.
+__device__ __forceinline__ void fast_rotation(double hpp, double hqq, double hpq, double& c, double& s) {
+    c = 1.0;
+    s = 0.0;
+    const double ahpq = fabs(hpq);
+    if (hpq == 0.0 || !(ahpq * ahpq > 0.25 * DBL_EPSILON * DBL_EPSILON * fabs(hpp) * fabs(hqq))) return;
+    const double d = hqq - hpp;
+    const double r2 = fma(d, d, 4.0 * hpq * hpq);
+    if (!(r2 > 1e-290 && r2 < 1e290)) {
+        rutishauser_rotation(hpp, hqq, hpq, c, s);
+        return;
+    }
+    const double rr = rsq3(r2);                   // 1 / r
+    const double h = fma(0.5 * fabs(d), rr, 0.5);  // c^2
+    const double rc = rsq3(h);                    // 1 / c
+    c = h * rc;
+    s = (d < 0 ? -hpq : hpq) * (rr * rc);
 }
 
 // Slot permutation between inner steps. Slots 0..31 hold the 32 columns of a pair; step
@@ -190,15 +236,16 @@ __device__ __forceinline__ int inner_next_slot(int x) {
 
 // One workgroup of 256 threads per pair. Thread (a, b) keeps the 2x2 blocks
 // H[2a:2a+2][2b:2b+2] and W[2a:2a+2][2b:2b+2] in registers (H indexed by slots on both
-// sides, W by input column and slot). In a step the 16 diagonal threads compute the rotation
-// of their slot pair, every thread applies J_a^T (.) J_b to its H block and (.) J_b to its W
-// block in registers, and the blocks are scattered to their next slots through LDS.
+// sides, W by input column and slot), with a copy of H in LDS. In a step every thread
+// computes the rotations of its slot pairs a and b from the diagonal blocks in LDS (so all
+// threads use bitwise the same rotations), applies J_a^T (.) J_b to its H block and (.) J_b
+// to its W block in registers, and scatters the blocks to their next slots through the
+// other LDS buffer: one barrier per step.
 __global__ __launch_bounds__(256) void k_eig_solve(const EigJob* __restrict__ jobs,
                                                    const int* __restrict__ pre, int nact,
                                                    int* __restrict__ state, int inner_sweeps) {
     __shared__ double Hs[2][PW][PW + 1];
     __shared__ double Ws[2][PW][PW + 1];
-    __shared__ double rot[PW / 2][2];
     __shared__ int s_need;
     const int j = job_of(pre, nact, blockIdx.x);
     if (state[ST_WORDS * j + ST_DONE]) return;
@@ -208,26 +255,21 @@ __global__ __launch_bounds__(256) void k_eig_solve(const EigJob* __restrict__ jo
     const double tol = J.tol;
     const double* Hp = J.Hpart + static_cast<int64_t>(pair) * nchunk * (PW * PW);
     {
-        // H = sum of the partial Grams in chunk order; four chunks' loads in flight at once
+        // H = sum of the partial Grams in chunk order, up to 12 chunks' loads in flight at once
+        constexpr int CG = 12;
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        int c = 0;
-        for (; c + 4 <= nchunk; c += 4) {
-            double v[4][4];
+        for (int c0 = 0; c0 < nchunk; c0 += CG) {
+            double v[CG][4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < CG; ++u)
 #pragma unroll
-                for (int k = 0; k < 4; ++k) v[u][k] = Hp[static_cast<int64_t>(c + u) * PW * PW + threadIdx.x + k * 256];
+                for (int k = 0; k < 4; ++k)
+                    v[u][k] = c0 + u < nchunk ? Hp[static_cast<int64_t>(c0 + u) * PW * PW + threadIdx.x + k * 256] : 0.0;
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < CG; ++u)
 #pragma unroll
-                for (int k = 0; k < 4; ++k) acc[k] += v[u][k];
-        }
-        for (; c < nchunk; ++c) {
-            double v[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) v[k] = Hp[static_cast<int64_t>(c) * PW * PW + threadIdx.x + k * 256];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) acc[k] += v[k];
+                for (int k = 0; k < 4; ++k)
+                    if (c0 + u < nchunk) acc[k] += v[u][k];
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -244,7 +286,7 @@ __global__ __launch_bounds__(256) void k_eig_solve(const EigJob* __restrict__ jo
             const int i = e / PW, k = e % PW;
             if (i < k) {
                 const double hii = Hs[0][i][i], hkk = Hs[0][k][k], hik = Hs[0][i][k];
-                if (hii > nf && hkk > nf && fabs(hik) > tol * sqrt(hii) * sqrt(hkk)) need = 1;
+                if (hii > nf && hkk > nf && hik * hik > tol * tol * (hii * hkk)) need = 1;
             }
         }
         if (need) s_need = 1;
@@ -261,17 +303,23 @@ __global__ __launch_bounds__(256) void k_eig_solve(const EigJob* __restrict__ jo
     // slot permutation of the four rows/columns this thread owns
     const int pr0 = inner_next_slot(r0), pr1 = inner_next_slot(r1);
     const int pc0 = inner_next_slot(c0), pc1 = inner_next_slot(c1);
-    int buf = 1;
+    int cur = 0;
     for (int sw = 0; sw < inner_sweeps; ++sw) {
         for (int step = 0; step < PW - 1; ++step) {
-            if (a == b) {
-                double c = 1.0, s = 0.0;
-                if (h00 > nf && h11 > nf) fast_rotation(h00, h11, h01, c, s);
-                rot[a][0] = c;
-                rot[a][1] = s;
+            // the rotations of this thread's row pair a and column pair b, each computed
+            // from its diagonal 2 x 2 block (every thread computes the ones it needs)
+            double ca = 1.0, sa = 0.0, cb = 1.0, sb = 0.0;
+            {
+                const double app = Hs[cur][r0][r0], apq = Hs[cur][r0][r1], aqq = Hs[cur][r1][r1];
+                if (app > nf && aqq > nf) fast_rotation(app, aqq, apq, ca, sa);
             }
-            __syncthreads();
-            const double ca = rot[a][0], sa = rot[a][1], cb = rot[b][0], sb = rot[b][1];
+            if (b == a) {
+                cb = ca;
+                sb = sa;
+            } else {
+                const double bpp = Hs[cur][c0][c0], bpq = Hs[cur][c0][c1], bqq = Hs[cur][c1][c1];
+                if (bpp > nf && bqq > nf) fast_rotation(bpp, bqq, bpq, cb, sb);
+            }
             // rows: new row p = c row_p - s row_q, new row q = s row_p + c row_q
             const double x00 = ca * h00 - sa * h10, x01 = ca * h01 - sa * h11;
             const double x10 = sa * h00 + ca * h10, x11 = sa * h01 + ca * h11;
@@ -286,25 +334,27 @@ __global__ __launch_bounds__(256) void k_eig_solve(const EigJob* __restrict__ jo
             w01 = y01;
             w10 = y10;
             w11 = y11;
-            // move to the next step's slots (W rows are input columns and stay)
-            Hs[buf][pr0][pc0] = h00;
-            Hs[buf][pr0][pc1] = h01;
-            Hs[buf][pr1][pc0] = h10;
-            Hs[buf][pr1][pc1] = h11;
-            Ws[buf][r0][pc0] = w00;
-            Ws[buf][r0][pc1] = w01;
-            Ws[buf][r1][pc0] = w10;
-            Ws[buf][r1][pc1] = w11;
+            // move to the next step's slots (W rows are input columns and stay); the buffer
+            // written here was last read before the previous barrier
+            const int nxt = cur ^ 1;
+            Hs[nxt][pr0][pc0] = h00;
+            Hs[nxt][pr0][pc1] = h01;
+            Hs[nxt][pr1][pc0] = h10;
+            Hs[nxt][pr1][pc1] = h11;
+            Ws[nxt][r0][pc0] = w00;
+            Ws[nxt][r0][pc1] = w01;
+            Ws[nxt][r1][pc0] = w10;
+            Ws[nxt][r1][pc1] = w11;
             __syncthreads();
-            h00 = Hs[buf][r0][c0];
-            h01 = Hs[buf][r0][c1];
-            h10 = Hs[buf][r1][c0];
-            h11 = Hs[buf][r1][c1];
-            w00 = Ws[buf][r0][c0];
-            w01 = Ws[buf][r0][c1];
-            w10 = Ws[buf][r1][c0];
-            w11 = Ws[buf][r1][c1];
-            buf ^= 1;
+            h00 = Hs[nxt][r0][c0];
+            h01 = Hs[nxt][r0][c1];
+            h10 = Hs[nxt][r1][c0];
+            h11 = Hs[nxt][r1][c1];
+            w00 = Ws[nxt][r0][c0];
+            w01 = Ws[nxt][r0][c1];
+            w10 = Ws[nxt][r1][c0];
+            w11 = Ws[nxt][r1][c1];
+            cur = nxt;
         }
     }
     // after whole sweeps every slot holds its own column again
@@ -319,11 +369,13 @@ __global__ __launch_bounds__(256) void k_eig_solve(const EigJob* __restrict__ jo
     }
 }
 
-// X[:, I u J] <- X[:, I u J] W, one thread per row
-__global__ __launch_bounds__(UPD_ROWS) void k_eig_update(const EigJob* __restrict__ jobs,
-                                                         const int* __restrict__ pre, int nact,
-                                                         const int* __restrict__ state, int round) {
-    __shared__ double W[PW][PW];
+// X[:, I u J] <- X[:, I u J] W over a tile of UPD_ROWS rows: the tile and W staged in LDS,
+// each thread a 4 x 4 block of the product (rows lane-strided, so stores are coalesced).
+__global__ __launch_bounds__(256) void k_eig_update(const EigJob* __restrict__ jobs,
+                                                    const int* __restrict__ pre, int nact,
+                                                    const int* __restrict__ state, int round) {
+    __shared__ double Ws[PW][PW + 1];
+    __shared__ double Xs[PW][UPD_ROWS + 1];
     const int j = job_of(pre, nact, blockIdx.x);
     if (state[ST_WORDS * j + ST_DONE]) return;
     const EigJob& J = jobs[j];
@@ -333,36 +385,62 @@ __global__ __launch_bounds__(UPD_ROWS) void k_eig_update(const EigJob* __restric
     int bi, bj;
     round_robin_pair(round, pair, J.nbe, bi, bj);
     const bool hasJ = bj < J.nblk;
+    const int64_t ld = J.ld;
+    const int64_t r0 = static_cast<int64_t>(rb) * UPD_ROWS;
+    const int nr = static_cast<int>(min<int64_t>(UPD_ROWS, ld - r0));
+    double* X = J.X;
     const double* Wg = J.W + static_cast<int64_t>(pair) * PW * PW;
     {
-        double v[PW * PW / UPD_ROWS];
+        constexpr int PX = PW * UPD_ROWS / 256, PWW = PW * PW / 256;
+        double xv[PX], wv[PWW];
 #pragma unroll
-        for (int k = 0; k < PW * PW / UPD_ROWS; ++k) v[k] = Wg[threadIdx.x + k * UPD_ROWS];
+        for (int k = 0; k < PWW; ++k) wv[k] = Wg[threadIdx.x + k * 256];
 #pragma unroll
-        for (int k = 0; k < PW * PW / UPD_ROWS; ++k) {
-            const int e = threadIdx.x + k * UPD_ROWS;
-            W[e / PW][e % PW] = v[k];
+        for (int k = 0; k < PX; ++k) {
+            const int e = threadIdx.x + k * 256;
+            const int c = e / UPD_ROWS, r = e % UPD_ROWS;
+            const int col = c < BW ? bi * BW + c : bj * BW + (c - BW);
+            xv[k] = (r < nr && (c < BW || hasJ)) ? X[static_cast<int64_t>(col) * ld + r0 + r] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < PWW; ++k) {
+            const int e = threadIdx.x + k * 256;
+            Ws[e / PW][e % PW] = wv[k];
+        }
+#pragma unroll
+        for (int k = 0; k < PX; ++k) {
+            const int e = threadIdx.x + k * 256;
+            Xs[e / UPD_ROWS][e % UPD_ROWS] = xv[k];
         }
     }
     __syncthreads();
-    const int64_t ld = J.ld;
-    const int64_t r = static_cast<int64_t>(rb) * UPD_ROWS + threadIdx.x;
-    if (r >= ld) return;
-    double* X = J.X;
-    double y[PW];
+    constexpr int RL = UPD_ROWS / 4;              // row lanes; rows rl, rl + RL, ...
+    const int rl = threadIdx.x % RL, c0 = (threadIdx.x / RL) * 4;
+    double acc[4][4] = {};
+#pragma unroll 8
+    for (int k = 0; k < PW; ++k) {
+        double x[4], w[4];
 #pragma unroll
-    for (int c = 0; c < PW; ++c) {
-        const int col = c < BW ? bi * BW + c : bj * BW + (c - BW);
-        y[c] = (c < BW || hasJ) ? X[static_cast<int64_t>(col) * ld + r] : 0.0;
+        for (int u = 0; u < 4; ++u) {
+            x[u] = Xs[k][rl + u * RL];
+            w[u] = Ws[k][c0 + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] += x[u] * w[v];
     }
-    const int jend = hasJ ? PW : BW;
-#pragma unroll 4
-    for (int k = 0; k < jend; ++k) {
-        double acc = 0;
 #pragma unroll
-        for (int c = 0; c < PW; ++c) acc += y[c] * W[c][k];
-        const int col = k < BW ? bi * BW + k : bj * BW + (k - BW);
-        X[static_cast<int64_t>(col) * ld + r] = acc;
+    for (int v = 0; v < 4; ++v) {
+        const int c = c0 + v;
+        if (!(c < BW || hasJ)) continue;
+        const int col = c < BW ? bi * BW + c : bj * BW + (c - BW);
+        double* Xc = X + static_cast<int64_t>(col) * ld + r0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int r = rl + u * RL;
+            if (r < nr) Xc[r] = acc[u][v];
+        }
     }
 }
 
@@ -488,7 +566,7 @@ int eig_set_create(EigSet& es, std::vector<EigJob> jobs, int gram_rows, bool pre
     eig_set_free(es);
     es.gram_rows = gram_rows;
     for (const EigJob& J : jobs)
-        if (!J.A) precond = false;
+        if (!J.A || J.q > pchol_max_order()) precond = false;
     es.precond = precond ? 1 : 0;
     for (EigJob& J : jobs) J.squared = es.precond;
     std::stable_sort(jobs.begin(), jobs.end(),
@@ -580,7 +658,7 @@ void eig_sweep(const EigSet& es, int max_sweeps, int inner_sweeps, hipStream_t s
                            inner_sweeps);
         if (timer) timer->end(ts, st);
         ts = timer ? timer->begin(KT_EIG_UPDATE, st) : -1;
-        hipLaunchKernelGGL(k_eig_update, dim3(es.g_upd[t]), dim3(UPD_ROWS), 0, st, es.jobs, pu, na, es.state,
+        hipLaunchKernelGGL(k_eig_update, dim3(es.g_upd[t]), dim3(256), 0, st, es.jobs, pu, na, es.state,
                            t);
         if (timer) timer->end(ts, st);
     }

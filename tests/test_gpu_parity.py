@@ -55,7 +55,8 @@ def run_oracle(prob, alpha):
 # ------------------------------------------------------------------ eigensolver ---------
 @pytest.mark.parametrize("q,t,rank", [(1, 1, 1), (5, 3, 5), (16, 8, 16), (17, 17, 17),
                                       (40, 10, 40), (130, 60, 130), (300, 120, 250),
-                                      (513, 100, 513)])
+                                      (513, 100, 513), (1100, 64, 1100), (2500, 200, 2500),
+                                      (4500, 100, 4000)])
 def test_syev_top_matches_dense_eigensolver(fp, torch, q, t, rank):
     say(f"syev_top q={q} t={t} rank={rank}")
     rng = np.random.default_rng(q * 7 + t)
