@@ -229,6 +229,13 @@ int fastpi_sync(fastpi_handle* h);
 int fastpi_last_sweeps(fastpi_handle* h, int32_t* out3);
 
 /*
+ * Pairs of 16-column blocks whose 32 x 32 Jacobi solve ran (rather than being found
+ * orthogonal already) in the last fastpi_svd: out2[0] row-update core, out2[1] column-update
+ * core (the work count behind the eigensolver's algorithmic flops).
+ */
+int fastpi_last_rotations(fastpi_handle* h, int64_t* out2);
+
+/*
  * Measurement hook: times every launch of one kernel of the device path with a HIP event
  * pair on the handle's stream (each timed launch costs an extra event record).
  * kind: 0 = eigensolver partial Gram, 1 = eigensolver pair solve, 2 = eigensolver column
@@ -297,6 +304,8 @@ int fastpi_batch_svd(fastpi_batch* b, const double* const* val, double* const* U
  * in fastpi_last_sweeps. Returns the first non-OK code, or FASTPI_OK.
  */
 int fastpi_batch_sync(fastpi_batch* b, int32_t* status, int32_t* sweeps);
+/* fastpi_last_rotations for every matrix of the batch: out[2*i], out[2*i+1] (host int64). */
+int fastpi_batch_rotations(const fastpi_batch* b, int64_t* out);
 int fastpi_batch_set_graph(fastpi_batch* b, int enable);
 int64_t fastpi_batch_last_graph_launches(const fastpi_batch* b);
 int fastpi_batch_set_tuning(fastpi_batch* b, const fastpi_tuning* t);

@@ -81,6 +81,8 @@ SIGNATURES = [
                                 ctypes.c_float]),
     ("fastpi_timing_start", c_int, [c_void_p, c_int]),
     ("fastpi_timing_read", c_int, [c_void_p, POINTER(c_int64), POINTER(c_double)]),
+    ("fastpi_last_rotations", c_int, [c_void_p, c_void_p]),
+    ("fastpi_batch_rotations", c_int, [c_void_p, c_void_p]),
     ("fastpi_set_graph", c_int, [c_void_p, c_int]),
     ("fastpi_last_graph_launches", c_int64, [c_void_p]),
     ("fastpi_set_tuning", c_int, [c_void_p, POINTER(Tuning)]),
@@ -308,6 +310,12 @@ class Handle:
 
     KERNELS = {"eig_gram": 0, "eig_solve": 1, "eig_update": 2, "block_svd": 3}
 
+    def last_rotations(self):
+        """Pair solves that ran in the last svd: [row-update core, column-update core]."""
+        out = np.zeros(2, dtype=np.int64)
+        _check(load().fastpi_last_rotations(self._h, _ptr(out)))
+        return out.tolist()
+
     # ---- batching form: graphs and schedules ----
     def set_graph(self, enable=True):
         _check(load().fastpi_set_graph(self._h, 1 if enable else 0))
@@ -426,6 +434,12 @@ class Batch:
         sw = np.zeros((len(self.plans), 3), dtype=np.int32)
         load().fastpi_batch_sync(self._b, _ptr(st), _ptr(sw))
         return [STATUS.get(int(c), str(int(c))) for c in st], sw
+
+    def rotations(self):
+        """Pair solves that ran in the last svd, per matrix: array [count, 2]."""
+        out = np.zeros((len(self.plans), 2), dtype=np.int64)
+        _check(load().fastpi_batch_rotations(self._b, _ptr(out)))
+        return out
 
     def set_graph(self, enable=True):
         _check(load().fastpi_batch_set_graph(self._b, 1 if enable else 0))

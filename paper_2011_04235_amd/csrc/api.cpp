@@ -485,8 +485,8 @@ int fastpi_syev_top(fastpi_handle* h, int64_t q, const double* G, int64_t t, dou
         eig_end(es, h->stream);
         if (hipStreamSynchronize(h->stream) != hipSuccess) st = FASTPI_EHIP;
     }
-    h->syev_sweeps = es.host_state[2];
-    const bool capped = es.host_state[3] != 0;
+    h->syev_sweeps = es.host_state[kEigStSweeps];
+    const bool capped = es.host_state[kEigStCapped] != 0;
     eig_set_free(es);
     if (st != FASTPI_OK) return st;
     if (capped) {
@@ -628,6 +628,16 @@ int fastpi_last_sweeps(fastpi_handle* h, int32_t* out3) {
     for (int i = 0; i < 3; ++i) out3[i] = h->inst.sweeps[i];
     if (!h->inst.dp.valid) out3[1] = h->syev_sweeps;
     return st;
+}
+
+int fastpi_last_rotations(fastpi_handle* h, int64_t* out2) {
+    if (!h || !out2) {
+        set_error("null pointer");
+        return FASTPI_EINVAL;
+    }
+    out2[0] = h->inst.rotated[0];
+    out2[1] = h->inst.rotated[1];
+    return FASTPI_OK;
 }
 
 int fastpi_set_graph(fastpi_handle* h, int enable) {
@@ -801,6 +811,18 @@ int fastpi_batch_sync(fastpi_batch* b, int32_t* status, int32_t* sweeps) {
     }
     if (first != FASTPI_OK) set_error(first_msg);
     return first;
+}
+
+int fastpi_batch_rotations(const fastpi_batch* b, int64_t* out) {
+    if (!b || !out) {
+        set_error("null pointer");
+        return FASTPI_EINVAL;
+    }
+    for (size_t i = 0; i < b->inst.size(); ++i) {
+        out[2 * i] = b->inst[i].rotated[0];
+        out[2 * i + 1] = b->inst[i].rotated[1];
+    }
+    return FASTPI_OK;
 }
 
 int fastpi_batch_set_graph(fastpi_batch* b, int enable) {

@@ -228,19 +228,18 @@ void launch_copy(const double* src, int64_t n, double* dst, hipStream_t st) {
 }
 
 void launch_block_svd_tasks(bool fp32, const BlockTask* tasks, int ntasks, int* counter, int lds_bytes,
-                            int grid, int max_sweeps, double tol_scale, hipStream_t st) {
+                            int grid, int max_sweeps, double tol_scale, hipStream_t st, KernelTimer* timer) {
     if (ntasks <= 0) return;
     launch_fill_i32(counter, 1, 0, st);
     grid = std::max(1, std::min(grid, ntasks));
     if (fp32) {
         const int64_t lds_elems = lds_bytes / static_cast<int>(sizeof(float));
-        hipLaunchKernelGGL(k_block_svd<float>, dim3(grid), dim3(256), lds_bytes, st, tasks, ntasks, counter,
-                           lds_elems, max_sweeps,
-                           static_cast<float>(tol_scale > 0 ? tol_scale : FLT_EPSILON));
+        FASTPI_LAUNCH(timer, KT_BLOCK_SVD, k_block_svd<float>, dim3(grid), dim3(256), lds_bytes, st, tasks, ntasks,
+                      counter, lds_elems, max_sweeps, static_cast<float>(tol_scale > 0 ? tol_scale : FLT_EPSILON));
     } else {
         const int64_t lds_elems = lds_bytes / static_cast<int>(sizeof(double));
-        hipLaunchKernelGGL(k_block_svd<double>, dim3(grid), dim3(256), lds_bytes, st, tasks, ntasks, counter,
-                           lds_elems, max_sweeps, tol_scale > 0 ? tol_scale : DBL_EPSILON);
+        FASTPI_LAUNCH(timer, KT_BLOCK_SVD, k_block_svd<double>, dim3(grid), dim3(256), lds_bytes, st, tasks, ntasks,
+                      counter, lds_elems, max_sweeps, tol_scale > 0 ? tol_scale : DBL_EPSILON);
     }
 }
 

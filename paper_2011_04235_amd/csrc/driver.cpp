@@ -355,12 +355,8 @@ static void stage_front(Group& g, const double* const* val, const RunCfg& c, hip
         launch_gather(val[i], d.dst0, d.dst1, d.nnz, vals, I.status, st);
     }
     // a2: block SVDs (Eq. 1), every block of every instance in one persistent launch
-    {
-        const long ts = timer ? timer->begin(KT_BLOCK_SVD, st) : -1;
-        launch_block_svd_tasks(c.mixed, g.tasks, g.ntasks, g.counter, g.tune.block_lds,
-                               g.ncu * g.tune.block_wgs_per_cu, c.max_sweeps, c.tol, st);
-        if (timer) timer->end(ts, st);
-    }
+    launch_block_svd_tasks(c.mixed, g.tasks, g.ntasks, g.counter, g.tune.block_lds, g.ncu * g.tune.block_wgs_per_cu,
+                           c.max_sweeps, c.tol, st, timer);
     // a3, first half: M2^T M2 = V1 Sigma1^2 V1^T + A21^T A21
     for (Instance* Ip : g.inst) {
         Instance& I = *Ip;
@@ -477,12 +473,18 @@ static int launch_graph(Group& g, hipGraphExec_t e, hipStream_t st) {
 }
 
 static void record_sweeps(Group& g) {
-    for (Instance* I : g.inst) I->sweeps[1] = I->sweeps[2] = 0;
+    for (Instance* I : g.inst) {
+        I->sweeps[1] = I->sweeps[2] = 0;
+        I->rotated[0] = I->rotated[1] = 0;
+    }
     const EigSet* sets[2] = {&g.set2, &g.set3};
     for (int k = 0; k < 2; ++k) {
         const EigSet& es = *sets[k];
-        for (int j = 0; j < es.njobs; ++j)
-            g.inst[es.host[j].tag]->sweeps[1 + k] = es.host_state[4 * j + 2];
+        for (int j = 0; j < es.njobs; ++j) {
+            Instance* I = g.inst[es.host[j].tag];
+            I->sweeps[1 + k] = es.host_state[kEigStateWords * j + kEigStSweeps];
+            I->rotated[k] = es.host_state[kEigStateWords * j + kEigStTotal];
+        }
     }
 }
 

@@ -48,6 +48,7 @@ struct Instance {
     size_t iws_bytes = 0;
     int* status = nullptr;   // device [0] status bits, [1] block sweeps (not owned)
     int32_t sweeps[3] = {0, 0, 0};
+    int64_t rotated[2] = {0, 0};   // pairs rotated by the row- and column-update eigensolvers
     // offsets (in doubles) of the stage buffers inside ws
     int64_t o_vals = 0, o_u1 = 0, o_v1 = 0, o_sig1 = 0, o_g2 = 0, o_v2 = 0, o_lam2 = 0, o_sig2 = 0,
             o_inv2 = 0, o_u2 = 0, o_g3 = 0, o_vt = 0, o_lam3 = 0, o_sig3 = 0, o_inv3 = 0, o_c1 = 0,

@@ -28,7 +28,8 @@ namespace fastpi {
 constexpr int BW = 16;
 constexpr int PW = 2 * BW;         // columns in a pair
 constexpr int UPD_ROWS = 128;      // rows per update workgroup
-constexpr int ST_ROT = 0, ST_DONE = 1, ST_SWEEPS = 2, ST_CAPPED = 3, ST_WORDS = 4;
+constexpr int ST_ROT = kEigStRot, ST_DONE = kEigStDone, ST_SWEEPS = kEigStSweeps, ST_CAPPED = kEigStCapped,
+              ST_TOTAL = kEigStTotal, ST_WORDS = kEigStateWords;
 
 // largest j < nact with pre[j] <= bid (the job owning flattened workgroup bid)
 __device__ __forceinline__ int job_of(const int* __restrict__ pre, int nact, int bid) {
@@ -455,6 +456,7 @@ __global__ __launch_bounds__(256) void k_eig_sweep_end(const EigJob* __restrict_
         int* sj = state + ST_WORDS * j;
         if (!sj[ST_DONE]) {
             sj[ST_SWEEPS] += 1;
+            sj[ST_TOTAL] += sj[ST_ROT];
             if (sj[ST_ROT] == 0) {
                 sj[ST_DONE] = 1;
             } else if (sj[ST_SWEEPS] >= max_sweeps) {
@@ -638,29 +640,23 @@ void eig_sweep(const EigSet& es, int max_sweeps, int inner_sweeps, hipStream_t s
     const int* pu = es.pre + 2 * (nj + 1);
     for (int t = 0; t < es.rounds; ++t) {
         const int na = es.nact[t];
-        long ts = timer ? timer->begin(KT_EIG_GRAM, st) : -1;
         switch (es.gram_rows) {
             case 64:
-                hipLaunchKernelGGL(k_eig_gram<64>, dim3(es.g_gram[t]), dim3(256), 0, st, es.jobs, pg, na,
-                                   es.state, t);
+                FASTPI_LAUNCH(timer, KT_EIG_GRAM, (k_eig_gram<64>), dim3(es.g_gram[t]), dim3(256), 0, st, es.jobs, pg,
+                              na, es.state, t);
                 break;
             case 256:
-                hipLaunchKernelGGL(k_eig_gram<256>, dim3(es.g_gram[t]), dim3(256), 0, st, es.jobs, pg, na,
-                                   es.state, t);
+                FASTPI_LAUNCH(timer, KT_EIG_GRAM, (k_eig_gram<256>), dim3(es.g_gram[t]), dim3(256), 0, st, es.jobs, pg,
+                              na, es.state, t);
                 break;
             default:
-                hipLaunchKernelGGL(k_eig_gram<128>, dim3(es.g_gram[t]), dim3(256), 0, st, es.jobs, pg, na,
-                                   es.state, t);
+                FASTPI_LAUNCH(timer, KT_EIG_GRAM, (k_eig_gram<128>), dim3(es.g_gram[t]), dim3(256), 0, st, es.jobs, pg,
+                              na, es.state, t);
         }
-        if (timer) timer->end(ts, st);
-        ts = timer ? timer->begin(KT_EIG_SOLVE, st) : -1;
-        hipLaunchKernelGGL(k_eig_solve, dim3(es.g_solve[t]), dim3(256), 0, st, es.jobs, ps, na, es.state,
-                           inner_sweeps);
-        if (timer) timer->end(ts, st);
-        ts = timer ? timer->begin(KT_EIG_UPDATE, st) : -1;
-        hipLaunchKernelGGL(k_eig_update, dim3(es.g_upd[t]), dim3(256), 0, st, es.jobs, pu, na, es.state,
-                           t);
-        if (timer) timer->end(ts, st);
+        FASTPI_LAUNCH(timer, KT_EIG_SOLVE, k_eig_solve, dim3(es.g_solve[t]), dim3(256), 0, st, es.jobs, ps, na,
+                      es.state, inner_sweeps);
+        FASTPI_LAUNCH(timer, KT_EIG_UPDATE, k_eig_update, dim3(es.g_upd[t]), dim3(256), 0, st, es.jobs, pu, na,
+                      es.state, t);
     }
     hipLaunchKernelGGL(k_eig_sweep_end, dim3(1), dim3(256), 0, st, es.jobs, nj, es.state, max_sweeps);
 }

@@ -2,6 +2,7 @@
 // stated).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,8 +24,10 @@ struct SegDev {
     int64_t nseg, nmulti, npart;
 };
 
-// Per-launch timing of one kernel kind with HIP events on the launch stream (measurement
-// only; each timed launch gets an event pair).
+// Per-launch timing of one kernel kind (measurement only). A timed launch goes through
+// hipExtLaunchKernel with an event pair that the runtime stamps at the dispatch's own start
+// and end, so the pair measures the kernel body (events recorded around a launch would also
+// count its dispatch gap).
 enum KernelKind { KT_NONE = -1, KT_EIG_GRAM = 0, KT_EIG_SOLVE = 1, KT_EIG_UPDATE = 2, KT_BLOCK_SVD = 3 };
 struct KernelTimer {
     int target = KT_NONE;
@@ -42,21 +45,28 @@ struct KernelTimer {
         }
         return pool[used++];
     }
-    // records the start event if `kind` is the timed one; returns the slot index or -1
-    long begin(int kind, hipStream_t st) {
-        if (kind != target || failed) return -1;
-        hipEvent_t e = take();
-        if (!e) return -1;
-        hipEventRecord(e, st);
-        return static_cast<long>(used - 1);
-    }
-    void end(long slot, hipStream_t st) {
-        if (slot < 0) return;
-        hipEvent_t e = take();
-        if (!e) return;
-        hipEventRecord(e, st);
+    // an event pair for the next launch if `kind` is the timed one
+    bool pair(int kind, hipEvent_t& e0, hipEvent_t& e1) {
+        if (kind != target || failed) return false;
+        e0 = take();
+        e1 = e0 ? take() : nullptr;
+        if (!e0 || !e1) {
+            failed = true;
+            return false;
+        }
+        return true;
     }
 };
+
+// launches `kernel`, timed when `timer` is set and times `kind`
+#define FASTPI_LAUNCH(timer, kind, kernel, grid, block, shmem, st, ...)                               \
+    do {                                                                                            \
+        hipEvent_t fastpi_e0_, fastpi_e1_;                                                          \
+        if ((timer) && (timer)->pair((kind), fastpi_e0_, fastpi_e1_))                               \
+            hipExtLaunchKernelGGL(kernel, grid, block, shmem, st, fastpi_e0_, fastpi_e1_, 0u, __VA_ARGS__); \
+        else                                                                                        \
+            hipLaunchKernelGGL(kernel, grid, block, shmem, st, __VA_ARGS__);                        \
+    } while (0)
 
 void launch_fill(double* p, int64_t n, double v, hipStream_t st);
 void launch_fill_i32(int* p, int64_t n, int v, hipStream_t st);
@@ -80,7 +90,7 @@ struct BlockTask {
 // must hold 0 at launch; the launcher clears it with a fill kernel first).
 void launch_block_svd_tasks(bool fp32, const BlockTask* tasks, int ntasks, int* counter,
                             int lds_bytes, int grid, int max_sweeps, double tol_scale,
-                            hipStream_t st);
+                            hipStream_t st, KernelTimer* timer = nullptr);
 void launch_copy(const double* src, int64_t n, double* dst, hipStream_t st);
 
 // eigensolver (eig.hip): block one-sided Jacobi on a set of independent symmetric PSD
@@ -103,13 +113,19 @@ struct EigJob {
     int squared;        // X = R^T of a pivoted Cholesky: eigenvalues are squared column norms
     int pad;
 };
+// per-job device state words of an EigSet (then one all-done word after the last job)
+constexpr int kEigStRot = 0;      // pairs rotated in the current sweep
+constexpr int kEigStDone = 1;     // converged or capped
+constexpr int kEigStSweeps = 2;   // sweeps run
+constexpr int kEigStCapped = 3;   // stopped by the sweep cap
+constexpr int kEigStTotal = 4;    // pairs rotated over all finished sweeps
+constexpr int kEigStateWords = 6;
 struct EigSet {
     int njobs = 0, rounds = 0, gram_rows = 128;
     EigJob* jobs = nullptr;       // device, jobs sorted by rounds per sweep (descending)
     int* pre = nullptr;           // device prefix sums of the per-job workgroup counts:
                                   // gram, solve, update (each njobs + 1)
-    int* state = nullptr;         // device, per job {rotations, done, sweeps, capped}, then
-                                  // the all-done word
+    int* state = nullptr;         // device, kEigStateWords per job, then the all-done word
     int* host_state = nullptr;    // pinned mirror of state
     int* pstate = nullptr;        // device, per job {pivots taken, factorisation done}
     int precond = 0;              // start from the pivoted Cholesky factor instead of G

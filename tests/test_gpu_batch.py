@@ -81,6 +81,14 @@ def test_batch_matches_oracle_and_single_runs(fp, torch, small_probs):
     status, sweeps = b.sync()
     say(f"  status={status} sweeps={sweeps.tolist()}")
     assert status == ["OK"] * len(small_probs)
+    rot = b.rotations()
+    for (name, prob, alpha), r, sw in zip(small_probs, rot, sweeps):
+        plan = plan_of(fp, prob, alpha)
+        for k, q in enumerate((plan.n1, plan.s + plan.n2)):
+            nb = -(-q // 16)
+            # every sweep of a core checks (nb + nb % 2 - 1) rounds of ceil(nb / 2) pairs
+            bound = int(sw[1 + k]) * (nb + nb % 2 - 1) * ((nb + 1) // 2)
+            assert 0 <= r[k] <= bound, (name, k, r[k], bound)
     for (name, prob, alpha), (U, S, V) in zip(small_probs, out):
         ores = oracle.fastpi_svd(prob.m, prob.n, prob.indptr, prob.indices, prob.data, alpha, prob.cfg.k)
         ok, info = compare_svd(prob, to_np(U), to_np(S), to_np(V), ores)
