@@ -56,15 +56,18 @@ GRAM_ROWS = 128          # default rows per partial Gram (eigensolver)
 BW = 16                  # eigensolver column block
 
 
-# HBM bytes per k_eig_solve launch from the two counter runs summarised in
-# profiles/k_eig_solve_c2_pmc.md (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, both scales read off a
-# 256 MiB device copy in the same runs), and the digest of the kernel source they were taken
-# on; the figure is dropped (null) as soon as the kernel's source differs.
-SOLVE_TRAFFIC_BYTES = 3194395
+# HBM bytes per k_eig_solve launch on the 20000 x 2000 workload from the two counter runs
+# summarised in profiles/k_eig_solve_c2_pmc.md (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, both
+# scales read off a 256 MiB device copy in the same runs), and the digest of the kernel
+# source they were taken on; the figure is dropped (null) for any other workload and as
+# soon as the kernel's source differs.
+SOLVE_TRAFFIC_BYTES = {"c2": 3194395}
 SOLVE_TRAFFIC_DIGEST = "fba500e42e0dbc285d3bb2d2b59f88b04154aa3e948041015f2b07afbc94e9c2"
 
 
-def solve_traffic():
+def solve_traffic(config):
+    if config not in SOLVE_TRAFFIC_BYTES:
+        return None
     import hashlib
     with open(os.path.join(ROOT, "paper_2011_04235_amd", "csrc", "eig.hip")) as f:
         src = f.read()
@@ -72,7 +75,7 @@ def solve_traffic():
     b = src.index("__global__", a + 1)
     if hashlib.sha256(src[a:b].encode()).hexdigest() != SOLVE_TRAFFIC_DIGEST:
         return None
-    return SOLVE_TRAFFIC_BYTES
+    return SOLVE_TRAFFIC_BYTES[config]
 
 
 def eig_shape(q, gram_rows=128):
@@ -423,7 +426,7 @@ def main():
         peak = 78.6   # MI355X FP64 vector peak, TFLOP/s
         roof = {"bound": "alu", "kernel": "k_eig_solve", "achieved": round(achieved, 5),
                 "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 6),
-                "traffic": solve_traffic(), "traffic_unit": "bytes per launch", "launches": n_launch, "avg_us": round(k_ms / n_launch * 1e3, 3),
+                "traffic": solve_traffic(args.config), "traffic_unit": "bytes per launch", "launches": n_launch, "avg_us": round(k_ms / n_launch * 1e3, 3),
                 "flops_per_launch": f_alg / n_launch,
                 "timed_in": head_key + (" (eager pass of the same schedule)" if "batched" in head_key else "")}
     base = None
