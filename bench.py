@@ -315,6 +315,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (scale for the PMC byte counters)")
     ap.add_argument("--batch-count", type=int, default=64, help="matrices of the batched workload")
+    ap.add_argument("--ranks", default="alpha", choices=["alpha", "learned"],
+                    help="block ranks: the alpha rule, or the shipped rank network at the same total")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
@@ -341,6 +343,18 @@ def main():
     t0 = time.perf_counter()
     plan = fp.Plan(prob.m, prob.n, prob.indptr, prob.indices, prob.data, alpha=cfg.alpha, k=cfg.k)
     plan_s = time.perf_counter() - t0
+    ranks_note = "alpha rule"
+    if args.ranks == "learned":
+        from paper_2011_04235_amd.rank_mlp import RankPredictor
+        pred = RankPredictor.load(os.path.join(ROOT, "paper_2011_04235_amd", "rank_predictor.npz"))
+        blocks = plan.blocks()
+        dense = (blocks[:, 2] > 0) & (blocks[:, 3] > 0)
+        feats = plan.block_features(prob.data)
+        hk = fp.Handle(0)
+        plan.set_block_ranks(pred.block_ranks(hk, plan, prob.data, plan.block_ranks()[dense]))
+        del hk
+        ranks_note = (f"rank network ({int(pred.in_range(feats).sum())} of {len(feats)} blocks; the rest "
+                      "alpha rule), total s_b of the alpha rule")
     blocks = plan.blocks()
     ranks = plan.block_ranks()
     F = flop_model(plan, blocks, ranks, cfg.L)
@@ -465,7 +479,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"fastpi {cfg.name}: A {m}x{n} ({prob.nnz} nnz, power-law "
                                f"{cfg.gamma}, {cfg.values}), Y {m}x{cfg.L}, alpha {cfg.alpha}",
-                   "form": head_key, "m": m, "n": n,
+                   "form": head_key, "ranks": ranks_note, "m": m, "n": n,
                    "nnz": prob.nnz, "L": cfg.L,
                    "alpha": cfg.alpha, "shape": plan.info},
         "flop_model": F,

@@ -146,9 +146,17 @@ __device__ void block_svd_one(const BlockTask& w, T* X, T* J, int max_sweeps, T 
     if (q > 1) jacobi_sweeps<T>(X, J, p, q, max_sweeps, tol, w.status + 1, w.status);
     __syncthreads();
 
-    // column norms, then the descending rank of every column (ties: lower column first)
-    __shared__ double s_sig[256];
-    __shared__ int s_rank[256];
+    // column norms, then the descending rank of every column (ties: lower column first);
+    // in LDS up to 256 columns, else in the block's global scratch after J (the same
+    // workgroup writes and reads them, ordered by its barriers)
+    __shared__ double l_sig[256];
+    __shared__ int l_rank[256];
+    double* s_sig = l_sig;
+    int* s_rank = l_rank;
+    if (q > 256) {
+        s_sig = static_cast<double*>(w.scratch) + static_cast<int64_t>(p) * q + static_cast<int64_t>(q) * q;
+        s_rank = reinterpret_cast<int*>(s_sig + q);
+    }
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     for (int c = wave; c < q; c += blockDim.x / kWave) {
         double acc = 0;
@@ -209,7 +217,9 @@ __global__ __launch_bounds__(256) void k_block_svd(const BlockTask* __restrict__
         const int q = w.rows > w.cols ? w.cols : w.rows;
         const int64_t need = static_cast<int64_t>(p) * q + static_cast<int64_t>(q) * q;
         const T tol = tol_scale * static_cast<T>(p);
-        T* X = need <= lds_elems ? reinterpret_cast<T*>(smem_raw) : static_cast<T*>(w.scratch);
+        // blocks with more than 256 columns always work in global scratch (their norms and
+        // ranks live there too)
+        T* X = (need <= lds_elems && q <= 256) ? reinterpret_cast<T*>(smem_raw) : static_cast<T*>(w.scratch);
         T* J = X + static_cast<int64_t>(p) * q;
         block_svd_one<T>(w, X, J, max_sweeps, tol);
     }

@@ -150,12 +150,11 @@ int instance_upload(Instance& I, const Plan& p, size_t ws_cap, hipStream_t st) {
     for (size_t i = 0; i < p.work.size(); ++i) {
         const BlockWork& w = p.work[i];
         const int64_t pp = std::max(w.rows, w.cols), qq = std::min(w.rows, w.cols);
-        if (qq > 256) {
-            set_error("a diagonal block has both sides above 256; not supported");
-            return FASTPI_EINTERNAL;
-        }
         I.scratch_off[i] = gs;
-        gs += ((pp * qq + qq * qq + 31) / 32) * 32;
+        // X and J (in FP64 size, enough for either compute type), then for more than 256
+        // columns their norms (q doubles) and ranks (q ints)
+        const int64_t extra = qq > 256 ? 2 * qq : 0;
+        gs += ((pp * qq + qq * qq + extra + 31) / 32) * 32;
     }
     int rc;
     if ((rc = upload(I, d.work, p.work.data(), p.work.size(), st)) != FASTPI_OK) return rc;

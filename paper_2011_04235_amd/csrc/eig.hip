@@ -568,7 +568,7 @@ int eig_set_create(EigSet& es, std::vector<EigJob> jobs, int gram_rows, bool pre
     eig_set_free(es);
     es.gram_rows = gram_rows;
     for (const EigJob& J : jobs)
-        if (!J.A || J.q > pchol_max_order()) precond = false;
+        if (!J.A) precond = false;
     es.precond = precond ? 1 : 0;
     for (EigJob& J : jobs) J.squared = es.precond;
     std::stable_sort(jobs.begin(), jobs.end(),

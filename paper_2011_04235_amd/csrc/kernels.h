@@ -142,10 +142,8 @@ EigJob eig_make_job(const double* G, double* A, int64_t q, int64_t t, double* va
                     double* ws, int* iws, int* status, double tol, int gram_rows, int tag);
 // precond: factor every job's G first (every job needs A) and iterate on R^T
 int eig_set_create(EigSet& es, std::vector<EigJob> jobs, int gram_rows, bool precond, hipStream_t st);
-// pivoted Cholesky of every job of the set into its X (pchol.hip); orders up to
-// pchol_max_order()
+// pivoted Cholesky of every job of the set into its X (pchol.hip)
 void pchol_run(const EigSet& es, hipStream_t st);
-int pchol_max_order();
 void eig_set_free(EigSet& es);
 void eig_begin(const EigSet& es, hipStream_t st);
 void eig_sweep(const EigSet& es, int max_sweeps, int inner_sweeps, hipStream_t st,

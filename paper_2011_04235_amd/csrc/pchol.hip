@@ -43,8 +43,6 @@ __global__ void k_pchol_init(const EigJob* __restrict__ jobs, int* __restrict__ 
     }
 }
 
-int pchol_max_order() { return 8 * PT; }
-
 // (value, index) arg-max with ties to the lower index
 __device__ __forceinline__ void better(double& v, int& i, double ov, int oi) {
     if (ov > v || (ov == v && oi < i)) {
@@ -240,6 +238,133 @@ __global__ __launch_bounds__(PT) void k_pchol_panel_reg(const EigJob* __restrict
     }
 }
 
+// Panel for cores above the register variants' reach: the rows' remaining diagonal and
+// panel entries stay in global memory, each thread re-reading only its own rows (which it
+// wrote); the loads of RG rows are issued together.
+constexpr int PG = 16;   // panel width of this variant
+template <int RG>
+__global__ __launch_bounds__(PT) void k_pchol_panel_glob(const EigJob* __restrict__ jobs,
+                                                         int* __restrict__ pstate, int j0) {
+    const int jb = blockIdx.x;
+    const EigJob& J = jobs[jb];
+    const int q = static_cast<int>(J.q);
+    if (j0 >= q || pstate[2 * jb + 1]) return;
+    const int64_t ld = J.ld;
+    double* X = J.X;
+    const double* A = J.A;
+    double* d = J.Hpart;
+    __shared__ double s_v[PT / kWave];
+    __shared__ int s_i[PT / kWave];
+    __shared__ double s_piv[PG];
+    __shared__ double s_floor;
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    if (j0 == 0) {
+        double mx = 0.0;
+        for (int i = threadIdx.x; i < q; i += PT) mx = d[i] > mx ? d[i] : mx;
+        mx = wave_max(mx);
+        if (lane == 0) s_v[wave] = mx;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double m = 0.0;
+            for (int w = 0; w < PT / kWave; ++w) m = s_v[w] > m ? s_v[w] : m;
+            const double e = static_cast<double>(ld) * DBL_EPSILON;
+            J.lam[ld + 1] = e * e * m;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) s_floor = J.lam[ld + 1];
+    const int j1 = min(q, j0 + PG);
+    for (int j = j0; j < j1; ++j) {
+        const int jj = j - j0;
+        double bv = -DBL_MAX;
+        int bi = q;
+        for (int base = 0; base < q; base += RG * PT) {
+            double dv[RG];
+#pragma unroll
+            for (int u = 0; u < RG; ++u) {
+                const int i = base + threadIdx.x + u * PT;
+                dv[u] = i < q ? d[i] : -DBL_MAX;
+            }
+#pragma unroll
+            for (int u = 0; u < RG; ++u) better(bv, bi, dv[u], base + threadIdx.x + u * PT);
+        }
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(bv, off, kWave);
+            const int oi = __shfl_xor(bi, off, kWave);
+            better(bv, bi, ov, oi);
+        }
+        if (lane == 0) {
+            s_v[wave] = bv;
+            s_i[wave] = bi;
+        }
+        __syncthreads();
+        double dp = lane < PT / kWave ? s_v[lane] : -DBL_MAX;
+        int p = lane < PT / kWave ? s_i[lane] : q;
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(dp, off, kWave);
+            const int oi = __shfl_xor(p, off, kWave);
+            better(dp, p, ov, oi);
+        }
+        if (!(dp > s_floor) || p >= q) {
+            if (threadIdx.x == 0) {
+                pstate[2 * jb] = j;
+                pstate[2 * jb + 1] = 1;
+            }
+            return;
+        }
+        if (threadIdx.x == p % PT) {
+            double pv[PG];
+#pragma unroll
+            for (int l = 0; l < PG; ++l) pv[l] = l < jj ? X[p + ld * (j0 + l)] : 0.0;
+#pragma unroll
+            for (int l = 0; l < PG; ++l) s_piv[l] = pv[l];
+        }
+        // every thread has read s_v and s_i; the next writes of s_v, s_i and s_piv come after
+        // the next step's first barrier, which every reader of this step's s_piv has passed
+        __syncthreads();
+        const double r = sqrt(dp);
+        const double rinv = 1.0 / r;
+        const double* Ap = A + static_cast<int64_t>(p) * q;
+        for (int base = 0; base < q; base += RG * PT) {
+            double av[RG], dv[RG], xv[RG][PG];
+#pragma unroll
+            for (int u = 0; u < RG; ++u) {
+                const int i = base + threadIdx.x + u * PT;
+                const bool in = i < q;
+                av[u] = in ? Ap[i] : 0.0;
+                dv[u] = in ? d[i] : -DBL_MAX;
+#pragma unroll
+                for (int l = 0; l < PG; ++l) xv[u][l] = (in && l < jj) ? X[i + ld * (j0 + l)] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < RG; ++u) {
+                const int i = base + threadIdx.x + u * PT;
+                if (i >= q) continue;
+                double x;
+                if (i == p) {
+                    x = r;
+                    d[i] = -DBL_MAX;
+                } else if (dv[u] == -DBL_MAX) {
+                    x = 0.0;
+                } else {
+                    double sacc = av[u];
+#pragma unroll
+                    for (int l = 0; l < PG; ++l) sacc -= xv[u][l] * s_piv[l];
+                    x = sacc * rinv;
+                    d[i] = dv[u] - x * x;
+                }
+                X[i + ld * j] = x;
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
+        pstate[2 * jb] = j1;
+        if (j1 >= q) pstate[2 * jb + 1] = 1;
+    }
+}
+
 template <int R, int P>
 static void run_panels(const EigSet& es, unsigned nj, unsigned tgrid, hipStream_t st) {
     const int panels = static_cast<int>((es.max_q + P - 1) / P);
@@ -265,8 +390,16 @@ void pchol_run(const EigSet& es, hipStream_t st) {
         run_panels<2, 16>(es, nj, tgrid, st);
     } else if (es.max_q <= 4 * PT) {
         run_panels<4, 8>(es, nj, tgrid, st);
+    } else if (es.max_q <= 8 * PT) {
+        run_panels<8, 2>(es, nj, tgrid, st);
     } else {
-        run_panels<8, 2>(es, nj, tgrid, st);   // eig_set_create keeps max_q <= 8 * PT
+        const int panels = static_cast<int>((es.max_q + PG - 1) / PG);
+        for (int pnl = 0; pnl < panels; ++pnl) {
+            const int j0 = pnl * PG;
+            hipLaunchKernelGGL(k_pchol_panel_glob<2>, dim3(nj), dim3(PT), 0, st, es.jobs, es.pstate, j0);
+            if (pnl + 1 < panels)
+                hipLaunchKernelGGL(k_pchol_update<PG>, dim3(tgrid, nj), dim3(256), 0, st, es.jobs, es.pstate, j0);
+        }
     }
 }
 

@@ -1,5 +1,6 @@
-"""Full-size parity on the 100000 x 5000 workload (alpha 0.1, 1000 labels) in the bench's
-launch configuration, FP64 and mixed, against quantities of the oracle's result stored by
+"""Full-size parity on the 100000 x 5000 (alpha 0.1, 1000 labels) and 300000 x 10000 (alpha
+0.1, 2000 labels) workloads in the bench's launch configuration, FP64 and mixed, against
+quantities of the oracle's result stored by
 tests/golden/make_large_reference.py (the oracle takes minutes at this size): the singular
 values, the reconstruction and least-squares errors, Z at sampled rows, and rank-r products
 with fixed probe vectors at sampled rows of U and V.
@@ -27,31 +28,37 @@ def say(msg):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module")
-def setup():
-    import torch
+_CACHE = {}
 
-    import paper_2011_04235_amd as fp
-    fp.load()
-    path = os.path.join(GOLDEN, "c3_reference.npz")
-    ref = np.load(path)
-    prob = make_problem("c3")
-    cfg = CONFIGS["c3"]
-    plan = fp.Plan(prob.m, prob.n, prob.indptr, prob.indices, prob.data, alpha=cfg.alpha, k=cfg.k)
-    return torch, fp, ref, prob, cfg, plan
+
+def setup(name):
+    """Problem, plan and stored reference of one workload (built once per module)."""
+    if name not in _CACHE:
+        import torch
+
+        import paper_2011_04235_amd as fp
+        fp.load()
+        say(f"building {name}")
+        ref = np.load(os.path.join(GOLDEN, f"{name}_reference.npz"))
+        prob = make_problem(name)
+        cfg = CONFIGS[name]
+        plan = fp.Plan(prob.m, prob.n, prob.indptr, prob.indices, prob.data, alpha=cfg.alpha, k=cfg.k)
+        _CACHE.clear()
+        _CACHE[name] = (torch, fp, ref, prob, cfg, plan)
+    return _CACHE[name]
 
 
 def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_c3_full_size(setup, precision):
-    torch, fp, ref, prob, cfg, plan = setup
+@pytest.mark.parametrize("name,precision", [("c3", "fp64"), ("c3", "mixed"), ("c5", "fp64"), ("c5", "mixed")])
+def test_full_size(name, precision):
+    torch, fp, ref, prob, cfg, plan = setup(name)
     import scipy.sparse as sp
 
     import oracle
-    say(f"c3 {prob.m}x{prob.n} nnz={prob.nnz} alpha={cfg.alpha} {precision} (graph, autotuned schedule)")
+    say(f"{name} {prob.m}x{prob.n} nnz={prob.nnz} alpha={cfg.alpha} {precision} (graph replay)")
     dev = torch.device("cuda", 0)
     h = fp.Handle(0, precision=precision)
     h.upload_plan(plan)
@@ -77,6 +84,7 @@ def test_c3_full_size(setup, precision):
     assert np.all(err <= bound)
     A = sp.csr_matrix((prob.data, prob.indices, prob.indptr), shape=(prob.m, prob.n))
     Uh, Vh = U.cpu().numpy(), V.cpu().numpy()
+    say("  reconstruction error on the host")
     recon = oracle.recon_error(A, Uh, s, Vh)
     say(f"  recon {recon:.12f} oracle {float(ref['recon']):.12f}")
     assert abs(recon - float(ref["recon"])) <= (1e-10 if precision == "fp64" else 1e-5)

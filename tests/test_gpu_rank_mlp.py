@@ -151,3 +151,50 @@ def test_learned_ranks_end_to_end(env):
 def oracle_recon(A, U, S, V):
     import oracle
     return oracle.recon_error(A, U, S, V)
+
+
+def test_learned_ranks_at_scale(env):
+    """The 300000 x 10000 workload (alpha 0.1): the shipped predictor's ranks against the alpha
+    rule at the same total s_b, through the whole GPU path. Reported: the share of blocks the
+    network ranks (the rest fall back to the alpha rule), the squared A11 truncation loss of
+    both allocations (oracle block spectra) and the reconstruction error of A of both runs.
+    The learned allocation must lose less of A11 and must not raise the error of A."""
+    torch, fp, h, d, RankPredictor, init_params = env
+    from synth import CONFIGS, make_problem
+    cfg = CONFIGS["c5"]
+    say("learned ranks at scale: building the 300000 x 10000 workload")
+    p = make_problem("c5", with_labels=False)
+    pred = RankPredictor.load(os.path.join(os.path.dirname(fp.__file__), "rank_predictor.npz"))
+    dev = torch.device("cuda", 0)
+    import scipy.sparse as sp
+    A = sp.csr_matrix((p.data, p.indices, p.indptr), shape=(p.m, p.n))
+    errs, ranks_used = {}, {}
+    for mode in ("alpha", "learned"):
+        plan = fp.Plan(p.m, p.n, p.indptr, p.indices, p.data, alpha=cfg.alpha, k=cfg.k)
+        blocks = plan.blocks()
+        dense = (blocks[:, 2] > 0) & (blocks[:, 3] > 0)
+        if mode == "learned":
+            X = plan.block_features(p.data)
+            say(f"  network ranks {int(pred.in_range(X).sum())} of {len(X)} blocks")
+            plan.set_block_ranks(pred.block_ranks(h, plan, p.data, plan.block_ranks()[dense]))
+        ranks_used[mode] = plan.block_ranks()[dense]
+        h.upload_plan(plan)
+        say(f"  {mode}: s_b={plan.s_b} s={plan.s} r={plan.r}, GPU run")
+        U, S, V = h.svd(torch.from_numpy(p.indptr).to(dev), torch.from_numpy(p.indices).to(dev),
+                        torch.from_numpy(p.data).to(dev))
+        h.sync()
+        errs[mode] = oracle_recon(A, U.cpu().numpy(), S.cpu().numpy(), V.cpu().numpy())
+        del U, S, V
+        say(f"  {mode}: reconstruction error {errs[mode]:.8f}")
+    assert ranks_used["alpha"].sum() == ranks_used["learned"].sum()
+    say("  A11 block spectra (oracle)")
+    X, spectra, s_alpha, shapes = orank.problem_blocks(p.m, p.n, p.indptr, p.indices, p.data, cfg.alpha, cfg.k)
+    assert np.array_equal(s_alpha, ranks_used["alpha"])
+    e_alpha = orank.truncation_error2(spectra, ranks_used["alpha"])
+    e_net = orank.truncation_error2(spectra, ranks_used["learned"])
+    e_opt = orank.truncation_error2(spectra, orank.eckart_young_ranks(spectra, int(s_alpha.sum())))
+    say(f"  A11 loss: alpha rule {e_alpha:.6g}, network {e_net:.6g}, optimum {e_opt:.6g}; "
+        f"recon alpha {errs['alpha']:.8f} learned {errs['learned']:.8f}")
+    assert e_net < e_alpha
+    assert errs["learned"] <= errs["alpha"] + 1e-4
+
