@@ -26,6 +26,11 @@ import numpy as np  # noqa: E402
 import scipy.sparse as sp  # noqa: E402
 
 
+def progress(msg):
+    """Progress lines on stderr (stdout carries only the result line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def svd_thin_flops(p, q):
     """Golub & Van Loan R-SVD count for a p x q (p >= q) thin SVD with U and V."""
     p, q = max(p, q), min(p, q)
@@ -145,7 +150,9 @@ def run_batched_workload(args, torch, fp):
     dev = torch.device("cuda", 0)
     probs, plans, F, dev_in = [], [], [], []
     t0 = time.perf_counter()
-    for c in cfgs:
+    for ci_, c in enumerate(cfgs):
+        if ci_ % 8 == 0:
+            progress(f"generating matrices {ci_}..{min(ci_ + 8, len(cfgs)) - 1}")
         prob = make_problem(c)
         plan = fp.Plan(prob.m, prob.n, prob.indptr, prob.indices, prob.data, alpha=c.alpha, k=c.k)
         F.append(flop_model(plan, plan.blocks(), plan.block_ranks(), c.L)["total"])
@@ -176,6 +183,7 @@ def run_batched_workload(args, torch, fp):
 
     res = {}
     for prec in (["fp64", "mixed"] if args.precision == "both" else [args.precision]):
+        progress(f"{prec}: per-matrix runs")
         # plain: one handle per matrix, in sequence
         hs = []
         for plan in plans:
@@ -195,6 +203,7 @@ def run_batched_workload(args, torch, fp):
         for h in hs:
             h.sync()
         del hs
+        progress(f"{prec}: per-matrix {ms_plain:.1f} ms/step; batched runs (autotune first)")
         # batched: one batch over all matrices on one handle
         h = fp.Handle(0, precision=prec)
         b = fp.Batch(h, plans)
@@ -212,6 +221,7 @@ def run_batched_workload(args, torch, fp):
         for _ in range(args.warmup):
             batched_step()
         ms_batched = timed(batched_step, args.steps) * 1e3
+        progress(f"{prec}: batched {ms_batched:.1f} ms/step")
         status, sweeps = b.sync()
         rotated = b.rotations()
         graph_launches = b.last_graph_launches()
@@ -258,6 +268,7 @@ def run_batched_workload(args, torch, fp):
             cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
         except Exception:  # pragma: no cover
             cores = os.cpu_count() or 1
+        progress("oracle on the host cores")
         t0 = time.perf_counter()
         done_f = 0.0
         done = 0
@@ -338,7 +349,9 @@ def main():
         return run_batched_workload(args, torch, fp)
 
     cfg = CONFIGS[args.config]
+    progress(f"generating {args.config}")
     prob = make_problem(cfg)
+    progress(f"planning {prob.m}x{prob.n}, {prob.nnz} nonzeros")
     fp.load()
     t0 = time.perf_counter()
     plan = fp.Plan(prob.m, prob.n, prob.indptr, prob.indices, prob.data, alpha=cfg.alpha, k=cfg.k)
@@ -370,6 +383,7 @@ def main():
     def run_path(precision, batched):
         """Plain form: eager launches with the default schedule. Batched form: the
         autotuned schedule and the stage chain replayed from HIP graphs."""
+        progress(f"{precision} {'batched' if batched else 'plain'}: start")
         h = fp.Handle(0, precision=precision)
         h.upload_plan(plan)
         U = torch.empty((m, r), dtype=torch.float64, device=dev)
@@ -379,6 +393,7 @@ def main():
         tune_report = None
         if batched:
             tune_report = h.autotune(rowptr, col, val, out=(U, S, V))
+            progress(f"  autotuned: {tune_report.split('chose')[-1].strip()}")
             h.set_graph(True)
 
         def step():
@@ -403,6 +418,7 @@ def main():
             h.timing_start(args.roofline_kernel)
         dt = timed(args.steps)
         h.sync()
+        progress(f"  timed {args.steps} steps: {dt * 1e3:.2f} ms/step")
         graph_launches = h.last_graph_launches()
         if batched:
             h.set_graph(False)
@@ -445,6 +461,7 @@ def main():
                 "timed_in": head_key + (" (eager pass of the same schedule)" if "batched" in head_key else "")}
     base = None
     if not args.no_cpu_baseline:
+        progress("oracle on the host cores")
         base = cpu_baseline(prob, cfg.alpha, F["total"], args.cpu_budget)
     compare = {p: {"ms_per_step": round(v["ms"], 3), "tflops": round(F["total"] / v["ms"] / 1e9, 4),
                    "recon_error": v["recon"], "sweeps": v["sweeps"], "tuning": v["tuning"],
