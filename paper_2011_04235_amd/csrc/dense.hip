@@ -146,6 +146,7 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const double* __restrict__ A, i
 int gemm_tn_splits(int64_t M, int64_t N, int64_t K) {
     // enough workgroups to cover the chip (~4 per CU), chunks of at least 256 rows of K
     const int64_t tiles = ((M + TM - 1) / TM) * ((N + TN - 1) / TN);
+    if (tiles <= 0) return 1;   // empty product (e.g. a core of rank 0)
     int64_t splits = (1024 + tiles - 1) / tiles;
     splits = std::min<int64_t>(splits, (K + 255) / 256);
     return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(splits, 256)));
