@@ -10,3 +10,6 @@ from .fastpi import (  # noqa: F401
     target_rank, split_blocks, block_svd, row_update, column_update, fastpi_svd,
     pinv_apply, sigma_pinv, recon_error, ls_residual, orthonormality_error, OracleResult,
 )
+from .evaluate import (  # noqa: F401
+    labels_dense, pinv_apply_sparse, row_scores, rank_k, precision_at_k, topk_hits, p_at_k,
+)

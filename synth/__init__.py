@@ -22,6 +22,16 @@ in this order):
    first) so that index and degree are uncorrelated;
 5. values in CSR order: uniform(0,1] as 1-U[0,1), or lognormal(0,1) as exp(N(0,1));
 6. labels Y (m x L) i.i.d. Bernoulli(p) in {0,1}, drawn row-major in chunks.
+
+The evaluation loop of Application 1 needs labels that the features predict, which i.i.d.
+labels are not. ``make_labelled_problem`` draws, from its own stream (seed + 1):
+1. the feature matrix by steps 1-5 above;
+2. for each label, ``triggers`` distinct trigger features uniformly at random; the label is
+   positive on every row that stores one of them;
+3. each such positive is dropped with probability ``drop``;
+4. ``round(noise * planted)`` positives at uniform (row, label) positions are added;
+5. the rows are split by a random permutation: the first ``round(test_frac * m)`` go to the
+   test set (kept in increasing row order), the rest to the training set.
 """
 from __future__ import annotations
 
@@ -31,7 +41,8 @@ import math
 import numpy as np
 
 __all__ = ["Config", "CONFIGS", "Problem", "make_problem", "make_csr", "make_labels",
-           "sample_batch_configs", "small_config"]
+           "sample_batch_configs", "small_config", "CsrPart", "LabelledProblem",
+           "make_labelled_problem", "csr_rows"]
 
 
 @dataclasses.dataclass(frozen=True)
@@ -165,3 +176,77 @@ def make_problem(cfg: Config | str, with_labels=True) -> Problem:
     indptr, indices, data = make_csr(cfg, rng)
     Y = make_labels(cfg, rng) if with_labels else None
     return Problem(cfg, indptr, indices, data, Y)
+
+
+def csr_rows(indptr, indices, data, rows):
+    """The CSR of the given rows (in the given order) of a CSR matrix."""
+    rows = np.asarray(rows, np.int64)
+    lens = indptr[rows + 1] - indptr[rows]
+    out_ptr = np.zeros(rows.size + 1, np.int64)
+    np.cumsum(lens, out=out_ptr[1:])
+    src = np.repeat(indptr[rows] - out_ptr[:-1], lens) + np.arange(int(out_ptr[-1]), dtype=np.int64)
+    return out_ptr, indices[src], (data[src] if data is not None else None)
+
+
+@dataclasses.dataclass
+class CsrPart:
+    """Rows of a feature matrix with their labels (CSR, values 1)."""
+    m: int
+    n: int
+    indptr: np.ndarray
+    indices: np.ndarray
+    data: np.ndarray
+    y_indptr: np.ndarray
+    y_indices: np.ndarray
+    rows: np.ndarray      # row ids in the full matrix
+
+    @property
+    def nnz(self):
+        return int(self.indptr[-1])
+
+    @property
+    def y_nnz(self):
+        return int(self.y_indptr[-1])
+
+
+@dataclasses.dataclass
+class LabelledProblem:
+    cfg: Config
+    L: int
+    train: CsrPart
+    test: CsrPart
+
+
+def make_labelled_problem(cfg: Config | str, test_frac=0.1, triggers=3, drop=0.1,
+                          noise=0.1) -> LabelledProblem:
+    if isinstance(cfg, str):
+        cfg = CONFIGS[cfg]
+    rng = np.random.default_rng(cfg.seed + 1)
+    indptr, indices, data = make_csr(cfg, rng)
+    m, n, L = cfg.m, cfg.n, cfg.L
+    # rows of every feature (CSC pattern)
+    rows_of = np.repeat(np.arange(m, dtype=np.int64), np.diff(indptr))
+    order = np.argsort(indices, kind="stable")
+    col_ptr = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(indices, minlength=n), out=col_ptr[1:])
+    col_rows = rows_of[order]
+    keys = []
+    for lab in range(L):
+        trig = rng.choice(n, size=min(triggers, n), replace=False)
+        r = np.unique(np.concatenate([col_rows[col_ptr[j]:col_ptr[j + 1]] for j in trig]))
+        keys.append(r * L + lab)
+    keys = np.concatenate(keys) if keys else np.zeros(0, np.int64)
+    keys = keys[rng.random(keys.size) >= drop]
+    extra = rng.integers(0, m * L, size=int(round(noise * keys.size)), dtype=np.int64)
+    keys = np.unique(np.concatenate([keys, extra]))
+    y_rows, y_cols = keys // L, (keys % L).astype(np.int32)
+    y_ptr = np.zeros(m + 1, np.int64)
+    np.cumsum(np.bincount(y_rows, minlength=m), out=y_ptr[1:])
+    perm = rng.permutation(m)
+    nt = int(round(test_frac * m))
+    parts = []
+    for sel in (np.sort(perm[nt:]), np.sort(perm[:nt])):
+        a_ptr, a_idx, a_val = csr_rows(indptr, indices, data, sel)
+        b_ptr, b_idx, _ = csr_rows(y_ptr, y_cols, None, sel)
+        parts.append(CsrPart(int(sel.size), n, a_ptr, a_idx, a_val, b_ptr, b_idx, sel))
+    return LabelledProblem(cfg, L, parts[0], parts[1])
