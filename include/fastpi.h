@@ -77,6 +77,7 @@ typedef struct {
 typedef struct fastpi_plan fastpi_plan;
 typedef struct fastpi_handle fastpi_handle;
 typedef struct fastpi_batch fastpi_batch;
+typedef struct fastpi_labels fastpi_labels;
 
 /* ceil(alpha * x) evaluated in IEEE double, clamped at 0 (Table 1: r = ceil(alpha n)). */
 int64_t fastpi_target_rank(double alpha, int64_t x);
@@ -199,6 +200,48 @@ int fastpi_svd(fastpi_handle* h, const int64_t* rowptr, const int32_t* col, cons
  */
 int fastpi_apply(fastpi_handle* h, int64_t m, int64_t n, int64_t r, const double* U,
                  const double* S, const double* V, int64_t L, const double* Y, double* Z);
+
+/*
+ * Sparse label matrix of Application 1 (each row of Y is a binary label vector with few
+ * positives). Y (m x L) is given as a host CSR: rowptr int64[m+1] (rowptr[0] = 0, monotone),
+ * col int32[nnz] in [0, L), val double[nnz] or NULL for all ones. The object keeps a device
+ * copy of Y^T (per label, its rows in increasing order) and the work split used by
+ * fastpi_apply_sparse; the host arrays may be freed when the call returns (it waits for the
+ * copies on the handle's stream). Errors: FASTPI_EINVAL for a malformed pattern,
+ * FASTPI_ENONFINITE for a non-finite value, FASTPI_ENOMEM.
+ */
+int fastpi_labels_create(fastpi_labels** y, fastpi_handle* h, int64_t m, int64_t L,
+                         const int64_t* rowptr, const int32_t* col, const double* val);
+void fastpi_labels_destroy(fastpi_labels* y);
+int fastpi_labels_nnz(const fastpi_labels* y, int64_t* nnz);
+
+/*
+ * Pseudoinverse apply with a sparse Y (Application 1, Problem 1):
+ * Z = V diag(S^+) U^T Y, S^+ as in fastpi_apply. U^T Y is formed as Y^T U over Y's
+ * positives only (cost proportional to nnz(Y) * r rather than m * L * r), in a fixed
+ * summation order, then Z = V (Y^T U diag(S^+))^T.
+ *   U : device double[m*r], S : device double[r], V : device double[n*r], row-major;
+ *   Y : labels created on this handle's device with m rows;
+ *   Z : device double[n*L] row-major output (zero when r = 0).
+ */
+int fastpi_apply_sparse(fastpi_handle* h, int64_t m, int64_t n, int64_t r, const double* U,
+                        const double* S, const double* V, const fastpi_labels* Y, double* Z);
+
+/*
+ * Top-k precision counts of the accuracy experiment (Section 4) on held-out rows. For each
+ * row x of a device CSR test matrix (rows x n: rowptr int64[rows+1], col int32, val double),
+ * the score vector yhat = Z^T x (Z: device double[n*L] row-major) is accumulated over x's
+ * entries in storage order, one rounded multiply and one rounded add per entry; labels are
+ * ranked by descending score, equal scores to the lower label, non-finite scores never.
+ * hits[row * nk + t] (device int32[rows*nk]) = number of positives of the row (device CSR
+ * y_rowptr int64[rows+1], y_col int32) among its ks[t] top-ranked labels; P@k of the set is
+ * sum over rows of hits / (rows * k). ks is a host array of nk (1..16) values in [1, 64].
+ * A row with a column outside [0, n) gets -1 counts. The CSR arrays must be well formed
+ * (the kernel reads rowptr[0..rows] and the entries they address).
+ */
+int fastpi_topk_hits(fastpi_handle* h, int64_t rows, int64_t n, int64_t L, const int64_t* rowptr,
+                     const int32_t* col, const double* val, const double* Z, const int64_t* y_rowptr,
+                     const int32_t* y_col, int32_t nk, const int32_t* ks, int32_t* hits);
 
 /*
  * Intermediate results of the last fastpi_svd on this handle, for stage-level checks.

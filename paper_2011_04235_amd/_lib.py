@@ -101,6 +101,14 @@ SIGNATURES = [
     ("fastpi_batch_get_tuning", c_int, [c_void_p, POINTER(Tuning)]),
     ("fastpi_batch_autotune", c_int, [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
                                       POINTER(c_void_p), ctypes.c_char_p, c_int64]),
+    ("fastpi_labels_create", c_int, [POINTER(c_void_p), c_void_p, c_int64, c_int64, c_void_p, c_void_p,
+                                     c_void_p]),
+    ("fastpi_labels_destroy", None, [c_void_p]),
+    ("fastpi_labels_nnz", c_int, [c_void_p, POINTER(c_int64)]),
+    ("fastpi_apply_sparse", c_int, [c_void_p, c_int64, c_int64, c_int64, c_void_p, c_void_p, c_void_p,
+                                    c_void_p, c_void_p]),
+    ("fastpi_topk_hits", c_int, [c_void_p, c_int64, c_int64, c_int64, c_void_p, c_void_p, c_void_p,
+                                 c_void_p, c_void_p, c_void_p, ctypes.c_int32, c_void_p, c_void_p]),
     ("fastpi_last_error", ctypes.c_char_p, []),
 ]
 
@@ -283,6 +291,36 @@ class Handle:
                                    _dptr(Z)))
         return Z
 
+    def apply_sparse(self, U, S, V, labels, out=None):
+        """Z = V diag(S^+) U^T Y for a sparse label matrix (a Labels object)."""
+        torch = self.torch
+        m, r = U.shape
+        n = V.shape[0]
+        Z = torch.empty((n, labels.L), dtype=torch.float64, device=self.device) if out is None else out
+        for t in (U, S, V, Z):
+            assert t.is_contiguous() and t.dtype == torch.float64 and t.device == self.device
+        _check(load().fastpi_apply_sparse(self._h, m, n, r, _dptr(U), _dptr(S), _dptr(V), labels._y,
+                                          _dptr(Z)))
+        return Z
+
+    def topk_hits(self, rowptr, col, val, Z, y_rowptr, y_col, ks, out=None):
+        """Top-k hit counts of held-out rows (device CSR features and labels); returns a
+        device int32 tensor [rows, len(ks)]."""
+        torch = self.torch
+        rows = rowptr.shape[0] - 1
+        n, L = Z.shape
+        ks_h = np.ascontiguousarray(ks, dtype=np.int32)
+        hits = torch.empty((rows, ks_h.size), dtype=torch.int32, device=self.device) if out is None else out
+        for t in (rowptr, col, val, Z, y_rowptr, y_col, hits):
+            assert t.is_contiguous() and t.device == self.device
+        assert rowptr.dtype == torch.int64 and y_rowptr.dtype == torch.int64
+        assert col.dtype == torch.int32 and y_col.dtype == torch.int32
+        assert val.dtype == torch.float64 and Z.dtype == torch.float64
+        _check(load().fastpi_topk_hits(self._h, rows, n, L, _dptr(rowptr), _dptr(col), _dptr(val), _dptr(Z),
+                                       _dptr(y_rowptr), _dptr(y_col), int(ks_h.size), _ptr(ks_h),
+                                       _dptr(hits)))
+        return hits
+
     def stage_output(self, which):
         torch = self.torch
         info = self.plan.info
@@ -381,6 +419,32 @@ class Handle:
         if h is not None and _lib is not None:
             _lib.fastpi_destroy(h)
             self._h = None
+
+
+class Labels:
+    """A sparse label matrix Y (m x L, host CSR; values default to one) on a handle's device."""
+
+    def __init__(self, handle: Handle, m, L, indptr, indices, data=None):
+        lib = load()
+        self.m, self.L = int(m), int(L)
+        indptr = np.ascontiguousarray(indptr, dtype=np.int64)
+        indices = np.ascontiguousarray(indices, dtype=np.int32)
+        data = None if data is None else np.ascontiguousarray(data, dtype=np.float64)
+        y = c_void_p()
+        _check(lib.fastpi_labels_create(ctypes.byref(y), handle._h, self.m, self.L, _ptr(indptr),
+                                        _ptr(indices), _ptr(data)))
+        self._y = y
+
+    @property
+    def nnz(self):
+        out = c_int64(0)
+        _check(load().fastpi_labels_nnz(self._y, ctypes.byref(out)))
+        return out.value
+
+    def __del__(self):
+        if getattr(self, "_y", None) is not None and _lib is not None:
+            _lib.fastpi_labels_destroy(self._y)
+            self._y = None
 
 
 def _ptr_array(tensors):

@@ -51,6 +51,20 @@ struct fastpi_handle {
     // rank-predictor scratch
     float* mws = nullptr;
     size_t mws_bytes = 0;
+    // evaluation scratch (scores beyond the LDS capacity)
+    double* ews = nullptr;
+    size_t ews_bytes = 0;
+};
+
+// A sparse label matrix Y (m x L) held on the device as its transpose in CSR (per label,
+// the rows where it is positive, with their values) and a segment table over labels.
+struct fastpi_labels {
+    int device = 0;
+    int64_t m = 0, L = 0, nnz = 0;
+    int32_t* rows = nullptr;   // device, per label in increasing row order
+    double* vals = nullptr;
+    SegDev seg{};
+    std::vector<void*> allocs;
 };
 
 struct fastpi_batch {
@@ -359,6 +373,7 @@ void fastpi_destroy(fastpi_handle* h) {
     if (h->siws) hipFree(h->siws);
     if (h->sa) hipFree(h->sa);
     if (h->mws) hipFree(h->mws);
+    if (h->ews) hipFree(h->ews);
     if (h->status) hipFree(h->status);
     if (h->host_pinned) hipHostFree(h->host_pinned);
     if (h->copy_stream) hipStreamDestroy(h->copy_stream);
@@ -426,6 +441,181 @@ int fastpi_apply(fastpi_handle* h, int64_t m, int64_t n, int64_t r, const double
     const bool mixed = h->opts.precision == FASTPI_MIXED;
     launch_gemm_tn(U, r, Y, L, r, L, m, W, L, inv, nullptr, part, sp, st, mixed);
     launch_gemm_nn(V, r, nullptr, W, L, n, L, r, Z, L, nullptr, st, mixed);
+    return check_launch();
+}
+
+int fastpi_labels_create(fastpi_labels** out, fastpi_handle* h, int64_t m, int64_t L,
+                         const int64_t* rowptr, const int32_t* col, const double* val) {
+    if (!out || !h || m < 0 || L < 0 || L > INT32_MAX || m > INT32_MAX || !rowptr) {
+        set_error("bad labels arguments");
+        return FASTPI_EINVAL;
+    }
+    *out = nullptr;
+    if (rowptr[0] != 0) {
+        set_error("label rowptr[0] must be 0");
+        return FASTPI_EINVAL;
+    }
+    for (int64_t i = 0; i < m; ++i)
+        if (rowptr[i + 1] < rowptr[i]) {
+            set_error("label rowptr is not monotone at row " + std::to_string(i));
+            return FASTPI_EINVAL;
+        }
+    const int64_t nnz = rowptr[m];
+    if (nnz > 0 && !col) {
+        set_error("null label column array");
+        return FASTPI_EINVAL;
+    }
+    for (int64_t e = 0; e < nnz; ++e) {
+        if (col[e] < 0 || col[e] >= L) {
+            set_error("label index out of range at entry " + std::to_string(e));
+            return FASTPI_EINVAL;
+        }
+        if (val && !std::isfinite(val[e])) {
+            set_error("non-finite label value at entry " + std::to_string(e));
+            return FASTPI_ENONFINITE;
+        }
+    }
+    // transpose: per label, its rows in increasing order (counting sort is stable)
+    std::vector<int64_t> lptr(static_cast<size_t>(L) + 1, 0);
+    for (int64_t e = 0; e < nnz; ++e) ++lptr[static_cast<size_t>(col[e]) + 1];
+    for (int64_t l = 0; l < L; ++l) lptr[l + 1] += lptr[l];
+    std::vector<int32_t> trow(static_cast<size_t>(nnz));
+    std::vector<double> tval(static_cast<size_t>(nnz));
+    std::vector<int64_t> fill(lptr.begin(), lptr.end() - 1);
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            const int64_t d = fill[col[e]]++;
+            trow[d] = static_cast<int32_t>(i);
+            tval[d] = val ? val[e] : 1.0;
+        }
+    Segments sg;
+    build_segments(lptr, sg);
+    auto* y = new (std::nothrow) fastpi_labels();
+    if (!y) {
+        set_error("out of host memory");
+        return FASTPI_ENOMEM;
+    }
+    y->device = h->device;
+    y->m = m;
+    y->L = L;
+    y->nnz = nnz;
+    auto fail = [&](int rc) {
+        for (void* p : y->allocs) hipFree(p);
+        delete y;
+        return rc;
+    };
+    if (hipSetDevice(h->device) != hipSuccess) {
+        set_error("hipSetDevice failed");
+        return fail(FASTPI_EHIP);
+    }
+    if (nnz > 0) {
+        void* p = nullptr;
+        if (hipMalloc(&p, nnz * sizeof(int32_t)) != hipSuccess) {
+            set_error("device allocation failed (labels)");
+            return fail(FASTPI_ENOMEM);
+        }
+        y->allocs.push_back(p);
+        y->rows = static_cast<int32_t*>(p);
+        if (hipMalloc(&p, nnz * sizeof(double)) != hipSuccess) {
+            set_error("device allocation failed (labels)");
+            return fail(FASTPI_ENOMEM);
+        }
+        y->allocs.push_back(p);
+        y->vals = static_cast<double*>(p);
+        if (hipMemcpyAsync(y->rows, trow.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice, h->stream) !=
+                hipSuccess ||
+            hipMemcpyAsync(y->vals, tval.data(), nnz * sizeof(double), hipMemcpyHostToDevice, h->stream) !=
+                hipSuccess) {
+            set_error("label upload failed");
+            return fail(FASTPI_EHIP);
+        }
+    }
+    int rc = upload_segments(y->allocs, sg, y->seg, h->stream);
+    if (rc != FASTPI_OK) return fail(rc);
+    // the host tables above go out of scope: wait for the copies
+    if (hipStreamSynchronize(h->stream) != hipSuccess) {
+        set_error("label upload failed");
+        return fail(FASTPI_EHIP);
+    }
+    *out = y;
+    return FASTPI_OK;
+}
+
+void fastpi_labels_destroy(fastpi_labels* y) {
+    if (!y) return;
+    hipSetDevice(y->device);
+    hipDeviceSynchronize();
+    for (void* p : y->allocs) hipFree(p);
+    delete y;
+}
+
+int fastpi_labels_nnz(const fastpi_labels* y, int64_t* nnz) {
+    if (!y || !nnz) {
+        set_error("null labels or output");
+        return FASTPI_EINVAL;
+    }
+    *nnz = y->nnz;
+    return FASTPI_OK;
+}
+
+int fastpi_apply_sparse(fastpi_handle* h, int64_t m, int64_t n, int64_t r, const double* U,
+                        const double* S, const double* V, const fastpi_labels* Y, double* Z) {
+    if (!h || !Y || m <= 0 || n <= 0 || r < 0 || Y->m != m || Y->device != h->device) {
+        set_error("bad handle, labels or sizes (the labels must have m rows, on the handle's device)");
+        return FASTPI_EINVAL;
+    }
+    const int64_t L = Y->L;
+    if (L == 0) return FASTPI_OK;
+    if (!Z || (r > 0 && (!U || !S || !V))) {
+        set_error("null device pointer");
+        return FASTPI_EINVAL;
+    }
+    HIP_TRY(hipSetDevice(h->device));
+    hipStream_t st = h->stream;
+    if (r == 0) {
+        launch_fill(Z, n * L, 0.0, st);
+        return check_launch();
+    }
+    const size_t need = static_cast<size_t>(r + L * r + Y->seg.npart * r) * sizeof(double);
+    int rc = grow(h->aws, h->aws_bytes, need, st, "apply scratch");
+    if (rc != FASTPI_OK) return rc;
+    double* inv = h->aws;
+    double* C = inv + r;          // L x r: Y^T U diag(S^+)
+    double* part = C + L * r;
+    launch_pinv_sigma(S, r, static_cast<double>(std::max(m, n)) * DBL_EPSILON, inv, st);
+    launch_fill(C, L * r, 0.0, st);   // labels without a positive keep a zero row
+    launch_spmm_rows(Y->seg, Y->rows, Y->vals, U, r, inv, C, r, nullptr, false, part, st);
+    launch_gemm_nt(V, r, C, r, n, L, r, Z, L, st, h->opts.precision == FASTPI_MIXED);
+    return check_launch();
+}
+
+int fastpi_topk_hits(fastpi_handle* h, int64_t rows, int64_t n, int64_t L, const int64_t* rowptr,
+                     const int32_t* col, const double* val, const double* Z, const int64_t* y_rowptr,
+                     const int32_t* y_col, int32_t nk, const int32_t* ks, int32_t* hits) {
+    if (!h || rows < 0 || n < 0 || L < 0 || L > INT32_MAX - 1 || nk < 1 || nk > kTopkMaxKs || !ks) {
+        set_error("bad handle or sizes (1 <= nk <= 16)");
+        return FASTPI_EINVAL;
+    }
+    int kmax = 0;
+    for (int i = 0; i < nk; ++i) {
+        if (ks[i] < 1 || ks[i] > kTopkMaxK) {
+            set_error("every k must lie in [1, 64]");
+            return FASTPI_EINVAL;
+        }
+        kmax = std::max(kmax, static_cast<int>(ks[i]));
+    }
+    if (rows == 0) return FASTPI_OK;
+    if (!rowptr || !col || !val || !Z || !y_rowptr || !y_col || !hits) {
+        set_error("null device pointer");
+        return FASTPI_EINVAL;
+    }
+    HIP_TRY(hipSetDevice(h->device));
+    const int64_t sd = topk_scratch_doubles(rows, L);
+    if (sd > 0) {
+        int rc = grow(h->ews, h->ews_bytes, static_cast<size_t>(sd) * sizeof(double), h->stream, "evaluation scratch");
+        if (rc != FASTPI_OK) return rc;
+    }
+    launch_topk_hits(rows, n, L, rowptr, col, val, Z, y_rowptr, y_col, nk, ks, kmax, hits, h->ews, h->stream);
     return check_launch();
 }
 

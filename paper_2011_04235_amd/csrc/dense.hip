@@ -9,6 +9,7 @@
 //   gemm_tn : C_part[z] = A[kz]^T B[kz]  (A: K x M, B: K x N, both row-major; split over K)
 //   gemm_nn : C[ci(i)] = A[ai(i)] B        (A: M x K row-major with optional row gather,
 //                                            B: K x N row-major, optional C row scatter)
+//   gemm_nt : C = A B^T                    (A: M x K, B: N x K, both row-major)
 #include "device_common.h"
 #include "kernels.h"
 
@@ -85,7 +86,7 @@ __global__ void k_reduce_parts(const double* __restrict__ Cpart, int nsplit, int
     }
 }
 
-template <typename Tc>
+template <typename Tc, bool TB>
 __global__ __launch_bounds__(256) void k_gemm_nn(const double* __restrict__ A, int64_t lda,
                                                  const int* __restrict__ arow,
                                                  const double* __restrict__ B, int64_t ldb,
@@ -110,9 +111,15 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const double* __restrict__ A, i
             As[kk][ii] = static_cast<Tc>(v);
         }
         for (int e = threadIdx.x; e < TK * TN; e += 256) {
-            const int kk = e / TN, jj = e % TN;
-            const int64_t k = k0 + kk, j = j0 + jj;
-            Bs[kk][jj] = static_cast<Tc>((k < K && j < N) ? B[k * ldb + j] : 0.0);
+            if (TB) {   // B is N x K row-major: read along k
+                const int jj = e / TK, kk = e % TK;
+                const int64_t k = k0 + kk, j = j0 + jj;
+                Bs[kk][jj] = static_cast<Tc>((k < K && j < N) ? B[j * ldb + k] : 0.0);
+            } else {
+                const int kk = e / TN, jj = e % TN;
+                const int64_t k = k0 + kk, j = j0 + jj;
+                Bs[kk][jj] = static_cast<Tc>((k < K && j < N) ? B[k * ldb + j] : 0.0);
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -176,11 +183,23 @@ void launch_gemm_nn(const double* A, int64_t lda, const int* arow, const double*
     if (M <= 0 || N <= 0) return;
     dim3 grid(static_cast<unsigned>((M + TM - 1) / TM), static_cast<unsigned>((N + TN - 1) / TN));
     if (fp32)
-        hipLaunchKernelGGL(k_gemm_nn<float>, grid, dim3(256), 0, st, A, lda, arow, B, ldb, M, N, K, C, ldc,
-                           crow);
+        hipLaunchKernelGGL((k_gemm_nn<float, false>), grid, dim3(256), 0, st, A, lda, arow, B, ldb, M, N, K, C,
+                           ldc, crow);
     else
-        hipLaunchKernelGGL(k_gemm_nn<double>, grid, dim3(256), 0, st, A, lda, arow, B, ldb, M, N, K, C, ldc,
-                           crow);
+        hipLaunchKernelGGL((k_gemm_nn<double, false>), grid, dim3(256), 0, st, A, lda, arow, B, ldb, M, N, K, C,
+                           ldc, crow);
+}
+
+void launch_gemm_nt(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M, int64_t N,
+                    int64_t K, double* C, int64_t ldc, hipStream_t st, bool fp32) {
+    if (M <= 0 || N <= 0) return;
+    dim3 grid(static_cast<unsigned>((M + TM - 1) / TM), static_cast<unsigned>((N + TN - 1) / TN));
+    if (fp32)
+        hipLaunchKernelGGL((k_gemm_nn<float, true>), grid, dim3(256), 0, st, A, lda, nullptr, B, ldb, M, N, K, C,
+                           ldc, nullptr);
+    else
+        hipLaunchKernelGGL((k_gemm_nn<double, true>), grid, dim3(256), 0, st, A, lda, nullptr, B, ldb, M, N, K, C,
+                           ldc, nullptr);
 }
 
 }  // namespace fastpi

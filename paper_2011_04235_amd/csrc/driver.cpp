@@ -36,7 +36,7 @@ int launch_status() {
 }
 
 template <typename T>
-int upload(Instance& I, T*& dst, const T* src, size_t count, hipStream_t st) {
+int upload(std::vector<void*>& allocs, T*& dst, const T* src, size_t count, hipStream_t st) {
     dst = nullptr;
     if (count == 0) return FASTPI_OK;
     void* p = nullptr;
@@ -44,32 +44,9 @@ int upload(Instance& I, T*& dst, const T* src, size_t count, hipStream_t st) {
         set_error("device allocation failed for a plan table");
         return FASTPI_ENOMEM;
     }
-    I.allocs.push_back(p);
+    allocs.push_back(p);
     dst = static_cast<T*>(p);
     HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyHostToDevice, st));
-    return FASTPI_OK;
-}
-
-int upload_segments(Instance& I, const Segments& s, SegDev& d, hipStream_t st) {
-    int rc;
-    d = SegDev{};
-    int32_t *owner = nullptr, *pidx = nullptr, *mo = nullptr, *mp = nullptr;
-    int64_t *b = nullptr, *e = nullptr;
-    if ((rc = upload(I, owner, s.owner.data(), s.owner.size(), st)) != FASTPI_OK) return rc;
-    if ((rc = upload(I, pidx, s.pidx.data(), s.pidx.size(), st)) != FASTPI_OK) return rc;
-    if ((rc = upload(I, b, s.begin.data(), s.begin.size(), st)) != FASTPI_OK) return rc;
-    if ((rc = upload(I, e, s.end.data(), s.end.size(), st)) != FASTPI_OK) return rc;
-    if ((rc = upload(I, mo, s.multi_owner.data(), s.multi_owner.size(), st)) != FASTPI_OK) return rc;
-    if ((rc = upload(I, mp, s.multi_ptr.data(), s.multi_ptr.size(), st)) != FASTPI_OK) return rc;
-    d.owner = owner;
-    d.pidx = pidx;
-    d.begin = b;
-    d.end = e;
-    d.multi_owner = mo;
-    d.multi_ptr = mp;
-    d.nseg = static_cast<int64_t>(s.owner.size());
-    d.nmulti = static_cast<int64_t>(s.multi_owner.size());
-    d.npart = s.npart;
     return FASTPI_OK;
 }
 
@@ -100,6 +77,29 @@ int ensure(T*& buf, size_t& have, size_t bytes, size_t cap, hipStream_t st) {
 constexpr int kMinGramRows = 64;
 
 }  // namespace
+
+int upload_segments(std::vector<void*>& allocs, const Segments& s, SegDev& d, hipStream_t st) {
+    int rc;
+    d = SegDev{};
+    int32_t *owner = nullptr, *pidx = nullptr, *mo = nullptr, *mp = nullptr;
+    int64_t *b = nullptr, *e = nullptr;
+    if ((rc = upload(allocs, owner, s.owner.data(), s.owner.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(allocs, pidx, s.pidx.data(), s.pidx.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(allocs, b, s.begin.data(), s.begin.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(allocs, e, s.end.data(), s.end.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(allocs, mo, s.multi_owner.data(), s.multi_owner.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(allocs, mp, s.multi_ptr.data(), s.multi_ptr.size(), st)) != FASTPI_OK) return rc;
+    d.owner = owner;
+    d.pidx = pidx;
+    d.begin = b;
+    d.end = e;
+    d.multi_owner = mo;
+    d.multi_ptr = mp;
+    d.nseg = static_cast<int64_t>(s.owner.size());
+    d.nmulti = static_cast<int64_t>(s.multi_owner.size());
+    d.npart = s.npart;
+    return FASTPI_OK;
+}
 
 bool tuning_valid(const Tuning& t) {
     return t.block_lds >= 4096 && t.block_lds <= 60 * 1024 && t.block_wgs_per_cu >= 1 &&
@@ -157,24 +157,24 @@ int instance_upload(Instance& I, const Plan& p, size_t ws_cap, hipStream_t st) {
         gs += ((pp * qq + qq * qq + extra + 31) / 32) * 32;
     }
     int rc;
-    if ((rc = upload(I, d.work, p.work.data(), p.work.size(), st)) != FASTPI_OK) return rc;
-    if ((rc = upload(I, d.dst0, p.dst0.data(), p.dst0.size(), st)) != FASTPI_OK) return rc;
-    if ((rc = upload(I, d.dst1, p.dst1.data(), p.dst1.size(), st)) != FASTPI_OK) return rc;
-    if ((rc = upload(I, d.a21_rowptr, p.a21_rowptr.data(), p.a21_rowptr.size(), st)) != FASTPI_OK) return rc;
-    if ((rc = upload(I, d.a21_colptr, p.a21_colptr.data(), p.a21_colptr.size(), st)) != FASTPI_OK) return rc;
-    if ((rc = upload(I, d.t_rowptr, p.t_rowptr.data(), p.t_rowptr.size(), st)) != FASTPI_OK) return rc;
-    if ((rc = upload(I, d.t_colptr, p.t_colptr.data(), p.t_colptr.size(), st)) != FASTPI_OK) return rc;
-    if ((rc = upload(I, d.a21_colidx, p.a21_colidx.data(), p.a21_colidx.size(), st)) != FASTPI_OK) return rc;
-    if ((rc = upload(I, d.a21_rowidx, p.a21_rowidx.data(), p.a21_rowidx.size(), st)) != FASTPI_OK) return rc;
-    if ((rc = upload(I, d.t_colidx, p.t_colidx.data(), p.t_colidx.size(), st)) != FASTPI_OK) return rc;
-    if ((rc = upload(I, d.t_rowidx, p.t_rowidx.data(), p.t_rowidx.size(), st)) != FASTPI_OK) return rc;
-    if ((rc = upload(I, d.piT, p.ro.piT.data(), p.ro.piT.size(), st)) != FASTPI_OK) return rc;
-    if ((rc = upload(I, d.invF, p.invF.data(), p.invF.size(), st)) != FASTPI_OK) return rc;
-    if ((rc = upload(I, d.invT, p.invT.data(), p.invT.size(), st)) != FASTPI_OK) return rc;
-    if ((rc = upload_segments(I, p.seg_a21c, d.seg_a21c, st)) != FASTPI_OK) return rc;
-    if ((rc = upload_segments(I, p.seg_a21r, d.seg_a21r, st)) != FASTPI_OK) return rc;
-    if ((rc = upload_segments(I, p.seg_tc, d.seg_tc, st)) != FASTPI_OK) return rc;
-    if ((rc = upload_segments(I, p.seg_tr, d.seg_tr, st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I.allocs, d.work, p.work.data(), p.work.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I.allocs, d.dst0, p.dst0.data(), p.dst0.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I.allocs, d.dst1, p.dst1.data(), p.dst1.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I.allocs, d.a21_rowptr, p.a21_rowptr.data(), p.a21_rowptr.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I.allocs, d.a21_colptr, p.a21_colptr.data(), p.a21_colptr.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I.allocs, d.t_rowptr, p.t_rowptr.data(), p.t_rowptr.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I.allocs, d.t_colptr, p.t_colptr.data(), p.t_colptr.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I.allocs, d.a21_colidx, p.a21_colidx.data(), p.a21_colidx.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I.allocs, d.a21_rowidx, p.a21_rowidx.data(), p.a21_rowidx.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I.allocs, d.t_colidx, p.t_colidx.data(), p.t_colidx.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I.allocs, d.t_rowidx, p.t_rowidx.data(), p.t_rowidx.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I.allocs, d.piT, p.ro.piT.data(), p.ro.piT.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I.allocs, d.invF, p.invF.data(), p.invF.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload(I.allocs, d.invT, p.invT.data(), p.invT.size(), st)) != FASTPI_OK) return rc;
+    if ((rc = upload_segments(I.allocs, p.seg_a21c, d.seg_a21c, st)) != FASTPI_OK) return rc;
+    if ((rc = upload_segments(I.allocs, p.seg_a21r, d.seg_a21r, st)) != FASTPI_OK) return rc;
+    if ((rc = upload_segments(I.allocs, p.seg_tc, d.seg_tc, st)) != FASTPI_OK) return rc;
+    if ((rc = upload_segments(I.allocs, p.seg_tr, d.seg_tr, st)) != FASTPI_OK) return rc;
 
     // workspace layout (doubles)
     const int64_t m = d.m, n1 = d.n1, n2 = d.n2, s = d.s, r = d.r;

@@ -57,6 +57,8 @@ struct Instance {
 
 // Uploads the plan's tables and sizes the workspace (cap: 0 = none). Synchronises `st`.
 int instance_upload(Instance& I, const Plan& p, size_t ws_cap, hipStream_t st);
+// Copies a segment table to the device; every allocation is appended to `allocs`.
+int upload_segments(std::vector<void*>& allocs, const Segments& s, SegDev& d, hipStream_t st);
 void instance_free(Instance& I, hipStream_t st);
 
 struct RunCfg {

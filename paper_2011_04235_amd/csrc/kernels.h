@@ -162,6 +162,8 @@ void launch_gemm_tn(const double* A, int64_t lda, const double* B, int64_t ldb, 
 void launch_gemm_nn(const double* A, int64_t lda, const int* arow, const double* B, int64_t ldb,
                     int64_t M, int64_t N, int64_t K, double* C, int64_t ldc, const int* crow,
                     hipStream_t st, bool fp32 = false);
+void launch_gemm_nt(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M, int64_t N,
+                    int64_t K, double* C, int64_t ldc, hipStream_t st, bool fp32 = false);
 
 // sparse and block-structured (sparse.hip)
 void launch_sparse_gram(const SegDev& sg, const int* rowidx, const double* cval,
@@ -185,6 +187,21 @@ void launch_col_coeffs(const double* Vt, int64_t s, int64_t n2, int64_t r, const
 void launch_copy_rows(const double* src, int64_t rows, int64_t cols, const int* dst_row, double* dst,
                       hipStream_t st);
 void launch_pinv_sigma(const double* S, int64_t r, double cut, double* inv, hipStream_t st);
+
+// label evaluation (evaluate.hip): for every row x of a sparse test matrix (CSR over n
+// columns), scores s = x Z (Z: n x L row-major), the kmax highest labels (ties to the lower
+// label) and hits[row * nk + t] = |top ks[t] labels ∩ the row's true labels (CSR)|; a row
+// with a column outside [0, n) gets -1 counts.
+// ks_host: host array of nk values in [1, kTopkMaxK]; kmax = max(ks). Scores of more than
+// kTopkLdsLabels labels go to `scratch` (topk_scratch_doubles(rows, L) doubles).
+constexpr int kTopkMaxK = 64;
+constexpr int kTopkMaxKs = 16;
+constexpr int64_t kTopkLdsLabels = 7680;
+constexpr int64_t kTopkGlobalGrid = 2048;
+int64_t topk_scratch_doubles(int64_t rows, int64_t L);
+void launch_topk_hits(int64_t rows, int64_t n, int64_t L, const int64_t* a_rowptr, const int* a_col,
+                      const double* a_val, const double* Z, const int64_t* y_rowptr, const int* y_col,
+                      int nk, const int* ks_host, int kmax, int* hits, double* scratch, hipStream_t st);
 
 // rank predictor (mlp.hip)
 int mlp_param_count();
