@@ -311,6 +311,122 @@ def run_batched_workload(args, torch, fp):
     print(json.dumps(out), flush=True)
 
 
+def run_eval_workload(args, torch, fp):
+    """Application 1's evaluation loop on the labelled form of a workload (planted labels,
+    90/10 row split; synth.make_labelled_problem): the SVD of the training rows once, then
+    per step the sparse-label apply Z = V Sigma^+ U^T Y and the top-k hit counts of the test
+    rows. The dense-label apply of the same Y is timed beside it."""
+    import oracle
+    from synth import CONFIGS, make_labelled_problem
+    cfg = CONFIGS[args.config]
+    progress(f"generating labelled {args.config}")
+    lp = make_labelled_problem(cfg)
+    tr, te, L = lp.train, lp.test, lp.L
+    precision = "mixed" if args.precision == "mixed" else "fp64"
+    dev = torch.device("cuda", 0)
+    plan = fp.Plan(tr.m, tr.n, tr.indptr, tr.indices, tr.data, alpha=cfg.alpha, k=cfg.k)
+    info = plan.info
+    m, n, r = info["m"], info["n"], info["r"]
+    h = fp.Handle(0, precision=precision)
+    h.upload_plan(plan)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    progress(f"SVD of the training rows {m}x{n} (r={r})")
+    U, S, V = h.svd(t(tr.indptr), t(tr.indices), t(tr.data))
+    h.sync()
+    t0 = time.perf_counter()
+    labels = fp.Labels(h, m, L, tr.y_indptr, tr.y_indices)
+    labels_s = time.perf_counter() - t0
+    Yd = t(oracle.labels_dense(m, L, tr.y_indptr, tr.y_indices))
+    te_in = [t(a) for a in (te.indptr, te.indices, te.data)]
+    ty_in = [t(a) for a in (te.y_indptr, te.y_indices)]
+    ks = [1, 3, 5]
+    Z = torch.empty((n, L), dtype=torch.float64, device=dev)
+    hits = torch.empty((te.m, len(ks)), dtype=torch.int32, device=dev)
+
+    def time_calls(fn, kernels):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        per = {}
+        for kname in kernels:
+            h.timing_start(kname)
+            for _ in range(args.steps):
+                fn()
+            per[kname] = h.timing_read()
+        h.timing_start(None)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps, per
+
+    progress("timing the sparse-label apply, the dense-label apply and the scoring")
+    sp_ms, sp_k = time_calls(lambda: h.apply_sparse(U, S, V, labels, out=Z), ["label_spmm", "gemm_nt"])
+    dn_ms, _ = time_calls(lambda: h.apply(U, S, V, Yd), [])
+    h.apply_sparse(U, S, V, labels, out=Z)
+    tk_ms, tk_k = time_calls(lambda: h.topk_hits(*te_in, Z, *ty_in, ks, out=hits), ["topk"])
+    hits_h = hits.cpu().numpy().astype(np.int64)
+    p_at = oracle.p_at_k(hits_h, ks)
+    kern = {}
+    for name, (cnt, ms_tot) in {**sp_k, **tk_k}.items():
+        kern[name] = {"launches": cnt, "avg_us": round(ms_tot / max(cnt, 1) * 1e3, 3)}
+    # algorithmic bytes of the label SpMM: the U rows that carry a label, Y^T's entries
+    # (row id and value), the L x r product written once
+    rows_with_label = int(np.count_nonzero(np.diff(tr.y_indptr)))
+    spmm_bytes = rows_with_label * r * 8 + tr.y_nnz * 12 + L * r * 8
+    spmm_launch_us = sp_k["label_spmm"][1] / max(args.steps, 1) * 1e3   # both passes, per call
+    achieved = spmm_bytes / (spmm_launch_us * 1e-6) / 1e9
+    roof = {"bound": "hbm", "kernel": "k_spmm_rows (+ k_seg_reduce_spmm)", "achieved": round(achieved, 2),
+            "peak": 8000.0, "unit": "GB/s", "frac": round(achieved / 8000.0, 5), "traffic": None,
+            "bytes_per_call": spmm_bytes, "us_per_call": round(spmm_launch_us, 3)}
+    base = None
+    if not args.no_cpu_baseline:
+        progress("oracle on the host cores (apply and scoring)")
+        Uh, Sh, Vh = U.cpu().numpy(), S.cpu().numpy(), V.cpu().numpy()
+        c0 = time.perf_counter()
+        Zo = oracle.pinv_apply_sparse(Uh, Sh, Vh, m, n, L, tr.y_indptr, tr.y_indices)
+        c1 = time.perf_counter()
+        rows = min(te.m, 2000)
+        sub_ptr = te.indptr[:rows + 1]
+        oracle.topk_hits(sub_ptr, te.indices, te.data, Zo, te.y_indptr[:rows + 1], te.y_indices, ks)
+        c2 = time.perf_counter()
+        cpu_ms = (c1 - c0) * 1e3 + (c2 - c1) * 1e3 * te.m / rows
+        base = {"value": round(cpu_ms, 3), "unit": "ms per evaluation", "cores": int(torch.get_num_threads()),
+                "kind": "oracle",
+                "sample": f"one oracle apply of the full Y and scoring of {rows} of {te.m} test rows "
+                          f"({c2 - c0:.1f} s), scoring scaled to all rows"}
+    out = {
+        "metric": "evaluation loop time (sparse-label apply + top-k scoring of the test rows)",
+        "value": round(sp_ms + tk_ms, 4),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sp_ms + tk_ms, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"fastpi {cfg.name} labelled: train {m}x{n} ({tr.nnz} nnz), "
+                               f"Y {m}x{L} ({tr.y_nnz} positives), test {te.m} rows, alpha {cfg.alpha}",
+                   "r": r, "ks": ks},
+        "apply_sparse_ms": round(sp_ms, 4),
+        "apply_dense_ms": round(dn_ms, 4),
+        "speedup_sparse_vs_dense_apply": round(dn_ms / sp_ms, 3),
+        "topk_ms": round(tk_ms, 4),
+        "kernels": kern,
+        "labels_upload_s": round(labels_s, 4),
+        "p_at_k": {str(k): round(float(v), 5) for k, v in zip(ks, p_at)},
+        "roofline": roof,
+        "cpu_baseline": base,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -326,6 +442,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (scale for the PMC byte counters)")
     ap.add_argument("--batch-count", type=int, default=64, help="matrices of the batched workload")
+    ap.add_argument("--eval", action="store_true",
+                    help="time Application 1's evaluation loop (sparse-label apply + P@k scoring)")
     ap.add_argument("--ranks", default="alpha", choices=["alpha", "learned"],
                     help="block ranks: the alpha rule, or the shipped rank network at the same total")
     args = ap.parse_args()
@@ -347,6 +465,8 @@ def main():
         del src, dst
     if args.config == "c4":
         return run_batched_workload(args, torch, fp)
+    if args.eval:
+        return run_eval_workload(args, torch, fp)
 
     cfg = CONFIGS[args.config]
     progress(f"generating {args.config}")

@@ -282,7 +282,9 @@ int fastpi_last_rotations(fastpi_handle* h, int64_t* out2);
  * Measurement hook: times every launch of one kernel of the device path with a HIP event
  * pair on the handle's stream (each timed launch costs an extra event record).
  * kind: 0 = eigensolver partial Gram, 1 = eigensolver pair solve, 2 = eigensolver column
- * update, 3 = block SVD launches, -1 = off. Starting discards earlier timings.
+ * update, 3 = block SVD launches, 4 = the label SpMM of fastpi_apply_sparse (both passes),
+ * 5 = fastpi_topk_hits, 6 = the transposed-B GEMM of fastpi_apply_sparse, -1 = off.
+ * Starting discards earlier timings.
  */
 int fastpi_timing_start(fastpi_handle* h, int kind);
 /* Waits for the stream; returns the number of timed launches and their summed duration in

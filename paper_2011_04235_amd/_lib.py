@@ -346,7 +346,8 @@ class Handle:
         _check(load().fastpi_last_sweeps(self._h, _ptr(out)))
         return out.tolist()
 
-    KERNELS = {"eig_gram": 0, "eig_solve": 1, "eig_update": 2, "block_svd": 3}
+    KERNELS = {"eig_gram": 0, "eig_solve": 1, "eig_update": 2, "block_svd": 3, "label_spmm": 4,
+               "topk": 5, "gemm_nt": 6}
 
     def last_rotations(self):
         """Pair solves that ran in the last svd: [row-update core, column-update core]."""

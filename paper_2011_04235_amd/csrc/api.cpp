@@ -584,8 +584,8 @@ int fastpi_apply_sparse(fastpi_handle* h, int64_t m, int64_t n, int64_t r, const
     double* part = C + L * r;
     launch_pinv_sigma(S, r, static_cast<double>(std::max(m, n)) * DBL_EPSILON, inv, st);
     launch_fill(C, L * r, 0.0, st);   // labels without a positive keep a zero row
-    launch_spmm_rows(Y->seg, Y->rows, Y->vals, U, r, inv, C, r, nullptr, false, part, st);
-    launch_gemm_nt(V, r, C, r, n, L, r, Z, L, st, h->opts.precision == FASTPI_MIXED);
+    launch_spmm_rows(Y->seg, Y->rows, Y->vals, U, r, inv, C, r, nullptr, false, part, st, &h->timer);
+    launch_gemm_nt(V, r, C, r, n, L, r, Z, L, st, h->opts.precision == FASTPI_MIXED, &h->timer);
     return check_launch();
 }
 
@@ -615,7 +615,8 @@ int fastpi_topk_hits(fastpi_handle* h, int64_t rows, int64_t n, int64_t L, const
         int rc = grow(h->ews, h->ews_bytes, static_cast<size_t>(sd) * sizeof(double), h->stream, "evaluation scratch");
         if (rc != FASTPI_OK) return rc;
     }
-    launch_topk_hits(rows, n, L, rowptr, col, val, Z, y_rowptr, y_col, nk, ks, kmax, hits, h->ews, h->stream);
+    launch_topk_hits(rows, n, L, rowptr, col, val, Z, y_rowptr, y_col, nk, ks, kmax, hits, h->ews, h->stream,
+                     &h->timer);
     return check_launch();
 }
 
@@ -773,7 +774,7 @@ int fastpi_mlp_adam(fastpi_handle* h, float* theta, const float* grad, float* m,
 }
 
 int fastpi_timing_start(fastpi_handle* h, int kind) {
-    if (!h || kind < KT_NONE || kind > KT_BLOCK_SVD) {
+    if (!h || kind < KT_NONE || kind > KT_LAST) {
         set_error("bad handle or kernel kind");
         return FASTPI_EINVAL;
     }

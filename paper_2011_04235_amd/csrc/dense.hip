@@ -191,15 +191,16 @@ void launch_gemm_nn(const double* A, int64_t lda, const int* arow, const double*
 }
 
 void launch_gemm_nt(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M, int64_t N,
-                    int64_t K, double* C, int64_t ldc, hipStream_t st, bool fp32) {
+                    int64_t K, double* C, int64_t ldc, hipStream_t st, bool fp32, KernelTimer* timer) {
     if (M <= 0 || N <= 0) return;
     dim3 grid(static_cast<unsigned>((M + TM - 1) / TM), static_cast<unsigned>((N + TN - 1) / TN));
+    const int* none = nullptr;
     if (fp32)
-        hipLaunchKernelGGL((k_gemm_nn<float, true>), grid, dim3(256), 0, st, A, lda, nullptr, B, ldb, M, N, K, C,
-                           ldc, nullptr);
+        FASTPI_LAUNCH(timer, KT_GEMM_NT, (k_gemm_nn<float, true>), grid, dim3(256), 0, st, A, lda, none, B, ldb, M,
+                      N, K, C, ldc, none);
     else
-        hipLaunchKernelGGL((k_gemm_nn<double, true>), grid, dim3(256), 0, st, A, lda, nullptr, B, ldb, M, N, K, C,
-                           ldc, nullptr);
+        FASTPI_LAUNCH(timer, KT_GEMM_NT, (k_gemm_nn<double, true>), grid, dim3(256), 0, st, A, lda, none, B, ldb,
+                      M, N, K, C, ldc, none);
 }
 
 }  // namespace fastpi

@@ -28,7 +28,17 @@ struct SegDev {
 // hipExtLaunchKernel with an event pair that the runtime stamps at the dispatch's own start
 // and end, so the pair measures the kernel body (events recorded around a launch would also
 // count its dispatch gap).
-enum KernelKind { KT_NONE = -1, KT_EIG_GRAM = 0, KT_EIG_SOLVE = 1, KT_EIG_UPDATE = 2, KT_BLOCK_SVD = 3 };
+enum KernelKind {
+    KT_NONE = -1,
+    KT_EIG_GRAM = 0,
+    KT_EIG_SOLVE = 1,
+    KT_EIG_UPDATE = 2,
+    KT_BLOCK_SVD = 3,
+    KT_LABEL_SPMM = 4,
+    KT_TOPK = 5,
+    KT_GEMM_NT = 6,
+    KT_LAST = KT_GEMM_NT
+};
 struct KernelTimer {
     int target = KT_NONE;
     std::vector<hipEvent_t> pool;
@@ -163,7 +173,8 @@ void launch_gemm_nn(const double* A, int64_t lda, const int* arow, const double*
                     int64_t M, int64_t N, int64_t K, double* C, int64_t ldc, const int* crow,
                     hipStream_t st, bool fp32 = false);
 void launch_gemm_nt(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M, int64_t N,
-                    int64_t K, double* C, int64_t ldc, hipStream_t st, bool fp32 = false);
+                    int64_t K, double* C, int64_t ldc, hipStream_t st, bool fp32 = false,
+                    KernelTimer* timer = nullptr);
 
 // sparse and block-structured (sparse.hip)
 void launch_sparse_gram(const SegDev& sg, const int* rowidx, const double* cval,
@@ -174,7 +185,7 @@ void launch_sparse_proj(const SegDev& sg, const int* rowidx, const double* cval,
                         double* part, hipStream_t st);
 void launch_spmm_rows(const SegDev& sg, const int* colidx, const double* rval, const double* B,
                       int64_t N, const double* cs, double* C, int64_t ldc, const int* crow,
-                      bool accumulate, double* part, hipStream_t st);
+                      bool accumulate, double* part, hipStream_t st, KernelTimer* timer = nullptr);
 void launch_blockdiag_gram(const BlockWork* work, int nwork, const double* V1, const double* sig1,
                            double* G, int64_t ldg, hipStream_t st);
 void launch_u2_top(const BlockWork* work, int nwork, const double* U1, const double* sig1,
@@ -191,17 +202,17 @@ void launch_pinv_sigma(const double* S, int64_t r, double cut, double* inv, hipS
 // label evaluation (evaluate.hip): for every row x of a sparse test matrix (CSR over n
 // columns), scores s = x Z (Z: n x L row-major), the kmax highest labels (ties to the lower
 // label) and hits[row * nk + t] = |top ks[t] labels ∩ the row's true labels (CSR)|; a row
-// with a column outside [0, n) gets -1 counts.
-// ks_host: host array of nk values in [1, kTopkMaxK]; kmax = max(ks). Scores of more than
-// kTopkLdsLabels labels go to `scratch` (topk_scratch_doubles(rows, L) doubles).
+// with a column outside [0, n) gets -1 counts. ks_host: host array of nk values in
+// [1, kTopkMaxK]; kmax = max(ks). The scores of a chunk of rows go to `scratch`
+// (topk_scratch_doubles(rows, L) doubles, at most kTopkScoreDoubles or one row).
 constexpr int kTopkMaxK = 64;
 constexpr int kTopkMaxKs = 16;
-constexpr int64_t kTopkLdsLabels = 7680;
-constexpr int64_t kTopkGlobalGrid = 2048;
+constexpr int64_t kTopkScoreDoubles = int64_t(32) << 20;
 int64_t topk_scratch_doubles(int64_t rows, int64_t L);
 void launch_topk_hits(int64_t rows, int64_t n, int64_t L, const int64_t* a_rowptr, const int* a_col,
                       const double* a_val, const double* Z, const int64_t* y_rowptr, const int* y_col,
-                      int nk, const int* ks_host, int kmax, int* hits, double* scratch, hipStream_t st);
+                      int nk, const int* ks_host, int kmax, int* hits, double* scratch, hipStream_t st,
+                      KernelTimer* timer = nullptr);
 
 // rank predictor (mlp.hip)
 int mlp_param_count();

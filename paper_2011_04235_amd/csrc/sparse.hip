@@ -204,14 +204,14 @@ __global__ void k_seg_reduce_spmm(SegDev sg, const double* __restrict__ part, in
 
 void launch_spmm_rows(const SegDev& sg, const int* colidx, const double* rval, const double* B,
                       int64_t N, const double* cs, double* C, int64_t ldc, const int* crow,
-                      bool accumulate, double* part, hipStream_t st) {
+                      bool accumulate, double* part, hipStream_t st, KernelTimer* timer) {
     if (sg.nseg <= 0 || N <= 0) return;
-    hipLaunchKernelGGL(k_spmm_rows, dim3(static_cast<unsigned>((sg.nseg + 3) / 4)), dim3(256), 0, st, sg,
-                       colidx, rval, B, N, cs, C, ldc, crow, accumulate ? 1 : 0, part);
+    FASTPI_LAUNCH(timer, KT_LABEL_SPMM, k_spmm_rows, dim3(static_cast<unsigned>((sg.nseg + 3) / 4)), dim3(256), 0,
+                  st, sg, colidx, rval, B, N, cs, C, ldc, crow, accumulate ? 1 : 0, part);
     if (sg.nmulti > 0)
-        hipLaunchKernelGGL(k_seg_reduce_spmm, dim3(static_cast<unsigned>(sg.nmulti),
-                                                   static_cast<unsigned>((N + 255) / 256)),
-                           dim3(256), 0, st, sg, part, N, cs, C, ldc, crow, accumulate ? 1 : 0);
+        FASTPI_LAUNCH(timer, KT_LABEL_SPMM, k_seg_reduce_spmm,
+                      dim3(static_cast<unsigned>(sg.nmulti), static_cast<unsigned>((N + 255) / 256)), dim3(256),
+                      0, st, sg, part, N, cs, C, ldc, crow, accumulate ? 1 : 0);
 }
 
 // Diagonal blocks of V1 Sigma1^2 V1^T into G2 (n1 x n1): one workgroup per dense block.

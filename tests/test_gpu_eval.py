@@ -135,15 +135,15 @@ def test_hits_equal_oracle_at_the_scoring_workload(env):
     assert np.array_equal(hg, ho)
 
 
-@pytest.mark.parametrize("L", [3, 50, 7680, 9000])
-def test_topk_ties_and_label_counts(env, L):
+@pytest.mark.parametrize("L,rows", [(3, 150), (50, 150), (64, 150), (7680, 150), (9000, 4000)])
+def test_topk_ties_and_label_counts(env, L, rows):
     """Integer scores (exact, heavily tied) so the tie rule decides; L = 3 has fewer labels
-    than the largest k; 7680 is the largest count scored in LDS, 9000 goes through the
-    device-scratch path. Includes rows without entries (all scores zero) and without
-    positives."""
+    than the largest k, 64 is one full label slice, 50 and 7680 end in a partial one, and
+    4000 rows of 9000 labels take two chunks of the score buffer (32M doubles). Includes rows
+    without entries (all scores zero) and without positives."""
     torch, fp = env
     rng = np.random.default_rng(L)
-    n, rows = 40, 150
+    n = 40
     A = sp.random(rows, n, density=0.08, random_state=L, format="csr")
     A.data = rng.integers(1, 4, size=A.nnz).astype(np.float64)
     A.sort_indices()
