@@ -37,6 +37,7 @@ import math
 import numpy as np
 import scipy.sparse as sp
 
+from .randomized import InnerSolver, rsvd_right, use_randomized
 from .reorder import Reordering, reorder
 
 EPS = np.finfo(np.float64).eps
@@ -130,28 +131,40 @@ class Stage:
     full_sigma: np.ndarray  # every singular value of the formed matrix (for gap checks)
 
 
-def row_update(S: Split, B: BlockStage, alpha: float) -> Stage:
-    """Eq. 2: SVD of M2 = [Sigma1 V1^T ; A21] truncated to s, U2 = [U1 Ut_top ; Ut_bot]."""
+def row_update(S: Split, B: BlockStage, alpha: float, inner: InnerSolver | None = None) -> Stage:
+    """Eq. 2: SVD of M2 = [Sigma1 V1^T ; A21] truncated to s, U2 = [U1 Ut_top ; Ut_bot].
+    With a randomized inner solver that applies (oracle.randomized), the truncated SVD of
+    M2 is the randomized one (full_sigma then holds the exact spectrum for reference)."""
     s_b = B.sigma1.size
     top = (B.V1.multiply(B.sigma1[None, :])).T.toarray() if s_b else np.zeros((0, S.n1))
     M2 = np.vstack([top, S.A21.toarray()])
     if M2.size == 0:
         m = S.m1 + S.m2
         return Stage(np.zeros((m, 0)), np.zeros(0), np.zeros((S.n1, 0)), np.zeros(0))
-    Ut, st, Vt = np.linalg.svd(M2, full_matrices=False)
     s = min(target_rank(alpha, S.n1), s_b + S.m2, S.n1)
+    if use_randomized(inner, s, S.n1):
+        Ut, sig, V2 = rsvd_right(M2, s, inner.oversample, inner.iters, inner.seed, 0)
+        U2 = np.vstack([B.U1 @ Ut[:s_b], Ut[s_b:]])
+        return Stage(U2, sig, V2, np.linalg.svd(M2, compute_uv=False))
+    Ut, st, Vt = np.linalg.svd(M2, full_matrices=False)
     U2 = np.vstack([B.U1 @ Ut[:s_b, :s], Ut[s_b:, :s]])
     return Stage(U2, st[:s].copy(), Vt[:s].T.copy(), st)
 
 
-def column_update(S: Split, R2: Stage, alpha: float, m: int, n: int) -> Stage:
-    """Eq. 3: SVD of X3 = [U2 Sigma2, T] truncated to r, V = [V2 Vt_top ; Vt_bot]."""
+def column_update(S: Split, R2: Stage, alpha: float, m: int, n: int,
+                  inner: InnerSolver | None = None) -> Stage:
+    """Eq. 3: SVD of X3 = [U2 Sigma2, T] truncated to r, V = [V2 Vt_top ; Vt_bot] (randomized
+    as in row_update when the inner solver applies)."""
     s = R2.sigma.size
     X3 = np.hstack([R2.U * R2.sigma[None, :], S.T.toarray()])
     if X3.size == 0:
         return Stage(np.zeros((m, 0)), np.zeros(0), np.zeros((n, 0)), np.zeros(0))
-    Ut, st, Vt = np.linalg.svd(X3, full_matrices=False)
     r = min(target_rank(alpha, min(m, n)), s + S.n2, m)
+    if use_randomized(inner, r, s + S.n2):
+        Ur, sig, Vh = rsvd_right(X3, r, inner.oversample, inner.iters, inner.seed, 1)
+        V = np.vstack([R2.V @ Vh[:s], Vh[s:]])
+        return Stage(Ur, sig, V, np.linalg.svd(X3, compute_uv=False))
+    Ut, st, Vt = np.linalg.svd(X3, full_matrices=False)
     Vh = Vt[:r].T
     V = np.vstack([R2.V @ Vh[:s], Vh[s:]])
     return Stage(Ut[:, :r].copy(), st[:r].copy(), V, st)
@@ -173,8 +186,10 @@ class OracleResult:
         return self.sigma.size
 
 
-def fastpi_svd(m, n, indptr, indices, data, alpha, k=0.01) -> OracleResult:
-    """Algorithm 1 lines 1-4, results mapped back to the original order."""
+def fastpi_svd(m, n, indptr, indices, data, alpha, k=0.01,
+               inner: InnerSolver | None = None) -> OracleResult:
+    """Algorithm 1 lines 1-4, results mapped back to the original order; `inner` selects
+    the truncated inner solver of the two updates (None: exact)."""
     if not (0.0 < alpha <= 1.0):
         raise ValueError("alpha must lie in (0, 1]")
     A = sp.csr_matrix((np.asarray(data, np.float64), np.asarray(indices), np.asarray(indptr)),
@@ -184,8 +199,8 @@ def fastpi_svd(m, n, indptr, indices, data, alpha, k=0.01) -> OracleResult:
     R = reorder(m, n, A.indptr, A.indices, k)
     S = split_blocks(m, n, A.indptr, A.indices, A.data, R)
     B = block_svd(S, alpha)
-    R2 = row_update(S, B, alpha)
-    R3 = column_update(S, R2, alpha, m, n)
+    R2 = row_update(S, B, alpha, inner)
+    R3 = column_update(S, R2, alpha, m, n, inner)
     U = R3.U[R.piT.astype(np.int64), :]
     V = R3.V[R.piF.astype(np.int64), :]
     return OracleResult(U, R3.sigma, V, R, S, B, R2, R3)

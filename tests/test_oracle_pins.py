@@ -364,9 +364,9 @@ def test_planted_mistakes_are_caught(monkeypatch):
 
     orig_row = ofp.row_update
 
-    def row_without_sigma(S, B, alpha):
+    def row_without_sigma(S, B, alpha, inner=None):
         B2 = ofp.BlockStage(B.U1, np.ones_like(B.sigma1), B.V1, B.ranks, B.block_sigma)
-        return orig_row(S, B2, alpha)
+        return orig_row(S, B2, alpha, inner)
 
     monkeypatch.setattr(ofp, "row_update", row_without_sigma)
     bad = ofp.fastpi_svd(p.m, p.n, p.indptr, p.indices, p.data, 1.0, 0.05)
@@ -375,8 +375,8 @@ def test_planted_mistakes_are_caught(monkeypatch):
 
     orig_col = ofp.column_update
 
-    def col_transposed(S, R2, alpha, m, n):
-        st = orig_col(S, R2, alpha, m, n)
+    def col_transposed(S, R2, alpha, m, n, inner=None):
+        st = orig_col(S, R2, alpha, m, n, inner)
         s = R2.sigma.size
         Vh_top = np.linalg.lstsq(R2.V, st.V[:S.n1], rcond=None)[0]
         V = np.vstack([R2.V @ Vh_top[:, ::-1], st.V[S.n1:]])
