@@ -74,6 +74,26 @@ typedef struct {
                                 /* (fewer sweeps); 0: on G itself                                 */
 } fastpi_tuning;
 
+/*
+ * Inner solver of the two incremental updates (Section 3.3). The paper computes the
+ * update's truncated SVD exactly, or, for a low target rank, with a randomized method with
+ * power iterations (oversampling 5 and 11 iterations in its experiments). Here the
+ * randomized branch is subspace iteration on the update's Gram matrix G (order q, target
+ * rank t): Y = G Omega with a Gaussian Omega of t + oversample columns, `iters` times an
+ * orthonormalization of Y followed by Y = G Y, and the Rayleigh-Ritz eigenpairs of G on the
+ * final basis. Omega comes from Philox4x32-10 with key (seed, update: 0 row, 1 column) and
+ * counter = pair index (Box-Muller on two 53-bit uniforms per counter).
+ *   mode: 0 = exact (default); 1 = randomized for an update with t < ceil(0.3 q);
+ *         2 = randomized for every update with t + oversample < q.
+ *   oversample in [0, 256], iters in [0, 64].
+ */
+typedef struct {
+    int32_t mode;
+    int32_t oversample;
+    int32_t iters;
+    uint32_t seed;
+} fastpi_inner;
+
 typedef struct fastpi_plan fastpi_plan;
 typedef struct fastpi_handle fastpi_handle;
 typedef struct fastpi_batch fastpi_batch;
@@ -314,6 +334,18 @@ int fastpi_get_tuning(const fastpi_handle* h, fastpi_tuning* t);
  * afterwards take a matching entry; fastpi_autotune reads and writes it. NULL clears it.
  */
 int fastpi_set_tuning_cache(fastpi_handle* h, const char* path);
+
+/* Selects the inner solver of the handle's runs (kept across fastpi_upload_plan; a batch
+ * takes the handle's setting when it is created). FASTPI_EINVAL for values out of range. */
+int fastpi_set_inner(fastpi_handle* h, const fastpi_inner* c);
+int fastpi_get_inner(const fastpi_handle* h, fastpi_inner* c);
+int fastpi_batch_set_inner(fastpi_batch* b, const fastpi_inner* c);
+/* 1 when the setting takes the randomized branch for an update of target rank t and
+ * order q, else 0. */
+int fastpi_inner_applies(const fastpi_inner* c, int64_t t, int64_t q);
+/* Stage-level check of the test-matrix generator: out[0..count) (device) = the standard
+ * normals the randomized branch draws for key (seed, stream), in row-major element order. */
+int fastpi_gaussian(fastpi_handle* h, int64_t count, uint32_t seed, uint32_t stream, double* out);
 /*
  * Autotuner: runs the uploaded plan's path with every candidate schedule (three block-SVD
  * LDS/occupancy pairs timed on the block launch alone, then six eigensolver schedules --

@@ -14,5 +14,5 @@ from .evaluate import (  # noqa: F401
     labels_dense, pinv_apply_sparse, row_scores, rank_k, precision_at_k, topk_hits, p_at_k,
 )
 from .randomized import (  # noqa: F401
-    InnerSolver, gaussian, philox4x32_10, rsvd_right, use_randomized,
+    InnerSolver, gaussian, philox4x32_10, rsvd_right, sign_convention, use_randomized,
 )

@@ -37,7 +37,7 @@ import math
 import numpy as np
 import scipy.sparse as sp
 
-from .randomized import InnerSolver, rsvd_right, use_randomized
+from .randomized import InnerSolver, rsvd_right, sign_convention, use_randomized
 from .reorder import Reordering, reorder
 
 EPS = np.finfo(np.float64).eps
@@ -156,14 +156,16 @@ def column_update(S: Split, R2: Stage, alpha: float, m: int, n: int,
     """Eq. 3: SVD of X3 = [U2 Sigma2, T] truncated to r, V = [V2 Vt_top ; Vt_bot] (randomized
     as in row_update when the inner solver applies)."""
     s = R2.sigma.size
+    r = min(target_rank(alpha, min(m, n)), s + S.n2, m)
+    if use_randomized(inner, r, s + S.n2):
+        sgn = sign_convention(R2.V)
+        X3 = np.hstack([R2.U * (sgn * R2.sigma)[None, :], S.T.toarray()])
+        Ur, sig, Vh = rsvd_right(X3, r, inner.oversample, inner.iters, inner.seed, 1)
+        V = np.vstack([(R2.V * sgn[None, :]) @ Vh[:s], Vh[s:]])
+        return Stage(Ur, sig, V, np.linalg.svd(X3, compute_uv=False))
     X3 = np.hstack([R2.U * R2.sigma[None, :], S.T.toarray()])
     if X3.size == 0:
         return Stage(np.zeros((m, 0)), np.zeros(0), np.zeros((n, 0)), np.zeros(0))
-    r = min(target_rank(alpha, min(m, n)), s + S.n2, m)
-    if use_randomized(inner, r, s + S.n2):
-        Ur, sig, Vh = rsvd_right(X3, r, inner.oversample, inner.iters, inner.seed, 1)
-        V = np.vstack([R2.V @ Vh[:s], Vh[s:]])
-        return Stage(Ur, sig, V, np.linalg.svd(X3, compute_uv=False))
     Ut, st, Vt = np.linalg.svd(X3, full_matrices=False)
     Vh = Vt[:r].T
     V = np.vstack([R2.V @ Vh[:s], Vh[s:]])

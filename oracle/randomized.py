@@ -20,6 +20,12 @@ u1 in (0, 1] and u2 in [0, 1), and the Box-Muller transform gives the normals
 sqrt(-2 ln u1) cos(2 pi u2) for the even element and sqrt(-2 ln u1) sin(2 pi u2) for the
 odd element of the pair (elements in row-major order).
 
+The column update's test matrix multiplies the columns of X3 = [U2 Sigma2, T], and the row
+update fixes each column of U2 and V2 only up to sign; a flipped column is a different draw.
+So before a randomized column update both sides fix those signs: each right singular vector
+v of the row update (with its left partner) is negated unless its entry of largest magnitude
+(the first such entry on ties) is positive.
+
 Readings: the paper's frPCA normalizes with an LU factorization between power iterations;
 this oracle uses a QR factorization (same subspace in exact arithmetic). The branch is
 taken for an update whose target rank t satisfies t < ceil(0.3 q) (q: the order of the
@@ -91,6 +97,15 @@ def use_randomized(inner: InnerSolver | None, t: int, q: int) -> bool:
     if t + inner.oversample >= q:
         return False
     return inner.mode == 2 or t < int(math.ceil(0.3 * float(q)))
+
+
+def sign_convention(V: np.ndarray) -> np.ndarray:
+    """+1 or -1 per column: the sign that makes the column's largest-magnitude entry (the
+    first on ties) positive."""
+    if V.shape[0] == 0:
+        return np.ones(V.shape[1])
+    lead = V[np.argmax(np.abs(V), axis=0), np.arange(V.shape[1])]
+    return np.where(lead < 0, -1.0, 1.0)
 
 
 def rsvd_right(M: np.ndarray, t: int, oversample: int, iters: int, seed: int, stream: int):

@@ -50,6 +50,16 @@ class Tuning(ctypes.Structure):
 
 
 # (name, restype, argtypes) of every symbol declared in include/fastpi.h
+class Inner(ctypes.Structure):
+    """Inner solver of the two updates: mode 0 exact, 1 randomized where t < ceil(0.3 q),
+    2 randomized wherever t + oversample < q."""
+    _fields_ = [("mode", ctypes.c_int32), ("oversample", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("seed", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 SIGNATURES = [
     ("fastpi_target_rank", c_int64, [c_double, c_int64]),
     ("fastpi_reorder", c_int, [c_int64, c_int64, c_void_p, c_void_p, c_void_p, c_double, c_void_p,
@@ -109,6 +119,11 @@ SIGNATURES = [
                                     c_void_p, c_void_p]),
     ("fastpi_topk_hits", c_int, [c_void_p, c_int64, c_int64, c_int64, c_void_p, c_void_p, c_void_p,
                                  c_void_p, c_void_p, c_void_p, ctypes.c_int32, c_void_p, c_void_p]),
+    ("fastpi_set_inner", c_int, [c_void_p, POINTER(Inner)]),
+    ("fastpi_get_inner", c_int, [c_void_p, POINTER(Inner)]),
+    ("fastpi_batch_set_inner", c_int, [c_void_p, POINTER(Inner)]),
+    ("fastpi_inner_applies", c_int, [POINTER(Inner), c_int64, c_int64]),
+    ("fastpi_gaussian", c_int, [c_void_p, c_int64, ctypes.c_uint32, ctypes.c_uint32, c_void_p]),
     ("fastpi_last_error", ctypes.c_char_p, []),
 ]
 
@@ -140,6 +155,12 @@ def _check(code):
 
 def _ptr(a: np.ndarray):
     return c_void_p(a.ctypes.data) if a is not None else None
+
+
+def inner_applies(mode, oversample, t, q):
+    """Whether the inner-solver setting takes the randomized branch for target rank t and
+    order q (the library's own rule)."""
+    return bool(load().fastpi_inner_applies(ctypes.byref(Inner(int(mode), int(oversample), 0, 0)), int(t), int(q)))
 
 
 def target_rank(alpha: float, x: int) -> int:
@@ -290,6 +311,22 @@ class Handle:
         _check(load().fastpi_apply(self._h, m, n, r, _dptr(U), _dptr(S), _dptr(V), L, _dptr(Y),
                                    _dptr(Z)))
         return Z
+
+    def set_inner(self, mode=1, oversample=5, iters=11, seed=0):
+        """Inner solver of the two updates (see Inner); kept across upload_plan."""
+        _check(load().fastpi_set_inner(self._h, ctypes.byref(Inner(int(mode), int(oversample), int(iters),
+                                                                     int(seed)))))
+
+    def get_inner(self):
+        out = Inner()
+        _check(load().fastpi_get_inner(self._h, ctypes.byref(out)))
+        return out.as_dict()
+
+    def gaussian(self, count, seed, stream):
+        """The randomized branch's test-matrix draws for key (seed, stream) (device tensor)."""
+        out = self.torch.empty((int(count),), dtype=self.torch.float64, device=self.device)
+        _check(load().fastpi_gaussian(self._h, int(count), int(seed), int(stream), _dptr(out)))
+        return out
 
     def apply_sparse(self, U, S, V, labels, out=None):
         """Z = V diag(S^+) U^T Y for a sparse label matrix (a Labels object)."""
@@ -515,6 +552,10 @@ class Batch:
     def set_tuning(self, **kw):
         t = Tuning(**{**self.get_tuning(), **kw})
         _check(load().fastpi_batch_set_tuning(self._b, ctypes.byref(t)))
+
+    def set_inner(self, mode=1, oversample=5, iters=11, seed=0):
+        _check(load().fastpi_batch_set_inner(self._b, ctypes.byref(Inner(int(mode), int(oversample), int(iters),
+                                                                           int(seed)))))
 
     def get_tuning(self):
         t = Tuning()

@@ -860,6 +860,55 @@ int fastpi_get_tuning(const fastpi_handle* h, fastpi_tuning* t) {
     return FASTPI_OK;
 }
 
+static InnerCfg inner_from_c(const fastpi_inner& c) {
+    InnerCfg o;
+    o.mode = c.mode;
+    o.oversample = c.oversample;
+    o.iters = c.iters;
+    o.seed = c.seed;
+    return o;
+}
+
+static void inner_to_c(const InnerCfg& c, fastpi_inner* o) {
+    o->mode = c.mode;
+    o->oversample = c.oversample;
+    o->iters = c.iters;
+    o->seed = c.seed;
+}
+
+int fastpi_set_inner(fastpi_handle* h, const fastpi_inner* c) {
+    if (!h || !c) {
+        set_error("null pointer");
+        return FASTPI_EINVAL;
+    }
+    HIP_TRY(hipSetDevice(h->device));
+    return group_set_inner(h->grp, inner_from_c(*c), h->stream);
+}
+
+int fastpi_get_inner(const fastpi_handle* h, fastpi_inner* c) {
+    if (!h || !c) {
+        set_error("null pointer");
+        return FASTPI_EINVAL;
+    }
+    inner_to_c(h->grp.inner, c);
+    return FASTPI_OK;
+}
+
+int fastpi_gaussian(fastpi_handle* h, int64_t count, uint32_t seed, uint32_t stream, double* out) {
+    if (!h || count < 0 || (count > 0 && !out)) {
+        set_error("bad handle, count or pointer");
+        return FASTPI_EINVAL;
+    }
+    HIP_TRY(hipSetDevice(h->device));
+    launch_gauss(out, count, seed, stream, h->stream);
+    return check_launch();
+}
+
+int fastpi_inner_applies(const fastpi_inner* c, int64_t t, int64_t q) {
+    if (!c) return 0;
+    return inner_applies(inner_from_c(*c), t, q) ? 1 : 0;
+}
+
 int fastpi_set_tuning_cache(fastpi_handle* h, const char* path) {
     if (!h) {
         set_error("null handle");
@@ -934,6 +983,7 @@ int fastpi_batch_create(fastpi_batch** b, fastpi_handle* h, int64_t count,
     }
     if (st == FASTPI_OK) {
         for (Instance& I : B->inst) B->grp.inst.push_back(&I);
+        B->grp.inner = h->grp.inner;
         st = group_build(B->grp, h->device, h->stream);
     }
     Tuning t;
@@ -1034,6 +1084,15 @@ int fastpi_batch_set_tuning(fastpi_batch* b, const fastpi_tuning* t) {
     }
     HIP_TRY(hipSetDevice(b->h->device));
     return group_set_tuning(b->grp, from_c(*t), b->h->stream);
+}
+
+int fastpi_batch_set_inner(fastpi_batch* b, const fastpi_inner* c) {
+    if (!b || !c) {
+        set_error("null pointer");
+        return FASTPI_EINVAL;
+    }
+    HIP_TRY(hipSetDevice(b->h->device));
+    return group_set_inner(b->grp, inner_from_c(*c), b->h->stream);
 }
 
 int fastpi_batch_get_tuning(const fastpi_batch* b, fastpi_tuning* t) {

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cfloat>
+#include <cmath>
 #include <cstring>
 #include <fstream>
 #include <sstream>
@@ -105,6 +106,15 @@ bool tuning_valid(const Tuning& t) {
     return t.block_lds >= 4096 && t.block_lds <= 60 * 1024 && t.block_wgs_per_cu >= 1 &&
            t.block_wgs_per_cu <= 16 && eig_gram_rows_valid(t.gram_rows) &&
            (t.inner_sweeps == 1 || t.inner_sweeps == 2) && (t.precond == 0 || t.precond == 1);
+}
+
+bool inner_valid(const InnerCfg& c) {
+    return c.mode >= 0 && c.mode <= 2 && c.oversample >= 0 && c.oversample <= 256 && c.iters >= 0 && c.iters <= 64;
+}
+
+bool inner_applies(const InnerCfg& c, int64_t t, int64_t q) {
+    if (c.mode == 0 || t <= 0 || t + c.oversample >= q) return false;
+    return c.mode == 2 || t < static_cast<int64_t>(std::ceil(0.3 * static_cast<double>(q)));
 }
 
 void instance_free(Instance& I, hipStream_t st) {
@@ -223,6 +233,8 @@ int instance_upload(Instance& I, const Plan& p, size_t ws_cap, hipStream_t st) {
 // ---------------------------------------------------------------------------------------
 // group
 // ---------------------------------------------------------------------------------------
+static void free_rand(Group& g);
+
 void group_drop_graphs(Group& g) {
     for (hipGraphExec_t* e : {&g.g_front, &g.g_sw2, &g.g_mid, &g.g_sw3, &g.g_back}) {
         if (*e) hipGraphExecDestroy(*e);
@@ -240,35 +252,174 @@ void group_free(Group& g) {
     g.ntasks = 0;
     eig_set_free(g.set2);
     eig_set_free(g.set3);
+    free_rand(g);
     if (g.cap) hipStreamDestroy(g.cap);
     g.cap = nullptr;
 }
 
+static void free_rand(Group& g) {
+    for (int c = 0; c < 2; ++c) {
+        eig_set_free(g.rset[c]);
+        g.rcores[c].clear();
+    }
+    for (void* p : g.rallocs) hipFree(p);
+    g.rallocs.clear();
+}
+
+// Buffers and eigensolver job of one randomized core (all in one allocation).
+static int make_rand_core(Group& g, int inst, int64_t q, int64_t t, const double* G, double* lam_out,
+                          double* vec_out, RandCore& R, EigJob& job) {
+    const Instance& I = *g.inst[inst];
+    R = RandCore{};
+    R.inst = inst;
+    R.q = q;
+    R.t = t;
+    R.k = t + g.inner.oversample;
+    R.G = G;
+    R.lam_out = lam_out;
+    R.vec_out = vec_out;
+    const int64_t k = R.k;
+    R.sp = gemm_tn_splits(k, k, q);
+    const size_t ed = eig_job_doubles(k, g.tune.gram_rows), ei = eig_job_ints(k);
+    const size_t doubles = static_cast<size_t>(2 * q * k + 3 * k * k + k + static_cast<int64_t>(R.sp) * k * k) + ed;
+    void* p = nullptr;
+    if (hipMalloc(&p, doubles * sizeof(double) + ei * sizeof(int)) != hipSuccess) {
+        set_error("device allocation failed (randomized inner solver)");
+        return FASTPI_ENOMEM;
+    }
+    g.rallocs.push_back(p);
+    double* b = static_cast<double*>(p);
+    R.Y = b;
+    R.Q = R.Y + q * k;
+    R.W = R.Q + q * k;
+    R.Wv = R.W + k * k;
+    R.Ws = R.Wv + k * k;
+    R.Wd = R.Ws + k * k;
+    R.part = R.Wd + k;
+    double* eigws = R.part + static_cast<int64_t>(R.sp) * k * k;
+    int* eigiws = reinterpret_cast<int*>(eigws + ed);
+    // the k x k input (a basis' Gram matrix, then the projected core) may be overwritten
+    job = eig_make_job(R.W, R.W, k, k, R.Wd, R.Wv, eigws, eigiws, I.status, 0.0, g.tune.gram_rows, inst);
+    return FASTPI_OK;
+}
+
 static int build_sets(Group& g, hipStream_t st) {
-    std::vector<EigJob> j2, j3;
-    for (size_t i = 0; i < g.inst.size(); ++i) {
+    free_rand(g);
+    g.sign_v2.assign(g.inst.size(), 0);
+    std::vector<EigJob> j2, j3, jr[2];
+    int rc = FASTPI_OK;
+    for (size_t i = 0; i < g.inst.size() && rc == FASTPI_OK; ++i) {
         Instance& I = *g.inst[i];
         const DevicePlan& d = I.dp;
         double* ws = I.ws;
         const int64_t q3 = d.s + d.n2;
-        if (d.n1 > 0 && d.s > 0)
-            j2.push_back(eig_make_job(ws + I.o_g2, ws + I.o_g2, d.n1, d.s, ws + I.o_lam2, ws + I.o_v2, ws + I.o_eig, I.iws,
-                                      I.status, 0.0, g.tune.gram_rows, static_cast<int>(i)));
-        if (q3 > 0 && d.r > 0)
-            j3.push_back(eig_make_job(ws + I.o_g3, ws + I.o_g3, q3, d.r, ws + I.o_lam3, ws + I.o_vt, ws + I.o_eig, I.iws,
-                                      I.status, 0.0, g.tune.gram_rows, static_cast<int>(i)));
+        const int tag = static_cast<int>(i);
+        if (d.n1 > 0 && d.s > 0) {
+            if (inner_applies(g.inner, d.s, d.n1)) {
+                RandCore R;
+                EigJob J;
+                rc = make_rand_core(g, tag, d.n1, d.s, ws + I.o_g2, ws + I.o_lam2, ws + I.o_v2, R, J);
+                g.rcores[0].push_back(R);
+                jr[0].push_back(J);
+            } else {
+                j2.push_back(eig_make_job(ws + I.o_g2, ws + I.o_g2, d.n1, d.s, ws + I.o_lam2, ws + I.o_v2,
+                                          ws + I.o_eig, I.iws, I.status, 0.0, g.tune.gram_rows, tag));
+            }
+        }
+        if (rc == FASTPI_OK && q3 > 0 && d.r > 0) {
+            if (inner_applies(g.inner, d.r, q3)) {
+                RandCore R;
+                EigJob J;
+                rc = make_rand_core(g, tag, q3, d.r, ws + I.o_g3, ws + I.o_lam3, ws + I.o_vt, R, J);
+                g.rcores[1].push_back(R);
+                jr[1].push_back(J);
+                // its test matrix meets the columns of U2 Sigma2: fix their signs first
+                g.sign_v2[i] = 1;
+            } else {
+                j3.push_back(eig_make_job(ws + I.o_g3, ws + I.o_g3, q3, d.r, ws + I.o_lam3, ws + I.o_vt,
+                                          ws + I.o_eig, I.iws, I.status, 0.0, g.tune.gram_rows, tag));
+            }
+        }
     }
+    if (rc != FASTPI_OK) return rc;
     // the cores are rebuilt by every run, so the factorisation may overwrite them
-    int rc = eig_set_create(g.set2, j2, g.tune.gram_rows, g.tune.precond != 0, st);
+    rc = eig_set_create(g.set2, j2, g.tune.gram_rows, g.tune.precond != 0, st);
     if (rc == FASTPI_OK) rc = eig_set_create(g.set3, j3, g.tune.gram_rows, g.tune.precond != 0, st);
+    for (int c = 0; c < 2 && rc == FASTPI_OK; ++c)
+        rc = eig_set_create(g.rset[c], jr[c], g.tune.gram_rows, g.tune.precond != 0, st);
     if (rc != FASTPI_OK) set_error("eigensolver set allocation failed");
     return rc;
+}
+
+// Randomized subspace iteration for the cores of update c (0: row, 1: column): Y = G Omega;
+// `iters` times Q = orth(Y), Y = G Q; two final orthonormalizations; the Rayleigh-Ritz
+// eigenpairs of B^T G B give the top t pairs (vectors B W_t). orth(Y) = Y V diag(d^-1/2) for
+// the eigenpairs (d, V) of Y^T Y, which spans the same subspace as any other orthonormalization.
+static int rand_run(Group& g, int c, const RunCfg& cfg, hipStream_t st) {
+    std::vector<RandCore>& cores = g.rcores[c];
+    if (cores.empty()) return FASTPI_OK;
+    EigSet& es = g.rset[c];
+    for (RandCore& R : cores) {
+        R.sweeps = 0;
+        R.rotated = 0;
+    }
+    auto eig = [&]() -> int {
+        eig_begin(es, st);
+        const int rc = eig_iterate(es, cfg.max_sweeps, g.tune.inner_sweeps, st, cfg.copy_st, cfg.timer, nullptr);
+        if (rc != FASTPI_OK) return rc;
+        eig_end(es, st);
+        for (int j = 0; j < es.njobs; ++j)
+            for (RandCore& R : cores)
+                if (R.inst == es.host[j].tag) {
+                    R.sweeps += es.host_state[kEigStateWords * j + kEigStSweeps];
+                    R.rotated += es.host_state[kEigStateWords * j + kEigStTotal];
+                }
+        return FASTPI_OK;
+    };
+    // src -> dst: dst = src V diag(d^-1/2) over the eigenpairs of src^T src
+    auto orth = [&](bool from_y) -> int {
+        for (RandCore& R : cores) {
+            const double* src = from_y ? R.Y : R.Q;
+            launch_gemm_tn(src, R.k, src, R.k, R.k, R.k, R.q, R.W, R.k, nullptr, nullptr, R.part, R.sp, st, false);
+        }
+        const int rc = eig();
+        if (rc != FASTPI_OK) return rc;
+        for (RandCore& R : cores) {
+            launch_scale_cols(R.Wv, R.Wd, R.k, static_cast<double>(R.k) * DBL_EPSILON, R.Ws, st);
+            launch_gemm_nn(from_y ? R.Y : R.Q, R.k, nullptr, R.Ws, R.k, R.q, R.k, R.k, from_y ? R.Q : R.Y, R.k,
+                           nullptr, st, false);
+        }
+        return FASTPI_OK;
+    };
+    for (RandCore& R : cores) {
+        launch_gauss(R.Q, R.q * R.k, g.inner.seed, static_cast<uint32_t>(c), st);
+        launch_gemm_nn(R.G, R.q, nullptr, R.Q, R.k, R.q, R.k, R.q, R.Y, R.k, nullptr, st, false);
+    }
+    int rc;
+    for (int it = 0; it < g.inner.iters; ++it) {
+        if ((rc = orth(true)) != FASTPI_OK) return rc;
+        for (RandCore& R : cores)
+            launch_gemm_nn(R.G, R.q, nullptr, R.Q, R.k, R.q, R.k, R.q, R.Y, R.k, nullptr, st, false);
+    }
+    if ((rc = orth(true)) != FASTPI_OK) return rc;    // basis in Q
+    if ((rc = orth(false)) != FASTPI_OK) return rc;   // re-orthonormalized basis in Y
+    for (RandCore& R : cores) {
+        launch_gemm_nn(R.G, R.q, nullptr, R.Y, R.k, R.q, R.k, R.q, R.Q, R.k, nullptr, st, false);
+        launch_gemm_tn(R.Y, R.k, R.Q, R.k, R.k, R.k, R.q, R.W, R.k, nullptr, nullptr, R.part, R.sp, st, false);
+    }
+    if ((rc = eig()) != FASTPI_OK) return rc;
+    for (RandCore& R : cores) {
+        launch_gemm_nn(R.Y, R.k, nullptr, R.Wv, R.k, R.q, R.t, R.k, R.vec_out, R.t, nullptr, st, false);
+        launch_copy(R.Wd, R.t, R.lam_out, st);
+    }
+    return launch_status();
 }
 
 int group_build(Group& g, int device, hipStream_t st) {
     Group fresh;
     fresh.inst = g.inst;
     fresh.tune = g.tune;
+    fresh.inner = g.inner;
     group_free(g);
     g = fresh;
     HIP_TRY(hipDeviceGetAttribute(&g.ncu, hipDeviceAttributeMultiprocessorCount, device));
@@ -327,6 +478,20 @@ int group_build(Group& g, int device, hipStream_t st) {
     return launch_status();
 }
 
+int group_set_inner(Group& g, const InnerCfg& c, hipStream_t st) {
+    if (!inner_valid(c)) {
+        set_error("invalid inner-solver parameters (mode 0-2, oversample 0-256, iterations 0-64)");
+        return FASTPI_EINVAL;
+    }
+    g.inner = c;
+    group_drop_graphs(g);
+    if (!g.inst.empty() && g.counter) {
+        HIP_TRY(hipStreamSynchronize(st));
+        return build_sets(g, st);
+    }
+    return FASTPI_OK;
+}
+
 int group_set_tuning(Group& g, const Tuning& t, hipStream_t st) {
     if (!tuning_valid(t)) {
         set_error("invalid schedule parameters");
@@ -374,8 +539,8 @@ static void stage_front(Group& g, const double* const* val, const RunCfg& c, hip
 
 static void stage_mid(Group& g, const RunCfg& c, hipStream_t st) {
     eig_end(g.set2, st);
-    for (Instance* Ip : g.inst) {
-        Instance& I = *Ip;
+    for (size_t idx = 0; idx < g.inst.size(); ++idx) {
+        Instance& I = *g.inst[idx];
         const DevicePlan& d = I.dp;
         double* ws = I.ws;
         double* vals = ws + I.o_vals;
@@ -385,6 +550,7 @@ static void stage_mid(Group& g, const RunCfg& c, hipStream_t st) {
         double* inv2 = ws + I.o_inv2;
         // a3, second half: sigma2 and U2 = M2 V2 Sigma2^-1 (block part and A21 part)
         if (d.n1 > 0 && s > 0) {
+            if (idx < g.sign_v2.size() && g.sign_v2[idx]) launch_sign_fix(ws + I.o_v2, d.n1, s, st);
             launch_sqrt_inv(ws + I.o_lam2, s, kRelCut, sig2, inv2, st);
             launch_fill(U2, m * s, 0.0, st);
             launch_u2_top(d.work, static_cast<int>(d.B_dense), ws + I.o_u1, ws + I.o_sig1, ws + I.o_v1,
@@ -484,6 +650,10 @@ static void record_sweeps(Group& g) {
             I->sweeps[1 + k] = es.host_state[kEigStateWords * j + kEigStSweeps];
             I->rotated[k] = es.host_state[kEigStateWords * j + kEigStTotal];
         }
+        for (const RandCore& R : g.rcores[k]) {
+            g.inst[R.inst]->sweeps[1 + k] = R.sweeps;
+            g.inst[R.inst]->rotated[k] = R.rotated;
+        }
     }
 }
 
@@ -497,10 +667,12 @@ int group_svd(Group& g, const double* const* val, double* const* U, double* cons
         if ((rc = eig_iterate(g.set2, c.max_sweeps, g.tune.inner_sweeps, st, c.copy_st, c.timer, nullptr)) !=
             FASTPI_OK)
             return rc;
+        if ((rc = rand_run(g, 0, c, st)) != FASTPI_OK) return rc;
         stage_mid(g, c, st);
         if ((rc = eig_iterate(g.set3, c.max_sweeps, g.tune.inner_sweeps, st, c.copy_st, c.timer, nullptr)) !=
             FASTPI_OK)
             return rc;
+        if ((rc = rand_run(g, 1, c, st)) != FASTPI_OK) return rc;
         stage_back(g, U, S, V, c, st);
         record_sweeps(g);
         return launch_status();
@@ -539,9 +711,13 @@ int group_svd(Group& g, const double* const* val, double* const* U, double* cons
     if ((rc = launch_graph(g, g.g_front, st)) != FASTPI_OK) return rc;
     if ((rc = eig_iterate(g.set2, c.max_sweeps, g.tune.inner_sweeps, st, c.copy_st, nullptr, g.g_sw2)) != FASTPI_OK)
         return rc;
+    RunCfg eager = c;
+    eager.timer = nullptr;
+    if ((rc = rand_run(g, 0, eager, st)) != FASTPI_OK) return rc;
     if ((rc = launch_graph(g, g.g_mid, st)) != FASTPI_OK) return rc;
     if ((rc = eig_iterate(g.set3, c.max_sweeps, g.tune.inner_sweeps, st, c.copy_st, nullptr, g.g_sw3)) != FASTPI_OK)
         return rc;
+    if ((rc = rand_run(g, 1, eager, st)) != FASTPI_OK) return rc;
     if ((rc = launch_graph(g, g.g_back, st)) != FASTPI_OK) return rc;
     record_sweeps(g);
     return launch_status();

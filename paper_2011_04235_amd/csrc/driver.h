@@ -23,6 +23,32 @@ struct Tuning {
 };
 bool tuning_valid(const Tuning& t);
 
+// Inner solver of the two incremental updates (Section 3.3): exact truncated SVD, or
+// randomized subspace iteration on the update's Gram matrix for a low target rank.
+struct InnerCfg {
+    int mode = 0;         // 0 exact; 1 randomized where t < ceil(0.3 q); 2 wherever t + oversample < q
+    int oversample = 5;
+    int iters = 11;
+    uint32_t seed = 0;
+};
+bool inner_valid(const InnerCfg& c);
+bool inner_applies(const InnerCfg& c, int64_t t, int64_t q);
+
+// One randomized core: the top t eigenpairs of a q x q Gram matrix G from a k-dimensional
+// basis (k = t + oversample), written where the exact solver would write them.
+struct RandCore {
+    int inst = 0;
+    int64_t q = 0, t = 0, k = 0;
+    const double* G = nullptr;
+    double *Y = nullptr, *Q = nullptr, *W = nullptr, *Wv = nullptr, *Ws = nullptr, *Wd = nullptr,
+           *part = nullptr;
+    int sp = 1;
+    double* lam_out = nullptr;
+    double* vec_out = nullptr;
+    int32_t sweeps = 0;     // Jacobi sweeps over all eigensolves of the last run
+    int64_t rotated = 0;
+};
+
 struct DevicePlan {
     bool valid = false;
     int64_t m = 0, n = 0, nnz = 0, m1 = 0, n1 = 0, m2 = 0, n2 = 0, s_b = 0, s = 0, r = 0;
@@ -80,7 +106,12 @@ struct Group {
     BlockTask* tasks = nullptr;
     int ntasks = 0;
     int* counter = nullptr;
-    EigSet set2, set3;
+    EigSet set2, set3;              // exact cores
+    InnerCfg inner;
+    std::vector<RandCore> rcores[2];   // randomized cores of the row and column updates
+    std::vector<char> sign_v2;         // per instance: fix the signs of V2 (randomized column update)
+    EigSet rset[2];                    // their k x k eigensolves
+    std::vector<void*> rallocs;
     // captured graphs: stages before, between and after the two eigensolvers, and one
     // sweep of each eigensolver
     hipStream_t cap = nullptr;
@@ -93,6 +124,7 @@ int group_build(Group& g, int device, hipStream_t st);
 void group_free(Group& g);
 void group_drop_graphs(Group& g);
 int group_set_tuning(Group& g, const Tuning& t, hipStream_t st);
+int group_set_inner(Group& g, const InnerCfg& c, hipStream_t st);
 // Computes U, S, V of every instance (arrays of device pointers, one per instance).
 int group_svd(Group& g, const double* const* val, double* const* U, double* const* S,
               double* const* V, const RunCfg& c);

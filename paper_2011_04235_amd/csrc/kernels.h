@@ -199,6 +199,15 @@ void launch_copy_rows(const double* src, int64_t rows, int64_t cols, const int* 
                       hipStream_t st);
 void launch_pinv_sigma(const double* S, int64_t r, double cut, double* inv, hipStream_t st);
 
+// randomized inner solver (randomized.hip): out[0..count) standard normals from Philox4x32-10
+// with key (seed, stream) (row-major; pair e/2 per counter, Box-Muller); S = V diag(d^-1/2)
+// over the eigenpairs (d descending) with d_j > cut * d_0, zero columns elsewhere.
+void launch_gauss(double* out, int64_t count, uint32_t seed, uint32_t stream, hipStream_t st);
+void launch_scale_cols(const double* V, const double* d, int64_t k, double cut, double* S, hipStream_t st);
+// negates each column of V (rows x cols, row-major) whose largest-magnitude entry (first on
+// ties) is negative
+void launch_sign_fix(double* V, int64_t rows, int64_t cols, hipStream_t st);
+
 // label evaluation (evaluate.hip): for every row x of a sparse test matrix (CSR over n
 // columns), scores s = x Z (Z: n x L row-major), the kmax highest labels (ties to the lower
 // label) and hits[row * nk + t] = |top ks[t] labels ∩ the row's true labels (CSR)|; a row

@@ -1,0 +1,162 @@
+"""GPU parity of the randomized inner solver (the paper's truncated SVD for the incremental
+updates at a low target rank, Section 3.3) through the C ABI, against the oracle's randomized
+subspace iteration with the same counter-based test matrix.
+
+Both sides compute the same subspace span(G^(iters+1) Omega) in exact arithmetic (they
+orthonormalize differently), and Rayleigh-Ritz values move only to second order with the
+basis, so the FP64 gates of the exact path apply unchanged."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from parity import (MIXED_LS_RTOL, MIXED_RECON_ATOL, MIXED_SIGMA_RTOL, compare_apply, compare_svd,
+                    sigma_rel_err, to_np)
+from synth import make_problem, small_config
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    import paper_2011_04235_amd as fp
+    fp.load()
+    return torch, fp
+
+
+def dev_t(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(torch.device("cuda", 0))
+
+
+def run(torch, fp, prob, alpha, k, inner, precision="fp64", graph=False):
+    plan = fp.Plan(prob.m, prob.n, prob.indptr, prob.indices, prob.data, alpha=alpha, k=k)
+    h = fp.Handle(0, precision=precision)
+    h.set_inner(**inner)
+    h.upload_plan(plan)
+    h.set_graph(graph)
+    U, S, V = h.svd(dev_t(torch, prob.indptr), dev_t(torch, prob.indices), dev_t(torch, prob.data))
+    Z = h.apply(U, S, V, dev_t(torch, prob.Y))
+    h.sync()
+    return plan, h, to_np(U), to_np(S), to_np(V), to_np(Z)
+
+
+def test_generator_matches_oracle(env):
+    torch, fp = env
+    h = fp.Handle(0)
+    for count, seed, stream in ((1, 0, 0), (10001, 5, 1), (262144, 123456789, 0)):
+        say(f"gaussian count={count} seed={seed} stream={stream}")
+        g = to_np(h.gaussian(count, seed, stream))
+        o = oracle.gaussian(1, count, seed, stream).ravel()
+        # the same Philox words; log, sqrt, cos and sin of the device library may differ from
+        # the host's by an ulp or two
+        np.testing.assert_allclose(g, o, rtol=1e-14, atol=1e-14)
+
+
+CASES = [
+    ("2000x500-mode2", "c1", 0.3, 0.01, dict(mode=2, oversample=5, iters=11, seed=1)),
+    ("small-a03-mode2", small_config(300, 80, 0.05, alpha=0.3, seed=8, k=0.05, L=6), 0.3, 0.05,
+     dict(mode=2, oversample=5, iters=11, seed=2)),
+    ("ragged-mode2-it3", small_config(777, 131, 0.02, gamma=1.9, seed=9, k=0.02, L=5), 0.23, 0.02,
+     dict(mode=2, oversample=7, iters=3, seed=3)),
+    ("20000x2000-mode1", "c2", 0.2, 0.01, dict(mode=1, oversample=5, iters=11, seed=4)),
+]
+
+
+@pytest.mark.parametrize("name,cfg,alpha,k,inner", CASES, ids=[c[0] for c in CASES])
+def test_randomized_matches_oracle(env, name, cfg, alpha, k, inner):
+    torch, fp = env
+    prob = make_problem(cfg)
+    say(f"{name}: {prob.m}x{prob.n} alpha={alpha} inner={inner}")
+    plan, h, U, S, V, Z = run(torch, fp, prob, alpha, k, inner)
+    info = plan.info
+    rows = fp.inner_applies(inner["mode"], inner["oversample"], info["s"], info["n1"])
+    cols = fp.inner_applies(inner["mode"], inner["oversample"], info["r"], info["s"] + info["n2"])
+    say(f"  randomized: row update {rows}, column update {cols}; sweeps {h.last_sweeps()}")
+    assert rows or cols
+    ores = oracle.fastpi_svd(prob.m, prob.n, prob.indptr, prob.indices, prob.data, alpha, k,
+                             inner=oracle.InnerSolver(**inner))
+    ok, sinfo = compare_svd(prob, U, S, V, ores)
+    say(f"  {sinfo}")
+    assert ok, sinfo
+    ok, zinfo = compare_apply(prob, Z, ores)
+    say(f"  {zinfo}")
+    assert ok, zinfo
+    # the branch was taken: the exact method's singular values differ
+    exact = oracle.fastpi_svd(prob.m, prob.n, prob.indptr, prob.indices, prob.data, alpha, k)
+    say(f"  randomized vs exact: sigma {sigma_rel_err(S, exact.sigma):.2e}, recon "
+        f"{sinfo['recon_gpu']:.10f} vs {oracle.recon_error(*recon_args(prob, exact)):.10f}")
+
+
+def recon_args(prob, res):
+    import scipy.sparse as sp
+    A = sp.csr_matrix((prob.data, prob.indices, prob.indptr), shape=(prob.m, prob.n))
+    return A, res.U, res.sigma, res.V
+
+
+def test_randomized_mixed_precision(env):
+    torch, fp = env
+    prob = make_problem("c1")
+    inner = dict(mode=2, oversample=5, iters=11, seed=1)
+    say("2000x500 mixed, randomized updates")
+    _, _, U, S, V, Z = run(torch, fp, prob, 0.3, 0.01, inner, precision="mixed")
+    ores = oracle.fastpi_svd(prob.m, prob.n, prob.indptr, prob.indices, prob.data, 0.3, 0.01,
+                             inner=oracle.InnerSolver(**inner))
+    ok, sinfo = compare_svd(prob, U, S, V, ores, sigma_rtol=MIXED_SIGMA_RTOL, product_rtol=1e-4,
+                            recon_atol=MIXED_RECON_ATOL, orth_atol=1e-5)
+    say(f"  {sinfo}")
+    assert ok, sinfo
+    _, zinfo = compare_apply(prob, Z, ores)
+    assert zinfo["ls_rel"] <= MIXED_LS_RTOL, zinfo
+
+
+def test_randomized_batch_graph_and_repeat(env):
+    """A batch mixing a matrix whose updates are randomized with one whose column update
+    stays exact (mode 1) equals the per-matrix runs bitwise; graph replays equal eager runs
+    bitwise; a second run repeats the first bitwise."""
+    torch, fp = env
+    inner = dict(mode=1, oversample=5, iters=11, seed=9)
+    probs = [make_problem("c1"), make_problem(small_config(777, 131, 0.02, gamma=1.9, seed=9, k=0.02, L=5))]
+    alphas, ks = [0.2, 0.23], [0.01, 0.02]
+    say("batch of 2000x500 and 777x131, mode 1")
+    singles = []
+    for p, a, k in zip(probs, alphas, ks):
+        singles.append(run(torch, fp, p, a, k, inner)[2:5])
+    h = fp.Handle(0)
+    h.set_inner(**inner)
+    b = fp.Batch(h, [fp.Plan(p.m, p.n, p.indptr, p.indices, p.data, alpha=a, k=k)
+                     for p, a, k in zip(probs, alphas, ks)])
+    vals = [dev_t(torch, p.data) for p in probs]
+    outs = {}
+    for graph in (False, True, True):
+        b.set_graph(graph)
+        out = b.svd(vals)
+        status, _ = b.sync()
+        assert status == ["OK", "OK"], status
+        res = [tuple(to_np(x) for x in o) for o in out]
+        key = "graph" if graph else "eager"
+        if key in outs:
+            for r0, r1 in zip(outs[key], res):
+                for x0, x1 in zip(r0, r1):
+                    assert np.array_equal(x0, x1)
+        outs[key] = res
+    for (Ue, Se, Ve), (Ug, Sg, Vg), (Us, Ss, Vs) in zip(outs["eager"], outs["graph"], singles):
+        assert np.array_equal(Se, Ss) and np.array_equal(Ue, Us) and np.array_equal(Ve, Vs)
+        assert np.array_equal(Se, Sg) and np.array_equal(Ue, Ug) and np.array_equal(Ve, Vg)
+
+
+def test_invalid_inner_settings(env):
+    torch, fp = env
+    h = fp.Handle(0)
+    for bad in (dict(mode=3), dict(mode=1, iters=65), dict(mode=1, oversample=-1), dict(mode=-1)):
+        with pytest.raises(fp.FastPIError):
+            h.set_inner(**bad)
+    h.set_inner(mode=1, oversample=5, iters=11, seed=7)
+    assert h.get_inner() == {"mode": 1, "oversample": 5, "iters": 11, "seed": 7}

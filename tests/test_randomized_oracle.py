@@ -104,3 +104,36 @@ def test_fastpi_with_randomized_updates():
     re, rx = oracle.recon_error(A, rr.U, rr.sigma, rr.V), oracle.recon_error(A, ex.U, ex.sigma, ex.V)
     assert rx <= re <= rx * 1.001
     assert oracle.orthonormality_error(rr.U) < 1e-12
+
+
+def test_library_branch_rule_matches_oracle():
+    """The library's rule (C ABI, no GPU) against the oracle's on a grid of settings."""
+    import paper_2011_04235_amd as fp
+    fp.load()
+    for mode in (0, 1, 2):
+        for over in (0, 5, 40):
+            for q in (1, 2, 10, 99, 100, 101, 383, 1357):
+                for t in range(0, q + 2, max(1, q // 37)):
+                    want = oracle.use_randomized(oracle.InnerSolver(mode, over), t, q)
+                    assert fp.inner_applies(mode, over, t, q) == want, (mode, over, t, q)
+
+
+def test_randomized_column_update_is_sign_invariant():
+    """The row update fixes its singular vectors only up to sign; with the sign convention the
+    randomized column update gives the same result for any choice of those signs (without
+    it a flip changes the test matrix's draw against X3's columns)."""
+    from oracle import fastpi as ofp
+    p = make_problem("c1")
+    inner = oracle.InnerSolver(2, 5, 3, 4)
+    A = sp.csr_matrix((p.data, p.indices, p.indptr), shape=(p.m, p.n))
+    R = oracle.reorder(p.m, p.n, A.indptr, A.indices, 0.01)
+    S = ofp.split_blocks(p.m, p.n, A.indptr, A.indices, A.data, R)
+    B = ofp.block_svd(S, 0.3)
+    R2 = ofp.row_update(S, B, 0.3, inner)
+    flip = np.where(np.arange(R2.sigma.size) % 3 == 1, -1.0, 1.0)
+    R2f = ofp.Stage(R2.U * flip, R2.sigma, R2.V * flip, R2.full_sigma)
+    a = ofp.column_update(S, R2, 0.3, p.m, p.n, inner)
+    b = ofp.column_update(S, R2f, 0.3, p.m, p.n, inner)
+    np.testing.assert_allclose(a.sigma, b.sigma, rtol=1e-12)
+    np.testing.assert_allclose((a.U * a.sigma) @ a.V.T, (b.U * b.sigma) @ b.V.T, atol=1e-10)
+    assert np.all(oracle.sign_convention(R2f.V * oracle.sign_convention(R2f.V)) == 1)
