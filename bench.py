@@ -442,6 +442,9 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (scale for the PMC byte counters)")
     ap.add_argument("--batch-count", type=int, default=64, help="matrices of the batched workload")
+    ap.add_argument("--inner", default="exact", choices=["exact", "rand"],
+                    help="inner solver of the two updates: exact, or the randomized branch where "
+                         "the target rank is low (oversampling 5, 11 power iterations)")
     ap.add_argument("--eval", action="store_true",
                     help="time Application 1's evaluation loop (sparse-label apply + P@k scoring)")
     ap.add_argument("--ranks", default="alpha", choices=["alpha", "learned"],
@@ -505,6 +508,8 @@ def main():
         autotuned schedule and the stage chain replayed from HIP graphs."""
         progress(f"{precision} {'batched' if batched else 'plain'}: start")
         h = fp.Handle(0, precision=precision)
+        if args.inner == "rand":
+            h.set_inner(mode=1, oversample=5, iters=11, seed=0)
         h.upload_plan(plan)
         U = torch.empty((m, r), dtype=torch.float64, device=dev)
         S = torch.empty((r,), dtype=torch.float64, device=dev)
@@ -569,7 +574,7 @@ def main():
     n_launch, k_ms = head["n_launch"], head["k_ms"]
 
     roof = None
-    if n_launch > 0 and args.roofline_kernel == "eig_solve":
+    if n_launch > 0 and args.roofline_kernel == "eig_solve" and args.inner == "exact":
         # the timed pass ran args.steps identical steps
         f_alg = solve_alg_flops(plan.info, sweeps, head["rotated"], head["tuning"]) * args.steps
         achieved = f_alg / (k_ms * 1e-3) / 1e12
@@ -616,7 +621,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"fastpi {cfg.name}: A {m}x{n} ({prob.nnz} nnz, power-law "
                                f"{cfg.gamma}, {cfg.values}), Y {m}x{cfg.L}, alpha {cfg.alpha}",
-                   "form": head_key, "ranks": ranks_note, "m": m, "n": n,
+                   "form": head_key, "ranks": ranks_note, "inner": args.inner, "m": m, "n": n,
                    "nnz": prob.nnz, "L": cfg.L,
                    "alpha": cfg.alpha, "shape": plan.info},
         "flop_model": F,
