@@ -335,6 +335,18 @@ int fastpi_get_tuning(const fastpi_handle* h, fastpi_tuning* t);
  */
 int fastpi_set_tuning_cache(fastpi_handle* h, const char* path);
 
+/*
+ * Route of the diagonal blocks of A11 (Eq. 1). A block whose sides p >= q give
+ * p * q^2 < min_cost is solved by one workgroup's one-sided Jacobi (the persistent block
+ * launch); a costlier one through the Gram matrix of its long side: G = X^T X (q x q), the
+ * batched FP64 eigensolver of the updates, and the other factor X E diag(sigma^-1)
+ * (singular values below 1e-7 of the block's largest are returned as zero). Default 8e6;
+ * 0 sends every block with rank > 0 and q >= 2 that way. Kept across fastpi_upload_plan; a
+ * batch takes the handle's setting when it is created.
+ */
+int fastpi_set_block_route(fastpi_handle* h, double min_cost);
+int fastpi_batch_set_block_route(fastpi_batch* b, double min_cost);
+
 /* Selects the inner solver of the handle's runs (kept across fastpi_upload_plan; a batch
  * takes the handle's setting when it is created). FASTPI_EINVAL for values out of range. */
 int fastpi_set_inner(fastpi_handle* h, const fastpi_inner* c);

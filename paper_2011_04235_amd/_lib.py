@@ -119,6 +119,8 @@ SIGNATURES = [
                                     c_void_p, c_void_p]),
     ("fastpi_topk_hits", c_int, [c_void_p, c_int64, c_int64, c_int64, c_void_p, c_void_p, c_void_p,
                                  c_void_p, c_void_p, c_void_p, ctypes.c_int32, c_void_p, c_void_p]),
+    ("fastpi_set_block_route", c_int, [c_void_p, c_double]),
+    ("fastpi_batch_set_block_route", c_int, [c_void_p, c_double]),
     ("fastpi_set_inner", c_int, [c_void_p, POINTER(Inner)]),
     ("fastpi_get_inner", c_int, [c_void_p, POINTER(Inner)]),
     ("fastpi_batch_set_inner", c_int, [c_void_p, POINTER(Inner)]),
@@ -311,6 +313,10 @@ class Handle:
         _check(load().fastpi_apply(self._h, m, n, r, _dptr(U), _dptr(S), _dptr(V), L, _dptr(Y),
                                    _dptr(Z)))
         return Z
+
+    def set_block_route(self, min_cost):
+        """Blocks with p q^2 >= min_cost take the Gram route (default 8e6)."""
+        _check(load().fastpi_set_block_route(self._h, float(min_cost)))
 
     def set_inner(self, mode=1, oversample=5, iters=11, seed=0):
         """Inner solver of the two updates (see Inner); kept across upload_plan."""
@@ -552,6 +558,9 @@ class Batch:
     def set_tuning(self, **kw):
         t = Tuning(**{**self.get_tuning(), **kw})
         _check(load().fastpi_batch_set_tuning(self._b, ctypes.byref(t)))
+
+    def set_block_route(self, min_cost):
+        _check(load().fastpi_batch_set_block_route(self._b, float(min_cost)))
 
     def set_inner(self, mode=1, oversample=5, iters=11, seed=0):
         _check(load().fastpi_batch_set_inner(self._b, ctypes.byref(Inner(int(mode), int(oversample), int(iters),

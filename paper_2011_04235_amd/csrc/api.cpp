@@ -876,6 +876,29 @@ static void inner_to_c(const InnerCfg& c, fastpi_inner* o) {
     o->seed = c.seed;
 }
 
+int fastpi_set_block_route(fastpi_handle* h, double min_cost) {
+    if (!h || !(min_cost >= 0)) {
+        set_error("bad handle or cost");
+        return FASTPI_EINVAL;
+    }
+    HIP_TRY(hipSetDevice(h->device));
+    h->grp.big_cost = min_cost;
+    if (!h->inst.dp.valid) return FASTPI_OK;
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return group_build(h->grp, h->device, h->stream);
+}
+
+int fastpi_batch_set_block_route(fastpi_batch* b, double min_cost) {
+    if (!b || !(min_cost >= 0)) {
+        set_error("bad batch or cost");
+        return FASTPI_EINVAL;
+    }
+    HIP_TRY(hipSetDevice(b->h->device));
+    b->grp.big_cost = min_cost;
+    HIP_TRY(hipStreamSynchronize(b->h->stream));
+    return group_build(b->grp, b->h->device, b->h->stream);
+}
+
 int fastpi_set_inner(fastpi_handle* h, const fastpi_inner* c) {
     if (!h || !c) {
         set_error("null pointer");
@@ -984,6 +1007,7 @@ int fastpi_batch_create(fastpi_batch** b, fastpi_handle* h, int64_t count,
     if (st == FASTPI_OK) {
         for (Instance& I : B->inst) B->grp.inst.push_back(&I);
         B->grp.inner = h->grp.inner;
+        B->grp.big_cost = h->grp.big_cost;
         st = group_build(B->grp, h->device, h->stream);
     }
     Tuning t;

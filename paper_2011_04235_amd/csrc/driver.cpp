@@ -236,7 +236,7 @@ int instance_upload(Instance& I, const Plan& p, size_t ws_cap, hipStream_t st) {
 static void free_rand(Group& g);
 
 void group_drop_graphs(Group& g) {
-    for (hipGraphExec_t* e : {&g.g_front, &g.g_sw2, &g.g_mid, &g.g_sw3, &g.g_back}) {
+    for (hipGraphExec_t* e : {&g.g_front, &g.g_sw1, &g.g_front2, &g.g_sw2, &g.g_mid, &g.g_sw3, &g.g_back}) {
         if (*e) hipGraphExecDestroy(*e);
         *e = nullptr;
     }
@@ -250,9 +250,12 @@ void group_free(Group& g) {
     g.tasks = nullptr;
     g.counter = nullptr;
     g.ntasks = 0;
+    eig_set_free(g.set1);
     eig_set_free(g.set2);
     eig_set_free(g.set3);
     free_rand(g);
+    for (void* p : g.ballocs) hipFree(p);
+    g.ballocs.clear();
     if (g.cap) hipStreamDestroy(g.cap);
     g.cap = nullptr;
 }
@@ -305,9 +308,38 @@ static int make_rand_core(Group& g, int inst, int64_t q, int64_t t, const double
 
 static int build_sets(Group& g, hipStream_t st) {
     free_rand(g);
+    eig_set_free(g.set1);
+    for (void* p : g.ballocs) hipFree(p);
+    g.ballocs.clear();
     g.sign_v2.assign(g.inst.size(), 0);
-    std::vector<EigJob> j2, j3, jr[2];
+    std::vector<EigJob> j1, j2, j3, jr[2];
     int rc = FASTPI_OK;
+    // blocks on the Gram route: G, E, lam, W, split-K partials and eigensolver workspace
+    for (BigBlock& b : g.big) {
+        const int64_t p = b.p, q = b.q, t = b.t;
+        const int spg = b.trans ? gemm_tn_splits(q, q, p) : 1;
+        const int spw = b.trans ? 1 : gemm_tn_splits(p, t, q);
+        b.sp = std::max(spg, spw);
+        const int64_t part = std::max<int64_t>(static_cast<int64_t>(spg) * q * q, static_cast<int64_t>(spw) * p * t);
+        const size_t ed = eig_job_doubles(q, g.tune.gram_rows), ei = eig_job_ints(q);
+        const size_t doubles = static_cast<size_t>(q * q + q * t + t + p * t + part) + ed;
+        void* mem = nullptr;
+        if (hipMalloc(&mem, doubles * sizeof(double) + ei * sizeof(int)) != hipSuccess) {
+            set_error("device allocation failed (large diagonal blocks)");
+            return FASTPI_ENOMEM;
+        }
+        g.ballocs.push_back(mem);
+        b.G = static_cast<double*>(mem);
+        b.E = b.G + q * q;
+        b.lam = b.E + q * t;
+        b.W = b.lam + t;
+        b.part = b.W + p * t;
+        double* ews = b.part + part;
+        int* eiws = reinterpret_cast<int*>(ews + ed);
+        // the status words of the block's matrix take its eigensolver's flags
+        j1.push_back(eig_make_job(b.G, b.G, q, t, b.lam, b.E, ews, eiws, g.inst[b.inst]->status, 0.0,
+                                  g.tune.gram_rows, b.inst));
+    }
     for (size_t i = 0; i < g.inst.size() && rc == FASTPI_OK; ++i) {
         Instance& I = *g.inst[i];
         const DevicePlan& d = I.dp;
@@ -343,7 +375,8 @@ static int build_sets(Group& g, hipStream_t st) {
     }
     if (rc != FASTPI_OK) return rc;
     // the cores are rebuilt by every run, so the factorisation may overwrite them
-    rc = eig_set_create(g.set2, j2, g.tune.gram_rows, g.tune.precond != 0, st);
+    rc = eig_set_create(g.set1, j1, g.tune.gram_rows, g.tune.precond != 0, st);
+    if (rc == FASTPI_OK) rc = eig_set_create(g.set2, j2, g.tune.gram_rows, g.tune.precond != 0, st);
     if (rc == FASTPI_OK) rc = eig_set_create(g.set3, j3, g.tune.gram_rows, g.tune.precond != 0, st);
     for (int c = 0; c < 2 && rc == FASTPI_OK; ++c)
         rc = eig_set_create(g.rset[c], jr[c], g.tune.gram_rows, g.tune.precond != 0, st);
@@ -420,14 +453,15 @@ int group_build(Group& g, int device, hipStream_t st) {
     fresh.inst = g.inst;
     fresh.tune = g.tune;
     fresh.inner = g.inner;
+    fresh.big_cost = g.big_cost;
     group_free(g);
     g = fresh;
     HIP_TRY(hipDeviceGetAttribute(&g.ncu, hipDeviceAttributeMultiprocessorCount, device));
     if (g.ncu <= 0) g.ncu = 256;
     // all blocks of all instances, largest cost (p q^2) first
     std::vector<std::pair<double, BlockTask>> all;
-    for (Instance* Ip : g.inst) {
-        Instance& I = *Ip;
+    for (size_t ii = 0; ii < g.inst.size(); ++ii) {
+        Instance& I = *g.inst[ii];
         if (!I.dp.valid) {
             set_error("instance without an uploaded plan");
             return FASTPI_EINVAL;
@@ -446,6 +480,22 @@ int group_build(Group& g, int device, hipStream_t st) {
             t.cols = w.cols;
             t.rank = w.rank;
             const double pp = std::max(w.rows, w.cols), qq = std::min(w.rows, w.cols);
+            if (pp * qq * qq >= g.big_cost && w.rank > 0 && qq >= 2) {
+                BigBlock b;
+                b.inst = static_cast<int>(ii);
+                b.A = t.A;
+                b.U = t.U;
+                b.V = t.V;
+                b.sig = t.sig;
+                b.rows = w.rows;
+                b.cols = w.cols;
+                b.trans = w.rows < w.cols;
+                b.p = static_cast<int64_t>(pp);
+                b.q = static_cast<int64_t>(qq);
+                b.t = w.rank;
+                g.big.push_back(b);
+                continue;
+            }
             all.emplace_back(pp * qq * qq, t);
         }
     }
@@ -521,6 +571,29 @@ static void stage_front(Group& g, const double* const* val, const RunCfg& c, hip
     // a2: block SVDs (Eq. 1), every block of every instance in one persistent launch
     launch_block_svd_tasks(c.mixed, g.tasks, g.ntasks, g.counter, g.tune.block_lds, g.ncu * g.tune.block_wgs_per_cu,
                            c.max_sweeps, c.tol, st, timer);
+    // large blocks: Gram matrices of their long side for the batched eigensolver
+    for (BigBlock& b : g.big) {
+        if (b.trans)
+            launch_gemm_tn(b.A, b.q, b.A, b.q, b.q, b.q, b.p, b.G, b.q, nullptr, nullptr, b.part, b.sp, st, false);
+        else
+            launch_gemm_nt(b.A, b.p, b.A, b.p, b.q, b.q, b.p, b.G, b.q, st, false);
+    }
+    eig_begin(g.set1, st);
+}
+
+static void stage_front2(Group& g, const RunCfg& c, hipStream_t st) {
+    (void)c;
+    eig_end(g.set1, st);
+    // large blocks: the other factor W = X E, then sigma and both factors into the packed
+    // outputs (non-transposed: q side V, p side U; transposed: the reverse)
+    for (BigBlock& b : g.big) {
+        if (b.trans)
+            launch_gemm_nn(b.A, b.q, nullptr, b.E, b.t, b.p, b.t, b.q, b.W, b.t, nullptr, st, false);
+        else
+            launch_gemm_tn(b.A, b.p, b.E, b.t, b.p, b.t, b.q, b.W, b.t, nullptr, nullptr, b.part, b.sp, st, false);
+        launch_block_gram_out(b.lam, b.E, b.W, b.q, b.p, b.t, kRelCut, b.trans ? b.U : b.V, b.trans ? b.V : b.U,
+                              b.sig, st);
+    }
     // a3, first half: M2^T M2 = V1 Sigma1^2 V1^T + A21^T A21
     for (Instance* Ip : g.inst) {
         Instance& I = *Ip;
@@ -664,6 +737,10 @@ int group_svd(Group& g, const double* const* val, double* const* U, double* cons
     g.graph_launches = 0;
     if (!c.use_graph) {
         stage_front(g, val, c, st, c.timer);
+        if ((rc = eig_iterate(g.set1, c.max_sweeps, g.tune.inner_sweeps, st, c.copy_st, c.timer, nullptr)) !=
+            FASTPI_OK)
+            return rc;
+        stage_front2(g, c, st);
         if ((rc = eig_iterate(g.set2, c.max_sweeps, g.tune.inner_sweeps, st, c.copy_st, c.timer, nullptr)) !=
             FASTPI_OK)
             return rc;
@@ -695,6 +772,11 @@ int group_svd(Group& g, const double* const* val, double* const* U, double* cons
         HIP_TRY(hipStreamSynchronize(st));
         if ((rc = capture(g, [&](hipStream_t s) { stage_front(g, val, c, s, nullptr); }, g.g_front)) != FASTPI_OK)
             return rc;
+        if (g.set1.njobs > 0 &&
+            (rc = capture(g, [&](hipStream_t s) { eig_sweep(g.set1, c.max_sweeps, g.tune.inner_sweeps, s, nullptr); },
+                          g.g_sw1)) != FASTPI_OK)
+            return rc;
+        if ((rc = capture(g, [&](hipStream_t s) { stage_front2(g, c, s); }, g.g_front2)) != FASTPI_OK) return rc;
         if (g.set2.njobs > 0 &&
             (rc = capture(g, [&](hipStream_t s) { eig_sweep(g.set2, c.max_sweeps, g.tune.inner_sweeps, s, nullptr); },
                           g.g_sw2)) != FASTPI_OK)
@@ -709,6 +791,9 @@ int group_svd(Group& g, const double* const* val, double* const* U, double* cons
         g.key = key;
     }
     if ((rc = launch_graph(g, g.g_front, st)) != FASTPI_OK) return rc;
+    if ((rc = eig_iterate(g.set1, c.max_sweeps, g.tune.inner_sweeps, st, c.copy_st, nullptr, g.g_sw1)) != FASTPI_OK)
+        return rc;
+    if ((rc = launch_graph(g, g.g_front2, st)) != FASTPI_OK) return rc;
     if ((rc = eig_iterate(g.set2, c.max_sweeps, g.tune.inner_sweeps, st, c.copy_st, nullptr, g.g_sw2)) != FASTPI_OK)
         return rc;
     RunCfg eager = c;

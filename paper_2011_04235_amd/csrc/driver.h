@@ -34,6 +34,20 @@ struct InnerCfg {
 bool inner_valid(const InnerCfg& c);
 bool inner_applies(const InnerCfg& c, int64_t t, int64_t q);
 
+// A diagonal block of A11 too costly for one workgroup's one-sided Jacobi (p q^2 at least
+// kBigBlockCost, p >= q its sides): its SVD goes through the Gram matrix of its long side,
+// G = X^T X (q x q), the batched FP64 eigensolver, and W = X E for the other factor.
+constexpr double kBigBlockCost = 8.0e6;
+struct BigBlock {
+    int inst = 0;                // index of its matrix in the group
+    const double* A = nullptr;   // dense block, column-major rows x cols
+    double *U = nullptr, *V = nullptr, *sig = nullptr;   // the block's packed outputs
+    int64_t rows = 0, cols = 0, p = 0, q = 0, t = 0;
+    bool trans = false;          // rows < cols: X = A^T
+    double *G = nullptr, *E = nullptr, *lam = nullptr, *W = nullptr, *part = nullptr;
+    int sp = 1;
+};
+
 // One randomized core: the top t eigenpairs of a q x q Gram matrix G from a k-dimensional
 // basis (k = t + oversample), written where the exact solver would write them.
 struct RandCore {
@@ -106,6 +120,10 @@ struct Group {
     BlockTask* tasks = nullptr;
     int ntasks = 0;
     int* counter = nullptr;
+    double big_cost = kBigBlockCost;   // p q^2 from which a block takes the Gram route
+    std::vector<BigBlock> big;      // blocks on the Gram route (not in `tasks`)
+    EigSet set1;                    // their eigensolves
+    std::vector<void*> ballocs;
     EigSet set2, set3;              // exact cores
     InnerCfg inner;
     std::vector<RandCore> rcores[2];   // randomized cores of the row and column updates
@@ -115,7 +133,8 @@ struct Group {
     // captured graphs: stages before, between and after the two eigensolvers, and one
     // sweep of each eigensolver
     hipStream_t cap = nullptr;
-    hipGraphExec_t g_front = nullptr, g_sw2 = nullptr, g_mid = nullptr, g_sw3 = nullptr, g_back = nullptr;
+    hipGraphExec_t g_front = nullptr, g_sw1 = nullptr, g_front2 = nullptr, g_sw2 = nullptr, g_mid = nullptr,
+                   g_sw3 = nullptr, g_back = nullptr;
     std::vector<uint64_t> key;
     int graph_launches = 0;   // graph launches of the last run
 };

@@ -204,6 +204,12 @@ void launch_pinv_sigma(const double* S, int64_t r, double cut, double* inv, hipS
 // over the eigenpairs (d descending) with d_j > cut * d_0, zero columns elsewhere.
 void launch_gauss(double* out, int64_t count, uint32_t seed, uint32_t stream, hipStream_t st);
 void launch_scale_cols(const double* V, const double* d, int64_t k, double cut, double* S, hipStream_t st);
+// Outputs of a block SVD computed through its Gram matrix: sigma_k = sqrt(lam_k) (0 when
+// lam_k <= (cut sigma_0)^2), the q-side factor E[:, k] (E: q x t row-major) and the p-side
+// factor W[:, k] / sigma_k (W: p x t row-major; 0 for a zero sigma), both written
+// column-major into the block's packed outputs.
+void launch_block_gram_out(const double* lam, const double* E, const double* W, int64_t q, int64_t p,
+                           int64_t t, double cut, double* qout, double* pout, double* sig, hipStream_t st);
 // negates each column of V (rows x cols, row-major) whose largest-magnitude entry (first on
 // ties) is negative
 void launch_sign_fix(double* V, int64_t rows, int64_t cols, hipStream_t st);
