@@ -83,6 +83,26 @@ def solve_traffic(config):
     return SOLVE_TRAFFIC_BYTES[config]
 
 
+# HBM bytes per call of the label SpMM (both passes) on the 300000 x 10000 labelled workload
+# from the counter runs summarised in profiles/label_spmm_c5_pmc.md, with the digest of the
+# kernel source they were taken on (null for other workloads or another source).
+LABEL_SPMM_TRAFFIC_BYTES = {"c5": 4924894288}
+LABEL_SPMM_DIGEST = "1b0cf4f0673f7f0380021ae44037cea475a24b498b2614ca3c3a1922df6e4746"
+
+
+def label_spmm_traffic(config):
+    if config not in LABEL_SPMM_TRAFFIC_BYTES:
+        return None
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2011_04235_amd", "csrc", "sparse.hip")) as f:
+        src = f.read()
+    a = src.index("void k_spmm_rows(")
+    b = src.index("// Diagonal blocks of V1", a)
+    if hashlib.sha256(src[a:b].encode()).hexdigest() != LABEL_SPMM_DIGEST:
+        return None
+    return LABEL_SPMM_TRAFFIC_BYTES[config]
+
+
 def eig_shape(q, gram_rows=128):
     ld = (q + BW - 1) // BW * BW
     nblk = ld // BW
@@ -380,7 +400,8 @@ def run_eval_workload(args, torch, fp):
     spmm_launch_us = sp_k["label_spmm"][1] / max(args.steps, 1) * 1e3   # both passes, per call
     achieved = spmm_bytes / (spmm_launch_us * 1e-6) / 1e9
     roof = {"bound": "hbm", "kernel": "k_spmm_rows (+ k_seg_reduce_spmm)", "achieved": round(achieved, 2),
-            "peak": 8000.0, "unit": "GB/s", "frac": round(achieved / 8000.0, 5), "traffic": None,
+            "peak": 8000.0, "unit": "GB/s", "frac": round(achieved / 8000.0, 5),
+            "traffic": label_spmm_traffic(args.config), "traffic_unit": "bytes per call",
             "bytes_per_call": spmm_bytes, "us_per_call": round(spmm_launch_us, 3)}
     base = None
     if not args.no_cpu_baseline:
