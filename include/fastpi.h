@@ -129,6 +129,18 @@ int fastpi_reorder(int64_t m, int64_t n, const int64_t* rowptr, const int32_t* c
                    int64_t* blocks, int64_t blocks_cap, int64_t* num_blocks, fastpi_split* out);
 
 /*
+ * The same reordering computed on the GPU of a handle (Section 3.2, Algorithm 2, with the
+ * tie-breaks above; the result is identical to fastpi_reorder's). The CSR is in device
+ * memory: rowptr int64[m+1], col int32[nnz], val double[nnz] or NULL; it is validated on
+ * the device first (rowptr from 0 to nnz and monotone, columns in range and strictly
+ * increasing within a row, finite values), with the error codes of fastpi_reorder. The
+ * outputs are host buffers as in fastpi_reorder. Synchronous on the handle's stream.
+ */
+int fastpi_reorder_gpu(fastpi_handle* h, int64_t m, int64_t n, int64_t nnz, const int64_t* rowptr,
+                       const int32_t* col, const double* val, double k, int32_t* piT, int32_t* piF,
+                       int64_t* blocks, int64_t blocks_cap, int64_t* num_blocks, fastpi_split* out);
+
+/*
  * Plan for one sparsity pattern and one alpha (Algorithm 1, line 1, plus the rank rule
  * of Eqs. 1-3): runs the reordering, derives every block's rank, and precomputes the index
  * maps that move values from the caller's CSR into the blocks of A11, A21 and T = [A12; A22].
@@ -137,6 +149,11 @@ int fastpi_reorder(int64_t m, int64_t n, const int64_t* rowptr, const int32_t* c
  */
 int fastpi_plan_create(fastpi_plan** plan, int64_t m, int64_t n, const int64_t* rowptr,
                        const int32_t* col, const double* val, double alpha, double k);
+/* As fastpi_plan_create (host CSR, validated on the host), with the reordering run on the
+ * handle's GPU (fastpi_reorder_gpu); the plan is the same. */
+int fastpi_plan_create_gpu(fastpi_plan** plan, fastpi_handle* h, int64_t m, int64_t n,
+                           const int64_t* rowptr, const int32_t* col, const double* val,
+                           double alpha, double k);
 int fastpi_plan_info(const fastpi_plan* plan, fastpi_split* out);
 /* Copies the permutations (host int32[m], int32[n]); either pointer may be NULL. */
 int fastpi_plan_permutation(const fastpi_plan* plan, int32_t* piT, int32_t* piF);

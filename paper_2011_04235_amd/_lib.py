@@ -120,6 +120,10 @@ SIGNATURES = [
     ("fastpi_topk_hits", c_int, [c_void_p, c_int64, c_int64, c_int64, c_void_p, c_void_p, c_void_p,
                                  c_void_p, c_void_p, c_void_p, ctypes.c_int32, c_void_p, c_void_p]),
     ("fastpi_set_block_route", c_int, [c_void_p, c_double]),
+    ("fastpi_reorder_gpu", c_int, [c_void_p, c_int64, c_int64, c_int64, c_void_p, c_void_p, c_void_p, c_double,
+                                   c_void_p, c_void_p, c_void_p, c_int64, POINTER(c_int64), POINTER(Split)]),
+    ("fastpi_plan_create_gpu", c_int, [POINTER(c_void_p), c_void_p, c_int64, c_int64, c_void_p, c_void_p,
+                                       c_void_p, c_double, c_double]),
     ("fastpi_batch_set_block_route", c_int, [c_void_p, c_double]),
     ("fastpi_set_inner", c_int, [c_void_p, POINTER(Inner)]),
     ("fastpi_get_inner", c_int, [c_void_p, POINTER(Inner)]),
@@ -190,14 +194,19 @@ def reorder(m, n, indptr, indices, data=None, k=0.01):
 class Plan:
     """Reordering + ranks + value maps for one pattern and one alpha (host, C++)."""
 
-    def __init__(self, m, n, indptr, indices, data=None, alpha=0.2, k=0.01):
+    def __init__(self, m, n, indptr, indices, data=None, alpha=0.2, k=0.01, gpu=None):
+        """gpu: a Handle to run the reordering on its device (the plan is the same)."""
         lib = load()
         indptr = np.ascontiguousarray(indptr, dtype=np.int64)
         indices = np.ascontiguousarray(indices, dtype=np.int32)
         data = None if data is None else np.ascontiguousarray(data, dtype=np.float64)
         h = c_void_p()
-        _check(lib.fastpi_plan_create(ctypes.byref(h), int(m), int(n), _ptr(indptr), _ptr(indices),
-                                      _ptr(data), float(alpha), float(k)))
+        if gpu is None:
+            _check(lib.fastpi_plan_create(ctypes.byref(h), int(m), int(n), _ptr(indptr), _ptr(indices),
+                                          _ptr(data), float(alpha), float(k)))
+        else:
+            _check(lib.fastpi_plan_create_gpu(ctypes.byref(h), gpu._h, int(m), int(n), _ptr(indptr),
+                                              _ptr(indices), _ptr(data), float(alpha), float(k)))
         self._h = h
         self.alpha = alpha
         self.k = k
@@ -313,6 +322,23 @@ class Handle:
         _check(load().fastpi_apply(self._h, m, n, r, _dptr(U), _dptr(S), _dptr(V), L, _dptr(Y),
                                    _dptr(Z)))
         return Z
+
+    def reorder(self, m, n, rowptr, col, val=None, k=0.01):
+        """Algorithm 2 on this handle's GPU from a device CSR (torch tensors); returns
+        (piT, piF, blocks[B, 4], split dict) on the host, as reorder()."""
+        nnz = int(col.shape[0])
+        piT = np.empty(m, dtype=np.int32)
+        piF = np.empty(n, dtype=np.int32)
+        nb = c_int64(0)
+        spl = Split()
+        lib = load()
+        _check(lib.fastpi_reorder_gpu(self._h, int(m), int(n), nnz, _dptr(rowptr), _dptr(col), _dptr(val),
+                                      float(k), _ptr(piT), _ptr(piF), None, 0, ctypes.byref(nb), ctypes.byref(spl)))
+        blocks = np.empty((nb.value, 4), dtype=np.int64)
+        _check(lib.fastpi_reorder_gpu(self._h, int(m), int(n), nnz, _dptr(rowptr), _dptr(col), _dptr(val),
+                                      float(k), _ptr(piT), _ptr(piF), _ptr(blocks), nb.value, ctypes.byref(nb),
+                                      ctypes.byref(spl)))
+        return piT, piF, blocks, spl.as_dict()
 
     def set_block_route(self, min_cost):
         """Blocks with p q^2 >= min_cost take the Gram route (default 8e6)."""

@@ -178,18 +178,9 @@ const char* fastpi_last_error(void) { return g_last_error.c_str(); }
 
 int64_t fastpi_target_rank(double alpha, int64_t x) { return target_rank(alpha, x); }
 
-int fastpi_reorder(int64_t m, int64_t n, const int64_t* rowptr, const int32_t* col,
-                   const double* val, double k, int32_t* piT, int32_t* piF, int64_t* blocks,
-                   int64_t blocks_cap, int64_t* num_blocks, fastpi_split* out) {
-    if (!piT || !piF || !num_blocks) {
-        set_error("null output pointer");
-        return FASTPI_EINVAL;
-    }
-    int st = validate_csr(m, n, rowptr, col, val);
-    if (st != FASTPI_OK) return st;
-    ReorderOut ro;
-    st = reorder_pattern(m, n, rowptr, col, val, k, ro);
-    if (st != FASTPI_OK) return st;
+// piT, piF, blocks and the shape report of a reordering into the caller's host buffers
+static int reorder_outputs(const ReorderOut& ro, int64_t m, int64_t n, int32_t* piT, int32_t* piF, int64_t* blocks,
+                           int64_t blocks_cap, int64_t* num_blocks, fastpi_split* out) {
     const int64_t B = static_cast<int64_t>(ro.blocks.size());
     *num_blocks = B;
     if (blocks_cap > 0 && blocks_cap < B) {
@@ -224,6 +215,21 @@ int fastpi_reorder(int64_t m, int64_t n, const int64_t* rowptr, const int32_t* c
     return FASTPI_OK;
 }
 
+int fastpi_reorder(int64_t m, int64_t n, const int64_t* rowptr, const int32_t* col,
+                   const double* val, double k, int32_t* piT, int32_t* piF, int64_t* blocks,
+                   int64_t blocks_cap, int64_t* num_blocks, fastpi_split* out) {
+    if (!piT || !piF || !num_blocks) {
+        set_error("null output pointer");
+        return FASTPI_EINVAL;
+    }
+    int st = validate_csr(m, n, rowptr, col, val);
+    if (st != FASTPI_OK) return st;
+    ReorderOut ro;
+    st = reorder_pattern(m, n, rowptr, col, val, k, ro);
+    if (st != FASTPI_OK) return st;
+    return reorder_outputs(ro, m, n, piT, piF, blocks, blocks_cap, num_blocks, out);
+}
+
 int fastpi_plan_create(fastpi_plan** plan, int64_t m, int64_t n, const int64_t* rowptr,
                        const int32_t* col, const double* val, double alpha, double k) {
     if (!plan) {
@@ -237,6 +243,76 @@ int fastpi_plan_create(fastpi_plan** plan, int64_t m, int64_t n, const int64_t* 
         return FASTPI_ENOMEM;
     }
     int st = build_plan(p->p, m, n, rowptr, col, val, alpha, k);
+    if (st != FASTPI_OK) {
+        delete p;
+        return st;
+    }
+    *plan = p;
+    return FASTPI_OK;
+}
+
+int fastpi_reorder_gpu(fastpi_handle* h, int64_t m, int64_t n, int64_t nnz, const int64_t* rowptr,
+                       const int32_t* col, const double* val, double k, int32_t* piT, int32_t* piF,
+                       int64_t* blocks, int64_t blocks_cap, int64_t* num_blocks, fastpi_split* out) {
+    if (!h || !piT || !piF || !num_blocks) {
+        set_error("null handle or output pointer");
+        return FASTPI_EINVAL;
+    }
+    HIP_TRY(hipSetDevice(h->device));
+    int st = validate_csr_gpu(m, n, nnz, rowptr, col, val, h->stream);
+    if (st != FASTPI_OK) return st;
+    ReorderOut ro;
+    st = reorder_pattern_gpu(m, n, rowptr, col, val, nnz, k, h->stream, ro);
+    if (st != FASTPI_OK) return st;
+    return reorder_outputs(ro, m, n, piT, piF, blocks, blocks_cap, num_blocks, out);
+}
+
+int fastpi_plan_create_gpu(fastpi_plan** plan, fastpi_handle* h, int64_t m, int64_t n, const int64_t* rowptr,
+                           const int32_t* col, const double* val, double alpha, double k) {
+    if (!plan || !h) {
+        set_error("null plan pointer or handle");
+        return FASTPI_EINVAL;
+    }
+    *plan = nullptr;
+    int st = validate_csr(m, n, rowptr, col, val);
+    if (st != FASTPI_OK) return st;
+    if (!(alpha > 0.0 && alpha <= 1.0)) {
+        set_error("alpha must lie in (0, 1]");
+        return FASTPI_EINVAL;
+    }
+    HIP_TRY(hipSetDevice(h->device));
+    const int64_t nnz = rowptr[m];
+    // the pattern (and values, for the stored-zero rule) on the device for the reordering
+    std::vector<void*> bufs;
+    auto cleanup = [&]() {
+        hipStreamSynchronize(h->stream);
+        for (void* p : bufs) hipFree(p);
+    };
+    auto dev_copy = [&](const void* src, size_t bytes) -> void* {
+        void* p = nullptr;
+        if (hipMalloc(&p, std::max<size_t>(bytes, 1)) != hipSuccess) return nullptr;
+        bufs.push_back(p);
+        if (bytes && hipMemcpyAsync(p, src, bytes, hipMemcpyHostToDevice, h->stream) != hipSuccess) return nullptr;
+        return p;
+    };
+    auto* drp = static_cast<int64_t*>(dev_copy(rowptr, sizeof(int64_t) * (m + 1)));
+    auto* dcol = static_cast<int32_t*>(dev_copy(col, sizeof(int32_t) * nnz));
+    double* dval = val ? static_cast<double*>(dev_copy(val, sizeof(double) * nnz)) : nullptr;
+    if (!drp || !dcol || (val && !dval)) {
+        cleanup();
+        set_error("device allocation or copy failed (GPU reordering)");
+        return FASTPI_ENOMEM;
+    }
+    ReorderOut ro;
+    st = reorder_pattern_gpu(m, n, drp, dcol, dval, nnz, k, h->stream, ro);
+    cleanup();
+    if (st != FASTPI_OK) return st;
+    fastpi_plan* p = new (std::nothrow) fastpi_plan();
+    if (!p) {
+        set_error("host allocation failed");
+        return FASTPI_ENOMEM;
+    }
+    st = build_plan(p->p, m, n, rowptr, col, val, alpha, k, &ro);
     if (st != FASTPI_OK) {
         delete p;
         return st;

@@ -79,8 +79,10 @@ struct Plan {
     std::vector<int32_t> invF;   // new column -> original column
 };
 
+// `given`: a reordering computed elsewhere (the GPU's) for this pattern and k, used instead
+// of running the host one
 int build_plan(Plan& p, int64_t m, int64_t n, const int64_t* rowptr, const int32_t* col,
-               const double* val, double alpha, double k);
+               const double* val, double alpha, double k, const ReorderOut* given = nullptr);
 void assign_ranks(Plan& p, const std::vector<int64_t>& ranks);
 int block_features(const Plan& p, const double* val, double* out);
 

@@ -214,6 +214,14 @@ void launch_block_gram_out(const double* lam, const double* E, const double* W, 
 // ties) is negative
 void launch_sign_fix(double* V, int64_t rows, int64_t cols, hipStream_t st);
 
+// GPU reordering (reorder_gpu.hip): Algorithm 2 on a device CSR with the host reordering's
+// result (piT, piF, blocks, split); validate_csr_gpu checks a device CSR first (shape,
+// column range and order, finite values).
+int validate_csr_gpu(int64_t m, int64_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col,
+                     const double* val, hipStream_t st);
+int reorder_pattern_gpu(int64_t m, int64_t n, const int64_t* rowptr, const int32_t* col, const double* val,
+                        int64_t nnz, double k, hipStream_t st, ReorderOut& out);
+
 // label evaluation (evaluate.hip): for every row x of a sparse test matrix (CSR over n
 // columns), scores s = x Z (Z: n x L row-major), the kmax highest labels (ties to the lower
 // label) and hits[row * nk + t] = |top ks[t] labels ∩ the row's true labels (CSR)|; a row

@@ -139,15 +139,19 @@ int block_features(const Plan& p, const double* val, double* out) {
 }
 
 int build_plan(Plan& p, int64_t m, int64_t n, const int64_t* rowptr, const int32_t* col,
-               const double* val, double alpha, double k) {
+               const double* val, double alpha, double k, const ReorderOut* given) {
     if (!(alpha > 0.0 && alpha <= 1.0)) {
         set_error("alpha must lie in (0, 1]");
         return FASTPI_EINVAL;
     }
     int st = validate_csr(m, n, rowptr, col, val);
     if (st != FASTPI_OK) return st;
-    st = reorder_pattern(m, n, rowptr, col, val, k, p.ro);
-    if (st != FASTPI_OK) return st;
+    if (given) {
+        p.ro = *given;
+    } else {
+        st = reorder_pattern(m, n, rowptr, col, val, k, p.ro);
+        if (st != FASTPI_OK) return st;
+    }
     p.m = m;
     p.n = n;
     p.nnz = rowptr[m];
