@@ -8,9 +8,9 @@
 //     histogram gives the threshold degree D and the count above it; the nodes of degree D
 //     are taken in index order through a prefix count; the hubs are then sorted by
 //     (degree desc, index asc) and take the highest free ids in that order;
-//  3. connected components of what remains, by min-label propagation with pointer jumping:
-//     node codes are row i -> i and column j -> m + j, and every node ends with the smallest
-//     code of its component. That code is the component's seed in the scan order (rows by
+//  3. connected components of what remains, by lock-free union-find that always hooks the
+//     larger root under the smaller: node codes are row i -> i and column j -> m + j, and
+//     every node ends with the smallest code of its component. That code is the component's seed in the scan order (rows by
 //     index, then columns), so ordering components by it is their discovery order;
 //  4. the giant component (most nodes, the first found on ties) continues; every other
 //     component is a diagonal block, its rows and its columns in ascending index order, the
@@ -36,39 +36,84 @@ unsigned grid_of(int64_t n, int per = kThreads) {
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < (n); \
          i += static_cast<int64_t>(gridDim.x) * blockDim.x)
 
-// ---- graph build -----------------------------------------------------------------------
-// nonzero-valued entries per row (all entries when val is null)
-__global__ void k_row_keep(const int64_t* __restrict__ rowptr, const double* __restrict__ val, int64_t m,
-                           int* __restrict__ cnt) {
-    GRID_STRIDE(i, m) {
-        int c = 0;
-        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) c += (val == nullptr || val[e] != 0.0) ? 1 : 0;
-        cnt[i] = c;
-    }
+// One wave (64 lanes) per node: the node index of this wave, uniform across its lanes.
+#define WAVE_NODE(v, cnt)                                                                                    \
+    const int lane = threadIdx.x % 64;                                                                    \
+    const int64_t v = static_cast<int64_t>(blockIdx.x) * (kThreads / 64) +                             \
+                      __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / 64));                  \
+    if (v >= (cnt)) return;
+
+__device__ inline int wave_sum_i(int x) {
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
 }
 
-__global__ void k_row_fill(const int64_t* __restrict__ rowptr, const int* __restrict__ col,
-                           const double* __restrict__ val, int64_t m, const int64_t* __restrict__ rp,
-                           int* __restrict__ rc, int* __restrict__ ccnt) {
-    GRID_STRIDE(i, m) {
-        int64_t o = rp[i];
-        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
-            if (val == nullptr || val[e] != 0.0) {
-                rc[o++] = col[e];
-                atomicAdd(&ccnt[col[e]], 1);
-            }
+__device__ inline int wave_min_i(int x) {
+    for (int off = 32; off > 0; off >>= 1) x = min(x, __shfl_xor(x, off, 64));
+    return x;
+}
+
+// one atomic per wave: the lanes with `take` get consecutive slots of *counter (every lane of
+// the wave must call this)
+__device__ inline int wave_slot(bool take, int* counter) {
+    const unsigned long long mask = __ballot(take);
+    const int lane = threadIdx.x % 64;
+    int base = 0;
+    if (mask) {
+        const int leader = __ffsll(static_cast<long long>(mask)) - 1;
+        if (lane == leader) base = atomicAdd(counter, __popcll(mask));
+        base = __shfl(base, leader, 64);
+    }
+    return base + __popcll(mask & ((1ull << lane) - 1ull));
+}
+
+unsigned wave_grid(int64_t nodes) {
+    return static_cast<unsigned>(std::max<int64_t>(1, (nodes + kThreads / 64 - 1) / (kThreads / 64)));
+}
+
+// ---- graph build -----------------------------------------------------------------------
+// nonzero-valued entries per row (all entries when val is null); one wave per row
+__global__ __launch_bounds__(kThreads) void k_row_keep(const int64_t* __restrict__ rowptr,
+                                                       const double* __restrict__ val, int64_t m,
+                                                       int* __restrict__ cnt) {
+    WAVE_NODE(i, m)
+    int c = 0;
+    for (int64_t e = rowptr[i] + lane; e < rowptr[i + 1]; e += 64) c += (val == nullptr || val[e] != 0.0) ? 1 : 0;
+    c = wave_sum_i(c);
+    if (lane == 0) cnt[i] = c;
+}
+
+// kept entries in order (ballot prefix inside each chunk of 64), column counts on the side
+__global__ __launch_bounds__(kThreads) void k_row_fill(const int64_t* __restrict__ rowptr,
+                                                       const int* __restrict__ col,
+                                                       const double* __restrict__ val, int64_t m,
+                                                       const int64_t* __restrict__ rp, int* __restrict__ rc,
+                                                       int* __restrict__ ccnt) {
+    WAVE_NODE(i, m)
+    int64_t base = rp[i];
+    const int64_t end = rowptr[i + 1];
+    for (int64_t e0 = rowptr[i]; e0 < end; e0 += 64) {
+        const int64_t e = e0 + lane;
+        const bool keep = e < end && (val == nullptr || val[e] != 0.0);
+        const unsigned long long mask = __ballot(keep);
+        if (keep) {
+            const int pos = __popcll(mask & ((1ull << lane) - 1ull));
+            const int c = col[e];
+            rc[base + pos] = c;
+            atomicAdd(&ccnt[c], 1);
+        }
+        base += __popcll(mask);
     }
 }
 
 // CSC from the kept CSR; the order inside a column is immaterial (degrees and components
 // do not depend on it)
-__global__ void k_col_fill(const int64_t* __restrict__ rp, const int* __restrict__ rc, int64_t m,
-                           int* __restrict__ cpos, int* __restrict__ cr) {
-    GRID_STRIDE(i, m) {
-        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
-            const int slot = atomicAdd(&cpos[rc[e]], 1);
-            cr[slot] = static_cast<int>(i);
-        }
+__global__ __launch_bounds__(kThreads) void k_col_fill(const int64_t* __restrict__ rp, const int* __restrict__ rc,
+                                                       int64_t m, int* __restrict__ cpos, int* __restrict__ cr) {
+    WAVE_NODE(i, m)
+    for (int64_t e = rp[i] + lane; e < rp[i + 1]; e += 64) {
+        const int slot = atomicAdd(&cpos[rc[e]], 1);
+        cr[slot] = static_cast<int>(i);
     }
 }
 
@@ -145,28 +190,56 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(const int* __restrict__
 }
 
 // ---- degrees and hubs ------------------------------------------------------------------
-__global__ void k_degrees(const int64_t* __restrict__ ptr, const int* __restrict__ idx, int64_t cnt,
-                          const unsigned char* __restrict__ alive_self,
-                          const unsigned char* __restrict__ alive_other, int* __restrict__ deg,
-                          int* __restrict__ hist) {
+// A node with at most kLight edges is handled by one thread; heavier nodes (listed once) by
+// one wave each, lanes striding over the edges (hub-like nodes have thousands).
+constexpr int64_t kLight = 64;
+
+__device__ inline void put_degree(int64_t v, int d, int* deg, int* hist, int* dmax) {
+    deg[v] = d;
+    atomicAdd(&hist[d], 1);
+    atomicMax(dmax, d);
+}
+
+__global__ __launch_bounds__(kThreads) void k_degrees(const int64_t* __restrict__ ptr, const int* __restrict__ idx,
+                                                      int64_t cnt, const unsigned char* __restrict__ alive_self,
+                                                      const unsigned char* __restrict__ alive_other,
+                                                      int* __restrict__ deg, int* __restrict__ hist,
+                                                      int* __restrict__ dmax) {
     GRID_STRIDE(v, cnt) {
         if (!alive_self[v]) {
             deg[v] = -1;
             continue;
         }
+        const int64_t b = ptr[v], e1 = ptr[v + 1];
+        if (e1 - b > kLight) continue;   // heavy: k_degrees_heavy
         int d = 0;
-        for (int64_t e = ptr[v]; e < ptr[v + 1]; ++e) d += alive_other[idx[e]];
-        deg[v] = d;
-        atomicAdd(&hist[d], 1);
+        for (int64_t e = b; e < e1; ++e) d += alive_other[idx[e]];
+        put_degree(v, d, deg, hist, dmax);
     }
+}
+
+__global__ __launch_bounds__(kThreads) void k_degrees_heavy(const int64_t* __restrict__ ptr,
+                                                            const int* __restrict__ idx,
+                                                            const int* __restrict__ heavy, int64_t nheavy,
+                                                            const unsigned char* __restrict__ alive_self,
+                                                            const unsigned char* __restrict__ alive_other,
+                                                            int* __restrict__ deg, int* __restrict__ hist,
+                                                            int* __restrict__ dmax) {
+    WAVE_NODE(h, nheavy)
+    const int64_t v = heavy[h];
+    if (!alive_self[v]) return;   // deg[v] = -1 was written by k_degrees
+    int d = 0;
+    for (int64_t e = ptr[v] + lane; e < ptr[v + 1]; e += 64) d += alive_other[idx[e]];
+    d = wave_sum_i(d);
+    if (lane == 0) put_degree(v, d, deg, hist, dmax);
 }
 
 // One workgroup: the threshold degree D with count(deg > D) < h <= count(deg >= D), written
 // as out[0] = D, out[1] = h - count(deg > D) (nodes of degree D to take, lowest index first).
-__global__ __launch_bounds__(1024) void k_hub_threshold(const int* __restrict__ hist, int64_t maxdeg, int64_t h,
-                                                        int64_t* __restrict__ out) {
+__global__ __launch_bounds__(1024) void k_hub_threshold(const int* __restrict__ hist, const int* __restrict__ dmax,
+                                                        int64_t h, int64_t* __restrict__ out) {
     __shared__ int64_t s[1024];
-    const int64_t bins = maxdeg + 1;
+    const int64_t bins = static_cast<int64_t>(*dmax) + 1;   // every bin above the largest degree is empty
     const int64_t chunk = (bins + 1023) / 1024;
     // chunk t covers degrees from the top: [bins - (t+1) chunk, bins - t chunk)
     const int64_t hi = bins - static_cast<int64_t>(threadIdx.x) * chunk;
@@ -215,19 +288,21 @@ __global__ void k_hub_keys(const int* __restrict__ deg, int64_t cnt, const int64
     const int64_t take = thr[1];
     GRID_STRIDE(v, cnt) {
         const int d = deg[v];
-        if (d < 0) continue;
-        if (d > D || (d == D && eqrank[v] < take)) {
-            const int slot = atomicAdd(nkeys, 1);
+        const bool hub = d >= 0 && (d > D || (d == D && eqrank[v] < take));
+        const int slot = wave_slot(hub, nkeys);
+        if (hub)
             keys[slot] = (static_cast<unsigned long long>(0x7FFFFFFF - d) << 32) | static_cast<unsigned long long>(v);
-        }
     }
 }
 
-// hub r (in key order) takes id hi - r and leaves the graph
-__global__ void k_hub_assign(const unsigned long long* __restrict__ keys, int64_t h, int64_t hi,
+// hub r (in key order) takes id hi - r and leaves the graph; slots still holding the
+// all-ones filler (fewer keys than expected) are skipped, and the final id check reports it
+__global__ void k_hub_assign(const unsigned long long* __restrict__ keys, int64_t h, int64_t hi, int64_t cnt,
                              int* __restrict__ pi, unsigned char* __restrict__ alive) {
     GRID_STRIDE(r, h) {
-        const int v = static_cast<int>(keys[r] & 0xFFFFFFFFull);
+        const unsigned long long key = keys[r];
+        const int64_t v = static_cast<int64_t>(key & 0xFFFFFFFFull);
+        if (key == ~0ull || v >= cnt) continue;
         pi[v] = static_cast<int>(hi - r);
         alive[v] = 0;
     }
@@ -274,6 +349,34 @@ __global__ __launch_bounds__(1024) void k_bitonic_local(unsigned long long* __re
         if (base + t < n) a[base + t] = s[t];
 }
 
+// the whole sort of at most 4096 keys in one workgroup
+__global__ __launch_bounds__(1024) void k_bitonic_small(unsigned long long* __restrict__ a, int64_t n) {
+    __shared__ unsigned long long s[4096];
+    for (int t = threadIdx.x; t < n; t += 1024) s[t] = a[t];
+    __syncthreads();
+    for (int k = 2; k <= n; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = threadIdx.x; t < n; t += 1024) {
+                const int l = t ^ j;
+                if (l > t) {
+                    const bool up = (t & k) == 0;
+                    const unsigned long long x = s[t], y = s[l];
+                    if ((x > y) == up) {
+                        s[t] = y;
+                        s[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    for (int t = threadIdx.x; t < n; t += 1024) a[t] = s[t];
+}
+
+__global__ void k_copy_u64(const unsigned long long* __restrict__ src, int64_t n,
+                           unsigned long long* __restrict__ dst) {
+    GRID_STRIDE(i, n) dst[i] = src[i];
+}
+
 __global__ void k_fill_u8(unsigned char* __restrict__ a, int64_t n, unsigned char v) {
     GRID_STRIDE(i, n) a[i] = v;
 }
@@ -289,52 +392,107 @@ __global__ void k_cc_init(const unsigned char* __restrict__ aliveT, const unsign
     GRID_STRIDE(v, m + n) lab[v] = (v < m ? aliveT[v] : aliveF[v - m]) ? static_cast<int>(v) : -1;
 }
 
-// min over every alive edge, both ends; `changed` is set when a label drops
-__global__ void k_cc_hook(const int64_t* __restrict__ rp, const int* __restrict__ rc, int64_t m,
-                          int* __restrict__ lab, int* __restrict__ changed) {
-    GRID_STRIDE(i, m) {
-        const int li = lab[i];
-        if (li < 0) continue;
-        int best = li;
-        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
-            const int64_t vj = m + rc[e];
-            const int lj = lab[vj];
-            if (lj < 0) continue;
-            if (lj < best) best = lj;
-            if (li < lj) {
-                if (atomicMin(&lab[vj], li) > li) *changed = 1;
-            }
+// ---- union-find ------------------------------------------------------------------------
+// p[v] <= v always: a root is only ever hooked under a smaller root, so the root of every
+// set is its smallest code, whatever the order of the unions. find() halves the path it
+// walks (benign races: every write moves a node to one of its ancestors).
+// Parent reads and writes go to the device-coherent level (relaxed atomics at agent
+// scope): plain loads may be served from a compute unit's own cache, which does not see
+// the hooks other compute units make during the launch.
+__device__ inline int uf_load(const int* p, int v) {
+    return __hip_atomic_load(p + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline void uf_store(int* p, int v, int x) {
+    __hip_atomic_store(p + v, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline int uf_find(int* p, int v) {
+    int par = uf_load(p, v);
+    if (par != v) {
+        int prev = v, next;
+        while (par > (next = uf_load(p, par))) {
+            uf_store(p, prev, next);
+            prev = par;
+            par = next;
         }
-        if (best < li) {
-            if (atomicMin(&lab[i], best) > best) *changed = 1;
+    }
+    return par;
+}
+
+__device__ inline void uf_unite(int* p, int a, int b) {
+    int ra = uf_find(p, a), rb = uf_find(p, b);
+    while (ra != rb) {
+        if (ra > rb) {
+            const int t = ra;
+            ra = rb;
+            rb = t;
+        }
+        // hook the larger root rb under ra; if rb stopped being a root, climb and retry
+        const int old = atomicCAS(&p[rb], rb, ra);
+        if (old == rb) break;
+        rb = uf_find(p, old);
+        ra = uf_find(p, ra);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_uf_hook(const int64_t* __restrict__ rp, const int* __restrict__ rc,
+                                                      int64_t m, int* p) {
+    GRID_STRIDE(i, m) {
+        const int64_t b = rp[i], e1 = rp[i + 1];
+        if (e1 - b > kLight || p[i] < 0) continue;   // heavy rows: k_uf_hook_heavy
+        for (int64_t e = b; e < e1; ++e) {
+            const int vj = static_cast<int>(m + rc[e]);
+            if (p[vj] >= 0) uf_unite(p, static_cast<int>(i), vj);
         }
     }
 }
 
-// pointer jumping: lab[v] <- lab[lab[v]] until it stops dropping (labels only decrease and
-// stay inside the component, so the walk ends)
-__global__ void k_cc_jump(int64_t total, int* __restrict__ lab, int* __restrict__ changed) {
+__global__ __launch_bounds__(kThreads) void k_uf_hook_heavy(const int64_t* __restrict__ rp, const int* __restrict__ rc,
+                                                            int64_t m, const int* __restrict__ heavy, int64_t nheavy,
+                                                            int* p) {
+    WAVE_NODE(h, nheavy)
+    const int64_t i = heavy[h];
+    if (p[i] < 0) return;
+    for (int64_t e = rp[i] + lane; e < rp[i + 1]; e += 64) {
+        const int vj = static_cast<int>(m + rc[e]);
+        if (p[vj] >= 0) uf_unite(p, static_cast<int>(i), vj);
+    }
+}
+
+// every alive node points at its root (after all unions). The walk only reads: a halving
+// store here could overwrite a node already set to its root with an older ancestor, and the
+// node would end outside its component's count. The only stores are roots.
+__global__ void k_uf_compress(int64_t total, int* p) {
     GRID_STRIDE(v, total) {
-        int l = lab[v];
-        if (l < 0) continue;
-        int nl = lab[l];
-        bool moved = false;
-        while (nl >= 0 && nl < l) {
-            l = nl;
-            nl = lab[l];
-            moved = true;
-        }
-        if (moved) {
-            if (atomicMin(&lab[v], l) > l) *changed = 1;
-        }
+        int r = uf_load(p, static_cast<int>(v));
+        if (r < 0) continue;
+        for (int nx = uf_load(p, r); nx != r; nx = uf_load(p, r)) r = nx;
+        uf_store(p, static_cast<int>(v), r);
     }
 }
 
 // sizes per root code; the giant as the maximum of (size, -code) packed in 64 bits
-__global__ void k_cc_sizes(const int* __restrict__ lab, int64_t total, int* __restrict__ size) {
-    GRID_STRIDE(v, total) {
-        const int l = lab[v];
-        if (l >= 0) atomicAdd(&size[l], 1);
+// most nodes share the giant's label: the lanes of a wave with equal labels add together
+__global__ __launch_bounds__(kThreads) void k_cc_sizes(const int* __restrict__ lab, int64_t total,
+                                                       int* __restrict__ size) {
+    const int lane = threadIdx.x % 64;
+    // the loop bound is uniform across the workgroup, so every lane joins every ballot
+    for (int64_t base = static_cast<int64_t>(blockIdx.x) * blockDim.x; base < total;
+         base += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t v = base + threadIdx.x;
+        const int l = v < total ? lab[v] : -1;
+        bool pending = l >= 0;
+        while (true) {
+            const unsigned long long act = __ballot(pending);
+            if (!act) break;
+            const int leader = __ffsll(static_cast<long long>(act)) - 1;
+            const int ll = __shfl(l, leader, 64);
+            const bool mine = pending && l == ll;
+            const unsigned long long same = __ballot(mine);
+            if (lane == leader) atomicAdd(&size[ll], __popcll(same));
+            if (mine) pending = false;
+        }
     }
 }
 
@@ -351,17 +509,17 @@ __global__ void k_cc_giant(const int* __restrict__ lab, const int* __restrict__ 
 }
 
 // nodes of the giant (count) and keys (code, index) of every other alive node
-__global__ void k_spoke_keys(const int* __restrict__ lab, int64_t from, int64_t cnt, int giant,
-                             unsigned long long* __restrict__ keys, int* __restrict__ nkeys, int* __restrict__ ngiant) {
+__global__ void k_spoke_keys(const int* __restrict__ lab, int64_t from, int64_t cnt,
+                             const unsigned long long* __restrict__ best, unsigned long long* __restrict__ keys,
+                             int* __restrict__ nkeys, int* __restrict__ ngiant) {
+    const int giant = 0x7FFFFFFF - static_cast<int>(*best & 0xFFFFFFFFull);
     GRID_STRIDE(i, cnt) {
         const int l = lab[from + i];
-        if (l < 0) continue;
-        if (l == giant) {
-            atomicAdd(ngiant, 1);
-        } else {
-            const int slot = atomicAdd(nkeys, 1);
-            keys[slot] = (static_cast<unsigned long long>(l) << 32) | static_cast<unsigned long long>(i);
-        }
+        const bool in_giant = l >= 0 && l == giant;
+        const bool spoke = l >= 0 && l != giant;
+        wave_slot(in_giant, ngiant);
+        const int slot = wave_slot(spoke, nkeys);
+        if (spoke) keys[slot] = (static_cast<unsigned long long>(l) << 32) | static_cast<unsigned long long>(i);
     }
 }
 
@@ -394,18 +552,23 @@ __global__ void k_check_rowptr(const int64_t* __restrict__ rowptr, int64_t m, in
 }
 
 // pass 2 (only after pass 1): columns in [0, n), strictly increasing per row; finite values
-__global__ void k_check_entries(const int64_t* __restrict__ rowptr, const int* __restrict__ col,
-                                const double* __restrict__ val, int64_t m, int64_t n, int* __restrict__ bad) {
-    GRID_STRIDE(i, m) {
-        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
-            const int c = col[e];
-            if (c < 0 || c >= n || (e > rowptr[i] && c <= col[e - 1])) atomicOr(bad, 2);
-            if (val && !isfinite(val[e])) atomicOr(bad, 4);
-        }
+__global__ __launch_bounds__(kThreads) void k_check_entries(const int64_t* __restrict__ rowptr,
+                                                             const int* __restrict__ col,
+                                                             const double* __restrict__ val, int64_t m, int64_t n,
+                                                             int* __restrict__ bad) {
+    WAVE_NODE(i, m)
+    int flags = 0;
+    for (int64_t e = rowptr[i] + lane; e < rowptr[i + 1]; e += 64) {
+        const int c = col[e];
+        if (c < 0 || c >= n || (e > rowptr[i] && c <= col[e - 1])) flags |= 2;
+        if (val && !isfinite(val[e])) flags |= 4;
     }
+    if (__any(flags & 2) && lane == 0) atomicOr(bad, 2);
+    if (__any(flags & 4) && lane == 0) atomicOr(bad, 4);
 }
 
 #undef GRID_STRIDE
+#undef WAVE_NODE
 
 // ---- host helpers ----------------------------------------------------------------------
 struct DevBuf {
@@ -443,6 +606,10 @@ void sort_keys(unsigned long long* keys, int64_t n, hipStream_t st) {
     while (p2 < n) p2 <<= 1;
     if (p2 > n)
         hipLaunchKernelGGL(k_fill_u64, dim3(grid_of(p2 - n)), dim3(kThreads), 0, st, keys, n, p2, ~0ull);
+    if (p2 <= 4096) {
+        hipLaunchKernelGGL(k_bitonic_small, dim3(1), dim3(1024), 0, st, keys, p2);
+        return;
+    }
     const unsigned lb = static_cast<unsigned>((p2 + 4095) / 4096);
     for (int64_t k = 2; k <= p2; k <<= 1) {
         int64_t j = k >> 1;
@@ -495,7 +662,7 @@ int validate_csr_gpu(int64_t m, int64_t n, int64_t nnz, const int64_t* rowptr, c
         set_error("rowptr must start at 0, end at nnz and be monotone");
         rc = FASTPI_ESHAPE;
     } else {
-        hipLaunchKernelGGL(k_check_entries, dim3(grid_of(m)), dim3(kThreads), 0, st, rowptr, col, val, m, n, dbad);
+        hipLaunchKernelGGL(k_check_entries, dim3(wave_grid(m)), dim3(kThreads), 0, st, rowptr, col, val, m, n, dbad);
         if (!read()) {
             set_error("GPU validation failed");
             rc = FASTPI_EHIP;
@@ -545,8 +712,14 @@ int reorder_pattern_gpu(int64_t m, int64_t n, const int64_t* rowptr, const int32
     int* size = db.get<int>(total);
     int* piT = db.get<int>(m);
     int* piF = db.get<int>(n);
-    unsigned long long* keys = db.get<unsigned long long>(pow2_at_least(side));
-    int* words = db.get<int>(8);   // [0] key count, [1] giant nodes, [2] changed, [3] components
+    unsigned long long* keysT = db.get<unsigned long long>(pow2_at_least(m));
+    unsigned long long* keysF = db.get<unsigned long long>(pow2_at_least(n));
+    unsigned long long* logT = db.get<unsigned long long>(m);   // sorted spoke keys of every iteration
+    unsigned long long* logF = db.get<unsigned long long>(n);
+    // [0] row keys, [1] row giant nodes, [3] components, [4] column keys, [5] column giant nodes,
+    // [6] [7] row and column hub keys
+    int* words = db.get<int>(8);
+    int* dmax = db.get<int>(2);   // largest degree of the rows, of the columns
     unsigned long long* best = db.get<unsigned long long>(1);
     Scan sc;
     sc.cap = (side + kScanBlock - 1) / kScanBlock + 1;
@@ -575,11 +748,13 @@ int reorder_pattern_gpu(int64_t m, int64_t n, const int64_t* rowptr, const int32
         return hipMemcpyAsync(hwords, words, 8 * sizeof(int), hipMemcpyDeviceToHost, st) == hipSuccess && sync();
     };
 
+    int *heavyT = nullptr, *heavyF = nullptr;
+    int64_t nheavyT = 0, nheavyF = 0;
     // graph without stored zeros: CSR, then CSC (column cursors start at the column offsets)
-    hipLaunchKernelGGL(k_row_keep, dim3(grid_of(m)), dim3(kThreads), 0, st, rowptr, val, m, cnt);
+    hipLaunchKernelGGL(k_row_keep, dim3(wave_grid(m)), dim3(kThreads), 0, st, rowptr, val, m, cnt);
     scan_ints(cnt, m, 0, rp, sc, st);
     launch_fill_i32(ccnt, n, 0, st);
-    hipLaunchKernelGGL(k_row_fill, dim3(grid_of(m)), dim3(kThreads), 0, st, rowptr, col, val, m, rp, rc, ccnt);
+    hipLaunchKernelGGL(k_row_fill, dim3(wave_grid(m)), dim3(kThreads), 0, st, rowptr, col, val, m, rp, rc, ccnt);
     scan_ints(ccnt, n, 0, cp, sc, st);
     {
         std::vector<int64_t> hcp(static_cast<size_t>(n) + 1);
@@ -591,55 +766,59 @@ int reorder_pattern_gpu(int64_t m, int64_t n, const int64_t* rowptr, const int32
         if (hipMemcpyAsync(cpos, hpos.data(), n * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess)
             return hip_fail("copy failed");
         out.nnz_edges = hcp[n];
-        hipLaunchKernelGGL(k_col_fill, dim3(grid_of(m)), dim3(kThreads), 0, st, rp, rc, m, cpos, cr);
-        if (!sync()) return hip_fail("graph build failed");
+        hipLaunchKernelGGL(k_col_fill, dim3(wave_grid(m)), dim3(kThreads), 0, st, rp, rc, m, cpos, cr);
+        // nodes with more than kLight edges go to the one-wave-per-node kernels
+        std::vector<int64_t> hrp(static_cast<size_t>(m) + 1);
+        if (hipMemcpyAsync(hrp.data(), rp, (m + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            !sync())
+            return hip_fail("graph build failed");
+        std::vector<int> hT, hF;
+        for (int64_t i = 0; i < m; ++i)
+            if (hrp[i + 1] - hrp[i] > kLight) hT.push_back(static_cast<int>(i));
+        for (int64_t j = 0; j < n; ++j)
+            if (hcp[j + 1] - hcp[j] > kLight) hF.push_back(static_cast<int>(j));
+        nheavyT = static_cast<int64_t>(hT.size());
+        nheavyF = static_cast<int64_t>(hF.size());
+        heavyT = db.get<int>(nheavyT);
+        heavyF = db.get<int>(nheavyF);
+        if (!heavyT || !heavyF) {
+            set_error("GPU reordering: device allocation failed");
+            return FASTPI_ENOMEM;
+        }
+        if ((nheavyT && hipMemcpyAsync(heavyT, hT.data(), nheavyT * sizeof(int), hipMemcpyHostToDevice, st) !=
+                            hipSuccess) ||
+            (nheavyF && hipMemcpyAsync(heavyF, hF.data(), nheavyF * sizeof(int), hipMemcpyHostToDevice, st) !=
+                            hipSuccess) ||
+            !sync())
+            return hip_fail("graph build failed");
     }
     hipLaunchKernelGGL(k_fill_u8, dim3(grid_of(m)), dim3(kThreads), 0, st, aliveT, m, static_cast<unsigned char>(1));
     hipLaunchKernelGGL(k_fill_u8, dim3(grid_of(n)), dim3(kThreads), 0, st, aliveF, n, static_cast<unsigned char>(1));
     launch_fill_i32(piT, m, -1, st);
     launch_fill_i32(piF, n, -1, st);
 
-    // hubs of one side from its degrees and histogram (maxdeg: the other side's size)
-    auto take_hubs = [&](int64_t cntv, int64_t maxdeg, const int* deg, const int* hist, int64_t h, int64_t& hi,
-                         int* pi, unsigned char* alive) -> bool {
-        if (h <= 0) return true;
-        hipLaunchKernelGGL(k_hub_threshold, dim3(1), dim3(1024), 0, st, hist, maxdeg, h, thr);
+    // hubs of one side from its degrees and histogram (maxdeg: the other side's size); the key
+    // slots start as all-ones so that a short count cannot hand out stale indices
+    auto take_hubs = [&](int64_t cntv, const int* dm, const int* deg, const int* hist, int64_t h, int64_t& hi,
+                         int* pi, unsigned char* alive, unsigned long long* keys, int* nkeys) {
+        if (h <= 0) return;
+        hipLaunchKernelGGL(k_fill_u64, dim3(grid_of(h)), dim3(kThreads), 0, st, keys, static_cast<int64_t>(0), h,
+                           ~0ull);
+        hipLaunchKernelGGL(k_hub_threshold, dim3(1), dim3(1024), 0, st, hist, dm, h, thr);
         hipLaunchKernelGGL(k_eq_flags, dim3(grid_of(cntv)), dim3(kThreads), 0, st, deg, cntv, thr, flag);
         scan_ints(flag, cntv, 0, rank, sc, st);
-        launch_fill_i32(words, 8, 0, st);
         hipLaunchKernelGGL(k_hub_keys, dim3(grid_of(cntv)), dim3(kThreads), 0, st, deg, cntv, thr, rank, keys,
-                           words);
-        // exactly h keys, or the ids below would come from unwritten slots
-        if (!read_words() || hwords[0] != h) return false;
+                           nkeys);
         sort_keys(keys, h, st);
-        hipLaunchKernelGGL(k_hub_assign, dim3(grid_of(h)), dim3(kThreads), 0, st, keys, h, hi, pi, alive);
+        hipLaunchKernelGGL(k_hub_assign, dim3(grid_of(h)), dim3(kThreads), 0, st, keys, h, hi, cntv, pi, alive);
         hi -= h;
-        return true;
-    };
-    // the non-giant nodes of one side, sorted by (component code, index); returns their codes
-    auto take_spokes = [&](int64_t from, int64_t cntv, int giant, int64_t& lo, int* pi, unsigned char* alive,
-                           std::vector<int>& codes, int64_t& ngiant) -> bool {
-        launch_fill_i32(words, 8, 0, st);
-        hipLaunchKernelGGL(k_spoke_keys, dim3(grid_of(cntv)), dim3(kThreads), 0, st, lab, from, cntv, giant, keys,
-                           words, words + 1);
-        if (!read_words()) return false;
-        const int64_t nk = hwords[0];
-        ngiant = hwords[1];
-        codes.assign(static_cast<size_t>(nk), 0);
-        if (nk == 0) return true;
-        sort_keys(keys, nk, st);
-        hipLaunchKernelGGL(k_spoke_assign, dim3(grid_of(nk)), dim3(kThreads), 0, st, keys, nk, lo, pi, alive);
-        std::vector<unsigned long long> hk(static_cast<size_t>(nk));
-        if (hipMemcpyAsync(hk.data(), keys, nk * sizeof(unsigned long long), hipMemcpyDeviceToHost, st) !=
-                hipSuccess ||
-            !sync())
-            return false;
-        for (int64_t r = 0; r < nk; ++r) codes[r] = static_cast<int>(hk[r] >> 32);
-        lo += nk;
-        return true;
     };
 
     out.blocks.clear();
+    struct Peel {
+        int64_t loT, loF, offT, offF, nkT, nkF;   // ids and log offsets of one iteration's spokes
+    };
+    std::vector<Peel> peels;
     int64_t nT = m, nF = n, loT = 0, loF = 0, hiT = m - 1, hiF = n - 1, iters = 0;
     while (true) {
         ++iters;
@@ -647,62 +826,93 @@ int reorder_pattern_gpu(int64_t m, int64_t n, const int64_t* rowptr, const int32
         // 1. degrees of both sides in the current graph
         launch_fill_i32(histT, n + 1, 0, st);
         launch_fill_i32(histF, m + 1, 0, st);
-        hipLaunchKernelGGL(k_degrees, dim3(grid_of(m)), dim3(kThreads), 0, st, rp, rc, m, aliveT, aliveF, degT,
-                           histT);
-        hipLaunchKernelGGL(k_degrees, dim3(grid_of(n)), dim3(kThreads), 0, st, cp, cr, n, aliveF, aliveT, degF,
-                           histF);
-        // 2. hubs take the highest free ids
-        if (!take_hubs(m, n, degT, histT, mh, hiT, piT, aliveT) || !take_hubs(n, m, degF, histF, nh, hiF, piF, aliveF))
-            return hip_fail("hub selection failed");
-        // 3. components of the rest
-        hipLaunchKernelGGL(k_cc_init, dim3(grid_of(total)), dim3(kThreads), 0, st, aliveT, aliveF, m, n, lab);
-        for (int pass = 0;; ++pass) {
-            launch_fill_i32(words, 8, 0, st);
-            hipLaunchKernelGGL(k_cc_hook, dim3(grid_of(m)), dim3(kThreads), 0, st, rp, rc, m, lab, words + 2);
-            hipLaunchKernelGGL(k_cc_jump, dim3(grid_of(total)), dim3(kThreads), 0, st, total, lab, words + 2);
-            if (!read_words()) return hip_fail("component labelling failed");
-            if (hwords[2] == 0) break;
-            if (pass > 4 * (total + 1)) return hip_fail("component labelling did not settle");
-        }
-        // 4. giant: most nodes, the smallest code on ties
-        launch_fill_i32(size, total, 0, st);
         launch_fill_i32(words, 8, 0, st);
+        launch_fill_i32(dmax, 2, 0, st);
+        hipLaunchKernelGGL(k_degrees, dim3(grid_of(m)), dim3(kThreads), 0, st, rp, rc, m, aliveT, aliveF, degT,
+                           histT, dmax);
+        if (nheavyT)
+            hipLaunchKernelGGL(k_degrees_heavy, dim3(wave_grid(nheavyT)), dim3(kThreads), 0, st, rp, rc, heavyT,
+                               nheavyT, aliveT, aliveF, degT, histT, dmax);
+        hipLaunchKernelGGL(k_degrees, dim3(grid_of(n)), dim3(kThreads), 0, st, cp, cr, n, aliveF, aliveT, degF,
+                           histF, dmax + 1);
+        if (nheavyF)
+            hipLaunchKernelGGL(k_degrees_heavy, dim3(wave_grid(nheavyF)), dim3(kThreads), 0, st, cp, cr, heavyF,
+                               nheavyF, aliveF, aliveT, degF, histF, dmax + 1);
+        // 2. hubs take the highest free ids
+        take_hubs(m, dmax, degT, histT, mh, hiT, piT, aliveT, keysT, words + 6);
+        take_hubs(n, dmax + 1, degF, histF, nh, hiF, piF, aliveF, keysF, words + 7);
+        // 3. components of the rest: union-find over the alive edges, then full compression
+        hipLaunchKernelGGL(k_cc_init, dim3(grid_of(total)), dim3(kThreads), 0, st, aliveT, aliveF, m, n, lab);
+        hipLaunchKernelGGL(k_uf_hook, dim3(grid_of(m)), dim3(kThreads), 0, st, rp, rc, m, lab);
+        if (nheavyT)
+            hipLaunchKernelGGL(k_uf_hook_heavy, dim3(wave_grid(nheavyT)), dim3(kThreads), 0, st, rp, rc, m, heavyT,
+                               nheavyT, lab);
+        hipLaunchKernelGGL(k_uf_compress, dim3(grid_of(total)), dim3(kThreads), 0, st, total, lab);
+        // 4. giant (most nodes, the smallest code on ties) and the spoke keys of both sides
+        launch_fill_i32(size, total, 0, st);
         hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(kThreads), 0, st, best, static_cast<int64_t>(0),
                            static_cast<int64_t>(1), 0ull);
         hipLaunchKernelGGL(k_cc_sizes, dim3(grid_of(total)), dim3(kThreads), 0, st, lab, total, size);
         hipLaunchKernelGGL(k_cc_giant, dim3(grid_of(total)), dim3(kThreads), 0, st, lab, size, total, best, words + 3);
-        if (hipMemcpyAsync(hbest, best, sizeof(unsigned long long), hipMemcpyDeviceToHost, st) != hipSuccess ||
-            !read_words())
-            return hip_fail("giant selection failed");
+        hipLaunchKernelGGL(k_spoke_keys, dim3(grid_of(m)), dim3(kThreads), 0, st, lab, static_cast<int64_t>(0), m,
+                           best, keysT, words, words + 1);
+        hipLaunchKernelGGL(k_spoke_keys, dim3(grid_of(n)), dim3(kThreads), 0, st, lab, m, n, best, keysF, words + 4,
+                           words + 5);
+        if (!read_words()) return hip_fail("component counts failed");
         if (hwords[3] == 0) {   // nothing left after the hubs
             nT = nF = 0;
             break;
         }
-        const int giant = 0x7FFFFFFF - static_cast<int>(*hbest & 0xFFFFFFFFull);
-        std::vector<int> codesT, codesF;
-        int64_t gT = 0, gF = 0;
-        const int64_t lo0T = loT, lo0F = loF;
-        if (!take_spokes(0, m, giant, loT, piT, aliveT, codesT, gT) ||
-            !take_spokes(m, n, giant, loF, piF, aliveF, codesF, gF))
-            return hip_fail("spoke assignment failed");
-        // blocks in component order: merge the two sorted code lists
-        {
-            size_t a = 0, b = 0;
-            int64_t r0 = lo0T, c0 = lo0F;
-            while (a < codesT.size() || b < codesF.size()) {
-                const int c = (b >= codesF.size() || (a < codesT.size() && codesT[a] <= codesF[b])) ? codesT[a]
-                                                                                                   : codesF[b];
+        const int64_t nkT = hwords[0], gT = hwords[1], nkF = hwords[4], gF = hwords[5];
+        // every node left after the hubs is in the giant or in a spoke
+        if (nkT + gT != nT - mh || nkF + gF != nF - nh) return hip_fail("component counts do not add up");
+        Peel pl{loT, loF, 0, 0, nkT, nkF};
+        pl.offT = peels.empty() ? 0 : peels.back().offT + peels.back().nkT;
+        pl.offF = peels.empty() ? 0 : peels.back().offF + peels.back().nkF;
+        if (nkT > 0) {
+            sort_keys(keysT, nkT, st);
+            hipLaunchKernelGGL(k_spoke_assign, dim3(grid_of(nkT)), dim3(kThreads), 0, st, keysT, nkT, loT, piT,
+                               aliveT);
+            hipLaunchKernelGGL(k_copy_u64, dim3(grid_of(nkT)), dim3(kThreads), 0, st, keysT, nkT, logT + pl.offT);
+        }
+        if (nkF > 0) {
+            sort_keys(keysF, nkF, st);
+            hipLaunchKernelGGL(k_spoke_assign, dim3(grid_of(nkF)), dim3(kThreads), 0, st, keysF, nkF, loF, piF,
+                               aliveF);
+            hipLaunchKernelGGL(k_copy_u64, dim3(grid_of(nkF)), dim3(kThreads), 0, st, keysF, nkF, logF + pl.offF);
+        }
+        peels.push_back(pl);
+        loT += nkT;
+        loF += nkF;
+        nT = gT;
+        nF = gF;
+        if (gT < mh || gF < nh || gT + gF == 0) break;
+    }
+    // blocks of every iteration, in component order: merge its two sorted code lists
+    {
+        const int64_t totT = peels.empty() ? 0 : peels.back().offT + peels.back().nkT;
+        const int64_t totF = peels.empty() ? 0 : peels.back().offF + peels.back().nkF;
+        std::vector<unsigned long long> hT(static_cast<size_t>(totT)), hF(static_cast<size_t>(totF));
+        if ((totT > 0 && hipMemcpyAsync(hT.data(), logT, totT * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                        st) != hipSuccess) ||
+            (totF > 0 && hipMemcpyAsync(hF.data(), logF, totF * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                        st) != hipSuccess) ||
+            !sync())
+            return hip_fail("copy of the component log failed");
+        for (const Peel& pl : peels) {
+            int64_t a = 0, b = 0, r0 = pl.loT, c0 = pl.loF;
+            auto codeT = [&](int64_t x) { return static_cast<int64_t>(hT[pl.offT + x] >> 32); };
+            auto codeF = [&](int64_t x) { return static_cast<int64_t>(hF[pl.offF + x] >> 32); };
+            while (a < pl.nkT || b < pl.nkF) {
+                const int64_t c = (b >= pl.nkF || (a < pl.nkT && codeT(a) <= codeF(b))) ? codeT(a) : codeF(b);
                 int64_t nr = 0, nc = 0;
-                while (a < codesT.size() && codesT[a] == c) ++a, ++nr;
-                while (b < codesF.size() && codesF[b] == c) ++b, ++nc;
+                while (a < pl.nkT && codeT(a) == c) ++a, ++nr;
+                while (b < pl.nkF && codeF(b) == c) ++b, ++nc;
                 out.blocks.push_back({r0, c0, nr, nc});
                 r0 += nr;
                 c0 += nc;
             }
         }
-        nT = gT;
-        nF = gF;
-        if (gT < mh || gF < nh || gT + gF == 0) break;
     }
     // the last giant: ascending ids
     if (nT > 0 || nF > 0) {

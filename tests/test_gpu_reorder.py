@@ -116,6 +116,10 @@ def test_workloads(env, name):
     host, gpu, th, tg = both(torch, fp, h, p.m, p.n, p.indptr, p.indices, p.data, CONFIGS[name].k)
     say(f"  host {th * 1e3:.1f} ms, GPU {tg * 1e3:.1f} ms, T_it {gpu[3]['T_it']}, blocks {len(gpu[2])}")
     assert same(host, gpu)
+    # the components come from concurrent unions: every repetition must give the same result
+    args = (p.m, p.n, dev_t(torch, p.indptr), dev_t(torch, p.indices), dev_t(torch, p.data))
+    for _ in range(3):
+        assert same(host, h.reorder(*args, k=CONFIGS[name].k))
 
 
 def test_batched_workload_instances(env):
