@@ -500,6 +500,16 @@ def main():
     t0 = time.perf_counter()
     plan = fp.Plan(prob.m, prob.n, prob.indptr, prob.indices, prob.data, alpha=cfg.alpha, k=cfg.k)
     plan_s = time.perf_counter() - t0
+    # the same plan with the reordering on the GPU (one warm-up call, then the median of three)
+    hr = fp.Handle(0)
+    fp.Plan(prob.m, prob.n, prob.indptr, prob.indices, prob.data, alpha=cfg.alpha, k=cfg.k, gpu=hr)
+    gpu_plan_times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        fp.Plan(prob.m, prob.n, prob.indptr, prob.indices, prob.data, alpha=cfg.alpha, k=cfg.k, gpu=hr)
+        gpu_plan_times.append(time.perf_counter() - t0)
+    plan_gpu_s = sorted(gpu_plan_times)[1]
+    del hr
     ranks_note = "alpha rule"
     if args.ranks == "learned":
         from paper_2011_04235_amd.rank_mlp import RankPredictor
@@ -647,6 +657,7 @@ def main():
                    "alpha": cfg.alpha, "shape": plan.info},
         "flop_model": F,
         "plan_s": round(plan_s, 4),
+        "plan_gpu_reorder_s": round(plan_gpu_s, 4),
         "sweeps": sweeps,
         "precision_compare": compare,
         "roofline": roof,
