@@ -385,8 +385,9 @@ static int build_sets(Group& g, hipStream_t st) {
 }
 
 // Randomized subspace iteration for the cores of update c (0: row, 1: column): Y = G Omega;
-// `iters` times Q = orth(Y), Y = G Q; two final orthonormalizations; the Rayleigh-Ritz
-// eigenpairs of B^T G B give the top t pairs (vectors B W_t). orth(Y) = Y V diag(d^-1/2) for
+// `iters` products by G, orthonormalized before every other one; two final
+// orthonormalizations; the Rayleigh-Ritz eigenpairs of B^T G B give the top t pairs (vectors
+// B W_t). orth(Y) = Y V diag(d^-1/2) for
 // the eigenpairs (d, V) of Y^T Y, which spans the same subspace as any other orthonormalization.
 static int rand_run(Group& g, int c, const RunCfg& cfg, hipStream_t st) {
     std::vector<RandCore>& cores = g.rcores[c];
@@ -429,20 +430,37 @@ static int rand_run(Group& g, int c, const RunCfg& cfg, hipStream_t st) {
         launch_gemm_nn(R.G, R.q, nullptr, R.Q, R.k, R.q, R.k, R.q, R.Y, R.k, nullptr, st, false);
     }
     int rc;
-    for (int it = 0; it < g.inner.iters; ++it) {
-        if ((rc = orth(true)) != FASTPI_OK) return rc;
+    // the current block alternates between Y and Q; every other power iteration skips the
+    // orthonormalization (the subspace is the same in exact arithmetic, and one product by G
+    // squares the block's condition number at most once between two of them)
+    bool in_y = true;
+    auto apply = [&]() {
         for (RandCore& R : cores)
-            launch_gemm_nn(R.G, R.q, nullptr, R.Q, R.k, R.q, R.k, R.q, R.Y, R.k, nullptr, st, false);
+            launch_gemm_nn(R.G, R.q, nullptr, in_y ? R.Y : R.Q, R.k, R.q, R.k, R.q, in_y ? R.Q : R.Y, R.k,
+                           nullptr, st, false);
+        in_y = !in_y;
+    };
+    auto normalize = [&]() -> int {
+        const int r = orth(in_y);
+        in_y = !in_y;
+        return r;
+    };
+    for (int it = 0; it < g.inner.iters; ++it) {
+        if (it % 2 == 0 && (rc = normalize()) != FASTPI_OK) return rc;
+        apply();
     }
-    if ((rc = orth(true)) != FASTPI_OK) return rc;    // basis in Q
-    if ((rc = orth(false)) != FASTPI_OK) return rc;   // re-orthonormalized basis in Y
+    if ((rc = normalize()) != FASTPI_OK) return rc;
+    if ((rc = normalize()) != FASTPI_OK) return rc;   // re-orthonormalized basis B
+    // Rayleigh-Ritz: H = B^T (G B), its eigenpairs, vectors B W_t
     for (RandCore& R : cores) {
-        launch_gemm_nn(R.G, R.q, nullptr, R.Y, R.k, R.q, R.k, R.q, R.Q, R.k, nullptr, st, false);
-        launch_gemm_tn(R.Y, R.k, R.Q, R.k, R.k, R.k, R.q, R.W, R.k, nullptr, nullptr, R.part, R.sp, st, false);
+        const double* B = in_y ? R.Y : R.Q;
+        double* GB = in_y ? R.Q : R.Y;
+        launch_gemm_nn(R.G, R.q, nullptr, B, R.k, R.q, R.k, R.q, GB, R.k, nullptr, st, false);
+        launch_gemm_tn(B, R.k, GB, R.k, R.k, R.k, R.q, R.W, R.k, nullptr, nullptr, R.part, R.sp, st, false);
     }
     if ((rc = eig()) != FASTPI_OK) return rc;
     for (RandCore& R : cores) {
-        launch_gemm_nn(R.Y, R.k, nullptr, R.Wv, R.k, R.q, R.t, R.k, R.vec_out, R.t, nullptr, st, false);
+        launch_gemm_nn(in_y ? R.Y : R.Q, R.k, nullptr, R.Wv, R.k, R.q, R.t, R.k, R.vec_out, R.t, nullptr, st, false);
         launch_copy(R.Wd, R.t, R.lam_out, st);
     }
     return launch_status();
