@@ -448,6 +448,42 @@ def run_eval_workload(args, torch, fp):
     print(json.dumps(out), flush=True)
 
 
+def run_reorder_workload(args, torch, fp):
+    """Algorithm 2 on the GPU (fastpi_reorder_gpu on the device CSR) against the host
+    reordering, on the same pattern: one warm-up call, then the median of --steps calls; the
+    two results must be identical."""
+    from synth import CONFIGS, make_problem
+    cfg = CONFIGS[args.config]
+    progress(f"generating {args.config}")
+    prob = make_problem(cfg)
+    dev = torch.device("cuda", 0)
+    h = fp.Handle(0)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    dargs = (prob.m, prob.n, t(prob.indptr), t(prob.indices), t(prob.data))
+    gpu = h.reorder(*dargs, k=cfg.k)
+    times = []
+    for _ in range(max(1, args.steps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gpu = h.reorder(*dargs, k=cfg.k)
+        times.append(time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    host = fp.reorder(prob.m, prob.n, prob.indptr, prob.indices, prob.data, k=cfg.k)
+    host_s = time.perf_counter() - t0
+    same = all(np.array_equal(a, b) for a, b in zip(host[:3], gpu[:3])) and host[3] == gpu[3]
+    ms = sorted(times)[len(times) // 2] * 1e3
+    out = {
+        "metric": "reordering time (Algorithm 2), GPU vs host, identical output",
+        "value": round(ms, 3), "unit": "ms", "n_gpus": 1, "steps": len(times), "warmup": 1,
+        "ms_per_step": round(ms, 3), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"fastpi {cfg.name}: A {prob.m}x{prob.n} ({prob.nnz} nnz), k {cfg.k}",
+                   "T_it": gpu[3]["T_it"], "blocks": int(len(gpu[2]))},
+        "host_ms": round(host_s * 1e3, 3), "identical": bool(same),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -466,6 +502,8 @@ def main():
     ap.add_argument("--inner", default="exact", choices=["exact", "rand"],
                     help="inner solver of the two updates: exact, or the randomized branch where "
                          "the target rank is low (oversampling 5, 11 power iterations)")
+    ap.add_argument("--reorder", action="store_true",
+                    help="time the GPU reordering against the host one on the workload's pattern")
     ap.add_argument("--eval", action="store_true",
                     help="time Application 1's evaluation loop (sparse-label apply + P@k scoring)")
     ap.add_argument("--ranks", default="alpha", choices=["alpha", "learned"],
@@ -491,6 +529,8 @@ def main():
         return run_batched_workload(args, torch, fp)
     if args.eval:
         return run_eval_workload(args, torch, fp)
+    if args.reorder:
+        return run_reorder_workload(args, torch, fp)
 
     cfg = CONFIGS[args.config]
     progress(f"generating {args.config}")
