@@ -66,8 +66,8 @@ BW = 16                  # eigensolver column block
 # scales read off a 256 MiB device copy in the same runs), and the digest of the kernel
 # source they were taken on; the figure is dropped (null) for any other workload and as
 # soon as the kernel's source differs.
-SOLVE_TRAFFIC_BYTES = {"c2": 3194395}
-SOLVE_TRAFFIC_DIGEST = "fba500e42e0dbc285d3bb2d2b59f88b04154aa3e948041015f2b07afbc94e9c2"
+SOLVE_TRAFFIC_BYTES = {"c2": 3193787}
+SOLVE_TRAFFIC_DIGEST = "8bb7f99cd14505103cbd1fba4f72c7c948042797cdac6d75b001a228722dc40a"
 
 
 def solve_traffic(config):

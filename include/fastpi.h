@@ -59,7 +59,14 @@ typedef struct {
 typedef struct {
     fastpi_precision precision;   /* FASTPI_FP64 (default) or FASTPI_MIXED                  */
     int max_sweeps;               /* Jacobi sweep cap (0 = default 60)                       */
-    double tol;                   /* Jacobi rotation threshold (0 = default, size * eps)     */
+    double tol;                   /* Jacobi rotation thresholds; 0 = defaults. The Jacobi    */
+                                  /* block SVDs rotate columns of cosine above p * tol (p:   */
+                                  /* block rows; default tol = eps of the block precision;   */
+                                  /* the FP32 blocks of FASTPI_MIXED never go below FP32     */
+                                  /* eps); every eigensolver (the cores of both updates, the */
+                                  /* Gram route of large blocks, the randomized solver's     */
+                                  /* small problems) above tol itself (default: its padded   */
+                                  /* order * FP64 eps)                                       */
     size_t max_workspace_bytes;   /* 0 = unlimited; larger needs fail with FASTPI_ENOMEM     */
 } fastpi_options;
 

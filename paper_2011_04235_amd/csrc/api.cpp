@@ -468,6 +468,7 @@ int fastpi_upload_plan(fastpi_handle* h, const fastpi_plan* plan) {
     int st = instance_upload(h->inst, plan->p, h->opts.max_workspace_bytes, h->stream);
     if (st != FASTPI_OK) return st;
     h->grp.inst = {&h->inst};
+    h->grp.eig_tol = h->opts.tol;
     if ((st = group_build(h->grp, h->device, h->stream)) != FASTPI_OK) return st;
     Tuning t;
     if (!h->tune_cache.empty() &&
@@ -1084,6 +1085,7 @@ int fastpi_batch_create(fastpi_batch** b, fastpi_handle* h, int64_t count,
         for (Instance& I : B->inst) B->grp.inst.push_back(&I);
         B->grp.inner = h->grp.inner;
         B->grp.big_cost = h->grp.big_cost;
+        B->grp.eig_tol = h->grp.eig_tol;
         st = group_build(B->grp, h->device, h->stream);
     }
     Tuning t;

@@ -263,9 +263,10 @@ void launch_block_svd_tasks(bool fp32, const BlockTask* tasks, int ntasks, int* 
     launch_fill_i32(counter, 1, 0, st);
     grid = std::max(1, std::min(grid, ntasks));
     if (fp32) {
+        // FP32 rounding bounds what the cosines can reach: a finer scale is taken as FLT_EPSILON
         const int64_t lds_elems = lds_bytes / static_cast<int>(sizeof(float));
         FASTPI_LAUNCH(timer, KT_BLOCK_SVD, k_block_svd<float>, dim3(grid), dim3(256), lds_bytes, st, tasks, ntasks,
-                      counter, lds_elems, max_sweeps, static_cast<float>(tol_scale > 0 ? tol_scale : FLT_EPSILON));
+                      counter, lds_elems, max_sweeps, static_cast<float>(std::max(tol_scale, static_cast<double>(FLT_EPSILON))));
     } else {
         const int64_t lds_elems = lds_bytes / static_cast<int>(sizeof(double));
         FASTPI_LAUNCH(timer, KT_BLOCK_SVD, k_block_svd<double>, dim3(grid), dim3(256), lds_bytes, st, tasks, ntasks,

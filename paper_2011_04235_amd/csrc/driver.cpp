@@ -302,7 +302,7 @@ static int make_rand_core(Group& g, int inst, int64_t q, int64_t t, const double
     double* eigws = R.part + static_cast<int64_t>(R.sp) * k * k;
     int* eigiws = reinterpret_cast<int*>(eigws + ed);
     // the k x k input (a basis' Gram matrix, then the projected core) may be overwritten
-    job = eig_make_job(R.W, R.W, k, k, R.Wd, R.Wv, eigws, eigiws, I.status, 0.0, g.tune.gram_rows, inst);
+    job = eig_make_job(R.W, R.W, k, k, R.Wd, R.Wv, eigws, eigiws, I.status, g.eig_tol, g.tune.gram_rows, inst);
     return FASTPI_OK;
 }
 
@@ -337,7 +337,7 @@ static int build_sets(Group& g, hipStream_t st) {
         double* ews = b.part + part;
         int* eiws = reinterpret_cast<int*>(ews + ed);
         // the status words of the block's matrix take its eigensolver's flags
-        j1.push_back(eig_make_job(b.G, b.G, q, t, b.lam, b.E, ews, eiws, g.inst[b.inst]->status, 0.0,
+        j1.push_back(eig_make_job(b.G, b.G, q, t, b.lam, b.E, ews, eiws, g.inst[b.inst]->status, g.eig_tol,
                                   g.tune.gram_rows, b.inst));
     }
     for (size_t i = 0; i < g.inst.size() && rc == FASTPI_OK; ++i) {
@@ -355,7 +355,7 @@ static int build_sets(Group& g, hipStream_t st) {
                 jr[0].push_back(J);
             } else {
                 j2.push_back(eig_make_job(ws + I.o_g2, ws + I.o_g2, d.n1, d.s, ws + I.o_lam2, ws + I.o_v2,
-                                          ws + I.o_eig, I.iws, I.status, 0.0, g.tune.gram_rows, tag));
+                                          ws + I.o_eig, I.iws, I.status, g.eig_tol, g.tune.gram_rows, tag));
             }
         }
         if (rc == FASTPI_OK && q3 > 0 && d.r > 0) {
@@ -369,7 +369,7 @@ static int build_sets(Group& g, hipStream_t st) {
                 g.sign_v2[i] = 1;
             } else {
                 j3.push_back(eig_make_job(ws + I.o_g3, ws + I.o_g3, q3, d.r, ws + I.o_lam3, ws + I.o_vt,
-                                          ws + I.o_eig, I.iws, I.status, 0.0, g.tune.gram_rows, tag));
+                                          ws + I.o_eig, I.iws, I.status, g.eig_tol, g.tune.gram_rows, tag));
             }
         }
     }
@@ -472,6 +472,7 @@ int group_build(Group& g, int device, hipStream_t st) {
     fresh.tune = g.tune;
     fresh.inner = g.inner;
     fresh.big_cost = g.big_cost;
+    fresh.eig_tol = g.eig_tol;
     group_free(g);
     g = fresh;
     HIP_TRY(hipDeviceGetAttribute(&g.ncu, hipDeviceAttributeMultiprocessorCount, device));

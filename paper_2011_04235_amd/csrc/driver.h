@@ -121,6 +121,7 @@ struct Group {
     int ntasks = 0;
     int* counter = nullptr;
     double big_cost = kBigBlockCost;   // p q^2 from which a block takes the Gram route
+    double eig_tol = 0;                // cosine threshold of every eigensolver job (0: order * eps)
     std::vector<BigBlock> big;      // blocks on the Gram route (not in `tasks`)
     EigSet set1;                    // their eigensolves
     std::vector<void*> ballocs;

@@ -202,23 +202,21 @@ __device__ __forceinline__ void rutishauser_rotation(double hpp, double hqq, dou
 // The same (smaller) rotation from the double angle, with a shorter dependency chain: for
 // d = hqq - hpp and r = sqrt(d^2 + 4 hpq^2), cos 2theta = |d| / r in [0, 1], so
 // c^2 = (1 + cos 2theta) / 2 and s = sign(d) hpq / (r c) (sign(0) = +1), c^2 + s^2 = 1.
-// Falls back to the tangent form when d^2 + 4 hpq^2 leaves the normal range.
-__device__ __forceinline__ void fast_rotation(double hpp, double hqq, double hpq, double& c, double& s) {
-    c = 1.0;
-    s = 0.0;
+// The identity (c, s) = (1, 0) unless `live` and the coupling exceeds rounding level.
+// Straight-line code with selects; where d^2 + 4 hpq^2 leaves the normal range the tangent
+// form is taken instead (rare: one branch at the end).
+__device__ __forceinline__ void fast_rotation(double hpp, double hqq, double hpq, bool live, double& c, double& s) {
     const double ahpq = fabs(hpq);
-    if (hpq == 0.0 || !(ahpq * ahpq > 0.25 * DBL_EPSILON * DBL_EPSILON * fabs(hpp) * fabs(hqq))) return;
+    const bool rot = live && hpq != 0.0 && ahpq * ahpq > 0.25 * DBL_EPSILON * DBL_EPSILON * fabs(hpp) * fabs(hqq);
     const double d = hqq - hpp;
     const double r2 = fma(d, d, 4.0 * hpq * hpq);
-    if (!(r2 > 1e-290 && r2 < 1e290)) {
-        rutishauser_rotation(hpp, hqq, hpq, c, s);
-        return;
-    }
-    const double rr = rsq3(r2);                   // 1 / r
+    const bool normal = r2 > 1e-290 && r2 < 1e290;
+    const double rr = rsq3(normal ? r2 : 1.0);      // 1 / r
     const double h = fma(0.5 * fabs(d), rr, 0.5);  // c^2
-    const double rc = rsq3(h);                    // 1 / c
-    c = h * rc;
-    s = (d < 0 ? -hpq : hpq) * (rr * rc);
+    const double rc = rsq3(h);                     // 1 / c
+    c = rot ? h * rc : 1.0;
+    s = rot ? (d < 0 ? -hpq : hpq) * (rr * rc) : 0.0;
+    if (rot && !normal) rutishauser_rotation(hpp, hqq, hpq, c, s);
 }
 
 // Slot permutation between inner steps. Slots 0..31 hold the 32 columns of a pair; step
@@ -235,6 +233,16 @@ __device__ __forceinline__ int inner_next_slot(int x) {
     return x + 2;                     // offset -d -> -(d+1)
 }
 
+// LDS slot of H[i][j] (and W[i][j]) in the pair solve: rows LS = 40 doubles apart, the even
+// columns of a row in its first 16 doubles and the odd ones in the next 16 (column 2k + 1 at
+// 16 + (k + 15) mod 16). The 16 lanes of a quarter wave share a row pair and, in a step, write
+// the next slots of the even (or odd) columns, read their own adjacent columns and read the
+// diagonal blocks of 16 distinct rows: with this map each of these accesses touches 16
+// distinct 8-byte bank pairs (and rows two apart land 16 pairs apart), where a plain
+// row-major layout serialises them two to four ways.
+constexpr int LS = 40;
+__device__ __forceinline__ int slot(int i, int j) { return i * LS + ((j & 1) ? 16 + (((j >> 1) + 15) & 15) : (j >> 1)); }
+
 // One workgroup of 256 threads per pair. Thread (a, b) keeps the 2x2 blocks
 // H[2a:2a+2][2b:2b+2] and W[2a:2a+2][2b:2b+2] in registers (H indexed by slots on both
 // sides, W by input column and slot), with a copy of H in LDS. In a step every thread
@@ -245,8 +253,8 @@ __device__ __forceinline__ int inner_next_slot(int x) {
 __global__ __launch_bounds__(256) void k_eig_solve(const EigJob* __restrict__ jobs,
                                                    const int* __restrict__ pre, int nact,
                                                    int* __restrict__ state, int inner_sweeps) {
-    __shared__ double Hs[2][PW][PW + 1];
-    __shared__ double Ws[2][PW][PW + 1];
+    __shared__ double Hs[2][PW * LS];
+    __shared__ double Ws[2][PW * LS];
     __shared__ int s_need;
     const int j = job_of(pre, nact, blockIdx.x);
     if (state[ST_WORDS * j + ST_DONE]) return;
@@ -275,7 +283,7 @@ __global__ __launch_bounds__(256) void k_eig_solve(const EigJob* __restrict__ jo
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int e = threadIdx.x + k * 256;
-            Hs[0][e / PW][e % PW] = acc[k];
+            Hs[0][slot(e / PW, e % PW)] = acc[k];
         }
     }
     if (threadIdx.x == 0) s_need = 0;
@@ -286,7 +294,7 @@ __global__ __launch_bounds__(256) void k_eig_solve(const EigJob* __restrict__ jo
         for (int e = threadIdx.x; e < PW * PW; e += 256) {
             const int i = e / PW, k = e % PW;
             if (i < k) {
-                const double hii = Hs[0][i][i], hkk = Hs[0][k][k], hik = Hs[0][i][k];
+                const double hii = Hs[0][slot(i, i)], hkk = Hs[0][slot(k, k)], hik = Hs[0][slot(i, k)];
                 if (hii > nf && hkk > nf && hik * hik > tol * tol * (hii * hkk)) need = 1;
             }
         }
@@ -299,7 +307,7 @@ __global__ __launch_bounds__(256) void k_eig_solve(const EigJob* __restrict__ jo
     }
     const int a = threadIdx.x / (PW / 2), b = threadIdx.x % (PW / 2);
     const int r0 = 2 * a, r1 = 2 * a + 1, c0 = 2 * b, c1 = 2 * b + 1;
-    double h00 = Hs[0][r0][c0], h01 = Hs[0][r0][c1], h10 = Hs[0][r1][c0], h11 = Hs[0][r1][c1];
+    double h00 = Hs[0][slot(r0, c0)], h01 = Hs[0][slot(r0, c1)], h10 = Hs[0][slot(r1, c0)], h11 = Hs[0][slot(r1, c1)];
     double w00 = (r0 == c0), w01 = (r0 == c1), w10 = (r1 == c0), w11 = (r1 == c1);
     // slot permutation of the four rows/columns this thread owns
     const int pr0 = inner_next_slot(r0), pr1 = inner_next_slot(r1);
@@ -307,20 +315,16 @@ __global__ __launch_bounds__(256) void k_eig_solve(const EigJob* __restrict__ jo
     int cur = 0;
     for (int sw = 0; sw < inner_sweeps; ++sw) {
         for (int step = 0; step < PW - 1; ++step) {
-            // the rotations of this thread's row pair a and column pair b, each computed
-            // from its diagonal 2 x 2 block (every thread computes the ones it needs)
-            double ca = 1.0, sa = 0.0, cb = 1.0, sb = 0.0;
+            // the rotations of this thread's column pair b (computed here from its diagonal
+            // 2 x 2 block) and row pair a (computed by lane a of the same wave, whose column
+            // pair is a: every wave holds all 16 rotations, so all threads apply bitwise the
+            // same ones)
+            double cb, sb;
             {
-                const double app = Hs[cur][r0][r0], apq = Hs[cur][r0][r1], aqq = Hs[cur][r1][r1];
-                if (app > nf && aqq > nf) fast_rotation(app, aqq, apq, ca, sa);
+                const double bpp = Hs[cur][slot(c0, c0)], bpq = Hs[cur][slot(c0, c1)], bqq = Hs[cur][slot(c1, c1)];
+                fast_rotation(bpp, bqq, bpq, bpp > nf && bqq > nf, cb, sb);
             }
-            if (b == a) {
-                cb = ca;
-                sb = sa;
-            } else {
-                const double bpp = Hs[cur][c0][c0], bpq = Hs[cur][c0][c1], bqq = Hs[cur][c1][c1];
-                if (bpp > nf && bqq > nf) fast_rotation(bpp, bqq, bpq, cb, sb);
-            }
+            const double ca = __shfl(cb, a, kWave), sa = __shfl(sb, a, kWave);
             // rows: new row p = c row_p - s row_q, new row q = s row_p + c row_q
             const double x00 = ca * h00 - sa * h10, x01 = ca * h01 - sa * h11;
             const double x10 = sa * h00 + ca * h10, x11 = sa * h01 + ca * h11;
@@ -338,23 +342,23 @@ __global__ __launch_bounds__(256) void k_eig_solve(const EigJob* __restrict__ jo
             // move to the next step's slots (W rows are input columns and stay); the buffer
             // written here was last read before the previous barrier
             const int nxt = cur ^ 1;
-            Hs[nxt][pr0][pc0] = h00;
-            Hs[nxt][pr0][pc1] = h01;
-            Hs[nxt][pr1][pc0] = h10;
-            Hs[nxt][pr1][pc1] = h11;
-            Ws[nxt][r0][pc0] = w00;
-            Ws[nxt][r0][pc1] = w01;
-            Ws[nxt][r1][pc0] = w10;
-            Ws[nxt][r1][pc1] = w11;
+            Hs[nxt][slot(pr0, pc0)] = h00;
+            Hs[nxt][slot(pr0, pc1)] = h01;
+            Hs[nxt][slot(pr1, pc0)] = h10;
+            Hs[nxt][slot(pr1, pc1)] = h11;
+            Ws[nxt][slot(r0, pc0)] = w00;
+            Ws[nxt][slot(r0, pc1)] = w01;
+            Ws[nxt][slot(r1, pc0)] = w10;
+            Ws[nxt][slot(r1, pc1)] = w11;
             __syncthreads();
-            h00 = Hs[nxt][r0][c0];
-            h01 = Hs[nxt][r0][c1];
-            h10 = Hs[nxt][r1][c0];
-            h11 = Hs[nxt][r1][c1];
-            w00 = Ws[nxt][r0][c0];
-            w01 = Ws[nxt][r0][c1];
-            w10 = Ws[nxt][r1][c0];
-            w11 = Ws[nxt][r1][c1];
+            h00 = Hs[nxt][slot(r0, c0)];
+            h01 = Hs[nxt][slot(r0, c1)];
+            h10 = Hs[nxt][slot(r1, c0)];
+            h11 = Hs[nxt][slot(r1, c1)];
+            w00 = Ws[nxt][slot(r0, c0)];
+            w01 = Ws[nxt][slot(r0, c1)];
+            w10 = Ws[nxt][slot(r1, c0)];
+            w11 = Ws[nxt][slot(r1, c1)];
             cur = nxt;
         }
     }

@@ -193,3 +193,29 @@ def test_mixed_precision_meets_gates(fp, torch, name, cfg, alpha):
     _, zinfo = compare_apply(prob, to_np(Z), ores)
     say(f"  {zinfo}")
     assert zinfo["ls_rel"] <= MIXED_LS_RTOL, zinfo
+
+
+def test_tolerance_option_reaches_the_eigensolvers(fp, torch):
+    """The handle's tol is the cosine threshold of the eigensolvers of both cores: a loose one
+    rotates fewer pairs and still meets the mixed-precision gates. One below FP32 rounding
+    leaves the mixed form's FP32 block Jacobi at FP32 epsilon (a threshold it can reach)
+    instead of running it into its sweep cap."""
+    prob = make_problem("c1")
+    ores = run_oracle(prob, 0.3)
+    gates = dict(sigma_rtol=MIXED_SIGMA_RTOL, product_rtol=1e-4, recon_atol=MIXED_RECON_ATOL, orth_atol=1e-5)
+    say("tolerance option c1: default")
+    h0, _, _, _, _ = run_gpu(fp, torch, prob, 0.3)
+    rot0 = h0.last_rotations()
+    say("tolerance option c1: tol 1e-6")
+    h1, _, U, S, V = run_gpu(fp, torch, prob, 0.3, handle=fp.Handle(0, tol=1e-6))
+    rot1 = h1.last_rotations()
+    say(f"  rotated pairs: default {rot0}, tol 1e-6 {rot1}")
+    assert sum(rot1) < sum(rot0)
+    ok, info = compare_svd(prob, to_np(U), to_np(S), to_np(V), ores, **gates)
+    assert ok, info
+    say("tolerance option c1: mixed, tol 1e-11")
+    h2, _, U, S, V = run_gpu(fp, torch, prob, 0.3, precision="mixed",
+                             handle=fp.Handle(0, precision="mixed", tol=1e-11))
+    assert h2.last_sweeps()[0] < 60
+    ok, info = compare_svd(prob, to_np(U), to_np(S), to_np(V), ores, **gates)
+    assert ok, info
