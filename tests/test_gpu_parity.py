@@ -78,6 +78,27 @@ def test_syev_top_matches_dense_eigensolver(fp, torch, q, t, rank):
     assert np.max(np.abs(vecs.T @ vecs - np.eye(t))) <= 1e-10
 
 
+@pytest.mark.parametrize("e2", [500, -300, -500])
+def test_syev_top_is_scale_invariant(fp, torch, e2):
+    """The eigenpairs of 2^e2 G are 2^e2 times those of G. At 2^500 and 2^-500 the pair
+    solves' d^2 + 4 h^2 leaves the normal range and their rotations take the tangent form."""
+    q, t = 130, 60
+    say(f"syev_top q={q} t={t} scale 2^{e2}")
+    rng = np.random.default_rng(5)
+    X = rng.lognormal(size=(q + 20, q)) * (rng.random((q + 20, q)) < 0.3)
+    G = X.T @ X
+    c = 2.0 ** e2
+    h = fp.Handle(0)
+    vals, vecs = h.syev_top(torch.from_numpy(G * c).cuda(), t)
+    torch.cuda.synchronize()
+    vals, vecs = to_np(vals) / c, to_np(vecs)
+    w = np.linalg.eigvalsh(G)[::-1]
+    assert np.max(np.abs(vals - w[:t])) <= 1e-12 * w[0] * 1.3
+    res = G @ vecs - vecs * vals[None, :]
+    assert np.max(np.abs(res)) <= 1e-10 * w[0]
+    assert np.max(np.abs(vecs.T @ vecs - np.eye(t))) <= 1e-10
+
+
 # ------------------------------------------------------------------ whole path ----------
 SMALL = [
     ("small-a1", small_config(300, 80, 0.05, alpha=1.0, seed=7, k=0.05, L=6), 1.0),
