@@ -9,7 +9,9 @@
 // diagonalises G^2 and hence the positive semidefinite G, so X = V Lambda: the eigenvalues
 // are the column norms of X and the eigenvectors its normalised columns (V is never formed).
 // A pair whose columns are already orthogonal to `tol` (cosine) is left alone; a problem is
-// done after a sweep with no rotated pair.
+// done after a sweep with no rotated pair. Before every sweep the columns of X are reordered
+// by descending norm (de Rijk's ordering), which saves sweeps; X X^T, and so the result, does
+// not depend on the order.
 //
 // Several independent problems ("jobs") advance together: each round is three launches
 // (partial Grams, pair solves, column updates) whose workgroups are spread over the jobs
@@ -54,7 +56,8 @@ __global__ void k_eig_init(const EigJob* __restrict__ jobs) {
 
 // eigenvalue estimates: column norms of X (non-finite values sort last so the order stays
 // a permutation)
-__global__ void k_eig_norms(const EigJob* __restrict__ jobs) {
+__global__ void k_eig_norms(const EigJob* __restrict__ jobs, const int* __restrict__ state) {
+    if (state && state[ST_WORDS * blockIdx.y + ST_DONE]) return;
     const EigJob& J = jobs[blockIdx.y];
     const int lane = threadIdx.x % kWave;
     const int64_t c = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
@@ -89,6 +92,77 @@ __global__ __launch_bounds__(256) void k_eig_floor(const EigJob* __restrict__ jo
         const double mx2 = J.squared ? red[0] : red[0] * red[0];   // largest squared column norm
         J.lam[J.ld] = isfinite(red[0]) ? e * e * static_cast<double>(J.ld) * mx2 : 0.0;
     }
+}
+
+// Column order of the next sweep: the columns by descending norm (J.lam, from k_eig_norms;
+// ties by index, so the order is deterministic), one workgroup per job, bitonic sort in LDS.
+// Jobs above kSortMax columns (no reordering scratch) keep their order.
+constexpr int kSortMax = 4096;
+__global__ __launch_bounds__(1024) void k_eig_sort_cols(const EigJob* __restrict__ jobs,
+                                                        const int* __restrict__ state) {
+    __shared__ double key[kSortMax];
+    __shared__ int idx[kSortMax];
+    const int j = blockIdx.x;
+    if (state[ST_WORDS * j + ST_DONE]) return;
+    const EigJob& J = jobs[j];
+    const int ld = static_cast<int>(J.ld);
+    if (!J.Xs) return;
+    int n = 1;
+    while (n < ld) n <<= 1;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        key[i] = i < ld ? J.lam[i] : -DBL_MAX;
+        idx[i] = i;
+    }
+    __syncthreads();
+    // (key descending, index ascending): element a goes before b
+    auto before = [](double ka, int ia, double kb, int ib) { return ka > kb || (ka == kb && ia < ib); };
+    for (int size = 2; size <= n; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < n / 2; i += blockDim.x) {
+                const int lo = 2 * i - (i & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const double klo = key[lo], khi = key[hi];
+                const int ilo = idx[lo], ihi = idx[hi];
+                if (before(khi, ihi, klo, ilo) == up) {
+                    key[lo] = khi;
+                    key[hi] = klo;
+                    idx[lo] = ihi;
+                    idx[hi] = ilo;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < ld; i += blockDim.x) J.perm[i] = idx[i];
+}
+
+// Xs[:, i] = X[:, perm[i]] (one wave per column), then (second launch) X = Xs.
+__global__ __launch_bounds__(256) void k_eig_gather_cols(const EigJob* __restrict__ jobs,
+                                                         const int* __restrict__ state) {
+    const int j = blockIdx.y;
+    if (state[ST_WORDS * j + ST_DONE]) return;
+    const EigJob& J = jobs[j];
+    if (!J.Xs) return;
+    const int64_t ld = J.ld;
+    const int lane = threadIdx.x % kWave;
+    for (int64_t c = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave; c < ld;
+         c += static_cast<int64_t>(gridDim.x) * (blockDim.x / kWave)) {
+        const double* src = J.X + static_cast<int64_t>(J.perm[c]) * ld;
+        double* dst = J.Xs + c * ld;
+        for (int64_t r = lane; r < ld; r += kWave) dst[r] = src[r];
+    }
+}
+__global__ __launch_bounds__(256) void k_eig_copy_back(const EigJob* __restrict__ jobs,
+                                                       const int* __restrict__ state) {
+    const int j = blockIdx.y;
+    if (state[ST_WORDS * j + ST_DONE]) return;
+    const EigJob& J = jobs[j];
+    if (!J.Xs) return;
+    const int64_t n = J.ld * J.ld;
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+         e += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        J.X[e] = J.Xs[e];
 }
 
 // Partial Gram of one pair over one row chunk of X. Wave w accumulates the 32 x 32 product
@@ -528,13 +602,13 @@ size_t eig_job_doubles(int64_t q, int gram_rows) {
     int nblk, nbe, npairs, nchunk, nupd;
     job_shape(q, gram_rows, ld, nblk, nbe, npairs, nchunk, nupd);
     return static_cast<size_t>(ld * ld + static_cast<int64_t>(npairs) * nchunk * PW * PW +
-                               static_cast<int64_t>(npairs) * PW * PW + ld + 32);
+                               static_cast<int64_t>(npairs) * PW * PW + ld + 32 + (ld <= kSortMax ? ld * ld : 0));
 }
 
 size_t eig_job_ints(int64_t q) {
     const int64_t ld = eig_padded_order(q);
     const int64_t npairs = (ld / BW + 1) / 2;
-    return static_cast<size_t>(npairs + ld + 32);
+    return static_cast<size_t>(npairs + 2 * ld + 32);
 }
 
 EigJob eig_make_job(const double* G, double* A, int64_t q, int64_t t, double* vals, double* vecs,
@@ -551,8 +625,10 @@ EigJob eig_make_job(const double* G, double* A, int64_t q, int64_t t, double* va
     J.Hpart = J.X + J.ld * J.ld;
     J.W = J.Hpart + static_cast<int64_t>(J.npairs) * J.nchunk * PW * PW;
     J.lam = J.W + static_cast<int64_t>(J.npairs) * PW * PW;
+    J.Xs = J.ld <= kSortMax ? J.lam + J.ld + 32 : nullptr;
     J.flag = iws;
     J.order = iws + J.npairs;
+    J.perm = J.order + J.ld;
     J.status = status;
     J.tol = tol > 0 ? tol : static_cast<double>(J.ld) * DBL_EPSILON;
     J.tag = tag;
@@ -632,7 +708,7 @@ void eig_begin(const EigSet& es, hipStream_t st) {
         hipLaunchKernelGGL(k_eig_init, dim3(gx, nj), dim3(256), 0, st, es.jobs);
     }
     hipLaunchKernelGGL(k_eig_norms, dim3(static_cast<unsigned>((es.max_ld + 3) / 4), nj), dim3(256), 0, st,
-                       es.jobs);
+                       es.jobs, nullptr);
     hipLaunchKernelGGL(k_eig_floor, dim3(nj), dim3(256), 0, st, es.jobs);
 }
 
@@ -642,6 +718,14 @@ void eig_sweep(const EigSet& es, int max_sweeps, int inner_sweeps, hipStream_t s
     const int* pg = es.pre;
     const int* ps = es.pre + (nj + 1);
     const int* pu = es.pre + 2 * (nj + 1);
+    // the running jobs' column maps by their current norms
+    hipLaunchKernelGGL(k_eig_norms, dim3(static_cast<unsigned>((es.max_ld + 3) / 4), nj), dim3(256), 0, st,
+                       es.jobs, es.state);
+    hipLaunchKernelGGL(k_eig_sort_cols, dim3(nj), dim3(1024), 0, st, es.jobs, es.state);
+    const unsigned gc = static_cast<unsigned>(std::min<int64_t>((es.max_ld + 3) / 4, 1024));
+    hipLaunchKernelGGL(k_eig_gather_cols, dim3(gc, nj), dim3(256), 0, st, es.jobs, es.state);
+    const unsigned gx = static_cast<unsigned>(std::min<int64_t>((es.max_ld * es.max_ld + 255) / 256, 2048));
+    hipLaunchKernelGGL(k_eig_copy_back, dim3(gx, nj), dim3(256), 0, st, es.jobs, es.state);
     for (int t = 0; t < es.rounds; ++t) {
         const int na = es.nact[t];
         switch (es.gram_rows) {
@@ -671,7 +755,7 @@ void eig_end(const EigSet& es, hipStream_t st) {
     int64_t max_qt = 0;
     for (const EigJob& J : es.host) max_qt = std::max(max_qt, J.q * J.t);
     hipLaunchKernelGGL(k_eig_norms, dim3(static_cast<unsigned>((es.max_ld + 3) / 4), nj), dim3(256), 0, st,
-                       es.jobs);
+                       es.jobs, nullptr);
     hipLaunchKernelGGL(k_eig_select, dim3(nj), dim3(1024), 0, st, es.jobs);
     const unsigned gx = static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>((max_qt + 255) / 256, 4096)));
     hipLaunchKernelGGL(k_eig_output, dim3(gx, nj), dim3(256), 0, st, es.jobs);

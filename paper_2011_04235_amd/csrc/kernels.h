@@ -111,11 +111,13 @@ struct EigJob {
     double* vals;       // t eigenvalues, descending
     double* vecs;       // q x t row-major eigenvectors
     double* X;          // ld x ld column-major iterate
+    double* Xs;         // ld x ld scratch of the column reordering, or null (order above 4096)
     double* Hpart;      // npairs * nchunk partial 32 x 32 Grams
     double* W;          // npairs 32 x 32 rotations
     double* lam;        // ld column norms, then the noise floor
     int* flag;          // npairs: pair rotated in this round
     int* order;         // t: columns of the t largest norms
+    int* perm;          // ld: the columns of X by descending norm (column order of the next sweep)
     int* status;        // status word of the owner (bit 1 when the sweep cap is hit), or null
     double tol;         // cosine threshold of the outer pairs
     int64_t q, t, ld;
