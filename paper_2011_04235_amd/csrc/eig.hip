@@ -95,36 +95,26 @@ __global__ __launch_bounds__(256) void k_eig_floor(const EigJob* __restrict__ jo
 }
 
 // Column order of the next sweep: the columns by descending norm (J.lam, from k_eig_norms;
-// ties by index, so the order is deterministic), one workgroup per job, bitonic sort in LDS.
-// Jobs above kSortMax columns (no reordering scratch) keep their order.
-constexpr int kSortMax = 4096;
-__global__ __launch_bounds__(1024) void k_eig_sort_cols(const EigJob* __restrict__ jobs,
-                                                        const int* __restrict__ state) {
-    __shared__ double key[kSortMax];
-    __shared__ int idx[kSortMax];
-    const int j = blockIdx.x;
-    if (state[ST_WORDS * j + ST_DONE]) return;
-    const EigJob& J = jobs[j];
-    const int ld = static_cast<int>(J.ld);
-    if (!J.Xs) return;
-    int n = 1;
-    while (n < ld) n <<= 1;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        key[i] = i < ld ? J.lam[i] : -DBL_MAX;
-        idx[i] = i;
-    }
-    __syncthreads();
-    // (key descending, index ascending): element a goes before b
-    auto before = [](double ka, int ia, double kb, int ib) { return ka > kb || (ka == kb && ia < ib); };
+// ties by index, so the order is deterministic), one workgroup per job, bitonic sort in LDS:
+// FP64 keys up to order kSortExact, FP32 keys (the order of norms equal to FP32 rounding
+// falls back to the index) up to kSortMax. The key type depends on the job's own order
+// only, so a matrix is ordered alike alone and in a batch. Jobs above kSortMax columns (no
+// reordering scratch) keep their order.
+constexpr int kSortExact = 4096;
+constexpr int kSortMax = 16384;
+template <typename K>
+__device__ void bitonic_desc(K* key, int* idx, int n) {
     for (int size = 2; size <= n; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             for (int i = threadIdx.x; i < n / 2; i += blockDim.x) {
                 const int lo = 2 * i - (i & (stride - 1));
                 const int hi = lo + stride;
                 const bool up = (lo & size) == 0;
-                const double klo = key[lo], khi = key[hi];
+                const K klo = key[lo], khi = key[hi];
                 const int ilo = idx[lo], ihi = idx[hi];
-                if (before(khi, ihi, klo, ilo) == up) {
+                // (key descending, index ascending): hi goes before lo
+                const bool hi_first = khi > klo || (khi == klo && ihi < ilo);
+                if (hi_first == up) {
                     key[lo] = khi;
                     key[hi] = klo;
                     idx[lo] = ihi;
@@ -133,6 +123,41 @@ __global__ __launch_bounds__(1024) void k_eig_sort_cols(const EigJob* __restrict
             }
             __syncthreads();
         }
+    }
+}
+__global__ __launch_bounds__(1024) void k_eig_sort_cols(const EigJob* __restrict__ jobs,
+                                                        const int* __restrict__ state) {
+    constexpr int EXACT_BYTES = kSortExact * (sizeof(double) + sizeof(int));
+    constexpr int WIDE_BYTES = kSortMax * (sizeof(float) + sizeof(int));
+    __shared__ __align__(16) unsigned char sm[EXACT_BYTES > WIDE_BYTES ? EXACT_BYTES : WIDE_BYTES];
+    const int j = blockIdx.x;
+    if (state[ST_WORDS * j + ST_DONE]) return;
+    const EigJob& J = jobs[j];
+    const int ld = static_cast<int>(J.ld);
+    if (!J.Xs) return;
+    int n = 1;
+    while (n < ld) n <<= 1;
+    int* idx;
+    if (ld <= kSortExact) {
+        double* key = reinterpret_cast<double*>(sm);
+        idx = reinterpret_cast<int*>(sm + kSortExact * sizeof(double));
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            key[i] = i < ld ? J.lam[i] : -DBL_MAX;
+            idx[i] = i;
+        }
+        __syncthreads();
+        bitonic_desc(key, idx, n);
+    } else {
+        float* key = reinterpret_cast<float*>(sm);
+        idx = reinterpret_cast<int*>(sm + kSortMax * sizeof(float));
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            // FP32 of the norm, saturated (a norm above FLT_MAX keeps its place among the largest)
+            key[i] = i < ld ? static_cast<float>(fmax(fmin(J.lam[i], static_cast<double>(FLT_MAX)), -static_cast<double>(FLT_MAX)))
+                            : -FLT_MAX;
+            idx[i] = i;
+        }
+        __syncthreads();
+        bitonic_desc(key, idx, n);
     }
     for (int i = threadIdx.x; i < ld; i += blockDim.x) J.perm[i] = idx[i];
 }
