@@ -378,8 +378,12 @@ static int build_sets(Group& g, hipStream_t st) {
     rc = eig_set_create(g.set1, j1, g.tune.gram_rows, g.tune.precond != 0, st);
     if (rc == FASTPI_OK) rc = eig_set_create(g.set2, j2, g.tune.gram_rows, g.tune.precond != 0, st);
     if (rc == FASTPI_OK) rc = eig_set_create(g.set3, j3, g.tune.gram_rows, g.tune.precond != 0, st);
+    // the randomized solver's basis Grams are numerically rank-deficient and its
+    // orthonormalization divides by the square roots of their eigenvalues down to k eps of the
+    // largest: those need relative accuracy, which the pivoted-Cholesky start gives (from G
+    // itself they carry absolute errors of ~ld eps of the largest), whatever the schedule
     for (int c = 0; c < 2 && rc == FASTPI_OK; ++c)
-        rc = eig_set_create(g.rset[c], jr[c], g.tune.gram_rows, g.tune.precond != 0, st);
+        rc = eig_set_create(g.rset[c], jr[c], g.tune.gram_rows, true, st);
     if (rc != FASTPI_OK) set_error("eigensolver set allocation failed");
     return rc;
 }
