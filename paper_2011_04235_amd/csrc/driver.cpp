@@ -375,7 +375,10 @@ static int build_sets(Group& g, hipStream_t st) {
     }
     if (rc != FASTPI_OK) return rc;
     // the cores are rebuilt by every run, so the factorisation may overwrite them
-    rc = eig_set_create(g.set1, j1, g.tune.gram_rows, g.tune.precond != 0, st);
+    // the Gram route of large blocks takes sigma = sqrt(lambda) down to 1e-7 of the largest and
+    // divides by it, so its eigensolves start from the pivoted-Cholesky factor (relative
+    // accuracy) whatever the schedule
+    rc = eig_set_create(g.set1, j1, g.tune.gram_rows, true, st);
     if (rc == FASTPI_OK) rc = eig_set_create(g.set2, j2, g.tune.gram_rows, g.tune.precond != 0, st);
     if (rc == FASTPI_OK) rc = eig_set_create(g.set3, j3, g.tune.gram_rows, g.tune.precond != 0, st);
     // the randomized solver's basis Grams are numerically rank-deficient and its

@@ -170,6 +170,7 @@ SCHEDULES = [
     dict(block_lds=16384, block_wgs_per_cu=8, gram_rows=64, inner_sweeps=2),
     dict(block_lds=57344, block_wgs_per_cu=2, gram_rows=256, inner_sweeps=1),
     dict(block_lds=4096, block_wgs_per_cu=1, gram_rows=128, inner_sweeps=1),
+    dict(block_lds=32768, block_wgs_per_cu=4, gram_rows=128, inner_sweeps=1, precond=0),
 ]
 
 
