@@ -188,6 +188,37 @@ def test_nonfinite_value_is_reported(fp, torch):
     assert ei.value.status == "ENONFINITE"
 
 
+def test_c2_benchmark_form_parity(fp, torch):
+    """The benchmark line's form at its full size: 20000 x 2000, alpha 0.2, mixed precision,
+    the autotuned schedule and the stages replayed from graphs, against the oracle under the
+    mixed-precision gates, on two replays, each bitwise equal to an eager run."""
+    prob = make_problem("c2")
+    say(f"benchmark form c2 m={prob.m} n={prob.n}: mixed, autotuned, graph replay")
+    plan = fp.Plan(prob.m, prob.n, prob.indptr, prob.indices, prob.data, alpha=0.2, k=prob.cfg.k)
+    h = fp.Handle(0, precision="mixed")
+    h.upload_plan(plan)
+    dev = torch.device("cuda", 0)
+    args = [torch.from_numpy(x).to(dev) for x in (prob.indptr, prob.indices, prob.data)]
+    U = torch.empty((plan.m, plan.r), dtype=torch.float64, device=dev)
+    S = torch.empty((plan.r,), dtype=torch.float64, device=dev)
+    V = torch.empty((plan.n, plan.r), dtype=torch.float64, device=dev)
+    say(f"  {h.autotune(*args, out=(U, S, V)).split('chose')[-1].strip()}")
+    h.svd(*args, out=(U, S, V))
+    h.sync()
+    eager = (to_np(U), to_np(S), to_np(V))
+    ores = run_oracle(prob, 0.2)
+    h.set_graph(True)
+    for rep in range(2):
+        h.svd(*args, out=(U, S, V))
+        h.sync()
+        got = (to_np(U), to_np(S), to_np(V))
+        assert all(np.array_equal(x, y) for x, y in zip(got, eager)), rep
+        ok, info = compare_svd(prob, *got, ores, sigma_rtol=MIXED_SIGMA_RTOL, product_rtol=1e-4,
+                               recon_atol=MIXED_RECON_ATOL, orth_atol=1e-5)
+        say(f"  replay {rep}: {info}")
+        assert ok, info
+
+
 # ------------------------------------------------------------------ mixed precision -----
 MIXED = [
     ("c1", "c1", 0.3),
