@@ -54,8 +54,9 @@ __global__ void k_eig_init(const EigJob* __restrict__ jobs) {
     }
 }
 
-// eigenvalue estimates: column norms of X (non-finite values sort last so the order stays
-// a permutation)
+// Column norms of X: the eigenvalue estimates at the end, and the keys of the column order
+// before every sweep (then with the state: finished jobs are skipped). Non-finite values
+// sort last so the order stays a permutation.
 __global__ void k_eig_norms(const EigJob* __restrict__ jobs, const int* __restrict__ state) {
     if (state && state[ST_WORDS * blockIdx.y + ST_DONE]) return;
     const EigJob& J = jobs[blockIdx.y];
@@ -345,10 +346,11 @@ __device__ __forceinline__ int slot(int i, int j) { return i * LS + ((j & 1) ? 1
 // One workgroup of 256 threads per pair. Thread (a, b) keeps the 2x2 blocks
 // H[2a:2a+2][2b:2b+2] and W[2a:2a+2][2b:2b+2] in registers (H indexed by slots on both
 // sides, W by input column and slot), with a copy of H in LDS. In a step every thread
-// computes the rotations of its slot pairs a and b from the diagonal blocks in LDS (so all
-// threads use bitwise the same rotations), applies J_a^T (.) J_b to its H block and (.) J_b
-// to its W block in registers, and scatters the blocks to their next slots through the
-// other LDS buffer: one barrier per step.
+// computes the rotation of its column slot pair b from the diagonal block in LDS and takes
+// that of its row slot pair a from lane a of its wave by a shuffle (so all threads use
+// bitwise the same rotations), applies J_a^T (.) J_b to its H block and (.) J_b to its W
+// block in registers, and scatters the blocks to their next slots through the other LDS
+// buffer: one barrier per step.
 __global__ __launch_bounds__(256) void k_eig_solve(const EigJob* __restrict__ jobs,
                                                    const int* __restrict__ pre, int nact,
                                                    int* __restrict__ state, int inner_sweeps) {
