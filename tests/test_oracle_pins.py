@@ -385,3 +385,125 @@ def test_planted_mistakes_are_caught(monkeypatch):
     monkeypatch.setattr(ofp, "column_update", col_transposed)
     bad = ofp.fastpi_svd(p.m, p.n, p.indptr, p.indices, p.data, 1.0, 0.05)
     assert not exact(bad)
+
+
+# ------------------------------------- the two metric functions every parity test uses -----
+# ls_residual is Application 1's least-squares objective ||A Z - Y||_F / ||Y||_F, and
+# orthonormality_error is max |Q^T Q - I| over the columns kept by the pseudoinverse
+# threshold (the orthonormality claims after Eqs. 1-3 hold for those). Both are pinned to
+# hand-computed values, and a planted slip in either must break its pin.
+
+def _ls_pin(fn):
+    """Integer A, Z, Y with the residual worked out by hand:
+    A Z = [[1, 2], [0, 3], [4, 0]], Y = [[1, 2], [0, 5], [3, 0]], so A Z - Y has the
+    entries 0, 0, 0, -2, 1, 0: ||A Z - Y||_F = sqrt(5), ||Y||_F = sqrt(1+4+25+9) = sqrt(39)."""
+    A = sp.csr_matrix(np.array([[1.0, 2.0], [0.0, 3.0], [4.0, 0.0]]))
+    Z = np.array([[1.0, 0.0], [0.0, 1.0]])
+    Y = np.array([[1.0, 2.0], [0.0, 5.0], [3.0, 0.0]])
+    ok = abs(fn(A, Z, Y) - math.sqrt(5.0 / 39.0)) <= 1e-15
+    # a non-square Z: A (3x2) Z (2x3) with Z = [[1, 0, 2], [0, 1, -1]]:
+    # A Z = [[1, 2, 0], [0, 3, -3], [4, 0, 8]]; Y2 = A Z + E with E = [[0, 0, 1], [0, -2, 0],
+    # [0, 0, 0]] gives ||A Z - Y2||_F = sqrt(5) and ||Y2||_F^2 = 1+4+1+0+1+9+16+0+64 = 96
+    Z2 = np.array([[1.0, 0.0, 2.0], [0.0, 1.0, -1.0]])
+    Y2 = np.array([[1.0, 2.0, 1.0], [0.0, 1.0, -3.0], [4.0, 0.0, 8.0]])
+    ok &= abs(fn(A, Z2, Y2) - math.sqrt(5.0 / 96.0)) <= 1e-15
+    # at the least-squares solution the residual is Y minus its projection on range(A):
+    # ||R||^2 = ||Y||^2 - ||Q^T Y||^2 with Q from a QR of A (another routine than the
+    # product the function forms)
+    rng = np.random.default_rng(7)
+    Ad = rng.standard_normal((30, 6))
+    Yd = rng.standard_normal((30, 4))
+    Zd = sla.lstsq(Ad, Yd)[0]
+    Q, _ = sla.qr(Ad, mode="economic")
+    want = math.sqrt(max(np.sum(Yd ** 2) - np.sum((Q.T @ Yd) ** 2), 0.0) / np.sum(Yd ** 2))
+    ok &= abs(fn(sp.csr_matrix(Ad), Zd, Yd) - want) <= 1e-13
+    return bool(ok)
+
+
+def test_ls_residual_pinned():
+    assert _ls_pin(oracle.ls_residual)
+    # Y = 0: the unnormalised residual norm (documented), here ||A Z||_F = sqrt(1+4+9+16)
+    A = sp.csr_matrix(np.array([[1.0, 2.0], [0.0, 3.0], [4.0, 0.0]]))
+    assert abs(oracle.ls_residual(A, np.eye(2), np.zeros((3, 2))) - math.sqrt(30.0)) <= 1e-15
+
+
+def test_ls_residual_planted_slips_fail_the_pin():
+    def by_square_norm(A, Z, Y):            # normalised by ||Y||^2 instead of ||Y||
+        R = sp.csr_matrix(A) @ Z - Y
+        return float(np.linalg.norm(R)) / float(np.sum(Y ** 2))
+
+    def plus_y(A, Z, Y):                     # A Z + Y instead of A Z - Y
+        R = sp.csr_matrix(A) @ Z + Y
+        return float(np.linalg.norm(R)) / float(np.linalg.norm(Y))
+
+    def max_norm(A, Z, Y):                   # largest entry instead of the Frobenius norm
+        R = sp.csr_matrix(A) @ Z - Y
+        return float(np.abs(R).max()) / float(np.linalg.norm(Y))
+
+    for slip in (by_square_norm, plus_y, max_norm):
+        assert not _ls_pin(slip), slip.__name__
+
+
+def _orth_pin(fn):
+    """A planted Q (6 x 4) with known defects:
+    q1 = e1; q2 = (1 + eta) e2 (norm defect (1+eta)^2 - 1); q3 = e3 + delta e1 (off-diagonal
+    defect delta < 0, norm defect delta^2); q4 = 5 e4 (defect 24) carried by a singular value
+    that the pseudoinverse threshold max(m, n) eps sigma_1 drops or keeps."""
+    eta, delta = 1e-3, -3e-3
+    Q = np.zeros((6, 4))
+    Q[0, 0] = 1.0
+    Q[1, 1] = 1.0 + eta
+    Q[2, 2] = 1.0
+    Q[0, 2] = delta
+    Q[3, 3] = 5.0
+    eps = np.finfo(np.float64).eps
+    m, n = 6, 1000                    # threshold 1000 eps sigma_1, set by n (not by Q's rows)
+    want_kept3 = max((1 + eta) ** 2 - 1, abs(delta), delta ** 2)      # = 3e-3 (the |delta|)
+    ok = True
+    # sigma_4 under the threshold: column 4 is left out
+    s_drop = np.array([1.0, 0.5, 0.2, 500 * eps])
+    ok &= abs(fn(Q, s_drop, m, n) - want_kept3) <= 1e-15
+    # sigma_4 just above it: column 4 counts, its defect 24 dominates
+    s_keep = np.array([1.0, 0.5, 0.2, 1001 * eps])
+    ok &= abs(fn(Q, s_keep, m, n) - 24.0) <= 1e-12
+    # no sigma: every column counts
+    ok &= abs(fn(Q) - 24.0) <= 1e-12
+    # an exactly orthonormal Q (a Householder reflector's columns) reads ~0
+    v = np.arange(1.0, 7.0)[:, None]
+    H = np.eye(6) - 2.0 * (v @ v.T) / float(np.sum(v * v))
+    ok &= fn(H[:, :4]) <= 4 * eps
+    return bool(ok)
+
+
+def test_orthonormality_error_pinned():
+    assert _orth_pin(oracle.orthonormality_error)
+    assert oracle.orthonormality_error(np.zeros((5, 0))) == 0.0
+
+
+def test_orthonormality_error_planted_slips_fail_the_pin():
+    def signed_max(Q, sigma=None, m=None, n=None):        # missing abs
+        if sigma is not None:
+            Q = Q[:, oracle.sigma_pinv(sigma, m or Q.shape[0], n or Q.shape[0]) > 0]
+        return float(np.max(Q.T @ Q - np.eye(Q.shape[1])))
+
+    def rows_as_n(Q, sigma=None, m=None, n=None):         # threshold from Q's rows, not n
+        if sigma is not None:
+            Q = Q[:, oracle.sigma_pinv(sigma, Q.shape[0], Q.shape[0]) > 0]
+        return float(np.max(np.abs(Q.T @ Q - np.eye(Q.shape[1]))))
+
+    def no_filter(Q, sigma=None, m=None, n=None):         # sigma ignored
+        return float(np.max(np.abs(Q.T @ Q - np.eye(Q.shape[1]))))
+
+    def positive_filter(Q, sigma=None, m=None, n=None):   # keeps every sigma > 0
+        if sigma is not None:
+            Q = Q[:, np.asarray(sigma) > 0]
+        return float(np.max(np.abs(Q.T @ Q - np.eye(Q.shape[1]))))
+
+    def offdiag_only(Q, sigma=None, m=None, n=None):      # norm defects missed
+        if sigma is not None:
+            Q = Q[:, oracle.sigma_pinv(sigma, m, n) > 0]
+        G = Q.T @ Q
+        return float(np.max(np.abs(G - np.diag(np.diag(G)))))
+
+    for slip in (signed_max, rows_as_n, no_filter, positive_filter, offdiag_only):
+        assert not _orth_pin(slip), slip.__name__
