@@ -2,13 +2,13 @@
 
 One step = the whole device path on resident inputs: value split (a1), block SVDs (a2),
 row update (a3), column update (a4), unpermute (a5) and the pseudoinverse apply
-Z = V Sigma^+ U^T Y (a6), for the workload 20000 x 2000 (0.5% dense, power-law 2.0,
-lognormal values, 200 Bernoulli(0.02) labels, alpha 0.2) unless --config says otherwise.
+Z = V Sigma^+ U^T Y (a6), for the workload 100000 x 5000 (0.2% dense, power-law 1.9,
+lognormal values, 1000 Bernoulli(0.005) labels, alpha 0.1) unless --config says otherwise.
 The host reordering and planning run once before the timed region (their time is
 reported separately as plan_s).
 
 Prints one JSON line. `value` is the algorithmic throughput F_model / T_step in TFLOP/s,
-where F_model is the flop count of the exact method (see flop_model()).
+where F_model is the flop count of the method's Brand-form update terms (see flop_model()).
 """
 from __future__ import annotations
 
@@ -32,24 +32,69 @@ def progress(msg):
 
 
 def svd_thin_flops(p, q):
-    """Golub & Van Loan R-SVD count for a p x q (p >= q) thin SVD with U and V."""
+    """Golub & Van Loan R-SVD count for a thin SVD of a p x q matrix with both factors:
+    6 P Q^2 + 20 Q^3 with P = max(p, q), Q = min(p, q)."""
     p, q = max(p, q), min(p, q)
+    if q <= 0:
+        return 0.0
     return 6.0 * p * q * q + 20.0 * q ** 3
 
 
-def flop_model(plan, blocks, ranks, L):
-    """Algorithmic flops of one step (precision-independent):
-    a2: a thin SVD of every dense diagonal block;
-    a3: the thin SVD of M2 ((s_b + m2) x n1) plus the block products U1 Ut_top;
-    a4: the thin SVD of X3 (m x (s + n2)) plus V2 Vt_top;
-    a6: U^T Y and V (Sigma^+ W)."""
+def qr_thin_flops(p, q):
+    """Householder QR of a p x q matrix with k = min(p, q) reflectors (R: 4pqk - 2(p+q)k^2
+    + 4k^3/3, i.e. 2pq^2 - 2q^3/3 when p >= q), doubled for the thin Q."""
+    k = min(p, q)
+    if k <= 0:
+        return 0.0
+    return 2.0 * (4.0 * p * q * k - 2.0 * (p + q) * k * k + 4.0 * k ** 3 / 3.0)
+
+
+def border_counts(plan, indptr, indices):
+    """nnz(A21), nnz(T) and the sum over A21's entries of the rank of the diagonal block its
+    column belongs to (the cost of P2 = V1^T A21^T), from the host CSR and the plan's
+    permutation and block table."""
     i = plan.info
-    f2 = sum(svd_thin_flops(r, c) for (_, _, r, c) in blocks if r > 0 and c > 0)
-    mis = sum(int(r) * int(s) for (_, _, r, _), s in zip(blocks, ranks))
-    f3 = svd_thin_flops(i["s_b"] + i["m2"], i["n1"]) + 2.0 * mis * i["s"] if i["n1"] else 0.0
-    f4 = svd_thin_flops(i["m"], i["s"] + i["n2"]) + 2.0 * i["n1"] * i["s"] * i["r"]
-    f6 = 2.0 * i["m"] * i["r"] * L + 2.0 * i["n"] * i["r"] * L
-    return {"a2": f2, "a3": f3, "a4": f4, "a6": f6, "total": f2 + f3 + f4 + f6}
+    piT, piF = plan.permutation()
+    rows = np.repeat(np.arange(i["m"]), np.diff(indptr))
+    r_new = piT[rows]
+    c_new = piF[np.asarray(indices)]
+    in_t = c_new >= i["n1"]
+    in_a21 = (r_new >= i["m1"]) & ~in_t
+    blocks, ranks = plan.blocks(), plan.block_ranks()
+    col_rank = np.zeros(max(i["n1"], 1), dtype=np.int64)
+    for (_, c0, _, ni), s in zip(blocks, ranks):
+        col_rank[c0:c0 + ni] = s
+    return int(in_a21.sum()), int(in_t.sum()), float(col_rank[c_new[in_a21]].sum())
+
+
+def flop_model(plan, blocks, ranks, L, indptr, indices):
+    """Algorithmic flops of one step (precision-independent), the Brand-form terms of the
+    incremental updates. rho2 = min(n1 - s_b, m2) and rho3 = min(m - s, n2) are the generic
+    ranks of the two residuals (each lies in the complement of s_b or s directions).
+    a2: a thin SVD of every dense diagonal block (Eq. 1);
+    a3 (Eq. 2): P2 = V1^T A21^T, R2 = A21^T - V1 P2, the thin QR of R2, the core SVD of
+        (s_b + rho2) x (s_b + m2), U1 Ut_top and V2 = [V1 Q2] Uhat;
+    a4 (Eq. 3): P3 = U2^T T and R3 = T - U2 P3 twice (a second Gram-Schmidt pass), the thin QR
+        of R3, the core SVD of (s + rho3) x (s + n2), U = [U2 Q3] Uhat and V2 Vt_top;
+    a6: U^T Y, Sigma^+ W and V W."""
+    i = plan.info
+    m, n, m2, n1, n2 = i["m"], i["n"], i["m2"], i["n1"], i["n2"]
+    s_b, s, r = i["s_b"], i["s"], i["r"]
+    nnz21, nnzT, p2_terms = border_counts(plan, indptr, indices)
+    f2 = sum(svd_thin_flops(bm, bn) for (_, _, bm, bn) in blocks if bm > 0 and bn > 0)
+    sum_ms = float(sum(int(bm) * int(sv) for (_, _, bm, _), sv in zip(blocks, ranks)))
+    sum_ns = float(sum(int(bn) * int(sv) for (_, _, _, bn), sv in zip(blocks, ranks)))
+    rho2 = max(0, min(n1 - s_b, m2))
+    rho3 = max(0, min(m - s, n2))
+    f3 = 0.0
+    if n1 > 0:
+        f3 = (2.0 * p2_terms + 2.0 * sum_ns * m2 + qr_thin_flops(n1, m2)
+              + svd_thin_flops(s_b + m2, s_b + rho2) + 2.0 * sum_ms * s + 2.0 * n1 * (s_b + rho2) * s)
+    f4 = (2.0 * (2.0 * nnzT * s + 2.0 * m * s * n2) + qr_thin_flops(m, n2)
+          + svd_thin_flops(s + n2, s + rho3) + 2.0 * m * (s + rho3) * r + 2.0 * n1 * s * r)
+    f6 = 2.0 * m * r * L + r * L + 2.0 * n * r * L
+    return {"a2": f2, "a3": f3, "a4": f4, "a6": f6, "total": f2 + f3 + f4 + f6,
+            "rho2": rho2, "rho3": rho3, "nnz_A21": nnz21, "nnz_T": nnzT}
 
 
 # Per-unit algorithmic work of the eigensolver's pair solve (k_eig_solve): one cyclic Jacobi
@@ -136,28 +181,83 @@ def recon_error(A, U, S, V):
     return math.sqrt(e2 / a2)
 
 
-def cpu_baseline(prob, alpha, F, budget_s):
-    """The oracle as it stands, on the host cores, repeated on the same workload until
-    about budget_s seconds have passed (at least once)."""
-    import oracle
+def cpu_model():
     try:
-        from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    except Exception:  # pragma: no cover
-        cores = os.cpu_count() or 1
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:  # pragma: no cover
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def oracle_stages(prob, alpha, deadline=None):
+    """One run of the oracle, stage by stage (the steps of oracle.fastpi_svd, then the apply),
+    with the wall time of each. With a deadline (perf_counter value) no further stage starts
+    once it has passed; returns (times, completed)."""
+    import oracle
+    from oracle.fastpi import block_svd, column_update, row_update, split_blocks
+    A = sp.csr_matrix((prob.data, prob.indices, prob.indptr), shape=(prob.m, prob.n))
+    A.eliminate_zeros()
+    A.sort_indices()
+    k = prob.cfg.k
+    st = {}
+    times = {}
+
+    steps = [
+        ("a0_reorder", lambda: st.__setitem__("R", oracle.reorder(prob.m, prob.n, A.indptr, A.indices, k))),
+        ("a1_split", lambda: st.__setitem__("S", split_blocks(prob.m, prob.n, A.indptr, A.indices, A.data,
+                                                               st["R"]))),
+        ("a2_blocks", lambda: st.__setitem__("B", block_svd(st["S"], alpha))),
+        ("a3_row_update", lambda: st.__setitem__("R2", row_update(st["S"], st["B"], alpha))),
+        ("a4_column_update", lambda: st.__setitem__("R3", column_update(st["S"], st["R2"], alpha,
+                                                                         prob.m, prob.n))),
+        ("a5_a6_unpermute_apply", lambda: oracle.pinv_apply(
+            st["R3"].U[st["R"].piT.astype(np.int64)], st["R3"].sigma,
+            st["R3"].V[st["R"].piF.astype(np.int64)], prob.Y, prob.m, prob.n)),
+    ]
+    for name, fn in steps:
+        if deadline is not None and time.perf_counter() >= deadline:
+            return times, False
+        t0 = time.perf_counter()
+        fn()
+        times[name] = round(time.perf_counter() - t0, 4)
+    return times, True
+
+
+def cpu_baseline(prob, alpha, F, budget_s, full_single):
+    """The oracle as it stands on the host cores: one whole run with every thread the BLAS
+    library starts (the value, per-stage times), then a single-thread run (the paper times one
+    thread), stage by stage, that stops starting stages once budget_s has passed (all stages
+    with full_single)."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+    blas_threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        avail = os.cpu_count() or 1
     t0 = time.perf_counter()
-    reps = 0
-    while True:
-        res = oracle.fastpi_svd(prob.m, prob.n, prob.indptr, prob.indices, prob.data, alpha,
-                                prob.cfg.k)
-        oracle.pinv_apply(res.U, res.sigma, res.V, prob.Y, prob.m, prob.n)
-        reps += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": F * reps / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{reps} full run(s) of the oracle (reorder, block SVDs, both updates, "
-                      f"apply) on the same workload, {dt:.1f} s; s per run {dt / reps:.3f}"}
+    times_n, _ = oracle_stages(prob, alpha)
+    dt_n = time.perf_counter() - t0
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        times_1, done = oracle_stages(prob, alpha, None if full_single else t0 + budget_s)
+        dt_1 = time.perf_counter() - t0
+    one = {"cores": 1, "stage_s": times_1, "complete": done}
+    if done:
+        one["value"] = F / dt_1 / 1e12
+        one["s_per_run"] = round(dt_1, 3)
+    return {"value": F / dt_n / 1e12, "unit": "TFLOP/s", "cores": int(blas_threads), "kind": "oracle",
+            "cpu_model": cpu_model(), "cpus_available": int(avail), "os_cpu_count": os.cpu_count(),
+            "stage_s": times_n, "s_per_run": round(dt_n, 3),
+            "sample": (f"one whole run of the oracle (reorder, split, block SVDs, both updates, "
+                       f"unpermute and apply) on the same workload with {blas_threads} BLAS threads, "
+                       f"{dt_n:.1f} s; then one thread, stage by stage"
+                       + ("" if done else f", stopped after {len(times_1)} stages at the "
+                                          f"{budget_s:.0f} s budget")),
+            "single_thread": one}
 
 
 def run_batched_workload(args, torch, fp):
@@ -175,7 +275,7 @@ def run_batched_workload(args, torch, fp):
             progress(f"generating matrices {ci_}..{min(ci_ + 8, len(cfgs)) - 1}")
         prob = make_problem(c)
         plan = fp.Plan(prob.m, prob.n, prob.indptr, prob.indices, prob.data, alpha=c.alpha, k=c.k)
-        F.append(flop_model(plan, plan.blocks(), plan.block_ranks(), c.L)["total"])
+        F.append(flop_model(plan, plan.blocks(), plan.block_ranks(), c.L, prob.indptr, prob.indices)["total"])
         dev_in.append((torch.from_numpy(prob.indptr).to(dev), torch.from_numpy(prob.indices).to(dev),
                        torch.from_numpy(prob.data).to(dev), torch.from_numpy(prob.Y).to(dev)))
         probs.append(prob)
@@ -489,10 +589,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--config", default="c3")
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
     ap.add_argument("--form", default="both", choices=["plain", "batched", "both"])
-    ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--cpu-budget", type=float, default=20.0,
+                    help="seconds after which the single-thread oracle run starts no further stage")
+    ap.add_argument("--cpu-full-single", action="store_true",
+                    help="run every stage of the single-thread oracle, whatever its time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--roofline-kernel", default="eig_solve",
                     choices=["eig_solve", "eig_gram", "eig_update", "block_svd"])
@@ -564,7 +667,7 @@ def main():
                       "alpha rule), total s_b of the alpha rule")
     blocks = plan.blocks()
     ranks = plan.block_ranks()
-    F = flop_model(plan, blocks, ranks, cfg.L)
+    F = flop_model(plan, blocks, ranks, cfg.L, prob.indptr, prob.indices)
 
     dev = torch.device("cuda", 0)
     rowptr = torch.from_numpy(prob.indptr).to(dev)
@@ -658,7 +761,7 @@ def main():
     base = None
     if not args.no_cpu_baseline:
         progress("oracle on the host cores")
-        base = cpu_baseline(prob, cfg.alpha, F["total"], args.cpu_budget)
+        base = cpu_baseline(prob, cfg.alpha, F["total"], args.cpu_budget, args.cpu_full_single)
     compare = {p: {"ms_per_step": round(v["ms"], 3), "tflops": round(F["total"] / v["ms"] / 1e9, 4),
                    "recon_error": v["recon"], "sweeps": v["sweeps"], "tuning": v["tuning"],
                    "graph_launches_per_step": v["graph_launches_per_step"],

@@ -29,6 +29,9 @@ extern "C" {
 #endif
 
 typedef enum {
+    FASTPI_WFLOOR = 1,       /* warning, outputs valid: a kept singular value lay at or below  */
+                             /* the Gram route's resolution floor and is returned as 0 (see    */
+                             /* fastpi_svd); reported by fastpi_sync / fastpi_batch_sync only  */
     FASTPI_OK = 0,
     FASTPI_EINVAL = -1,      /* bad argument: null pointer, alpha or k out of range, bad id   */
     FASTPI_ESHAPE = -2,      /* CSR not well formed: rowptr not monotone, column out of range, */
@@ -227,8 +230,16 @@ int fastpi_upload_plan(fastpi_handle* h, const fastpi_plan* plan);
  *                      (int64[m+1], int32[nnz], double[nnz])
  *   U : device double[m * r] row-major;  S : device double[r], descending;
  *   V : device double[n * r] row-major;  r = fastpi_split.r of the plan.
- * Columns whose singular value is at or below max(m, n) * eps * S[0] carry no information
- * and may be zero.
+ * The two updates and the diagonal blocks on the Gram route (blocks with p q^2 above the
+ * route threshold) take their truncated factors from the eigenpairs of an FP64 Gram matrix,
+ * which resolves a singular value only down to about sqrt(q eps) of the largest: every
+ * singular value at or below 1e-7 * (the largest of its stage) is returned as exactly 0 with
+ * its U column zero (and the V column unspecified), and fastpi_apply's S^+ is 0 there. When
+ * that happens to a non-zero matrix, fastpi_sync returns FASTPI_WFLOOR (for an exactly
+ * rank-deficient A this is expected: its zero singular values are at that floor). A with
+ * singular values in (about 1e-12, 1e-7) times the largest therefore does not reach
+ * Problem 1's exact pseudoinverse at alpha = 1; the truncated pseudoinverse it gives drops
+ * those directions. Columns at or below max(m, n) * eps * S[0] carry no information either.
  * The two incremental cores are solved by Jacobi sweeps whose number depends on the data:
  * the host reads each sweep's convergence state (one sweep behind, on a side stream), so
  * the call returns once the last sweep is queued; the final stages are queued, not finished.
@@ -307,8 +318,9 @@ int fastpi_stage_output(fastpi_handle* h, int which, double* dst, int64_t count)
 int fastpi_syev_top(fastpi_handle* h, int64_t q, const double* G, int64_t t, double* vals,
                     double* vecs);
 
-/* Waits for the handle's stream and reports device-side failures (non-finite input,
- * Jacobi sweep cap reached). */
+/* Waits for the handle's stream and reports device-side failures of the last fastpi_svd
+ * (FASTPI_ENONFINITE: non-finite input; FASTPI_ENOCONV: a Jacobi sweep cap reached), or the
+ * warning FASTPI_WFLOOR (a kept singular value under the Gram floor, see fastpi_svd). */
 int fastpi_sync(fastpi_handle* h);
 
 /* Number of sweeps used by the last Jacobi run of each kind on this handle:
@@ -414,7 +426,8 @@ int fastpi_batch_svd(fastpi_batch* b, const double* const* val, double* const* U
  * Waits for the stream. status (host int32[count], may be NULL) receives each matrix's own
  * fastpi_status, so that one failing matrix (e.g. a non-finite value) leaves the others'
  * results and codes intact; sweeps (host int32[3*count], may be NULL) the sweep counts as
- * in fastpi_last_sweeps. Returns the first non-OK code, or FASTPI_OK.
+ * in fastpi_last_sweeps. Returns the first negative (error) code, else FASTPI_WFLOOR if any
+ * matrix has that warning, else FASTPI_OK.
  */
 int fastpi_batch_sync(fastpi_batch* b, int32_t* status, int32_t* sweeps);
 /* fastpi_last_rotations for every matrix of the batch: out[2*i], out[2*i+1] (host int64). */

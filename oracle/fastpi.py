@@ -92,8 +92,14 @@ class BlockStage:
     block_sigma: list      # full singular value list of every dense block
 
 
-def block_svd(S: Split, alpha: float) -> BlockStage:
-    """Eq. 1: truncated SVD of every diagonal block, joined with bdiag."""
+def block_svd(S: Split, alpha: float, block_ranks=None) -> BlockStage:
+    """Eq. 1: truncated SVD of every diagonal block, joined with bdiag. Block i keeps
+    s_i = min(ceil(alpha n_i), m_i, n_i) directions, or min(block_ranks[i], m_i, n_i) when
+    per-block ranks are given (one per entry of the block table, e.g. a learned allocation)."""
+    if block_ranks is not None:
+        block_ranks = np.asarray(block_ranks, dtype=np.int64)
+        if block_ranks.shape != (len(S.blocks),) or np.any(block_ranks < 0):
+            raise ValueError("block_ranks needs one non-negative rank per block")
     ranks = np.zeros(len(S.blocks), dtype=np.int64)
     urows, ucols, uvals = [], [], []
     vrows, vcols, vvals = [], [], []
@@ -104,7 +110,8 @@ def block_svd(S: Split, alpha: float) -> BlockStage:
         r0, c0, mi, ni = (int(x) for x in S.blocks[b])
         U, s, Vt = np.linalg.svd(Ai, full_matrices=False)
         block_sigma.append(s)
-        si = min(target_rank(alpha, ni), mi, ni)
+        want = target_rank(alpha, ni) if block_ranks is None else int(block_ranks[b])
+        si = min(want, mi, ni)
         ranks[b] = si
         if si == 0:
             continue
@@ -189,9 +196,11 @@ class OracleResult:
 
 
 def fastpi_svd(m, n, indptr, indices, data, alpha, k=0.01,
-               inner: InnerSolver | None = None) -> OracleResult:
+               inner: InnerSolver | None = None, block_ranks=None) -> OracleResult:
     """Algorithm 1 lines 1-4, results mapped back to the original order; `inner` selects
-    the truncated inner solver of the two updates (None: exact)."""
+    the truncated inner solver of the two updates (None: exact); `block_ranks` replaces
+    Eq. 1's per-block ranks (one per entry of the reordering's block table), the later
+    truncations keep their rules (s from n1 and the new s_b, r from min(m, n))."""
     if not (0.0 < alpha <= 1.0):
         raise ValueError("alpha must lie in (0, 1]")
     A = sp.csr_matrix((np.asarray(data, np.float64), np.asarray(indices), np.asarray(indptr)),
@@ -200,7 +209,7 @@ def fastpi_svd(m, n, indptr, indices, data, alpha, k=0.01,
     A.sort_indices()
     R = reorder(m, n, A.indptr, A.indices, k)
     S = split_blocks(m, n, A.indptr, A.indices, A.data, R)
-    B = block_svd(S, alpha)
+    B = block_svd(S, alpha, block_ranks)
     R2 = row_update(S, B, alpha, inner)
     R3 = column_update(S, R2, alpha, m, n, inner)
     U = R3.U[R.piT.astype(np.int64), :]

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libfastpi.so")
 
 FP64, MIXED = 0, 1
 
-STATUS = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ENONFINITE", -4: "ENOMEM", -5: "EHIP",
+STATUS = {1: "WFLOOR", 0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ENONFINITE", -4: "ENOMEM", -5: "EHIP",
           -6: "ENOCONV", -7: "EINTERNAL"}
 
 
@@ -408,7 +408,12 @@ class Handle:
         return vals, vecs
 
     def sync(self):
-        _check(load().fastpi_sync(self._h))
+        """Waits; raises on an error code, returns "OK" or the warning "WFLOOR" (a kept singular
+        value under the Gram floor, returned as 0)."""
+        code = load().fastpi_sync(self._h)
+        if code < 0:
+            _check(code)
+        return STATUS[code]
 
     def last_sweeps(self):
         out = np.zeros(3, dtype=np.int32)

@@ -130,6 +130,11 @@ int decode_status(int bits) {
         set_error("internal: block rank above the supported bound");
         return FASTPI_EINTERNAL;
     }
+    if (bits & kStatusFloor) {
+        set_error("warning: a kept singular value was at or below the Gram floor (1e-7 of the largest) "
+                  "and is returned as 0");
+        return FASTPI_WFLOOR;
+    }
     return FASTPI_OK;
 }
 
@@ -1147,7 +1152,8 @@ int fastpi_batch_sync(fastpi_batch* b, int32_t* status, int32_t* sweeps) {
         if (status) status[i] = code;
         if (sweeps)
             for (int k = 0; k < 3; ++k) sweeps[3 * i + k] = b->inst[i].sweeps[k];
-        if (code != FASTPI_OK && first == FASTPI_OK) {
+        // the first error wins over any warning
+        if (code != FASTPI_OK && (first == FASTPI_OK || (first > 0 && code < 0))) {
             first = code;
             first_msg = "instance " + std::to_string(i) + ": " + fastpi_last_error();
         }

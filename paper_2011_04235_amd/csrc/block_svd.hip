@@ -228,12 +228,15 @@ __global__ __launch_bounds__(256) void k_block_svd(const BlockTask* __restrict__
 __global__ __launch_bounds__(256) void k_block_gram_out(const double* __restrict__ lam, const double* __restrict__ E,
                                                         const double* __restrict__ W, int64_t q, int64_t p, int64_t t,
                                                         double cut, double* __restrict__ qout,
-                                                        double* __restrict__ pout, double* __restrict__ sig) {
+                                                        double* __restrict__ pout, double* __restrict__ sig,
+                                                        int* __restrict__ status) {
     const int64_t k = blockIdx.y;
     const double l0 = lam[0] > 0 ? lam[0] : 0.0;
     const double lk = lam[k];
     const double lim = cut * cut * l0;
     const double sk = (lk > lim && lk > 0) ? sqrt(lk) : 0.0;
+    // a kept singular value under the Gram floor of a non-zero block: warning bit
+    if (sk == 0.0 && l0 > 0 && status && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(status, kStatusFloor);
     const double inv = sk > 0 ? 1.0 / sk : 0.0;
     for (int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; r < p + q;
          r += static_cast<int64_t>(gridDim.x) * blockDim.x) {
@@ -275,11 +278,12 @@ void launch_block_svd_tasks(bool fp32, const BlockTask* tasks, int ntasks, int* 
 }
 
 void launch_block_gram_out(const double* lam, const double* E, const double* W, int64_t q, int64_t p,
-                           int64_t t, double cut, double* qout, double* pout, double* sig, hipStream_t st) {
+                           int64_t t, double cut, double* qout, double* pout, double* sig, int* status,
+                           hipStream_t st) {
     if (t <= 0) return;
     const unsigned gx = static_cast<unsigned>(std::min<int64_t>((p + q + 255) / 256, 64));
     hipLaunchKernelGGL(k_block_gram_out, dim3(gx, static_cast<unsigned>(t)), dim3(256), 0, st, lam, E, W, q, p, t,
-                       cut, qout, pout, sig);
+                       cut, qout, pout, sig, status);
 }
 
 }  // namespace fastpi

@@ -23,8 +23,9 @@ namespace {
         }                                                                           \
     } while (0)
 
-// Singular values below this fraction of the largest are not resolved by the Gram route
-// (about sqrt(q eps)); they are returned as zero.
+// Singular values at or below this fraction of the largest are not resolved by the Gram
+// route (about sqrt(q eps)); they are returned as zero and the matrix's status word takes
+// the floor warning bit.
 constexpr double kRelCut = 1e-7;
 
 int launch_status() {
@@ -618,7 +619,7 @@ static void stage_front2(Group& g, const RunCfg& c, hipStream_t st) {
         else
             launch_gemm_tn(b.A, b.p, b.E, b.t, b.p, b.t, b.q, b.W, b.t, nullptr, nullptr, b.part, b.sp, st, false);
         launch_block_gram_out(b.lam, b.E, b.W, b.q, b.p, b.t, kRelCut, b.trans ? b.U : b.V, b.trans ? b.V : b.U,
-                              b.sig, st);
+                              b.sig, g.inst[b.inst]->status, st);
     }
     // a3, first half: M2^T M2 = V1 Sigma1^2 V1^T + A21^T A21
     for (Instance* Ip : g.inst) {
@@ -650,7 +651,7 @@ static void stage_mid(Group& g, const RunCfg& c, hipStream_t st) {
         // a3, second half: sigma2 and U2 = M2 V2 Sigma2^-1 (block part and A21 part)
         if (d.n1 > 0 && s > 0) {
             if (idx < g.sign_v2.size() && g.sign_v2[idx]) launch_sign_fix(ws + I.o_v2, d.n1, s, st);
-            launch_sqrt_inv(ws + I.o_lam2, s, kRelCut, sig2, inv2, st);
+            launch_sqrt_inv(ws + I.o_lam2, s, kRelCut, sig2, inv2, I.status, st);
             launch_fill(U2, m * s, 0.0, st);
             launch_u2_top(d.work, static_cast<int>(d.B_dense), ws + I.o_u1, ws + I.o_sig1, ws + I.o_v1,
                           ws + I.o_v2, s, inv2, U2, I.status, st);
@@ -689,7 +690,7 @@ static void stage_back(Group& g, double* const* U, double* const* S, double* con
         double* C2 = ws + I.o_c2;
         double* sig3 = ws + I.o_sig3;
         double* inv3 = ws + I.o_inv3;
-        launch_sqrt_inv(ws + I.o_lam3, r, kRelCut, sig3, inv3, st);
+        launch_sqrt_inv(ws + I.o_lam3, r, kRelCut, sig3, inv3, I.status, st);
         launch_col_coeffs(Vt, s, n2, r, ws + I.o_sig2, inv3, C1, C2, st);
         // a4, second half, and a5: U and V in the caller's order
         launch_gemm_nn(ws + I.o_u2, s, d.piT, C1, r, m, r, s, U[i], r, nullptr, st, c.mixed);

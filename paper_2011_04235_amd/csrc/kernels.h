@@ -193,7 +193,10 @@ void launch_blockdiag_gram(const BlockWork* work, int nwork, const double* V1, c
 void launch_u2_top(const BlockWork* work, int nwork, const double* U1, const double* sig1,
                    const double* V1, const double* V2, int64_t s, const double* inv_sig2,
                    double* U2, int* status, hipStream_t st);
-void launch_sqrt_inv(const double* lam, int64_t t, double rel_cut, double* sigma, double* inv,
+// Status word bits of one matrix: 1 non-finite value, 2 sweep cap reached, 4 internal bound,
+// 8 a kept singular value under the Gram floor (warning).
+constexpr int kStatusFloor = 8;
+void launch_sqrt_inv(const double* lam, int64_t t, double rel_cut, double* sigma, double* inv, int* status,
                      hipStream_t st);
 void launch_col_coeffs(const double* Vt, int64_t s, int64_t n2, int64_t r, const double* sig2,
                        const double* inv3, double* C1, double* C2, hipStream_t st);
@@ -207,11 +210,12 @@ void launch_pinv_sigma(const double* S, int64_t r, double cut, double* inv, hipS
 void launch_gauss(double* out, int64_t count, uint32_t seed, uint32_t stream, hipStream_t st);
 void launch_scale_cols(const double* V, const double* d, int64_t k, double cut, double* S, hipStream_t st);
 // Outputs of a block SVD computed through its Gram matrix: sigma_k = sqrt(lam_k) (0 when
-// lam_k <= (cut sigma_0)^2), the q-side factor E[:, k] (E: q x t row-major) and the p-side
-// factor W[:, k] / sigma_k (W: p x t row-major; 0 for a zero sigma), both written
-// column-major into the block's packed outputs.
+// lam_k <= (cut sigma_0)^2, with kStatusFloor set in *status when sigma_0 > 0), the q-side
+// factor E[:, k] (E: q x t row-major) and the p-side factor W[:, k] / sigma_k (W: p x t
+// row-major; 0 for a zero sigma), both written column-major into the block's packed outputs.
 void launch_block_gram_out(const double* lam, const double* E, const double* W, int64_t q, int64_t p,
-                           int64_t t, double cut, double* qout, double* pout, double* sig, hipStream_t st);
+                           int64_t t, double cut, double* qout, double* pout, double* sig, int* status,
+                           hipStream_t st);
 // negates each column of V (rows x cols, row-major) whose largest-magnitude entry (first on
 // ties) is negative
 void launch_sign_fix(double* V, int64_t rows, int64_t cols, hipStream_t st);

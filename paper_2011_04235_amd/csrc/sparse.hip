@@ -293,8 +293,12 @@ void launch_u2_top(const BlockWork* work, int nwork, const double* U1, const dou
 
 // sigma = sqrt(max(lam, 0)); inv = 1/sigma above the cut-off (else 0) -- for the rank
 // deficient case the corresponding columns are zero (their singular value is 0 in effect)
+// sigma = sqrt(lambda) and its reciprocal for the t kept eigenvalues of a Gram matrix; a
+// value at or below rel_cut times the largest is not resolved by the Gram matrix and is
+// returned as 0 (reciprocal 0), with bit 8 of the owner's status word set when the largest
+// is positive (the kept rank reaches the floor)
 __global__ void k_sqrt_inv(const double* __restrict__ lam, int64_t t, double rel_cut,
-                           double* __restrict__ sigma, double* __restrict__ inv) {
+                           double* __restrict__ sigma, double* __restrict__ inv, int* __restrict__ status) {
     const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= t) return;
     const double l0 = lam[0] > 0 ? lam[0] : 0.0;
@@ -303,13 +307,14 @@ __global__ void k_sqrt_inv(const double* __restrict__ lam, int64_t t, double rel
     const bool keep = sg > rel_cut * sqrt(l0);
     sigma[k] = keep ? sg : 0.0;
     inv[k] = keep ? 1.0 / sg : 0.0;
+    if (!keep && l0 > 0 && status) atomicOr(status, kStatusFloor);
 }
 
-void launch_sqrt_inv(const double* lam, int64_t t, double rel_cut, double* sigma, double* inv,
+void launch_sqrt_inv(const double* lam, int64_t t, double rel_cut, double* sigma, double* inv, int* status,
                      hipStream_t st) {
     if (t <= 0) return;
     hipLaunchKernelGGL(k_sqrt_inv, dim3(static_cast<unsigned>((t + 255) / 256)), dim3(256), 0, st, lam, t,
-                       rel_cut, sigma, inv);
+                       rel_cut, sigma, inv, status);
 }
 
 // C1 = diag(sig2) Vt[0:s, :] diag(inv3) (s x r) and C2 = Vt[s:, :] diag(inv3) (n2 x r)

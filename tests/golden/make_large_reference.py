@@ -1,5 +1,7 @@
 """Writes tests/golden/<workload>_reference.npz: quantities of the oracle's result on a full-size
 workload that a GPU test can compare without re-running the oracle (which takes minutes there).
+A workload is a named configuration (c3, c5) or instance i of the 64-matrix batched workload
+(c4:i, written as c4_i_reference.npz).
 
 Only oracle/ and synth/ are called. Stored: the r singular values, the reconstruction error
 ||A - U S V^T||_F / ||A||_F, the least-squares residual ||A Z - Y||_F / ||Y||_F, Z at 16 seeded
@@ -9,6 +11,7 @@ Q (m x 4) drawn from a seeded generator (invariant under the sign freedom of the
 vectors).
 
     python tests/golden/make_large_reference.py c3
+    python tests/golden/make_large_reference.py c4:23
 """
 import os
 import sys
@@ -20,7 +23,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import oracle  # noqa: E402
-from synth import CONFIGS, make_problem  # noqa: E402
+from synth import CONFIGS, make_problem, sample_batch_configs  # noqa: E402
 
 PROBE_SEED = 77
 
@@ -34,8 +37,16 @@ def probes(m, n):
     return g.standard_normal((n, 4)), g.standard_normal((m, 4))
 
 
+def workload(name):
+    """(config, file stem) of a named workload or of batched-workload instance c4:i."""
+    if name.startswith("c4:"):
+        i = int(name.split(":")[1])
+        return sample_batch_configs(64)[i], f"c4_{i}"
+    return CONFIGS[name], name
+
+
 def main(name):
-    cfg = CONFIGS[name]
+    cfg, stem = workload(name)
     prob = make_problem(cfg)
     t0 = time.time()
     res = oracle.fastpi_svd(prob.m, prob.n, prob.indptr, prob.indices, prob.data, cfg.alpha, cfg.k)
@@ -49,7 +60,7 @@ def main(name):
     rows_z = sample_rows(16, prob.n, PROBE_SEED + 3)
     usvp = (res.U[rows_u] * res.sigma[None, :]) @ (res.V.T @ P)
     vsuq = (res.V[rows_v] * res.sigma[None, :]) @ (res.U.T @ Q)
-    out = os.path.join(HERE, f"{name}_reference.npz")
+    out = os.path.join(HERE, f"{stem}_reference.npz")
     np.savez_compressed(out, sigma=res.sigma, recon=oracle.recon_error(A, res.U, res.sigma, res.V),
                         ls=oracle.ls_residual(A, Z, prob.Y), rows_u=rows_u, rows_v=rows_v, rows_z=rows_z,
                         usvp=usvp, vsuq=vsuq, z_rows=Z[rows_z], probe_seed=PROBE_SEED, r=res.r,
@@ -58,4 +69,5 @@ def main(name):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else "c3")
+    for arg in (sys.argv[1:] or ["c3"]):
+        main(arg)

@@ -113,3 +113,122 @@ def test_degenerate_inputs_in_one_batch(env):
             ores = oracle.fastpi_svd(p.m, p.n, p.indptr, p.indices, p.data, a, k)
             ok, info = compare_svd(p, U, S, V, ores)
             assert ok, (graph, info)
+
+
+def graded_problem(m=400, n=60, decades=9.0, seed=5):
+    """A sparse matrix whose singular values span about `decades` orders of magnitude: a
+    random sparse pattern with U(0.5, 1] values plus a full diagonal (so every column is
+    used), columns scaled by 10^(-decades * j / (n - 1)) in a random column order."""
+    rng = np.random.default_rng(seed)
+    mask = rng.random((m, n)) < 0.08
+    mask[np.arange(n), np.arange(n)] = True
+    dense = np.where(mask, 0.5 + 0.5 * rng.random((m, n)), 0.0)
+    scale = 10.0 ** (-decades * rng.permutation(n) / (n - 1))
+    dense *= scale[None, :]
+    indptr = np.concatenate([[0], np.cumsum(mask.sum(1))])
+    rows, cols = np.nonzero(mask)
+    return P(m, n, indptr, cols, dense[rows, cols], L=4, seed=seed)
+
+
+def test_graded_spectrum_full_rank_reports_the_gram_floor(env):
+    """alpha = 1 on a matrix with singular values from 1 down to ~1e-9 of the largest: the
+    Gram route resolves a singular value sigma to a relative error of about q eps
+    (sigma_1 / sigma)^2, so values at or below 1e-7 sigma_1 come back as exactly 0 and
+    fastpi_sync reports the warning WFLOOR. The resolved values match the oracle within that
+    bound, and the pseudoinverse apply restricted to the well-resolved directions
+    (sigma >= 1e-3 sigma_1) matches the oracle's on the same directions."""
+    torch, fp = env
+    p = graded_problem()
+    say("graded spectrum 400x60, alpha=1")
+    h = fp.Handle(0)
+    dev = torch.device("cuda", 0)
+    plan = fp.Plan(p.m, p.n, p.indptr, p.indices, p.data, alpha=1.0, k=0.05)
+    h.upload_plan(plan)
+    Ut, St, Vt = h.svd(*(torch.from_numpy(a).to(dev) for a in (p.indptr, p.indices, p.data)))
+    code = h.sync()
+    U, S, V = to_np(Ut), to_np(St), to_np(Vt)
+    ores = oracle.fastpi_svd(p.m, p.n, p.indptr, p.indices, p.data, 1.0, 0.05)
+    so = ores.sigma
+    say(f"  status {code}, oracle sigma range {so[0]:.3e} .. {so[-1]:.3e}")
+    assert so[-1] < 1e-8 * so[0]            # the input does reach under the floor
+    assert code == "WFLOOR"
+    q = max(plan.n1, plan.s + plan.n2)
+    eps = np.finfo(np.float64).eps
+    bound = np.maximum(1e-9, 8.0 * q * eps * (so[0] / so) ** 2)
+    resolved = bound <= 1e-2
+    rel = np.abs(S - so) / so
+    say(f"  resolved {int(resolved.sum())} of {so.size}; worst ratio err/bound "
+        f"{np.max(rel[resolved] / bound[resolved]):.3f}")
+    assert np.all(rel[resolved] <= bound[resolved])
+    assert np.all(S[so <= 1e-8 * so[0]] == 0.0)   # under the floor with margin: returned as 0
+    # Z on the well-resolved directions, both sides restricted the same way
+    def z_restricted(U, S, V, keep):
+        return V[:, keep] @ ((U[:, keep].T @ p.Y) / S[keep, None])
+    keep_g, keep_o = S >= 1e-3 * S[0], so >= 1e-3 * so[0]
+    assert np.array_equal(keep_g, keep_o)
+    Zg, Zo = z_restricted(U, S, V, keep_g), z_restricted(ores.U, so, ores.V, keep_o)
+    err = float(np.max(np.abs(Zg - Zo)) / np.max(np.abs(Zo)))
+    say(f"  restricted Z max rel err {err:.2e}")
+    assert err <= 1e-6
+
+
+def test_graded_spectrum_truncated_above_the_floor_meets_fp64_gates(env):
+    """The same graded matrix at alpha = 0.3: every kept singular value lies far above the
+    floor, no warning, and the FP64 gates hold against the oracle."""
+    torch, fp = env
+    p = graded_problem()
+    say("graded spectrum 400x60, alpha=0.3")
+    h = fp.Handle(0)
+    plan, U, S, V, Z = run(fp, torch, p, 0.3, h)
+    assert h.sync() == "OK"
+    ores = oracle.fastpi_svd(p.m, p.n, p.indptr, p.indices, p.data, 0.3, 0.1)
+    ok, info = compare_svd(p, U, S, V, ores)
+    say(f"  {info}")
+    assert ok, info
+    ok, zinfo = compare_apply(p, Z, ores)
+    assert ok, zinfo
+
+
+def test_sweep_cap_reports_enoconv(env):
+    """max_sweeps = 1 stops every Jacobi iteration after one sweep (a bounded exit: the
+    kernels return normally); fastpi_sync and fastpi_batch_sync report ENOCONV."""
+    torch, fp = env
+    from synth import make_problem
+    p = make_problem("c1")
+    say("sweep cap 1 on 2000x500")
+    dev = torch.device("cuda", 0)
+    h = fp.Handle(0, max_sweeps=1)
+    plan = fp.Plan(p.m, p.n, p.indptr, p.indices, p.data, alpha=0.3, k=0.01)
+    h.upload_plan(plan)
+    h.svd(*(torch.from_numpy(a).to(dev) for a in (p.indptr, p.indices, p.data)))
+    with pytest.raises(fp.FastPIError) as ei:
+        h.sync()
+    assert ei.value.status == "ENOCONV"
+    b = fp.Batch(h, [plan])
+    b.svd([torch.from_numpy(p.data).to(dev)])
+    status, sweeps = b.sync()
+    assert status == ["ENOCONV"], status
+    # the same handle without the cap converges
+    h2 = fp.Handle(0)
+    h2.upload_plan(plan)
+    h2.svd(*(torch.from_numpy(a).to(dev) for a in (p.indptr, p.indices, p.data)))
+    assert h2.sync() == "OK"
+
+
+def test_workspace_cap_reports_enomem(env):
+    """A workspace cap below what the plan needs fails the upload with ENOMEM (nothing is
+    launched); a cap above it works."""
+    torch, fp = env
+    from synth import make_problem
+    p = make_problem("c1")
+    say("workspace cap on 2000x500")
+    plan = fp.Plan(p.m, p.n, p.indptr, p.indices, p.data, alpha=0.3, k=0.01)
+    h = fp.Handle(0, max_workspace_bytes=1 << 16)
+    with pytest.raises(fp.FastPIError) as ei:
+        h.upload_plan(plan)
+    assert ei.value.status == "ENOMEM"
+    h2 = fp.Handle(0, max_workspace_bytes=1 << 32)
+    h2.upload_plan(plan)
+    dev = torch.device("cuda", 0)
+    h2.svd(*(torch.from_numpy(a).to(dev) for a in (p.indptr, p.indices, p.data)))
+    assert h2.sync() == "OK"

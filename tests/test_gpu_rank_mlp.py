@@ -198,3 +198,41 @@ def test_learned_ranks_at_scale(env):
     assert e_net < e_alpha
     assert errs["learned"] <= errs["alpha"] + 1e-4
 
+
+
+def test_learned_ranks_match_oracle_with_same_ranks(env):
+    """The whole GPU path under the shipped predictor's per-block ranks against the oracle
+    run with the same per-block ranks (Eq. 1 with given s_i), on two held-out matrices, FP64
+    gates (singular values, rank-r product, reconstruction error, orthonormality, Z)."""
+    torch, fp, h, d, RankPredictor, init_params = env
+    sys.path.insert(0, GOLDEN)
+    sys.path.insert(0, os.path.dirname(__file__))
+    import oracle
+    from make_rank_dataset import instance_config
+    from parity import compare_apply, compare_svd
+    from synth import make_problem
+    pred = RankPredictor.load(os.path.join(os.path.dirname(fp.__file__), "rank_predictor.npz"))
+    dev = torch.device("cuda", 0)
+    for i in range(int(d["n_train"]), int(d["n_train"]) + 2):
+        cfg = instance_config(i)
+        p = make_problem(cfg)
+        say(f"learned ranks vs oracle, matrix {i}: {p.m}x{p.n} alpha {cfg.alpha}")
+        plan = fp.Plan(p.m, p.n, p.indptr, p.indices, p.data, alpha=cfg.alpha, k=cfg.k)
+        blocks = plan.blocks()
+        dense = (blocks[:, 2] > 0) & (blocks[:, 3] > 0)
+        alpha_ranks = plan.block_ranks().copy()
+        plan.set_block_ranks(pred.block_ranks(h, plan, p.data, alpha_ranks[dense]))
+        ranks = plan.block_ranks()
+        assert not np.array_equal(ranks, alpha_ranks)
+        h.upload_plan(plan)
+        U, S, V = h.svd(*(torch.from_numpy(a).to(dev) for a in (p.indptr, p.indices, p.data)))
+        Z = h.apply(U, S, V, torch.from_numpy(p.Y).to(dev))
+        h.sync()
+        ores = oracle.fastpi_svd(p.m, p.n, p.indptr, p.indices, p.data, cfg.alpha, cfg.k, block_ranks=ranks)
+        assert np.array_equal(ores.blocks.ranks, ranks)
+        ok, info = compare_svd(p, U.cpu().numpy(), S.cpu().numpy(), V.cpu().numpy(), ores)
+        say(f"  {info}")
+        assert ok, info
+        okz, zinfo = compare_apply(p, Z.cpu().numpy(), ores)
+        say(f"  {zinfo}")
+        assert okz, zinfo

@@ -157,3 +157,22 @@ def test_malformed_device_csr_is_rejected(env):
     with pytest.raises(fp.FastPIError):
         h.reorder(2, 3, dev_t(torch, ok_ip.astype(np.int64)), dev_t(torch, ok_ix.astype(np.int32)),
                   dev_t(torch, np.array([1.0, np.inf, 2.0])), k=0.1)
+
+
+@pytest.mark.parametrize("name", ["c3", "c5"])
+def test_large_workloads_equal_the_oracle(env, name):
+    """The GPU reordering at 100000 x 5000 and 300000 x 10000 against the oracle's Algorithm 2
+    directly (not through the host library): permutations, block table and split sizes bit
+    for bit."""
+    torch, fp, h = env
+    import oracle
+    cfg = CONFIGS[name]
+    p = make_problem(cfg, with_labels=False)
+    say(f"GPU reordering vs oracle at {name} {p.m}x{p.n}")
+    gpu = h.reorder(p.m, p.n, dev_t(torch, p.indptr), dev_t(torch, p.indices), dev_t(torch, p.data), k=cfg.k)
+    R = oracle.reorder(p.m, p.n, p.indptr, p.indices, cfg.k)
+    assert np.array_equal(gpu[0], R.piT) and np.array_equal(gpu[1], R.piF)
+    assert np.array_equal(gpu[2], R.blocks)
+    split = gpu[3]
+    assert (split["m1"], split["n1"], split["m2"], split["n2"], split["T_it"]) == \
+        (R.m1, R.n1, R.m2, R.n2, R.iterations)

@@ -507,3 +507,57 @@ def test_orthonormality_error_planted_slips_fail_the_pin():
 
     for slip in (signed_max, rows_as_n, no_filter, positive_filter, offdiag_only):
         assert not _orth_pin(slip), slip.__name__
+
+
+def _block_override_pin(fastpi_svd):
+    """Eq. 1 with given per-block ranks: each dense block keeps min(given, m_i, n_i)
+    directions, its truncation loss is the Eckart-Young one (eigenvalue route), the block
+    singular values are the block's largest ones, and the later ranks follow their rules."""
+    p = small_problem(m=300, n=90, density=0.05, seed=21, alpha=0.3, k=0.05)
+    alpha = 0.3
+    R = oracle.reorder(p.m, p.n, p.indptr, p.indices, 0.05)
+    rng = np.random.default_rng(4)
+    given = rng.integers(0, 6, size=len(R.blocks))
+    res = fastpi_svd(p.m, p.n, p.indptr, p.indices, p.data, alpha, 0.05, block_ranks=given)
+    S = ofp.split_blocks(p.m, p.n, p.indptr, p.indices, p.data, R)
+    col = 0
+    for Ai, b in zip(S.block_dense, S.block_index):
+        mi, ni = Ai.shape
+        si = min(int(given[b]), mi, ni)
+        assert res.blocks.ranks[b] == si
+        sig = eig_sigma(Ai)
+        r0, c0 = int(S.blocks[b][0]), int(S.blocks[b][1])
+        U1 = res.blocks.U1[r0:r0 + mi, col:col + si].toarray()
+        V1 = res.blocks.V1[c0:c0 + ni, col:col + si].toarray()
+        s1 = res.blocks.sigma1[col:col + si]
+        assert np.allclose(s1, sig[:si], rtol=1e-10, atol=1e-12 * max(sig[0], 1e-300))
+        loss = np.sum((Ai - (U1 * s1) @ V1.T) ** 2)
+        assert abs(loss - np.sum(sig[si:] ** 2)) <= 1e-10 * np.sum(sig ** 2)
+        col += si
+    s_b = col
+    assert res.blocks.sigma1.size == s_b
+    assert res.row.sigma.size == min(ofp.target_rank(alpha, S.n1), s_b + S.m2, S.n1)
+    return res
+
+
+def test_block_rank_override_pinned():
+    p = small_problem(m=300, n=90, density=0.05, seed=21, alpha=0.3, k=0.05)
+    _block_override_pin(oracle.fastpi_svd)
+    # the alpha rule's own ranks given explicitly: the same result, bit for bit
+    ref = oracle.fastpi_svd(p.m, p.n, p.indptr, p.indices, p.data, 0.3, 0.05)
+    same = oracle.fastpi_svd(p.m, p.n, p.indptr, p.indices, p.data, 0.3, 0.05, block_ranks=ref.blocks.ranks)
+    assert np.array_equal(ref.sigma, same.sigma) and np.array_equal(ref.U, same.U)
+
+
+def test_block_rank_override_planted_slip_fails_the_pin():
+    """An oracle that ignores the given ranks (keeps Eq. 1's alpha rule) fails the pin."""
+    def ignoring(m, n, indptr, indices, data, alpha, k=0.01, block_ranks=None):
+        return oracle.fastpi_svd(m, n, indptr, indices, data, alpha, k)
+    with pytest.raises(AssertionError):
+        _block_override_pin(ignoring)
+
+    def off_by_one(m, n, indptr, indices, data, alpha, k=0.01, block_ranks=None):
+        return oracle.fastpi_svd(m, n, indptr, indices, data, alpha, k,
+                                 block_ranks=np.asarray(block_ranks) + 1)
+    with pytest.raises(AssertionError):
+        _block_override_pin(off_by_one)
