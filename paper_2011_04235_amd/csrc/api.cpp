@@ -1,6 +1,7 @@
 // C ABI: plans (host), handles, batches and the device path of Algorithm 1 lines 2-5.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 #include <cstring>
@@ -54,6 +55,9 @@ struct fastpi_handle {
     // evaluation scratch (scores beyond the LDS capacity)
     double* ews = nullptr;
     size_t ews_bytes = 0;
+    // batches created on this handle and not destroyed yet: released (and detached) when the
+    // handle is destroyed first, so the two may be destroyed in either order
+    std::vector<fastpi_batch*> batches;
 };
 
 // A sparse label matrix Y (m x L) held on the device as its transpose in CSR (per label,
@@ -68,7 +72,7 @@ struct fastpi_labels {
 };
 
 struct fastpi_batch {
-    fastpi_handle* h = nullptr;
+    fastpi_handle* h = nullptr;   // null once the handle was destroyed (the batch is detached)
     std::vector<Instance> inst;
     Group grp;
     int* status = nullptr;        // device: 2 words per instance
@@ -443,10 +447,20 @@ int fastpi_set_precision(fastpi_handle* h, fastpi_precision p) {
     return FASTPI_OK;
 }
 
+static void batch_release(fastpi_batch* b);
+static bool batch_live(const fastpi_batch* b);
+
 void fastpi_destroy(fastpi_handle* h) {
     if (!h) return;
     hipSetDevice(h->device);
     hipStreamSynchronize(h->stream);
+    // release the device resources of the batches still alive on this handle; their host
+    // objects stay valid (detached) until fastpi_batch_destroy
+    for (fastpi_batch* b : h->batches) {
+        batch_release(b);
+        b->h = nullptr;
+    }
+    h->batches.clear();
     group_free(h->grp);
     instance_free(h->inst, h->stream);
     if (h->aws) hipFree(h->aws);
@@ -971,6 +985,7 @@ int fastpi_set_block_route(fastpi_handle* h, double min_cost) {
 }
 
 int fastpi_batch_set_block_route(fastpi_batch* b, double min_cost) {
+    if (!batch_live(b)) return FASTPI_EINVAL;
     if (!b || !(min_cost >= 0)) {
         set_error("bad batch or cost");
         return FASTPI_EINVAL;
@@ -1064,18 +1079,18 @@ int fastpi_batch_create(fastpi_batch** b, fastpi_handle* h, int64_t count,
         return FASTPI_ENOMEM;
     }
     B->h = h;
+    h->batches.push_back(B);
     B->inst.resize(static_cast<size_t>(count));
     void* p = nullptr;
     const size_t words = static_cast<size_t>(2 * count + 16);
     if (hipMalloc(&p, words * sizeof(int)) != hipSuccess) {
-        delete B;
+        fastpi_batch_destroy(B);
         set_error("device allocation failed (batch status)");
         return FASTPI_ENOMEM;
     }
     B->status = static_cast<int*>(p);
     if (hipHostMalloc(&p, words * sizeof(int), hipHostMallocDefault) != hipSuccess) {
-        hipFree(B->status);
-        delete B;
+        fastpi_batch_destroy(B);
         set_error("pinned host allocation failed");
         return FASTPI_ENOMEM;
     }
@@ -1105,8 +1120,8 @@ int fastpi_batch_create(fastpi_batch** b, fastpi_handle* h, int64_t count,
     return check_launch();
 }
 
-void fastpi_batch_destroy(fastpi_batch* b) {
-    if (!b) return;
+// frees a batch's device resources on its handle's device and stream (handle alive)
+static void batch_release(fastpi_batch* b) {
     fastpi_handle* h = b->h;
     hipSetDevice(h->device);
     hipStreamSynchronize(h->stream);
@@ -1114,11 +1129,36 @@ void fastpi_batch_destroy(fastpi_batch* b) {
     for (Instance& I : b->inst) instance_free(I, h->stream);
     if (b->status) hipFree(b->status);
     if (b->host_status) hipHostFree(b->host_status);
+    b->status = nullptr;
+    b->host_status = nullptr;
+}
+
+void fastpi_batch_destroy(fastpi_batch* b) {
+    if (!b) return;
+    if (fastpi_handle* h = b->h) {
+        batch_release(b);
+        auto& v = h->batches;
+        v.erase(std::remove(v.begin(), v.end(), b), v.end());
+    }
     delete b;
+}
+
+// a batch whose handle is still alive
+static bool batch_live(const fastpi_batch* b) {
+    if (!b) {
+        set_error("null batch");
+        return false;
+    }
+    if (!b->h) {
+        set_error("the batch's handle was destroyed");
+        return false;
+    }
+    return true;
 }
 
 int fastpi_batch_svd(fastpi_batch* b, const double* const* val, double* const* U, double* const* S,
                      double* const* V) {
+    if (!batch_live(b)) return FASTPI_EINVAL;
     if (!b || !val || !U || !S || !V) {
         set_error("null pointer");
         return FASTPI_EINVAL;
@@ -1135,6 +1175,7 @@ int fastpi_batch_svd(fastpi_batch* b, const double* const* val, double* const* U
 }
 
 int fastpi_batch_sync(fastpi_batch* b, int32_t* status, int32_t* sweeps) {
+    if (!batch_live(b)) return FASTPI_EINVAL;
     if (!b) {
         set_error("null batch");
         return FASTPI_EINVAL;
@@ -1175,6 +1216,7 @@ int fastpi_batch_rotations(const fastpi_batch* b, int64_t* out) {
 }
 
 int fastpi_batch_set_graph(fastpi_batch* b, int enable) {
+    if (!batch_live(b)) return FASTPI_EINVAL;
     if (!b) {
         set_error("null batch");
         return FASTPI_EINVAL;
@@ -1186,6 +1228,7 @@ int fastpi_batch_set_graph(fastpi_batch* b, int enable) {
 int64_t fastpi_batch_last_graph_launches(const fastpi_batch* b) { return b ? b->grp.graph_launches : -1; }
 
 int fastpi_batch_set_tuning(fastpi_batch* b, const fastpi_tuning* t) {
+    if (!batch_live(b)) return FASTPI_EINVAL;
     if (!b || !t) {
         set_error("null pointer");
         return FASTPI_EINVAL;
@@ -1195,6 +1238,7 @@ int fastpi_batch_set_tuning(fastpi_batch* b, const fastpi_tuning* t) {
 }
 
 int fastpi_batch_set_inner(fastpi_batch* b, const fastpi_inner* c) {
+    if (!batch_live(b)) return FASTPI_EINVAL;
     if (!b || !c) {
         set_error("null pointer");
         return FASTPI_EINVAL;
@@ -1214,6 +1258,7 @@ int fastpi_batch_get_tuning(const fastpi_batch* b, fastpi_tuning* t) {
 
 int fastpi_batch_autotune(fastpi_batch* b, const double* const* val, double* const* U, double* const* S,
                           double* const* V, char* report, int64_t report_cap) {
+    if (!batch_live(b)) return FASTPI_EINVAL;
     if (!b || !val || !U || !S || !V) {
         set_error("null pointer");
         return FASTPI_EINVAL;

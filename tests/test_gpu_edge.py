@@ -232,3 +232,29 @@ def test_workspace_cap_reports_enomem(env):
     dev = torch.device("cuda", 0)
     h2.svd(*(torch.from_numpy(a).to(dev) for a in (p.indptr, p.indices, p.data)))
     assert h2.sync() == "OK"
+
+
+def test_handle_destroyed_before_its_batch(env):
+    """A handle destroyed while a batch created on it is alive releases the batch's device
+    resources and detaches it: later batch calls fail with EINVAL, and destroying the batch
+    afterwards is safe (the order in which a garbage collector finalises the two objects
+    does not matter)."""
+    torch, fp = env
+    import ctypes
+    from synth import make_problem
+    p = make_problem("c1")
+    say("handle destroyed before its batch")
+    lib = fp.load()
+    plan = fp.Plan(p.m, p.n, p.indptr, p.indices, p.data, alpha=0.3, k=0.01)
+    h = fp.Handle(0)
+    b = fp.Batch(h, [plan])
+    dev = torch.device("cuda", 0)
+    b.svd([torch.from_numpy(p.data).to(dev)])
+    assert b.sync()[0] == ["OK"]
+    lib.fastpi_destroy(h._h)            # the handle goes first
+    h._h = None
+    st = (ctypes.c_int32 * 1)()
+    assert lib.fastpi_batch_sync(b._b, st, None) == -1
+    assert lib.fastpi_batch_set_tuning(b._b, ctypes.byref(fp.Tuning(32768, 4, 128, 1, 1))) == -1
+    lib.fastpi_batch_destroy(b._b)      # then the batch
+    b._b = None
