@@ -257,6 +257,20 @@ int fastpi_apply(fastpi_handle* h, int64_t m, int64_t n, int64_t r, const double
                  const double* S, const double* V, int64_t L, const double* Y, double* Z);
 
 /*
+ * fastpi_apply without any device allocation, for callers that cannot allocate (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc). Same arguments,
+ * layout and result as fastpi_apply; the intermediate S^+, U^T Y and its split-K partials
+ * live in a fixed scratch of 8,388,608 doubles (64 MiB) that the library holds on every GPU
+ * it runs on until the process ends. Needs r + 2 r L doubles at least (FASTPI_EINVAL
+ * beyond that); when fastpi_apply's split of U^T Y does not fit, fewer splits are used (the
+ * same result up to the summation order). Every call on a GPU shares that GPU's scratch:
+ * calls that overlap on one GPU (two streams, two threads) race and must be serialised by
+ * the caller.
+ */
+int fastpi_apply_noalloc(fastpi_handle* h, int64_t m, int64_t n, int64_t r, const double* U,
+                         const double* S, const double* V, int64_t L, const double* Y, double* Z);
+
+/*
  * Sparse label matrix of Application 1 (each row of Y is a binary label vector with few
  * positives). Y (m x L) is given as a host CSR: rowptr int64[m+1] (rowptr[0] = 0, monotone),
  * col int32[nnz] in [0, L), val double[nnz] or NULL for all ones. The object keeps a device

@@ -78,6 +78,8 @@ SIGNATURES = [
     ("fastpi_svd", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     ("fastpi_apply", c_int, [c_void_p, c_int64, c_int64, c_int64, c_void_p, c_void_p, c_void_p,
                              c_int64, c_void_p, c_void_p]),
+    ("fastpi_apply_noalloc", c_int, [c_void_p, c_int64, c_int64, c_int64, c_void_p, c_void_p, c_void_p,
+                                     c_int64, c_void_p, c_void_p]),
     ("fastpi_stage_output", c_int, [c_void_p, c_int, c_void_p, c_int64]),
     ("fastpi_syev_top", c_int, [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p]),
     ("fastpi_sync", c_int, [c_void_p]),
@@ -322,6 +324,19 @@ class Handle:
         _check(load().fastpi_apply(self._h, m, n, r, _dptr(U), _dptr(S), _dptr(V), L, _dptr(Y),
                                    _dptr(Z)))
         return Z
+
+    def apply_noalloc(self, U, S, V, Y, out):
+        """fastpi_apply without device allocation (the library's fixed per-GPU scratch); `out`
+        must be given."""
+        torch = self.torch
+        m, r = U.shape
+        n = V.shape[0]
+        L = Y.shape[1]
+        for t in (U, S, V, Y, out):
+            assert t.is_contiguous() and t.dtype == torch.float64 and t.device == self.device
+        _check(load().fastpi_apply_noalloc(self._h, m, n, r, _dptr(U), _dptr(S), _dptr(V), L, _dptr(Y),
+                                           _dptr(out)))
+        return out
 
     def reorder(self, m, n, rowptr, col, val=None, k=0.01):
         """Algorithm 2 on this handle's GPU from a device CSR (torch tensors); returns

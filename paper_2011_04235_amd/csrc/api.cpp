@@ -5,6 +5,7 @@
 #include <cfloat>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -533,6 +534,74 @@ int fastpi_apply(fastpi_handle* h, int64_t m, int64_t n, int64_t r, const double
     double* inv = h->aws;
     double* W = inv + r;
     double* part = W + r * L;
+    launch_pinv_sigma(S, r, static_cast<double>(std::max(m, n)) * DBL_EPSILON, inv, st);
+    const bool mixed = h->opts.precision == FASTPI_MIXED;
+    launch_gemm_tn(U, r, Y, L, r, L, m, W, L, inv, nullptr, part, sp, st, mixed);
+    launch_gemm_nn(V, r, nullptr, W, L, n, L, r, Z, L, nullptr, st, mixed);
+    return check_launch();
+}
+
+}  // extern "C"
+
+// Scratch of fastpi_apply_noalloc: one file-scope device array per GPU (the code object's
+// copy on that device), resolved to a device address once per device with
+// hipGetSymbolAddress; host code only ever uses that address, never the array's name.
+constexpr int64_t kNoAllocApplyDoubles = int64_t(8) << 20;   // 64 MiB
+static __device__ __align__(256) double scratch[kNoAllocApplyDoubles];
+constexpr int kMaxDevices = 64;
+static double* g_scratch_ptr[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+// device address of this device's scratch (resolved on first use, with the device current)
+static int noalloc_scratch(int device, double** out) {
+    if (device < 0 || device >= kMaxDevices) {
+        set_error("device index out of range for the no-allocation scratch");
+        return FASTPI_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            set_error(std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+            return FASTPI_EHIP;
+        }
+        g_scratch_ptr[device] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_ptr[device];
+    return FASTPI_OK;
+}
+
+extern "C" {
+
+int fastpi_apply_noalloc(fastpi_handle* h, int64_t m, int64_t n, int64_t r, const double* U,
+                         const double* S, const double* V, int64_t L, const double* Y, double* Z) {
+    if (!h || m <= 0 || n <= 0 || r < 0 || L < 0) {
+        set_error("bad handle or sizes");
+        return FASTPI_EINVAL;
+    }
+    if (r == 0 || L == 0) return FASTPI_OK;
+    if (!U || !S || !V || !Y || !Z) {
+        set_error("null device pointer");
+        return FASTPI_EINVAL;
+    }
+    // the same split of U^T Y as fastpi_apply where it fits the scratch, fewer splits otherwise
+    const int64_t rl = r * L;
+    if (rl > (kNoAllocApplyDoubles - r) / 2) {
+        set_error("fastpi_apply_noalloc: r * L = " + std::to_string(rl) + " needs more than the " +
+                  std::to_string(kNoAllocApplyDoubles) + "-double scratch (at most r + 2 r L doubles)");
+        return FASTPI_EINVAL;
+    }
+    const int64_t fit = (kNoAllocApplyDoubles - r - rl) / rl;
+    const int sp = static_cast<int>(std::min<int64_t>(gemm_tn_splits(r, L, m), fit));
+    HIP_TRY(hipSetDevice(h->device));
+    double* base = nullptr;
+    int rc = noalloc_scratch(h->device, &base);
+    if (rc != FASTPI_OK) return rc;
+    hipStream_t st = h->stream;
+    double* inv = base;
+    double* W = inv + r;
+    double* part = W + rl;
     launch_pinv_sigma(S, r, static_cast<double>(std::max(m, n)) * DBL_EPSILON, inv, st);
     const bool mixed = h->opts.precision == FASTPI_MIXED;
     launch_gemm_tn(U, r, Y, L, r, L, m, W, L, inv, nullptr, part, sp, st, mixed);
