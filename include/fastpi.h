@@ -397,6 +397,41 @@ int fastpi_set_tuning_cache(fastpi_handle* h, const char* path);
 int fastpi_set_block_route(fastpi_handle* h, double min_cost);
 int fastpi_batch_set_block_route(fastpi_batch* b, double min_cost);
 
+/*
+ * Core solver of the exact branch (the truncated SVD of M2 and of X3, Eqs. 2-3, taken as the
+ * top t eigenpairs of their Gram matrix G of order q). mode 0: block one-sided Jacobi on G
+ * for every core. mode 1 (default): where q >= min_order and k = 32 * ceil(k_factor * t / 32)
+ * is at most max_frac * q, subspace iteration with a k-column block: products Y = G Q (FP32
+ * in FASTPI_MIXED), a Cholesky QR of the block before every orth_every-th product, a fixed
+ * number of products (iters_fp64, iters_mixed), two FP64 Cholesky QRs, then Rayleigh-Ritz:
+ * the top t eigenpairs of Q^T G Q by the block Jacobi, vectors Q W. Every such core is
+ * checked (each pair's residual ||G v - lambda v|| against res_tol * lambda_1 of the form,
+ * the rank of every Cholesky QR); a core that fails is solved again by Jacobi on G, so the
+ * result is always the converged one. Ranges: min_order >= 64, 1 <= k_factor <= 8,
+ * 0 < max_frac <= 1, iterations 1..256, orth_every 1..4, tolerances > 0.
+ */
+typedef struct {
+    int32_t mode;
+    int32_t min_order;
+    double k_factor;
+    double max_frac;
+    int32_t iters_fp64;
+    int32_t iters_mixed;
+    int32_t orth_every;
+    int32_t pad;
+    double res_tol_fp64;
+    double res_tol_mixed;
+} fastpi_core_solver;
+/* Kept across fastpi_upload_plan; a batch takes the handle's setting when it is created. */
+int fastpi_set_core_solver(fastpi_handle* h, const fastpi_core_solver* c);
+int fastpi_get_core_solver(const fastpi_handle* h, fastpi_core_solver* c);
+int fastpi_batch_set_core_solver(fastpi_batch* b, const fastpi_core_solver* c);
+/* Route each core took in the last fastpi_svd (out2[0] row update, out2[1] column update) or
+ * batch run (out: 2 per matrix): 0 Jacobi, 1 subspace iteration, 2 subspace iteration that
+ * failed its check and was solved again by Jacobi, 3 the randomized branch. */
+int fastpi_last_core_routes(const fastpi_handle* h, int32_t* out2);
+int fastpi_batch_core_routes(const fastpi_batch* b, int32_t* out);
+
 /* Selects the inner solver of the handle's runs (kept across fastpi_upload_plan; a batch
  * takes the handle's setting when it is created). FASTPI_EINVAL for values out of range. */
 int fastpi_set_inner(fastpi_handle* h, const fastpi_inner* c);

@@ -60,6 +60,19 @@ class Inner(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class CoreSolver(ctypes.Structure):
+    """Core solver of the exact branch: mode 0 Jacobi on G, 1 subspace iteration where it
+    applies (see include/fastpi.h)."""
+    _fields_ = [("mode", c_int32), ("min_order", c_int32), ("k_factor", c_double), ("max_frac", c_double),
+                ("iters_fp64", c_int32), ("iters_mixed", c_int32), ("orth_every", c_int32), ("pad", c_int32),
+                ("res_tol_fp64", c_double), ("res_tol_mixed", c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
+
+
+ROUTES = {0: "jacobi", 1: "subspace", 2: "subspace+jacobi", 3: "randomized"}
+
 SIGNATURES = [
     ("fastpi_target_rank", c_int64, [c_double, c_int64]),
     ("fastpi_reorder", c_int, [c_int64, c_int64, c_void_p, c_void_p, c_void_p, c_double, c_void_p,
@@ -132,6 +145,11 @@ SIGNATURES = [
     ("fastpi_batch_set_inner", c_int, [c_void_p, POINTER(Inner)]),
     ("fastpi_inner_applies", c_int, [POINTER(Inner), c_int64, c_int64]),
     ("fastpi_gaussian", c_int, [c_void_p, c_int64, ctypes.c_uint32, ctypes.c_uint32, c_void_p]),
+    ("fastpi_set_core_solver", c_int, [c_void_p, POINTER(CoreSolver)]),
+    ("fastpi_get_core_solver", c_int, [c_void_p, POINTER(CoreSolver)]),
+    ("fastpi_batch_set_core_solver", c_int, [c_void_p, POINTER(CoreSolver)]),
+    ("fastpi_last_core_routes", c_int, [c_void_p, c_void_p]),
+    ("fastpi_batch_core_routes", c_int, [c_void_p, c_void_p]),
     ("fastpi_last_error", ctypes.c_char_p, []),
 ]
 
@@ -364,6 +382,26 @@ class Handle:
         _check(load().fastpi_set_inner(self._h, ctypes.byref(Inner(int(mode), int(oversample), int(iters),
                                                                      int(seed)))))
 
+    def set_core_solver(self, **kw):
+        """Updates the core-solver fields given (mode, min_order, k_factor, max_frac, iters_fp64,
+        iters_mixed, orth_every, res_tol_fp64, res_tol_mixed)."""
+        c = CoreSolver()
+        _check(load().fastpi_get_core_solver(self._h, ctypes.byref(c)))
+        for key, v in kw.items():
+            setattr(c, key, v)
+        _check(load().fastpi_set_core_solver(self._h, ctypes.byref(c)))
+
+    def get_core_solver(self):
+        c = CoreSolver()
+        _check(load().fastpi_get_core_solver(self._h, ctypes.byref(c)))
+        return c.as_dict()
+
+    def last_core_routes(self):
+        """[row-update core, column-update core] route names of the last svd."""
+        out = np.zeros(2, dtype=np.int32)
+        _check(load().fastpi_last_core_routes(self._h, _ptr(out)))
+        return [ROUTES[int(x)] for x in out]
+
     def get_inner(self):
         out = Inner()
         _check(load().fastpi_get_inner(self._h, ctypes.byref(out)))
@@ -588,6 +626,19 @@ class Batch:
         sw = np.zeros((len(self.plans), 3), dtype=np.int32)
         load().fastpi_batch_sync(self._b, _ptr(st), _ptr(sw))
         return [STATUS.get(int(c), str(int(c))) for c in st], sw
+
+    def set_core_solver(self, **kw):
+        c = CoreSolver()
+        _check(load().fastpi_get_core_solver(self.handle._h, ctypes.byref(c)))
+        for key, v in kw.items():
+            setattr(c, key, v)
+        _check(load().fastpi_batch_set_core_solver(self._b, ctypes.byref(c)))
+
+    def core_routes(self):
+        """Per matrix [row-update, column-update] route names of the last svd."""
+        out = np.zeros((len(self.plans), 2), dtype=np.int32)
+        _check(load().fastpi_batch_core_routes(self._b, _ptr(out)))
+        return [[ROUTES[int(x)] for x in row] for row in out]
 
     def rotations(self):
         """Pair solves that ran in the last svd, per matrix: array [count, 2]."""

@@ -1083,6 +1083,84 @@ int fastpi_get_inner(const fastpi_handle* h, fastpi_inner* c) {
     return FASTPI_OK;
 }
 
+}  // extern "C"
+
+static CoreCfg core_from_c(const fastpi_core_solver& c) {
+    CoreCfg o;
+    o.mode = c.mode;
+    o.min_order = c.min_order;
+    o.k_factor = c.k_factor;
+    o.max_frac = c.max_frac;
+    o.iters_fp64 = c.iters_fp64;
+    o.iters_mixed = c.iters_mixed;
+    o.orth_every = c.orth_every;
+    o.res_tol_fp64 = c.res_tol_fp64;
+    o.res_tol_mixed = c.res_tol_mixed;
+    return o;
+}
+
+extern "C" {
+
+int fastpi_set_core_solver(fastpi_handle* h, const fastpi_core_solver* c) {
+    if (!h || !c) {
+        set_error("null pointer");
+        return FASTPI_EINVAL;
+    }
+    HIP_TRY(hipSetDevice(h->device));
+    return group_set_core(h->grp, core_from_c(*c), h->stream);
+}
+
+int fastpi_get_core_solver(const fastpi_handle* h, fastpi_core_solver* c) {
+    if (!h || !c) {
+        set_error("null pointer");
+        return FASTPI_EINVAL;
+    }
+    const CoreCfg& o = h->grp.core;
+    *c = fastpi_core_solver{};
+    c->mode = o.mode;
+    c->min_order = o.min_order;
+    c->k_factor = o.k_factor;
+    c->max_frac = o.max_frac;
+    c->iters_fp64 = o.iters_fp64;
+    c->iters_mixed = o.iters_mixed;
+    c->orth_every = o.orth_every;
+    c->res_tol_fp64 = o.res_tol_fp64;
+    c->res_tol_mixed = o.res_tol_mixed;
+    return FASTPI_OK;
+}
+
+int fastpi_batch_set_core_solver(fastpi_batch* b, const fastpi_core_solver* c) {
+    if (!batch_live(b)) return FASTPI_EINVAL;
+    if (!c) {
+        set_error("null pointer");
+        return FASTPI_EINVAL;
+    }
+    HIP_TRY(hipSetDevice(b->h->device));
+    return group_set_core(b->grp, core_from_c(*c), b->h->stream);
+}
+
+int fastpi_last_core_routes(const fastpi_handle* h, int32_t* out2) {
+    if (!h || !out2) {
+        set_error("null pointer");
+        return FASTPI_EINVAL;
+    }
+    out2[0] = h->inst.route[0];
+    out2[1] = h->inst.route[1];
+    return FASTPI_OK;
+}
+
+int fastpi_batch_core_routes(const fastpi_batch* b, int32_t* out) {
+    if (!b || !out) {
+        set_error("null pointer");
+        return FASTPI_EINVAL;
+    }
+    for (size_t i = 0; i < b->inst.size(); ++i) {
+        out[2 * i] = b->inst[i].route[0];
+        out[2 * i + 1] = b->inst[i].route[1];
+    }
+    return FASTPI_OK;
+}
+
 int fastpi_gaussian(fastpi_handle* h, int64_t count, uint32_t seed, uint32_t stream, double* out) {
     if (!h || count < 0 || (count > 0 && !out)) {
         set_error("bad handle, count or pointer");
@@ -1173,6 +1251,7 @@ int fastpi_batch_create(fastpi_batch** b, fastpi_handle* h, int64_t count,
     if (st == FASTPI_OK) {
         for (Instance& I : B->inst) B->grp.inst.push_back(&I);
         B->grp.inner = h->grp.inner;
+        B->grp.core = h->grp.core;
         B->grp.big_cost = h->grp.big_cost;
         B->grp.eig_tol = h->grp.eig_tol;
         st = group_build(B->grp, h->device, h->stream);

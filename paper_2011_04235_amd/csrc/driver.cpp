@@ -27,6 +27,8 @@ namespace {
 // route (about sqrt(q eps)); they are returned as zero and the matrix's status word takes
 // the floor warning bit.
 constexpr double kRelCut = 1e-7;
+// Philox key of the subspace core solver's starting block (stream = update: 0 row, 1 column)
+constexpr uint32_t kSubSeed = 0x5eed5eedu;
 
 int launch_status() {
     hipError_t e = hipGetLastError();
@@ -116,6 +118,20 @@ bool inner_valid(const InnerCfg& c) {
 bool inner_applies(const InnerCfg& c, int64_t t, int64_t q) {
     if (c.mode == 0 || t <= 0 || t + c.oversample >= q) return false;
     return c.mode == 2 || t < static_cast<int64_t>(std::ceil(0.3 * static_cast<double>(q)));
+}
+
+bool core_cfg_valid(const CoreCfg& c) {
+    return (c.mode == 0 || c.mode == 1) && c.min_order >= 64 && c.k_factor >= 1.0 && c.k_factor <= 8.0 &&
+           c.max_frac > 0.0 && c.max_frac <= 1.0 && c.iters_fp64 >= 1 && c.iters_fp64 <= 256 &&
+           c.iters_mixed >= 1 && c.iters_mixed <= 256 && c.orth_every >= 1 && c.orth_every <= 4 &&
+           c.res_tol_fp64 > 0 && c.res_tol_mixed > 0;
+}
+
+int64_t core_basis(const CoreCfg& c, int64_t t, int64_t q) {
+    if (c.mode == 0 || q < c.min_order || t <= 0) return 0;
+    const int64_t k = (static_cast<int64_t>(std::ceil(c.k_factor * static_cast<double>(t))) + 31) / 32 * 32;
+    if (k <= t || static_cast<double>(k) > c.max_frac * static_cast<double>(q)) return 0;
+    return k;
 }
 
 void instance_free(Instance& I, hipStream_t st) {
@@ -235,6 +251,7 @@ int instance_upload(Instance& I, const Plan& p, size_t ws_cap, hipStream_t st) {
 // group
 // ---------------------------------------------------------------------------------------
 static void free_rand(Group& g);
+static void free_sub(Group& g);
 
 void group_drop_graphs(Group& g) {
     for (hipGraphExec_t* e : {&g.g_front, &g.g_sw1, &g.g_front2, &g.g_sw2, &g.g_mid, &g.g_sw3, &g.g_back}) {
@@ -255,10 +272,101 @@ void group_free(Group& g) {
     eig_set_free(g.set2);
     eig_set_free(g.set3);
     free_rand(g);
+    free_sub(g);
     for (void* p : g.ballocs) hipFree(p);
     g.ballocs.clear();
     if (g.cap) hipStreamDestroy(g.cap);
     g.cap = nullptr;
+}
+
+static void free_sub(Group& g) {
+    for (int c = 0; c < 2; ++c) {
+        SubSet& S = g.sub[c];
+        eig_set_free(S.hset);
+        eig_set_free(S.fb);
+        if (S.dchol) hipFree(S.dchol);
+        if (S.flags) hipFree(S.flags);
+        if (S.host_flags) hipHostFree(S.host_flags);
+        for (void* p : S.allocs) hipFree(p);
+        S = SubSet{};
+    }
+}
+
+// Buffers of one core on the subspace route and its Rayleigh-Ritz eigensolver job.
+static int make_sub_core(Group& g, SubSet& S, int inst, int64_t q, int64_t t, int64_t k, const double* G,
+                         double* lam_out, double* vec_out, EigJob& hjob, hipStream_t st) {
+    const Instance& I = *g.inst[inst];
+    SubCore R;
+    R.inst = inst;
+    R.q = q;
+    R.t = t;
+    R.k = k;
+    R.kc = static_cast<int>((k + 31) / 32 * 32);
+    R.kp = 32;
+    while (R.kp < R.kc) R.kp *= 2;
+    R.G = G;
+    R.lam_out = lam_out;
+    R.vec_out = vec_out;
+    R.sp = gemm_tn_splits(k, k, q);
+    const int64_t kp = R.kp;
+    const size_t ed = eig_job_doubles(k, g.tune.gram_rows), ei = eig_job_ints(k);
+    const size_t doubles = static_cast<size_t>(2 * q * k + k * k + k * t + static_cast<int64_t>(R.sp) * k * k +
+                                               2 * kp * kp + kp * 32 + kp * kp / 2 + kp) + ed;
+    void* p = nullptr;
+    if (hipMalloc(&p, doubles * sizeof(double) + ei * sizeof(int)) != hipSuccess) {
+        set_error("device allocation failed (subspace core solver)");
+        return FASTPI_ENOMEM;
+    }
+    S.allocs.push_back(p);
+    double* b = static_cast<double*>(p);
+    R.Q = b;
+    R.Y = R.Q + q * k;
+    R.H = R.Y + q * k;
+    R.Wv = R.H + k * k;
+    R.part = R.Wv + k * t;
+    CholJob J{};
+    J.B = R.part + static_cast<int64_t>(R.sp) * k * k;
+    J.Linv = J.B + kp * kp;
+    J.Ld = J.Linv + kp * kp;
+    J.T = J.Ld + kp * 32;
+    J.dg = J.T + kp * kp / 2;
+    double* eigws = J.dg + kp;
+    int* eigiws = reinterpret_cast<int*>(eigws + ed);
+    J.k = static_cast<int>(k);
+    J.kc = R.kc;
+    J.kp = R.kp;
+    // B and Linv start as zeros, B and Ld hold the identity past k and kc (never rewritten)
+    HIP_TRY(hipMemsetAsync(J.B, 0, sizeof(double) * static_cast<size_t>(2 * kp * kp + kp * 32), st));
+    launch_fill_diag(J.B, kp, k, kp, 1.0, st);
+    for (int64_t b0 = R.kc; b0 < kp; b0 += 32) launch_fill_diag(J.Ld + b0 * 32, 32, 0, 32, 1.0, st);
+    S.cores.push_back(R);
+    S.chol.push_back(J);
+    S.max_kc = std::max(S.max_kc, R.kc);
+    S.max_kp = std::max(S.max_kp, R.kp);
+    // the projected matrix H may be overwritten by the factorisation (rebuilt every run)
+    hjob = eig_make_job(R.H, R.H, k, t, lam_out, R.Wv, eigws, eigiws, I.status, g.eig_tol, g.tune.gram_rows, inst);
+    return launch_status();
+}
+
+static int finish_sub_set(Group& g, SubSet& S, std::vector<EigJob>& hjobs, std::vector<EigJob>& fbjobs,
+                          hipStream_t st) {
+    const int nc = static_cast<int>(S.cores.size());
+    if (nc == 0) return FASTPI_OK;
+    void* p = nullptr;
+    if (hipMalloc(&p, sizeof(int) * (nc + 16)) != hipSuccess) return FASTPI_ENOMEM;
+    S.flags = static_cast<int*>(p);
+    if (hipHostMalloc(&p, sizeof(int) * (nc + 16), hipHostMallocDefault) != hipSuccess) return FASTPI_ENOMEM;
+    S.host_flags = static_cast<int*>(p);
+    for (int i = 0; i < nc; ++i) S.chol[i].flag = S.flags + i;
+    if (hipMalloc(&p, sizeof(CholJob) * nc) != hipSuccess) return FASTPI_ENOMEM;
+    S.dchol = static_cast<CholJob*>(p);
+    HIP_TRY(hipMemcpyAsync(S.dchol, S.chol.data(), sizeof(CholJob) * nc, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    // the Rayleigh-Ritz matrices are Grams of an orthonormal basis under G: the pivoted-Cholesky
+    // start as for every core; the fallback follows the schedule like the Jacobi cores
+    int rc = eig_set_create(S.hset, hjobs, g.tune.gram_rows, true, st);
+    if (rc == FASTPI_OK) rc = eig_set_create(S.fb, fbjobs, g.tune.gram_rows, g.tune.precond != 0, st);
+    return rc;
 }
 
 static void free_rand(Group& g) {
@@ -309,6 +417,8 @@ static int make_rand_core(Group& g, int inst, int64_t q, int64_t t, const double
 
 static int build_sets(Group& g, hipStream_t st) {
     free_rand(g);
+    free_sub(g);
+    std::vector<EigJob> hj[2], fj[2];
     eig_set_free(g.set1);
     for (void* p : g.ballocs) hipFree(p);
     g.ballocs.clear();
@@ -355,8 +465,17 @@ static int build_sets(Group& g, hipStream_t st) {
                 g.rcores[0].push_back(R);
                 jr[0].push_back(J);
             } else {
-                j2.push_back(eig_make_job(ws + I.o_g2, ws + I.o_g2, d.n1, d.s, ws + I.o_lam2, ws + I.o_v2,
-                                          ws + I.o_eig, I.iws, I.status, g.eig_tol, g.tune.gram_rows, tag));
+                const EigJob J = eig_make_job(ws + I.o_g2, ws + I.o_g2, d.n1, d.s, ws + I.o_lam2, ws + I.o_v2,
+                                              ws + I.o_eig, I.iws, I.status, g.eig_tol, g.tune.gram_rows, tag);
+                const int64_t k = core_basis(g.core, d.s, d.n1);
+                if (k > 0) {
+                    EigJob H;
+                    rc = make_sub_core(g, g.sub[0], tag, d.n1, d.s, k, ws + I.o_g2, ws + I.o_lam2, ws + I.o_v2, H, st);
+                    hj[0].push_back(H);
+                    fj[0].push_back(J);
+                } else {
+                    j2.push_back(J);
+                }
             }
         }
         if (rc == FASTPI_OK && q3 > 0 && d.r > 0) {
@@ -369,8 +488,17 @@ static int build_sets(Group& g, hipStream_t st) {
                 // its test matrix meets the columns of U2 Sigma2: fix their signs first
                 g.sign_v2[i] = 1;
             } else {
-                j3.push_back(eig_make_job(ws + I.o_g3, ws + I.o_g3, q3, d.r, ws + I.o_lam3, ws + I.o_vt,
-                                          ws + I.o_eig, I.iws, I.status, g.eig_tol, g.tune.gram_rows, tag));
+                const EigJob J = eig_make_job(ws + I.o_g3, ws + I.o_g3, q3, d.r, ws + I.o_lam3, ws + I.o_vt,
+                                              ws + I.o_eig, I.iws, I.status, g.eig_tol, g.tune.gram_rows, tag);
+                const int64_t k = core_basis(g.core, d.r, q3);
+                if (k > 0) {
+                    EigJob H;
+                    rc = make_sub_core(g, g.sub[1], tag, q3, d.r, k, ws + I.o_g3, ws + I.o_lam3, ws + I.o_vt, H, st);
+                    hj[1].push_back(H);
+                    fj[1].push_back(J);
+                } else {
+                    j3.push_back(J);
+                }
             }
         }
     }
@@ -388,8 +516,96 @@ static int build_sets(Group& g, hipStream_t st) {
     // itself they carry absolute errors of ~ld eps of the largest), whatever the schedule
     for (int c = 0; c < 2 && rc == FASTPI_OK; ++c)
         rc = eig_set_create(g.rset[c], jr[c], g.tune.gram_rows, true, st);
+    for (int c = 0; c < 2 && rc == FASTPI_OK; ++c) rc = finish_sub_set(g, g.sub[c], hj[c], fj[c], st);
     if (rc != FASTPI_OK) set_error("eigensolver set allocation failed");
     return rc;
+}
+
+// Subspace core solver for the cores of update c (0: row, 1: column) on that route: start
+// from a Gaussian block Q (k columns), then `iters` products Y = G Q, the block orthonormalised
+// (Cholesky QR: Y^T Y = L L^T, Q = Y L^-T) before every orth_every-th product; in the mixed
+// form the products by G and by L^-T run in FP32 (the Gram and the factorisation in FP64). Then two FP64 orthonormalisations,
+// H = Q^T G Q, its top t eigenpairs (W, lambda) by the block Jacobi eigensolver, vectors Q W.
+// Every core's result is checked (the residual of each pair, the rank of every Cholesky QR);
+// the host reads the checks and solves the failing set again with Jacobi on G.
+static int sub_run(Group& g, int c, const RunCfg& cfg, hipStream_t st) {
+    SubSet& S = g.sub[c];
+    S.fallbacks = 0;
+    if (S.cores.empty()) return FASTPI_OK;
+    const bool mixed = cfg.mixed;
+    const int iters = mixed ? g.core.iters_mixed : g.core.iters_fp64;
+    const double tol = mixed ? g.core.res_tol_mixed : g.core.res_tol_fp64;
+    const int nc = static_cast<int>(S.cores.size());
+    launch_fill_i32(S.flags, nc, 0, st);
+    for (SubCore& R : S.cores) launch_gauss(R.Q, R.q * R.k, kSubSeed, static_cast<uint32_t>(c), st);
+    bool in_q = true;
+    auto cur = [&](SubCore& R) { return in_q ? R.Q : R.Y; };
+    auto oth = [&](SubCore& R) { return in_q ? R.Y : R.Q; };
+    // the block's Gram matrix is always formed in FP64: an FP32 Gram of a block whose
+    // condition grew over two products can lose definiteness
+    auto orth = [&](bool fp32) {
+        for (int i = 0; i < nc; ++i) {
+            SubCore& R = S.cores[i];
+            launch_gemm_tn(cur(R), R.k, cur(R), R.k, R.k, R.k, R.q, S.chol[i].B, R.kp, nullptr, nullptr, R.part, R.sp,
+                           st, false);
+        }
+        launch_chol_inverse(S.dchol, nc, S.max_kc, S.max_kp, st);
+        for (int i = 0; i < nc; ++i) {
+            SubCore& R = S.cores[i];
+            launch_gemm_nt(cur(R), R.k, S.chol[i].Linv, R.kp, R.q, R.k, R.k, oth(R), R.k, st, fp32, nullptr);
+        }
+        in_q = !in_q;
+    };
+    auto apply = [&](bool fp32) {
+        for (SubCore& R : S.cores)
+            launch_gemm_nn(R.G, R.q, nullptr, cur(R), R.k, R.q, R.k, R.q, oth(R), R.k, nullptr, st, fp32);
+        in_q = !in_q;
+    };
+    for (int it = 0; it < iters; ++it) {
+        if (it % g.core.orth_every == 0) orth(mixed);
+        apply(mixed);
+    }
+    orth(false);
+    orth(false);
+    for (SubCore& R : S.cores) {
+        launch_gemm_nn(R.G, R.q, nullptr, cur(R), R.k, R.q, R.k, R.q, oth(R), R.k, nullptr, st, false);
+        launch_gemm_tn(cur(R), R.k, oth(R), R.k, R.k, R.k, R.q, R.H, R.k, nullptr, nullptr, R.part, R.sp, st, false);
+        launch_symmetrize(R.H, R.k, st);
+    }
+    eig_begin(S.hset, st);
+    int rc = eig_iterate(S.hset, cfg.max_sweeps, g.tune.inner_sweeps, st, cfg.copy_st, cfg.timer, nullptr);
+    if (rc != FASTPI_OK) return rc;
+    eig_end(S.hset, st);
+    for (int i = 0; i < nc; ++i) {
+        SubCore& R = S.cores[i];
+        launch_gemm_nn(cur(R), R.k, nullptr, R.Wv, R.t, R.q, R.t, R.k, R.vec_out, R.t, nullptr, st, false);
+        launch_gemm_nn(R.G, R.q, nullptr, R.vec_out, R.t, R.q, R.t, R.q, oth(R), R.t, nullptr, st, false);
+        launch_sub_residual(oth(R), R.vec_out, R.lam_out, R.q, R.t, tol, S.flags + i, st);
+    }
+    HIP_TRY(hipMemcpyAsync(S.host_flags, S.flags, sizeof(int) * nc, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int i = 0; i < nc; ++i) S.fallbacks += S.host_flags[i] != 0 ? 1 : 0;
+    if (S.fallbacks > 0) {
+        eig_begin(S.fb, st);
+        rc = eig_iterate(S.fb, cfg.max_sweeps, g.tune.inner_sweeps, st, cfg.copy_st, cfg.timer, nullptr);
+        if (rc != FASTPI_OK) return rc;
+        eig_end(S.fb, st);
+    }
+    return launch_status();
+}
+
+int group_set_core(Group& g, const CoreCfg& c, hipStream_t st) {
+    if (!core_cfg_valid(c)) {
+        set_error("invalid core-solver parameters");
+        return FASTPI_EINVAL;
+    }
+    g.core = c;
+    group_drop_graphs(g);
+    if (!g.inst.empty() && g.counter) {
+        HIP_TRY(hipStreamSynchronize(st));
+        return build_sets(g, st);
+    }
+    return FASTPI_OK;
 }
 
 // Randomized subspace iteration for the cores of update c (0: row, 1: column): Y = G Omega;
@@ -479,6 +695,7 @@ int group_build(Group& g, int device, hipStream_t st) {
     fresh.inst = g.inst;
     fresh.tune = g.tune;
     fresh.inner = g.inner;
+    fresh.core = g.core;
     fresh.big_cost = g.big_cost;
     fresh.eig_tol = g.eig_tol;
     group_free(g);
@@ -741,6 +958,25 @@ static void record_sweeps(Group& g) {
     for (Instance* I : g.inst) {
         I->sweeps[1] = I->sweeps[2] = 0;
         I->rotated[0] = I->rotated[1] = 0;
+        I->route[0] = I->route[1] = 0;
+    }
+    // cores on the subspace route: the sweeps and pair solves of their Rayleigh-Ritz Jacobi
+    // (and of the Jacobi run again on G when the check failed)
+    for (int k = 0; k < 2; ++k) {
+        const SubSet& S = g.sub[k];
+        for (int j = 0; j < S.hset.njobs; ++j) {
+            Instance* I = g.inst[S.hset.host[j].tag];
+            I->sweeps[1 + k] = S.hset.host_state[kEigStateWords * j + kEigStSweeps];
+            I->rotated[k] = S.hset.host_state[kEigStateWords * j + kEigStTotal];
+            I->route[k] = 1;
+        }
+        if (S.fallbacks > 0)
+            for (int j = 0; j < S.fb.njobs; ++j) {
+                Instance* I = g.inst[S.fb.host[j].tag];
+                I->sweeps[1 + k] += S.fb.host_state[kEigStateWords * j + kEigStSweeps];
+                I->rotated[k] += S.fb.host_state[kEigStateWords * j + kEigStTotal];
+                I->route[k] = 2;
+            }
     }
     const EigSet* sets[2] = {&g.set2, &g.set3};
     for (int k = 0; k < 2; ++k) {
@@ -753,6 +989,7 @@ static void record_sweeps(Group& g) {
         for (const RandCore& R : g.rcores[k]) {
             g.inst[R.inst]->sweeps[1 + k] = R.sweeps;
             g.inst[R.inst]->rotated[k] = R.rotated;
+            g.inst[R.inst]->route[k] = 3;
         }
     }
 }
@@ -772,11 +1009,13 @@ int group_svd(Group& g, const double* const* val, double* const* U, double* cons
             FASTPI_OK)
             return rc;
         if ((rc = rand_run(g, 0, c, st)) != FASTPI_OK) return rc;
+        if ((rc = sub_run(g, 0, c, st)) != FASTPI_OK) return rc;
         stage_mid(g, c, st);
         if ((rc = eig_iterate(g.set3, c.max_sweeps, g.tune.inner_sweeps, st, c.copy_st, c.timer, nullptr)) !=
             FASTPI_OK)
             return rc;
         if ((rc = rand_run(g, 1, c, st)) != FASTPI_OK) return rc;
+        if ((rc = sub_run(g, 1, c, st)) != FASTPI_OK) return rc;
         stage_back(g, U, S, V, c, st);
         record_sweeps(g);
         return launch_status();
@@ -826,10 +1065,12 @@ int group_svd(Group& g, const double* const* val, double* const* U, double* cons
     RunCfg eager = c;
     eager.timer = nullptr;
     if ((rc = rand_run(g, 0, eager, st)) != FASTPI_OK) return rc;
+    if ((rc = sub_run(g, 0, eager, st)) != FASTPI_OK) return rc;
     if ((rc = launch_graph(g, g.g_mid, st)) != FASTPI_OK) return rc;
     if ((rc = eig_iterate(g.set3, c.max_sweeps, g.tune.inner_sweeps, st, c.copy_st, nullptr, g.g_sw3)) != FASTPI_OK)
         return rc;
     if ((rc = rand_run(g, 1, eager, st)) != FASTPI_OK) return rc;
+    if ((rc = sub_run(g, 1, eager, st)) != FASTPI_OK) return rc;
     if ((rc = launch_graph(g, g.g_back, st)) != FASTPI_OK) return rc;
     record_sweeps(g);
     return launch_status();

@@ -63,6 +63,50 @@ struct RandCore {
     int64_t rotated = 0;
 };
 
+// Core solver of the two updates' exact branch: the existing block Jacobi on G, or subspace
+// iteration (Y = G Q with Cholesky-QR orthonormalisation every `orth_every` products, a
+// fixed number of products, a final double orthonormalisation and Rayleigh-Ritz through the
+// block Jacobi of the k x k projected matrix) where the basis k = ceil32(k_factor t) is small
+// against q. Each result is checked (residual of every kept pair against res_tol * lambda_1,
+// rank of every orthonormalisation); a core that fails the check is solved again by Jacobi.
+struct CoreCfg {
+    int mode = 1;             // 0: Jacobi for every core; 1: subspace iteration where it applies
+    int min_order = 1024;     // cores of smaller order stay on Jacobi
+    double k_factor = 2.0;
+    double max_frac = 0.65;   // and k <= max_frac * q
+    int iters_fp64 = 28;      // products by G (FP64 form)
+    int iters_mixed = 14;     // products by G in FP32 (mixed form)
+    int orth_every = 2;
+    double res_tol_fp64 = 1e-9;
+    double res_tol_mixed = 1e-5;
+};
+bool core_cfg_valid(const CoreCfg& c);
+// basis size of the subspace route for target t and order q, or 0 when the core stays on Jacobi
+int64_t core_basis(const CoreCfg& c, int64_t t, int64_t q);
+
+// One core on the subspace route (buffers in one allocation per core).
+struct SubCore {
+    int inst = 0;
+    int64_t q = 0, t = 0, k = 0;
+    int kc = 0, kp = 0, sp = 1;
+    const double* G = nullptr;
+    double *Q = nullptr, *Y = nullptr, *H = nullptr, *Wv = nullptr, *part = nullptr;
+    double* lam_out = nullptr;
+    double* vec_out = nullptr;
+};
+struct SubSet {
+    std::vector<SubCore> cores;
+    std::vector<CholJob> chol;      // host copy of the Cholesky-QR job table
+    CholJob* dchol = nullptr;
+    int* flags = nullptr;           // device, one per core
+    int* host_flags = nullptr;      // pinned
+    int max_kc = 0, max_kp = 0;
+    EigSet hset;                    // block Jacobi on the k x k Rayleigh-Ritz matrices
+    EigSet fb;                      // block Jacobi on G itself, for cores that fail the check
+    std::vector<void*> allocs;
+    int fallbacks = 0;              // cores solved again by Jacobi in the last run
+};
+
 struct DevicePlan {
     bool valid = false;
     int64_t m = 0, n = 0, nnz = 0, m1 = 0, n1 = 0, m2 = 0, n2 = 0, s_b = 0, s = 0, r = 0;
@@ -89,6 +133,8 @@ struct Instance {
     int* status = nullptr;   // device [0] status bits, [1] block sweeps (not owned)
     int32_t sweeps[3] = {0, 0, 0};
     int64_t rotated[2] = {0, 0};   // pairs rotated by the row- and column-update eigensolvers
+    int32_t route[2] = {0, 0};     // core route of the last run: 0 Jacobi, 1 subspace, 2 subspace
+                                   // then Jacobi (failed check), 3 randomized
     // offsets (in doubles) of the stage buffers inside ws
     int64_t o_vals = 0, o_u1 = 0, o_v1 = 0, o_sig1 = 0, o_g2 = 0, o_v2 = 0, o_lam2 = 0, o_sig2 = 0,
             o_inv2 = 0, o_u2 = 0, o_g3 = 0, o_vt = 0, o_lam3 = 0, o_sig3 = 0, o_inv3 = 0, o_c1 = 0,
@@ -131,6 +177,8 @@ struct Group {
     std::vector<char> sign_v2;         // per instance: fix the signs of V2 (randomized column update)
     EigSet rset[2];                    // their k x k eigensolves
     std::vector<void*> rallocs;
+    CoreCfg core;
+    SubSet sub[2];                     // cores of the row and column updates on the subspace route
     // captured graphs: stages before, between and after the two eigensolvers, and one
     // sweep of each eigensolver
     hipStream_t cap = nullptr;
@@ -145,6 +193,7 @@ void group_free(Group& g);
 void group_drop_graphs(Group& g);
 int group_set_tuning(Group& g, const Tuning& t, hipStream_t st);
 int group_set_inner(Group& g, const InnerCfg& c, hipStream_t st);
+int group_set_core(Group& g, const CoreCfg& c, hipStream_t st);
 // Computes U, S, V of every instance (arrays of device pointers, one per instance).
 int group_svd(Group& g, const double* const* val, double* const* U, double* const* S,
               double* const* V, const RunCfg& c);
