@@ -301,9 +301,7 @@ static int make_sub_core(Group& g, SubSet& S, int inst, int64_t q, int64_t t, in
     R.q = q;
     R.t = t;
     R.k = k;
-    R.kc = static_cast<int>((k + 31) / 32 * 32);
-    R.kp = 32;
-    while (R.kp < R.kc) R.kp *= 2;
+    R.kp = static_cast<int>((k + 63) / 64 * 64);
     R.G = G;
     R.lam_out = lam_out;
     R.vec_out = vec_out;
@@ -311,7 +309,7 @@ static int make_sub_core(Group& g, SubSet& S, int inst, int64_t q, int64_t t, in
     const int64_t kp = R.kp;
     const size_t ed = eig_job_doubles(k, g.tune.gram_rows), ei = eig_job_ints(k);
     const size_t doubles = static_cast<size_t>(2 * q * k + k * k + k * t + static_cast<int64_t>(R.sp) * k * k +
-                                               2 * kp * kp + kp * 32 + kp * kp / 2 + kp) + ed;
+                                               2 * kp * kp + kp) + ed;
     void* p = nullptr;
     if (hipMalloc(&p, doubles * sizeof(double) + ei * sizeof(int)) != hipSuccess) {
         set_error("device allocation failed (subspace core solver)");
@@ -326,22 +324,17 @@ static int make_sub_core(Group& g, SubSet& S, int inst, int64_t q, int64_t t, in
     R.part = R.Wv + k * t;
     CholJob J{};
     J.B = R.part + static_cast<int64_t>(R.sp) * k * k;
-    J.Linv = J.B + kp * kp;
-    J.Ld = J.Linv + kp * kp;
-    J.T = J.Ld + kp * 32;
-    J.dg = J.T + kp * kp / 2;
+    J.M = J.B + kp * kp;
+    J.dg = J.M + kp * kp;
     double* eigws = J.dg + kp;
     int* eigiws = reinterpret_cast<int*>(eigws + ed);
     J.k = static_cast<int>(k);
-    J.kc = R.kc;
     J.kp = R.kp;
-    // B and Linv start as zeros, B and Ld hold the identity past k and kc (never rewritten)
-    HIP_TRY(hipMemsetAsync(J.B, 0, sizeof(double) * static_cast<size_t>(2 * kp * kp + kp * 32), st));
+    // B and M start as zeros and B holds the identity past k (neither is rewritten there)
+    HIP_TRY(hipMemsetAsync(J.B, 0, sizeof(double) * static_cast<size_t>(2 * kp * kp), st));
     launch_fill_diag(J.B, kp, k, kp, 1.0, st);
-    for (int64_t b0 = R.kc; b0 < kp; b0 += 32) launch_fill_diag(J.Ld + b0 * 32, 32, 0, 32, 1.0, st);
     S.cores.push_back(R);
     S.chol.push_back(J);
-    S.max_kc = std::max(S.max_kc, R.kc);
     S.max_kp = std::max(S.max_kp, R.kp);
     // the projected matrix H may be overwritten by the factorisation (rebuilt every run)
     hjob = eig_make_job(R.H, R.H, k, t, lam_out, R.Wv, eigws, eigiws, I.status, g.eig_tol, g.tune.gram_rows, inst);
@@ -549,10 +542,10 @@ static int sub_run(Group& g, int c, const RunCfg& cfg, hipStream_t st) {
             launch_gemm_tn(cur(R), R.k, cur(R), R.k, R.k, R.k, R.q, S.chol[i].B, R.kp, nullptr, nullptr, R.part, R.sp,
                            st, false);
         }
-        launch_chol_inverse(S.dchol, nc, S.max_kc, S.max_kp, st);
+        launch_chol_inverse(S.dchol, nc, S.max_kp, st);
         for (int i = 0; i < nc; ++i) {
             SubCore& R = S.cores[i];
-            launch_gemm_nt(cur(R), R.k, S.chol[i].Linv, R.kp, R.q, R.k, R.k, oth(R), R.k, st, fp32, nullptr);
+            launch_gemm_nt(cur(R), R.k, S.chol[i].M, R.kp, R.q, R.k, R.k, oth(R), R.k, st, fp32, nullptr);
         }
         in_q = !in_q;
     };

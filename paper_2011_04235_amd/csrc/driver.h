@@ -88,7 +88,7 @@ int64_t core_basis(const CoreCfg& c, int64_t t, int64_t q);
 struct SubCore {
     int inst = 0;
     int64_t q = 0, t = 0, k = 0;
-    int kc = 0, kp = 0, sp = 1;
+    int kp = 0, sp = 1;
     const double* G = nullptr;
     double *Q = nullptr, *Y = nullptr, *H = nullptr, *Wv = nullptr, *part = nullptr;
     double* lam_out = nullptr;
@@ -100,7 +100,7 @@ struct SubSet {
     CholJob* dchol = nullptr;
     int* flags = nullptr;           // device, one per core
     int* host_flags = nullptr;      // pinned
-    int max_kc = 0, max_kp = 0;
+    int max_kp = 0;
     EigSet hset;                    // block Jacobi on the k x k Rayleigh-Ritz matrices
     EigSet fb;                      // block Jacobi on G itself, for cores that fail the check
     std::vector<void*> allocs;

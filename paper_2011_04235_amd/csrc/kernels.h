@@ -126,22 +126,19 @@ struct EigJob {
     int pad;
 };
 // Cholesky QR of the subspace core solver (subspace.hip): one job per core and call.
-// B (kp x kp row-major) holds Y^T Y in [0, k)^2 and the identity beyond (zero off the
-// diagonal, set once); the factorisation covers [0, kc), kc = k rounded up to 32, and writes L
-// below B's diagonal blocks, the diagonal blocks into Ld (kp x 32, identity past kc); Linv
-// (kp x kp, zero above the diagonal) receives L^-1; T (kp * kp / 2) is scratch of the
-// inverse, dg (kp) B's diagonal before the factorisation; flag (device int) is or-ed with 1
-// when a pivot shows numerical rank loss.
+// B (kp x kp row-major, kp = k rounded up to 64) holds Y^T Y in [0, k)^2 and the identity
+// beyond (zero off the diagonal, set once); its lower triangle is overwritten by L. M
+// (kp x kp, zero above the diagonal, set once) receives L^-1; dg (kp) is B's diagonal before
+// the factorisation; flag (device int) is or-ed with 1 when a pivot shows numerical rank
+// loss.
 struct CholJob {
     double* B;
-    double* Ld;
-    double* Linv;
-    double* T;
+    double* M;
     double* dg;
     int* flag;
-    int k, kc, kp, pad;
+    int k, kp;
 };
-void launch_chol_inverse(const CholJob* jobs, int njobs, int max_kc, int max_kp, hipStream_t st);
+void launch_chol_inverse(const CholJob* jobs, int njobs, int max_kp, hipStream_t st);
 // flag |= 1 when a column of R = G V (q x t) leaves lam_i V[:, i] by more than tol * lam_0
 void launch_sub_residual(const double* R, const double* V, const double* lam, int64_t q, int64_t t, double tol,
                          int* flag, hipStream_t st);

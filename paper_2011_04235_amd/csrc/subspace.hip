@@ -4,18 +4,18 @@
 // the final eigenpairs. Everything is batched over the cores of one update step ("jobs"):
 // one launch per kernel and panel for all of them.
 //
-// Cholesky: right-looking, panels of 32 columns, in place on the lower triangle of B
-// (kp x kp row-major, kp = 32 * 2^j >= k). Per panel, one kernel factors the 32 x 32
-// diagonal block in LDS (every workgroup of the launch does it, each then solves its own
-// chunk of rows below, x L11^T = b, so no second launch is needed for the panel's rows), and
-// a 64 x 64-tiled kernel subtracts L21 L21^T from the lower triangle of the trailing matrix.
-// A pivot whose square falls to kc * eps of its column's original diagonal marks the job
-// (the iterate lost rank numerically); the caller then takes the Jacobi route instead.
-//
-// Inverse L^-1: the 32 x 32 diagonal blocks are inverted in LDS, then recursive doubling
-// over levels s = 32, 64, ..: the off-diagonal block of a 2s x 2s diagonal block is
-// -D^-1 (C A^-1) (A^-1, D^-1 from the level below, C the block of L), two small GEMMs per
-// pair, batched over pairs and jobs. Rows and columns between k and kp are the identity.
+// Cholesky with the inverse accumulated on the way (B kp x kp row-major, kp = k rounded up
+// to 64, the identity past k): right-looking over panels of 64 columns, two launches each.
+//  * k_cq_panel(p): every workgroup loads the 64 x 64 diagonal block, factors it and inverts
+//    the factor in LDS, X = L_pp^-1 (blocked by 16); then its 64 x 64 tile: rows below the
+//    panel, L21 = B21 X^T (in place in B), or columns of block row p of M = L^-1,
+//    M_pj = -X W_pj (j < p), where W_pj = sum_{l<p} L_pl M_lj was accumulated in M's own
+//    storage; workgroup 0 writes M_pp = X.
+//  * k_cq_update(p): the trailing lower triangle of B minus L21 L21^T, and W_ij += L_ip M_pj
+//    for every block row i > p and column block j <= p (the first term, j = p, assigned).
+// A pivot whose square falls to kp * eps of its column's original diagonal marks the job
+// (the block lost rank numerically); the caller then takes the Jacobi route instead. M's
+// upper triangle stays zero, so Q = Y M^T is one GEMM.
 #include <cfloat>
 
 #include "device_common.h"
@@ -23,101 +23,246 @@
 
 namespace fastpi {
 
-constexpr int CP = 32;    // panel width / diagonal block of the inverse
-constexpr int CT = 64;    // tile of the trailing update and of the inverse products
+constexpr int CP = 64;    // panel width (= the wave width of the diagonal factorisation)
+constexpr int CT = 64;    // tile of the trailing products
+
+// rocPRIM's wave-level barrier: orders LDS accesses of one wave without a workgroup barrier
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // original diagonal of every job's B (the reference of the rank test)
 __global__ void k_chol_diag(const CholJob* __restrict__ jobs) {
     const CholJob& J = jobs[blockIdx.y];
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < J.kc; i += gridDim.x * blockDim.x)
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < J.kp; i += gridDim.x * blockDim.x)
         J.dg[i] = J.B[static_cast<int64_t>(i) * J.kp + i];
 }
 
-// Panel [c0, c0 + 32): factor the diagonal block, then rows [c0 + 32 + 256 * blockIdx.x, ..)
-// of the panel by forward substitution against L11.
-__global__ __launch_bounds__(256) void k_chol_panel(const CholJob* __restrict__ jobs, int c0) {
+// The panel's diagonal block D (64 x 64, in LDS) factored in place, L lower (blocked by 16:
+// one wave factors each 16 x 16 diagonal block wave-synchronously, all waves solve the rows
+// below it and update the trailing part), then X = L^-1 (16 x 16 diagonal blocks by one wave
+// each, off-diagonal blocks by block rows); returns the number of pivots that lost rank.
+__device__ int cq_factor_invert(double (*D)[CP + 1], double (*X)[CP + 1], double (*T)[CP + 1], const double* dg,
+                                double lim) {
+    const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
+    __shared__ int nbad;
+    if (tid == 0) nbad = 0;
+    for (int e = tid; e < CP * CP; e += 256) X[e / CP][e % CP] = 0.0;
+    __syncthreads();
+    for (int bb = 0; bb < CP; bb += 16) {
+        if (w == 0) {
+            int lost_here = 0;
+            for (int c = 0; c < 16; ++c) {
+                const int col = bb + c;
+                double sv = 0.0;
+                if (lane < 16 && lane >= c) {
+                    sv = D[bb + lane][col];
+                    for (int l = 0; l < c; ++l) sv -= D[bb + lane][bb + l] * D[col][bb + l];
+                }
+                const double sc = __shfl(sv, c);
+                const bool lost = !(sc > lim * dg[col]);
+                lost_here += lost ? 1 : 0;
+                const double piv = lost ? 1.0 : sqrt(sc);   // keeps the arithmetic finite
+                if (lane > c && lane < 16) D[bb + lane][col] = sv / piv;
+                if (lane == c) D[col][col] = piv;
+                wave_sync();
+            }
+            if (lane == 0 && lost_here) nbad += lost_here;
+        }
+        __syncthreads();
+        const int nr = CP - bb - 16;   // rows below the 16-block
+        if (tid < nr) {
+            const int i = bb + 16 + tid;
+            double x[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) x[j] = D[i][bb + j];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                double v = x[j];
+#pragma unroll
+                for (int l = 0; l < j; ++l) v -= x[l] * D[bb + j][bb + l];
+                x[j] = v / D[bb + j][bb + j];
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j) D[i][bb + j] = x[j];
+        }
+        __syncthreads();
+        for (int e = tid; e < nr * nr; e += 256) {
+            const int i = bb + 16 + e / nr, j = bb + 16 + e % nr;
+            if (j > i) continue;
+            double v = 0.0;
+#pragma unroll
+            for (int l = 0; l < 16; ++l) v += D[i][bb + l] * D[j][bb + l];
+            D[i][j] -= v;
+        }
+        __syncthreads();
+    }
+    // diagonal 16 x 16 blocks of X: wave w inverts block w, lane j < 16 its column j
+    {
+        const int bb = w * 16;
+        if (lane < 16) {
+            const int j = lane;
+            X[bb + j][bb + j] = 1.0 / D[bb + j][bb + j];
+            for (int i = j + 1; i < 16; ++i) {
+                double v = 0.0;
+                for (int l = j; l < i; ++l) v += D[bb + i][bb + l] * X[bb + l][bb + j];
+                X[bb + i][bb + j] = -v / D[bb + i][bb + i];
+            }
+        }
+    }
+    __syncthreads();
+    // block row bi: T_j = sum_{l=j}^{bi-1} L_{bi,l} X_{l,j}, then X_{bi,j} = -X_{bi,bi} T_j (j < bi)
+    for (int bi = 1; bi < 4; ++bi) {
+        const int r0 = bi * 16, n = bi * 16;   // columns [0, n) of block row bi
+        for (int e = tid; e < 16 * n; e += 256) {
+            const int r = e / n, cc = e % n;
+            const int lj = cc / 16 * 16;       // first block row l = block column of cc
+            double v = 0.0;
+            for (int l = lj; l < r0; ++l) v += D[r0 + r][l] * X[l][cc];
+            T[r][cc] = v;
+        }
+        __syncthreads();
+        for (int e = tid; e < 16 * n; e += 256) {
+            const int r = e / n, cc = e % n;
+            double v = 0.0;
+            for (int l = 0; l <= r; ++l) v += X[r0 + r][r0 + l] * T[l][cc];
+            X[r0 + r][cc] = -v;
+        }
+        __syncthreads();
+    }
+    return nbad;
+}
+
+__global__ __launch_bounds__(256) void k_cq_panel(const CholJob* __restrict__ jobs, int c0) {
     const CholJob& J = jobs[blockIdx.y];
-    const int kc = J.kc, kp = J.kp;
-    if (c0 >= kc) return;
-    const int tid = threadIdx.x;
-    const int row = c0 + CP + static_cast<int>(blockIdx.x) * 256 + tid;
-    if (blockIdx.x > 0 && c0 + CP + static_cast<int>(blockIdx.x) * 256 >= kc) return;
+    const int kp = J.kp;
+    if (c0 >= kp) return;
+    const int c1 = c0 + CP;
+    const int nrt = (kp - c1) / CT;   // row tiles of L21
+    const int nct = c0 / CT;          // column tiles of M's block row p
+    const int tile = static_cast<int>(blockIdx.x);
+    if (tile > 0 && tile >= nrt + nct) return;
     __shared__ double D[CP][CP + 1];
-    __shared__ int bad;
+    __shared__ double X[CP][CP + 1];
+    __shared__ double S[CP][CT + 1];
+    const int tid = threadIdx.x;
     double* B = J.B;
+    double* M = J.M;
     for (int e = tid; e < CP * CP; e += 256) {
         const int i = e / CP, j = e % CP;
         D[i][j] = B[static_cast<int64_t>(c0 + i) * kp + c0 + j];
     }
-    if (tid == 0) bad = 0;
     __syncthreads();
-    const double lim = static_cast<double>(kc) * DBL_EPSILON;
-    for (int c = 0; c < CP; ++c) {
-        if (tid == 0) {
-            double d = D[c][c];
-            if (!(d > lim * J.dg[c0 + c])) {
-                bad = 1;
-                d = 1.0;   // keeps the arithmetic finite; the job is marked
-            }
-            D[c][c] = sqrt(d);
-        }
-        __syncthreads();
-        if (tid > c && tid < CP) D[tid][c] /= D[c][c];
-        __syncthreads();
+    const int bad = cq_factor_invert(D, X, S, J.dg + c0, static_cast<double>(kp) * DBL_EPSILON);
+    if (tile == 0) {
         for (int e = tid; e < CP * CP; e += 256) {
             const int i = e / CP, j = e % CP;
-            if (j > c && i >= j) D[i][j] -= D[i][c] * D[j][c];
-        }
-        __syncthreads();
-    }
-    // L11 goes to the job's stack of diagonal blocks, not into B: the other workgroups of this
-    // launch still read B's diagonal block
-    if (blockIdx.x == 0) {
-        for (int e = tid; e < CP * CP; e += 256) {
-            const int i = e / CP, j = e % CP;
-            J.Ld[static_cast<int64_t>(c0 + i) * CP + j] = (j <= i) ? D[i][j] : 0.0;
+            M[static_cast<int64_t>(c0 + i) * kp + c0 + j] = X[i][j];
         }
         if (tid == 0 && bad) atomicOr(J.flag, 1);
     }
-    if (row >= kc) return;
-    double x[CP];
-    double* br = B + static_cast<int64_t>(row) * kp + c0;
+    if (tile >= nrt + nct) return;
+    const int tx = tid % 16, ty = tid / 16;
+    double acc[4][4] = {};
+    if (tile < nrt) {
+        // rows [r0, r0 + 64) of L21 = A21 X^T
+        const int r0 = c1 + tile * CT;
+        for (int e = tid; e < CT * CP; e += 256) {
+            const int r = e / CP, l = e % CP;
+            S[l][r] = B[static_cast<int64_t>(r0 + r) * kp + c0 + l];
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int l = 0; l < CP; ++l) {
+            double a[4], b[4];
 #pragma unroll
-    for (int j = 0; j < CP; ++j) x[j] = br[j];
+            for (int u = 0; u < 4; ++u) {
+                a[u] = S[l][ty * 4 + u];
+                b[u] = X[tx * 4 + u][l];
+            }
 #pragma unroll
-    for (int j = 0; j < CP; ++j) {
-        double v = x[j];
+            for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int l = 0; l < j; ++l) v -= x[l] * D[j][l];
-        x[j] = v / D[j][j];
+                for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                B[static_cast<int64_t>(r0 + ty * 4 + u) * kp + c0 + tx * 4 + v] = acc[u][v];
+    } else {
+        // columns [q0, q0 + 64) of M's block row p: M_pj = -X W_pj
+        const int q0 = (tile - nrt) * CT;
+        for (int e = tid; e < CP * CT; e += 256) {
+            const int l = e / CT, cc = e % CT;
+            S[l][cc] = M[static_cast<int64_t>(c0 + l) * kp + q0 + cc];
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int l = 0; l < CP; ++l) {
+            double a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a[u] = X[ty * 4 + u][l];
+                b[u] = S[l][tx * 4 + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                M[static_cast<int64_t>(c0 + ty * 4 + u) * kp + q0 + tx * 4 + v] = -acc[u][v];
     }
-#pragma unroll
-    for (int j = 0; j < CP; ++j) br[j] = x[j];
 }
 
-// B[i][j] -= sum_l L[i][c0+32+.. ] ... : the trailing lower triangle [c1, kc)^2, c1 = c0 + 32,
-// minus L21 L21^T with L21 = B[c1:kc, c0:c0+32]. Tiles (ti, tj), tj <= ti, numbered
-// row by row of the lower triangle.
-__global__ __launch_bounds__(256) void k_chol_update(const CholJob* __restrict__ jobs, int c0) {
+// After panel p: B[i][j] -= sum_l L[i][c0+l] L[j][c0+l] on the lower triangle of
+// [c1, kp)^2 (tiles numbered row by row), then W tiles: M[i][j] (+)= sum_l L[i][c0+l]
+// M[c0+l][j] for rows [c1, kp) and columns [0, c1) (assigned in columns [c0, c1)).
+__global__ __launch_bounds__(256) void k_cq_update(const CholJob* __restrict__ jobs, int c0) {
     const CholJob& J = jobs[blockIdx.y];
-    const int kc = J.kc, kp = J.kp;
+    const int kp = J.kp;
     const int c1 = c0 + CP;
-    if (c1 >= kc) return;
-    const int nt = (kc - c1 + CT - 1) / CT;
-    const int tri = static_cast<int>(blockIdx.x);
-    if (tri >= nt * (nt + 1) / 2) return;
-    int ti = static_cast<int>((sqrt(8.0 * tri + 1.0) - 1.0) * 0.5);
-    while ((ti + 1) * (ti + 2) / 2 <= tri) ++ti;
-    while (ti * (ti + 1) / 2 > tri) --ti;
-    const int tj = tri - ti * (ti + 1) / 2;
-    const int i0 = c1 + ti * CT, j0 = c1 + tj * CT;
-    __shared__ double Li[CP][CT + 1];
-    __shared__ double Lj[CP][CT + 1];
+    if (c1 >= kp) return;
+    const int nt = (kp - c1) / CT;                   // kp - c1 is a multiple of 64
+    const int ntri = nt * (nt + 1) / 2;
+    const int nw = nt * (c1 / CT);
+    int tile = static_cast<int>(blockIdx.x);
+    if (tile >= ntri + nw) return;
+    __shared__ double Ls[CP][CT + 1];   // L rows of the output tile's rows, transposed
+    __shared__ double Rs[CP][CT + 1];   // the right operand: L rows (B part) or M block row p
+    int i0, j0;
+    bool wpart = tile >= ntri;
     double* B = J.B;
-    for (int e = threadIdx.x; e < CP * CT; e += 256) {
-        const int t = e / CP, l = e % CP;
-        Li[l][t] = (i0 + t < kc) ? B[static_cast<int64_t>(i0 + t) * kp + c0 + l] : 0.0;
-        Lj[l][t] = (j0 + t < kc) ? B[static_cast<int64_t>(j0 + t) * kp + c0 + l] : 0.0;
+    double* M = J.M;
+    if (!wpart) {
+        int ti = static_cast<int>((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
+        while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
+        while (ti * (ti + 1) / 2 > tile) --ti;
+        const int tj = tile - ti * (ti + 1) / 2;
+        i0 = c1 + ti * CT;
+        j0 = c1 + tj * CT;
+        for (int e = threadIdx.x; e < CP * CT; e += 256) {
+            const int t = e / CP, l = e % CP;
+            Ls[l][t] = B[static_cast<int64_t>(i0 + t) * kp + c0 + l];
+            Rs[l][t] = B[static_cast<int64_t>(j0 + t) * kp + c0 + l];
+        }
+    } else {
+        tile -= ntri;
+        const int ncw = c1 / CT;
+        i0 = c1 + (tile / ncw) * CT;
+        j0 = (tile % ncw) * CT;
+        for (int e = threadIdx.x; e < CP * CT; e += 256) {
+            const int t = e / CP, l = e % CP;
+            Ls[l][t] = B[static_cast<int64_t>(i0 + t) * kp + c0 + l];
+            const int l2 = e / CT, t2 = e % CT;
+            Rs[l2][t2] = M[static_cast<int64_t>(c0 + l2) * kp + j0 + t2];
+        }
     }
     __syncthreads();
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
@@ -127,155 +272,52 @@ __global__ __launch_bounds__(256) void k_chol_update(const CholJob* __restrict__
         double a[4], b[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            a[u] = Li[l][ty * 4 + u];
-            b[u] = Lj[l][tx * 4 + u];
+            a[u] = Ls[l][ty * 4 + u];
+            b[u] = Rs[l][tx * 4 + u];
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
     }
+    if (!wpart) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int i = i0 + ty * 4 + u;
-        if (i >= kc) continue;
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + ty * 4 + u;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int j = j0 + tx * 4 + v;
-            if (j < kc && j <= i) B[static_cast<int64_t>(i) * kp + j] -= acc[u][v];
-        }
-    }
-}
-
-// Linv's 32 x 32 diagonal blocks: the inverse of L's (lower triangular) diagonal blocks
-// (the panels' stack Ld), one wave per block, lane j computing column j by forward
-// substitution. Blocks at or past kc hold the identity (Ld is the identity there).
-__global__ __launch_bounds__(64) void k_trinv_diag(const CholJob* __restrict__ jobs) {
-    const CholJob& J = jobs[blockIdx.y];
-    const int kp = J.kp;
-    const int b0 = static_cast<int>(blockIdx.x) * CP;
-    if (b0 >= kp) return;
-    __shared__ double L[CP][CP + 1];
-    __shared__ double X[CP][CP + 1];
-    const int tid = threadIdx.x;
-    for (int e = tid; e < CP * CP; e += 64) {
-        const int i = e / CP, j = e % CP;
-        L[i][j] = (j <= i) ? J.Ld[static_cast<int64_t>(b0 + i) * CP + j] : 0.0;
-    }
-    __syncthreads();
-    if (tid < CP) {
-        const int j = tid;
-        for (int i = 0; i < j; ++i) X[i][j] = 0.0;
-        X[j][j] = 1.0 / L[j][j];
-        for (int i = j + 1; i < CP; ++i) {
-            double v = 0.0;
-            for (int l = j; l < i; ++l) v += L[i][l] * X[l][j];
-            X[i][j] = -v / L[i][i];
-        }
-    }
-    __syncthreads();
-    for (int e = tid; e < CP * CP; e += 64) {
-        const int i = e / CP, j = e % CP;
-        J.Linv[static_cast<int64_t>(b0 + i) * kp + b0 + j] = X[i][j];
-    }
-}
-
-// One product of a doubling level s for every pair p (rows i1 = (2p+1) s, columns i0 = 2p s):
-// phase 0: T_p = L[i1:, i0:] Linv[i0:, i0:]; phase 1: Linv[i1:, i0:] = -Linv[i1:, i1:] T_p.
-// Pairs whose second block starts at or past kc keep a zero block.
-__global__ __launch_bounds__(256) void k_trinv_mul(const CholJob* __restrict__ jobs, int s, int phase) {
-    const CholJob& J = jobs[blockIdx.z];
-    const int kp = J.kp;
-    const int p = static_cast<int>(blockIdx.y);
-    const int i0 = 2 * p * s, i1 = i0 + s;
-    if (i1 >= J.kc || i1 + s > kp) return;
-    const int tps = (s + CT - 1) / CT;
-    const int tile = static_cast<int>(blockIdx.x);
-    if (tile >= tps * tps) return;
-    const int r0 = (tile / tps) * CT, q0 = (tile % tps) * CT;
-    const double* A;
-    const double* Bm;
-    int64_t lda = kp, ldb;
-    double* C;
-    int64_t ldc;
-    double alpha;
-    double* T = J.T + static_cast<int64_t>(p) * s * s;
-    if (phase == 0) {
-        A = J.B + static_cast<int64_t>(i1) * kp + i0;
-        Bm = J.Linv + static_cast<int64_t>(i0) * kp + i0;
-        ldb = kp;
-        C = T;
-        ldc = s;
-        alpha = 1.0;
-    } else {
-        A = J.Linv + static_cast<int64_t>(i1) * kp + i1;
-        Bm = T;
-        ldb = s;
-        C = J.Linv + static_cast<int64_t>(i1) * kp + i0;
-        ldc = kp;
-        alpha = -1.0;
-    }
-    __shared__ double As[16][CT + 1];
-    __shared__ double Bs[16][CT + 1];
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    double acc[4][4] = {};
-    for (int k0 = 0; k0 < s; k0 += 16) {
-        for (int e = threadIdx.x; e < 16 * CT; e += 256) {
-            const int kk = e % 16, ii = e / 16;
-            const int r = r0 + ii, k = k0 + kk;
-            As[kk][ii] = (r < s && k < s) ? A[r * lda + k] : 0.0;
-            const int kb = k0 + e / CT, jj = e % CT, c = q0 + jj;
-            Bs[e / CT][jj] = (kb < s && c < s) ? Bm[kb * ldb + c] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            double a[4], b[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                a[u] = As[kk][ty * 4 + u];
-                b[u] = Bs[kk][tx * 4 + u];
+            for (int v = 0; v < 4; ++v) {
+                const int j = j0 + tx * 4 + v;
+                if (j <= i) B[static_cast<int64_t>(i) * kp + j] -= acc[u][v];
             }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
         }
-        __syncthreads();
-    }
+    } else {
+        const bool first = j0 >= c0;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int r = r0 + ty * 4 + u;
-        if (r >= s) continue;
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + ty * 4 + u;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int c = q0 + tx * 4 + v;
-            if (c < s) C[r * ldc + c] = alpha * acc[u][v];
+            for (int v = 0; v < 4; ++v) {
+                const int j = j0 + tx * 4 + v;
+                double* o = M + static_cast<int64_t>(i) * kp + j;
+                *o = first ? acc[u][v] : *o + acc[u][v];
+            }
         }
     }
 }
 
-void launch_chol_inverse(const CholJob* jobs, int njobs, int max_kc, int max_kp, hipStream_t st) {
-    if (njobs <= 0 || max_kc <= 0) return;
+void launch_chol_inverse(const CholJob* jobs, int njobs, int max_kp, hipStream_t st) {
+    if (njobs <= 0 || max_kp <= 0) return;
     const unsigned nj = static_cast<unsigned>(njobs);
-    hipLaunchKernelGGL(k_chol_diag, dim3(static_cast<unsigned>((max_kc + 255) / 256), nj), dim3(256), 0, st, jobs);
-    for (int c0 = 0; c0 < max_kc; c0 += CP) {
-        const int below = max_kc - c0 - CP;
-        const unsigned chunks = static_cast<unsigned>(below > 0 ? (below + 255) / 256 : 1);
-        hipLaunchKernelGGL(k_chol_panel, dim3(chunks, nj), dim3(256), 0, st, jobs, c0);
-        if (below > 0) {
-            const int nt = (below + CT - 1) / CT;
-            hipLaunchKernelGGL(k_chol_update, dim3(static_cast<unsigned>(nt * (nt + 1) / 2), nj), dim3(256), 0, st,
-                               jobs, c0);
+    hipLaunchKernelGGL(k_chol_diag, dim3(static_cast<unsigned>((max_kp + 255) / 256), nj), dim3(256), 0, st, jobs);
+    for (int c0 = 0; c0 < max_kp; c0 += CP) {
+        const int c1 = c0 + CP;
+        const unsigned tiles = static_cast<unsigned>(std::max(1, (max_kp - c1) / CT + c0 / CT));
+        hipLaunchKernelGGL(k_cq_panel, dim3(tiles, nj), dim3(256), 0, st, jobs, c0);
+        if (c1 < max_kp) {
+            const int nt = (max_kp - c1) / CT;
+            const unsigned tiles = static_cast<unsigned>(nt * (nt + 1) / 2 + nt * (c1 / CT));
+            hipLaunchKernelGGL(k_cq_update, dim3(tiles, nj), dim3(256), 0, st, jobs, c0);
         }
-    }
-    hipLaunchKernelGGL(k_trinv_diag, dim3(static_cast<unsigned>(max_kp / CP), nj), dim3(64), 0, st, jobs);
-    for (int s = CP; s < max_kp; s *= 2) {
-        const int tps = (s + CT - 1) / CT;
-        const unsigned pairs = static_cast<unsigned>(max_kp / (2 * s));
-        for (int phase = 0; phase < 2; ++phase)
-            hipLaunchKernelGGL(k_trinv_mul, dim3(static_cast<unsigned>(tps * tps), pairs, nj), dim3(256), 0, st, jobs,
-                               s, phase);
     }
 }
 
