@@ -332,6 +332,16 @@ int fastpi_stage_output(fastpi_handle* h, int which, double* dst, int64_t count)
 int fastpi_syev_top(fastpi_handle* h, int64_t q, const double* G, int64_t t, double* vals,
                     double* vecs);
 
+/*
+ * Stage-level check of the matrix-core product used by the dense steps (the subspace core
+ * solver's products, the update and apply GEMMs): C = op(A) op(B) on the handle's stream,
+ * op(A) = A (M x K, lda) or, with ta, A stored K x M; op(B) = B (K x N, ldb) or, with tb,
+ * B stored N x K; all device FP64 row-major; fp32 = 1 rounds the operands to FP32 and
+ * accumulates in FP32 (the mixed form). Any shape is accepted (the kernel masks the edges).
+ */
+int fastpi_mfma_gemm(fastpi_handle* h, int ta, int tb, int64_t M, int64_t N, int64_t K, const double* A,
+                     int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc, int fp32);
+
 /* Waits for the handle's stream and reports device-side failures of the last fastpi_svd
  * (FASTPI_ENONFINITE: non-finite input; FASTPI_ENOCONV: a Jacobi sweep cap reached), or the
  * warning FASTPI_WFLOOR (a kept singular value under the Gram floor, see fastpi_svd). */
@@ -353,7 +363,8 @@ int fastpi_last_rotations(fastpi_handle* h, int64_t* out2);
  * pair on the handle's stream (each timed launch costs an extra event record).
  * kind: 0 = eigensolver partial Gram, 1 = eigensolver pair solve, 2 = eigensolver column
  * update, 3 = block SVD launches, 4 = the label SpMM of fastpi_apply_sparse (both passes),
- * 5 = fastpi_topk_hits, 6 = the transposed-B GEMM of fastpi_apply_sparse, -1 = off.
+ * 5 = fastpi_topk_hits, 6 = the transposed-B GEMM of fastpi_apply_sparse, 7 = the products by G
+ * of the subspace core solver (fastpi_set_core_solver), -1 = off.
  * Starting discards earlier timings.
  */
 int fastpi_timing_start(fastpi_handle* h, int kind);

@@ -150,6 +150,8 @@ SIGNATURES = [
     ("fastpi_batch_set_core_solver", c_int, [c_void_p, POINTER(CoreSolver)]),
     ("fastpi_last_core_routes", c_int, [c_void_p, c_void_p]),
     ("fastpi_batch_core_routes", c_int, [c_void_p, c_void_p]),
+    ("fastpi_mfma_gemm", c_int, [c_void_p, c_int, c_int, c_int64, c_int64, c_int64, c_void_p, c_int64, c_void_p,
+                                 c_int64, c_void_p, c_int64, c_int]),
     ("fastpi_last_error", ctypes.c_char_p, []),
 ]
 
@@ -452,6 +454,17 @@ class Handle:
         _check(load().fastpi_stage_output(self._h, int(which), _dptr(out), out.numel()))
         return out
 
+    def mfma_gemm(self, A, B, ta=False, tb=False, fp32=False, out=None):
+        """C = op(A) op(B) by the library's matrix-core product (a stage-level check)."""
+        torch = self.torch
+        M = A.shape[1] if ta else A.shape[0]
+        K = A.shape[0] if ta else A.shape[1]
+        N = B.shape[0] if tb else B.shape[1]
+        C = torch.empty((M, N), dtype=torch.float64, device=self.device) if out is None else out
+        _check(load().fastpi_mfma_gemm(self._h, int(ta), int(tb), M, N, K, _dptr(A), A.stride(0), _dptr(B),
+                                       B.stride(0), _dptr(C), C.stride(0), int(fp32)))
+        return C
+
     def syev_top(self, G, t):
         torch = self.torch
         q = G.shape[0]
@@ -474,7 +487,7 @@ class Handle:
         return out.tolist()
 
     KERNELS = {"eig_gram": 0, "eig_solve": 1, "eig_update": 2, "block_svd": 3, "label_spmm": 4,
-               "topk": 5, "gemm_nt": 6}
+               "topk": 5, "gemm_nt": 6, "sub_gemm": 7}
 
     def last_rotations(self):
         """Pair solves that ran in the last svd: [row-update core, column-update core]."""

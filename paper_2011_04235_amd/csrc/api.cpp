@@ -852,6 +852,18 @@ int fastpi_syev_top(fastpi_handle* h, int64_t q, const double* G, int64_t t, dou
     return check_launch();
 }
 
+int fastpi_mfma_gemm(fastpi_handle* h, int ta, int tb, int64_t M, int64_t N, int64_t K, const double* A,
+                     int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc, int fp32) {
+    if (!h || M < 0 || N < 0 || K < 0 || (M * N > 0 && (!C || ldc < N)) ||
+        (M * N * K > 0 && (!A || !B || lda < (ta ? M : K) || ldb < (tb ? K : N)))) {
+        set_error("bad handle, shape, leading dimension or pointer");
+        return FASTPI_EINVAL;
+    }
+    HIP_TRY(hipSetDevice(h->device));
+    launch_mfma_gemm(ta != 0, tb != 0, A, lda, B, ldb, M, N, K, C, ldc, 1, 0, h->stream, fp32 != 0);
+    return check_launch();
+}
+
 int fastpi_sync(fastpi_handle* h) {
     if (!h) {
         set_error("null handle");

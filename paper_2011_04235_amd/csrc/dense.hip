@@ -159,10 +159,20 @@ int gemm_tn_splits(int64_t M, int64_t N, int64_t K) {
     return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(splits, 256)));
 }
 
+// products big enough for the 128 x 128 matrix-core tiles go there
+static bool use_mfma(int64_t M, int64_t N, int64_t K) { return M >= 128 && N >= 64 && K >= 64; }
+
 void launch_gemm_tn(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M,
                     int64_t N, int64_t K, double* C, int64_t ldc, const double* rs,
                     const double* cs, double* part, int nsplit, hipStream_t st, bool fp32) {
     if (M <= 0 || N <= 0) return;
+    if (use_mfma(M, N, K)) {
+        launch_mfma_gemm(true, false, A, lda, B, ldb, M, N, K, part, N, nsplit, M * N, st, fp32);
+        const int64_t n = M * N;
+        hipLaunchKernelGGL(k_reduce_parts, dim3(static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 8192))),
+                           dim3(256), 0, st, part, nsplit, M, N, C, ldc, rs, cs);
+        return;
+    }
     const int64_t kchunk = ((K + nsplit - 1) / nsplit + TK - 1) / TK * TK;
     dim3 grid(static_cast<unsigned>((M + TM - 1) / TM), static_cast<unsigned>((N + TN - 1) / TN),
               static_cast<unsigned>(nsplit));
@@ -179,8 +189,12 @@ void launch_gemm_tn(const double* A, int64_t lda, const double* B, int64_t ldb, 
 
 void launch_gemm_nn(const double* A, int64_t lda, const int* arow, const double* B, int64_t ldb,
                     int64_t M, int64_t N, int64_t K, double* C, int64_t ldc, const int* crow,
-                    hipStream_t st, bool fp32) {
+                    hipStream_t st, bool fp32, KernelTimer* timer, int kind) {
     if (M <= 0 || N <= 0) return;
+    if (!arow && !crow && use_mfma(M, N, K)) {
+        launch_mfma_gemm(false, false, A, lda, B, ldb, M, N, K, C, ldc, 1, 0, st, fp32, timer, kind);
+        return;
+    }
     dim3 grid(static_cast<unsigned>((M + TM - 1) / TM), static_cast<unsigned>((N + TN - 1) / TN));
     if (fp32)
         hipLaunchKernelGGL((k_gemm_nn<float, false>), grid, dim3(256), 0, st, A, lda, arow, B, ldb, M, N, K, C,
@@ -193,6 +207,10 @@ void launch_gemm_nn(const double* A, int64_t lda, const int* arow, const double*
 void launch_gemm_nt(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M, int64_t N,
                     int64_t K, double* C, int64_t ldc, hipStream_t st, bool fp32, KernelTimer* timer) {
     if (M <= 0 || N <= 0) return;
+    if (use_mfma(M, N, K)) {
+        launch_mfma_gemm(false, true, A, lda, B, ldb, M, N, K, C, ldc, 1, 0, st, fp32, timer, KT_GEMM_NT);
+        return;
+    }
     dim3 grid(static_cast<unsigned>((M + TM - 1) / TM), static_cast<unsigned>((N + TN - 1) / TN));
     const int* none = nullptr;
     if (fp32)

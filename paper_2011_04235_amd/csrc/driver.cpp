@@ -551,7 +551,8 @@ static int sub_run(Group& g, int c, const RunCfg& cfg, hipStream_t st) {
     };
     auto apply = [&](bool fp32) {
         for (SubCore& R : S.cores)
-            launch_gemm_nn(R.G, R.q, nullptr, cur(R), R.k, R.q, R.k, R.q, oth(R), R.k, nullptr, st, fp32);
+            launch_gemm_nn(R.G, R.q, nullptr, cur(R), R.k, R.q, R.k, R.q, oth(R), R.k, nullptr, st, fp32, cfg.timer,
+                           KT_SUB_GEMM);
         in_q = !in_q;
     };
     for (int it = 0; it < iters; ++it) {

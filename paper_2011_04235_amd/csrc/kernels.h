@@ -37,7 +37,8 @@ enum KernelKind {
     KT_LABEL_SPMM = 4,
     KT_TOPK = 5,
     KT_GEMM_NT = 6,
-    KT_LAST = KT_GEMM_NT
+    KT_SUB_GEMM = 7,   // products by G of the subspace core solver
+    KT_LAST = KT_SUB_GEMM
 };
 struct KernelTimer {
     int target = KT_NONE;
@@ -77,6 +78,13 @@ struct KernelTimer {
         else                                                                                        \
             hipLaunchKernelGGL(kernel, grid, block, shmem, st, __VA_ARGS__);                        \
     } while (0)
+
+// C = op(A) op(B) on the matrix cores (mfma_gemm.hip): op(A) = A (M x K) or, with ta, A stored
+// K x M; op(B) = B (K x N) or, with tb, B stored N x K; FP64, or FP32 operands and
+// accumulation with fp32; nsplit > 1 writes partial products of K chunks at C + z cstride.
+void launch_mfma_gemm(bool ta, bool tb, const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M,
+                      int64_t N, int64_t K, double* C, int64_t ldc, int nsplit, int64_t cstride, hipStream_t st,
+                      bool fp32, KernelTimer* timer = nullptr, int kind = KT_NONE);
 
 void launch_fill(double* p, int64_t n, double v, hipStream_t st);
 void launch_fill_i32(int* p, int64_t n, int v, hipStream_t st);
@@ -194,7 +202,7 @@ void launch_gemm_tn(const double* A, int64_t lda, const double* B, int64_t ldb, 
                     const double* cs, double* part, int nsplit, hipStream_t st, bool fp32 = false);
 void launch_gemm_nn(const double* A, int64_t lda, const int* arow, const double* B, int64_t ldb,
                     int64_t M, int64_t N, int64_t K, double* C, int64_t ldc, const int* crow,
-                    hipStream_t st, bool fp32 = false);
+                    hipStream_t st, bool fp32 = false, KernelTimer* timer = nullptr, int kind = KT_NONE);
 void launch_gemm_nt(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M, int64_t N,
                     int64_t K, double* C, int64_t ldc, hipStream_t st, bool fp32 = false,
                     KernelTimer* timer = nullptr);

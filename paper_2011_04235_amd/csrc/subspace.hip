@@ -48,7 +48,9 @@ __device__ int cq_factor_invert(double (*D)[CP + 1], double (*X)[CP + 1], double
                                 double lim) {
     const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
     __shared__ int nbad;
+    __shared__ double lims[CP];   // rank-test threshold of every pivot (no global load in the chain)
     if (tid == 0) nbad = 0;
+    if (tid < CP) lims[tid] = lim * dg[tid];
     for (int e = tid; e < CP * CP; e += 256) X[e / CP][e % CP] = 0.0;
     __syncthreads();
     for (int bb = 0; bb < CP; bb += 16) {
@@ -62,7 +64,7 @@ __device__ int cq_factor_invert(double (*D)[CP + 1], double (*X)[CP + 1], double
                     for (int l = 0; l < c; ++l) sv -= D[bb + lane][bb + l] * D[col][bb + l];
                 }
                 const double sc = __shfl(sv, c);
-                const bool lost = !(sc > lim * dg[col]);
+                const bool lost = !(sc > lims[col]);
                 lost_here += lost ? 1 : 0;
                 const double piv = lost ? 1.0 : sqrt(sc);   // keeps the arithmetic finite
                 if (lane > c && lane < 16) D[bb + lane][col] = sv / piv;

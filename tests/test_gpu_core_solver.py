@@ -160,3 +160,27 @@ def test_batch_mixing_routes_equals_single_runs(env):
         for p, a, (Ub, Sb, Vb) in zip(probs, alphas, out):
             _, _, _, U, S, V, _ = run(torch, fp, p, a, 0.01)
             assert np.array_equal(to_np(Sb), S) and np.array_equal(to_np(Ub), U) and np.array_equal(to_np(Vb), V)
+
+
+@pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_matrix_core_product(env, ta, tb, fp32):
+    """The matrix-core product against numpy on ragged shapes (edges inside a 128 x 128 tile
+    and a 16-deep slice), every operand orientation, FP64 and FP32; a strided output."""
+    torch, fp = env
+    dev = torch.device("cuda", 0)
+    h = fp.Handle(0)
+    rng = np.random.default_rng(7)
+    for (M, N, K) in [(1, 1, 1), (130, 70, 33), (257, 300, 129), (64, 129, 1000)]:
+        A = rng.standard_normal((K, M) if ta else (M, K))
+        B = rng.standard_normal((N, K) if tb else (K, N))
+        ref = (A.T if ta else A) @ (B.T if tb else B)
+        Cbig = torch.full((M, N + 5), 7.0, dtype=torch.float64, device=dev)
+        C = h.mfma_gemm(torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev), ta=ta, tb=tb, fp32=fp32,
+                        out=Cbig[:, :N])
+        torch.cuda.synchronize()
+        got = C.cpu().numpy()
+        err = np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300)
+        tol = 1e-5 if fp32 else 1e-13
+        assert err <= tol, (M, N, K, ta, tb, fp32, err)
+        assert np.all(Cbig[:, N:].cpu().numpy() == 7.0)
