@@ -159,6 +159,13 @@ int gemm_tn_splits(int64_t M, int64_t N, int64_t K) {
     return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(splits, 256)));
 }
 
+void launch_sum_parts(const double* part, int nsplit, int64_t M, int64_t N, double* C, int64_t ldc, hipStream_t st) {
+    const int64_t n = M * N;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_reduce_parts, dim3(static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 8192))), dim3(256),
+                       0, st, part, nsplit, M, N, C, ldc, nullptr, nullptr);
+}
+
 // products big enough for the 128 x 128 matrix-core tiles go there
 static bool use_mfma(int64_t M, int64_t N, int64_t K) { return M >= 128 && N >= 64 && K >= 64; }
 

@@ -306,10 +306,16 @@ static int make_sub_core(Group& g, SubSet& S, int inst, int64_t q, int64_t t, in
     R.lam_out = lam_out;
     R.vec_out = vec_out;
     R.sp = gemm_tn_splits(k, k, q);
+    // the q x k products by G fill the chip through a K split when their 128 x 128 tiles are
+    // fewer than two per compute unit
+    const int64_t tiles = ((q + 127) / 128) * ((k + 127) / 128);
+    R.gsplit = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((2 * g.ncu + tiles - 1) / tiles, q / 256)));
     const int64_t kp = R.kp;
     const size_t ed = eig_job_doubles(k, g.tune.gram_rows), ei = eig_job_ints(k);
     const size_t doubles = static_cast<size_t>(2 * q * k + k * k + k * t + static_cast<int64_t>(R.sp) * k * k +
-                                               2 * kp * kp + kp) + ed;
+                                               2 * kp * kp + kp +
+                                               (R.gsplit > 1 ? static_cast<int64_t>(R.gsplit) * q * k : 0)) +
+                           ed;
     void* p = nullptr;
     if (hipMalloc(&p, doubles * sizeof(double) + ei * sizeof(int)) != hipSuccess) {
         set_error("device allocation failed (subspace core solver)");
@@ -326,7 +332,8 @@ static int make_sub_core(Group& g, SubSet& S, int inst, int64_t q, int64_t t, in
     J.B = R.part + static_cast<int64_t>(R.sp) * k * k;
     J.M = J.B + kp * kp;
     J.dg = J.M + kp * kp;
-    double* eigws = J.dg + kp;
+    R.gpart = R.gsplit > 1 ? J.dg + kp : nullptr;
+    double* eigws = J.dg + kp + (R.gsplit > 1 ? static_cast<int64_t>(R.gsplit) * q * k : 0);
     int* eigiws = reinterpret_cast<int*>(eigws + ed);
     J.k = static_cast<int>(k);
     J.kp = R.kp;
@@ -550,9 +557,16 @@ static int sub_run(Group& g, int c, const RunCfg& cfg, hipStream_t st) {
         in_q = !in_q;
     };
     auto apply = [&](bool fp32) {
-        for (SubCore& R : S.cores)
-            launch_gemm_nn(R.G, R.q, nullptr, cur(R), R.k, R.q, R.k, R.q, oth(R), R.k, nullptr, st, fp32, cfg.timer,
-                           KT_SUB_GEMM);
+        for (SubCore& R : S.cores) {
+            if (R.gsplit > 1) {
+                launch_mfma_gemm(false, false, R.G, R.q, cur(R), R.k, R.q, R.k, R.q, R.gpart, R.k, R.gsplit, R.q * R.k,
+                                 st, fp32, cfg.timer, KT_SUB_GEMM);
+                launch_sum_parts(R.gpart, R.gsplit, R.q, R.k, oth(R), R.k, st);
+            } else {
+                launch_gemm_nn(R.G, R.q, nullptr, cur(R), R.k, R.q, R.k, R.q, oth(R), R.k, nullptr, st, fp32, cfg.timer,
+                               KT_SUB_GEMM);
+            }
+        }
         in_q = !in_q;
     };
     for (int it = 0; it < iters; ++it) {

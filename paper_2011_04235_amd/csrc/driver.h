@@ -89,8 +89,9 @@ struct SubCore {
     int inst = 0;
     int64_t q = 0, t = 0, k = 0;
     int kp = 0, sp = 1;
+    int gsplit = 1;             // K split of the products by G (partials in gpart)
     const double* G = nullptr;
-    double *Q = nullptr, *Y = nullptr, *H = nullptr, *Wv = nullptr, *part = nullptr;
+    double *Q = nullptr, *Y = nullptr, *H = nullptr, *Wv = nullptr, *part = nullptr, *gpart = nullptr;
     double* lam_out = nullptr;
     double* vec_out = nullptr;
 };

@@ -86,6 +86,9 @@ void launch_mfma_gemm(bool ta, bool tb, const double* A, int64_t lda, const doub
                       int64_t N, int64_t K, double* C, int64_t ldc, int nsplit, int64_t cstride, hipStream_t st,
                       bool fp32, KernelTimer* timer = nullptr, int kind = KT_NONE);
 
+// C[i * ldc + j] = sum_z part[z][i][j] (z < nsplit, fixed order)
+void launch_sum_parts(const double* part, int nsplit, int64_t M, int64_t N, double* C, int64_t ldc, hipStream_t st);
+
 void launch_fill(double* p, int64_t n, double v, hipStream_t st);
 void launch_fill_i32(int* p, int64_t n, int v, hipStream_t st);
 void launch_gather(const double* val, const int64_t* dst0, const int64_t* dst1, int64_t nnz,
