@@ -41,48 +41,35 @@ __global__ void k_chol_diag(const CholJob* __restrict__ jobs) {
 }
 
 // The panel's diagonal block D (64 x 64, in LDS) factored in place, L lower (blocked by 16:
-// the lanes 0..15 of wave 0 factor each 16 x 16 diagonal block from registers, a row per
-// lane, the pivot row's entries broadcast by shuffles; all waves then solve the rows below
-// it and update the trailing part), then X = L^-1 (16 x 16 diagonal blocks by one wave each,
-// a column per lane; off-diagonal blocks by block rows). Every inner loop has a static trip
-// count (predicated), so its LDS loads issue together. Returns the pivots that lost rank.
+// one wave factors each 16 x 16 diagonal block wave-synchronously, all waves solve the rows
+// below it and update the trailing part), then X = L^-1 (16 x 16 diagonal blocks by one wave
+// each, off-diagonal blocks by block rows); returns the number of pivots that lost rank.
 __device__ int cq_factor_invert(double (*D)[CP + 1], double (*X)[CP + 1], double (*T)[CP + 1], const double* dg,
                                 double lim) {
     const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
     __shared__ int nbad;
-    __shared__ double lims[CP];   // rank-test threshold of every pivot
-    __shared__ double dinv[CP];   // 1 / L[c][c]
+    __shared__ double lims[CP];   // rank-test threshold of every pivot (no global load in the chain)
     if (tid == 0) nbad = 0;
     if (tid < CP) lims[tid] = lim * dg[tid];
     for (int e = tid; e < CP * CP; e += 256) X[e / CP][e % CP] = 0.0;
     __syncthreads();
     for (int bb = 0; bb < CP; bb += 16) {
         if (w == 0) {
-            const int li = lane < 16 ? lane : 15;
-            double row[16];
-#pragma unroll
-            for (int l = 0; l < 16; ++l) row[l] = D[bb + li][bb + l];
             int lost_here = 0;
-#pragma unroll
             for (int c = 0; c < 16; ++c) {
-                double sv = row[c];
-#pragma unroll
-                for (int l = 0; l < c; ++l) sv -= row[l] * __shfl(row[l], c);
+                const int col = bb + c;
+                double sv = 0.0;
+                if (lane < 16 && lane >= c) {
+                    sv = D[bb + lane][col];
+                    for (int l = 0; l < c; ++l) sv -= D[bb + lane][bb + l] * D[col][bb + l];
+                }
                 const double sc = __shfl(sv, c);
-                const bool lost = !(sc > lims[bb + c]);
+                const bool lost = !(sc > lims[col]);
                 lost_here += lost ? 1 : 0;
                 const double piv = lost ? 1.0 : sqrt(sc);   // keeps the arithmetic finite
-                const double rp = 1.0 / piv;
-                if (lane > c) row[c] = sv * rp;
-                if (lane == c) {
-                    row[c] = piv;
-                    dinv[bb + c] = rp;
-                }
-            }
-            if (lane < 16) {
-#pragma unroll
-                for (int l = 0; l < 16; ++l)
-                    if (l <= lane) D[bb + lane][bb + l] = row[l];
+                if (lane > c && lane < 16) D[bb + lane][col] = sv / piv;
+                if (lane == c) D[col][col] = piv;
+                wave_sync();
             }
             if (lane == 0 && lost_here) nbad += lost_here;
         }
@@ -98,7 +85,7 @@ __device__ int cq_factor_invert(double (*D)[CP + 1], double (*X)[CP + 1], double
                 double v = x[j];
 #pragma unroll
                 for (int l = 0; l < j; ++l) v -= x[l] * D[bb + j][bb + l];
-                x[j] = v * dinv[bb + j];
+                x[j] = v / D[bb + j][bb + j];
             }
 #pragma unroll
             for (int j = 0; j < 16; ++j) D[i][bb + j] = x[j];
@@ -119,16 +106,12 @@ __device__ int cq_factor_invert(double (*D)[CP + 1], double (*X)[CP + 1], double
         const int bb = w * 16;
         if (lane < 16) {
             const int j = lane;
-            double x[16];
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
+            X[bb + j][bb + j] = 1.0 / D[bb + j][bb + j];
+            for (int i = j + 1; i < 16; ++i) {
                 double v = 0.0;
-#pragma unroll
-                for (int l = 0; l < i; ++l) v += (l >= j) ? D[bb + i][bb + l] * x[l] : 0.0;
-                x[i] = (i < j) ? 0.0 : (i == j ? dinv[bb + i] : -v * dinv[bb + i]);
+                for (int l = j; l < i; ++l) v += D[bb + i][bb + l] * X[bb + l][bb + j];
+                X[bb + i][bb + j] = -v / D[bb + i][bb + i];
             }
-#pragma unroll
-            for (int i = 0; i < 16; ++i) X[bb + i][bb + j] = x[i];
         }
     }
     __syncthreads();
@@ -137,20 +120,16 @@ __device__ int cq_factor_invert(double (*D)[CP + 1], double (*X)[CP + 1], double
         const int r0 = bi * 16, n = bi * 16;   // columns [0, n) of block row bi
         for (int e = tid; e < 16 * n; e += 256) {
             const int r = e / n, cc = e % n;
-            const int lj = cc / 16 * 16;       // X[l][cc] is zero above block row lj
+            const int lj = cc / 16 * 16;       // first block row l = block column of cc
             double v = 0.0;
-#pragma unroll
-            for (int l = 0; l < 48; ++l)
-                if (l >= lj && l < r0) v += D[r0 + r][l] * X[l][cc];
+            for (int l = lj; l < r0; ++l) v += D[r0 + r][l] * X[l][cc];
             T[r][cc] = v;
         }
         __syncthreads();
         for (int e = tid; e < 16 * n; e += 256) {
             const int r = e / n, cc = e % n;
             double v = 0.0;
-#pragma unroll
-            for (int l = 0; l < 16; ++l)
-                if (l <= r) v += X[r0 + r][r0 + l] * T[l][cc];
+            for (int l = 0; l <= r; ++l) v += X[r0 + r][r0 + l] * T[l][cc];
             X[r0 + r][cc] = -v;
         }
         __syncthreads();
@@ -173,9 +152,8 @@ __global__ __launch_bounds__(256) void k_cq_panel(const CholJob* __restrict__ jo
     const int tid = threadIdx.x;
     double* B = J.B;
     double* M = J.M;
-#pragma unroll
-    for (int u = 0; u < CP * CP / 256; ++u) {
-        const int e = tid + 256 * u, i = e / CP, j = e % CP;
+    for (int e = tid; e < CP * CP; e += 256) {
+        const int i = e / CP, j = e % CP;
         D[i][j] = B[static_cast<int64_t>(c0 + i) * kp + c0 + j];
     }
     __syncthreads();
@@ -193,9 +171,8 @@ __global__ __launch_bounds__(256) void k_cq_panel(const CholJob* __restrict__ jo
     if (tile < nrt) {
         // rows [r0, r0 + 64) of L21 = A21 X^T
         const int r0 = c1 + tile * CT;
-#pragma unroll
-        for (int u = 0; u < CT * CP / 256; ++u) {
-            const int e = tid + 256 * u, r = e / CP, l = e % CP;
+        for (int e = tid; e < CT * CP; e += 256) {
+            const int r = e / CP, l = e % CP;
             S[l][r] = B[static_cast<int64_t>(r0 + r) * kp + c0 + l];
         }
         __syncthreads();
@@ -220,9 +197,8 @@ __global__ __launch_bounds__(256) void k_cq_panel(const CholJob* __restrict__ jo
     } else {
         // columns [q0, q0 + 64) of M's block row p: M_pj = -X W_pj
         const int q0 = (tile - nrt) * CT;
-#pragma unroll
-        for (int u = 0; u < CP * CT / 256; ++u) {
-            const int e = tid + 256 * u, l = e / CT, cc = e % CT;
+        for (int e = tid; e < CP * CT; e += 256) {
+            const int l = e / CT, cc = e % CT;
             S[l][cc] = M[static_cast<int64_t>(c0 + l) * kp + q0 + cc];
         }
         __syncthreads();
@@ -273,9 +249,8 @@ __global__ __launch_bounds__(256) void k_cq_update(const CholJob* __restrict__ j
         const int tj = tile - ti * (ti + 1) / 2;
         i0 = c1 + ti * CT;
         j0 = c1 + tj * CT;
-#pragma unroll
-        for (int u = 0; u < CP * CT / 256; ++u) {
-            const int e = threadIdx.x + 256 * u, t = e / CP, l = e % CP;
+        for (int e = threadIdx.x; e < CP * CT; e += 256) {
+            const int t = e / CP, l = e % CP;
             Ls[l][t] = B[static_cast<int64_t>(i0 + t) * kp + c0 + l];
             Rs[l][t] = B[static_cast<int64_t>(j0 + t) * kp + c0 + l];
         }
@@ -284,9 +259,8 @@ __global__ __launch_bounds__(256) void k_cq_update(const CholJob* __restrict__ j
         const int ncw = c1 / CT;
         i0 = c1 + (tile / ncw) * CT;
         j0 = (tile % ncw) * CT;
-#pragma unroll
-        for (int u = 0; u < CP * CT / 256; ++u) {
-            const int e = threadIdx.x + 256 * u, t = e / CP, l = e % CP;
+        for (int e = threadIdx.x; e < CP * CT; e += 256) {
+            const int t = e / CP, l = e % CP;
             Ls[l][t] = B[static_cast<int64_t>(i0 + t) * kp + c0 + l];
             const int l2 = e / CT, t2 = e % CT;
             Rs[l2][t2] = M[static_cast<int64_t>(c0 + l2) * kp + j0 + t2];
