@@ -106,26 +106,35 @@ GRAM_ROWS = 128          # default rows per partial Gram (eigensolver)
 BW = 16                  # eigensolver column block
 
 
-# HBM bytes per k_eig_solve launch on the 20000 x 2000 workload from the two counter runs
-# summarised in profiles/k_eig_solve_c2_pmc.md (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, both
-# scales read off a 256 MiB device copy in the same runs), and the digest of the kernel
-# source they were taken on; the figure is dropped (null) for any other workload and as
-# soon as the kernel's source differs.
-SOLVE_TRAFFIC_BYTES = {"c2": 3193787}
-SOLVE_TRAFFIC_DIGEST = "8bb7f99cd14505103cbd1fba4f72c7c948042797cdac6d75b001a228722dc40a"
+# HBM bytes per launch of a timed kernel, from the two counter runs summarised under
+# profiles/ (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the scales read off a 256 MiB device copy in
+# the same runs), keyed by (kernel, workload, precision of the timed form), with the digest
+# of the kernel source they were taken on; the figure is dropped (null) for any other
+# workload and as soon as the kernel's source differs.
+TRAFFIC = {
+    ("eig_solve", "c2", "fp64"): (3193787, "eig.hip", "void k_eig_solve(", "__global__",
+                                  "8bb7f99cd14505103cbd1fba4f72c7c948042797cdac6d75b001a228722dc40a"),
+    ("cq_panel", "c3", "mixed"): (1518045, "subspace.hip", "__device__ int cq_factor_invert(", "// After panel p:",
+                                  "ffb9071d7575d26a9a3c2a8f7592525a2c9c9c53aea93f439fb8dbec100cbed0"),
+    ("sub_gemm", "c3", "mixed"): (328228707, "mfma_gemm.hip", "template <typename Tc, bool TA, bool TB>",
+                                  "// C (M x N, ldc) = op(A) op(B)",
+                                  "fd7925f0523d4073a12f38d53a4c415d2ecb720249ca91724cf59e4bf085578f"),
+}
 
 
-def solve_traffic(config):
-    if config not in SOLVE_TRAFFIC_BYTES:
+def kernel_traffic(kname, config, precision):
+    key = (kname, config, precision)
+    if key not in TRAFFIC:
         return None
     import hashlib
-    with open(os.path.join(ROOT, "paper_2011_04235_amd", "csrc", "eig.hip")) as f:
+    nbytes, fname, start, end, digest = TRAFFIC[key]
+    with open(os.path.join(ROOT, "paper_2011_04235_amd", "csrc", fname)) as f:
         src = f.read()
-    a = src.index("void k_eig_solve(")
-    b = src.index("__global__", a + 1)
-    if hashlib.sha256(src[a:b].encode()).hexdigest() != SOLVE_TRAFFIC_DIGEST:
+    a = src.index(start)
+    b = src.index(end, a + 1) if end else len(src)
+    if hashlib.sha256(src[a:b].encode()).hexdigest() != digest:
         return None
-    return SOLVE_TRAFFIC_BYTES[config]
+    return nbytes
 
 
 # HBM bytes per call of the label SpMM (both passes) on the 300000 x 10000 labelled workload
@@ -169,6 +178,67 @@ def solve_alg_flops(info, sweeps, rotated, tuning):
         real_pairs = nblk // 2 + (nblk & 1)          # the odd block out still solves alone
         tot += rot * inner * PAIR_SWEEP_FLOPS + sw * rounds * real_pairs * nchunk * 1024
     return tot
+
+
+ROOF_KERNELS = ["cq_panel", "sub_gemm", "eig_solve"]
+KERNEL_NAMES = {"cq_panel": "k_cq_panel", "sub_gemm": "k_mfma_gemm (products by G)", "eig_solve": "k_eig_solve"}
+
+
+def core_basis(core, t, q):
+    """Basis size of the subspace route (the library's rule), 0 when the core stays on Jacobi."""
+    if core["mode"] == 0 or q < core["min_order"] or t <= 0:
+        return 0
+    k = (int(math.ceil(core["k_factor"] * t)) + 31) // 32 * 32
+    return k if (k > t and k <= core["max_frac"] * q) else 0
+
+
+def kernel_alg_flops(info, routes, core, mixed, tuning, sweeps, rotated):
+    """Algorithmic flops per step of the timed kernels.
+    sub_gemm: every product Y = G Q of a subspace core, 2 q^2 k each;
+    cq_panel: per Cholesky-QR panel launch, the factorisation and inversion of the 64 x 64
+      diagonal block (2 * 64^3 / 3) and one 64 x 64 x 64 product (2 * 64^3) for each of the
+      kp / 64 - 1 tiles of the panel (its L21 rows and its block row of L^-1);
+    eig_solve: as solve_alg_flops, at the order the Jacobi ran on (k for a subspace core's
+      Rayleigh-Ritz matrix, q otherwise)."""
+    iters = core["iters_mixed"] if mixed else core["iters_fp64"]
+    oe = core["orth_every"]
+    out = {"sub_gemm": 0.0, "cq_panel": 0.0, "eig_solve": 0.0}
+    inner = tuning.get("inner_sweeps", 1)
+    for c, (q, t) in enumerate(((info["n1"], info["s"]), (info["s"] + info["n2"], info["r"]))):
+        if q <= 0 or t <= 0:
+            continue
+        order = q
+        if routes[c] in ("subspace", "subspace+jacobi"):
+            k = core_basis(core, t, q)
+            kp = (k + 63) // 64 * 64
+            out["sub_gemm"] += iters * 2.0 * q * q * k
+            n_orth = (iters + oe - 1) // oe + 2
+            out["cq_panel"] += n_orth * (kp // 64) * (2.0 * 64 ** 3 / 3.0 + 2.0 * 64 ** 3 * (kp // 64 - 1))
+            order = k
+        sw = sweeps[1 + c]
+        if sw > 0:
+            ld, nblk, npairs, rounds, nchunk = eig_shape(order, tuning.get("gram_rows", GRAM_ROWS))
+            real_pairs = nblk // 2 + (nblk & 1)
+            out["eig_solve"] += rotated[c] * inner * PAIR_SWEEP_FLOPS + sw * rounds * real_pairs * nchunk * 1024
+    return out
+
+
+def roofline_entry(kname, kms, alg, mixed, config, head_key):
+    """Roofline object of one timed kernel: algorithmic flops per step over its summed launch
+    time per step, against the peak of its unit."""
+    n_launch, k_ms = kms[kname]
+    achieved = alg[kname] / (k_ms * 1e-3) / 1e12 if k_ms > 0 else 0.0
+    if kname == "sub_gemm":
+        bound, peak = "mfma", (157.3 if mixed else 78.6)   # FP32 / FP64 matrix-core peak
+    else:
+        bound, peak = "alu", 78.6                          # FP64 vector peak
+    return {"bound": bound, "kernel": KERNEL_NAMES[kname], "achieved": round(achieved, 5), "peak": peak,
+            "unit": "TFLOP/s", "frac": round(achieved / peak, 6),
+            "traffic": kernel_traffic(kname, config, "mixed" if mixed else "fp64"),
+            "traffic_unit": "bytes per launch", "launches": round(n_launch, 1),
+            "avg_us": round(k_ms / max(n_launch, 1) * 1e3, 3), "ms_per_step": round(k_ms, 4),
+            "flops_per_launch": alg[kname] / max(n_launch, 1),
+            "timed_in": head_key + " (eager pass of the same schedule)"}
 
 
 def recon_error(A, U, S, V):
@@ -224,6 +294,7 @@ def oracle_stages(prob, alpha, deadline=None):
         t0 = time.perf_counter()
         fn()
         times[name] = round(time.perf_counter() - t0, 4)
+        progress(f"oracle {name}: {times[name]:.2f} s")
     return times, True
 
 
@@ -598,7 +669,8 @@ def main():
                     help="run every stage of the single-thread oracle, whatever its time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--roofline-kernel", default="eig_solve",
-                    choices=["eig_solve", "eig_gram", "eig_update", "block_svd"])
+                    choices=["eig_solve", "eig_gram", "eig_update", "block_svd", "cq_panel", "sub_gemm"],
+                    help="kernel timed for the roofline of the batched 64-matrix workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (scale for the PMC byte counters)")
     ap.add_argument("--batch-count", type=int, default=64, help="matrices of the batched workload")
@@ -657,11 +729,9 @@ def main():
     if args.ranks == "learned":
         from paper_2011_04235_amd.rank_mlp import RankPredictor
         pred = RankPredictor.load(os.path.join(ROOT, "paper_2011_04235_amd", "rank_predictor.npz"))
-        blocks = plan.blocks()
-        dense = (blocks[:, 2] > 0) & (blocks[:, 3] > 0)
         feats = plan.block_features(prob.data)
         hk = fp.Handle(0)
-        plan.set_block_ranks(pred.block_ranks(hk, plan, prob.data, plan.block_ranks()[dense]))
+        plan.set_block_ranks(pred.block_ranks(hk, plan, prob.data))
         del hk
         ranks_note = (f"rank network ({int(pred.in_range(feats).sum())} of {len(feats)} blocks; the rest "
                       "alpha rule), total s_b of the alpha rule")
@@ -710,31 +780,38 @@ def main():
         for _ in range(args.warmup):
             step()
         h.sync()
-        # the dominant kernel is timed launch by launch with HIP events on the library's
-        # stream; graph replays carry no per-kernel events, so a batched leg times it in an
-        # eager pass of the same schedule right after its timed region
-        if not batched:
-            h.timing_start(args.roofline_kernel)
         dt = timed(args.steps)
         h.sync()
         progress(f"  timed {args.steps} steps: {dt * 1e3:.2f} ms/step")
         graph_launches = h.last_graph_launches()
-        if batched:
-            h.set_graph(False)
-            h.timing_start(args.roofline_kernel)
-            eager_dt = timed(args.steps)
-            h.set_graph(True)
-        n_launch, k_ms = h.timing_read()
-        h.timing_start(None)
         sweeps = h.last_sweeps()
         rotated = h.last_rotations()
+        routes = h.last_core_routes()
+        # candidate kernels timed launch by launch with HIP events on the library's stream, in
+        # eager passes of the same schedule right after the timed region (graph replays carry
+        # no per-kernel events); each pass runs `kpass` steps
+        kernel_ms = {}
+        if batched:
+            h.set_graph(False)
+        eager_dt = None
+        kpass = max(2, args.steps // 2)
+        for kname in ROOF_KERNELS:
+            h.timing_start(kname)
+            edt = timed(kpass)
+            n_launch, k_ms = h.timing_read()
+            kernel_ms[kname] = (n_launch / kpass, k_ms / kpass)
+            eager_dt = edt if eager_dt is None else min(eager_dt, edt)
+        h.timing_start(None)
+        if batched:
+            h.set_graph(True)
         Uh, Sh, Vh = U.cpu().numpy(), S.cpu().numpy(), V.cpu().numpy()
-        out = {"ms": dt * 1e3, "sweeps": sweeps, "rotated": rotated, "n_launch": n_launch, "k_ms": k_ms,
+        out = {"ms": dt * 1e3, "sweeps": sweeps, "rotated": rotated, "kernel_ms": kernel_ms,
+               "routes": routes, "core": h.get_core_solver(),
                "recon": recon_error(A_host, Uh, Sh, Vh), "sigma": Sh, "tuning": h.get_tuning(),
                "graph_launches_per_step": graph_launches}
         if batched:
             out["tune_report"] = tune_report
-            out["eager_ms"] = eager_dt * 1e3
+        out["eager_ms"] = eager_dt * 1e3
         return out
 
     precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
@@ -745,19 +822,16 @@ def main():
     ms = head["ms"]
     tflops = F["total"] / (ms * 1e-3) / 1e12
     sweeps = head["sweeps"]
-    n_launch, k_ms = head["n_launch"], head["k_ms"]
-
-    roof = None
-    if n_launch > 0 and args.roofline_kernel == "eig_solve" and args.inner == "exact":
-        # the timed pass ran args.steps identical steps
-        f_alg = solve_alg_flops(plan.info, sweeps, head["rotated"], head["tuning"]) * args.steps
-        achieved = f_alg / (k_ms * 1e-3) / 1e12
-        peak = 78.6   # MI355X FP64 vector peak, TFLOP/s
-        roof = {"bound": "alu", "kernel": "k_eig_solve", "achieved": round(achieved, 5),
-                "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 6),
-                "traffic": solve_traffic(args.config), "traffic_unit": "bytes per launch", "launches": n_launch, "avg_us": round(k_ms / n_launch * 1e3, 3),
-                "flops_per_launch": f_alg / n_launch,
-                "timed_in": head_key + (" (eager pass of the same schedule)" if "batched" in head_key else "")}
+    mixed_head = head_key.startswith("mixed")
+    alg = kernel_alg_flops(plan.info, head["routes"], head["core"], mixed_head, head["tuning"], sweeps,
+                           head["rotated"])
+    kms = head["kernel_ms"]
+    share = {k: round(v[1] / head["eager_ms"], 4) for k, v in kms.items()}
+    # the dominant kernel: the largest summed launch time per step among the timed ones
+    dom = max((k for k in kms if kms[k][0] > 0), key=lambda k: kms[k][1], default=None)
+    roof = roofline_entry(dom, kms, alg, mixed_head, args.config, head_key) if dom else None
+    roof_mfma = roofline_entry("sub_gemm", kms, alg, mixed_head, args.config, head_key) \
+        if kms.get("sub_gemm", (0, 0))[0] > 0 else None
     base = None
     if not args.no_cpu_baseline:
         progress("oracle on the host cores")
@@ -765,8 +839,10 @@ def main():
     compare = {p: {"ms_per_step": round(v["ms"], 3), "tflops": round(F["total"] / v["ms"] / 1e9, 4),
                    "recon_error": v["recon"], "sweeps": v["sweeps"], "tuning": v["tuning"],
                    "graph_launches_per_step": v["graph_launches_per_step"],
-                   **({"eager_ms_per_step": round(v["eager_ms"], 3), "tune_report": v["tune_report"]}
-                      if "eager_ms" in v else {})}
+                   "core_routes": v["routes"],
+                   "kernel_ms_per_step": {k: round(x[1], 4) for k, x in v["kernel_ms"].items()},
+                   "eager_ms_per_step": round(v["eager_ms"], 3),
+                   **({"tune_report": v["tune_report"]} if "tune_report" in v else {})}
                for p, v in res.items()}
     ref_key = "fp64-plain" if "fp64-plain" in res else None
     if ref_key:
@@ -804,6 +880,8 @@ def main():
         "sweeps": sweeps,
         "precision_compare": compare,
         "roofline": roof,
+        "roofline_mfma": roof_mfma,
+        "kernel_share_of_eager_step": share,
         "cpu_baseline": base,
     }
     print(json.dumps(out), flush=True)

@@ -192,6 +192,48 @@ int fastpi_block_features(const fastpi_plan* plan, const double* val, double* ou
 int fastpi_plan_set_block_ranks(fastpi_plan* plan, const int64_t* ranks);
 
 /*
+ * Learned allocation of the block ranks: the learned form of Eq. 1's rank rule
+ * (s_i = ceil(alpha n_i) per diagonal block), with the same total s_b.
+ *   fastpi_rank_model: the training statistics of the 16 block features (fastpi_block_features
+ *     order), each host double[16]: mean, std (every entry > 0), lo and hi (the minimum and
+ *     maximum over the training set); margin >= 0: a block is in range when every feature f_j
+ *     lies in [lo_j - margin span_j, hi_j + margin span_j], span_j = max(hi_j - lo_j, 1e-12).
+ *   fastpi_rank_inputs: for n feature rows (host double[n*16]), the network's input
+ *     X = (f - mean) / std rounded to float (host float[n*16]) and the range flags (host
+ *     int32[n], 1 = in range); either output may be NULL. Host only.
+ *   fastpi_rank_allocate: integer ranks s (host int64[n]) with 0 <= s_i <= q_i and sum exactly
+ *     min(budget, sum q_i), in proportion to x_i = max(f_i q_i, 1e-9), f_i (host float[n])
+ *     clipped to [0, 1] (NaN read as 0), q (host int64[n]) >= 0: the largest scale c with
+ *     sum_i min(c x_i, q_i) <= budget is located by 200 bisection steps on
+ *     [0, max q / min x + 1] (sums in index order), s_i = floor(min(c x_i, q_i)), and the
+ *     units still missing go one each to the blocks with the largest fractional parts (ties to
+ *     the lower index) that are below q_i. Host only.
+ *   fastpi_plan_learned_ranks: the whole allocation for the plan, written to ranks (host
+ *     int64[B], block order, 0 for blocks of height or width 0); val is the host CSR values of
+ *     the plan's pattern. Out-of-range blocks keep the alpha rule's rank
+ *     min(ceil(alpha cols), rows, cols); the network (theta: device float[5313], the packed
+ *     parameters below) runs on the handle's GPU for the in-range blocks, which share the alpha
+ *     rule's total s_b minus the out-of-range ranks through fastpi_rank_allocate with
+ *     q_i = min(rows, cols). The plan is not changed (apply the result with
+ *     fastpi_plan_set_block_ranks). Synchronises the handle's stream; allocates and frees
+ *     device memory for the network's input and output.
+ * Errors: FASTPI_EINVAL for null pointers, n < 0, a std entry <= 0 or a negative margin or q_i;
+ * FASTPI_ENOMEM / FASTPI_EHIP from the device part.
+ */
+typedef struct fastpi_rank_model {
+    const double* mean;
+    const double* std;
+    const double* lo;
+    const double* hi;
+    double margin;
+} fastpi_rank_model;
+int fastpi_rank_inputs(int64_t n, const double* feats, const fastpi_rank_model* model, float* X,
+                       int32_t* in_range);
+int fastpi_rank_allocate(int64_t n, const float* f, const int64_t* q, int64_t budget, int64_t* s);
+int fastpi_plan_learned_ranks(const fastpi_plan* plan, fastpi_handle* h, const double* val,
+                              const fastpi_rank_model* model, const float* theta, int64_t* ranks);
+
+/*
  * Learned rank predictor: a 16-64-64-1 network (ReLU, ReLU, sigmoid), FP32, predicting a
  * block's kept fraction s_i / min(rows, cols). Packed parameters (device float[5313]):
  * W1 (64x16 row-major), b1 (64), W2 (64x64), b2 (64), W3 (64), b3.
@@ -364,7 +406,8 @@ int fastpi_last_rotations(fastpi_handle* h, int64_t* out2);
  * kind: 0 = eigensolver partial Gram, 1 = eigensolver pair solve, 2 = eigensolver column
  * update, 3 = block SVD launches, 4 = the label SpMM of fastpi_apply_sparse (both passes),
  * 5 = fastpi_topk_hits, 6 = the transposed-B GEMM of fastpi_apply_sparse, 7 = the products by G
- * of the subspace core solver (fastpi_set_core_solver), -1 = off.
+ * of the subspace core solver (fastpi_set_core_solver), 8 = its Cholesky-QR panel kernel,
+ * -1 = off.
  * Starting discards earlier timings.
  */
 int fastpi_timing_start(fastpi_handle* h, int kind);

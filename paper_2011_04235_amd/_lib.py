@@ -71,6 +71,41 @@ class CoreSolver(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
 
 
+class RankModel(ctypes.Structure):
+    """Training statistics of the rank network's 16 block features (fastpi_rank_model)."""
+    _fields_ = [("mean", c_void_p), ("std", c_void_p), ("lo", c_void_p), ("hi", c_void_p),
+                ("margin", c_double)]
+
+
+def _rank_model(mean, std, lo, hi, margin):
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (mean, std, lo, hi)]
+    for a in arrs:
+        assert a.shape == (16,)
+    return RankModel(*[_ptr(a) for a in arrs], float(margin)), arrs   # arrs keeps the memory alive
+
+
+def rank_inputs(feats, mean, std, lo, hi, margin):
+    """The rank network's standardised inputs (float32 [n, 16]) and range flags (bool [n])."""
+    feats = np.ascontiguousarray(feats, dtype=np.float64).reshape(-1, 16)
+    n = feats.shape[0]
+    X = np.empty((n, 16), dtype=np.float32)
+    ok = np.empty(n, dtype=np.int32)
+    model, keep = _rank_model(mean, std, lo, hi, margin)
+    _check(load().fastpi_rank_inputs(n, _ptr(feats), ctypes.byref(model), _ptr(X), _ptr(ok)))
+    del keep
+    return X, ok.astype(bool)
+
+
+def rank_allocate(f, q, budget):
+    """Integer ranks in [0, q_i] summing to min(budget, sum q), in proportion to f_i q_i."""
+    f = np.ascontiguousarray(f, dtype=np.float32)
+    q = np.ascontiguousarray(q, dtype=np.int64)
+    assert f.shape == q.shape
+    out = np.empty(q.shape, dtype=np.int64)
+    _check(load().fastpi_rank_allocate(q.size, _ptr(f), _ptr(q), int(budget), _ptr(out)))
+    return out
+
+
 ROUTES = {0: "jacobi", 1: "subspace", 2: "subspace+jacobi", 3: "randomized"}
 
 SIGNATURES = [
@@ -99,6 +134,9 @@ SIGNATURES = [
     ("fastpi_last_sweeps", c_int, [c_void_p, c_void_p]),
     ("fastpi_block_features", c_int, [c_void_p, c_void_p, c_void_p]),
     ("fastpi_plan_set_block_ranks", c_int, [c_void_p, c_void_p]),
+    ("fastpi_rank_inputs", c_int, [c_int64, c_void_p, POINTER(RankModel), c_void_p, c_void_p]),
+    ("fastpi_rank_allocate", c_int, [c_int64, c_void_p, c_void_p, c_int64, c_void_p]),
+    ("fastpi_plan_learned_ranks", c_int, [c_void_p, c_void_p, c_void_p, POINTER(RankModel), c_void_p, c_void_p]),
     ("fastpi_mlp_param_count", c_int, []),
     ("fastpi_mlp_forward", c_int, [c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
     ("fastpi_mlp_gradient", c_int, [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
@@ -266,6 +304,18 @@ class Plan:
         out = np.empty((self.info["B_dense"], 16), dtype=np.float64)
         if out.size:
             _check(load().fastpi_block_features(self._h, _ptr(data), _ptr(out)))
+        return out
+
+    def learned_ranks(self, handle, data, theta, mean, std, lo, hi, margin):
+        """Per-block ranks of the learned allocation (fastpi_plan_learned_ranks): theta is the
+        network's packed parameters on the handle's device (float32 tensor)."""
+        data = np.ascontiguousarray(data, dtype=np.float64)
+        out = np.empty(self.info["B"], dtype=np.int64)
+        model, keep = _rank_model(mean, std, lo, hi, margin)
+        assert theta.dtype == handle.torch.float32 and theta.is_contiguous()
+        _check(load().fastpi_plan_learned_ranks(self._h, handle._h, _ptr(data), ctypes.byref(model),
+                                                _dptr(theta), _ptr(out)))
+        del keep
         return out
 
     def set_block_ranks(self, ranks):
@@ -487,7 +537,7 @@ class Handle:
         return out.tolist()
 
     KERNELS = {"eig_gram": 0, "eig_solve": 1, "eig_update": 2, "block_svd": 3, "label_spmm": 4,
-               "topk": 5, "gemm_nt": 6, "sub_gemm": 7}
+               "topk": 5, "gemm_nt": 6, "sub_gemm": 7, "cq_panel": 8}
 
     def last_rotations(self):
         """Pair solves that ran in the last svd: [row-update core, column-update core]."""

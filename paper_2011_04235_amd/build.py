@@ -10,7 +10,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfastpi.so")
-SOURCES = ["api.cpp", "driver.cpp", "reorder.cpp", "plan.cpp", "block_svd.hip", "eig.hip", "dense.hip",
+SOURCES = ["api.cpp", "driver.cpp", "reorder.cpp", "plan.cpp", "rank_alloc.cpp", "block_svd.hip", "eig.hip", "dense.hip",
            "sparse.hip", "mlp.hip", "pchol.hip", "evaluate.hip", "randomized.hip", "reorder_gpu.hip", "subspace.hip", "mfma_gemm.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",

@@ -900,6 +900,111 @@ int fastpi_plan_set_block_ranks(fastpi_plan* plan, const int64_t* ranks) {
     return FASTPI_OK;
 }
 
+static bool rank_model_valid(const fastpi_rank_model* m) {
+    if (!m || !m->mean || !m->std || !m->lo || !m->hi || !(m->margin >= 0.0)) return false;
+    for (int j = 0; j < kRankFeatures; ++j)
+        if (!(m->std[j] > 0.0)) return false;
+    return true;
+}
+
+int fastpi_rank_inputs(int64_t n, const double* feats, const fastpi_rank_model* model, float* X,
+                       int32_t* in_range) {
+    if (n < 0 || (n > 0 && !feats) || !rank_model_valid(model)) {
+        set_error("bad arguments (null pointer, n < 0, std <= 0 or negative margin)");
+        return FASTPI_EINVAL;
+    }
+    rank_inputs(n, feats, *model, X, in_range);
+    return FASTPI_OK;
+}
+
+int fastpi_rank_allocate(int64_t n, const float* f, const int64_t* q, int64_t budget, int64_t* s) {
+    if (n < 0 || (n > 0 && (!f || !q || !s))) {
+        set_error("bad arguments");
+        return FASTPI_EINVAL;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        if (q[i] < 0) {
+            set_error("negative block capacity");
+            return FASTPI_EINVAL;
+        }
+    rank_allocate(n, f, q, budget, s);
+    return FASTPI_OK;
+}
+
+int fastpi_plan_learned_ranks(const fastpi_plan* plan, fastpi_handle* h, const double* val,
+                              const fastpi_rank_model* model, const float* theta, int64_t* ranks) {
+    if (!plan || !h || !val || !theta || !ranks || !rank_model_valid(model)) {
+        set_error("bad arguments (null pointer, std <= 0 or negative margin)");
+        return FASTPI_EINVAL;
+    }
+    const Plan& P = plan->p;
+    const std::vector<BlockDesc>& blocks = P.ro.blocks;
+    const int64_t B = static_cast<int64_t>(blocks.size());
+    std::vector<int64_t> dense;   // block ids of the dense blocks, in block order
+    for (int64_t b = 0; b < B; ++b)
+        if (blocks[b].rows > 0 && blocks[b].cols > 0) dense.push_back(b);
+    const int64_t nd = static_cast<int64_t>(dense.size());
+    std::vector<double> feats(static_cast<size_t>(nd) * kRankFeatures);
+    if (nd > 0) {
+        const int rc = block_features(P, val, feats.data());
+        if (rc != FASTPI_OK) return rc;
+    }
+    std::vector<float> X(static_cast<size_t>(nd) * kRankFeatures);
+    std::vector<int32_t> ok(nd);
+    rank_inputs(nd, feats.data(), *model, X.data(), ok.data());
+    // the alpha rule: the fallback of out-of-range blocks and the total budget
+    std::vector<int64_t> alpha_rank(nd), q(nd);
+    int64_t budget = 0, kept = 0, nin = 0;
+    for (int64_t i = 0; i < nd; ++i) {
+        const BlockDesc& d = blocks[dense[i]];
+        q[i] = std::min(d.rows, d.cols);
+        alpha_rank[i] = std::min({target_rank(P.alpha, d.cols), d.rows, d.cols});
+        budget += alpha_rank[i];
+        if (ok[i]) ++nin;
+        else kept += alpha_rank[i];
+    }
+    std::vector<int64_t> out(nd);
+    for (int64_t i = 0; i < nd; ++i) out[i] = alpha_rank[i];
+    if (nin > 0) {
+        std::vector<float> Xin(static_cast<size_t>(nin) * kRankFeatures), f(nin);
+        std::vector<int64_t> qin(nin), s_in(nin);
+        for (int64_t i = 0, k = 0; i < nd; ++i)
+            if (ok[i]) {
+                std::copy(X.begin() + i * kRankFeatures, X.begin() + (i + 1) * kRankFeatures,
+                          Xin.begin() + k * kRankFeatures);
+                qin[k++] = q[i];
+            }
+        HIP_TRY(hipSetDevice(h->device));
+        void* dX = nullptr;
+        void* df = nullptr;
+        if (hipMalloc(&dX, Xin.size() * sizeof(float)) != hipSuccess ||
+            hipMalloc(&df, f.size() * sizeof(float)) != hipSuccess) {
+            if (dX) hipFree(dX);
+            set_error("device allocation failed (rank-network input)");
+            return FASTPI_ENOMEM;
+        }
+        hipError_t e = hipMemcpyAsync(dX, Xin.data(), Xin.size() * sizeof(float), hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess) {
+            launch_mlp_forward(nin, static_cast<const float*>(dX), theta, static_cast<float*>(df), nullptr, h->stream);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(f.data(), df, f.size() * sizeof(float), hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        hipFree(dX);
+        hipFree(df);
+        if (e != hipSuccess) {
+            set_error(std::string("HIP error in the rank network: ") + hipGetErrorString(e));
+            return FASTPI_EHIP;
+        }
+        rank_allocate(nin, f.data(), qin.data(), budget - kept, s_in.data());
+        for (int64_t i = 0, k = 0; i < nd; ++i)
+            if (ok[i]) out[i] = s_in[k++];
+    }
+    std::fill(ranks, ranks + B, 0);
+    for (int64_t i = 0; i < nd; ++i) ranks[dense[i]] = out[i];
+    return FASTPI_OK;
+}
+
 int fastpi_mlp_param_count(void) { return mlp_param_count(); }
 
 int fastpi_mlp_forward(fastpi_handle* h, int64_t N, const float* X, const float* theta, float* f) {

@@ -549,7 +549,7 @@ static int sub_run(Group& g, int c, const RunCfg& cfg, hipStream_t st) {
             launch_gemm_tn(cur(R), R.k, cur(R), R.k, R.k, R.k, R.q, S.chol[i].B, R.kp, nullptr, nullptr, R.part, R.sp,
                            st, false);
         }
-        launch_chol_inverse(S.dchol, nc, S.max_kp, st);
+        launch_chol_inverse(S.dchol, nc, S.max_kp, st, cfg.timer);
         for (int i = 0; i < nc; ++i) {
             SubCore& R = S.cores[i];
             launch_gemm_nt(cur(R), R.k, S.chol[i].M, R.kp, R.q, R.k, R.k, oth(R), R.k, st, fp32, nullptr);

@@ -86,4 +86,9 @@ int build_plan(Plan& p, int64_t m, int64_t n, const int64_t* rowptr, const int32
 void assign_ranks(Plan& p, const std::vector<int64_t>& ranks);
 int block_features(const Plan& p, const double* val, double* out);
 
+// learned rank allocation (host arithmetic)
+constexpr int kRankFeatures = 16;
+void rank_inputs(int64_t n, const double* feats, const fastpi_rank_model& m, float* X, int32_t* ok);
+void rank_allocate(int64_t n, const float* f, const int64_t* q, int64_t budget, int64_t* s);
+
 }  // namespace fastpi

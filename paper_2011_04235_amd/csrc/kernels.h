@@ -38,7 +38,8 @@ enum KernelKind {
     KT_TOPK = 5,
     KT_GEMM_NT = 6,
     KT_SUB_GEMM = 7,   // products by G of the subspace core solver
-    KT_LAST = KT_SUB_GEMM
+    KT_CQ_PANEL = 8,   // panel kernel of the subspace solver's Cholesky QR
+    KT_LAST = KT_CQ_PANEL
 };
 struct KernelTimer {
     int target = KT_NONE;
@@ -149,7 +150,7 @@ struct CholJob {
     int* flag;
     int k, kp;
 };
-void launch_chol_inverse(const CholJob* jobs, int njobs, int max_kp, hipStream_t st);
+void launch_chol_inverse(const CholJob* jobs, int njobs, int max_kp, hipStream_t st, KernelTimer* timer = nullptr);
 // flag |= 1 when a column of R = G V (q x t) leaves lam_i V[:, i] by more than tol * lam_0
 void launch_sub_residual(const double* R, const double* V, const double* lam, int64_t q, int64_t t, double tol,
                          int* flag, hipStream_t st);

@@ -59,8 +59,17 @@ __global__ __launch_bounds__(256) void k_mfma_gemm(const double* __restrict__ A,
     __shared__ Tc Bs[KT][NT + PAD];
     const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
     const int wm = w / 2, wn = w % 2;
-    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * MT;
-    const int64_t j0 = static_cast<int64_t>(blockIdx.y) * NT;
+    // Tile order: workgroups are dealt to the 8 XCDs round robin by their linear id, and each
+    // XCD has its own L2. The linear id is remapped so that each XCD gets a contiguous range
+    // of tiles, numbered with the N tile fastest: the tiles sharing a row band of op(A) then
+    // run on one XCD and reuse it from that L2 (op(B) stays in the shared MALL).
+    const int nx = gridDim.x, ny = gridDim.y;
+    const int ntile = nx * ny;
+    const int lin = blockIdx.x + nx * blockIdx.y;
+    const int per = ntile / 8, extra = ntile % 8, xcd = lin % 8, slot = lin / 8;
+    const int tile = (xcd < extra ? xcd * (per + 1) : extra * (per + 1) + (xcd - extra) * per) + slot;
+    const int64_t i0 = static_cast<int64_t>(tile / ny) * MT;
+    const int64_t j0 = static_cast<int64_t>(tile % ny) * NT;
     const int64_t kb = static_cast<int64_t>(blockIdx.z) * kchunk;
     const int64_t ke = min(K, kb + kchunk);
     C += static_cast<int64_t>(blockIdx.z) * cstride;

@@ -307,14 +307,14 @@ __global__ __launch_bounds__(256) void k_cq_update(const CholJob* __restrict__ j
     }
 }
 
-void launch_chol_inverse(const CholJob* jobs, int njobs, int max_kp, hipStream_t st) {
+void launch_chol_inverse(const CholJob* jobs, int njobs, int max_kp, hipStream_t st, KernelTimer* timer) {
     if (njobs <= 0 || max_kp <= 0) return;
     const unsigned nj = static_cast<unsigned>(njobs);
     hipLaunchKernelGGL(k_chol_diag, dim3(static_cast<unsigned>((max_kp + 255) / 256), nj), dim3(256), 0, st, jobs);
     for (int c0 = 0; c0 < max_kp; c0 += CP) {
         const int c1 = c0 + CP;
         const unsigned tiles = static_cast<unsigned>(std::max(1, (max_kp - c1) / CT + c0 / CT));
-        hipLaunchKernelGGL(k_cq_panel, dim3(tiles, nj), dim3(256), 0, st, jobs, c0);
+        FASTPI_LAUNCH(timer, KT_CQ_PANEL, k_cq_panel, dim3(tiles, nj), dim3(256), 0, st, jobs, c0);
         if (c1 < max_kp) {
             const int nt = (max_kp - c1) / CT;
             const unsigned tiles = static_cast<unsigned>(nt * (nt + 1) / 2 + nt * (c1 / CT));

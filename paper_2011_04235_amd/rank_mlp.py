@@ -5,12 +5,16 @@ trained on the GPU by the library's own forward, backward and Adam kernels, pred
 cheap block features (fastpi_block_features) the fraction of a block's directions that the
 Eckart-Young allocation at the same total budget would keep. The predictions are turned into
 integer ranks with exactly the alpha rule's total s_b; blocks whose features fall outside the
-training range keep the alpha rule's rank (the fallback). Only argument marshalling and
-integer bookkeeping happen here; the network runs in HIP kernels.
+training range keep the alpha rule's rank (the fallback). The standardisation, the range test
+and the budgeted allocation are library calls (fastpi_rank_inputs, fastpi_rank_allocate,
+fastpi_plan_learned_ranks) and the network runs in HIP kernels; this module only keeps the
+parameters and the training statistics and marshals them.
 """
 from __future__ import annotations
 
 import numpy as np
+
+from . import _lib
 
 N_FEATURES = 16
 N_PARAMS = 5313
@@ -61,8 +65,13 @@ class RankPredictor:
         self.theta = th.cpu().numpy()
         return history
 
+    MARGIN = 0.05
+
+    def _model(self):
+        return (self.mean, self.std, self.lo, self.hi, self.MARGIN)
+
     def _standardise(self, X):
-        return ((np.asarray(X, np.float64) - self.mean) / self.std).astype(np.float32)
+        return _lib.rank_inputs(X, *self._model())[0]
 
     def predict(self, handle, X):
         torch = handle.torch
@@ -72,59 +81,15 @@ class RankPredictor:
         th = torch.from_numpy(self.theta).to(handle.device)
         return handle.mlp_forward(Xd, th).cpu().numpy()
 
-    def in_range(self, X, margin=0.05):
-        span = np.maximum(self.hi - self.lo, 1e-12)
-        return np.all((X >= self.lo - margin * span) & (X <= self.hi + margin * span), axis=1)
+    def in_range(self, X):
+        return _lib.rank_inputs(X, *self._model())[1]
 
-    # ---------------------------------------------------------------- allocation --------
-    @staticmethod
-    def allocate(f, q, budget):
-        """Integer ranks s_i in [0, q_i] with sum exactly `budget`, proportional to the
-        predicted kept counts f_i q_i: the scale is found by bisection, then the remainder
-        goes to the largest fractional parts (ties to the lower index)."""
-        f = np.clip(np.asarray(f, np.float64), 0.0, 1.0)
-        q = np.asarray(q, np.int64)
-        budget = int(min(budget, q.sum()))
-        if budget <= 0 or q.size == 0:
-            return np.zeros(q.size, np.int64)
-        x = np.maximum(f * q, 1e-9)
-        lo, hi = 0.0, float(q.max() / x.min()) + 1.0
-        for _ in range(200):
-            mid = 0.5 * (lo + hi)
-            if np.minimum(mid * x, q).sum() > budget:
-                hi = mid
-            else:
-                lo = mid
-        share = np.minimum(lo * x, q)
-        s = np.floor(share).astype(np.int64)
-        rest = budget - int(s.sum())
-        if rest > 0:
-            frac = share - s
-            order = np.lexsort((np.arange(s.size), -frac))
-            for i in order:
-                if rest == 0:
-                    break
-                if s[i] < q[i]:
-                    s[i] += 1
-                    rest -= 1
-        return s
-
-    def block_ranks(self, handle, plan, data, alpha_ranks_dense):
-        """Ranks for every block of the plan's block table: predictions for in-range dense
-        blocks, the alpha rule for out-of-range ones, at the alpha rule's total budget."""
-        blocks = plan.blocks()
-        dense = (blocks[:, 2] > 0) & (blocks[:, 3] > 0)
-        q = np.minimum(blocks[dense, 2], blocks[dense, 3])
-        X = plan.block_features(data)
-        ok = self.in_range(X)
-        s = np.asarray(alpha_ranks_dense, np.int64).copy()
-        budget = int(s.sum())
-        if ok.any():
-            f = self.predict(handle, X[ok])
-            s[ok] = self.allocate(f, q[ok], budget - int(s[~ok].sum()))
-        out = np.zeros(len(blocks), np.int64)
-        out[dense] = s
-        return out
+    def block_ranks(self, handle, plan, data):
+        """Ranks for every block of the plan's block table (fastpi_plan_learned_ranks):
+        predictions for in-range dense blocks, the alpha rule for the others, at the alpha
+        rule's total budget."""
+        th = handle.torch.from_numpy(self.theta).to(handle.device)
+        return plan.learned_ranks(handle, data, th, *self._model())
 
     def save(self, path):
         np.savez(path, theta=self.theta, mean=self.mean, std=self.std, lo=self.lo, hi=self.hi)

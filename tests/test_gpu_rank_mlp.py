@@ -101,7 +101,7 @@ def test_training_beats_alpha_rule_and_gains_on_held_out_matrices(env):
         X, spectra, s_alpha, shapes = orank.problem_blocks(p.m, p.n, p.indptr, p.indices, p.data,
                                                            cfg.alpha, cfg.k)
         q = np.minimum(shapes[:, 0], shapes[:, 1])
-        s_net = pred.allocate(pred.predict(h, X), q, int(s_alpha.sum()))
+        s_net = fp.rank_allocate(pred.predict(h, X), q, int(s_alpha.sum()))
         e_net = orank.truncation_error2(spectra, s_net)
         e_alpha = orank.truncation_error2(spectra, s_alpha)
         e_opt = orank.truncation_error2(spectra, orank.eckart_young_ranks(spectra, int(s_alpha.sum())))
@@ -135,7 +135,7 @@ def test_learned_ranks_end_to_end(env):
             if mode == "learned":
                 blocks = plan.blocks()
                 dense = (blocks[:, 2] > 0) & (blocks[:, 3] > 0)
-                ranks = pred.block_ranks(h, plan, p.data, plan.block_ranks()[dense])
+                ranks = pred.block_ranks(h, plan, p.data)
                 plan.set_block_ranks(ranks)
             h.upload_plan(plan)
             U, S, V = h.svd(torch.from_numpy(p.indptr).to(dev), torch.from_numpy(p.indices).to(dev),
@@ -176,7 +176,7 @@ def test_learned_ranks_at_scale(env):
         if mode == "learned":
             X = plan.block_features(p.data)
             say(f"  network ranks {int(pred.in_range(X).sum())} of {len(X)} blocks")
-            plan.set_block_ranks(pred.block_ranks(h, plan, p.data, plan.block_ranks()[dense]))
+            plan.set_block_ranks(pred.block_ranks(h, plan, p.data))
         ranks_used[mode] = plan.block_ranks()[dense]
         h.upload_plan(plan)
         say(f"  {mode}: s_b={plan.s_b} s={plan.s} r={plan.r}, GPU run")
@@ -221,7 +221,7 @@ def test_learned_ranks_match_oracle_with_same_ranks(env):
         blocks = plan.blocks()
         dense = (blocks[:, 2] > 0) & (blocks[:, 3] > 0)
         alpha_ranks = plan.block_ranks().copy()
-        plan.set_block_ranks(pred.block_ranks(h, plan, p.data, alpha_ranks[dense]))
+        plan.set_block_ranks(pred.block_ranks(h, plan, p.data))
         ranks = plan.block_ranks()
         assert not np.array_equal(ranks, alpha_ranks)
         h.upload_plan(plan)
@@ -236,3 +236,30 @@ def test_learned_ranks_match_oracle_with_same_ranks(env):
         okz, zinfo = compare_apply(p, Z.cpu().numpy(), ores)
         say(f"  {zinfo}")
         assert okz, zinfo
+
+
+def test_plan_learned_ranks_match_reference(env):
+    """fastpi_plan_learned_ranks (standardisation, range fallback, network, budgeted
+    allocation inside the library) against the Python reference of the same rules fed by the
+    network's outputs, on the 20000 x 2000 workload and a held-out matrix; bit-exact ranks."""
+    torch, fp, h, d, RankPredictor, init_params = env
+    sys.path.insert(0, GOLDEN)
+    sys.path.insert(0, os.path.dirname(__file__))
+    import rank_reference as ref
+    from make_rank_dataset import instance_config
+    from synth import CONFIGS, make_problem
+    pred = RankPredictor.load(os.path.join(os.path.dirname(fp.__file__), "rank_predictor.npz"))
+    dev = torch.device("cuda", 0)
+    th = torch.from_numpy(pred.theta).to(dev)
+    for name, cfg in (("c2", CONFIGS["c2"]), ("held-out", instance_config(int(d["n_train"])))):
+        p = make_problem(cfg, with_labels=False)
+        plan = fp.Plan(p.m, p.n, p.indptr, p.indices, p.data, alpha=cfg.alpha, k=cfg.k)
+        got = plan.learned_ranks(h, p.data, th, pred.mean, pred.std, pred.lo, pred.hi, pred.MARGIN)
+        F = plan.block_features(p.data)
+        X, ok = ref.inputs(F, pred.mean, pred.std, pred.lo, pred.hi, pred.MARGIN)
+        f = h.mlp_forward(torch.from_numpy(np.ascontiguousarray(X[ok])).to(dev), th).cpu().numpy()
+        want = ref.plan_ranks(plan.blocks(), plan.block_ranks(), f, ok)
+        say(f"  {name}: {int(ok.sum())} of {len(ok)} blocks ranked by the network, "
+            f"{int(np.sum(got != plan.block_ranks()))} ranks moved")
+        assert np.array_equal(got, want)
+        assert got.sum() == plan.block_ranks().sum()
