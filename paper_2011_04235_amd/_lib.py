@@ -13,7 +13,8 @@ from ctypes import POINTER, c_double, c_int, c_int32, c_int64, c_size_t, c_void_
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libfastpi.so")
+# FASTPI_LIBRARY names another build of the same library (the host-sanitizer build)
+LIB_PATH = os.environ.get("FASTPI_LIBRARY") or os.path.join(HERE, "libfastpi.so")
 
 FP64, MIXED = 0, 1
 

@@ -26,31 +26,52 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src: str, obj_dir: str) -> str:
+# Host-sanitizer build (libfastpi_san.so): AddressSanitizer and UndefinedBehaviorSanitizer on
+# the host half of every source only (device code is built as usual), against the shared
+# sanitizer runtime so that the library can be loaded into an uninstrumented Python with that
+# runtime preloaded.
+SAN_OUT = os.path.join(HERE, "libfastpi_san.so")
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+             "-Xarch_host", "-shared-libasan", "-g"]
+
+
+def _compile(src: str, obj_dir: str, extra=()) -> str:
     obj = os.path.join(obj_dir, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc(), *FLAGS, *extra, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    obj_dir = os.path.join(HERE, "_build")
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    obj_dir = os.path.join(HERE, "_build_san" if sanitize else "_build")
+    out = SAN_OUT if sanitize else OUT
+    extra = SAN_FLAGS if sanitize else ()
     os.makedirs(obj_dir, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, obj_dir), SOURCES))
-    tmp = OUT + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+        objs = list(ex.map(lambda s: _compile(s, obj_dir, extra), SOURCES))
+    tmp = out + ".tmp"
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *extra, "-o", tmp, *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
-    os.replace(tmp, OUT)
+    os.replace(tmp, out)
     if verbose:
-        print(f"built {OUT}")
-    return OUT
+        print(f"built {out}")
+    return out
+
+
+def sanitizer_runtime() -> str:
+    """Path of the shared AddressSanitizer runtime the sanitizer build links against."""
+    res = subprocess.run([hipcc(), "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    return res.stdout.strip()
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    if "--sanitizer-runtime" in sys.argv:
+        print(sanitizer_runtime())
+    else:
+        build(verbose=True, sanitize="--sanitize" in sys.argv)
     sys.exit(0)
