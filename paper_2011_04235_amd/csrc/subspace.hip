@@ -40,55 +40,90 @@ __global__ void k_chol_diag(const CholJob* __restrict__ jobs) {
         J.dg[i] = J.B[static_cast<int64_t>(i) * J.kp + i];
 }
 
-// The panel's diagonal block D (64 x 64, in LDS) factored in place, L lower (blocked by 16:
-// one wave factors each 16 x 16 diagonal block wave-synchronously, all waves solve the rows
-// below it and update the trailing part), then X = L^-1 (16 x 16 diagonal blocks by one wave
-// each, off-diagonal blocks by block rows); returns the number of pivots that lost rank.
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), lane);
+    const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), lane);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// The panel's diagonal block D (64 x 64, in LDS) factored in place, L lower, and X = L^-1,
+// blocked by 16. For each 16-block: wave 0 holds the block's 16 rows in registers (lane i:
+// row i) and factors it column by column, every operand of the dependent chain moved between
+// lanes by readlane instead of through LDS; it then inverts the 16 x 16 factor in registers
+// (lane j: column j of the inverse) and writes both. All waves then form the rows below,
+// L_ib = D_ib X_bb^T (independent dot products), and update the rest of D. The block rows of
+// X below the diagonal follow at the end. Returns the number of pivots that lost rank.
 __device__ int cq_factor_invert(double (*D)[CP + 1], double (*X)[CP + 1], double (*T)[CP + 1], const double* dg,
                                 double lim) {
     const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
     __shared__ int nbad;
-    __shared__ double lims[CP];   // rank-test threshold of every pivot (no global load in the chain)
+    __shared__ double lims[CP];   // rank-test threshold of every pivot
     if (tid == 0) nbad = 0;
     if (tid < CP) lims[tid] = lim * dg[tid];
     for (int e = tid; e < CP * CP; e += 256) X[e / CP][e % CP] = 0.0;
     __syncthreads();
+#pragma unroll 1
     for (int bb = 0; bb < CP; bb += 16) {
         if (w == 0) {
+            const int li = lane < 16 ? lane : 15;
+            double r[16];
+#pragma unroll
+            for (int l = 0; l < 16; ++l) r[l] = D[bb + li][bb + l];
+            const double mylim = lims[bb + li];
+            double dv[16];   // 1 / L[c][c] (the same on every lane)
             int lost_here = 0;
+#pragma unroll
             for (int c = 0; c < 16; ++c) {
-                const int col = bb + c;
-                double sv = 0.0;
-                if (lane < 16 && lane >= c) {
-                    sv = D[bb + lane][col];
-                    for (int l = 0; l < c; ++l) sv -= D[bb + lane][bb + l] * D[col][bb + l];
-                }
-                const double sc = __shfl(sv, c);
-                const bool lost = !(sc > lims[col]);
+                const double sc = lane_value(r[c], c);
+                const bool lost = !(sc > lane_value(mylim, c));
                 lost_here += lost ? 1 : 0;
                 const double piv = lost ? 1.0 : sqrt(sc);   // keeps the arithmetic finite
-                if (lane > c && lane < 16) D[bb + lane][col] = sv / piv;
-                if (lane == c) D[col][col] = piv;
-                wave_sync();
+                const double rp = 1.0 / piv;
+                dv[c] = rp;
+                const double l = lane > c ? r[c] * rp : (lane == c ? piv : 0.0);
+                r[c] = l;
+#pragma unroll
+                for (int j = c + 1; j < 16; ++j) r[j] -= l * lane_value(l, j);
+            }
+            // column `lane` of the inverse: x_i = -(sum_{l<i} L_il x_l) / L_ii, x_lane = 1 / L_ll
+            double x[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                double v = 0.0;
+#pragma unroll
+                for (int l = 0; l < i; ++l) v += lane_value(r[l], i) * x[l];
+                x[i] = i < lane ? 0.0 : (i == lane ? dv[i] : -v * dv[i]);
+            }
+            if (lane < 16) {
+#pragma unroll
+                for (int l = 0; l < 16; ++l) {
+                    if (l <= lane) D[bb + lane][bb + l] = r[l];
+                    X[bb + l][bb + lane] = x[l];
+                }
             }
             if (lane == 0 && lost_here) nbad += lost_here;
         }
         __syncthreads();
-        const int nr = CP - bb - 16;   // rows below the 16-block
-        if (tid < nr) {
-            const int i = bb + 16 + tid;
-            double x[16];
+        // rows below: L_ib = D_ib X_bb^T, X_bb lower triangular
+        const int nr = CP - bb - 16;
+        double v3[3];
 #pragma unroll
-            for (int j = 0; j < 16; ++j) x[j] = D[i][bb + j];
+        for (int u = 0; u < 3; ++u) {
+            const int e = tid + 256 * u;
+            v3[u] = 0.0;
+            if (e < nr * 16) {
+                const int i = bb + 16 + e / 16, j = e % 16;
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                double v = x[j];
-#pragma unroll
-                for (int l = 0; l < j; ++l) v -= x[l] * D[bb + j][bb + l];
-                x[j] = v / D[bb + j][bb + j];
+                for (int l = 0; l < 16; ++l)
+                    if (l <= j) v3[u] += D[i][bb + l] * X[bb + j][bb + l];
             }
+        }
+        __syncthreads();
 #pragma unroll
-            for (int j = 0; j < 16; ++j) D[i][bb + j] = x[j];
+        for (int u = 0; u < 3; ++u) {
+            const int e = tid + 256 * u;
+            if (e < nr * 16) D[bb + 16 + e / 16][bb + e % 16] = v3[u];
         }
         __syncthreads();
         for (int e = tid; e < nr * nr; e += 256) {
@@ -101,36 +136,22 @@ __device__ int cq_factor_invert(double (*D)[CP + 1], double (*X)[CP + 1], double
         }
         __syncthreads();
     }
-    // diagonal 16 x 16 blocks of X: wave w inverts block w, lane j < 16 its column j
-    {
-        const int bb = w * 16;
-        if (lane < 16) {
-            const int j = lane;
-            X[bb + j][bb + j] = 1.0 / D[bb + j][bb + j];
-            for (int i = j + 1; i < 16; ++i) {
-                double v = 0.0;
-                for (int l = j; l < i; ++l) v += D[bb + i][bb + l] * X[bb + l][bb + j];
-                X[bb + i][bb + j] = -v / D[bb + i][bb + i];
-            }
-        }
-    }
-    __syncthreads();
     // block row bi: T_j = sum_{l=j}^{bi-1} L_{bi,l} X_{l,j}, then X_{bi,j} = -X_{bi,bi} T_j (j < bi)
     for (int bi = 1; bi < 4; ++bi) {
         const int r0 = bi * 16, n = bi * 16;   // columns [0, n) of block row bi
         for (int e = tid; e < 16 * n; e += 256) {
-            const int r = e / n, cc = e % n;
+            const int rr = e / n, cc = e % n;
             const int lj = cc / 16 * 16;       // first block row l = block column of cc
             double v = 0.0;
-            for (int l = lj; l < r0; ++l) v += D[r0 + r][l] * X[l][cc];
-            T[r][cc] = v;
+            for (int l = lj; l < r0; ++l) v += D[r0 + rr][l] * X[l][cc];
+            T[rr][cc] = v;
         }
         __syncthreads();
         for (int e = tid; e < 16 * n; e += 256) {
-            const int r = e / n, cc = e % n;
+            const int rr = e / n, cc = e % n;
             double v = 0.0;
-            for (int l = 0; l <= r; ++l) v += X[r0 + r][r0 + l] * T[l][cc];
-            X[r0 + r][cc] = -v;
+            for (int l = 0; l <= rr; ++l) v += X[r0 + rr][r0 + l] * T[l][cc];
+            X[r0 + rr][cc] = -v;
         }
         __syncthreads();
     }
