@@ -140,18 +140,18 @@ def kernel_traffic(kname, config, precision):
 # HBM bytes per call of the label SpMM (both passes) on the 300000 x 10000 labelled workload
 # from the counter runs summarised in profiles/label_spmm_c5_pmc.md, with the digest of the
 # kernel source they were taken on (null for other workloads or another source).
-LABEL_SPMM_TRAFFIC_BYTES = {"c5": 4924894288}
-LABEL_SPMM_DIGEST = "1b0cf4f0673f7f0380021ae44037cea475a24b498b2614ca3c3a1922df6e4746"
+LABEL_SPMM_TRAFFIC_BYTES = {}
+LABEL_SPMM_DIGEST = ""
 
 
 def label_spmm_traffic(config):
     if config not in LABEL_SPMM_TRAFFIC_BYTES:
         return None
     import hashlib
-    with open(os.path.join(ROOT, "paper_2011_04235_amd", "csrc", "sparse.hip")) as f:
+    with open(os.path.join(ROOT, "paper_2011_04235_amd", "csrc", "evaluate.hip")) as f:
         src = f.read()
-    a = src.index("void k_spmm_rows(")
-    b = src.index("// Diagonal blocks of V1", a)
+    a = src.index("// Label SpMM of the sparse-label apply")
+    b = src.index("int label_spmm_chunks(", a)
     if hashlib.sha256(src[a:b].encode()).hexdigest() != LABEL_SPMM_DIGEST:
         return None
     return LABEL_SPMM_TRAFFIC_BYTES[config]
@@ -379,6 +379,7 @@ def run_batched_workload(args, torch, fp):
         hs = []
         for plan in plans:
             h = fp.Handle(0, precision=prec)
+            h.set_core_solver(mode=args.core_mode)
             h.upload_plan(plan)
             hs.append(h)
         outs = outputs()
@@ -397,6 +398,7 @@ def run_batched_workload(args, torch, fp):
         progress(f"{prec}: per-matrix {ms_plain:.1f} ms/step; batched runs (autotune first)")
         # batched: one batch over all matrices on one handle
         h = fp.Handle(0, precision=prec)
+        h.set_core_solver(mode=args.core_mode)
         b = fp.Batch(h, plans)
         outb = outputs()
         uvs = [(U, S, V) for U, S, V, _ in outb]
@@ -570,7 +572,7 @@ def run_eval_workload(args, torch, fp):
     spmm_bytes = rows_with_label * r * 8 + tr.y_nnz * 12 + L * r * 8
     spmm_launch_us = sp_k["label_spmm"][1] / max(args.steps, 1) * 1e3   # both passes, per call
     achieved = spmm_bytes / (spmm_launch_us * 1e-6) / 1e9
-    roof = {"bound": "hbm", "kernel": "k_spmm_rows (+ k_seg_reduce_spmm)", "achieved": round(achieved, 2),
+    roof = {"bound": "hbm", "kernel": "k_label_spmm (+ k_label_reduce)", "achieved": round(achieved, 2),
             "peak": 8000.0, "unit": "GB/s", "frac": round(achieved / 8000.0, 5),
             "traffic": label_spmm_traffic(args.config), "traffic_unit": "bytes per call",
             "bytes_per_call": spmm_bytes, "us_per_call": round(spmm_launch_us, 3)}
@@ -674,6 +676,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (scale for the PMC byte counters)")
     ap.add_argument("--batch-count", type=int, default=64, help="matrices of the batched workload")
+    ap.add_argument("--core-mode", type=int, default=1, choices=[0, 1],
+                    help="core solver of the updates: 0 block Jacobi on G, 1 subspace iteration where it applies")
     ap.add_argument("--inner", default="exact", choices=["exact", "rand"],
                     help="inner solver of the two updates: exact, or the randomized branch where "
                          "the target rank is low (oversampling 5, 11 power iterations)")
@@ -752,6 +756,7 @@ def main():
         autotuned schedule and the stage chain replayed from HIP graphs."""
         progress(f"{precision} {'batched' if batched else 'plain'}: start")
         h = fp.Handle(0, precision=precision)
+        h.set_core_solver(mode=args.core_mode)
         if args.inner == "rand":
             h.set_inner(mode=1, oversample=5, iters=11, seed=0)
         h.upload_plan(plan)
@@ -856,6 +861,19 @@ def main():
             keep = s64 > 1e-6 * s64[0]
             compare[f"sigma_rel_diff_{k}"] = float(np.max(np.abs(s64[keep] - sx[keep]) / s64[keep]))
 
+    # the path's roofline time by the flop model's stages, T_roof = sum max(F_i / P_i, B_i / BW):
+    # the gather's bytes (a1), each stage's flops at the peak of its precision (mixed: the block
+    # Jacobi and the apply in FP32, the two updates' cores in FP64), frac = T_roof / T_path
+    blocks_dense = blocks[(blocks[:, 2] > 0) & (blocks[:, 3] > 0)]
+    b1 = (prob.nnz * 12 + (m + 1) * 8 + (m + n) * 4 + float(np.sum(blocks_dense[:, 2] * blocks_dense[:, 3])) * 8
+          + F["nnz_A21"] * 12 + F["nnz_T"] * 12)
+    mixed_head_form = head_key.startswith("mixed")
+    p32, p64, bw = 157.3e12, 78.6e12, 8.0e12
+    t_roof = (b1 / bw + F["a2"] / (p32 if mixed_head_form else p64) + F["a3"] / p64 + F["a4"] / p64
+              + max(F["a6"] / (p32 if mixed_head_form else p64), 8.0 * (m * cfg.L + m * r + n * r + n * cfg.L) / bw))
+    path_roof = {"t_roof_ms": round(t_roof * 1e3, 4), "t_path_ms": round(ms, 4), "frac": round(t_roof * 1e3 / ms, 4),
+                 "basis": "flop model stages at the MI355X peaks of their precision (a1 at HBM 8 TB/s)"}
+
     out = {
         "metric": "Ã⁺Y time & TFLOP/s, mixed-precision vs FP64 GPU at equal recon error",
         "value": round(tflops, 4),
@@ -881,6 +899,7 @@ def main():
         "precision_compare": compare,
         "roofline": roof,
         "roofline_mfma": roof_mfma,
+        "path_roofline": path_roof,
         "kernel_share_of_eager_step": share,
         "cpu_baseline": base,
     }

@@ -282,7 +282,6 @@ void group_free(Group& g) {
 static void free_sub(Group& g) {
     for (int c = 0; c < 2; ++c) {
         SubSet& S = g.sub[c];
-        eig_set_free(S.hset);
         eig_set_free(S.fb);
         if (S.dchol) hipFree(S.dchol);
         if (S.flags) hipFree(S.flags);
@@ -348,8 +347,7 @@ static int make_sub_core(Group& g, SubSet& S, int inst, int64_t q, int64_t t, in
     return launch_status();
 }
 
-static int finish_sub_set(Group& g, SubSet& S, std::vector<EigJob>& hjobs, std::vector<EigJob>& fbjobs,
-                          hipStream_t st) {
+static int finish_sub_set(Group& g, SubSet& S, std::vector<EigJob>& fbjobs, hipStream_t st) {
     const int nc = static_cast<int>(S.cores.size());
     if (nc == 0) return FASTPI_OK;
     void* p = nullptr;
@@ -362,11 +360,8 @@ static int finish_sub_set(Group& g, SubSet& S, std::vector<EigJob>& hjobs, std::
     S.dchol = static_cast<CholJob*>(p);
     HIP_TRY(hipMemcpyAsync(S.dchol, S.chol.data(), sizeof(CholJob) * nc, hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
-    // the Rayleigh-Ritz matrices are Grams of an orthonormal basis under G: the pivoted-Cholesky
-    // start as for every core; the fallback follows the schedule like the Jacobi cores
-    int rc = eig_set_create(S.hset, hjobs, g.tune.gram_rows, true, st);
-    if (rc == FASTPI_OK) rc = eig_set_create(S.fb, fbjobs, g.tune.gram_rows, g.tune.precond != 0, st);
-    return rc;
+    // the fallback follows the schedule like the Jacobi cores
+    return eig_set_create(S.fb, fbjobs, g.tune.gram_rows, g.tune.precond != 0, st);
 }
 
 static void free_rand(Group& g) {
@@ -418,7 +413,7 @@ static int make_rand_core(Group& g, int inst, int64_t q, int64_t t, const double
 static int build_sets(Group& g, hipStream_t st) {
     free_rand(g);
     free_sub(g);
-    std::vector<EigJob> hj[2], fj[2];
+    std::vector<EigJob> fj[2];
     eig_set_free(g.set1);
     for (void* p : g.ballocs) hipFree(p);
     g.ballocs.clear();
@@ -471,7 +466,7 @@ static int build_sets(Group& g, hipStream_t st) {
                 if (k > 0) {
                     EigJob H;
                     rc = make_sub_core(g, g.sub[0], tag, d.n1, d.s, k, ws + I.o_g2, ws + I.o_lam2, ws + I.o_v2, H, st);
-                    hj[0].push_back(H);
+                    j2.push_back(H);
                     fj[0].push_back(J);
                 } else {
                     j2.push_back(J);
@@ -494,7 +489,7 @@ static int build_sets(Group& g, hipStream_t st) {
                 if (k > 0) {
                     EigJob H;
                     rc = make_sub_core(g, g.sub[1], tag, q3, d.r, k, ws + I.o_g3, ws + I.o_lam3, ws + I.o_vt, H, st);
-                    hj[1].push_back(H);
+                    j3.push_back(H);
                     fj[1].push_back(J);
                 } else {
                     j3.push_back(J);
@@ -507,16 +502,20 @@ static int build_sets(Group& g, hipStream_t st) {
     // the Gram route of large blocks takes sigma = sqrt(lambda) down to 1e-7 of the largest and
     // divides by it, so its eigensolves start from the pivoted-Cholesky factor (relative
     // accuracy) whatever the schedule
+    // a set holding Rayleigh-Ritz matrices (Grams of an orthonormal basis under G) takes the
+    // pivoted-Cholesky start, as those jobs always have
     rc = eig_set_create(g.set1, j1, g.tune.gram_rows, true, st);
-    if (rc == FASTPI_OK) rc = eig_set_create(g.set2, j2, g.tune.gram_rows, g.tune.precond != 0, st);
-    if (rc == FASTPI_OK) rc = eig_set_create(g.set3, j3, g.tune.gram_rows, g.tune.precond != 0, st);
+    if (rc == FASTPI_OK)
+        rc = eig_set_create(g.set2, j2, g.tune.gram_rows, g.tune.precond != 0 || !g.sub[0].cores.empty(), st);
+    if (rc == FASTPI_OK)
+        rc = eig_set_create(g.set3, j3, g.tune.gram_rows, g.tune.precond != 0 || !g.sub[1].cores.empty(), st);
     // the randomized solver's basis Grams are numerically rank-deficient and its
     // orthonormalization divides by the square roots of their eigenvalues down to k eps of the
     // largest: those need relative accuracy, which the pivoted-Cholesky start gives (from G
     // itself they carry absolute errors of ~ld eps of the largest), whatever the schedule
     for (int c = 0; c < 2 && rc == FASTPI_OK; ++c)
         rc = eig_set_create(g.rset[c], jr[c], g.tune.gram_rows, true, st);
-    for (int c = 0; c < 2 && rc == FASTPI_OK; ++c) rc = finish_sub_set(g, g.sub[c], hj[c], fj[c], st);
+    for (int c = 0; c < 2 && rc == FASTPI_OK; ++c) rc = finish_sub_set(g, g.sub[c], fj[c], st);
     if (rc != FASTPI_OK) set_error("eigensolver set allocation failed");
     return rc;
 }
@@ -528,13 +527,11 @@ static int build_sets(Group& g, hipStream_t st) {
 // H = Q^T G Q, its top t eigenpairs (W, lambda) by the block Jacobi eigensolver, vectors Q W.
 // Every core's result is checked (the residual of each pair, the rank of every Cholesky QR);
 // the host reads the checks and solves the failing set again with Jacobi on G.
-static int sub_run(Group& g, int c, const RunCfg& cfg, hipStream_t st) {
+static void sub_pre(Group& g, int c, const RunCfg& cfg, KernelTimer* timer, hipStream_t st) {
     SubSet& S = g.sub[c];
-    S.fallbacks = 0;
-    if (S.cores.empty()) return FASTPI_OK;
+    if (S.cores.empty()) return;
     const bool mixed = cfg.mixed;
     const int iters = mixed ? g.core.iters_mixed : g.core.iters_fp64;
-    const double tol = mixed ? g.core.res_tol_mixed : g.core.res_tol_fp64;
     const int nc = static_cast<int>(S.cores.size());
     launch_fill_i32(S.flags, nc, 0, st);
     for (SubCore& R : S.cores) launch_gauss(R.Q, R.q * R.k, kSubSeed, static_cast<uint32_t>(c), st);
@@ -549,7 +546,7 @@ static int sub_run(Group& g, int c, const RunCfg& cfg, hipStream_t st) {
             launch_gemm_tn(cur(R), R.k, cur(R), R.k, R.k, R.k, R.q, S.chol[i].B, R.kp, nullptr, nullptr, R.part, R.sp,
                            st, false);
         }
-        launch_chol_inverse(S.dchol, nc, S.max_kp, st, cfg.timer);
+        launch_chol_inverse(S.dchol, nc, S.max_kp, st, timer);
         for (int i = 0; i < nc; ++i) {
             SubCore& R = S.cores[i];
             launch_gemm_nt(cur(R), R.k, S.chol[i].M, R.kp, R.q, R.k, R.k, oth(R), R.k, st, fp32, nullptr);
@@ -560,10 +557,10 @@ static int sub_run(Group& g, int c, const RunCfg& cfg, hipStream_t st) {
         for (SubCore& R : S.cores) {
             if (R.gsplit > 1) {
                 launch_mfma_gemm(false, false, R.G, R.q, cur(R), R.k, R.q, R.k, R.q, R.gpart, R.k, R.gsplit, R.q * R.k,
-                                 st, fp32, cfg.timer, KT_SUB_GEMM);
+                                 st, fp32, timer, KT_SUB_GEMM);
                 launch_sum_parts(R.gpart, R.gsplit, R.q, R.k, oth(R), R.k, st);
             } else {
-                launch_gemm_nn(R.G, R.q, nullptr, cur(R), R.k, R.q, R.k, R.q, oth(R), R.k, nullptr, st, fp32, cfg.timer,
+                launch_gemm_nn(R.G, R.q, nullptr, cur(R), R.k, R.q, R.k, R.q, oth(R), R.k, nullptr, st, fp32, timer,
                                KT_SUB_GEMM);
             }
         }
@@ -575,27 +572,36 @@ static int sub_run(Group& g, int c, const RunCfg& cfg, hipStream_t st) {
     }
     orth(false);
     orth(false);
+    // H = Q^T (G Q), a job of the update's batched Jacobi set
     for (SubCore& R : S.cores) {
         launch_gemm_nn(R.G, R.q, nullptr, cur(R), R.k, R.q, R.k, R.q, oth(R), R.k, nullptr, st, false);
         launch_gemm_tn(cur(R), R.k, oth(R), R.k, R.k, R.k, R.q, R.H, R.k, nullptr, nullptr, R.part, R.sp, st, false);
         launch_symmetrize(R.H, R.k, st);
     }
-    eig_begin(S.hset, st);
-    int rc = eig_iterate(S.hset, cfg.max_sweeps, g.tune.inner_sweeps, st, cfg.copy_st, cfg.timer, nullptr);
-    if (rc != FASTPI_OK) return rc;
-    eig_end(S.hset, st);
+    S.basis_in_q = in_q;
+}
+
+static int sub_post(Group& g, int c, const RunCfg& cfg, hipStream_t st) {
+    SubSet& S = g.sub[c];
+    S.fallbacks = 0;
+    if (S.cores.empty()) return FASTPI_OK;
+    const double tol = cfg.mixed ? g.core.res_tol_mixed : g.core.res_tol_fp64;
+    const int nc = static_cast<int>(S.cores.size());
+    const bool in_q = S.basis_in_q;
     for (int i = 0; i < nc; ++i) {
         SubCore& R = S.cores[i];
-        launch_gemm_nn(cur(R), R.k, nullptr, R.Wv, R.t, R.q, R.t, R.k, R.vec_out, R.t, nullptr, st, false);
-        launch_gemm_nn(R.G, R.q, nullptr, R.vec_out, R.t, R.q, R.t, R.q, oth(R), R.t, nullptr, st, false);
-        launch_sub_residual(oth(R), R.vec_out, R.lam_out, R.q, R.t, tol, S.flags + i, st);
+        const double* Qb = in_q ? R.Q : R.Y;
+        double* Rb = in_q ? R.Y : R.Q;
+        launch_gemm_nn(Qb, R.k, nullptr, R.Wv, R.t, R.q, R.t, R.k, R.vec_out, R.t, nullptr, st, false);
+        launch_gemm_nn(R.G, R.q, nullptr, R.vec_out, R.t, R.q, R.t, R.q, Rb, R.t, nullptr, st, false);
+        launch_sub_residual(Rb, R.vec_out, R.lam_out, R.q, R.t, tol, S.flags + i, st);
     }
     HIP_TRY(hipMemcpyAsync(S.host_flags, S.flags, sizeof(int) * nc, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     for (int i = 0; i < nc; ++i) S.fallbacks += S.host_flags[i] != 0 ? 1 : 0;
     if (S.fallbacks > 0) {
         eig_begin(S.fb, st);
-        rc = eig_iterate(S.fb, cfg.max_sweeps, g.tune.inner_sweeps, st, cfg.copy_st, cfg.timer, nullptr);
+        const int rc = eig_iterate(S.fb, cfg.max_sweeps, g.tune.inner_sweeps, st, cfg.copy_st, cfg.timer, nullptr);
         if (rc != FASTPI_OK) return rc;
         eig_end(S.fb, st);
     }
@@ -833,8 +839,7 @@ static void stage_front(Group& g, const double* const* val, const RunCfg& c, hip
     eig_begin(g.set1, st);
 }
 
-static void stage_front2(Group& g, const RunCfg& c, hipStream_t st) {
-    (void)c;
+static void stage_front2(Group& g, const RunCfg& c, KernelTimer* timer, hipStream_t st) {
     eig_end(g.set1, st);
     // large blocks: the other factor W = X E, then sigma and both factors into the packed
     // outputs (non-transposed: q side V, p side U; transposed: the reverse)
@@ -859,11 +864,15 @@ static void stage_front2(Group& g, const RunCfg& c, hipStream_t st) {
         launch_sparse_gram(d.seg_a21c, d.a21_rowidx, ws + I.o_vals + d.off_a21c, d.a21_rowptr, d.a21_colidx,
                            ws + I.o_vals + d.off_a21r, n1, G2, n1, true, ws + I.o_spart, st);
     }
+    // cores on the subspace route: the iteration up to the Rayleigh-Ritz matrices, which join
+    // the Jacobi set
+    sub_pre(g, 0, c, timer, st);
     eig_begin(g.set2, st);
 }
 
-static void stage_mid(Group& g, const RunCfg& c, hipStream_t st) {
-    eig_end(g.set2, st);
+// after the row-update eigensolve (and eig_end of its set): the stages up to the column
+// update's eigensolve
+static void stage_mid(Group& g, const RunCfg& c, KernelTimer* timer, hipStream_t st) {
     for (size_t idx = 0; idx < g.inst.size(); ++idx) {
         Instance& I = *g.inst[idx];
         const DevicePlan& d = I.dp;
@@ -897,12 +906,13 @@ static void stage_mid(Group& g, const RunCfg& c, hipStream_t st) {
                                G3 + s * q3 + s, q3, false, ws + I.o_spart, st);
         }
     }
+    sub_pre(g, 1, c, timer, st);
     eig_begin(g.set3, st);
 }
 
+// after the column-update eigensolve (and eig_end of its set): U, S, V
 static void stage_back(Group& g, double* const* U, double* const* S, double* const* V, const RunCfg& c,
                        hipStream_t st) {
-    eig_end(g.set3, st);
     for (size_t i = 0; i < g.inst.size(); ++i) {
         Instance& I = *g.inst[i];
         const DevicePlan& d = I.dp;
@@ -968,24 +978,8 @@ static void record_sweeps(Group& g) {
         I->rotated[0] = I->rotated[1] = 0;
         I->route[0] = I->route[1] = 0;
     }
-    // cores on the subspace route: the sweeps and pair solves of their Rayleigh-Ritz Jacobi
-    // (and of the Jacobi run again on G when the check failed)
-    for (int k = 0; k < 2; ++k) {
-        const SubSet& S = g.sub[k];
-        for (int j = 0; j < S.hset.njobs; ++j) {
-            Instance* I = g.inst[S.hset.host[j].tag];
-            I->sweeps[1 + k] = S.hset.host_state[kEigStateWords * j + kEigStSweeps];
-            I->rotated[k] = S.hset.host_state[kEigStateWords * j + kEigStTotal];
-            I->route[k] = 1;
-        }
-        if (S.fallbacks > 0)
-            for (int j = 0; j < S.fb.njobs; ++j) {
-                Instance* I = g.inst[S.fb.host[j].tag];
-                I->sweeps[1 + k] += S.fb.host_state[kEigStateWords * j + kEigStSweeps];
-                I->rotated[k] += S.fb.host_state[kEigStateWords * j + kEigStTotal];
-                I->route[k] = 2;
-            }
-    }
+    // the update sets hold the Jacobi cores and the subspace cores' Rayleigh-Ritz problems (one
+    // job per matrix and update either way); a fallback's Jacobi on G adds its sweeps
     const EigSet* sets[2] = {&g.set2, &g.set3};
     for (int k = 0; k < 2; ++k) {
         const EigSet& es = *sets[k];
@@ -994,6 +988,15 @@ static void record_sweeps(Group& g) {
             I->sweeps[1 + k] = es.host_state[kEigStateWords * j + kEigStSweeps];
             I->rotated[k] = es.host_state[kEigStateWords * j + kEigStTotal];
         }
+        const SubSet& S = g.sub[k];
+        for (const SubCore& R : S.cores) g.inst[R.inst]->route[k] = 1;
+        if (S.fallbacks > 0)
+            for (int j = 0; j < S.fb.njobs; ++j) {
+                Instance* I = g.inst[S.fb.host[j].tag];
+                I->sweeps[1 + k] += S.fb.host_state[kEigStateWords * j + kEigStSweeps];
+                I->rotated[k] += S.fb.host_state[kEigStateWords * j + kEigStTotal];
+                I->route[k] = 2;
+            }
         for (const RandCore& R : g.rcores[k]) {
             g.inst[R.inst]->sweeps[1 + k] = R.sweeps;
             g.inst[R.inst]->rotated[k] = R.rotated;
@@ -1012,18 +1015,20 @@ int group_svd(Group& g, const double* const* val, double* const* U, double* cons
         if ((rc = eig_iterate(g.set1, c.max_sweeps, g.tune.inner_sweeps, st, c.copy_st, c.timer, nullptr)) !=
             FASTPI_OK)
             return rc;
-        stage_front2(g, c, st);
+        stage_front2(g, c, c.timer, st);
         if ((rc = eig_iterate(g.set2, c.max_sweeps, g.tune.inner_sweeps, st, c.copy_st, c.timer, nullptr)) !=
             FASTPI_OK)
             return rc;
         if ((rc = rand_run(g, 0, c, st)) != FASTPI_OK) return rc;
-        if ((rc = sub_run(g, 0, c, st)) != FASTPI_OK) return rc;
-        stage_mid(g, c, st);
+        eig_end(g.set2, st);
+        if ((rc = sub_post(g, 0, c, st)) != FASTPI_OK) return rc;
+        stage_mid(g, c, c.timer, st);
         if ((rc = eig_iterate(g.set3, c.max_sweeps, g.tune.inner_sweeps, st, c.copy_st, c.timer, nullptr)) !=
             FASTPI_OK)
             return rc;
         if ((rc = rand_run(g, 1, c, st)) != FASTPI_OK) return rc;
-        if ((rc = sub_run(g, 1, c, st)) != FASTPI_OK) return rc;
+        eig_end(g.set3, st);
+        if ((rc = sub_post(g, 1, c, st)) != FASTPI_OK) return rc;
         stage_back(g, U, S, V, c, st);
         record_sweeps(g);
         return launch_status();
@@ -1050,12 +1055,13 @@ int group_svd(Group& g, const double* const* val, double* const* U, double* cons
             (rc = capture(g, [&](hipStream_t s) { eig_sweep(g.set1, c.max_sweeps, g.tune.inner_sweeps, s, nullptr); },
                           g.g_sw1)) != FASTPI_OK)
             return rc;
-        if ((rc = capture(g, [&](hipStream_t s) { stage_front2(g, c, s); }, g.g_front2)) != FASTPI_OK) return rc;
+        if ((rc = capture(g, [&](hipStream_t s) { stage_front2(g, c, nullptr, s); }, g.g_front2)) != FASTPI_OK)
+            return rc;
         if (g.set2.njobs > 0 &&
             (rc = capture(g, [&](hipStream_t s) { eig_sweep(g.set2, c.max_sweeps, g.tune.inner_sweeps, s, nullptr); },
                           g.g_sw2)) != FASTPI_OK)
             return rc;
-        if ((rc = capture(g, [&](hipStream_t s) { stage_mid(g, c, s); }, g.g_mid)) != FASTPI_OK) return rc;
+        if ((rc = capture(g, [&](hipStream_t s) { stage_mid(g, c, nullptr, s); }, g.g_mid)) != FASTPI_OK) return rc;
         if (g.set3.njobs > 0 &&
             (rc = capture(g, [&](hipStream_t s) { eig_sweep(g.set3, c.max_sweeps, g.tune.inner_sweeps, s, nullptr); },
                           g.g_sw3)) != FASTPI_OK)
@@ -1073,12 +1079,14 @@ int group_svd(Group& g, const double* const* val, double* const* U, double* cons
     RunCfg eager = c;
     eager.timer = nullptr;
     if ((rc = rand_run(g, 0, eager, st)) != FASTPI_OK) return rc;
-    if ((rc = sub_run(g, 0, eager, st)) != FASTPI_OK) return rc;
+    eig_end(g.set2, st);
+    if ((rc = sub_post(g, 0, eager, st)) != FASTPI_OK) return rc;
     if ((rc = launch_graph(g, g.g_mid, st)) != FASTPI_OK) return rc;
     if ((rc = eig_iterate(g.set3, c.max_sweeps, g.tune.inner_sweeps, st, c.copy_st, nullptr, g.g_sw3)) != FASTPI_OK)
         return rc;
     if ((rc = rand_run(g, 1, eager, st)) != FASTPI_OK) return rc;
-    if ((rc = sub_run(g, 1, eager, st)) != FASTPI_OK) return rc;
+    eig_end(g.set3, st);
+    if ((rc = sub_post(g, 1, eager, st)) != FASTPI_OK) return rc;
     if ((rc = launch_graph(g, g.g_back, st)) != FASTPI_OK) return rc;
     record_sweeps(g);
     return launch_status();

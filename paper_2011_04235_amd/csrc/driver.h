@@ -102,10 +102,12 @@ struct SubSet {
     int* flags = nullptr;           // device, one per core
     int* host_flags = nullptr;      // pinned
     int max_kp = 0;
-    EigSet hset;                    // block Jacobi on the k x k Rayleigh-Ritz matrices
+    // the k x k Rayleigh-Ritz matrices are jobs of the update's batched Jacobi set (set2 or
+    // set3), next to the cores that stay on Jacobi, so that one eigensolve serves both
     EigSet fb;                      // block Jacobi on G itself, for cores that fail the check
     std::vector<void*> allocs;
     int fallbacks = 0;              // cores solved again by Jacobi in the last run
+    bool basis_in_q = true;         // after the pre-phase: the basis is in Q (else in Y)
 };
 
 struct DevicePlan {
