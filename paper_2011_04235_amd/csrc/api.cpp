@@ -8,6 +8,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <queue>
 #include <vector>
 
 #include "driver.h"
@@ -69,8 +70,13 @@ struct fastpi_labels {
     int32_t* rows = nullptr;   // device, per label in increasing row order
     double* vals = nullptr;
     SegDev seg{};
+    // row-blocked form of the label SpMM (when no row has more than kLabelBlockPos positives):
+    // the labelled rows in blocks, each block's positives by (sub-label, row)
+    bool blocked = false;
+    LabelBlocks lb;
     std::vector<void*> allocs;
 };
+
 
 struct fastpi_batch {
     fastpi_handle* h = nullptr;   // null once the handle was destroyed (the batch is detached)
@@ -697,6 +703,144 @@ int fastpi_labels_create(fastpi_labels** out, fastpi_handle* h, int64_t m, int64
     }
     int rc = upload_segments(y->allocs, sg, y->seg, h->stream);
     if (rc != FASTPI_OK) return fail(rc);
+    // the row-blocked form: labelled rows in blocks of at most kLabelBlockRows rows and
+    // kLabelBlockPos positives, each block's positives by (sub-label, row), every block's
+    // entries starting 16-byte aligned (padding entries are never addressed by a run)
+    std::vector<int32_t> lrows, bstart;
+    int64_t maxrow = 0;
+    for (int64_t i = 0; i < m; ++i)
+        if (rowptr[i + 1] > rowptr[i]) {
+            lrows.push_back(static_cast<int32_t>(i));
+            maxrow = std::max(maxrow, rowptr[i + 1] - rowptr[i]);
+        }
+    const int64_t nl = static_cast<int64_t>(lrows.size());
+    bstart.push_back(0);
+    for (int64_t k = 0, rows = 0, pos = 0; k < nl; ++k) {
+        const int64_t d = rowptr[lrows[k] + 1] - rowptr[lrows[k]];
+        if (rows == kLabelBlockRows || pos + d > kLabelBlockPos) {
+            bstart.push_back(static_cast<int32_t>(k));
+            rows = pos = 0;
+        }
+        ++rows;
+        pos += d;
+    }
+    if (nl > 0) bstart.push_back(static_cast<int32_t>(nl));
+    const int64_t nblk = static_cast<int64_t>(bstart.size()) - 1;
+    std::vector<int32_t> bbase, rg, rv, re;   // block starts, group starts, runs (see LabelBlocks)
+    std::vector<uint8_t> prow;
+    std::vector<double> pval;
+    bool ones = true;
+    for (int64_t e = 0; e < nnz && val; ++e) ones = ones && val[e] == 1.0;
+    // sub-labels: the thread slots the launch has beyond L go to the most frequent labels,
+    // one at a time to the label with the most positives per sub-label
+    std::vector<int64_t> lcount(static_cast<size_t>(L), 0);
+    for (int64_t e = 0; e < nnz; ++e) ++lcount[col[e]];
+    std::vector<int32_t> K(static_cast<size_t>(L), 1), vbase(static_cast<size_t>(L) + 1, 0);
+    {
+        int64_t spare = label_slots(L) - L;
+        std::priority_queue<std::pair<double, int64_t>> heap;
+        for (int64_t l = 0; l < L; ++l)
+            if (lcount[l] > std::max<int64_t>(1, nblk)) heap.push({static_cast<double>(lcount[l]), l});
+        while (spare > 0 && !heap.empty()) {
+            const int64_t l = heap.top().second;
+            heap.pop();
+            ++K[l];
+            --spare;
+            const double per = static_cast<double>(lcount[l]) / K[l];
+            if (per > static_cast<double>(std::max<int64_t>(1, nblk))) heap.push({per, l});
+        }
+    }
+    for (int64_t l = 0; l < L; ++l) vbase[l + 1] = vbase[l] + K[l];
+    const int64_t Lv = vbase[L];
+    const int64_t padded = nnz + 16 * nblk;   // bound on the aligned layout's size
+    const int64_t ngroup = label_groups(Lv);
+    if (nnz > 0 && maxrow <= kLabelBlockPos && padded < INT32_MAX && nblk * (ngroup + 1) < INT32_MAX) {
+        bbase.assign(static_cast<size_t>(nblk) + 1, 0);
+        rg.assign(static_cast<size_t>(nblk * (ngroup + 1)), 0);
+        prow.assign(static_cast<size_t>(padded), 0);
+        if (!ones) pval.assign(static_cast<size_t>(padded), 0.0);
+        int64_t base = 0;
+        std::vector<int64_t> cnt(static_cast<size_t>(Lv) + 1), seen(static_cast<size_t>(L), 0);
+        std::vector<int32_t> sub;   // sub-label of each of the block's positives, in row order
+        for (int64_t b = 0; b < nblk; ++b) {
+            const int64_t k0 = bstart[b], k1 = bstart[b + 1];
+            bbase[b] = static_cast<int32_t>(base);
+            // the i-th positive of label l in the block goes to sub-label vbase[l] + i mod K_l;
+            // then a counting sort by sub-label (stable: rows stay increasing)
+            sub.clear();
+            for (int64_t k = k0; k < k1; ++k)
+                for (int64_t e = rowptr[lrows[k]]; e < rowptr[lrows[k] + 1]; ++e) {
+                    const int32_t l = col[e];
+                    sub.push_back(vbase[l] + static_cast<int32_t>(seen[l]++ % K[l]));
+                }
+            for (int64_t k = k0; k < k1; ++k)
+                for (int64_t e = rowptr[lrows[k]]; e < rowptr[lrows[k] + 1]; ++e) seen[col[e]] = 0;
+            std::fill(cnt.begin(), cnt.end(), 0);
+            for (int32_t v : sub) ++cnt[v + 1];
+            for (int64_t v = 0; v < Lv; ++v) cnt[v + 1] += cnt[v];
+            // runs: one per sub-label present, in sub-label order, then the block's sentinel
+            int64_t grp = 0;
+            for (int64_t v = 0; v < Lv; ++v) {
+                while (grp <= v / kLabelSubGroup && grp < ngroup)
+                    rg[b * (ngroup + 1) + grp++] = static_cast<int32_t>(rv.size());
+                if (cnt[v + 1] > cnt[v]) {
+                    rv.push_back(static_cast<int32_t>(v));
+                    re.push_back(static_cast<int32_t>(cnt[v]));
+                }
+            }
+            while (grp <= ngroup) rg[b * (ngroup + 1) + grp++] = static_cast<int32_t>(rv.size());
+            rv.push_back(-1);
+            re.push_back(static_cast<int32_t>(cnt[Lv]));
+            size_t q = 0;
+            for (int64_t k = k0; k < k1; ++k)
+                for (int64_t e = rowptr[lrows[k]]; e < rowptr[lrows[k] + 1]; ++e) {
+                    const int64_t d = base + cnt[sub[q++]]++;
+                    prow[d] = static_cast<uint8_t>(k - k0);
+                    if (!ones) pval[d] = val[e];
+                }
+            base = (base + static_cast<int64_t>(sub.size()) + 15) / 16 * 16;
+        }
+        bbase[nblk] = static_cast<int32_t>(base);
+        prow.resize(static_cast<size_t>(base));
+        if (!ones) pval.resize(static_cast<size_t>(base));
+        auto up = [&](const void* src, size_t bytes, void** dst) {
+            if (hipMalloc(dst, std::max<size_t>(bytes, 16)) != hipSuccess) {
+                set_error("device allocation failed (label blocks)");
+                return FASTPI_ENOMEM;
+            }
+            y->allocs.push_back(*dst);
+            if (bytes > 0 && hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, h->stream) != hipSuccess) {
+                set_error("label upload failed");
+                return FASTPI_EHIP;
+            }
+            return FASTPI_OK;
+        };
+        void* d = nullptr;
+        LabelBlocks& lb = y->lb;
+        if ((rc = up(lrows.data(), lrows.size() * sizeof(int32_t), &d)) != FASTPI_OK) return fail(rc);
+        lb.lrows = static_cast<int32_t*>(d);
+        if ((rc = up(bstart.data(), bstart.size() * sizeof(int32_t), &d)) != FASTPI_OK) return fail(rc);
+        lb.bstart = static_cast<int32_t*>(d);
+        if ((rc = up(vbase.data(), vbase.size() * sizeof(int32_t), &d)) != FASTPI_OK) return fail(rc);
+        lb.vbase = static_cast<int32_t*>(d);
+        if ((rc = up(bbase.data(), bbase.size() * sizeof(int32_t), &d)) != FASTPI_OK) return fail(rc);
+        lb.bbase = static_cast<int32_t*>(d);
+        if ((rc = up(rg.data(), rg.size() * sizeof(int32_t), &d)) != FASTPI_OK) return fail(rc);
+        lb.rg = static_cast<int32_t*>(d);
+        if ((rc = up(rv.data(), rv.size() * sizeof(int32_t), &d)) != FASTPI_OK) return fail(rc);
+        lb.rv = static_cast<int32_t*>(d);
+        if ((rc = up(re.data(), re.size() * sizeof(int32_t), &d)) != FASTPI_OK) return fail(rc);
+        lb.re = static_cast<int32_t*>(d);
+        if ((rc = up(prow.data(), prow.size(), &d)) != FASTPI_OK) return fail(rc);
+        lb.prow = static_cast<uint8_t*>(d);
+        if (!ones) {
+            if ((rc = up(pval.data(), pval.size() * sizeof(double), &d)) != FASTPI_OK) return fail(rc);
+            lb.pval = static_cast<double*>(d);
+        }
+        lb.nblk = nblk;
+        lb.Lv = Lv;
+        y->blocked = true;
+    }
     // the host tables above go out of scope: wait for the copies
     if (hipStreamSynchronize(h->stream) != hipSuccess) {
         set_error("label upload failed");
@@ -741,15 +885,20 @@ int fastpi_apply_sparse(fastpi_handle* h, int64_t m, int64_t n, int64_t r, const
         launch_fill(Z, n * L, 0.0, st);
         return check_launch();
     }
-    const size_t need = static_cast<size_t>(r + L * r + Y->seg.npart * r) * sizeof(double);
+    const int64_t npart = Y->blocked ? label_spmm_chunks(Y->lb.nblk, r, Y->lb.Lv) * Y->lb.Lv : Y->seg.npart;
+    const size_t need = static_cast<size_t>(r + L * r + npart * r) * sizeof(double);
     int rc = grow(h->aws, h->aws_bytes, need, st, "apply scratch");
     if (rc != FASTPI_OK) return rc;
     double* inv = h->aws;
     double* C = inv + r;          // L x r: Y^T U diag(S^+)
     double* part = C + L * r;
     launch_pinv_sigma(S, r, static_cast<double>(std::max(m, n)) * DBL_EPSILON, inv, st);
-    launch_fill(C, L * r, 0.0, st);   // labels without a positive keep a zero row
-    launch_spmm_rows(Y->seg, Y->rows, Y->vals, U, r, inv, C, r, nullptr, false, part, st, &h->timer);
+    if (Y->blocked) {
+        launch_label_spmm(Y->lb, U, r, L, inv, C, part, st, &h->timer);
+    } else {
+        launch_fill(C, L * r, 0.0, st);   // labels without a positive keep a zero row
+        launch_spmm_rows(Y->seg, Y->rows, Y->vals, U, r, inv, C, r, nullptr, false, part, st, &h->timer);
+    }
     launch_gemm_nt(V, r, C, r, n, L, r, Z, L, st, h->opts.precision == FASTPI_MIXED, &h->timer);
     return check_launch();
 }

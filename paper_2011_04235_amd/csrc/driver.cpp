@@ -108,7 +108,8 @@ int upload_segments(std::vector<void*>& allocs, const Segments& s, SegDev& d, hi
 bool tuning_valid(const Tuning& t) {
     return t.block_lds >= 4096 && t.block_lds <= 60 * 1024 && t.block_wgs_per_cu >= 1 &&
            t.block_wgs_per_cu <= 16 && eig_gram_rows_valid(t.gram_rows) &&
-           (t.inner_sweeps == 1 || t.inner_sweeps == 2) && (t.precond == 0 || t.precond == 1);
+           (t.inner_sweeps == 1 || t.inner_sweeps == 2) && (t.precond == 0 || t.precond == 1) &&
+           t.core_mode >= -1 && t.core_mode <= 1;
 }
 
 bool inner_valid(const InnerCfg& c) {
@@ -805,7 +806,11 @@ int group_set_tuning(Group& g, const Tuning& t, hipStream_t st) {
         set_error("invalid schedule parameters");
         return FASTPI_EINVAL;
     }
-    const bool resize = t.gram_rows != g.tune.gram_rows || t.precond != g.tune.precond;
+    bool resize = t.gram_rows != g.tune.gram_rows || t.precond != g.tune.precond;
+    if (t.core_mode >= 0 && t.core_mode != g.core.mode) {
+        g.core.mode = t.core_mode;
+        resize = true;
+    }
     g.tune = t;
     group_drop_graphs(g);
     if (resize && !g.inst.empty()) {
@@ -1113,9 +1118,15 @@ static std::string tuning_key(const Group& g, int device, bool mixed) {
         if (colon != std::string::npos) arch = arch.substr(0, colon);
     }
     std::ostringstream k;
+    // the core orders from the matrices' shapes (not from the eigensolver sets, whose jobs
+    // depend on the core route the schedule itself chooses)
+    int64_t q2 = 0, q3 = 0;
+    for (const Instance* I : g.inst) {
+        q2 = std::max(q2, I->dp.n1);
+        q3 = std::max(q3, I->dp.s + I->dp.n2);
+    }
     k << arch << ' ' << (mixed ? "mixed" : "fp64") << " inst" << log2_bucket(static_cast<int64_t>(g.inst.size()))
-      << " blk" << log2_bucket(g.ntasks) << " g2_" << log2_bucket(g.set2.max_ld) << " g3_"
-      << log2_bucket(g.set3.max_ld);
+      << " blk" << log2_bucket(g.ntasks) << " q2_" << log2_bucket(q2) << " q3_" << log2_bucket(q3);
     return k.str();
 }
 
@@ -1131,8 +1142,10 @@ int tuning_lookup(const Group& g, const char* cache, int device, bool mixed, Tun
         if (bar == std::string::npos || line.substr(0, bar) != key) continue;
         std::istringstream v(line.substr(bar + 1));
         Tuning t;
-        if (v >> t.block_lds >> t.block_wgs_per_cu >> t.gram_rows >> t.inner_sweeps >> t.precond &&
-            tuning_valid(t)) {
+        if (v >> t.block_lds >> t.block_wgs_per_cu >> t.gram_rows >> t.inner_sweeps >> t.precond) {
+            int cm = -1;
+            if (v >> cm) t.core_mode = cm;   // optional sixth field
+            if (!tuning_valid(t)) continue;
             out = t;
             found = 1;   // the last matching line wins
         }
@@ -1159,7 +1172,7 @@ static int store_tuning(const Group& g, const char* cache, int device, bool mixe
     }
     for (const std::string& l : keep) o << l << '\n';
     o << key << '|' << t.block_lds << ' ' << t.block_wgs_per_cu << ' ' << t.gram_rows << ' ' << t.inner_sweeps
-      << ' ' << t.precond << '\n';
+      << ' ' << t.precond << ' ' << t.core_mode << '\n';
     return FASTPI_OK;
 }
 
@@ -1242,9 +1255,43 @@ int group_autotune(Group& g, const double* const* val, double* const* U, double*
         }
         if (rc != FASTPI_OK) break;
         best = eig_best;
+        // 3) the core route: subspace iteration where it applies, or Jacobi on every core
+        // (in a batch the Jacobi cores of all matrices share the eigensolver's launches, which
+        // can outweigh the subspace route's smaller problems); timed only when it changes a route
+        {
+            const int other = g.core.mode == 1 ? 0 : 1;
+            CoreCfg alt = g.core;
+            alt.mode = other;
+            bool changes = false;
+            for (const Instance* I : g.inst) {
+                const DevicePlan& d = I->dp;
+                const bool a = core_basis(g.core, d.s, d.n1) > 0 || core_basis(g.core, d.r, d.s + d.n2) > 0;
+                const bool b = core_basis(alt, d.s, d.n1) > 0 || core_basis(alt, d.r, d.s + d.n2) > 0;
+                changes = changes || a != b;
+            }
+            best.core_mode = g.core.mode;
+            if (changes) {
+                Tuning cand = best;
+                cand.core_mode = other;
+                if ((rc = group_set_tuning(g, cand, st)) != FASTPI_OK) break;
+                hipEventRecord(e0, st);
+                if ((rc = group_svd(g, val, U, S, V, c)) != FASTPI_OK) break;
+                hipEventRecord(e1, st);
+                float ms = 0;
+                if (!elapsed(ms)) {
+                    rc = FASTPI_EHIP;
+                    break;
+                }
+                rep << "core=" << other << " " << ms << " ms; ";
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = cand;
+                }
+            }
+        }
         if ((rc = group_set_tuning(g, best, st)) != FASTPI_OK) break;
         rep << "chose lds=" << best.block_lds << " wgs/cu=" << best.block_wgs_per_cu << " rows=" << best.gram_rows
-            << " inner=" << best.inner_sweeps << " precond=" << best.precond;
+            << " inner=" << best.inner_sweeps << " precond=" << best.precond << " core=" << best.core_mode;
         if (cache) rc = store_tuning(g, cache, device, c.mixed, best);
     } while (false);
     hipEventDestroy(e0);

@@ -20,6 +20,7 @@ struct Tuning {
     int gram_rows = 128;         // rows per partial-Gram workgroup in the eigensolver
     int inner_sweeps = 1;        // inner Jacobi sweeps per pair solve
     int precond = 1;             // pivoted-Cholesky start of the core eigensolvers
+    int core_mode = -1;          // core solver route chosen by the autotuner (-1: the group's own)
 };
 bool tuning_valid(const Tuning& t);
 

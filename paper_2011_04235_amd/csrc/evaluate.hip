@@ -185,4 +185,187 @@ void launch_topk_hits(int64_t rows, int64_t n, int64_t L, const int64_t* a_rowpt
     }
 }
 
+// Label SpMM of the sparse-label apply, C = diag-scaled Y^T U (L x r), with every labelled
+// row of U read from memory once per call. The labelled rows (lrows) are cut into blocks of
+// at most kLabelBlockRows rows and kLabelBlockPos positives (block b: lrows[bstart[b],
+// bstart[b+1])). A frequent label is split into sub-labels (label l owns sub-labels vbase[l] ..
+// vbase[l+1] - 1; the i-th of its positives in a block goes to sub-label i mod K_l), so that no
+// run is long. Within a block the positives are sorted by sub-label, then by row (prow: the
+// row's position in the block, each block's run of entries starting at bbase[b], 16-byte
+// aligned); the block's runs, one per sub-label present, are listed in sub-label order (run i:
+// sub-label rv[i], entries re[i] .. re[i+1] - 1 relative to bbase[b]; each block's list ends
+// with a sentinel whose re is the block's count); rg[b * (ngroup + 1) + g] is the first run of
+// the block with a sub-label of group g (2048 sub-labels a group).
+// A workgroup owns kLabelCols columns of U, one group of sub-labels (accumulated in LDS) and a
+// chunk of consecutive blocks: it stages each block's slice of U and its row indices in LDS (the
+// next block's already loading into registers), and each thread sums the staged rows of the
+// runs dealt to it and adds the sum to its sub-label's accumulator. A sub-label has one run per
+// block and the blocks are taken in order between barriers, so every sum runs in a fixed order.
+// The chunks' partial sums (part, nchunk x Lv x r) are added in chunk order, and a label's
+// sub-labels in order, by k_label_reduce, which also applies the column scale cs.
+namespace {
+
+constexpr int kLabelRows = kLabelBlockRows;
+constexpr int kLabelCols = 8;
+constexpr int kLabelGroup = kLabelSubGroup;
+
+__global__ __launch_bounds__(256) void k_label_spmm(const int32_t* __restrict__ lrows, const int32_t* __restrict__ bstart,
+                                                    const int32_t* __restrict__ bbase, const int32_t* __restrict__ rg,
+                                                    const int32_t* __restrict__ rv, const int32_t* __restrict__ re,
+                                                    const uint8_t* __restrict__ prow,
+                                                    const double* __restrict__ pval,
+                                                    const double* __restrict__ U, int64_t r, int64_t Lv,
+                                                    int64_t nblk, int64_t bpc, int ncb, int ngroup, int nchunk,
+                                                    double* __restrict__ part) {
+    // XCD-grouped tile order (workgroups go to the 8 XCDs round robin by linear id): each XCD
+    // takes a contiguous range of tiles numbered chunk-major, column block fastest, so the
+    // workgroups sharing a chunk's tables run under one L2
+    const int ntile = ncb * ngroup * nchunk;
+    const int lin = blockIdx.x;
+    const int per = ntile / 8, extra = ntile % 8, xcd = lin % 8, slot = lin / 8;
+    const int tile = (xcd < extra ? xcd * (per + 1) : extra * (per + 1) + (xcd - extra) * per) + slot;
+    const int cb = tile % ncb;
+    const int g = (tile / ncb) % ngroup;
+    const int p = tile / (ncb * ngroup);
+    const int t = threadIdx.x;
+    const int64_t c0 = static_cast<int64_t>(cb) * kLabelCols;
+    const int64_t b0 = static_cast<int64_t>(p) * bpc;
+    const int64_t b1 = min(nblk, b0 + bpc);
+    const int v0 = g * kLabelGroup;
+    const int nv = static_cast<int>(min<int64_t>(kLabelGroup, Lv - v0));
+    __shared__ double acc[kLabelGroup][kLabelCols];
+    __shared__ double Us[kLabelRows + 1][kLabelCols + 1];   // padded rows; row kLabelRows stays 0
+    __shared__ uint4 Ps[kLabelBlockPos / 16 + 1];           // the block's row indices (+ slack)
+    for (int e = t; e < kLabelGroup * kLabelCols; e += 256) (&acc[0][0])[e] = 0.0;
+    if (t < kLabelCols) Us[kLabelRows][t] = 0.0;
+    // blocks ahead, in registers (a ring of three: two in flight while one is processed): the U
+    // slice row, 16 bytes of row indices and the first two runs of this thread
+    struct Ahead {
+        double u[kLabelCols];
+        uint4 p;
+        int32_t base, r0, r1, va, vb, e0a, e0b, e1a, e1b;   // runs t and t + 256 of the block
+    };
+    Ahead ra, rb, rc;   // three named slots (no indexing, so they stay in registers)
+    auto fetch = [&](int64_t b, Ahead& A) __attribute__((always_inline)) {
+        const int32_t k0 = bstart[b], k1 = bstart[b + 1];
+        const int64_t i = t < k1 - k0 ? lrows[k0 + t] : -1;
+#pragma unroll
+        for (int c = 0; c < kLabelCols; ++c) A.u[c] = (i >= 0 && c0 + c < r) ? U[i * r + c0 + c] : 0.0;
+        A.base = bbase[b];
+        const int32_t npos = bbase[b + 1] - A.base;
+        A.p = 16 * t < npos ? *reinterpret_cast<const uint4*>(prow + A.base + 16 * t) : make_uint4(0, 0, 0, 0);
+        A.r0 = rg[b * (ngroup + 1) + g];
+        A.r1 = rg[b * (ngroup + 1) + g + 1];
+        const int32_t ra0 = A.r0 + t, rb0 = A.r0 + t + 256;
+        A.va = ra0 < A.r1 ? rv[ra0] : 0;
+        A.e0a = ra0 < A.r1 ? re[ra0] : 0;
+        A.e1a = ra0 < A.r1 ? re[ra0 + 1] : 0;
+        A.vb = rb0 < A.r1 ? rv[rb0] : 0;
+        A.e0b = rb0 < A.r1 ? re[rb0] : 0;
+        A.e1b = rb0 < A.r1 ? re[rb0 + 1] : 0;
+    };
+    auto process = [&](const Ahead& A) __attribute__((always_inline)) {
+        __syncthreads();   // the previous block's staged data is no longer read
+#pragma unroll
+        for (int c = 0; c < kLabelCols; ++c) Us[t][c] = A.u[c];
+        Ps[t] = A.p;
+        __syncthreads();
+        const uint8_t* ps = reinterpret_cast<const uint8_t*>(Ps);
+        // one run: its positives' staged rows summed four at a time (their loads issue
+        // together; past the run's end the zero row is added, which leaves the sum unchanged),
+        // in order, then the sum added to the sub-label's accumulator
+        auto run = [&](int32_t v, int32_t e0, int32_t e1) __attribute__((always_inline)) {
+            double sum[kLabelCols];
+#pragma unroll
+            for (int c = 0; c < kLabelCols; ++c) sum[c] = 0.0;
+            for (int32_t e = e0; e < e1; e += 4) {
+                int j[4];
+                double w[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const bool in = e + q < e1;
+                    j[q] = in ? ps[e + q] : kLabelRows;
+                    w[q] = in ? (pval ? pval[A.base + e + q] : 1.0) : 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int c = 0; c < kLabelCols; ++c) sum[c] += w[q] * Us[j[q]][c];
+            }
+            double* a = acc[v - v0];
+#pragma unroll
+            for (int c = 0; c < kLabelCols; ++c) a[c] += sum[c];
+        };
+        if (A.r0 + t < A.r1) run(A.va, A.e0a, A.e1a);
+        if (A.r0 + t + 256 < A.r1) run(A.vb, A.e0b, A.e1b);
+        for (int32_t ri = A.r0 + t + 512; ri < A.r1; ri += 256) run(rv[ri], re[ri], re[ri + 1]);
+    };
+    if (b0 < b1) fetch(b0, ra);
+    if (b0 + 1 < b1) fetch(b0 + 1, rb);
+    for (int64_t b = b0; b < b1; b += 3) {
+        if (b + 2 < b1) fetch(b + 2, rc);
+        process(ra);
+        if (b + 1 >= b1) break;
+        if (b + 3 < b1) fetch(b + 3, ra);
+        process(rb);
+        if (b + 2 >= b1) break;
+        if (b + 4 < b1) fetch(b + 4, rb);
+        process(rc);
+    }
+    __syncthreads();
+    for (int e = t; e < nv * kLabelCols; e += 256) {
+        const int v = e / kLabelCols, c = e % kLabelCols;
+        if (c0 + c < r) part[(static_cast<int64_t>(p) * Lv + v0 + v) * r + c0 + c] = acc[v][c];
+    }
+}
+
+// C[l] = cs .* sum over chunks p, then over label l's sub-labels v in [vbase[l], vbase[l+1]),
+// of part[p][v] (Lv sub-labels in all)
+__global__ void k_label_reduce(const double* __restrict__ part, int nchunk, const int32_t* __restrict__ vbase,
+                               int64_t Lv, int64_t L, int64_t r, const double* __restrict__ cs,
+                               double* __restrict__ C) {
+    const int64_t l = blockIdx.x;
+    const int64_t k = static_cast<int64_t>(blockIdx.y) * blockDim.x + threadIdx.x;
+    if (l >= L || k >= r) return;
+    const int32_t v0 = vbase[l], v1 = vbase[l + 1];
+    double acc = 0.0;
+    for (int p = 0; p < nchunk; ++p)
+        for (int32_t v = v0; v < v1; ++v) acc += part[(static_cast<int64_t>(p) * Lv + v) * r + k];
+    C[l * r + k] = cs ? acc * cs[k] : acc;
+}
+
+}  // namespace
+
+int label_spmm_chunks(int64_t nblk, int64_t r, int64_t Lv) {
+    if (nblk <= 0) return 0;
+    const int64_t ncb = (r + kLabelCols - 1) / kLabelCols;
+    const int64_t ngroup = (Lv + kLabelGroup - 1) / kLabelGroup;
+    // one workgroup per compute unit at most (the accumulators take most of the LDS, and a
+    // second round would leave the chip mostly idle), each chunk at least one block
+    const int64_t want = 256 / (ncb * ngroup);
+    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>({want, nblk, 64})));
+}
+
+int label_slots(int64_t L) { return static_cast<int>((L + kLabelGroup - 1) / kLabelGroup * kLabelGroup); }
+
+int label_groups(int64_t Lv) { return static_cast<int>((Lv + kLabelGroup - 1) / kLabelGroup); }
+
+void launch_label_spmm(const LabelBlocks& lb, const double* U, int64_t r, int64_t L, const double* cs, double* C,
+                       double* part, hipStream_t st, KernelTimer* timer) {
+    if (r <= 0 || L <= 0) return;
+    const int nchunk = label_spmm_chunks(lb.nblk, r, lb.Lv);
+    if (nchunk == 0) {
+        launch_fill(C, L * r, 0.0, st);
+        return;
+    }
+    const int ncb = static_cast<int>((r + kLabelCols - 1) / kLabelCols);
+    const int ngroup = label_groups(lb.Lv);
+    const int64_t bpc = (lb.nblk + nchunk - 1) / nchunk;
+    const unsigned tiles = static_cast<unsigned>(ncb) * static_cast<unsigned>(ngroup) * static_cast<unsigned>(nchunk);
+    FASTPI_LAUNCH(timer, KT_LABEL_SPMM, k_label_spmm, dim3(tiles), dim3(256), 0, st, lb.lrows, lb.bstart, lb.bbase, lb.rg,
+                  lb.rv, lb.re, lb.prow, lb.pval, U, r, lb.Lv, lb.nblk, bpc, ncb, ngroup, nchunk, part);
+    FASTPI_LAUNCH(timer, KT_LABEL_SPMM, k_label_reduce, dim3(static_cast<unsigned>(L), static_cast<unsigned>((r + 255) / 256)),
+                  dim3(256), 0, st, part, nchunk, lb.vbase, lb.Lv, L, r, cs, C);
+}
+
 }  // namespace fastpi

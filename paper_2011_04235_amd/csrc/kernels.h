@@ -218,6 +218,31 @@ void launch_sparse_gram(const SegDev& sg, const int* rowidx, const double* cval,
 void launch_sparse_proj(const SegDev& sg, const int* rowidx, const double* cval, const double* U,
                         int64_t s, const double* sigma, double* G, int64_t ldg, int64_t off,
                         double* part, hipStream_t st);
+// Label SpMM over row blocks of the labelled rows (at most kLabelBlockRows rows and
+// kLabelBlockPos positives a block): C (L x r) = cs .* (Y^T U). Frequent labels are split into
+// sub-labels (label l: vbase[l] .. vbase[l+1] - 1, Lv in all, at most label_slots(L)); each
+// block lists its (sub-label, run) pairs; chunks of blocks are summed through part
+// (label_spmm_chunks(nblk, r, Lv) x Lv x r).
+constexpr int kLabelBlockRows = 256;
+constexpr int kLabelBlockPos = 4096;
+constexpr int kLabelSubGroup = 2048;   // sub-labels of one workgroup (accumulated in LDS)
+struct LabelBlocks {
+    const int32_t* lrows = nullptr;   // labelled rows, increasing (nl)
+    const int32_t* bstart = nullptr;  // first labelled row of each block (nblk + 1)
+    const int32_t* bbase = nullptr;   // first entry of each block in prow / pval, 16-aligned (nblk + 1)
+    const int32_t* rg = nullptr;      // first run of each (block, sub-label group) (nblk * (groups + 1))
+    const int32_t* rv = nullptr;      // sub-label of each run
+    const int32_t* re = nullptr;      // first entry of each run, relative to bbase (a sentinel ends a block)
+    const uint8_t* prow = nullptr;    // row within the block of each entry
+    const double* pval = nullptr;     // values, or null when every value is 1
+    const int32_t* vbase = nullptr;   // sub-labels of each label (L + 1)
+    int64_t nblk = 0, Lv = 0;
+};
+int label_spmm_chunks(int64_t nblk, int64_t r, int64_t Lv);
+int label_slots(int64_t L);
+int label_groups(int64_t Lv);
+void launch_label_spmm(const LabelBlocks& lb, const double* U, int64_t r, int64_t L, const double* cs, double* C,
+                       double* part, hipStream_t st, KernelTimer* timer);
 void launch_spmm_rows(const SegDev& sg, const int* colidx, const double* rval, const double* B,
                       int64_t N, const double* cs, double* C, int64_t ldc, const int* crow,
                       bool accumulate, double* part, hipStream_t st, KernelTimer* timer = nullptr);

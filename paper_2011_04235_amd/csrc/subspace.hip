@@ -136,22 +136,36 @@ __device__ int cq_factor_invert(double (*D)[CP + 1], double (*X)[CP + 1], double
         }
         __syncthreads();
     }
-    // block row bi: T_j = sum_{l=j}^{bi-1} L_{bi,l} X_{l,j}, then X_{bi,j} = -X_{bi,bi} T_j (j < bi)
+    // block row bi: T_j = sum_{l=j}^{bi-1} L_{bi,l} X_{l,j}, then X_{bi,j} = -X_{bi,bi} T_j (j < bi);
+    // static trip counts with predicated terms, so that each thread's LDS loads issue together
+#pragma unroll
     for (int bi = 1; bi < 4; ++bi) {
         const int r0 = bi * 16, n = bi * 16;   // columns [0, n) of block row bi
-        for (int e = tid; e < 16 * n; e += 256) {
-            const int rr = e / n, cc = e % n;
-            const int lj = cc / 16 * 16;       // first block row l = block column of cc
-            double v = 0.0;
-            for (int l = lj; l < r0; ++l) v += D[r0 + rr][l] * X[l][cc];
-            T[rr][cc] = v;
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            const int e = tid + 256 * u;
+            if (e < 16 * n) {
+                const int rr = e / n, cc = e % n;
+                const int lj = cc / 16 * 16;   // first block row l = block column of cc
+                double v = 0.0;
+#pragma unroll
+                for (int l = 0; l < r0; ++l)
+                    if (l >= lj) v += D[r0 + rr][l] * X[l][cc];
+                T[rr][cc] = v;
+            }
         }
         __syncthreads();
-        for (int e = tid; e < 16 * n; e += 256) {
-            const int rr = e / n, cc = e % n;
-            double v = 0.0;
-            for (int l = 0; l <= rr; ++l) v += X[r0 + rr][r0 + l] * T[l][cc];
-            X[r0 + rr][cc] = -v;
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            const int e = tid + 256 * u;
+            if (e < 16 * n) {
+                const int rr = e / n, cc = e % n;
+                double v = 0.0;
+#pragma unroll
+                for (int l = 0; l < 16; ++l)
+                    if (l <= rr) v += X[r0 + rr][r0 + l] * T[l][cc];
+                X[r0 + rr][cc] = -v;
+            }
         }
         __syncthreads();
     }
@@ -173,9 +187,19 @@ __global__ __launch_bounds__(256) void k_cq_panel(const CholJob* __restrict__ jo
     const int tid = threadIdx.x;
     double* B = J.B;
     double* M = J.M;
-    for (int e = tid; e < CP * CP; e += 256) {
-        const int i = e / CP, j = e % CP;
-        D[i][j] = B[static_cast<int64_t>(c0 + i) * kp + c0 + j];
+    {
+        // every thread's 16 loads in flight before the first store to LDS
+        double v[CP * CP / 256];
+#pragma unroll
+        for (int u = 0; u < CP * CP / 256; ++u) {
+            const int e = tid + 256 * u;
+            v[u] = B[static_cast<int64_t>(c0 + e / CP) * kp + c0 + e % CP];
+        }
+#pragma unroll
+        for (int u = 0; u < CP * CP / 256; ++u) {
+            const int e = tid + 256 * u;
+            D[e / CP][e % CP] = v[u];
+        }
     }
     __syncthreads();
     const int bad = cq_factor_invert(D, X, S, J.dg + c0, static_cast<double>(kp) * DBL_EPSILON);
@@ -192,9 +216,16 @@ __global__ __launch_bounds__(256) void k_cq_panel(const CholJob* __restrict__ jo
     if (tile < nrt) {
         // rows [r0, r0 + 64) of L21 = A21 X^T
         const int r0 = c1 + tile * CT;
-        for (int e = tid; e < CT * CP; e += 256) {
-            const int r = e / CP, l = e % CP;
-            S[l][r] = B[static_cast<int64_t>(r0 + r) * kp + c0 + l];
+        double v[CT * CP / 256];
+#pragma unroll
+        for (int u = 0; u < CT * CP / 256; ++u) {
+            const int e = tid + 256 * u;
+            v[u] = B[static_cast<int64_t>(r0 + e / CP) * kp + c0 + e % CP];
+        }
+#pragma unroll
+        for (int u = 0; u < CT * CP / 256; ++u) {
+            const int e = tid + 256 * u;
+            S[e % CP][e / CP] = v[u];
         }
         __syncthreads();
 #pragma unroll 8
@@ -218,9 +249,16 @@ __global__ __launch_bounds__(256) void k_cq_panel(const CholJob* __restrict__ jo
     } else {
         // columns [q0, q0 + 64) of M's block row p: M_pj = -X W_pj
         const int q0 = (tile - nrt) * CT;
-        for (int e = tid; e < CP * CT; e += 256) {
-            const int l = e / CT, cc = e % CT;
-            S[l][cc] = M[static_cast<int64_t>(c0 + l) * kp + q0 + cc];
+        double v[CP * CT / 256];
+#pragma unroll
+        for (int u = 0; u < CP * CT / 256; ++u) {
+            const int e = tid + 256 * u;
+            v[u] = M[static_cast<int64_t>(c0 + e / CT) * kp + q0 + e % CT];
+        }
+#pragma unroll
+        for (int u = 0; u < CP * CT / 256; ++u) {
+            const int e = tid + 256 * u;
+            S[e / CT][e % CT] = v[u];
         }
         __syncthreads();
 #pragma unroll 8
@@ -270,21 +308,29 @@ __global__ __launch_bounds__(256) void k_cq_update(const CholJob* __restrict__ j
         const int tj = tile - ti * (ti + 1) / 2;
         i0 = c1 + ti * CT;
         j0 = c1 + tj * CT;
-        for (int e = threadIdx.x; e < CP * CT; e += 256) {
-            const int t = e / CP, l = e % CP;
-            Ls[l][t] = B[static_cast<int64_t>(i0 + t) * kp + c0 + l];
-            Rs[l][t] = B[static_cast<int64_t>(j0 + t) * kp + c0 + l];
-        }
     } else {
         tile -= ntri;
         const int ncw = c1 / CT;
         i0 = c1 + (tile / ncw) * CT;
         j0 = (tile % ncw) * CT;
-        for (int e = threadIdx.x; e < CP * CT; e += 256) {
-            const int t = e / CP, l = e % CP;
-            Ls[l][t] = B[static_cast<int64_t>(i0 + t) * kp + c0 + l];
-            const int l2 = e / CT, t2 = e % CT;
-            Rs[l2][t2] = M[static_cast<int64_t>(c0 + l2) * kp + j0 + t2];
+    }
+    {
+        // every thread's loads in flight before the first store to LDS
+        constexpr int NU = CP * CT / 256;
+        double a[NU], bv[NU];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int e = threadIdx.x + 256 * u;
+            a[u] = B[static_cast<int64_t>(i0 + e / CP) * kp + c0 + e % CP];
+            bv[u] = wpart ? M[static_cast<int64_t>(c0 + e / CT) * kp + j0 + e % CT]
+                          : B[static_cast<int64_t>(j0 + e / CP) * kp + c0 + e % CP];
+        }
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int e = threadIdx.x + 256 * u;
+            Ls[e % CP][e / CP] = a[u];
+            if (wpart) Rs[e / CT][e % CT] = bv[u];
+            else Rs[e % CP][e / CP] = bv[u];
         }
     }
     __syncthreads();

@@ -209,3 +209,39 @@ def test_labels_edge_cases(env):
         fp.Labels(h, 2, 4, np.array([0, 1, 2]), np.array([0, 4], np.int32))
     with pytest.raises(fp.FastPIError):
         fp.Labels(h, 2, 4, np.array([0, 1, 2]), np.array([0, 1], np.int32), np.array([1.0, np.nan]))
+
+
+@pytest.mark.parametrize("m,n,r,L,density,weighted,seed", [
+    (3000, 400, 13, 2500, 0.004, True, 1),     # two label groups, ragged column block, weights
+    (5000, 300, 200, 37, 0.05, False, 2),      # few labels, many positives per label
+    (700, 200, 64, 300, 0.01, False, 3),       # fewer labelled rows than one row block
+])
+def test_label_spmm_against_oracle(env, m, n, r, L, density, weighted, seed):
+    """The sparse-label apply on random factors against the oracle's Z = V Sigma^+ U^T Y
+    (dense Y), element by element, for the row-blocked label SpMM's edge shapes: label counts
+    above one workgroup's 2048, r not a multiple of its 8 columns, a ragged last row block,
+    unlabelled rows, weighted labels; two calls give identical bits (fixed order)."""
+    torch, fp = env
+    say(f"label spmm m={m} n={n} r={r} L={L} density={density} weighted={weighted}")
+    rng = np.random.default_rng(seed)
+    U = np.linalg.qr(rng.standard_normal((m, r)))[0]
+    V = np.linalg.qr(rng.standard_normal((n, r)))[0]
+    S = np.sort(rng.uniform(0.5, 3.0, r))[::-1].copy()
+    Y = sp.random(m, L, density=density, format="csr", random_state=seed)
+    Y.data = rng.uniform(0.5, 2.0, Y.nnz) if weighted else np.ones(Y.nnz)
+    Y.sort_indices()
+    Y[: m // 10] = 0.0                                   # a band of unlabelled rows
+    Y.eliminate_zeros()
+    yp, yc = Y.indptr.astype(np.int64), Y.indices.astype(np.int32)
+    yv = Y.data.astype(np.float64) if weighted else None
+    h = fp.Handle(0)
+    labels = fp.Labels(h, m, L, yp, yc, yv)
+    Ud, Sd, Vd = dev_t(torch, U), dev_t(torch, S), dev_t(torch, V)
+    Z1 = to_np(h.apply_sparse(Ud, Sd, Vd, labels))
+    Z2 = to_np(h.apply_sparse(Ud, Sd, Vd, labels))
+    h.sync()
+    Zo = oracle.pinv_apply_sparse(U, S, V, m, n, L, yp, yc, yv)
+    err = np.max(np.abs(Z1 - Zo)) / max(np.max(np.abs(Zo)), 1e-300)
+    say(f"  max err {err:.2e}")
+    assert err <= 1e-12
+    assert np.array_equal(Z1.view(np.uint64), Z2.view(np.uint64))
