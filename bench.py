@@ -137,11 +137,11 @@ def kernel_traffic(kname, config, precision):
     return nbytes
 
 
-# HBM bytes per call of the label SpMM (both passes) on the 300000 x 10000 labelled workload
-# from the counter runs summarised in profiles/label_spmm_c5_pmc.md, with the digest of the
-# kernel source they were taken on (null for other workloads or another source).
-LABEL_SPMM_TRAFFIC_BYTES = {}
-LABEL_SPMM_DIGEST = ""
+# HBM bytes per call of the label SpMM (k_label_spmm + k_label_reduce) on the 300000 x 10000
+# labelled workload from the counter runs summarised in profiles/label_spmm_c5_pmc.md, with the
+# digest of the kernel source they were taken on (null for other workloads or another source).
+LABEL_SPMM_TRAFFIC_BYTES = {"c5": 1230828237}
+LABEL_SPMM_DIGEST = "6140b72fc1def9862d80d803a278cdcdf0cc159a4ebc6f61a2816322e6b5b226"
 
 
 def label_spmm_traffic(config):

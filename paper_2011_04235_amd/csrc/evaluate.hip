@@ -208,8 +208,9 @@ namespace {
 constexpr int kLabelRows = kLabelBlockRows;
 constexpr int kLabelCols = 8;
 constexpr int kLabelGroup = kLabelSubGroup;
+constexpr int kLabelThreads = 2 * kLabelRows;   // two threads stage each row of a block
 
-__global__ __launch_bounds__(256) void k_label_spmm(const int32_t* __restrict__ lrows, const int32_t* __restrict__ bstart,
+__global__ __launch_bounds__(kLabelThreads) void k_label_spmm(const int32_t* __restrict__ lrows, const int32_t* __restrict__ bstart,
                                                     const int32_t* __restrict__ bbase, const int32_t* __restrict__ rg,
                                                     const int32_t* __restrict__ rv, const int32_t* __restrict__ re,
                                                     const uint8_t* __restrict__ prow,
@@ -235,28 +236,30 @@ __global__ __launch_bounds__(256) void k_label_spmm(const int32_t* __restrict__ 
     const int nv = static_cast<int>(min<int64_t>(kLabelGroup, Lv - v0));
     __shared__ double acc[kLabelGroup][kLabelCols];
     __shared__ double Us[kLabelRows + 1][kLabelCols + 1];   // padded rows; row kLabelRows stays 0
-    __shared__ uint4 Ps[kLabelBlockPos / 16 + 1];           // the block's row indices (+ slack)
-    for (int e = t; e < kLabelGroup * kLabelCols; e += 256) (&acc[0][0])[e] = 0.0;
+    __shared__ uint2 Ps[kLabelBlockPos / 8 + 2];            // the block's row indices (+ slack)
+    for (int e = t; e < kLabelGroup * kLabelCols; e += kLabelThreads) (&acc[0][0])[e] = 0.0;
     if (t < kLabelCols) Us[kLabelRows][t] = 0.0;
-    // blocks ahead, in registers (a ring of three: two in flight while one is processed): the U
-    // slice row, 16 bytes of row indices and the first two runs of this thread
+    // blocks ahead, in registers (a ring of three: two in flight while one is processed): half
+    // of a U slice row, 8 bytes of row indices and the first two runs of this thread
     struct Ahead {
-        double u[kLabelCols];
-        uint4 p;
-        int32_t base, r0, r1, va, vb, e0a, e0b, e1a, e1b;   // runs t and t + 256 of the block
+        double u[kLabelCols / 2];
+        uint2 p;
+        int32_t base, r0, r1, va, vb, e0a, e0b, e1a, e1b;   // runs t and t + kLabelThreads of the block
     };
     Ahead ra, rb, rc;   // three named slots (no indexing, so they stay in registers)
     auto fetch = [&](int64_t b, Ahead& A) __attribute__((always_inline)) {
         const int32_t k0 = bstart[b], k1 = bstart[b + 1];
-        const int64_t i = t < k1 - k0 ? lrows[k0 + t] : -1;
+        const int row = t / 2, h = (t % 2) * (kLabelCols / 2);
+        const int64_t i = row < k1 - k0 ? lrows[k0 + row] : -1;
 #pragma unroll
-        for (int c = 0; c < kLabelCols; ++c) A.u[c] = (i >= 0 && c0 + c < r) ? U[i * r + c0 + c] : 0.0;
+        for (int c = 0; c < kLabelCols / 2; ++c)
+            A.u[c] = (i >= 0 && c0 + h + c < r) ? U[i * r + c0 + h + c] : 0.0;
         A.base = bbase[b];
         const int32_t npos = bbase[b + 1] - A.base;
-        A.p = 16 * t < npos ? *reinterpret_cast<const uint4*>(prow + A.base + 16 * t) : make_uint4(0, 0, 0, 0);
+        A.p = 8 * t < npos ? *reinterpret_cast<const uint2*>(prow + A.base + 8 * t) : make_uint2(0, 0);
         A.r0 = rg[b * (ngroup + 1) + g];
         A.r1 = rg[b * (ngroup + 1) + g + 1];
-        const int32_t ra0 = A.r0 + t, rb0 = A.r0 + t + 256;
+        const int32_t ra0 = A.r0 + t, rb0 = A.r0 + t + kLabelThreads;
         A.va = ra0 < A.r1 ? rv[ra0] : 0;
         A.e0a = ra0 < A.r1 ? re[ra0] : 0;
         A.e1a = ra0 < A.r1 ? re[ra0 + 1] : 0;
@@ -267,7 +270,7 @@ __global__ __launch_bounds__(256) void k_label_spmm(const int32_t* __restrict__ 
     auto process = [&](const Ahead& A) __attribute__((always_inline)) {
         __syncthreads();   // the previous block's staged data is no longer read
 #pragma unroll
-        for (int c = 0; c < kLabelCols; ++c) Us[t][c] = A.u[c];
+        for (int c = 0; c < kLabelCols / 2; ++c) Us[t / 2][(t % 2) * (kLabelCols / 2) + c] = A.u[c];
         Ps[t] = A.p;
         __syncthreads();
         const uint8_t* ps = reinterpret_cast<const uint8_t*>(Ps);
@@ -297,8 +300,8 @@ __global__ __launch_bounds__(256) void k_label_spmm(const int32_t* __restrict__ 
             for (int c = 0; c < kLabelCols; ++c) a[c] += sum[c];
         };
         if (A.r0 + t < A.r1) run(A.va, A.e0a, A.e1a);
-        if (A.r0 + t + 256 < A.r1) run(A.vb, A.e0b, A.e1b);
-        for (int32_t ri = A.r0 + t + 512; ri < A.r1; ri += 256) run(rv[ri], re[ri], re[ri + 1]);
+        if (A.r0 + t + kLabelThreads < A.r1) run(A.vb, A.e0b, A.e1b);
+        for (int32_t ri = A.r0 + t + 2 * kLabelThreads; ri < A.r1; ri += kLabelThreads) run(rv[ri], re[ri], re[ri + 1]);
     };
     if (b0 < b1) fetch(b0, ra);
     if (b0 + 1 < b1) fetch(b0 + 1, rb);
@@ -313,7 +316,7 @@ __global__ __launch_bounds__(256) void k_label_spmm(const int32_t* __restrict__ 
         process(rc);
     }
     __syncthreads();
-    for (int e = t; e < nv * kLabelCols; e += 256) {
+    for (int e = t; e < nv * kLabelCols; e += kLabelThreads) {
         const int v = e / kLabelCols, c = e % kLabelCols;
         if (c0 + c < r) part[(static_cast<int64_t>(p) * Lv + v0 + v) * r + c0 + c] = acc[v][c];
     }
@@ -362,7 +365,7 @@ void launch_label_spmm(const LabelBlocks& lb, const double* U, int64_t r, int64_
     const int ngroup = label_groups(lb.Lv);
     const int64_t bpc = (lb.nblk + nchunk - 1) / nchunk;
     const unsigned tiles = static_cast<unsigned>(ncb) * static_cast<unsigned>(ngroup) * static_cast<unsigned>(nchunk);
-    FASTPI_LAUNCH(timer, KT_LABEL_SPMM, k_label_spmm, dim3(tiles), dim3(256), 0, st, lb.lrows, lb.bstart, lb.bbase, lb.rg,
+    FASTPI_LAUNCH(timer, KT_LABEL_SPMM, k_label_spmm, dim3(tiles), dim3(kLabelThreads), 0, st, lb.lrows, lb.bstart, lb.bbase, lb.rg,
                   lb.rv, lb.re, lb.prow, lb.pval, U, r, lb.Lv, lb.nblk, bpc, ncb, ngroup, nchunk, part);
     FASTPI_LAUNCH(timer, KT_LABEL_SPMM, k_label_reduce, dim3(static_cast<unsigned>(L), static_cast<unsigned>((r + 255) / 256)),
                   dim3(256), 0, st, part, nchunk, lb.vbase, lb.Lv, L, r, cs, C);

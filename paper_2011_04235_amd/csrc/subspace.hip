@@ -63,76 +63,97 @@ __device__ int cq_factor_invert(double (*D)[CP + 1], double (*X)[CP + 1], double
     if (tid < CP) lims[tid] = lim * dg[tid];
     for (int e = tid; e < CP * CP; e += 256) X[e / CP][e % CP] = 0.0;
     __syncthreads();
-#pragma unroll 1
-    for (int bb = 0; bb < CP; bb += 16) {
-        if (w == 0) {
-            const int li = lane < 16 ? lane : 15;
-            double r[16];
+    // wave 0: factor the 16-block at bb and invert its factor (L into D, X_bb into X)
+    auto factor16 = [&](int bb) __attribute__((always_inline)) {
+        const int li = lane < 16 ? lane : 15;
+        double r[16];
 #pragma unroll
-            for (int l = 0; l < 16; ++l) r[l] = D[bb + li][bb + l];
-            const double mylim = lims[bb + li];
-            double dv[16];   // 1 / L[c][c] (the same on every lane)
-            int lost_here = 0;
+        for (int l = 0; l < 16; ++l) r[l] = D[bb + li][bb + l];
+        const double mylim = lims[bb + li];
+        double dv[16];   // 1 / L[c][c] (the same on every lane)
+        int lost_here = 0;
 #pragma unroll
-            for (int c = 0; c < 16; ++c) {
-                const double sc = lane_value(r[c], c);
-                const bool lost = !(sc > lane_value(mylim, c));
-                lost_here += lost ? 1 : 0;
-                const double piv = lost ? 1.0 : sqrt(sc);   // keeps the arithmetic finite
-                const double rp = 1.0 / piv;
-                dv[c] = rp;
-                const double l = lane > c ? r[c] * rp : (lane == c ? piv : 0.0);
-                r[c] = l;
+        for (int c = 0; c < 16; ++c) {
+            const double sc = lane_value(r[c], c);
+            const bool lost = !(sc > lane_value(mylim, c));
+            lost_here += lost ? 1 : 0;
+            const double piv = lost ? 1.0 : sqrt(sc);   // keeps the arithmetic finite
+            const double rp = 1.0 / piv;
+            dv[c] = rp;
+            const double l = lane > c ? r[c] * rp : (lane == c ? piv : 0.0);
+            r[c] = l;
 #pragma unroll
-                for (int j = c + 1; j < 16; ++j) r[j] -= l * lane_value(l, j);
-            }
-            // column `lane` of the inverse: x_i = -(sum_{l<i} L_il x_l) / L_ii, x_lane = 1 / L_ll
-            double x[16];
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                double v = 0.0;
-#pragma unroll
-                for (int l = 0; l < i; ++l) v += lane_value(r[l], i) * x[l];
-                x[i] = i < lane ? 0.0 : (i == lane ? dv[i] : -v * dv[i]);
-            }
-            if (lane < 16) {
-#pragma unroll
-                for (int l = 0; l < 16; ++l) {
-                    if (l <= lane) D[bb + lane][bb + l] = r[l];
-                    X[bb + l][bb + lane] = x[l];
-                }
-            }
-            if (lane == 0 && lost_here) nbad += lost_here;
+            for (int j = c + 1; j < 16; ++j) r[j] -= l * lane_value(l, j);
         }
-        __syncthreads();
-        // rows below: L_ib = D_ib X_bb^T, X_bb lower triangular
-        const int nr = CP - bb - 16;
-        double v3[3];
+        // column `lane` of the inverse: x_i = -(sum_{l<i} L_il x_l) / L_ii, x_lane = 1 / L_ll
+        double x[16];
 #pragma unroll
-        for (int u = 0; u < 3; ++u) {
-            const int e = tid + 256 * u;
-            v3[u] = 0.0;
-            if (e < nr * 16) {
-                const int i = bb + 16 + e / 16, j = e % 16;
-#pragma unroll
-                for (int l = 0; l < 16; ++l)
-                    if (l <= j) v3[u] += D[i][bb + l] * X[bb + j][bb + l];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < 3; ++u) {
-            const int e = tid + 256 * u;
-            if (e < nr * 16) D[bb + 16 + e / 16][bb + e % 16] = v3[u];
-        }
-        __syncthreads();
-        for (int e = tid; e < nr * nr; e += 256) {
-            const int i = bb + 16 + e / nr, j = bb + 16 + e % nr;
-            if (j > i) continue;
+        for (int i = 0; i < 16; ++i) {
             double v = 0.0;
 #pragma unroll
-            for (int l = 0; l < 16; ++l) v += D[i][bb + l] * D[j][bb + l];
-            D[i][j] -= v;
+            for (int l = 0; l < i; ++l) v += lane_value(r[l], i) * x[l];
+            x[i] = i < lane ? 0.0 : (i == lane ? dv[i] : -v * dv[i]);
+        }
+        if (lane < 16) {
+#pragma unroll
+            for (int l = 0; l < 16; ++l) {
+                if (l <= lane) D[bb + lane][bb + l] = r[l];
+                X[bb + l][bb + lane] = x[l];
+            }
+        }
+        if (lane == 0 && lost_here) nbad += lost_here;
+    };
+    // step bb: the rows below the factored block, the next diagonal block's update, then (with
+    // one step of lookahead) wave 0 factors the next block while the other waves update the
+    // rest of the trailing part, which that factorisation does not touch; the first step only
+    // factors the first block
+#pragma unroll 1
+    for (int bb = -16; bb + 16 < CP; bb += 16) {
+        const int nr = CP - bb - 16;   // rows below the 16-block at bb
+        if (bb >= 0) {
+            // rows below: L_ib = D_ib X_bb^T, X_bb lower triangular
+            double v3[3];
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                const int e = tid + 256 * u;
+                v3[u] = 0.0;
+                if (e < nr * 16) {
+                    const int i = bb + 16 + e / 16, j = e % 16;
+#pragma unroll
+                    for (int l = 0; l < 16; ++l)
+                        if (l <= j) v3[u] += D[i][bb + l] * X[bb + j][bb + l];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                const int e = tid + 256 * u;
+                if (e < nr * 16) D[bb + 16 + e / 16][bb + e % 16] = v3[u];
+            }
+            __syncthreads();
+            // the next diagonal block, rows and columns [bb + 16, bb + 32), minus L L^T
+            const int i = bb + 16 + tid / 16, j = bb + 16 + tid % 16;
+            if (j <= i) {
+                double v = 0.0;
+#pragma unroll
+                for (int l = 0; l < 16; ++l) v += D[i][bb + l] * D[j][bb + l];
+                D[i][j] -= v;
+            }
+            __syncthreads();
+        }
+        if (w == 0) {
+            factor16(bb + 16);
+        } else if (bb >= 0) {
+            // rows [bb + 32, CP) of the trailing lower triangle
+            const int nr2 = nr - 16;
+            for (int e = tid - 64; e < nr2 * nr; e += 192) {
+                const int i = bb + 32 + e / nr, j = bb + 16 + e % nr;
+                if (j > i) continue;
+                double v = 0.0;
+#pragma unroll
+                for (int l = 0; l < 16; ++l) v += D[i][bb + l] * D[j][bb + l];
+                D[i][j] -= v;
+            }
         }
         __syncthreads();
     }
