@@ -114,8 +114,10 @@ BW = 16                  # eigensolver column block
 TRAFFIC = {
     ("eig_solve", "c2", "fp64"): (3193787, "eig.hip", "void k_eig_solve(", "__global__",
                                   "8bb7f99cd14505103cbd1fba4f72c7c948042797cdac6d75b001a228722dc40a"),
-    ("cq_panel", "c3", "mixed"): (1518045, "subspace.hip", "__device__ int cq_factor_invert(", "// After panel p:",
-                                  "ffb9071d7575d26a9a3c2a8f7592525a2c9c9c53aea93f439fb8dbec100cbed0"),
+    ("cq_panel", "c3", "mixed"): (1850880, "subspace.hip", "__device__ int cq_factor_invert(", "// After panel p:",
+                                  "e30cd272f1eba6ff24a6d3cf541743028e1c68f324311ce9e44280b2cffe7132"),
+    ("eig_solve", "c3", "mixed"): (1752064, "eig.hip", "void k_eig_solve(", "__global__",
+                                   "8bb7f99cd14505103cbd1fba4f72c7c948042797cdac6d75b001a228722dc40a"),
     ("sub_gemm", "c3", "mixed"): (328228707, "mfma_gemm.hip", "template <typename Tc, bool TA, bool TB>",
                                   "// C (M x N, ldc) = op(A) op(B)",
                                   "fd7925f0523d4073a12f38d53a4c415d2ecb720249ca91724cf59e4bf085578f"),
