@@ -245,3 +245,33 @@ def test_label_spmm_against_oracle(env, m, n, r, L, density, weighted, seed):
     say(f"  max err {err:.2e}")
     assert err <= 1e-12
     assert np.array_equal(Z1.view(np.uint64), Z2.view(np.uint64))
+
+
+def test_label_spmm_segmented_fallback_against_oracle(env):
+    """A label matrix with a row of more than 4096 positives keeps the segmented label SpMM
+    (no row block can hold that row); Z against the oracle element by element, repeatable."""
+    torch, fp = env
+    m, n, r, L, seed = 900, 150, 24, 6000, 5
+    say(f"label spmm segmented form m={m} L={L} (one row with 5000 positives)")
+    rng = np.random.default_rng(seed)
+    U = np.linalg.qr(rng.standard_normal((m, r)))[0]
+    V = np.linalg.qr(rng.standard_normal((n, r)))[0]
+    S = np.sort(rng.uniform(0.5, 3.0, r))[::-1].copy()
+    Y = sp.random(m, L, density=0.002, format="lil", random_state=seed)
+    Y[7, :5000] = 1.0
+    Y = Y.tocsr()
+    Y.data[:] = 1.0
+    Y.sort_indices()
+    yp, yc = Y.indptr.astype(np.int64), Y.indices.astype(np.int32)
+    assert np.max(np.diff(yp)) > 4096
+    h = fp.Handle(0)
+    labels = fp.Labels(h, m, L, yp, yc)
+    Ud, Sd, Vd = dev_t(torch, U), dev_t(torch, S), dev_t(torch, V)
+    Z1 = to_np(h.apply_sparse(Ud, Sd, Vd, labels))
+    Z2 = to_np(h.apply_sparse(Ud, Sd, Vd, labels))
+    h.sync()
+    Zo = oracle.pinv_apply_sparse(U, S, V, m, n, L, yp, yc)
+    err = np.max(np.abs(Z1 - Zo)) / max(np.max(np.abs(Zo)), 1e-300)
+    say(f"  max err {err:.2e}")
+    assert err <= 1e-12
+    assert np.array_equal(Z1.view(np.uint64), Z2.view(np.uint64))
