@@ -682,6 +682,8 @@ def main():
                     help="core solver of the updates: 0 block Jacobi on G, 1 subspace iteration where it applies")
     ap.add_argument("--core-max-frac", type=float, default=None,
                     help="largest basis-to-order ratio k/q of the subspace route (default: the library's)")
+    ap.add_argument("--core-min-order", type=int, default=None,
+                    help="smallest core order q of the subspace route (default: the library's)")
     ap.add_argument("--inner", default="exact", choices=["exact", "rand"],
                     help="inner solver of the two updates: exact, or the randomized branch where "
                          "the target rank is low (oversampling 5, 11 power iterations)")
@@ -761,7 +763,8 @@ def main():
         progress(f"{precision} {'batched' if batched else 'plain'}: start")
         h = fp.Handle(0, precision=precision)
         h.set_core_solver(mode=args.core_mode,
-                          **({"max_frac": args.core_max_frac} if args.core_max_frac is not None else {}))
+                          **({"max_frac": args.core_max_frac} if args.core_max_frac is not None else {}),
+                          **({"min_order": args.core_min_order} if args.core_min_order is not None else {}))
         if args.inner == "rand":
             h.set_inner(mode=1, oversample=5, iters=11, seed=0)
         h.upload_plan(plan)

@@ -203,8 +203,7 @@ def load(path: str = LIB_PATH):
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise FastPIError(-7, f"{path} is not built; run paper_2011_04235_amd/build.py "
-                              "or __graft_entry__.build()")
+        raise FastPIError(-7, f"{path} is not built; run paper_2011_04235_amd/build.py")
     lib = ctypes.CDLL(path)
     for name, res, args in SIGNATURES:
         fn = getattr(lib, name)

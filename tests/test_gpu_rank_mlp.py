@@ -109,7 +109,6 @@ def test_training_beats_alpha_rule_and_gains_on_held_out_matrices(env):
         say(f"  matrix {i}: A11 loss network {e_net:.4g}, alpha rule {e_alpha:.4g}, optimum {e_opt:.4g}")
     say(f"  mean loss ratio network / alpha rule: {np.mean(ratios):.3f}")
     assert np.mean(ratios) < 0.9
-    pred.save(os.path.join("gpurun_out", "rank_predictor.npz")) if os.path.isdir("gpurun_out") else None
 
 
 def test_learned_ranks_end_to_end(env):
