@@ -143,7 +143,7 @@ def kernel_traffic(kname, config, precision):
 # labelled workload from the counter runs summarised in profiles/label_spmm_c5_pmc.md, with the
 # digest of the kernel source they were taken on (null for other workloads or another source).
 LABEL_SPMM_TRAFFIC_BYTES = {"c5": 1230828237}
-LABEL_SPMM_DIGEST = "6140b72fc1def9862d80d803a278cdcdf0cc159a4ebc6f61a2816322e6b5b226"
+LABEL_SPMM_DIGEST = "a3b3a0e0565694f0ea9b3e92443b5a19ef557d51d928d384045c64e120312663"
 
 
 def label_spmm_traffic(config):

@@ -196,10 +196,11 @@ void launch_topk_hits(int64_t rows, int64_t n, int64_t L, const int64_t* a_rowpt
 // sub-label rv[i], entries re[i] .. re[i+1] - 1 relative to bbase[b]; each block's list ends
 // with a sentinel whose re is the block's count); rg[b * (ngroup + 1) + g] is the first run of
 // the block with a sub-label of group g (2048 sub-labels a group).
-// A workgroup owns kLabelCols columns of U, one group of sub-labels (accumulated in LDS) and a
-// chunk of consecutive blocks: it stages each block's slice of U and its row indices in LDS (the
-// next block's already loading into registers), and each thread sums the staged rows of the
-// runs dealt to it and adds the sum to its sub-label's accumulator. A sub-label has one run per
+// A workgroup of kLabelThreads threads owns kLabelCols columns of U, one group of sub-labels
+// (accumulated in LDS) and a chunk of consecutive blocks: it stages each block's slice of U
+// (two threads to a row) and its row indices in LDS (the next two blocks already loading into
+// registers), and each thread sums the staged rows of the runs dealt to it and adds the sum to
+// its sub-label's accumulator. A sub-label has one run per
 // block and the blocks are taken in order between barriers, so every sum runs in a fixed order.
 // The chunks' partial sums (part, nchunk x Lv x r) are added in chunk order, and a label's
 // sub-labels in order, by k_label_reduce, which also applies the column scale cs.
