@@ -109,24 +109,32 @@ BW = 16                  # eigensolver column block
 # HBM bytes per launch of a timed kernel, from the two counter runs summarised under
 # profiles/ (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the scales read off a 256 MiB device copy in
 # the same runs), keyed by (kernel, workload, precision of the timed form), with the digest
-# of the kernel source they were taken on; the figure is dropped (null) for any other
-# workload and as soon as the kernel's source differs.
+# of the kernel source they were taken on and the core-solver settings of that run (they set
+# the basis sizes, hence the bytes of a launch); the figure is dropped (null) for any other
+# workload, as soon as the kernel's source differs, and for other core-solver settings.
+TRAFFIC_CORE = {"mode": 1, "min_order": 1024, "k_factor": 2.0, "k_factor_mixed": 1.5, "max_frac": 0.65,
+                "iters_fp64": 28, "iters_mixed": 18, "orth_every": 2}
 TRAFFIC = {
-    ("eig_solve", "c2", "fp64"): (3193787, "eig.hip", "void k_eig_solve(", "__global__",
-                                  "8bb7f99cd14505103cbd1fba4f72c7c948042797cdac6d75b001a228722dc40a"),
-    ("cq_panel", "c3", "mixed"): (1850880, "subspace.hip", "__device__ int cq_factor_invert(", "// After panel p:",
+    ("cq_panel", "c3", "mixed"): (1613722, "subspace.hip", "__device__ int cq_factor_invert(", "// After panel p:",
                                   "e30cd272f1eba6ff24a6d3cf541743028e1c68f324311ce9e44280b2cffe7132"),
-    ("eig_solve", "c3", "mixed"): (1752064, "eig.hip", "void k_eig_solve(", "__global__",
-                                   "8bb7f99cd14505103cbd1fba4f72c7c948042797cdac6d75b001a228722dc40a"),
-    ("sub_gemm", "c3", "mixed"): (328228707, "mfma_gemm.hip", "template <typename Tc, bool TA, bool TB>",
+    ("eig_solve", "c3", "mixed"): (1087283, "eig.hip", "__device__ __forceinline__ void pair_solve(",
+                                   "// X[:, I u J] <- X[:, I u J] W over a tile",
+                                   "c2f5ba0ce77ef0efbbd63cf84a9049359fb102d74557ba2d6f2ea1dfaf8a4f72"),
+    ("eig_round", "c3", "mixed"): (11164570, "eig.hip",
+                                   "template <int ROWS>\n__global__ __launch_bounds__(256) void k_eig_round(",
+                                   "// End of a sweep:",
+                                   "4a92ac0365fbc8a47656ae36c9ce1a75a33b9b20be34470f03ccecc02601554b"),
+    ("sub_gemm", "c3", "mixed"): (285009510, "mfma_gemm.hip", "template <typename Tc, bool TA, bool TB>",
                                   "// C (M x N, ldc) = op(A) op(B)",
                                   "fd7925f0523d4073a12f38d53a4c415d2ecb720249ca91724cf59e4bf085578f"),
 }
 
 
-def kernel_traffic(kname, config, precision):
+def kernel_traffic(kname, config, precision, core=None):
     key = (kname, config, precision)
     if key not in TRAFFIC:
+        return None
+    if core is not None and any(abs(float(core.get(f, -1)) - float(v)) > 1e-12 for f, v in TRAFFIC_CORE.items()):
         return None
     import hashlib
     nbytes, fname, start, end, digest = TRAFFIC[key]
@@ -166,31 +174,44 @@ def eig_shape(q, gram_rows=128):
     return ld, nblk, nbe // 2, nbe - 1, (ld + gram_rows - 1) // gram_rows
 
 
-def solve_alg_flops(info, sweeps, rotated, tuning):
-    """Algorithmic flops of the k_eig_solve launches of one run: every pair solve that ran
-    does one inner sweep (PAIR_SWEEP_FLOPS per inner sweep), and every pair checked in a
-    round of a sweep sums its row-chunk partial Grams (nchunk * 1024 flops). rotated = pair
-    solves that ran per core; checked = sweeps x rounds x real pairs per core."""
-    tot = 0.0
+def eig_job_flops(order, sw, rot, tuning, kernel):
+    """Algorithmic flops of one eigensolve's launches of `kernel` over a run of `sw` sweeps
+    in which `rot` pair solves ran (the others found their pair orthogonal already).
+    k_eig_solve: every pair solve that ran does its inner sweeps (PAIR_SWEEP_FLOPS each), and
+      every pair checked in a round sums its row-chunk partial Grams (nchunk * 1024 flops);
+    k_eig_round (a round's column update fused with the next round's partial Grams): every
+      pair's partial Grams over the ld rows (2 ld 32^2 per pair and round) and the column
+      update of every pair that rotated (2 ld 32^2)."""
+    ld, nblk, npairs, rounds, nchunk = eig_shape(order, tuning.get("gram_rows", GRAM_ROWS))
+    real_pairs = nblk // 2 + (nblk & 1)          # the odd block out still solves alone
     inner = tuning.get("inner_sweeps", 1)
+    if kernel == "eig_solve":
+        return rot * inner * PAIR_SWEEP_FLOPS + sw * rounds * real_pairs * nchunk * 1024
+    return sw * rounds * real_pairs * 2.0 * ld * 1024 + rot * 2.0 * ld * 1024
+
+
+def solve_alg_flops(info, sweeps, rotated, tuning, kernel="eig_solve"):
+    """Algorithmic flops of the eigensolver launches of `kernel` in one run of a matrix whose
+    cores both ran on Jacobi at their full order (eig_job_flops per core)."""
+    tot = 0.0
     for q, sw, rot in ((info["n1"], sweeps[1], rotated[0]), (info["s"] + info["n2"], sweeps[2], rotated[1])):
         if q <= 0 or sw <= 0:
             continue
-        ld, nblk, npairs, rounds, nchunk = eig_shape(q, tuning.get("gram_rows", GRAM_ROWS))
-        real_pairs = nblk // 2 + (nblk & 1)          # the odd block out still solves alone
-        tot += rot * inner * PAIR_SWEEP_FLOPS + sw * rounds * real_pairs * nchunk * 1024
+        tot += eig_job_flops(q, sw, rot, tuning, kernel)
     return tot
 
 
-ROOF_KERNELS = ["cq_panel", "sub_gemm", "eig_solve"]
-KERNEL_NAMES = {"cq_panel": "k_cq_panel", "sub_gemm": "k_mfma_gemm (products by G)", "eig_solve": "k_eig_solve"}
+ROOF_KERNELS = ["cq_panel", "sub_gemm", "eig_round", "eig_solve"]
+KERNEL_NAMES = {"cq_panel": "k_cq_panel", "sub_gemm": "k_mfma_gemm (products by G)", "eig_solve": "k_eig_solve",
+                "eig_round": "k_eig_round"}
 
 
-def core_basis(core, t, q):
-    """Basis size of the subspace route (the library's rule), 0 when the core stays on Jacobi."""
+def core_basis(core, t, q, mixed):
+    """Basis size of the subspace route (the library's rule, with the factor of the precision
+    form), 0 when the core stays on Jacobi."""
     if core["mode"] == 0 or q < core["min_order"] or t <= 0:
         return 0
-    k = (int(math.ceil(core["k_factor"] * t)) + 31) // 32 * 32
+    k = (int(math.ceil(core["k_factor_mixed" if mixed else "k_factor"] * t)) + 31) // 32 * 32
     return k if (k > t and k <= core["max_frac"] * q) else 0
 
 
@@ -200,18 +221,17 @@ def kernel_alg_flops(info, routes, core, mixed, tuning, sweeps, rotated):
     cq_panel: per Cholesky-QR panel launch, the factorisation and inversion of the 64 x 64
       diagonal block (2 * 64^3 / 3) and one 64 x 64 x 64 product (2 * 64^3) for each of the
       kp / 64 - 1 tiles of the panel (its L21 rows and its block row of L^-1);
-    eig_solve: as solve_alg_flops, at the order the Jacobi ran on (k for a subspace core's
-      Rayleigh-Ritz matrix, q otherwise)."""
+    eig_round, eig_solve: as eig_job_flops, at the order the Jacobi ran on (k for a subspace
+      core's Rayleigh-Ritz matrix, q otherwise)."""
     iters = core["iters_mixed"] if mixed else core["iters_fp64"]
     oe = core["orth_every"]
-    out = {"sub_gemm": 0.0, "cq_panel": 0.0, "eig_solve": 0.0}
-    inner = tuning.get("inner_sweeps", 1)
+    out = {"sub_gemm": 0.0, "cq_panel": 0.0, "eig_solve": 0.0, "eig_round": 0.0}
     for c, (q, t) in enumerate(((info["n1"], info["s"]), (info["s"] + info["n2"], info["r"]))):
         if q <= 0 or t <= 0:
             continue
         order = q
         if routes[c] in ("subspace", "subspace+jacobi"):
-            k = core_basis(core, t, q)
+            k = core_basis(core, t, q, mixed)
             kp = (k + 63) // 64 * 64
             out["sub_gemm"] += iters * 2.0 * q * q * k
             n_orth = (iters + oe - 1) // oe + 2
@@ -219,13 +239,12 @@ def kernel_alg_flops(info, routes, core, mixed, tuning, sweeps, rotated):
             order = k
         sw = sweeps[1 + c]
         if sw > 0:
-            ld, nblk, npairs, rounds, nchunk = eig_shape(order, tuning.get("gram_rows", GRAM_ROWS))
-            real_pairs = nblk // 2 + (nblk & 1)
-            out["eig_solve"] += rotated[c] * inner * PAIR_SWEEP_FLOPS + sw * rounds * real_pairs * nchunk * 1024
+            for kname in ("eig_solve", "eig_round"):
+                out[kname] += eig_job_flops(order, sw, rotated[c], tuning, kname)
     return out
 
 
-def roofline_entry(kname, kms, alg, mixed, config, head_key):
+def roofline_entry(kname, kms, alg, mixed, config, head_key, core=None):
     """Roofline object of one timed kernel: algorithmic flops per step over its summed launch
     time per step, against the peak of its unit."""
     n_launch, k_ms = kms[kname]
@@ -236,7 +255,7 @@ def roofline_entry(kname, kms, alg, mixed, config, head_key):
         bound, peak = "alu", 78.6                          # FP64 vector peak
     return {"bound": bound, "kernel": KERNEL_NAMES[kname], "achieved": round(achieved, 5), "peak": peak,
             "unit": "TFLOP/s", "frac": round(achieved / peak, 6),
-            "traffic": kernel_traffic(kname, config, "mixed" if mixed else "fp64"),
+            "traffic": kernel_traffic(kname, config, "mixed" if mixed else "fp64", core),
             "traffic_unit": "bytes per launch", "launches": round(n_launch, 1),
             "avg_us": round(k_ms / max(n_launch, 1) * 1e3, 3), "ms_per_step": round(k_ms, 4),
             "flops_per_launch": alg[kname] / max(n_launch, 1),
@@ -381,6 +400,7 @@ def run_batched_workload(args, torch, fp):
         hs = []
         for plan in plans:
             h = fp.Handle(0, precision=prec)
+            h.set_tuning(eig_fused=int(args.eig_rounds == "fused"))
             h.set_core_solver(mode=args.core_mode)
             h.upload_plan(plan)
             hs.append(h)
@@ -402,6 +422,7 @@ def run_batched_workload(args, torch, fp):
         h = fp.Handle(0, precision=prec)
         h.set_core_solver(mode=args.core_mode)
         b = fp.Batch(h, plans)
+        b.set_tuning(eig_fused=int(args.eig_rounds == "fused"))
         outb = outputs()
         uvs = [(U, S, V) for U, S, V, _ in outb]
         vals = [d[2] for d in dev_in]
@@ -440,17 +461,19 @@ def run_batched_workload(args, torch, fp):
                      "tune_report": tune_report, "graph_launches_per_step": graph_launches,
                      "n_launch": n_launch, "k_ms": k_ms, "sigma_rel_diff_plain_vs_batched": sig_diff,
                      "solve_alg_flops": eager_steps * sum(
-                         solve_alg_flops(plan.info, sw.tolist(), rot.tolist(), b.get_tuning())
+                         solve_alg_flops(plan.info, sw.tolist(), rot.tolist(), b.get_tuning(),
+                                         args.roofline_kernel)
                          for plan, sw, rot in zip(plans, sweeps, rotated))}
         del b, h
     head_key = "mixed" if "mixed" in res else "fp64"
     head = res[head_key]
     ms = head["batched_ms"]
     roof = None
-    if head["n_launch"] > 0 and args.roofline_kernel == "eig_solve":
+    if head["n_launch"] > 0 and args.roofline_kernel in ("eig_solve", "eig_round"):
         f_alg = head["solve_alg_flops"]
         achieved = f_alg / (head["k_ms"] * 1e-3) / 1e12
-        roof = {"bound": "alu", "kernel": "k_eig_solve", "achieved": round(achieved, 5), "peak": 78.6,
+        roof = {"bound": "alu", "kernel": KERNEL_NAMES[args.roofline_kernel], "achieved": round(achieved, 5),
+                "peak": 78.6,
                 "unit": "TFLOP/s", "frac": round(achieved / 78.6, 6), "traffic": None,
                 "launches": head["n_launch"], "avg_us": round(head["k_ms"] / head["n_launch"] * 1e3, 3),
                 "flops_per_launch": f_alg / head["n_launch"],
@@ -672,18 +695,26 @@ def main():
     ap.add_argument("--cpu-full-single", action="store_true",
                     help="run every stage of the single-thread oracle, whatever its time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--roofline-kernel", default="eig_solve",
-                    choices=["eig_solve", "eig_gram", "eig_update", "block_svd", "cq_panel", "sub_gemm"],
+    ap.add_argument("--roofline-kernel", default="eig_round",
+                    choices=["eig_round", "eig_solve", "eig_gram", "eig_update", "block_svd", "cq_panel", "sub_gemm"],
                     help="kernel timed for the roofline of the batched 64-matrix workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (scale for the PMC byte counters)")
     ap.add_argument("--batch-count", type=int, default=64, help="matrices of the batched workload")
+    ap.add_argument("--eig-rounds", default="fused", choices=["fused", "three"],
+                    help="eigensolver rounds: two launches each (column update fused with the next "
+                         "round's partial Grams, then the pair solves; default) or three")
     ap.add_argument("--core-mode", type=int, default=1, choices=[0, 1],
                     help="core solver of the updates: 0 block Jacobi on G, 1 subspace iteration where it applies")
     ap.add_argument("--core-max-frac", type=float, default=None,
                     help="largest basis-to-order ratio k/q of the subspace route (default: the library's)")
     ap.add_argument("--core-min-order", type=int, default=None,
                     help="smallest core order q of the subspace route (default: the library's)")
+    ap.add_argument("--core-k-factor", type=float, default=None,
+                    help="basis of the subspace route in the form being run, k = ceil32(factor * t) "
+                         "(default: the library's)")
+    ap.add_argument("--core-iters", type=int, default=None,
+                    help="products by G of the subspace route in the form being run (default: the library's)")
     ap.add_argument("--inner", default="exact", choices=["exact", "rand"],
                     help="inner solver of the two updates: exact, or the randomized branch where "
                          "the target rank is low (oversampling 5, 11 power iterations)")
@@ -762,9 +793,14 @@ def main():
         autotuned schedule and the stage chain replayed from HIP graphs."""
         progress(f"{precision} {'batched' if batched else 'plain'}: start")
         h = fp.Handle(0, precision=precision)
+        h.set_tuning(eig_fused=int(args.eig_rounds == "fused"))
         h.set_core_solver(mode=args.core_mode,
                           **({"max_frac": args.core_max_frac} if args.core_max_frac is not None else {}),
-                          **({"min_order": args.core_min_order} if args.core_min_order is not None else {}))
+                          **({"min_order": args.core_min_order} if args.core_min_order is not None else {}),
+                          **({("k_factor_mixed" if precision == "mixed" else "k_factor"): args.core_k_factor}
+                             if args.core_k_factor is not None else {}),
+                          **({("iters_mixed" if precision == "mixed" else "iters_fp64"): args.core_iters}
+                             if args.core_iters is not None else {}))
         if args.inner == "rand":
             h.set_inner(mode=1, oversample=5, iters=11, seed=0)
         h.upload_plan(plan)
@@ -842,8 +878,8 @@ def main():
     share = {k: round(v[1] / head["eager_ms"], 4) for k, v in kms.items()}
     # the dominant kernel: the largest summed launch time per step among the timed ones
     dom = max((k for k in kms if kms[k][0] > 0), key=lambda k: kms[k][1], default=None)
-    roof = roofline_entry(dom, kms, alg, mixed_head, args.config, head_key) if dom else None
-    roof_mfma = roofline_entry("sub_gemm", kms, alg, mixed_head, args.config, head_key) \
+    roof = roofline_entry(dom, kms, alg, mixed_head, args.config, head_key, head["core"]) if dom else None
+    roof_mfma = roofline_entry("sub_gemm", kms, alg, mixed_head, args.config, head_key, head["core"]) \
         if kms.get("sub_gemm", (0, 0))[0] > 0 else None
     base = None
     if not args.no_cpu_baseline:

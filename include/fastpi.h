@@ -69,7 +69,8 @@ typedef struct {
                                   /* eps); every eigensolver (the cores of both updates, the */
                                   /* Gram route of large blocks, the randomized solver's     */
                                   /* small problems) above tol itself (default: its padded   */
-                                  /* order * FP64 eps)                                       */
+                                  /* order * FP64 eps; 1e-8 for the Rayleigh-Ritz problems   */
+                                  /* of FASTPI_MIXED's subspace core solver)                 */
     size_t max_workspace_bytes;   /* 0 = unlimited; larger needs fail with FASTPI_ENOMEM     */
 } fastpi_options;
 
@@ -82,6 +83,10 @@ typedef struct {
     int32_t inner_sweeps;       /* Jacobi sweeps per 32 x 32 pair solve: 1 or 2                    */
     int32_t precond;            /* 1: run the core Jacobi on R^T of a pivoted Cholesky G = R^T R  */
                                 /* (fewer sweeps); 0: on G itself                                 */
+    int32_t eig_fused;          /* 1 (default): two launches per eigensolver round (the column    */
+                                /* update fused with the next round's partial Grams, on two       */
+                                /* iterates; the pair solves); 0: three launches per round on one */
+                                /* iterate. Same results bitwise                                  */
 } fastpi_tuning;
 
 /*
@@ -407,7 +412,8 @@ int fastpi_last_rotations(fastpi_handle* h, int64_t* out2);
  * update, 3 = block SVD launches, 4 = the label SpMM of fastpi_apply_sparse (both passes),
  * 5 = fastpi_topk_hits, 6 = the transposed-B GEMM of fastpi_apply_sparse, 7 = the products by G
  * of the subspace core solver (fastpi_set_core_solver), 8 = its Cholesky-QR panel kernel,
- * -1 = off.
+ * 9 = the eigensolver's fused column update and partial Grams (fastpi_tuning.eig_fused = 1,
+ * the default; kinds 0 and 2 then time nothing), -1 = off.
  * Starting discards earlier timings.
  */
 int fastpi_timing_start(fastpi_handle* h, int kind);
@@ -454,14 +460,16 @@ int fastpi_batch_set_block_route(fastpi_batch* b, double min_cost);
 /*
  * Core solver of the exact branch (the truncated SVD of M2 and of X3, Eqs. 2-3, taken as the
  * top t eigenpairs of their Gram matrix G of order q). mode 0: block one-sided Jacobi on G
- * for every core. mode 1 (default): where q >= min_order and k = 32 * ceil(k_factor * t / 32)
- * is at most max_frac * q, subspace iteration with a k-column block: products Y = G Q (FP32
+ * for every core. mode 1 (default): where q >= min_order and k = 32 * ceil(f * t / 32) is at
+ * most max_frac * q (f = k_factor in FASTPI_FP64, k_factor_mixed in FASTPI_MIXED: a smaller
+ * basis needs more products for the same accuracy, and the mixed form's gates are looser),
+ * subspace iteration with a k-column block: products Y = G Q (FP32
  * in FASTPI_MIXED), a Cholesky QR of the block before every orth_every-th product, a fixed
  * number of products (iters_fp64, iters_mixed), two FP64 Cholesky QRs, then Rayleigh-Ritz:
  * the top t eigenpairs of Q^T G Q by the block Jacobi, vectors Q W. Every such core is
  * checked (each pair's residual ||G v - lambda v|| against res_tol * lambda_1 of the form,
  * the rank of every Cholesky QR); a core that fails is solved again by Jacobi on G, so the
- * result is always the converged one. Ranges: min_order >= 64, 1 <= k_factor <= 8,
+ * result is always the converged one. Ranges: min_order >= 64, 1 <= k_factor, k_factor_mixed <= 8,
  * 0 < max_frac <= 1, iterations 1..256, orth_every 1..4, tolerances > 0.
  */
 typedef struct {
@@ -475,6 +483,7 @@ typedef struct {
     int32_t pad;
     double res_tol_fp64;
     double res_tol_mixed;
+    double k_factor_mixed;
 } fastpi_core_solver;
 /* Kept across fastpi_upload_plan; a batch takes the handle's setting when it is created. */
 int fastpi_set_core_solver(fastpi_handle* h, const fastpi_core_solver* c);

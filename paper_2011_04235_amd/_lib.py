@@ -44,7 +44,7 @@ class Options(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("block_lds", c_int32), ("block_wgs_per_cu", c_int32), ("gram_rows", c_int32),
-                ("inner_sweeps", c_int32), ("precond", c_int32)]
+                ("inner_sweeps", c_int32), ("precond", c_int32), ("eig_fused", c_int32)]
 
     def as_dict(self):
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
@@ -66,7 +66,7 @@ class CoreSolver(ctypes.Structure):
     applies (see include/fastpi.h)."""
     _fields_ = [("mode", c_int32), ("min_order", c_int32), ("k_factor", c_double), ("max_frac", c_double),
                 ("iters_fp64", c_int32), ("iters_mixed", c_int32), ("orth_every", c_int32), ("pad", c_int32),
-                ("res_tol_fp64", c_double), ("res_tol_mixed", c_double)]
+                ("res_tol_fp64", c_double), ("res_tol_mixed", c_double), ("k_factor_mixed", c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
@@ -435,8 +435,8 @@ class Handle:
                                                                      int(seed)))))
 
     def set_core_solver(self, **kw):
-        """Updates the core-solver fields given (mode, min_order, k_factor, max_frac, iters_fp64,
-        iters_mixed, orth_every, res_tol_fp64, res_tol_mixed)."""
+        """Updates the core-solver fields given (mode, min_order, k_factor, k_factor_mixed,
+        max_frac, iters_fp64, iters_mixed, orth_every, res_tol_fp64, res_tol_mixed)."""
         c = CoreSolver()
         _check(load().fastpi_get_core_solver(self._h, ctypes.byref(c)))
         for key, v in kw.items():
@@ -537,7 +537,7 @@ class Handle:
         return out.tolist()
 
     KERNELS = {"eig_gram": 0, "eig_solve": 1, "eig_update": 2, "block_svd": 3, "label_spmm": 4,
-               "topk": 5, "gemm_nt": 6, "sub_gemm": 7, "cq_panel": 8}
+               "topk": 5, "gemm_nt": 6, "sub_gemm": 7, "cq_panel": 8, "eig_round": 9}
 
     def last_rotations(self):
         """Pair solves that ran in the last svd: [row-update core, column-update core]."""

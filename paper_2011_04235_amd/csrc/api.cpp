@@ -168,6 +168,7 @@ Tuning from_c(const fastpi_tuning& t) {
     o.gram_rows = t.gram_rows;
     o.inner_sweeps = t.inner_sweeps;
     o.precond = t.precond;
+    o.eig_fused = t.eig_fused;
     return o;
 }
 
@@ -177,6 +178,7 @@ void to_c(const Tuning& t, fastpi_tuning* o) {
     o->gram_rows = t.gram_rows;
     o->inner_sweeps = t.inner_sweeps;
     o->precond = t.precond;
+    o->eig_fused = t.eig_fused;
 }
 
 void copy_report(const std::string& rep, char* out, int64_t cap) {
@@ -495,6 +497,7 @@ int fastpi_upload_plan(fastpi_handle* h, const fastpi_plan* plan) {
     if (st != FASTPI_OK) return st;
     h->grp.inst = {&h->inst};
     h->grp.eig_tol = h->opts.tol;
+    h->grp.mixed = h->opts.precision == FASTPI_MIXED;
     if ((st = group_build(h->grp, h->device, h->stream)) != FASTPI_OK) return st;
     Tuning t;
     if (!h->tune_cache.empty() &&
@@ -978,7 +981,7 @@ int fastpi_syev_top(fastpi_handle* h, int64_t q, const double* G, int64_t t, dou
     EigSet es;
     std::vector<EigJob> jobs{eig_make_job(G, precond ? h->sa : nullptr, q, t, vals, vecs, h->sws, h->siws, nullptr,
                                           h->opts.tol, rows, 0)};
-    if ((st = eig_set_create(es, jobs, rows, precond, h->stream)) != FASTPI_OK) {
+    if ((st = eig_set_create(es, jobs, rows, precond, h->grp.tune.eig_fused != 0, h->stream)) != FASTPI_OK) {
         eig_set_free(es);
         set_error("eigensolver allocation failed");
         return st;
@@ -1362,6 +1365,7 @@ static CoreCfg core_from_c(const fastpi_core_solver& c) {
     o.orth_every = c.orth_every;
     o.res_tol_fp64 = c.res_tol_fp64;
     o.res_tol_mixed = c.res_tol_mixed;
+    o.k_factor_mixed = c.k_factor_mixed;
     return o;
 }
 
@@ -1392,6 +1396,7 @@ int fastpi_get_core_solver(const fastpi_handle* h, fastpi_core_solver* c) {
     c->orth_every = o.orth_every;
     c->res_tol_fp64 = o.res_tol_fp64;
     c->res_tol_mixed = o.res_tol_mixed;
+    c->k_factor_mixed = o.k_factor_mixed;
     return FASTPI_OK;
 }
 
@@ -1520,6 +1525,7 @@ int fastpi_batch_create(fastpi_batch** b, fastpi_handle* h, int64_t count,
         B->grp.core = h->grp.core;
         B->grp.big_cost = h->grp.big_cost;
         B->grp.eig_tol = h->grp.eig_tol;
+        B->grp.mixed = h->opts.precision == FASTPI_MIXED;
         st = group_build(B->grp, h->device, h->stream);
     }
     Tuning t;

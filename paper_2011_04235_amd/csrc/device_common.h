@@ -28,7 +28,7 @@ __device__ __forceinline__ T wave_max(T v) {
 
 // Pair `pr` of round `round` of the circle-method round robin over `qe` (even) items:
 // every unordered pair appears once in qe-1 rounds and the pairs of a round are disjoint.
-__device__ __forceinline__ void round_robin_pair(int round, int pr, int qe, int& a, int& b) {
+__host__ __device__ __forceinline__ void round_robin_pair(int round, int pr, int qe, int& a, int& b) {
     if (pr == 0) {
         a = qe - 1;
         b = round;
@@ -41,6 +41,25 @@ __device__ __forceinline__ void round_robin_pair(int round, int pr, int qe, int&
         int t = a;
         a = b;
         b = t;
+    }
+}
+
+// The inverse: the pair `pr` of round `round` (0 <= round < qe - 1) that holds item x, and
+// x's partner in it.
+__host__ __device__ __forceinline__ void round_robin_find(int round, int x, int qe, int& pr, int& other) {
+    const int mod = qe - 1;
+    if (x == mod || x == round) {
+        pr = 0;
+        other = x == mod ? round : mod;
+        return;
+    }
+    const int d = (x - round + mod) % mod;   // x = round + d (mod qe - 1), 1 <= d < qe - 1
+    if (d <= (mod - 1) / 2) {
+        pr = d;
+        other = (round - d + mod) % mod;
+    } else {
+        pr = mod - d;
+        other = (round + pr) % mod;
     }
 }
 

@@ -109,7 +109,7 @@ bool tuning_valid(const Tuning& t) {
     return t.block_lds >= 4096 && t.block_lds <= 60 * 1024 && t.block_wgs_per_cu >= 1 &&
            t.block_wgs_per_cu <= 16 && eig_gram_rows_valid(t.gram_rows) &&
            (t.inner_sweeps == 1 || t.inner_sweeps == 2) && (t.precond == 0 || t.precond == 1) &&
-           t.core_mode >= -1 && t.core_mode <= 1;
+           t.core_mode >= -1 && t.core_mode <= 1 && (t.eig_fused == 0 || t.eig_fused == 1);
 }
 
 bool inner_valid(const InnerCfg& c) {
@@ -123,14 +123,16 @@ bool inner_applies(const InnerCfg& c, int64_t t, int64_t q) {
 
 bool core_cfg_valid(const CoreCfg& c) {
     return (c.mode == 0 || c.mode == 1) && c.min_order >= 64 && c.k_factor >= 1.0 && c.k_factor <= 8.0 &&
+           c.k_factor_mixed >= 1.0 && c.k_factor_mixed <= 8.0 &&
            c.max_frac > 0.0 && c.max_frac <= 1.0 && c.iters_fp64 >= 1 && c.iters_fp64 <= 256 &&
            c.iters_mixed >= 1 && c.iters_mixed <= 256 && c.orth_every >= 1 && c.orth_every <= 4 &&
            c.res_tol_fp64 > 0 && c.res_tol_mixed > 0;
 }
 
-int64_t core_basis(const CoreCfg& c, int64_t t, int64_t q) {
+int64_t core_basis(const CoreCfg& c, int64_t t, int64_t q, bool mixed) {
     if (c.mode == 0 || q < c.min_order || t <= 0) return 0;
-    const int64_t k = (static_cast<int64_t>(std::ceil(c.k_factor * static_cast<double>(t))) + 31) / 32 * 32;
+    const double f = mixed ? c.k_factor_mixed : c.k_factor;
+    const int64_t k = (static_cast<int64_t>(std::ceil(f * static_cast<double>(t))) + 31) / 32 * 32;
     if (k <= t || static_cast<double>(k) > c.max_frac * static_cast<double>(q)) return 0;
     return k;
 }
@@ -343,8 +345,11 @@ static int make_sub_core(Group& g, SubSet& S, int inst, int64_t q, int64_t t, in
     S.cores.push_back(R);
     S.chol.push_back(J);
     S.max_kp = std::max(S.max_kp, R.kp);
-    // the projected matrix H may be overwritten by the factorisation (rebuilt every run)
-    hjob = eig_make_job(R.H, R.H, k, t, lam_out, R.Wv, eigws, eigiws, I.status, g.eig_tol, g.tune.gram_rows, inst);
+    // the projected matrix H may be overwritten by the factorisation (rebuilt every run). Its
+    // cosine threshold in the mixed form (unless one is set): far below what the form's
+    // residual check and gates resolve, with the eigenvalue error quadratic in it
+    const double tol = g.eig_tol > 0 ? g.eig_tol : (g.mixed ? g.core.rr_tol_mixed : 0.0);
+    hjob = eig_make_job(R.H, R.H, k, t, lam_out, R.Wv, eigws, eigiws, I.status, tol, g.tune.gram_rows, inst);
     return launch_status();
 }
 
@@ -362,7 +367,7 @@ static int finish_sub_set(Group& g, SubSet& S, std::vector<EigJob>& fbjobs, hipS
     HIP_TRY(hipMemcpyAsync(S.dchol, S.chol.data(), sizeof(CholJob) * nc, hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
     // the fallback follows the schedule like the Jacobi cores
-    return eig_set_create(S.fb, fbjobs, g.tune.gram_rows, g.tune.precond != 0, st);
+    return eig_set_create(S.fb, fbjobs, g.tune.gram_rows, g.tune.precond != 0, g.tune.eig_fused != 0, st);
 }
 
 static void free_rand(Group& g) {
@@ -463,7 +468,7 @@ static int build_sets(Group& g, hipStream_t st) {
             } else {
                 const EigJob J = eig_make_job(ws + I.o_g2, ws + I.o_g2, d.n1, d.s, ws + I.o_lam2, ws + I.o_v2,
                                               ws + I.o_eig, I.iws, I.status, g.eig_tol, g.tune.gram_rows, tag);
-                const int64_t k = core_basis(g.core, d.s, d.n1);
+                const int64_t k = core_basis(g.core, d.s, d.n1, g.mixed);
                 if (k > 0) {
                     EigJob H;
                     rc = make_sub_core(g, g.sub[0], tag, d.n1, d.s, k, ws + I.o_g2, ws + I.o_lam2, ws + I.o_v2, H, st);
@@ -486,7 +491,7 @@ static int build_sets(Group& g, hipStream_t st) {
             } else {
                 const EigJob J = eig_make_job(ws + I.o_g3, ws + I.o_g3, q3, d.r, ws + I.o_lam3, ws + I.o_vt,
                                               ws + I.o_eig, I.iws, I.status, g.eig_tol, g.tune.gram_rows, tag);
-                const int64_t k = core_basis(g.core, d.r, q3);
+                const int64_t k = core_basis(g.core, d.r, q3, g.mixed);
                 if (k > 0) {
                     EigJob H;
                     rc = make_sub_core(g, g.sub[1], tag, q3, d.r, k, ws + I.o_g3, ws + I.o_lam3, ws + I.o_vt, H, st);
@@ -505,17 +510,19 @@ static int build_sets(Group& g, hipStream_t st) {
     // accuracy) whatever the schedule
     // a set holding Rayleigh-Ritz matrices (Grams of an orthonormal basis under G) takes the
     // pivoted-Cholesky start, as those jobs always have
-    rc = eig_set_create(g.set1, j1, g.tune.gram_rows, true, st);
+    rc = eig_set_create(g.set1, j1, g.tune.gram_rows, true, g.tune.eig_fused != 0, st);
     if (rc == FASTPI_OK)
-        rc = eig_set_create(g.set2, j2, g.tune.gram_rows, g.tune.precond != 0 || !g.sub[0].cores.empty(), st);
+        rc = eig_set_create(g.set2, j2, g.tune.gram_rows, g.tune.precond != 0 || !g.sub[0].cores.empty(),
+                            g.tune.eig_fused != 0, st);
     if (rc == FASTPI_OK)
-        rc = eig_set_create(g.set3, j3, g.tune.gram_rows, g.tune.precond != 0 || !g.sub[1].cores.empty(), st);
+        rc = eig_set_create(g.set3, j3, g.tune.gram_rows, g.tune.precond != 0 || !g.sub[1].cores.empty(),
+                            g.tune.eig_fused != 0, st);
     // the randomized solver's basis Grams are numerically rank-deficient and its
     // orthonormalization divides by the square roots of their eigenvalues down to k eps of the
     // largest: those need relative accuracy, which the pivoted-Cholesky start gives (from G
     // itself they carry absolute errors of ~ld eps of the largest), whatever the schedule
     for (int c = 0; c < 2 && rc == FASTPI_OK; ++c)
-        rc = eig_set_create(g.rset[c], jr[c], g.tune.gram_rows, true, st);
+        rc = eig_set_create(g.rset[c], jr[c], g.tune.gram_rows, true, g.tune.eig_fused != 0, st);
     for (int c = 0; c < 2 && rc == FASTPI_OK; ++c) rc = finish_sub_set(g, g.sub[c], fj[c], st);
     if (rc != FASTPI_OK) set_error("eigensolver set allocation failed");
     return rc;
@@ -1015,6 +1022,22 @@ int group_svd(Group& g, const double* const* val, double* const* U, double* cons
     hipStream_t st = c.st;
     int rc;
     g.graph_launches = 0;
+    if (c.mixed != g.mixed) {
+        // the subspace route (basis, Rayleigh-Ritz threshold) depends on the precision form:
+        // rebuild the sets where a core takes it in either form
+        bool differs = false;
+        for (const Instance* I : g.inst) {
+            const DevicePlan& d = I->dp;
+            for (bool m : {false, true})
+                differs = differs || core_basis(g.core, d.s, d.n1, m) > 0 || core_basis(g.core, d.r, d.s + d.n2, m) > 0;
+        }
+        g.mixed = c.mixed;
+        if (differs && g.counter) {
+            group_drop_graphs(g);
+            HIP_TRY(hipStreamSynchronize(st));
+            if ((rc = build_sets(g, st)) != FASTPI_OK) return rc;
+        }
+    }
     if (!c.use_graph) {
         stage_front(g, val, c, st, c.timer);
         if ((rc = eig_iterate(g.set1, c.max_sweeps, g.tune.inner_sweeps, st, c.copy_st, c.timer, nullptr)) !=
@@ -1143,8 +1166,9 @@ int tuning_lookup(const Group& g, const char* cache, int device, bool mixed, Tun
         std::istringstream v(line.substr(bar + 1));
         Tuning t;
         if (v >> t.block_lds >> t.block_wgs_per_cu >> t.gram_rows >> t.inner_sweeps >> t.precond) {
-            int cm = -1;
+            int cm = -1, ef = 1;
             if (v >> cm) t.core_mode = cm;   // optional sixth field
+            if (v >> ef) t.eig_fused = ef;   // optional seventh field
             if (!tuning_valid(t)) continue;
             out = t;
             found = 1;   // the last matching line wins
@@ -1172,7 +1196,7 @@ static int store_tuning(const Group& g, const char* cache, int device, bool mixe
     }
     for (const std::string& l : keep) o << l << '\n';
     o << key << '|' << t.block_lds << ' ' << t.block_wgs_per_cu << ' ' << t.gram_rows << ' ' << t.inner_sweeps
-      << ' ' << t.precond << ' ' << t.core_mode << '\n';
+      << ' ' << t.precond << ' ' << t.core_mode << ' ' << t.eig_fused << '\n';
     return FASTPI_OK;
 }
 
@@ -1265,8 +1289,9 @@ int group_autotune(Group& g, const double* const* val, double* const* U, double*
             bool changes = false;
             for (const Instance* I : g.inst) {
                 const DevicePlan& d = I->dp;
-                const bool a = core_basis(g.core, d.s, d.n1) > 0 || core_basis(g.core, d.r, d.s + d.n2) > 0;
-                const bool b = core_basis(alt, d.s, d.n1) > 0 || core_basis(alt, d.r, d.s + d.n2) > 0;
+                const bool a = core_basis(g.core, d.s, d.n1, g.mixed) > 0 ||
+                               core_basis(g.core, d.r, d.s + d.n2, g.mixed) > 0;
+                const bool b = core_basis(alt, d.s, d.n1, g.mixed) > 0 || core_basis(alt, d.r, d.s + d.n2, g.mixed) > 0;
                 changes = changes || a != b;
             }
             best.core_mode = g.core.mode;

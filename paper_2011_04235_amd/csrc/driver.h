@@ -21,6 +21,7 @@ struct Tuning {
     int inner_sweeps = 1;        // inner Jacobi sweeps per pair solve
     int precond = 1;             // pivoted-Cholesky start of the core eigensolvers
     int core_mode = -1;          // core solver route chosen by the autotuner (-1: the group's own)
+    int eig_fused = 1;           // eigensolver rounds in one launch (0: three launches a round)
 };
 bool tuning_valid(const Tuning& t);
 
@@ -68,22 +69,25 @@ struct RandCore {
 // iteration (Y = G Q with Cholesky-QR orthonormalisation every `orth_every` products, a
 // fixed number of products, a final double orthonormalisation and Rayleigh-Ritz through the
 // block Jacobi of the k x k projected matrix) where the basis k = ceil32(k_factor t) is small
-// against q. Each result is checked (residual of every kept pair against res_tol * lambda_1,
+// against q (its own factor per precision form). Each result is checked (residual of every kept pair against res_tol * lambda_1,
 // rank of every orthonormalisation); a core that fails the check is solved again by Jacobi.
 struct CoreCfg {
     int mode = 1;             // 0: Jacobi for every core; 1: subspace iteration where it applies
     int min_order = 1024;     // cores of smaller order stay on Jacobi
-    double k_factor = 2.0;
+    double k_factor = 2.0;    // basis factor of the FP64 form
     double max_frac = 0.65;   // and k <= max_frac * q
     int iters_fp64 = 28;      // products by G (FP64 form)
-    int iters_mixed = 14;     // products by G in FP32 (mixed form)
+    int iters_mixed = 18;     // products by G in FP32 (mixed form)
     int orth_every = 2;
     double res_tol_fp64 = 1e-9;
     double res_tol_mixed = 1e-5;
+    double k_factor_mixed = 1.5;   // basis factor of the mixed form
+    double rr_tol_mixed = 1e-8;    // cosine threshold of the Rayleigh-Ritz Jacobi, mixed form
 };
 bool core_cfg_valid(const CoreCfg& c);
-// basis size of the subspace route for target t and order q, or 0 when the core stays on Jacobi
-int64_t core_basis(const CoreCfg& c, int64_t t, int64_t q);
+// basis size of the subspace route for target t and order q in the given precision form, or 0
+// when the core stays on Jacobi
+int64_t core_basis(const CoreCfg& c, int64_t t, int64_t q, bool mixed);
 
 // One core on the subspace route (buffers in one allocation per core).
 struct SubCore {
@@ -182,6 +186,8 @@ struct Group {
     EigSet rset[2];                    // their k x k eigensolves
     std::vector<void*> rallocs;
     CoreCfg core;
+    bool mixed = false;                // precision form the core sets are built for (the basis
+                                       // of the subspace route depends on it)
     SubSet sub[2];                     // cores of the row and column updates on the subspace route
     // captured graphs: stages before, between and after the two eigensolvers, and one
     // sweep of each eigensolver

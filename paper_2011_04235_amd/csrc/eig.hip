@@ -350,17 +350,15 @@ __device__ __forceinline__ int slot(int i, int j) { return i * LS + ((j & 1) ? 1
 // that of its row slot pair a from lane a of its wave by a shuffle (so all threads use
 // bitwise the same rotations), applies J_a^T (.) J_b to its H block and (.) J_b to its W
 // block in registers, and scatters the blocks to their next slots through the other LDS
-// buffer: one barrier per step.
-__global__ __launch_bounds__(256) void k_eig_solve(const EigJob* __restrict__ jobs,
-                                                   const int* __restrict__ pre, int nact,
-                                                   int* __restrict__ state, int inner_sweeps) {
-    __shared__ double Hs[2][PW * LS];
-    __shared__ double Ws[2][PW * LS];
-    __shared__ int s_need;
-    const int j = job_of(pre, nact, blockIdx.x);
-    if (state[ST_WORDS * j + ST_DONE]) return;
-    const EigJob& J = jobs[j];
-    const int pair = blockIdx.x - pre[j];
+// buffer: one barrier per step. Runs in the calling workgroup: job j's pair `pair` from its
+// partial Grams at J.Hpart, the rotations to Wg and the rotated flag to *flagp; lds holds
+// 4 * PW * LS doubles.
+constexpr int kSolveLds = 4 * PW * LS;
+__device__ __forceinline__ void pair_solve(const EigJob& J, int j, int pair, double* __restrict__ Wg,
+                                           int* __restrict__ flagp, int* __restrict__ state, int inner_sweeps,
+                                           double* lds, int& s_need) {
+    double (*Hs)[PW * LS] = reinterpret_cast<double (*)[PW * LS]>(lds);
+    double (*Ws)[PW * LS] = reinterpret_cast<double (*)[PW * LS]>(lds + 2 * PW * LS);
     const int nchunk = J.nchunk;
     const double tol = J.tol;
     const double* Hp = J.Hpart + static_cast<int64_t>(pair) * nchunk * (PW * PW);
@@ -403,7 +401,7 @@ __global__ __launch_bounds__(256) void k_eig_solve(const EigJob* __restrict__ jo
     }
     __syncthreads();
     if (!s_need) {
-        if (threadIdx.x == 0) J.flag[pair] = 0;
+        if (threadIdx.x == 0) *flagp = 0;
         return;
     }
     const int a = threadIdx.x / (PW / 2), b = threadIdx.x % (PW / 2);
@@ -464,15 +462,29 @@ __global__ __launch_bounds__(256) void k_eig_solve(const EigJob* __restrict__ jo
         }
     }
     // after whole sweeps every slot holds its own column again
-    double* Wg = J.W + static_cast<int64_t>(pair) * PW * PW;
     Wg[r0 * PW + c0] = w00;
     Wg[r0 * PW + c1] = w01;
     Wg[r1 * PW + c0] = w10;
     Wg[r1 * PW + c1] = w11;
     if (threadIdx.x == 0) {
-        J.flag[pair] = 1;
+        *flagp = 1;
         atomicAdd(state + ST_WORDS * j + ST_ROT, 1);
     }
+}
+
+// par: the parity slot of the rotations and flags (the round's parity in the two-launch
+// rounds, 0 in the three-launch rounds)
+__global__ __launch_bounds__(256) void k_eig_solve(const EigJob* __restrict__ jobs,
+                                                   const int* __restrict__ pre, int nact,
+                                                   int* __restrict__ state, int inner_sweeps, int par) {
+    __shared__ double lds[kSolveLds];
+    __shared__ int s_need;
+    const int j = job_of(pre, nact, blockIdx.x);
+    if (state[ST_WORDS * j + ST_DONE]) return;
+    const EigJob& J = jobs[j];
+    const int pair = blockIdx.x - pre[j];
+    const int64_t slot = static_cast<int64_t>(par) * J.npairs + pair;
+    pair_solve(J, j, pair, J.W + slot * (PW * PW), J.flag + slot, state, inner_sweeps, lds, s_need);
 }
 
 // X[:, I u J] <- X[:, I u J] W over a tile of UPD_ROWS rows: the tile and W staged in LDS,
@@ -547,6 +559,155 @@ __global__ __launch_bounds__(256) void k_eig_update(const EigJob* __restrict__ j
             const int r = rl + u * RL;
             if (r < nr) Xc[r] = acc[u][v];
         }
+    }
+}
+
+// Column update of round t and partial Grams of round t + 1 in one launch, on two iterates
+// (X and Xs) that alternate by round; the pair solves of round t + 1 follow in k_eig_solve.
+// The workgroups are laid out by the pairs of round t + 1 and the row chunks, as the partial
+// Grams. Workgroup (pair (a, b), chunk) computes the chunk's rows of blocks a and b after
+// round t's rotations, each from the pair of round t that held it (read from one iterate,
+// written to the other, so no workgroup reads what another one writes), keeps them in LDS and
+// writes the pair's partial Gram of round t + 1 over them. t = -1 is the first launch of a
+// sweep (the blocks as reordered into Xs, no update); in a job's last round (t + 1 = its
+// rounds per sweep) only the update runs, laid out by the pairs of round 0. A sweep has an
+// odd number of rounds, so it starts from X, reorders into Xs and ends in X again. Rotations
+// and rotated flags alternate by round parity as well (round t's are read while round t + 1's
+// are written).
+template <int ROWS>
+__global__ __launch_bounds__(256) void k_eig_round(const EigJob* __restrict__ jobs,
+                                                   const int* __restrict__ pre, int nact,
+                                                   const int* __restrict__ state, int t) {
+    constexpr int YS = ROWS * (PW + 1);   // the two blocks' new rows
+    constexpr int WS = 2 * PW * PW;       // round t's rotations of the pairs that held them
+    constexpr int A1 = YS + WS, A2 = 4 * PW * PW;
+    __shared__ double smem[A1 > A2 ? A1 : A2];
+    __shared__ int s_flag[2];
+    double (*Y)[PW + 1] = reinterpret_cast<double (*)[PW + 1]>(smem);
+    const int j = job_of(pre, nact, blockIdx.x);
+    if (state[ST_WORDS * j + ST_DONE]) return;
+    const EigJob& J = jobs[j];
+    const int rounds = J.nbe - 1;
+    const int local = blockIdx.x - pre[j];
+    const int pair = local / J.nchunk, ch = local % J.nchunk;
+    int ba, bb;
+    round_robin_pair((t + 1) % rounds, pair, J.nbe, ba, bb);
+    const int64_t ld = J.ld;
+    const int64_t r0 = static_cast<int64_t>(ch) * ROWS;
+    const int nr = static_cast<int>(min<int64_t>(ROWS, ld - r0));
+    const int tid = threadIdx.x;
+    if (t < 0) {
+        const bool hasB = bb < J.nblk;   // the odd block out is paired with 16 zero columns
+        constexpr int PER = ROWS * PW / 256;
+        double v[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = tid + k * 256;
+            const int c = e / ROWS, r = e % ROWS;
+            const int col = c < BW ? ba * BW + c : bb * BW + (c - BW);
+            v[k] = (r < nr && (c < BW || hasB)) ? J.Xs[static_cast<int64_t>(col) * ld + r0 + r] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = tid + k * 256;
+            Y[e % ROWS][e / ROWS] = v[k];
+        }
+    } else {
+        const double* Xin = (t & 1) ? J.X : J.Xs;
+        double* Xout = (t & 1) ? J.Xs : J.X;
+        const int64_t par = t & 1;
+        const double* Wt = J.W + par * J.npairs * (PW * PW);
+        const int* ft = J.flag + par * J.npairs;
+        double* Wl = smem + YS;
+        int pr[2], lo[2], hi[2], off[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int x = h ? bb : ba;
+            int other;
+            round_robin_find(t, x, J.nbe, pr[h], other);
+            lo[h] = min(x, other);
+            hi[h] = max(x, other);
+            off[h] = x < other ? 0 : BW;
+        }
+        {
+            // both pairs' rotations (stale where a pair did not rotate: then unused)
+            constexpr int PWW = WS / 256;
+            double wv[PWW];
+#pragma unroll
+            for (int k = 0; k < PWW; ++k) {
+                const int e = tid + k * 256;
+                wv[k] = Wt[static_cast<int64_t>(pr[e / (PW * PW)]) * (PW * PW) + e % (PW * PW)];
+            }
+#pragma unroll
+            for (int k = 0; k < PWW; ++k) Wl[tid + k * 256] = wv[k];
+            if (tid < 2) s_flag[tid] = ft[pr[tid]];
+        }
+        __syncthreads();
+        // item (block h, row r): one thread per row of each block; a wave's items share h
+        for (int e = tid; e < 2 * ROWS; e += 256) {
+            const int h = e / ROWS, r = e % ROWS;
+            const int x = h ? bb : ba;
+            const bool live = x < J.nblk && r < nr;
+            double out[BW];
+            if (!s_flag[h]) {
+                // the pair left alone in round t: the block is unchanged
+#pragma unroll
+                for (int c = 0; c < BW; ++c)
+                    out[c] = live ? Xin[static_cast<int64_t>(x * BW + c) * ld + r0 + r] : 0.0;
+            } else {
+                double xin[PW];
+#pragma unroll
+                for (int c = 0; c < PW; ++c) {
+                    const int blk = c < BW ? lo[h] : hi[h];
+                    xin[c] = (live && blk < J.nblk) ? Xin[static_cast<int64_t>(blk * BW + c % BW) * ld + r0 + r] : 0.0;
+                }
+                const double* Wh = Wl + h * (PW * PW) + off[h];
+#pragma unroll
+                for (int c = 0; c < BW; ++c) out[c] = 0.0;
+#pragma unroll
+                for (int k = 0; k < PW; ++k)
+#pragma unroll
+                    for (int c = 0; c < BW; ++c) out[c] += xin[k] * Wh[k * PW + c];
+            }
+            if (live) {
+#pragma unroll
+                for (int c = 0; c < BW; ++c) Xout[static_cast<int64_t>(x * BW + c) * ld + r0 + r] = out[c];
+            }
+#pragma unroll
+            for (int c = 0; c < BW; ++c) Y[r][h * BW + c] = out[c];
+        }
+    }
+    if (t + 1 >= rounds) return;   // the job's last round: update only
+    __syncthreads();
+    // partial Gram of round t + 1's pair over the chunk, as k_eig_gram
+    const int lane = tid % kWave, wave = tid / kWave;
+    const int ra = (lane / 8) * 4, cb = (lane % 8) * 4;
+    double acc[4][4] = {};
+    constexpr int QR = ROWS / 4;
+    for (int r = wave * QR; r < wave * QR + QR; ++r) {
+        double x[4], y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            x[u] = Y[r][ra + u];
+            y[u] = Y[r][cb + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int w = 0; w < 4; ++w) acc[u][w] += x[u] * y[w];
+    }
+    __syncthreads();
+    double* part = smem + wave * PW * PW;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) part[(ra + u) * PW + cb + w] = acc[u][w];
+    __syncthreads();
+    double* Hp = J.Hpart + (static_cast<int64_t>(pair) * J.nchunk + ch) * (PW * PW);
+#pragma unroll
+    for (int k = 0; k < PW * PW / 256; ++k) {
+        const int e = tid + k * 256;
+        Hp[e] = ((smem[e] + smem[PW * PW + e]) + smem[2 * PW * PW + e]) + smem[3 * PW * PW + e];
     }
 }
 
@@ -629,13 +790,13 @@ size_t eig_job_doubles(int64_t q, int gram_rows) {
     int nblk, nbe, npairs, nchunk, nupd;
     job_shape(q, gram_rows, ld, nblk, nbe, npairs, nchunk, nupd);
     return static_cast<size_t>(ld * ld + static_cast<int64_t>(npairs) * nchunk * PW * PW +
-                               static_cast<int64_t>(npairs) * PW * PW + ld + 32 + (ld <= kSortMax ? ld * ld : 0));
+                               2 * static_cast<int64_t>(npairs) * PW * PW + ld + 32 + (ld <= kSortMax ? ld * ld : 0));
 }
 
 size_t eig_job_ints(int64_t q) {
     const int64_t ld = eig_padded_order(q);
     const int64_t npairs = (ld / BW + 1) / 2;
-    return static_cast<size_t>(npairs + 2 * ld + 32);
+    return static_cast<size_t>(2 * npairs + 2 * ld + 32);
 }
 
 EigJob eig_make_job(const double* G, double* A, int64_t q, int64_t t, double* vals, double* vecs,
@@ -651,10 +812,10 @@ EigJob eig_make_job(const double* G, double* A, int64_t q, int64_t t, double* va
     J.X = ws;
     J.Hpart = J.X + J.ld * J.ld;
     J.W = J.Hpart + static_cast<int64_t>(J.npairs) * J.nchunk * PW * PW;
-    J.lam = J.W + static_cast<int64_t>(J.npairs) * PW * PW;
+    J.lam = J.W + 2 * static_cast<int64_t>(J.npairs) * PW * PW;
     J.Xs = J.ld <= kSortMax ? J.lam + J.ld + 32 : nullptr;
     J.flag = iws;
-    J.order = iws + J.npairs;
+    J.order = iws + 2 * J.npairs;
     J.perm = J.order + J.ld;
     J.status = status;
     J.tol = tol > 0 ? tol : static_cast<double>(J.ld) * DBL_EPSILON;
@@ -671,12 +832,16 @@ void eig_set_free(EigSet& es) {
     es = EigSet{};
 }
 
-int eig_set_create(EigSet& es, std::vector<EigJob> jobs, int gram_rows, bool precond, hipStream_t st) {
+int eig_set_create(EigSet& es, std::vector<EigJob> jobs, int gram_rows, bool precond, bool fused,
+                   hipStream_t st) {
     eig_set_free(es);
     es.gram_rows = gram_rows;
-    for (const EigJob& J : jobs)
+    for (const EigJob& J : jobs) {
         if (!J.A) precond = false;
+        if (!J.Xs) fused = false;
+    }
     es.precond = precond ? 1 : 0;
+    es.fused = fused ? 1 : 0;
     for (EigJob& J : jobs) J.squared = es.precond;
     std::stable_sort(jobs.begin(), jobs.end(),
                      [](const EigJob& x, const EigJob& y) { return x.nbe > y.nbe; });
@@ -751,6 +916,32 @@ void eig_sweep(const EigSet& es, int max_sweeps, int inner_sweeps, hipStream_t s
     hipLaunchKernelGGL(k_eig_sort_cols, dim3(nj), dim3(1024), 0, st, es.jobs, es.state);
     const unsigned gc = static_cast<unsigned>(std::min<int64_t>((es.max_ld + 3) / 4, 1024));
     hipLaunchKernelGGL(k_eig_gather_cols, dim3(gc, nj), dim3(256), 0, st, es.jobs, es.state);
+    if (es.fused) {
+        // the reordered columns stay in Xs: round -1 reads them there
+        for (int t = -1; t < es.rounds; ++t) {
+            const int tt = t < 0 ? 0 : t;
+            const int na = es.nact[tt];
+            const dim3 grid(static_cast<unsigned>(es.g_gram[tt]));
+            switch (es.gram_rows) {
+                case 64:
+                    FASTPI_LAUNCH(timer, KT_EIG_ROUND, (k_eig_round<64>), grid, dim3(256), 0, st, es.jobs, pg, na,
+                                  es.state, t);
+                    break;
+                case 256:
+                    FASTPI_LAUNCH(timer, KT_EIG_ROUND, (k_eig_round<256>), grid, dim3(256), 0, st, es.jobs, pg, na,
+                                  es.state, t);
+                    break;
+                default:
+                    FASTPI_LAUNCH(timer, KT_EIG_ROUND, (k_eig_round<128>), grid, dim3(256), 0, st, es.jobs, pg, na,
+                                  es.state, t);
+            }
+            if (t + 1 < es.rounds)
+                FASTPI_LAUNCH(timer, KT_EIG_SOLVE, k_eig_solve, dim3(es.g_solve[t + 1]), dim3(256), 0, st, es.jobs, ps,
+                              es.nact[t + 1], es.state, inner_sweeps, (t + 1) & 1);
+        }
+        hipLaunchKernelGGL(k_eig_sweep_end, dim3(1), dim3(256), 0, st, es.jobs, nj, es.state, max_sweeps);
+        return;
+    }
     const unsigned gx = static_cast<unsigned>(std::min<int64_t>((es.max_ld * es.max_ld + 255) / 256, 2048));
     hipLaunchKernelGGL(k_eig_copy_back, dim3(gx, nj), dim3(256), 0, st, es.jobs, es.state);
     for (int t = 0; t < es.rounds; ++t) {
@@ -769,7 +960,7 @@ void eig_sweep(const EigSet& es, int max_sweeps, int inner_sweeps, hipStream_t s
                               na, es.state, t);
         }
         FASTPI_LAUNCH(timer, KT_EIG_SOLVE, k_eig_solve, dim3(es.g_solve[t]), dim3(256), 0, st, es.jobs, ps, na,
-                      es.state, inner_sweeps);
+                      es.state, inner_sweeps, 0);
         FASTPI_LAUNCH(timer, KT_EIG_UPDATE, k_eig_update, dim3(es.g_upd[t]), dim3(256), 0, st, es.jobs, pu, na,
                       es.state, t);
     }

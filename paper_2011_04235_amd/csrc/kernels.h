@@ -39,7 +39,8 @@ enum KernelKind {
     KT_GEMM_NT = 6,
     KT_SUB_GEMM = 7,   // products by G of the subspace core solver
     KT_CQ_PANEL = 8,   // panel kernel of the subspace solver's Cholesky QR
-    KT_LAST = KT_CQ_PANEL
+    KT_EIG_ROUND = 9,  // eigensolver column update and next round's partial Grams, one launch
+    KT_LAST = KT_EIG_ROUND
 };
 struct KernelTimer {
     int target = KT_NONE;
@@ -123,11 +124,12 @@ struct EigJob {
     double* vals;       // t eigenvalues, descending
     double* vecs;       // q x t row-major eigenvectors
     double* X;          // ld x ld column-major iterate
-    double* Xs;         // ld x ld scratch of the column reordering, or null (order above 4096)
+    double* Xs;         // ld x ld: the reordered columns, then the second iterate of the fused
+                        // rounds; null above order 16384 (no reordering, three launches a round)
     double* Hpart;      // npairs * nchunk partial 32 x 32 Grams
-    double* W;          // npairs 32 x 32 rotations
+    double* W;          // 2 * npairs 32 x 32 rotations (by round parity)
     double* lam;        // ld column norms, then the noise floor
-    int* flag;          // npairs: pair rotated in this round
+    int* flag;          // 2 * npairs: pair rotated in this round (by round parity)
     int* order;         // t: columns of the t largest norms
     int* perm;          // ld: the columns of X by descending norm (column order of the next sweep)
     int* status;        // status word of the owner (bit 1 when the sweep cap is hit), or null
@@ -174,6 +176,7 @@ struct EigSet {
     int* host_state = nullptr;    // pinned mirror of state
     int* pstate = nullptr;        // device, per job {pivots taken, factorisation done}
     int precond = 0;              // start from the pivoted Cholesky factor instead of G
+    int fused = 0;                // two launches per round (every job has its second iterate Xs)
     std::vector<EigJob> host;     // host copy, same order
     std::vector<int> nact, g_gram, g_solve, g_upd;   // per round: active jobs and grids
     int64_t max_ld = 0, max_q = 0;
@@ -186,7 +189,9 @@ size_t eig_job_ints(int64_t q);
 EigJob eig_make_job(const double* G, double* A, int64_t q, int64_t t, double* vals, double* vecs,
                     double* ws, int* iws, int* status, double tol, int gram_rows, int tag);
 // precond: factor every job's G first (every job needs A) and iterate on R^T
-int eig_set_create(EigSet& es, std::vector<EigJob> jobs, int gram_rows, bool precond, hipStream_t st);
+// fused: two launches per round where every job allows it (else three)
+int eig_set_create(EigSet& es, std::vector<EigJob> jobs, int gram_rows, bool precond, bool fused,
+                   hipStream_t st);
 // pivoted Cholesky of every job of the set into its X (pchol.hip)
 void pchol_run(const EigSet& es, hipStream_t st);
 void eig_set_free(EigSet& es);

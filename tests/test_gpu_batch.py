@@ -98,6 +98,32 @@ def test_batch_matches_oracle_and_single_runs(fp, torch, small_probs):
         assert same((U, S, V), ref), name
 
 
+def test_batch_fused_rounds_equal_three_launch_rounds(fp, torch, small_probs):
+    """The batched eigensolves with two launches per round equal, bitwise, those with three
+    launches per round, eager and replayed from graphs (the batch's jobs have different
+    rounds per sweep, so some sit out the last rounds of a sweep)."""
+    say("batch: fused vs three-launch eigensolver rounds")
+    vals = [dev(torch, p.data) for _, p, _ in small_probs]
+    res = {}
+    for fused in (0, 1):
+        for graph in (False, True):
+            h = fp.Handle(0)
+            b = fp.Batch(h, [plan_of(fp, p, a) for _, p, a in small_probs])
+            b.set_tuning(eig_fused=fused)
+            b.set_graph(graph)
+            for _ in range(2 if graph else 1):
+                out = b.svd(vals)
+                st, sweeps = b.sync()
+                assert st == ["OK"] * len(small_probs)
+            res[(fused, graph)] = ([tuple(t.clone() for t in o) for o in out], sweeps.tolist(),
+                                   b.rotations().tolist())
+    ref = res[(0, False)]
+    for key, got in res.items():
+        assert got[1] == ref[1] and got[2] == ref[2], key
+        for o, e in zip(got[0], ref[0]):
+            assert same(o, e), key
+
+
 def test_batch_graph_replays_equal_eager(fp, torch, small_probs):
     say("batch graph replay")
     h = fp.Handle(0)
@@ -171,6 +197,7 @@ SCHEDULES = [
     dict(block_lds=57344, block_wgs_per_cu=2, gram_rows=256, inner_sweeps=1),
     dict(block_lds=4096, block_wgs_per_cu=1, gram_rows=128, inner_sweeps=1),
     dict(block_lds=32768, block_wgs_per_cu=4, gram_rows=128, inner_sweeps=1, precond=0),
+    dict(block_lds=32768, block_wgs_per_cu=4, gram_rows=64, inner_sweeps=2, eig_fused=0),
 ]
 
 

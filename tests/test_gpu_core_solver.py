@@ -82,6 +82,42 @@ def test_benchmark_shape_takes_the_subspace_route(env, precision):
         assert float(np.linalg.norm(Z - Zj) / np.linalg.norm(Zj)) <= 1e-9
 
 
+def test_precision_switch_rebuilds_the_subspace_basis(env):
+    """20000 x 2000: the row core's basis is 544 columns in FP64 (k_factor 2) and 416 in the
+    mixed form (k_factor_mixed 1.5). Switching one handle's precision between runs rebuilds
+    the core sets; each run meets its form's gates and the FP64 runs before and after the
+    mixed one are bitwise equal."""
+    torch, fp = env
+    from synth import make_problem
+    p = make_problem("c2")
+    dev = torch.device("cuda", 0)
+    core = fp.Handle(0).get_core_solver()
+    assert core["k_factor"] == 2.0 and core["k_factor_mixed"] == 1.5
+    say("20000x2000: fp64, mixed, fp64 on one handle")
+    h = fp.Handle(0, precision="fp64")
+    plan = fp.Plan(p.m, p.n, p.indptr, p.indices, p.data, alpha=0.2, k=0.01)
+    h.upload_plan(plan)
+    args = [torch.from_numpy(a).to(dev) for a in (p.indptr, p.indices, p.data)]
+    ores = oracle_of(p, 0.2, 0.01)
+    outs = []
+    for precision in ("fp64", "mixed", "fp64"):
+        h.set_precision(precision)
+        U, S, V = h.svd(*args)
+        assert h.sync() == "OK"
+        assert h.last_core_routes() == ["subspace", "jacobi"]
+        U, S, V = to_np(U), to_np(S), to_np(V)
+        if precision == "fp64":
+            ok, info = compare_svd(p, U, S, V, ores)
+        else:
+            ok, info = compare_svd(p, U, S, V, ores, sigma_rtol=MIXED_SIGMA_RTOL, product_rtol=1e-4,
+                                   recon_atol=MIXED_RECON_ATOL, orth_atol=1e-5)
+        say(f"  {precision}: {info}")
+        assert ok, (precision, info)
+        outs.append((U, S, V))
+    for a, b in zip(outs[0], outs[2]):
+        assert np.array_equal(a, b)
+
+
 def test_forced_subspace_on_a_small_matrix(env):
     """2000 x 500 with the route opened to small orders: the row core (order 383) takes it,
     FP64 gates against the oracle."""

@@ -99,6 +99,31 @@ def test_syev_top_is_scale_invariant(fp, torch, e2):
     assert np.max(np.abs(vecs.T @ vecs - np.eye(t))) <= 1e-10
 
 
+@pytest.mark.parametrize("q,t,rows", [(1, 1, 128), (17, 9, 128), (40, 10, 64), (130, 60, 256),
+                                      (513, 100, 128), (1100, 64, 64), (2500, 200, 256)])
+def test_syev_top_fused_rounds_equal_three_launch_rounds(fp, torch, q, t, rows):
+    """Two launches per Jacobi round (round t's column update fused with round t + 1's partial
+    Grams, then the pair solves) compute bitwise what three launches per round compute: the
+    same products in the same order, on two iterates."""
+    say(f"syev_top fused vs three-launch rounds q={q} t={t} rows={rows}")
+    rng = np.random.default_rng(q * 3 + rows)
+    X = rng.lognormal(size=(q + 20, q)) * (rng.random((q + 20, q)) < 0.3)
+    G = X.T @ X
+    Gd = torch.from_numpy(G).cuda()
+    out = []
+    for fused in (0, 1):
+        h = fp.Handle(0)
+        h.set_tuning(gram_rows=rows, eig_fused=fused)
+        assert h.get_tuning()["eig_fused"] == fused
+        vals, vecs = h.syev_top(Gd, t)
+        torch.cuda.synchronize()
+        out.append((to_np(vals), to_np(vecs)))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    w = np.linalg.eigvalsh(G)[::-1]
+    assert np.max(np.abs(out[1][0] - w[:t])) <= 1e-12 * w[0] * max(1, q / 100)
+
+
 # ------------------------------------------------------------------ whole path ----------
 SMALL = [
     ("small-a1", small_config(300, 80, 0.05, alpha=1.0, seed=7, k=0.05, L=6), 1.0),
