@@ -704,6 +704,9 @@ def main():
     ap.add_argument("--eig-rounds", default="fused", choices=["fused", "three"],
                     help="eigensolver rounds: two launches each (column update fused with the next "
                          "round's partial Grams, then the pair solves; default) or three")
+    ap.add_argument("--eig-precond", type=int, default=None, choices=[0, 1],
+                    help="pivoted-Cholesky start of the core and Rayleigh-Ritz eigensolves (plain form; "
+                         "default: the library's)")
     ap.add_argument("--core-mode", type=int, default=1, choices=[0, 1],
                     help="core solver of the updates: 0 block Jacobi on G, 1 subspace iteration where it applies")
     ap.add_argument("--core-max-frac", type=float, default=None,
@@ -793,7 +796,8 @@ def main():
         autotuned schedule and the stage chain replayed from HIP graphs."""
         progress(f"{precision} {'batched' if batched else 'plain'}: start")
         h = fp.Handle(0, precision=precision)
-        h.set_tuning(eig_fused=int(args.eig_rounds == "fused"))
+        h.set_tuning(eig_fused=int(args.eig_rounds == "fused"),
+                     **({"precond": args.eig_precond} if args.eig_precond is not None else {}))
         h.set_core_solver(mode=args.core_mode,
                           **({"max_frac": args.core_max_frac} if args.core_max_frac is not None else {}),
                           **({"min_order": args.core_min_order} if args.core_min_order is not None else {}),

@@ -345,11 +345,12 @@ static int make_sub_core(Group& g, SubSet& S, int inst, int64_t q, int64_t t, in
     S.cores.push_back(R);
     S.chol.push_back(J);
     S.max_kp = std::max(S.max_kp, R.kp);
-    // the projected matrix H may be overwritten by the factorisation (rebuilt every run). Its
+    // the projected matrix H starts the Jacobi as it is, without the pivoted-Cholesky start (no
+    // scratch given): a Gram of a converged basis needs no fewer sweeps from that start. Its
     // cosine threshold in the mixed form (unless one is set): far below what the form's
     // residual check and gates resolve, with the eigenvalue error quadratic in it
     const double tol = g.eig_tol > 0 ? g.eig_tol : (g.mixed ? g.core.rr_tol_mixed : 0.0);
-    hjob = eig_make_job(R.H, R.H, k, t, lam_out, R.Wv, eigws, eigiws, I.status, tol, g.tune.gram_rows, inst);
+    hjob = eig_make_job(R.H, nullptr, k, t, lam_out, R.Wv, eigws, eigiws, I.status, tol, g.tune.gram_rows, inst);
     return launch_status();
 }
 
@@ -508,15 +509,11 @@ static int build_sets(Group& g, hipStream_t st) {
     // the Gram route of large blocks takes sigma = sqrt(lambda) down to 1e-7 of the largest and
     // divides by it, so its eigensolves start from the pivoted-Cholesky factor (relative
     // accuracy) whatever the schedule
-    // a set holding Rayleigh-Ritz matrices (Grams of an orthonormal basis under G) takes the
-    // pivoted-Cholesky start, as those jobs always have
     rc = eig_set_create(g.set1, j1, g.tune.gram_rows, true, g.tune.eig_fused != 0, st);
     if (rc == FASTPI_OK)
-        rc = eig_set_create(g.set2, j2, g.tune.gram_rows, g.tune.precond != 0 || !g.sub[0].cores.empty(),
-                            g.tune.eig_fused != 0, st);
+        rc = eig_set_create(g.set2, j2, g.tune.gram_rows, g.tune.precond != 0, g.tune.eig_fused != 0, st);
     if (rc == FASTPI_OK)
-        rc = eig_set_create(g.set3, j3, g.tune.gram_rows, g.tune.precond != 0 || !g.sub[1].cores.empty(),
-                            g.tune.eig_fused != 0, st);
+        rc = eig_set_create(g.set3, j3, g.tune.gram_rows, g.tune.precond != 0, g.tune.eig_fused != 0, st);
     // the randomized solver's basis Grams are numerically rank-deficient and its
     // orthonormalization divides by the square roots of their eigenvalues down to k eps of the
     // largest: those need relative accuracy, which the pivoted-Cholesky start gives (from G

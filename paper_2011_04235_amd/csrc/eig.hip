@@ -836,13 +836,15 @@ int eig_set_create(EigSet& es, std::vector<EigJob> jobs, int gram_rows, bool pre
                    hipStream_t st) {
     eig_set_free(es);
     es.gram_rows = gram_rows;
-    for (const EigJob& J : jobs) {
-        if (!J.A) precond = false;
+    // the pivoted-Cholesky start per job: the jobs given scratch for it take it
+    bool any = false;
+    for (EigJob& J : jobs) {
+        J.squared = precond && J.A ? 1 : 0;
+        any = any || J.squared;
         if (!J.Xs) fused = false;
     }
-    es.precond = precond ? 1 : 0;
+    es.precond = any ? 1 : 0;
     es.fused = fused ? 1 : 0;
-    for (EigJob& J : jobs) J.squared = es.precond;
     std::stable_sort(jobs.begin(), jobs.end(),
                      [](const EigJob& x, const EigJob& y) { return x.nbe > y.nbe; });
     const int nj = static_cast<int>(jobs.size());

@@ -136,7 +136,9 @@ struct EigJob {
     double tol;         // cosine threshold of the outer pairs
     int64_t q, t, ld;
     int nblk, nbe, npairs, nchunk, nupd, tag;
-    int squared;        // X = R^T of a pivoted Cholesky: eigenvalues are squared column norms
+    int squared;        // X = R^T of a pivoted Cholesky (the job's start; set by the set from
+                        // the set's choice and the job's scratch A): eigenvalues are squared
+                        // column norms
     int pad;
 };
 // Cholesky QR of the subspace core solver (subspace.hip): one job per core and call.
@@ -188,7 +190,8 @@ size_t eig_job_ints(int64_t q);
 // A: writable q x q scratch for the pivoted-Cholesky preconditioner (may alias G), or null
 EigJob eig_make_job(const double* G, double* A, int64_t q, int64_t t, double* vals, double* vecs,
                     double* ws, int* iws, int* status, double tol, int gram_rows, int tag);
-// precond: factor every job's G first (every job needs A) and iterate on R^T
+// precond: factor the G of every job that has scratch A first and iterate on its R^T (jobs
+// without A start from G)
 // fused: two launches per round where every job allows it (else three)
 int eig_set_create(EigSet& es, std::vector<EigJob> jobs, int gram_rows, bool precond, bool fused,
                    hipStream_t st);

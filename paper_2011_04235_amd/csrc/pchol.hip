@@ -26,12 +26,25 @@ namespace fastpi {
 constexpr int PT = 1024;    // threads of the panel kernel
 constexpr int UT = 64;      // trailing-update tile
 
+// X = 0 and the working copy A of G for the jobs that take the start; X = G (and the
+// factorisation marked done) for the others of the set.
 __global__ void k_pchol_init(const EigJob* __restrict__ jobs, int* __restrict__ pstate) {
     const int jb = blockIdx.y;
     const EigJob& J = jobs[jb];
     const int64_t q = J.q, ld = J.ld;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     const int64_t t0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (!J.squared) {
+        for (int64_t e = t0; e < ld * ld; e += stride) {
+            const int64_t r = e % ld, c = e / ld;
+            J.X[e] = (r < q && c < q) ? J.G[r * q + c] : 0.0;
+        }
+        if (t0 == 0) {
+            pstate[2 * jb] = 0;
+            pstate[2 * jb + 1] = 1;
+        }
+        return;
+    }
     for (int64_t e = t0; e < ld * ld; e += stride) J.X[e] = 0.0;
     if (J.A != J.G)
         for (int64_t e = t0; e < q * q; e += stride) J.A[e] = J.G[e];
