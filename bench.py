@@ -704,6 +704,8 @@ def main():
     ap.add_argument("--eig-rounds", default="fused", choices=["fused", "three"],
                     help="eigensolver rounds: two launches each (column update fused with the next "
                          "round's partial Grams, then the pair solves; default) or three")
+    ap.add_argument("--block-route", type=float, default=None,
+                    help="p q^2 from which a diagonal block takes the Gram route (default: the library's)")
     ap.add_argument("--eig-precond", type=int, default=None, choices=[0, 1],
                     help="pivoted-Cholesky start of the core and Rayleigh-Ritz eigensolves (plain form; "
                          "default: the library's)")
@@ -807,6 +809,8 @@ def main():
                              if args.core_iters is not None else {}))
         if args.inner == "rand":
             h.set_inner(mode=1, oversample=5, iters=11, seed=0)
+        if args.block_route is not None:
+            h.set_block_route(args.block_route)
         h.upload_plan(plan)
         U = torch.empty((m, r), dtype=torch.float64, device=dev)
         S = torch.empty((r,), dtype=torch.float64, device=dev)

@@ -450,7 +450,7 @@ int fastpi_set_tuning_cache(fastpi_handle* h, const char* path);
  * p * q^2 < min_cost is solved by one workgroup's one-sided Jacobi (the persistent block
  * launch); a costlier one through the Gram matrix of its long side: G = X^T X (q x q), the
  * batched FP64 eigensolver of the updates, and the other factor X E diag(sigma^-1)
- * (singular values below 1e-7 of the block's largest are returned as zero). Default 8e6;
+ * (singular values below 1e-7 of the block's largest are returned as zero). Default 1e6;
  * 0 sends every block with rank > 0 and q >= 2 that way. Kept across fastpi_upload_plan; a
  * batch takes the handle's setting when it is created.
  */

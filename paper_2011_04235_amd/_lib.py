@@ -426,7 +426,7 @@ class Handle:
         return piT, piF, blocks, spl.as_dict()
 
     def set_block_route(self, min_cost):
-        """Blocks with p q^2 >= min_cost take the Gram route (default 8e6)."""
+        """Blocks with p q^2 >= min_cost take the Gram route (default 1e6)."""
         _check(load().fastpi_set_block_route(self._h, float(min_cost)))
 
     def set_inner(self, mode=1, oversample=5, iters=11, seed=0):

@@ -39,7 +39,7 @@ bool inner_applies(const InnerCfg& c, int64_t t, int64_t q);
 // A diagonal block of A11 too costly for one workgroup's one-sided Jacobi (p q^2 at least
 // kBigBlockCost, p >= q its sides): its SVD goes through the Gram matrix of its long side,
 // G = X^T X (q x q), the batched FP64 eigensolver, and W = X E for the other factor.
-constexpr double kBigBlockCost = 8.0e6;
+constexpr double kBigBlockCost = 1.0e6;
 struct BigBlock {
     int inst = 0;                // index of its matrix in the group
     const double* A = nullptr;   // dense block, column-major rows x cols
