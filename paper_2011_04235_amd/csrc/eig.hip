@@ -276,15 +276,6 @@ __device__ __forceinline__ double rsq_nr(double x) {
     y = y * (1.5 - 0.5 * x * y * y);
     return y * (1.5 - 0.5 * x * y * y);
 }
-// 1/sqrt(x) from the hardware estimate (relative error ~2^-24) with one third-order
-// correction y (1 + e/2 + 3e^2/8), e = 1 - x y^2: error O(e^3), to FP64 rounding, in four
-// dependent operations instead of the eight of two Newton steps.
-__device__ __forceinline__ double rsq3(double x) {
-    const double y = __builtin_amdgcn_rsq(x);
-    const double e = fma(-(x * y), y, 1.0);
-    const double p = fma(0.375, e, 0.5);
-    return fma(y * e, p, y);
-}
 __device__ __forceinline__ void rutishauser_rotation(double hpp, double hqq, double hpq, double& c, double& s) {
     const double zeta = (hqq - hpp) * rcp_nr(2.0 * hpq);
     const double az = fabs(zeta);

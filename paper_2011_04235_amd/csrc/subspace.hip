@@ -49,9 +49,11 @@ __device__ __forceinline__ double lane_value(double v, int lane) {
 
 // The panel's diagonal block D (64 x 64, in LDS) factored in place, L lower, and X = L^-1,
 // blocked by 16. For each 16-block: wave 0 holds the block's 16 rows in registers (lane i:
-// row i) and factors it column by column, every operand of the dependent chain moved between
-// lanes by readlane instead of through LDS; it then inverts the 16 x 16 factor in registers
-// (lane j: column j of the inverse) and writes both. All waves then form the rows below,
+// row i) and factors it column by column: the pivot comes to every lane by readlane, its
+// reciprocal square root from the hardware estimate refined to FP64, and each new column of
+// L goes to the other lanes through a 16 x 16 LDS buffer (one write, broadcast reads, no
+// workgroup barrier). It then inverts the 16 x 16 factor in registers (lane j: column j of the
+// inverse, L read back from that buffer) and writes both. All waves then form the rows below,
 // L_ib = D_ib X_bb^T (independent dot products), and update the rest of D. The block rows of
 // X below the diagonal follow at the end. Returns the number of pivots that lost rank.
 __device__ int cq_factor_invert(double (*D)[CP + 1], double (*X)[CP + 1], double (*T)[CP + 1], const double* dg,
@@ -59,6 +61,7 @@ __device__ int cq_factor_invert(double (*D)[CP + 1], double (*X)[CP + 1], double
     const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
     __shared__ int nbad;
     __shared__ double lims[CP];   // rank-test threshold of every pivot
+    __shared__ double Lc[16][16];  // Lc[c][i] = L_ic of the 16-block being factored
     if (tid == 0) nbad = 0;
     if (tid < CP) lims[tid] = lim * dg[tid];
     for (int e = tid; e < CP * CP; e += 256) X[e / CP][e % CP] = 0.0;
@@ -69,21 +72,30 @@ __device__ int cq_factor_invert(double (*D)[CP + 1], double (*X)[CP + 1], double
         double r[16];
 #pragma unroll
         for (int l = 0; l < 16; ++l) r[l] = D[bb + li][bb + l];
-        const double mylim = lims[bb + li];
         double dv[16];   // 1 / L[c][c] (the same on every lane)
         int lost_here = 0;
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
-            const double sc = lane_value(r[c], c);
-            const bool lost = !(sc > lane_value(mylim, c));
+            const double sc = lane_value(r[c], c);   // the same on every lane: uniform branches
+            const bool lost = !(sc > lims[bb + c]);
             lost_here += lost ? 1 : 0;
-            const double piv = lost ? 1.0 : sqrt(sc);   // keeps the arithmetic finite
-            const double rp = 1.0 / piv;
+            double piv = 1.0, rp = 1.0;   // a lost pivot keeps the arithmetic finite
+            if (!lost) {
+                if (sc > 1e-290 && sc < 1e290) {
+                    rp = rsq3(sc);
+                    piv = sc * rp;
+                } else {
+                    piv = sqrt(sc);
+                    rp = 1.0 / piv;
+                }
+            }
             dv[c] = rp;
             const double l = lane > c ? r[c] * rp : (lane == c ? piv : 0.0);
             r[c] = l;
+            if (lane < 16) Lc[c][lane] = l;
+            wave_sync();
 #pragma unroll
-            for (int j = c + 1; j < 16; ++j) r[j] -= l * lane_value(l, j);
+            for (int j = c + 1; j < 16; ++j) r[j] -= l * Lc[c][j];
         }
         // column `lane` of the inverse: x_i = -(sum_{l<i} L_il x_l) / L_ii, x_lane = 1 / L_ll
         double x[16];
@@ -91,7 +103,7 @@ __device__ int cq_factor_invert(double (*D)[CP + 1], double (*X)[CP + 1], double
         for (int i = 0; i < 16; ++i) {
             double v = 0.0;
 #pragma unroll
-            for (int l = 0; l < i; ++l) v += lane_value(r[l], i) * x[l];
+            for (int l = 0; l < i; ++l) v += Lc[l][i] * x[l];
             x[i] = i < lane ? 0.0 : (i == lane ? dv[i] : -v * dv[i]);
         }
         if (lane < 16) {
@@ -157,8 +169,10 @@ __device__ int cq_factor_invert(double (*D)[CP + 1], double (*X)[CP + 1], double
         }
         __syncthreads();
     }
-    // block row bi: T_j = sum_{l=j}^{bi-1} L_{bi,l} X_{l,j}, then X_{bi,j} = -X_{bi,bi} T_j (j < bi);
-    // static trip counts with predicated terms, so that each thread's LDS loads issue together
+    // block row bi: T_j = sum_{l=j}^{bi-1} L_{bi,l} X_{l,j}, then X_{bi,j} = -X_{bi,bi} T_j (j < bi).
+    // X is zero above its diagonal blocks (cleared above, and the diagonal blocks are written
+    // with their zeros), so each sum runs over all rows of the earlier blocks with no
+    // predicates; four partial sums keep the LDS loads and the FMAs of a thread independent
 #pragma unroll
     for (int bi = 1; bi < 4; ++bi) {
         const int r0 = bi * 16, n = bi * 16;   // columns [0, n) of block row bi
@@ -167,12 +181,10 @@ __device__ int cq_factor_invert(double (*D)[CP + 1], double (*X)[CP + 1], double
             const int e = tid + 256 * u;
             if (e < 16 * n) {
                 const int rr = e / n, cc = e % n;
-                const int lj = cc / 16 * 16;   // first block row l = block column of cc
-                double v = 0.0;
+                double v[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int l = 0; l < r0; ++l)
-                    if (l >= lj) v += D[r0 + rr][l] * X[l][cc];
-                T[rr][cc] = v;
+                for (int l = 0; l < r0; ++l) v[l & 3] += D[r0 + rr][l] * X[l][cc];
+                T[rr][cc] = (v[0] + v[1]) + (v[2] + v[3]);
             }
         }
         __syncthreads();
@@ -181,11 +193,10 @@ __device__ int cq_factor_invert(double (*D)[CP + 1], double (*X)[CP + 1], double
             const int e = tid + 256 * u;
             if (e < 16 * n) {
                 const int rr = e / n, cc = e % n;
-                double v = 0.0;
+                double v[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int l = 0; l < 16; ++l)
-                    if (l <= rr) v += X[r0 + rr][r0 + l] * T[l][cc];
-                X[r0 + rr][cc] = -v;
+                for (int l = 0; l < 16; ++l) v[l & 3] += X[r0 + rr][r0 + l] * T[l][cc];
+                X[r0 + rr][cc] = -((v[0] + v[1]) + (v[2] + v[3]));
             }
         }
         __syncthreads();
