@@ -110,27 +110,29 @@ BW = 16                  # eigensolver column block
 # profiles/ (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the scales read off a 256 MiB device copy in
 # the same runs), keyed by (kernel, workload, precision of the timed form), with the digest
 # of the kernel source they were taken on and the core-solver settings of that run (they set
-# the basis sizes, hence the bytes of a launch); the figure is dropped (null) for any other
-# workload, as soon as the kernel's source differs, and for other core-solver settings.
+# the basis sizes, hence the bytes of a launch); the eigensolver kernels' figures are per
+# partial-Gram height (rows per chunk: it sets how many partials a pair solve reads). The
+# figure is dropped (null) for any other workload, as soon as the kernel's source differs,
+# and for other core-solver settings or chunk heights.
 TRAFFIC_CORE = {"mode": 1, "min_order": 1024, "k_factor": 2.0, "k_factor_mixed": 1.5, "max_frac": 0.65,
                 "iters_fp64": 28, "iters_mixed": 18, "orth_every": 2}
 TRAFFIC = {
-    ("cq_panel", "c3", "mixed"): (1613722, "subspace.hip", "__device__ int cq_factor_invert(", "// After panel p:",
-                                  "e30cd272f1eba6ff24a6d3cf541743028e1c68f324311ce9e44280b2cffe7132"),
-    ("eig_solve", "c3", "mixed"): (1087283, "eig.hip", "__device__ __forceinline__ void pair_solve(",
+    ("cq_panel", "c3", "mixed"): (1503334, "subspace.hip", "__device__ int cq_factor_invert(", "// After panel p:",
+                                  "034fe9c71c7400a65c362deb844ee215d67250e14fe77a159f508a1b9b223686"),
+    ("eig_solve", "c3", "mixed"): ({128: 1027891, 64: 1807053}, "eig.hip", "__device__ __forceinline__ void pair_solve(",
                                    "// X[:, I u J] <- X[:, I u J] W over a tile",
                                    "c2f5ba0ce77ef0efbbd63cf84a9049359fb102d74557ba2d6f2ea1dfaf8a4f72"),
-    ("eig_round", "c3", "mixed"): (11164570, "eig.hip",
+    ("eig_round", "c3", "mixed"): ({128: 10183885, 64: 9873818}, "eig.hip",
                                    "template <int ROWS>\n__global__ __launch_bounds__(256) void k_eig_round(",
                                    "// End of a sweep:",
                                    "4a92ac0365fbc8a47656ae36c9ce1a75a33b9b20be34470f03ccecc02601554b"),
-    ("sub_gemm", "c3", "mixed"): (285009510, "mfma_gemm.hip", "template <typename Tc, bool TA, bool TB>",
+    ("sub_gemm", "c3", "mixed"): (284999475, "mfma_gemm.hip", "template <typename Tc, bool TA, bool TB>",
                                   "// C (M x N, ldc) = op(A) op(B)",
                                   "fd7925f0523d4073a12f38d53a4c415d2ecb720249ca91724cf59e4bf085578f"),
 }
 
 
-def kernel_traffic(kname, config, precision, core=None):
+def kernel_traffic(kname, config, precision, core=None, tuning=None):
     key = (kname, config, precision)
     if key not in TRAFFIC:
         return None
@@ -138,6 +140,11 @@ def kernel_traffic(kname, config, precision, core=None):
         return None
     import hashlib
     nbytes, fname, start, end, digest = TRAFFIC[key]
+    if isinstance(nbytes, dict):
+        rows = (tuning or {}).get("gram_rows", GRAM_ROWS)
+        if rows not in nbytes:
+            return None
+        nbytes = nbytes[rows]
     with open(os.path.join(ROOT, "paper_2011_04235_amd", "csrc", fname)) as f:
         src = f.read()
     a = src.index(start)
@@ -244,7 +251,7 @@ def kernel_alg_flops(info, routes, core, mixed, tuning, sweeps, rotated):
     return out
 
 
-def roofline_entry(kname, kms, alg, mixed, config, head_key, core=None):
+def roofline_entry(kname, kms, alg, mixed, config, head_key, core=None, tuning=None):
     """Roofline object of one timed kernel: algorithmic flops per step over its summed launch
     time per step, against the peak of its unit."""
     n_launch, k_ms = kms[kname]
@@ -255,7 +262,7 @@ def roofline_entry(kname, kms, alg, mixed, config, head_key, core=None):
         bound, peak = "alu", 78.6                          # FP64 vector peak
     return {"bound": bound, "kernel": KERNEL_NAMES[kname], "achieved": round(achieved, 5), "peak": peak,
             "unit": "TFLOP/s", "frac": round(achieved / peak, 6),
-            "traffic": kernel_traffic(kname, config, "mixed" if mixed else "fp64", core),
+            "traffic": kernel_traffic(kname, config, "mixed" if mixed else "fp64", core, tuning),
             "traffic_unit": "bytes per launch", "launches": round(n_launch, 1),
             "avg_us": round(k_ms / max(n_launch, 1) * 1e3, 3), "ms_per_step": round(k_ms, 4),
             "flops_per_launch": alg[kname] / max(n_launch, 1),
@@ -706,6 +713,8 @@ def main():
                          "round's partial Grams, then the pair solves; default) or three")
     ap.add_argument("--block-route", type=float, default=None,
                     help="p q^2 from which a diagonal block takes the Gram route (default: the library's)")
+    ap.add_argument("--gram-rows", type=int, default=None, choices=[64, 128, 256],
+                    help="rows per partial Gram of the eigensolvers (plain form; default: the library's)")
     ap.add_argument("--eig-precond", type=int, default=None, choices=[0, 1],
                     help="pivoted-Cholesky start of the core and Rayleigh-Ritz eigensolves (plain form; "
                          "default: the library's)")
@@ -799,7 +808,8 @@ def main():
         progress(f"{precision} {'batched' if batched else 'plain'}: start")
         h = fp.Handle(0, precision=precision)
         h.set_tuning(eig_fused=int(args.eig_rounds == "fused"),
-                     **({"precond": args.eig_precond} if args.eig_precond is not None else {}))
+                     **({"precond": args.eig_precond} if args.eig_precond is not None else {}),
+                     **({"gram_rows": args.gram_rows} if args.gram_rows is not None else {}))
         h.set_core_solver(mode=args.core_mode,
                           **({"max_frac": args.core_max_frac} if args.core_max_frac is not None else {}),
                           **({"min_order": args.core_min_order} if args.core_min_order is not None else {}),
@@ -886,8 +896,10 @@ def main():
     share = {k: round(v[1] / head["eager_ms"], 4) for k, v in kms.items()}
     # the dominant kernel: the largest summed launch time per step among the timed ones
     dom = max((k for k in kms if kms[k][0] > 0), key=lambda k: kms[k][1], default=None)
-    roof = roofline_entry(dom, kms, alg, mixed_head, args.config, head_key, head["core"]) if dom else None
-    roof_mfma = roofline_entry("sub_gemm", kms, alg, mixed_head, args.config, head_key, head["core"]) \
+    roof = roofline_entry(dom, kms, alg, mixed_head, args.config, head_key, head["core"], head["tuning"]) \
+        if dom else None
+    roof_mfma = roofline_entry("sub_gemm", kms, alg, mixed_head, args.config, head_key, head["core"],
+                               head["tuning"]) \
         if kms.get("sub_gemm", (0, 0))[0] > 0 else None
     base = None
     if not args.no_cpu_baseline:
