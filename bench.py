@@ -197,14 +197,20 @@ def eig_job_flops(order, sw, rot, tuning, kernel):
     return sw * rounds * real_pairs * 2.0 * ld * 1024 + rot * 2.0 * ld * 1024
 
 
-def solve_alg_flops(info, sweeps, rotated, tuning, kernel="eig_solve"):
-    """Algorithmic flops of the eigensolver launches of `kernel` in one run of a matrix whose
-    cores both ran on Jacobi at their full order (eig_job_flops per core)."""
+def solve_alg_flops(info, sweeps, rotated, tuning, kernel="eig_solve", routes=None, core=None, mixed=False):
+    """Algorithmic flops of the eigensolver launches of `kernel` in one run of a matrix
+    (eig_job_flops per core), at the order each core's Jacobi ran on: k for a core on the
+    subspace route (its Rayleigh-Ritz matrix), q otherwise (also after a failed check, whose
+    Jacobi on G dominates)."""
     tot = 0.0
-    for q, sw, rot in ((info["n1"], sweeps[1], rotated[0]), (info["s"] + info["n2"], sweeps[2], rotated[1])):
+    cores = ((info["n1"], info["s"], sweeps[1], rotated[0]), (info["s"] + info["n2"], info["r"], sweeps[2], rotated[1]))
+    for c, (q, t, sw, rot) in enumerate(cores):
         if q <= 0 or sw <= 0:
             continue
-        tot += eig_job_flops(q, sw, rot, tuning, kernel)
+        order = q
+        if routes is not None and core is not None and routes[c] == "subspace":
+            order = core_basis(core, t, q, mixed) or q
+        tot += eig_job_flops(order, sw, rot, tuning, kernel)
     return tot
 
 
@@ -423,6 +429,7 @@ def run_batched_workload(args, torch, fp):
         ms_plain = timed(plain_step, args.steps) * 1e3
         for h in hs:
             h.sync()
+        plain_routes = [x for h in hs for x in h.last_core_routes()]
         del hs
         progress(f"{prec}: per-matrix {ms_plain:.1f} ms/step; batched runs (autotune first)")
         # batched: one batch over all matrices on one handle
@@ -447,6 +454,8 @@ def run_batched_workload(args, torch, fp):
         progress(f"{prec}: batched {ms_batched:.1f} ms/step")
         status, sweeps = b.sync()
         rotated = b.rotations()
+        routes = b.core_routes()
+        core = h.get_core_solver()
         graph_launches = b.last_graph_launches()
         # the dominant kernel, timed in an eager pass of the same schedule
         b.set_graph(False)
@@ -467,10 +476,13 @@ def run_batched_workload(args, torch, fp):
                      "sweeps_max": sweeps.max(axis=0).tolist(), "tuning": b.get_tuning(),
                      "tune_report": tune_report, "graph_launches_per_step": graph_launches,
                      "n_launch": n_launch, "k_ms": k_ms, "sigma_rel_diff_plain_vs_batched": sig_diff,
+                     "routes": {r: sum(1 for rr in routes for x in rr if x == r) for r in
+                                sorted({x for rr in routes for x in rr})},
+                     "plain_routes": {r: plain_routes.count(r) for r in sorted(set(plain_routes))},
                      "solve_alg_flops": eager_steps * sum(
                          solve_alg_flops(plan.info, sw.tolist(), rot.tolist(), b.get_tuning(),
-                                         args.roofline_kernel)
-                         for plan, sw, rot in zip(plans, sweeps, rotated))}
+                                         args.roofline_kernel, rr, core, prec == "mixed")
+                         for plan, sw, rot, rr in zip(plans, sweeps, rotated, routes))}
         del b, h
     head_key = "mixed" if "mixed" in res else "fp64"
     head = res[head_key]
