@@ -467,15 +467,21 @@ def run_batched_workload(args, torch, fp):
         b.set_graph(True)
         # agreement of the two forms (per matrix: largest relative sigma difference)
         sig_diff = 0.0
+        sig_nonfinite = 0   # matrices whose comparison is not finite (max() would drop a NaN)
         for o1, o2 in zip(outs, outb):
             s1, s2 = o1[1].cpu().numpy(), o2[1].cpu().numpy()
             keep = s1 > 1e-6 * s1[0]
-            sig_diff = max(sig_diff, float(np.max(np.abs(s1[keep] - s2[keep]) / s1[keep])))
+            rel = np.abs(s1[keep] - s2[keep]) / s1[keep]
+            if not np.all(np.isfinite(rel)):
+                sig_nonfinite += 1
+                continue
+            sig_diff = max(sig_diff, float(np.max(rel)) if rel.size else 0.0)
         res[prec] = {"plain_ms": ms_plain, "batched_ms": ms_batched, "eager_batched_ms": eager_ms,
                      "status_ok": int(sum(1 for x in status if x == "OK")),
                      "sweeps_max": sweeps.max(axis=0).tolist(), "tuning": b.get_tuning(),
                      "tune_report": tune_report, "graph_launches_per_step": graph_launches,
                      "n_launch": n_launch, "k_ms": k_ms, "sigma_rel_diff_plain_vs_batched": sig_diff,
+                     "sigma_nonfinite_plain_vs_batched": sig_nonfinite,
                      "routes": {r: sum(1 for rr in routes for x in rr if x == r) for r in
                                 sorted({x for rr in routes for x in rr})},
                      "plain_routes": {r: plain_routes.count(r) for r in sorted(set(plain_routes))},
@@ -539,7 +545,9 @@ def run_batched_workload(args, torch, fp):
                    "nnz_total": int(sum(p.nnz for p in probs))},
         "flop_model_total": F_tot,
         "plan_s": round(plan_s, 3),
-        "forms": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+        # times to 4 decimals; the sigma agreement keeps its significant digits (it sits near 1e-13)
+        "forms": {k: {kk: (float(f"{vv:.3g}") if kk.startswith("sigma_") else round(vv, 4))
+                      if isinstance(vv, float) else vv for kk, vv in v.items()}
                   for k, v in res.items()},
         "speedup_batched_vs_plain": {k: round(v["plain_ms"] / v["batched_ms"], 4) for k, v in res.items()},
         "roofline": roof,
