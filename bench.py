@@ -747,6 +747,8 @@ def main():
     ap.add_argument("--core-k-factor", type=float, default=None,
                     help="basis of the subspace route in the form being run, k = ceil32(factor * t) "
                          "(default: the library's)")
+    ap.add_argument("--core-orth-every", type=int, default=None,
+                    help="products by G between Cholesky QRs of the subspace route (default: the library's)")
     ap.add_argument("--core-iters", type=int, default=None,
                     help="products by G of the subspace route in the form being run (default: the library's)")
     ap.add_argument("--inner", default="exact", choices=["exact", "rand"],
@@ -836,7 +838,8 @@ def main():
                           **({("k_factor_mixed" if precision == "mixed" else "k_factor"): args.core_k_factor}
                              if args.core_k_factor is not None else {}),
                           **({("iters_mixed" if precision == "mixed" else "iters_fp64"): args.core_iters}
-                             if args.core_iters is not None else {}))
+                             if args.core_iters is not None else {}),
+                          **({"orth_every": args.core_orth_every} if args.core_orth_every is not None else {}))
         if args.inner == "rand":
             h.set_inner(mode=1, oversample=5, iters=11, seed=0)
         if args.block_route is not None:
