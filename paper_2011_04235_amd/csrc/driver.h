@@ -21,7 +21,7 @@ struct Tuning {
     int inner_sweeps = 1;        // inner Jacobi sweeps per pair solve
     int precond = 1;             // pivoted-Cholesky start of the core eigensolvers
     int core_mode = -1;          // core solver route chosen by the autotuner (-1: the group's own)
-    int eig_fused = 1;           // eigensolver rounds in one launch (0: three launches a round)
+    int eig_fused = 1;           // eigensolver rounds in two launches (0: three launches a round)
 };
 bool tuning_valid(const Tuning& t);
 

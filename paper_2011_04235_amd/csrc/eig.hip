@@ -13,9 +13,12 @@
 // by descending norm (de Rijk's ordering), which saves sweeps; X X^T, and so the result, does
 // not depend on the order.
 //
-// Several independent problems ("jobs") advance together: each round is three launches
-// (partial Grams, pair solves, column updates) whose workgroups are spread over the jobs
-// still inside their sweep, found from prefix sums of the per-job workgroup counts. Jobs
+// Several independent problems ("jobs") advance together. By default a round is two launches:
+// the column update of the previous round fused with this round's partial Grams
+// (k_eig_round, on two iterates that alternate by round), then the pair solves; the
+// three-launch form (partial Grams, pair solves, column updates on one iterate) gives the
+// same results bitwise. Each launch's workgroups are spread over the jobs still inside their
+// sweep, found from prefix sums of the per-job workgroup counts. Jobs
 // with fewer blocks have fewer rounds per sweep and sit out the remaining rounds. A done job
 // returns at once from every kernel, so a fixed launch sequence per sweep serves any mix of
 // converged and running jobs (and can be replayed from a captured graph).
