@@ -308,10 +308,23 @@ static int make_sub_core(Group& g, SubSet& S, int inst, int64_t q, int64_t t, in
     R.lam_out = lam_out;
     R.vec_out = vec_out;
     R.sp = gemm_tn_splits(k, k, q);
-    // the q x k products by G fill the chip through a K split when their 128 x 128 tiles are
-    // fewer than two per compute unit
+    // the q x k products by G (128 x 128 tiles) split K so that their workgroups fill whole
+    // waves of the resident slots: two workgroups per compute unit for the FP32 kernel of the
+    // mixed form, one for the FP64 kernel. The split s minimises ceil(tiles s / slots) / s (the
+    // product's time in units of one unsplit wave) plus 0.02 s for the partials written and
+    // summed, with chunks of at least 256 rows of K
     const int64_t tiles = ((q + 127) / 128) * ((k + 127) / 128);
-    R.gsplit = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((2 * g.ncu + tiles - 1) / tiles, q / 256)));
+    const int64_t slots = static_cast<int64_t>(g.mixed ? 2 : 1) * g.ncu;
+    const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(16, q / 256));
+    R.gsplit = 1;
+    double best = 1e30;
+    for (int64_t s = 1; s <= smax; ++s) {
+        const double c = static_cast<double>((tiles * s + slots - 1) / slots) / static_cast<double>(s) + 0.02 * s;
+        if (c < best - 1e-12) {
+            best = c;
+            R.gsplit = static_cast<int>(s);
+        }
+    }
     const int64_t kp = R.kp;
     const size_t ed = eig_job_doubles(k, g.tune.gram_rows), ei = eig_job_ints(k);
     const size_t doubles = static_cast<size_t>(2 * q * k + k * k + k * t + static_cast<int64_t>(R.sp) * k * k +
