@@ -126,9 +126,11 @@ TRAFFIC = {
                                    "template <int ROWS>\n__global__ __launch_bounds__(256) void k_eig_round(",
                                    "// End of a sweep:",
                                    "4a92ac0365fbc8a47656ae36c9ce1a75a33b9b20be34470f03ccecc02601554b"),
-    ("sub_gemm", "c3", "mixed"): (284999475, "mfma_gemm.hip", "template <typename Tc, bool TA, bool TB>",
-                                  "// C (M x N, ldc) = op(A) op(B)",
-                                  "fd7925f0523d4073a12f38d53a4c415d2ecb720249ca91724cf59e4bf085578f"),
+    # the products by G: the kernel and the K-split rule of the subspace route
+    ("sub_gemm", "c3", "mixed"): (280014746, ("mfma_gemm.hip", "driver.cpp"),
+                                  ("template <typename Tc, bool TA, bool TB>", "// the q x k products by G (128 x 128 tiles)"),
+                                  ("// C (M x N, ldc) = op(A) op(B)", "const int64_t kp = R.kp;"),
+                                  "dd824cd7524d5ab97c6ce5a586d20632ad739ac3945e1acb08885409d543252a"),
 }
 
 
@@ -140,16 +142,23 @@ def kernel_traffic(kname, config, precision, core=None, tuning=None):
         return None
     import hashlib
     nbytes, fname, start, end, digest = TRAFFIC[key]
+    if nbytes is None:
+        return None
     if isinstance(nbytes, dict):
         rows = (tuning or {}).get("gram_rows", GRAM_ROWS)
         if rows not in nbytes:
             return None
         nbytes = nbytes[rows]
-    with open(os.path.join(ROOT, "paper_2011_04235_amd", "csrc", fname)) as f:
-        src = f.read()
-    a = src.index(start)
-    b = src.index(end, a + 1) if end else len(src)
-    if hashlib.sha256(src[a:b].encode()).hexdigest() != digest:
+    # one source section, or several (kernel and launch rule) hashed in order
+    sections = [(fname, start, end)] if isinstance(fname, str) else list(zip(fname, start, end))
+    text = ""
+    for fn, st, en in sections:
+        with open(os.path.join(ROOT, "paper_2011_04235_amd", "csrc", fn)) as f:
+            src = f.read()
+        a = src.index(st)
+        b = src.index(en, a + 1) if en else len(src)
+        text += src[a:b]
+    if hashlib.sha256(text.encode()).hexdigest() != digest:
         return None
     return nbytes
 
