@@ -536,7 +536,8 @@ int fastpi_apply(fastpi_handle* h, int64_t m, int64_t n, int64_t r, const double
     }
     HIP_TRY(hipSetDevice(h->device));
     hipStream_t st = h->stream;
-    const int sp = gemm_tn_splits(r, L, m);
+    const bool mixed = h->opts.precision == FASTPI_MIXED;
+    const int sp = gemm_tn_splits(r, L, m, mixed, h->grp.ncu);
     const size_t need = static_cast<size_t>(r + r * L + static_cast<int64_t>(sp) * r * L) * sizeof(double);
     int rc = grow(h->aws, h->aws_bytes, need, st, "apply scratch");
     if (rc != FASTPI_OK) return rc;
@@ -544,7 +545,6 @@ int fastpi_apply(fastpi_handle* h, int64_t m, int64_t n, int64_t r, const double
     double* W = inv + r;
     double* part = W + r * L;
     launch_pinv_sigma(S, r, static_cast<double>(std::max(m, n)) * DBL_EPSILON, inv, st);
-    const bool mixed = h->opts.precision == FASTPI_MIXED;
     launch_gemm_tn(U, r, Y, L, r, L, m, W, L, inv, nullptr, part, sp, st, mixed);
     launch_gemm_nn(V, r, nullptr, W, L, n, L, r, Z, L, nullptr, st, mixed);
     return check_launch();
@@ -602,7 +602,8 @@ int fastpi_apply_noalloc(fastpi_handle* h, int64_t m, int64_t n, int64_t r, cons
         return FASTPI_EINVAL;
     }
     const int64_t fit = (kNoAllocApplyDoubles - r - rl) / rl;
-    const int sp = static_cast<int>(std::min<int64_t>(gemm_tn_splits(r, L, m), fit));
+    const bool mixed = h->opts.precision == FASTPI_MIXED;
+    const int sp = static_cast<int>(std::min<int64_t>(gemm_tn_splits(r, L, m, mixed, h->grp.ncu), fit));
     HIP_TRY(hipSetDevice(h->device));
     double* base = nullptr;
     int rc = noalloc_scratch(h->device, &base);
@@ -612,7 +613,6 @@ int fastpi_apply_noalloc(fastpi_handle* h, int64_t m, int64_t n, int64_t r, cons
     double* W = inv + r;
     double* part = W + rl;
     launch_pinv_sigma(S, r, static_cast<double>(std::max(m, n)) * DBL_EPSILON, inv, st);
-    const bool mixed = h->opts.precision == FASTPI_MIXED;
     launch_gemm_tn(U, r, Y, L, r, L, m, W, L, inv, nullptr, part, sp, st, mixed);
     launch_gemm_nn(V, r, nullptr, W, L, n, L, r, Z, L, nullptr, st, mixed);
     return check_launch();

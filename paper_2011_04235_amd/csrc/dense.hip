@@ -150,13 +150,37 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const double* __restrict__ A, i
     }
 }
 
-int gemm_tn_splits(int64_t M, int64_t N, int64_t K) {
-    // enough workgroups to cover the chip (~4 per CU), chunks of at least 256 rows of K
+// products big enough for the 128 x 128 matrix-core tiles go there
+static bool use_mfma(int64_t M, int64_t N, int64_t K) { return M >= 128 && N >= 64 && K >= 64; }
+
+int gemm_tn_splits(int64_t M, int64_t N, int64_t K, bool fp32, int ncu) {
+    // chunks of at least 256 rows of K
+    const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(256, (K + 255) / 256));
+    if (M <= 0 || N <= 0) return 1;   // empty product (e.g. a core of rank 0)
+    if (use_mfma(M, N, K)) {
+        // matrix cores: whole waves of the resident workgroups (two per CU in FP32, one in
+        // FP64). s minimises the estimated time: the waves times one workgroup's share of a
+        // tile (2 * 128^2 * K / s flops at ~120 GFLOP/s per resident workgroup), plus the s
+        // partials written and summed (16 M N bytes each at ~4 TB/s)
+        const int64_t tiles = ((M + 127) / 128) * ((N + 127) / 128);
+        const int64_t slots = static_cast<int64_t>(fp32 ? 2 : 1) * std::max(1, ncu);
+        const double t_tile = 2.0 * 128.0 * 128.0 * static_cast<double>(K) / 1.2e11;
+        const double t_part = 16.0 * static_cast<double>(M) * static_cast<double>(N) / 4.0e12;
+        int64_t best_s = 1;
+        double best = 1e30;
+        for (int64_t s = 1; s <= smax; ++s) {
+            const double c = static_cast<double>((tiles * s + slots - 1) / slots) * t_tile / static_cast<double>(s) +
+                             static_cast<double>(s) * t_part;
+            if (c < best - 1e-12) {
+                best = c;
+                best_s = s;
+            }
+        }
+        return static_cast<int>(best_s);
+    }
+    // FMA kernel: enough 64 x 64 tiles to cover the chip (~4 workgroups per CU)
     const int64_t tiles = ((M + TM - 1) / TM) * ((N + TN - 1) / TN);
-    if (tiles <= 0) return 1;   // empty product (e.g. a core of rank 0)
-    int64_t splits = (1024 + tiles - 1) / tiles;
-    splits = std::min<int64_t>(splits, (K + 255) / 256);
-    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(splits, 256)));
+    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((1024 + tiles - 1) / tiles, smax)));
 }
 
 void launch_sum_parts(const double* part, int nsplit, int64_t M, int64_t N, double* C, int64_t ldc, hipStream_t st) {
@@ -165,9 +189,6 @@ void launch_sum_parts(const double* part, int nsplit, int64_t M, int64_t N, doub
     hipLaunchKernelGGL(k_reduce_parts, dim3(static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 8192))), dim3(256),
                        0, st, part, nsplit, M, N, C, ldc, nullptr, nullptr);
 }
-
-// products big enough for the 128 x 128 matrix-core tiles go there
-static bool use_mfma(int64_t M, int64_t N, int64_t K) { return M >= 128 && N >= 64 && K >= 64; }
 
 void launch_gemm_tn(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M,
                     int64_t N, int64_t K, double* C, int64_t ldc, const double* rs,

@@ -234,7 +234,7 @@ int instance_upload(Instance& I, const Plan& p, size_t ws_cap, hipStream_t st) {
     I.o_c2 = take(n2 * r);
     I.o_eig = take(static_cast<int64_t>(std::max(eig_job_doubles(std::max<int64_t>(n1, 1), kMinGramRows),
                                                  eig_job_doubles(std::max<int64_t>(q3, 1), kMinGramRows))));
-    const int sp = gemm_tn_splits(s, s, m);
+    const int sp = std::max(gemm_tn_splits(s, s, m, false), gemm_tn_splits(s, s, m, true));   // either form
     I.o_part = take(static_cast<int64_t>(sp) * s * s);
     I.o_gs = take(gs);
     const int64_t spart = std::max({p.seg_a21c.npart * n1, p.seg_tc.npart * std::max(n2, s),
@@ -307,7 +307,7 @@ static int make_sub_core(Group& g, SubSet& S, int inst, int64_t q, int64_t t, in
     R.G = G;
     R.lam_out = lam_out;
     R.vec_out = vec_out;
-    R.sp = gemm_tn_splits(k, k, q);
+    R.sp = gemm_tn_splits(k, k, q, false, g.ncu);
     // the q x k products by G (128 x 128 tiles) split K so that their workgroups fill whole
     // waves of the resident slots: two workgroups per compute unit for the FP32 kernel of the
     // mixed form, one for the FP64 kernel. The split s minimises ceil(tiles s / slots) / s (the
@@ -406,7 +406,7 @@ static int make_rand_core(Group& g, int inst, int64_t q, int64_t t, const double
     R.lam_out = lam_out;
     R.vec_out = vec_out;
     const int64_t k = R.k;
-    R.sp = gemm_tn_splits(k, k, q);
+    R.sp = gemm_tn_splits(k, k, q, false, g.ncu);
     const size_t ed = eig_job_doubles(k, g.tune.gram_rows), ei = eig_job_ints(k);
     const size_t doubles = static_cast<size_t>(2 * q * k + 3 * k * k + k + static_cast<int64_t>(R.sp) * k * k) + ed;
     void* p = nullptr;
@@ -443,8 +443,8 @@ static int build_sets(Group& g, hipStream_t st) {
     // blocks on the Gram route: G, E, lam, W, split-K partials and eigensolver workspace
     for (BigBlock& b : g.big) {
         const int64_t p = b.p, q = b.q, t = b.t;
-        const int spg = b.trans ? gemm_tn_splits(q, q, p) : 1;
-        const int spw = b.trans ? 1 : gemm_tn_splits(p, t, q);
+        const int spg = b.trans ? gemm_tn_splits(q, q, p, false, g.ncu) : 1;
+        const int spw = b.trans ? 1 : gemm_tn_splits(p, t, q, false, g.ncu);
         b.sp = std::max(spg, spw);
         const int64_t part = std::max<int64_t>(static_cast<int64_t>(spg) * q * q, static_cast<int64_t>(spw) * p * t);
         const size_t ed = eig_job_doubles(q, g.tune.gram_rows), ei = eig_job_ints(q);
@@ -919,7 +919,7 @@ static void stage_mid(Group& g, const RunCfg& c, KernelTimer* timer, hipStream_t
             double* G3 = ws + I.o_g3;
             launch_fill(G3, q3 * q3, 0.0, st);
             if (s > 0) {
-                const int sp = gemm_tn_splits(s, s, m);
+                const int sp = gemm_tn_splits(s, s, m, c.mixed, g.ncu);
                 launch_gemm_tn(U2, s, U2, s, s, s, m, G3, q3, sig2, sig2, ws + I.o_part, sp, st, c.mixed);
                 launch_sparse_proj(d.seg_tc, d.t_rowidx, vals + d.off_tc, U2, s, sig2, G3, q3, s, ws + I.o_spart,
                                    st);

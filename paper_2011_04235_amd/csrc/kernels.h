@@ -208,7 +208,8 @@ int eig_iterate(const EigSet& es, int max_sweeps, int inner_sweeps, hipStream_t 
                 hipStream_t copy_st, KernelTimer* timer, hipGraphExec_t sweep_graph);
 
 // dense (dense.hip)
-int gemm_tn_splits(int64_t M, int64_t N, int64_t K);
+// K split of a transposed-A product (M x N over K) for launch_gemm_tn in the given precision
+int gemm_tn_splits(int64_t M, int64_t N, int64_t K, bool fp32 = false, int ncu = 256);
 void launch_gemm_tn(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M,
                     int64_t N, int64_t K, double* C, int64_t ldc, const double* rs,
                     const double* cs, double* part, int nsplit, hipStream_t st, bool fp32 = false);
