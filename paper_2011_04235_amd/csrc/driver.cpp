@@ -294,6 +294,19 @@ static void free_sub(Group& g) {
     }
 }
 
+// C (q x n) = G B for a core on the subspace route, through the core's K split and partials
+// when it has one (n <= k, so the partials fit); timed under `kind` when a timer is given.
+static void product_by_g(const SubCore& R, const double* B, int64_t n, double* C, bool fp32, hipStream_t st,
+                         KernelTimer* timer = nullptr, int kind = KT_NONE) {
+    if (R.gsplit > 1) {
+        launch_mfma_gemm(false, false, R.G, R.q, B, n, R.q, n, R.q, R.gpart, n, R.gsplit, R.q * n, st, fp32, timer,
+                         kind);
+        launch_sum_parts(R.gpart, R.gsplit, R.q, n, C, n, st);
+    } else {
+        launch_gemm_nn(R.G, R.q, nullptr, B, n, R.q, n, R.q, C, n, nullptr, st, fp32, timer, kind);
+    }
+}
+
 // Buffers of one core on the subspace route and its Rayleigh-Ritz eigensolver job.
 static int make_sub_core(Group& g, SubSet& S, int inst, int64_t q, int64_t t, int64_t k, const double* G,
                          double* lam_out, double* vec_out, EigJob& hjob, hipStream_t st) {
@@ -572,16 +585,7 @@ static void sub_pre(Group& g, int c, const RunCfg& cfg, KernelTimer* timer, hipS
         in_q = !in_q;
     };
     auto apply = [&](bool fp32) {
-        for (SubCore& R : S.cores) {
-            if (R.gsplit > 1) {
-                launch_mfma_gemm(false, false, R.G, R.q, cur(R), R.k, R.q, R.k, R.q, R.gpart, R.k, R.gsplit, R.q * R.k,
-                                 st, fp32, timer, KT_SUB_GEMM);
-                launch_sum_parts(R.gpart, R.gsplit, R.q, R.k, oth(R), R.k, st);
-            } else {
-                launch_gemm_nn(R.G, R.q, nullptr, cur(R), R.k, R.q, R.k, R.q, oth(R), R.k, nullptr, st, fp32, timer,
-                               KT_SUB_GEMM);
-            }
-        }
+        for (SubCore& R : S.cores) product_by_g(R, cur(R), R.k, oth(R), fp32, st, timer, KT_SUB_GEMM);
         in_q = !in_q;
     };
     for (int it = 0; it < iters; ++it) {
@@ -592,7 +596,7 @@ static void sub_pre(Group& g, int c, const RunCfg& cfg, KernelTimer* timer, hipS
     orth(false);
     // H = Q^T (G Q), a job of the update's batched Jacobi set
     for (SubCore& R : S.cores) {
-        launch_gemm_nn(R.G, R.q, nullptr, cur(R), R.k, R.q, R.k, R.q, oth(R), R.k, nullptr, st, false);
+        product_by_g(R, cur(R), R.k, oth(R), false, st);
         launch_gemm_tn(cur(R), R.k, oth(R), R.k, R.k, R.k, R.q, R.H, R.k, nullptr, nullptr, R.part, R.sp, st, false);
         launch_symmetrize(R.H, R.k, st);
     }
@@ -611,7 +615,7 @@ static int sub_post(Group& g, int c, const RunCfg& cfg, hipStream_t st) {
         const double* Qb = in_q ? R.Q : R.Y;
         double* Rb = in_q ? R.Y : R.Q;
         launch_gemm_nn(Qb, R.k, nullptr, R.Wv, R.t, R.q, R.t, R.k, R.vec_out, R.t, nullptr, st, false);
-        launch_gemm_nn(R.G, R.q, nullptr, R.vec_out, R.t, R.q, R.t, R.q, Rb, R.t, nullptr, st, false);
+        product_by_g(R, R.vec_out, R.t, Rb, false, st);
         launch_sub_residual(Rb, R.vec_out, R.lam_out, R.q, R.t, tol, S.flags + i, st);
     }
     HIP_TRY(hipMemcpyAsync(S.host_flags, S.flags, sizeof(int) * nc, hipMemcpyDeviceToHost, st));
