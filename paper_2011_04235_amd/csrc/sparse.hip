@@ -14,6 +14,24 @@ namespace fastpi {
 // G[a, :] (+)= sum_h S[h, a] S[h, :] for a sparse S given as CSC (segments over its
 // columns, rowidx, cval) and CSR (rowptr, colidx, rval): the Gram S^T S, q x q.
 constexpr int SG_WAVES = 4;
+constexpr int SG_GROUP = 8;   // entries whose first row batches are loaded together
+constexpr int SG_LONG = 4;    // row batches of a long row loaded together
+
+// value of lane l (uniform l) for 64-bit integers and doubles
+__device__ __forceinline__ int64_t lane_i64(int64_t v, int l) {
+    const int lo = __builtin_amdgcn_readlane(static_cast<int>(v), l);
+    const int hi = __builtin_amdgcn_readlane(static_cast<int>(v >> 32), l);
+    return static_cast<int64_t>((static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo));
+}
+__device__ __forceinline__ double lane_f64(double v, int l) { return __longlong_as_double(lane_i64(__double_as_longlong(v), l)); }
+
+// One wave per (segment, column chunk); the segment's entries are added in order, each entry's
+// row in 64-wide batches (lane i takes the row's elements i, i + 64, ...; a row's columns are
+// distinct, so the order within an entry does not matter). Memory latency is overlapped without
+// changing that order: the entries' rows, values and row extents are read once per 64 entries
+// (one per lane), the first batches of SG_GROUP entries are loaded together before they are
+// added one entry after the other, and the rest of a long row is loaded SG_LONG batches at a
+// time.
 __global__ __launch_bounds__(SG_WAVES * 64) void k_sparse_gram(
     SegDev sg, const int* __restrict__ rowidx, const double* __restrict__ cval,
     const int64_t* __restrict__ rowptr, const int* __restrict__ colidx, const double* __restrict__ rval,
@@ -34,17 +52,68 @@ __global__ __launch_bounds__(SG_WAVES * 64) void k_sparse_gram(
     for (int64_t c = c0 + lane; c < c1; c += kWave)
         buf[c - c0] = (pidx < 0 && accumulate) ? dst[c] : 0.0;
     __builtin_amdgcn_wave_barrier();
-    for (int64_t e = sg.begin[seg]; e < sg.end[seg]; ++e) {
-        const int64_t h = rowidx[e];
-        const double va = cval[e];
-        for (int64_t f = rowptr[h] + lane; f < rowptr[h + 1]; f += kWave) {
-            const int64_t b = colidx[f];
-            if (b >= c0 && b < c1) buf[b - c0] += va * rval[f];
+    const int64_t seg_end = sg.end[seg];
+    for (int64_t g0 = sg.begin[seg]; g0 < seg_end; g0 += kWave) {
+        const int ne = static_cast<int>(min<int64_t>(kWave, seg_end - g0));
+        // every load below reads a valid index (clamped; a segment's matrix has entries, and
+        // a row batch's index is clamped into its non-empty row or to entry 0), and the lanes
+        // or entries past the end select neutral values: no branches around the loads, so
+        // they stay in flight across the adds
+        const int64_t h = rowidx[g0 + min(lane, ne - 1)];
+        const double va = cval[g0 + min(lane, ne - 1)];
+        const int64_t rb = rowptr[h], re = rowptr[h + 1];
+        for (int k0 = 0; k0 < ne; k0 += SG_GROUP) {
+            // the first row batch of SG_GROUP entries, all loads in flight together
+            int fb[SG_GROUP];
+            double fv[SG_GROUP];
+#pragma unroll
+            for (int u = 0; u < SG_GROUP; ++u) {
+                const int kc = min(k0 + u, ne - 1);
+                const int64_t f = lane_i64(rb, kc) + lane;
+                const bool ok = k0 + u < ne && f < lane_i64(re, kc);
+                const int64_t fi = ok ? f : 0;
+                const int bl = colidx[fi];
+                const double vl = rval[fi];
+                fb[u] = ok ? bl : -1;
+                fv[u] = vl;
+            }
+#pragma unroll
+            for (int u = 0; u < SG_GROUP; ++u) asm volatile("" : "+v"(fb[u]), "+v"(fv[u]));
+#pragma unroll
+            for (int u = 0; u < SG_GROUP; ++u) {
+                const int k = k0 + u;
+                if (k >= ne) break;
+                const int b = fb[u];
+                const double v = fv[u];
+                const double ak = lane_f64(va, k);
+                if (b >= c0 && b < c1) buf[b - c0] += ak * v;
+                const int64_t e = lane_i64(re, k);
+                for (int64_t f0 = lane_i64(rb, k) + kWave; f0 < e; f0 += SG_LONG * kWave) {
+                    int bq[SG_LONG];
+                    double vq[SG_LONG];
+#pragma unroll
+                    for (int w = 0; w < SG_LONG; ++w) {
+                        const int64_t f = f0 + w * kWave + lane;
+                        const int64_t fi = f < e ? f : e - 1;
+                        const int bl = colidx[fi];
+                        const double vl = rval[fi];
+                        bq[w] = f < e ? bl : -1;
+                        vq[w] = vl;
+                    }
+                    // all SG_LONG batches arrive before the adds (keeps the compiler from moving
+                    // a value's load into the conditional add, behind the earlier adds)
+#pragma unroll
+                    for (int w = 0; w < SG_LONG; ++w) asm volatile("" : "+v"(bq[w]), "+v"(vq[w]));
+#pragma unroll
+                    for (int w = 0; w < SG_LONG; ++w)
+                        if (bq[w] >= c0 && bq[w] < c1) buf[bq[w] - c0] += ak * vq[w];
+                }
+                // the next entry may touch the same columns from other lanes
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
         }
-        // the next entry may touch the same columns from other lanes
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     for (int64_t c = c0 + lane; c < c1; c += kWave) dst[c] = buf[c - c0];
 }
@@ -244,6 +313,9 @@ void launch_blockdiag_gram(const BlockWork* work, int nwork, const double* V1, c
 // and the columns of U2 in chunks of S_CH.
 constexpr int S_CH = 128;
 constexpr int KC = 32;
+constexpr int U2_UNROLL = 8;   // terms of a dot product whose loads are issued together
+constexpr int U2_TASKS = 8;    // outputs of U2 a thread sums at once
+constexpr int U2_KSTEP = 4;    // terms of each of them loaded together
 __global__ __launch_bounds__(256) void k_u2_top(const BlockWork* __restrict__ work,
                                                 const double* __restrict__ U1,
                                                 const double* __restrict__ sig1,
@@ -263,19 +335,64 @@ __global__ __launch_bounds__(256) void k_u2_top(const BlockWork* __restrict__ wo
             const int kc = min(KC, sb - k0);
             for (int e = threadIdx.x; e < kc * nc; e += blockDim.x) {
                 const int k = e / nc, c = e % nc;
+                const double* x = Vb + static_cast<int64_t>(k0 + k) * nb;
+                const double* y = V2 + static_cast<int64_t>(w.col0) * s + c0 + c;
+                // the sum in order over a; U2_UNROLL terms' loads in flight together
                 double acc = 0;
-                for (int a = 0; a < nb; ++a)
-                    acc += Vb[static_cast<int64_t>(k0 + k) * nb + a] *
-                           V2[static_cast<int64_t>(w.col0 + a) * s + c0 + c];
+                int a = 0;
+                for (; a + U2_UNROLL <= nb; a += U2_UNROLL) {
+                    double xv[U2_UNROLL], yv[U2_UNROLL];
+#pragma unroll
+                    for (int u = 0; u < U2_UNROLL; ++u) {
+                        xv[u] = x[a + u];
+                        yv[u] = y[static_cast<int64_t>(a + u) * s];
+                    }
+#pragma unroll
+                    for (int u = 0; u < U2_UNROLL; ++u) acc += xv[u] * yv[u];
+                }
+                for (; a < nb; ++a) acc += x[a] * y[static_cast<int64_t>(a) * s];
                 Tm[k][c] = acc * sig1[w.sig_off + k0 + k] * inv_sig2[c0 + c];
             }
             __syncthreads();
-            for (int e = threadIdx.x; e < mb * nc; e += blockDim.x) {
-                const int r = e / nc, c = e % nc;
-                double acc = 0;
-                for (int k = 0; k < kc; ++k) acc += Ub[static_cast<int64_t>(k0 + k) * mb + r] * Tm[k][c];
-                double* dst = U2 + static_cast<int64_t>(w.row0 + r) * s + c0 + c;
-                *dst = k0 == 0 ? acc : *dst + acc;
+            // U2_TASKS outputs per thread at a time, each summed in order over k, with the
+            // loads of U2_TASKS x U2_KSTEP terms in flight together
+            const int ntask = mb * nc;
+            for (int e0 = threadIdx.x; e0 < ntask; e0 += U2_TASKS * static_cast<int>(blockDim.x)) {
+                int rr[U2_TASKS], cc[U2_TASKS];
+                double acc[U2_TASKS];
+#pragma unroll
+                for (int j = 0; j < U2_TASKS; ++j) {
+                    const int e = min(e0 + j * static_cast<int>(blockDim.x), ntask - 1);
+                    rr[j] = e / nc;
+                    cc[j] = e % nc;
+                    acc[j] = 0.0;
+                }
+                const double* ub = Ub + static_cast<int64_t>(k0) * mb;
+                int k = 0;
+                for (; k + U2_KSTEP <= kc; k += U2_KSTEP) {
+                    double uv[U2_TASKS][U2_KSTEP];
+#pragma unroll
+                    for (int j = 0; j < U2_TASKS; ++j)
+#pragma unroll
+                        for (int u = 0; u < U2_KSTEP; ++u) uv[j][u] = ub[static_cast<int64_t>(k + u) * mb + rr[j]];
+#pragma unroll
+                    for (int j = 0; j < U2_TASKS; ++j)
+#pragma unroll
+                        for (int u = 0; u < U2_KSTEP; ++u) acc[j] += uv[j][u] * Tm[k + u][cc[j]];
+                }
+                for (; k < kc; ++k) {
+                    double uv[U2_TASKS];
+#pragma unroll
+                    for (int j = 0; j < U2_TASKS; ++j) uv[j] = ub[static_cast<int64_t>(k) * mb + rr[j]];
+#pragma unroll
+                    for (int j = 0; j < U2_TASKS; ++j) acc[j] += uv[j] * Tm[k][cc[j]];
+                }
+#pragma unroll
+                for (int j = 0; j < U2_TASKS; ++j) {
+                    if (e0 + j * static_cast<int>(blockDim.x) >= ntask) break;
+                    double* dst = U2 + static_cast<int64_t>(w.row0 + rr[j]) * s + c0 + cc[j];
+                    *dst = k0 == 0 ? acc[j] : *dst + acc[j];
+                }
             }
             __syncthreads();
             if (sb == 0) break;
