@@ -219,8 +219,11 @@ void launch_gemm_nn(const double* A, int64_t lda, const int* arow, const double*
                     int64_t M, int64_t N, int64_t K, double* C, int64_t ldc, const int* crow,
                     hipStream_t st, bool fp32, KernelTimer* timer, int kind) {
     if (M <= 0 || N <= 0) return;
-    if (!arow && !crow && use_mfma(M, N, K)) {
-        launch_mfma_gemm(false, false, A, lda, B, ldb, M, N, K, C, ldc, 1, 0, st, fp32, timer, kind);
+    if (use_mfma(M, N, K)) {
+        if (arow || crow)
+            launch_mfma_gemm_rows(A, lda, arow, B, ldb, M, N, K, C, ldc, crow, st, fp32);
+        else
+            launch_mfma_gemm(false, false, A, lda, B, ldb, M, N, K, C, ldc, 1, 0, st, fp32, timer, kind);
         return;
     }
     dim3 grid(static_cast<unsigned>((M + TM - 1) / TM), static_cast<unsigned>((N + TN - 1) / TN));

@@ -87,6 +87,10 @@ struct KernelTimer {
 void launch_mfma_gemm(bool ta, bool tb, const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M,
                       int64_t N, int64_t K, double* C, int64_t ldc, int nsplit, int64_t cstride, hipStream_t st,
                       bool fp32, KernelTimer* timer = nullptr, int kind = KT_NONE);
+// C[crow(i)] = A[arow(i)] B on the matrix cores (row gather of A, row scatter of C; a null
+// map is the identity), one K chunk
+void launch_mfma_gemm_rows(const double* A, int64_t lda, const int* arow, const double* B, int64_t ldb, int64_t M,
+                           int64_t N, int64_t K, double* C, int64_t ldc, const int* crow, hipStream_t st, bool fp32);
 
 // C[i * ldc + j] = sum_z part[z][i][j] (z < nsplit, fixed order)
 void launch_sum_parts(const double* part, int nsplit, int64_t M, int64_t N, double* C, int64_t ldc, hipStream_t st);

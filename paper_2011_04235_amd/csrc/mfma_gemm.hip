@@ -16,6 +16,8 @@
 // op(A): TA = false, A is M x K row-major (lda); TA = true, A is stored K x M (A^T row-major).
 // op(B): TB = false, B is K x N row-major (ldb); TB = true, B is stored N x K.
 // Split K: blockIdx.z takes rows [z kchunk, (z + 1) kchunk) of K and writes C + z * cstride.
+// GA (with TA = TB = false, no split): row i of A is row arow[i] of the stored A and row i
+// of C goes to row crow[i] (either map may be null: the identity).
 #include "device_common.h"
 #include "kernels.h"
 
@@ -49,11 +51,13 @@ struct Mfma<float> {
     static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
 };
 
-template <typename Tc, bool TA, bool TB>
+template <typename Tc, bool TA, bool TB, bool GA>
 __global__ __launch_bounds__(256) void k_mfma_gemm(const double* __restrict__ A, int64_t lda,
                                                    const double* __restrict__ B, int64_t ldb, int64_t M,
                                                    int64_t N, int64_t K, int64_t kchunk, double* __restrict__ C,
-                                                   int64_t ldc, int64_t cstride) {
+                                                   int64_t ldc, int64_t cstride, const int* __restrict__ arow,
+                                                   const int* __restrict__ crow) {
+    static_assert(!GA || (!TA && !TB), "row maps only for C = A B");
     typedef typename Mfma<Tc>::acc_t acc_t;
     __shared__ Tc As[KT][MT + PAD];
     __shared__ Tc Bs[KT][NT + PAD];
@@ -74,7 +78,16 @@ __global__ __launch_bounds__(256) void k_mfma_gemm(const double* __restrict__ A,
     const int64_t ke = min(K, kb + kchunk);
     C += static_cast<int64_t>(blockIdx.z) * cstride;
 
-    // each thread moves 8 elements of each operand per slice
+    // each thread moves 8 elements of each operand per slice; with GA its 8 rows of A
+    // (i0 + tid / 16 + 16 u) are mapped once
+    int64_t arow_u[GA ? 8 : 1];
+    if (GA) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t i = i0 + tid / KT + 16 * u;
+            arow_u[u] = (i < M && arow) ? static_cast<int64_t>(arow[i]) : i;
+        }
+    }
     double ra[8], rb[8];
     auto load = [&](int64_t k0) {
 #pragma unroll
@@ -89,7 +102,10 @@ __global__ __launch_bounds__(256) void k_mfma_gemm(const double* __restrict__ A,
                 kk = e % KT;
             }
             const int64_t k = k0 + kk, i = i0 + ii;
-            ra[u] = (k < ke && i < M) ? (TA ? A[k * lda + i] : A[i * lda + k]) : 0.0;
+            if (GA)
+                ra[u] = (k < ke && i < M) ? A[arow_u[u] * lda + k] : 0.0;
+            else
+                ra[u] = (k < ke && i < M) ? (TA ? A[k * lda + i] : A[i * lda + k]) : 0.0;
             int jj, kk2;
             if (TB) {   // stored N x K: contiguous along k
                 jj = e / KT;
@@ -148,7 +164,9 @@ __global__ __launch_bounds__(256) void k_mfma_gemm(const double* __restrict__ A,
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int64_t i = i0 + wm * 64 + r * 16 + Mfma<Tc>::row(lk, v);
-                if (i < M) C[i * ldc + j] = static_cast<double>(acc[r][c][v]);
+                if (i >= M) continue;
+                const int64_t ci = (GA && crow) ? static_cast<int64_t>(crow[i]) : i;
+                C[ci * ldc + j] = static_cast<double>(acc[r][c][v]);
             }
         }
 }
@@ -161,27 +179,44 @@ void launch_mfma_gemm(bool ta, bool tb, const double* A, int64_t lda, const doub
                       int64_t N, int64_t K, double* C, int64_t ldc, int nsplit, int64_t cstride, hipStream_t st,
                       bool fp32, KernelTimer* timer, int kind) {
     if (M <= 0 || N <= 0) return;
+    const int* arow = nullptr;
+    const int* crow = nullptr;
     nsplit = std::max(1, nsplit);
     const int64_t kchunk = std::max<int64_t>(KT, ((K + nsplit - 1) / nsplit + KT - 1) / KT * KT);
     dim3 grid(static_cast<unsigned>((M + MT - 1) / MT), static_cast<unsigned>((N + NT - 1) / NT),
               static_cast<unsigned>(nsplit));
-#define FASTPI_MG(TC, TAV, TBV)                                                                                \
-    FASTPI_LAUNCH(timer, kind, (k_mfma_gemm<TC, TAV, TBV>), grid, dim3(256), 0, st, A, lda, B, ldb, M, N, K, kchunk, \
-                  C, ldc, cstride)
+#define FASTPI_MG(TC, TAV, TBV, GAV)                                                                           \
+    FASTPI_LAUNCH(timer, kind, (k_mfma_gemm<TC, TAV, TBV, GAV>), grid, dim3(256), 0, st, A, lda, B, ldb, M, N, K,  \
+                  kchunk, C, ldc, cstride, arow, crow)
     if (fp32) {
         if (ta) {
-            if (tb) FASTPI_MG(float, true, true); else FASTPI_MG(float, true, false);
+            if (tb) FASTPI_MG(float, true, true, false); else FASTPI_MG(float, true, false, false);
         } else {
-            if (tb) FASTPI_MG(float, false, true); else FASTPI_MG(float, false, false);
+            if (tb) FASTPI_MG(float, false, true, false); else FASTPI_MG(float, false, false, false);
         }
     } else {
         if (ta) {
-            if (tb) FASTPI_MG(double, true, true); else FASTPI_MG(double, true, false);
+            if (tb) FASTPI_MG(double, true, true, false); else FASTPI_MG(double, true, false, false);
         } else {
-            if (tb) FASTPI_MG(double, false, true); else FASTPI_MG(double, false, false);
+            if (tb) FASTPI_MG(double, false, true, false); else FASTPI_MG(double, false, false, false);
         }
     }
 #undef FASTPI_MG
+}
+
+// C[crow(i)] = A[arow(i)] B (C = A B with a row gather of A and a row scatter of C; either
+// map may be null), on the matrix cores, unsplit.
+void launch_mfma_gemm_rows(const double* A, int64_t lda, const int* arow, const double* B, int64_t ldb, int64_t M,
+                           int64_t N, int64_t K, double* C, int64_t ldc, const int* crow, hipStream_t st, bool fp32) {
+    if (M <= 0 || N <= 0) return;
+    dim3 grid(static_cast<unsigned>((M + MT - 1) / MT), static_cast<unsigned>((N + NT - 1) / NT), 1);
+    const int64_t kchunk = std::max<int64_t>(KT, (K + KT - 1) / KT * KT);
+    if (fp32)
+        hipLaunchKernelGGL((k_mfma_gemm<float, false, false, true>), grid, dim3(256), 0, st, A, lda, B, ldb, M, N, K,
+                           kchunk, C, ldc, int64_t{0}, arow, crow);
+    else
+        hipLaunchKernelGGL((k_mfma_gemm<double, false, false, true>), grid, dim3(256), 0, st, A, lda, B, ldb, M, N, K,
+                           kchunk, C, ldc, int64_t{0}, arow, crow);
 }
 
 }  // namespace fastpi
