@@ -424,25 +424,44 @@ void launch_chol_inverse(const CholJob* jobs, int njobs, int max_kp, hipStream_t
 
 // Residual of the final eigenpairs: column i of R = G V (q x t row-major) against
 // lam_i V[:, i]; the job is marked when ||r_i|| > tol * lam_0, or lam_i is not finite.
-// One workgroup per 64 columns, lane = column, the four waves splitting the rows.
-__global__ __launch_bounds__(256) void k_sub_residual(const double* __restrict__ R, const double* __restrict__ V,
-                                                      const double* __restrict__ lam, int64_t q, int64_t t,
-                                                      double tol, int* __restrict__ flag) {
+// One workgroup per 64 columns, lane = column, sixteen waves splitting the rows.
+constexpr int RES_WAVES = 16;
+__global__ __launch_bounds__(RES_WAVES * 64) void k_sub_residual(const double* __restrict__ R,
+                                                                const double* __restrict__ V,
+                                                                const double* __restrict__ lam, int64_t q, int64_t t,
+                                                                double tol, int* __restrict__ flag) {
     const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
     const int64_t c = static_cast<int64_t>(blockIdx.x) * 64 + lane;
-    __shared__ double part[4][64];
-    double s = 0.0;
+    __shared__ double part[RES_WAVES][64];
+    // wave w sums rows w, w + RES_WAVES, ... of column c, four rows' loads in flight at once
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
     if (c < t) {
         const double l = lam[c];
-        for (int64_t r = w; r < q; r += 4) {
+        int64_t r = w;
+        for (; r + 3 * RES_WAVES < q; r += 4 * RES_WAVES) {
+            double x[4], y[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                x[u] = R[(r + u * RES_WAVES) * t + c];
+                y[u] = V[(r + u * RES_WAVES) * t + c];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double d = x[u] - l * y[u];
+                s[u] += d * d;
+            }
+        }
+        for (; r < q; r += RES_WAVES) {
             const double d = R[r * t + c] - l * V[r * t + c];
-            s += d * d;
+            s[0] += d * d;
         }
     }
-    part[w][lane] = s;
+    part[w][lane] = (s[0] + s[1]) + (s[2] + s[3]);
     __syncthreads();
     if (w == 0 && c < t) {
-        const double tot = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+        double tot = 0.0;
+#pragma unroll
+        for (int k = 0; k < RES_WAVES; ++k) tot += part[k][lane];
         const double l0 = lam[0], l = lam[c];
         if (!(sqrt(tot) <= tol * l0) || !(l == l)) atomicOr(flag, 1);
     }
@@ -451,8 +470,8 @@ __global__ __launch_bounds__(256) void k_sub_residual(const double* __restrict__
 void launch_sub_residual(const double* R, const double* V, const double* lam, int64_t q, int64_t t, double tol,
                          int* flag, hipStream_t st) {
     if (q <= 0 || t <= 0) return;
-    hipLaunchKernelGGL(k_sub_residual, dim3(static_cast<unsigned>((t + 63) / 64)), dim3(256), 0, st, R, V, lam, q,
-                       t, tol, flag);
+    hipLaunchKernelGGL(k_sub_residual, dim3(static_cast<unsigned>((t + 63) / 64)), dim3(RES_WAVES * 64), 0, st, R, V,
+                       lam, q, t, tol, flag);
 }
 
 // H = (H + H^T) / 2 in place (k x k row-major)
