@@ -118,6 +118,22 @@ __global__ __launch_bounds__(SG_WAVES * 64) void k_sparse_gram(
     for (int64_t c = c0 + lane; c < c1; c += kWave) dst[c] = buf[c - c0];
 }
 
+// acc + part[p0 * ld] + part[(p0 + 1) * ld] + ... + part[(p1 - 1) * ld], added in that order
+// with eight loads in flight at a time (an owner may have hundreds of segments)
+__device__ __forceinline__ double sum_parts_in_order(double acc, const double* __restrict__ part, int64_t ld,
+                                                     int64_t p0, int64_t p1) {
+    int64_t p = p0;
+    for (; p + 8 <= p1; p += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = part[(p + u) * ld];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; p < p1; ++p) acc += part[p * ld];
+    return acc;
+}
+
 // rows of owners with several segments: G[a, :] = (accumulate ? G[a, :] : 0) + sum part
 __global__ void k_seg_reduce_rows(SegDev sg, const double* __restrict__ part, int64_t q,
                                   double* __restrict__ G, int64_t ldg, int accumulate) {
@@ -126,7 +142,7 @@ __global__ void k_seg_reduce_rows(SegDev sg, const double* __restrict__ part, in
     if (o >= sg.nmulti || c >= q) return;
     const int64_t a = sg.multi_owner[o];
     double acc = accumulate ? G[a * ldg + c] : 0.0;
-    for (int64_t p = sg.multi_ptr[o]; p < sg.multi_ptr[o + 1]; ++p) acc += part[p * q + c];
+    acc = sum_parts_in_order(acc, part + c, q, sg.multi_ptr[o], sg.multi_ptr[o + 1]);
     G[a * ldg + c] = acc;
 }
 
@@ -195,7 +211,7 @@ __global__ void k_seg_reduce_proj(SegDev sg, const double* __restrict__ part, in
     if (o >= sg.nmulti || k >= s) return;
     const int64_t a = sg.multi_owner[o];
     double acc = 0;
-    for (int64_t p = sg.multi_ptr[o]; p < sg.multi_ptr[o + 1]; ++p) acc += part[p * s + k];
+    acc = sum_parts_in_order(acc, part + k, s, sg.multi_ptr[o], sg.multi_ptr[o + 1]);
     const double val = acc * sigma[k];
     G[k * ldg + off + a] = val;
     G[(off + a) * ldg + k] = val;
@@ -264,7 +280,7 @@ __global__ void k_seg_reduce_spmm(SegDev sg, const double* __restrict__ part, in
     if (o >= sg.nmulti || k >= N) return;
     const int64_t h = sg.multi_owner[o];
     double acc = 0;
-    for (int64_t p = sg.multi_ptr[o]; p < sg.multi_ptr[o + 1]; ++p) acc += part[p * N + k];
+    acc = sum_parts_in_order(acc, part + k, N, sg.multi_ptr[o], sg.multi_ptr[o + 1]);
     if (cs) acc *= cs[k];
     const int64_t ci = crow ? crow[h] : h;
     double* dst = C + ci * ldc + k;
