@@ -459,7 +459,11 @@ static int build_sets(Group& g, hipStream_t st) {
         const int spg = b.trans ? gemm_tn_splits(q, q, p, false, g.ncu) : 1;
         const int spw = b.trans ? 1 : gemm_tn_splits(p, t, q, false, g.ncu);
         b.sp = std::max(spg, spw);
-        const int64_t part = std::max<int64_t>(static_cast<int64_t>(spg) * q * q, static_cast<int64_t>(spw) * p * t);
+        // the untransposed Gram of a narrow block runs one tile over a long K: chunks of 64
+        // rows on as many workgroups, their partials summed in order
+        b.sp_nt = (!b.trans && q <= 256) ? static_cast<int>(std::min<int64_t>(16, std::max<int64_t>(1, p / 64))) : 1;
+        const int64_t part = std::max({static_cast<int64_t>(spg) * q * q, static_cast<int64_t>(spw) * p * t,
+                                       static_cast<int64_t>(b.sp_nt) * q * q});
         const size_t ed = eig_job_doubles(q, g.tune.gram_rows), ei = eig_job_ints(q);
         const size_t doubles = static_cast<size_t>(q * q + q * t + t + p * t + part) + ed;
         void* mem = nullptr;
@@ -859,7 +863,11 @@ static void stage_front(Group& g, const double* const* val, const RunCfg& c, hip
     for (BigBlock& b : g.big) {
         if (b.trans)
             launch_gemm_tn(b.A, b.q, b.A, b.q, b.q, b.q, b.p, b.G, b.q, nullptr, nullptr, b.part, b.sp, st, false);
-        else
+        else if (b.sp_nt > 1) {
+            launch_mfma_gemm(false, true, b.A, b.p, b.A, b.p, b.q, b.q, b.p, b.part, b.q, b.sp_nt, b.q * b.q, st,
+                             false);
+            launch_sum_parts(b.part, b.sp_nt, b.q, b.q, b.G, b.q, st);
+        } else
             launch_gemm_nt(b.A, b.p, b.A, b.p, b.q, b.q, b.p, b.G, b.q, st, false);
     }
     eig_begin(g.set1, st);

@@ -47,7 +47,8 @@ struct BigBlock {
     int64_t rows = 0, cols = 0, p = 0, q = 0, t = 0;
     bool trans = false;          // rows < cols: X = A^T
     double *G = nullptr, *E = nullptr, *lam = nullptr, *W = nullptr, *part = nullptr;
-    int sp = 1;
+    int sp = 1;        // K split of the transposed products (the Gram when trans, W otherwise)
+    int sp_nt = 1;     // K split of the Gram X X^T when not trans (a small q over a long p)
 };
 
 // One randomized core: the top t eigenpairs of a q x q Gram matrix G from a k-dimensional
